@@ -1,0 +1,296 @@
+"""CPU oracle for RNS-CKKS -- TEST INFRASTRUCTURE ONLY.
+
+Python front end over oracle/liboracle.so (plain C, __int128 arithmetic,
+binary128 encoder).  Only tests/, the smoke check and the CPU-baseline leg of
+bench.py may import this module; the product library never does.
+
+Background (the paper's Background section, "Homomorphic encryption"):
+ciphertexts are pairs over Z_Q[x]/(x^n + 1), n = 2N, with N real slots; every
+multiplication consumes a level; ciphertexts support cyclic slot rotations.
+The scheme conventions that the paper leaves to its library are fixed here
+(and mirrored independently by the GPU library):
+
+* primes: q_0 .. q_L then special primes p_0 .. p_{k-1}; each is the first
+  prime 2^b - j*2n + 1 (j = 1, 2, ...) not already taken;
+* digits of the hybrid key switch: consecutive runs of alpha = ceil((L+1)/dnum)
+  primes of q_0..q_L;
+* rotation by r (left: slot j <- slot j+r) is the Galois map x -> x^g with
+  g = 5^(r mod N) mod 2n; rotation by 0 is the identity;
+* randomness: ChaCha20 streams named (seed, purpose, index).
+
+All ciphertexts here are in coefficient form, layout [2][level+1][n] uint64,
+which is also the canonical comparison form.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        _lib = ctypes.CDLL(path)
+        _declare(_lib)
+    return _lib
+
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+u32p = ctypes.POINTER(ctypes.c_uint32)
+dblp = ctypes.POINTER(ctypes.c_double)
+MAXP = 96
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("logn", ctypes.c_uint32), ("n", ctypes.c_uint32), ("L", ctypes.c_uint32),
+                ("k", ctypes.c_uint32), ("dnum", ctypes.c_uint32), ("alpha", ctypes.c_uint32),
+                ("mod", ctypes.c_uint64 * MAXP), ("psi", ctypes.c_uint64 * MAXP)]
+
+
+def _declare(L):
+    P = ctypes.POINTER(_Params)
+    u32, u64, dbl = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "orc_mulmod": (u64, [u64, u64, u64]),
+        "orc_powmod": (u64, [u64, u64, u64]),
+        "orc_invmod": (u64, [u64, u64]),
+        "orc_is_prime": (ctypes.c_int, [u64]),
+        "orc_find_prime": (u64, [u32, u32, u64p, u32]),
+        "orc_find_psi": (u64, [u64, u32]),
+        "orc_params_init": (ctypes.c_int, [P, u32, u32, u32p, u32, u32p, u32]),
+        "orc_ntt": (None, [u64p, u32, u64, u64]),
+        "orc_intt": (None, [u64p, u32, u64, u64]),
+        "orc_polymul": (None, [u64p, u64p, u64p, u32, u64, u64]),
+        "orc_chacha20_block": (None, [u32p, u32, u32p, u32p]),
+        "orc_stream_u64": (None, [u64, u32, u64, u64, u64, u64p]),
+        "orc_sample_uniform": (None, [P, u64, u32, u64, u32p, u32, u64p]),
+        "orc_sample_ternary": (None, [u64, u32, u64, u32, i64p]),
+        "orc_gauss_table": (None, [dbl, u64p]),
+        "orc_sample_gauss": (None, [u64, u32, u64, u32, dbl, i64p]),
+        "orc_encode_direct": (ctypes.c_int, [u32, dblp, u32, dbl, i64p]),
+        "orc_encode": (ctypes.c_int, [u32, dblp, u32, dbl, i64p]),
+        "orc_decode": (None, [u32, dblp, dbl, dblp]),
+        "orc_reduce_small": (None, [P, i64p, u32p, u32, u64p]),
+        "orc_automorph": (None, [P, u32p, u32, u32, u64p, u64p]),
+        "orc_keygen_secret": (None, [P, u64, i64p]),
+        "orc_keygen_pk": (None, [P, u64, dbl, i64p, u64p]),
+        "orc_keygen_swk": (None, [P, u64, dbl, i64p, u32, u64p]),
+        "orc_encrypt": (None, [P, u64p, dbl, u64p, u32, u64, u64, u64p]),
+        "orc_decrypt": (None, [P, i64p, u64p, u32, u64p]),
+        "orc_modup": (None, [P, u32, u32, u64p, u64p]),
+        "orc_moddown": (None, [P, u32, u64p, u64p]),
+        "orc_rotate_hoisted": (None, [P, u32, u64p, u32, u32p, ctypes.POINTER(u64p), ctypes.POINTER(u64p)]),
+        "orc_mul_pt": (None, [P, u32, u64p, u64p, u64p]),
+        "orc_add": (None, [P, u32, u32, u64p, u64p, u64p]),
+        "orc_rescale": (None, [P, u32, u64p, u64p]),
+        "orc_ntt_limbs": (None, [P, u32p, u32, u64p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def ptr(a, t=u64p):
+    return a.ctypes.data_as(t)
+
+
+def u32arr(xs):
+    return np.ascontiguousarray(np.asarray(xs, dtype=np.uint32))
+
+
+# purposes of the random streams (must match both implementations' convention)
+P_SECRET, P_PK_A, P_PK_E, P_SWK_A, P_SWK_E, P_ENC_V, P_ENC_E0, P_ENC_E1 = range(1, 9)
+
+
+class Params:
+    """An RNS-CKKS parameter set: ring degree n = 2^logn, ciphertext prime sizes
+    qbits[0..L], special prime sizes pbits[0..k-1], dnum key-switch digits."""
+
+    def __init__(self, logn, qbits, pbits, dnum, sigma=3.2):
+        self.logn, self.n, self.N = logn, 1 << logn, 1 << (logn - 1)
+        self.qbits, self.pbits = list(qbits), list(pbits)
+        self.sigma = float(sigma)
+        self.c = _Params()
+        qb, pb = u32arr(qbits), u32arr(pbits if len(pbits) else [0])
+        rc = lib().orc_params_init(ctypes.byref(self.c), logn, len(qbits), ptr(qb, u32p), len(pbits),
+                                   ptr(pb, u32p), dnum)
+        if rc != 0:
+            raise ValueError("oracle parameter set rejected (%d)" % rc)
+        self.L, self.k = self.c.L, self.c.k
+        self.dnum, self.alpha = self.c.dnum, self.c.alpha
+        self.mod = [int(self.c.mod[i]) for i in range(self.L + 1 + self.k)]
+        self.q = self.mod[: self.L + 1]
+        self.p = self.mod[self.L + 1:]
+        self.psi = [int(self.c.psi[i]) for i in range(self.L + 1 + self.k)]
+
+    @property
+    def cref(self):
+        return ctypes.byref(self.c)
+
+    def galois(self, step):
+        """Galois element of a left rotation by `step` slots."""
+        return pow(5, step % self.N, 2 * self.n)
+
+
+class Pt:
+    def __init__(self, limbs, level, scale, coeffs=None):
+        self.limbs, self.level, self.scale, self.coeffs = limbs, level, scale, coeffs
+
+
+class Ct:
+    def __init__(self, data, level, scale):
+        assert data.shape[0] == 2 and data.shape[1] == level + 1
+        self.data, self.level, self.scale = data, level, float(scale)
+
+    def copy(self):
+        return Ct(self.data.copy(), self.level, self.scale)
+
+
+class Oracle:
+    """The CPU oracle: keys, encoding, encryption and the evaluation steps."""
+
+    def __init__(self, params, seed):
+        self.p = params
+        self.seed = seed
+        n = params.n
+        self.s = np.zeros(n, dtype=np.int64)
+        lib().orc_keygen_secret(params.cref, seed, ptr(self.s, i64p))
+        self.pk = np.zeros((2, params.L + 1, n), dtype=np.uint64)
+        lib().orc_keygen_pk(params.cref, seed, params.sigma, ptr(self.s, i64p), ptr(self.pk))
+        self._swk = {}
+
+    # ---- keys -----------------------------------------------------------
+    def swk(self, g):
+        """Rotation key for Galois element g, coefficient form [dnum][2][L+1+k][n]."""
+        if g not in self._swk:
+            p = self.p
+            nl = p.L + 1 + p.k
+            k = np.zeros((p.dnum, 2, nl, p.n), dtype=np.uint64)
+            lib().orc_keygen_swk(p.cref, self.seed, p.sigma, ptr(self.s, i64p), g, ptr(k))
+            kn = k.copy()
+            pidx = u32arr(list(range(nl)) * (2 * p.dnum))
+            lib().orc_ntt_limbs(p.cref, ptr(pidx, u32p), 2 * p.dnum * nl, ptr(kn))
+            self._swk[g] = (k, kn)
+        return self._swk[g]
+
+    # ---- encoding ---------------------------------------------------------
+    def encode_coeffs(self, z, scale):
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        m = np.zeros(self.p.n, dtype=np.int64)
+        rc = lib().orc_encode(self.p.n, ptr(z, dblp), len(z), float(scale), ptr(m, i64p))
+        if rc != 0:
+            raise OverflowError("encoded coefficient exceeds 2^62")
+        return m
+
+    def limbs_of(self, m, level):
+        """Signed integer coefficients reduced mod q_0..q_level: [level+1][n]."""
+        out = np.zeros((level + 1, self.p.n), dtype=np.uint64)
+        pidx = u32arr(range(level + 1))
+        lib().orc_reduce_small(self.p.cref, ptr(m, i64p), ptr(pidx, u32p), level + 1, ptr(out))
+        return out
+
+    def encode(self, z, level, scale):
+        m = self.encode_coeffs(z, scale)
+        return Pt(self.limbs_of(m, level), level, float(scale), m)
+
+    def decode(self, m_float, scale):
+        m = np.ascontiguousarray(np.asarray(m_float, dtype=np.float64))
+        z = np.zeros(self.p.N, dtype=np.float64)
+        lib().orc_decode(self.p.n, ptr(m, dblp), float(scale), ptr(z, dblp))
+        return z
+
+    # ---- encryption ---------------------------------------------------------
+    def encrypt(self, pt, seed, index=0):
+        p = self.p
+        ct = np.zeros((2, pt.level + 1, p.n), dtype=np.uint64)
+        lib().orc_encrypt(p.cref, ptr(self.pk), p.sigma, ptr(np.ascontiguousarray(pt.limbs)), pt.level, seed,
+                          index, ptr(ct))
+        return Ct(ct, pt.level, pt.scale)
+
+    def decrypt_residues(self, ct):
+        m = np.zeros((ct.level + 1, self.p.n), dtype=np.uint64)
+        lib().orc_decrypt(self.p.cref, ptr(self.s, i64p), ptr(np.ascontiguousarray(ct.data)), ct.level, ptr(m))
+        return m
+
+    def crt_centered(self, res):
+        """Exact centered CRT of [l+1][n] residues with Python integers."""
+        qs = self.p.q[: res.shape[0]]
+        Q = 1
+        for q in qs:
+            Q *= q
+        acc = np.zeros(res.shape[1], dtype=object)
+        for i, q in enumerate(qs):
+            Qi = Q // q
+            c = Qi * pow(Qi % q, -1, q)
+            acc = acc + res[i].astype(object) * c
+        acc = acc % Q
+        half = Q // 2
+        return np.where(acc > half, acc - Q, acc)
+
+    def decrypt(self, ct):
+        m = self.crt_centered(self.decrypt_residues(ct))
+        return self.decode(np.array([float(v) for v in m]), ct.scale)
+
+    # ---- evaluation ---------------------------------------------------------
+    def rotate_hoisted(self, ct, steps):
+        p = self.p
+        outs, gs, keys = [], [], []
+        res = [None] * len(steps)
+        todo = []
+        for i, r in enumerate(steps):
+            if r % p.N == 0:
+                res[i] = ct.copy()
+            else:
+                todo.append(i)
+        if todo:
+            for i in todo:
+                g = p.galois(steps[i])
+                gs.append(g)
+                keys.append(self.swk(g)[1])
+                outs.append(np.zeros((2, ct.level + 1, p.n), dtype=np.uint64))
+            kp = (u64p * len(keys))(*[ptr(k) for k in keys])
+            op = (u64p * len(outs))(*[ptr(o) for o in outs])
+            gsa = u32arr(gs)
+            lib().orc_rotate_hoisted(p.cref, ct.level, ptr(np.ascontiguousarray(ct.data)), len(gs), ptr(gsa, u32p),
+                                     kp, op)
+            for i, o in zip(todo, outs):
+                res[i] = Ct(o, ct.level, ct.scale)
+        return res
+
+    def rotate(self, ct, step):
+        return self.rotate_hoisted(ct, [step])[0]
+
+    def mul_pt(self, ct, pt):
+        if pt.level != ct.level:
+            raise ValueError("level mismatch")
+        out = np.zeros_like(ct.data)
+        lib().orc_mul_pt(self.p.cref, ct.level, ptr(np.ascontiguousarray(ct.data)), ptr(np.ascontiguousarray(pt.limbs)),
+                         ptr(out))
+        return Ct(out, ct.level, ct.scale * pt.scale)
+
+    def add(self, a, b):
+        if a.level != b.level or a.scale != b.scale:
+            raise ValueError("level/scale mismatch")
+        out = np.zeros_like(a.data)
+        lib().orc_add(self.p.cref, a.level + 1, 2, ptr(np.ascontiguousarray(a.data)), ptr(np.ascontiguousarray(b.data)),
+                      ptr(out))
+        return Ct(out, a.level, a.scale)
+
+    def rescale(self, ct):
+        if ct.level == 0:
+            raise ValueError("cannot rescale at level 0")
+        out = np.zeros((2, ct.level, self.p.n), dtype=np.uint64)
+        lib().orc_rescale(self.p.cref, ct.level, ptr(np.ascontiguousarray(ct.data)), ptr(out))
+        return Ct(out, ct.level - 1, ct.scale / self.p.q[ct.level])
+
+    def drop_to(self, ct, level):
+        return Ct(ct.data[:, : level + 1].copy(), level, ct.scale)

@@ -1,0 +1,479 @@
+"""Homomorphic convolution and 2x2 average pooling -- oracle side (TEST ONLY).
+
+The schedule of the paper's Section 4 ("Homomorphic Neural Network
+Operators"), written once over an abstract backend so that it can run either
+on encrypted oracle ciphertexts (`CkksBackend`) or on cleartext FP64 slot
+vectors (`SlotSim`, where a rotation is `np.roll` and a plaintext product is an
+elementwise product).  The slot simulator checks the layout algebra against a
+direct FP64 convolution; the encrypted backend gives the bit-exact ciphertexts
+the GPU library must reproduce.
+
+Layout (Section 4, "Sharding and Encrypting an Image", "Duplicating and
+Permuting Channels"): every channel is stored row-major in a block of
+B = mp*mp slots, mp the channel side padded to a power of two (dimensions that
+are not powers of two are zero padded, as the paper allows); a shard holds
+N/B blocks.  Each shard carries a block map lam[b] = logical channel held by
+block b (-1 for an empty block); duplication and the permutation introduced by
+pooling are both just block maps.
+
+Readings of passages that are silent, garbled or ambiguous (each repeated in
+the design doc):
+  * duplicated channels are stored as consecutive copies, [M0, M0, M1, M1, ...],
+    the order the pooling duplication step produces;
+  * the offsets of a convolution are found by the two-phase rule in
+    `_rotation_offsets` (offsets that serve every output block first, then any
+    block still missing a channel), smallest offset first;
+  * horizontal reduction keeps column 2i (even rows only) and shifts it left by
+    i; vertical reduction takes the left half of row 2j and shifts it left by
+    3j*mp/2 (the printed equation's "3i" read as 3j);
+  * the 1/4 of the average is folded into the horizontal masks;
+  * consolidation shifts shard e of a group right by e*B/4 (the printed
+    equation repeats S_2 and writes m^2 for the post-pool block size);
+    duplication by d shifts by multiples of B/d;
+  * when only one level is left, the two reductions are fused into one
+    masked sum (masks combined non-homomorphically) with masks at scale q/4.
+"""
+import math
+
+import numpy as np
+
+
+def next_pow2(x):
+    return 1 << max(0, (int(x) - 1).bit_length())
+
+
+class Layout:
+    """Where each channel of a C x H x W image lives in a list of shards."""
+
+    def __init__(self, N, C, H, W, mp, kind, shards):
+        self.N, self.C, self.H, self.W, self.mp = N, C, H, W, mp
+        self.B = mp * mp
+        self.kind = kind          # "image" or "channel"
+        self.shards = shards      # image: list of block maps; channel: list of (channel, part)
+
+    @property
+    def nb(self):
+        return self.N // self.B
+
+    def copy(self):
+        return Layout(self.N, self.C, self.H, self.W, self.mp, self.kind, [list(s) if isinstance(s, list) else s
+                                                                           for s in self.shards])
+
+    def __repr__(self):
+        return "Layout(%s C=%d %dx%d mp=%d shards=%d)" % (self.kind, self.C, self.H, self.W, self.mp,
+                                                          len(self.shards))
+
+
+def natural_layout(N, C, H, W, mp=None):
+    """Channel-major row-major packing; channels spread over image shards when
+    m^2 c > N; a channel split into consecutive-row channel shards when
+    m^2 > N; d = N/(m^2 c) consecutive copies when the image underfills a shard
+    (Section 4, sharding and duplication paragraphs)."""
+    if mp is None:
+        mp = next_pow2(max(H, W))
+    B = mp * mp
+    if B <= N:
+        nb = N // B
+        Cp = next_pow2(C)
+        if Cp * B <= N:
+            d = N // (Cp * B)
+            return Layout(N, C, H, W, mp, "image", [[b // d if b // d < C else -1 for b in range(nb)]])
+        t = Cp * B // N
+        return Layout(N, C, H, W, mp, "image",
+                      [[u * nb + b if u * nb + b < C else -1 for b in range(nb)] for u in range(t)])
+    spc = B // N
+    return Layout(N, C, H, W, mp, "channel", [(f, part) for f in range(C) for part in range(spc)])
+
+
+def pack(x, lay):
+    """Cleartext image [C][H][W] -> list of slot vectors (one per shard)."""
+    N, mp, B = lay.N, lay.mp, lay.B
+    out = []
+    for s in lay.shards:
+        v = np.zeros(N)
+        if lay.kind == "image":
+            for b, f in enumerate(s):
+                if f >= 0:
+                    blk = np.zeros((mp, mp))
+                    blk[: lay.H, : lay.W] = x[f]
+                    v[b * B:(b + 1) * B] = blk.reshape(-1)
+        else:
+            f, part = s
+            R = N // mp
+            blk = np.zeros((mp, mp))
+            blk[: lay.H, : lay.W] = x[f]
+            v[:] = blk[part * R:(part + 1) * R].reshape(-1)
+        out.append(v)
+    return out
+
+
+def unpack(vecs, lay):
+    """Slot vectors -> image [C][H][W], reading the first copy of each channel."""
+    mp, B = lay.mp, lay.B
+    x = np.full((lay.C, lay.H, lay.W), np.nan)
+    if lay.kind == "image":
+        seen = set()
+        for u, s in enumerate(lay.shards):
+            for b, f in enumerate(s):
+                if f >= 0 and f not in seen:
+                    seen.add(f)
+                    x[f] = np.asarray(vecs[u][b * B:(b + 1) * B]).reshape(mp, mp)[: lay.H, : lay.W]
+    else:
+        R = lay.N // mp
+        full = np.zeros((lay.C, mp, mp))
+        for u, (f, part) in enumerate(lay.shards):
+            full[f, part * R:(part + 1) * R] = np.asarray(vecs[u]).reshape(R, mp)
+        x = full[:, : lay.H, : lay.W]
+    return x
+
+
+# ---------------------------------------------------------------------------
+# backends
+# ---------------------------------------------------------------------------
+
+class SlotSim:
+    """Cleartext slot vectors: rotation is np.roll, products are elementwise.
+    A value is (vector, level, scale) with level/scale bookkeeping only."""
+
+    def __init__(self, N, qs):
+        self.N, self.qs = N, qs
+
+    def q(self, level):
+        return float(self.qs[level])
+
+    def rotate_hoisted(self, ct, steps):
+        v, lvl, sc = ct
+        return [(np.roll(v, -(r % self.N)), lvl, sc) for r in steps]
+
+    def rotate(self, ct, r):
+        return self.rotate_hoisted(ct, [r])[0]
+
+    def mul_plain(self, ct, vec, pscale):
+        v, lvl, sc = ct
+        return (v * vec, lvl, sc * pscale)
+
+    def add(self, a, b):
+        assert a[1] == b[1]
+        return (a[0] + b[0], a[1], a[2])
+
+    def rescale(self, ct):
+        v, lvl, sc = ct
+        assert lvl > 0
+        return (v, lvl - 1, sc / self.qs[lvl])
+
+    def level(self, ct):
+        return ct[1]
+
+
+class CkksBackend:
+    """Encrypted oracle ciphertexts; a plaintext product encodes the slot
+    vector at the requested scale, at the ciphertext's level."""
+
+    def __init__(self, oracle):
+        self.o = oracle
+
+    def q(self, level):
+        return float(self.o.p.q[level])
+
+    def rotate_hoisted(self, ct, steps):
+        return self.o.rotate_hoisted(ct, steps)
+
+    def rotate(self, ct, r):
+        return self.o.rotate(ct, r)
+
+    def mul_plain(self, ct, vec, pscale):
+        return self.o.mul_pt(ct, self.o.encode(vec, ct.level, pscale))
+
+    def add(self, a, b):
+        return self.o.add(a, b)
+
+    def rescale(self, ct):
+        return self.o.rescale(ct)
+
+    def level(self, ct):
+        return ct.level
+
+
+def _sum(be, terms):
+    acc = None
+    for t in terms:
+        acc = t if acc is None else be.add(acc, t)
+    return acc
+
+
+# ---------------------------------------------------------------------------
+# convolution (Section 4.1)
+# ---------------------------------------------------------------------------
+
+def _rotation_offsets(lam, need_b):
+    """Block offsets r with, for each output block b, the input channel
+    lam[b+r] it takes (indices mod the block count).  Every output block must
+    see every channel present in the shard exactly once.  Phase 1 keeps the
+    offsets that bring a new channel to every needed block at once (for
+    consecutive d-fold copies these are 0, d, 2d, ...); phase 2 fills what is
+    still missing block by block.  Smallest offset first in both phases."""
+    nb = len(lam)
+    chans = set(f for f in lam if f >= 0)
+    covered = {b: set() for b in need_b}
+    assign = {}
+    for r in range(nb):
+        fs = {b: lam[(b + r) % nb] for b in need_b}
+        if all(f >= 0 and f not in covered[b] for b, f in fs.items()):
+            assign[r] = fs
+            for b, f in fs.items():
+                covered[b].add(f)
+    for r in range(nb):
+        for b in need_b:
+            f = lam[(b + r) % nb]
+            if f >= 0 and f not in covered[b]:
+                assign.setdefault(r, {})[b] = f
+                covered[b].add(f)
+    for b in need_b:
+        if covered[b] != chans:
+            raise ValueError("layout cannot be convolved")
+    return [(r, assign[r]) for r in sorted(assign)]
+
+
+def _tap_mask(lay, Ho, Wo, dk, dl):
+    """Valid-output x valid-input mask of one block for the shift S_{dk,dl}."""
+    mp = lay.mp
+    i = np.arange(mp)[:, None]
+    j = np.arange(mp)[None, :]
+    m = (i < Ho) & (j < Wo) & (i + dk >= 0) & (i + dk < lay.H) & (j + dl >= 0) & (j + dl < lay.W)
+    return m.astype(np.float64).reshape(-1)
+
+
+def conv_plan(lay, w, pad):
+    """Plan of a stride-1 convolution of an image-sharded input: the output
+    layout and, per input shard u, the list of (rotation amount, {v: slot
+    vector}) products.  Output shard v = sum over u and the list of
+    pt * rot(ct_u, amount) (Section 4.1, single shard and image shards;
+    duplicated / permuted inputs through the block map)."""
+    if lay.kind != "image":
+        raise ValueError("image-shard layout expected")
+    w = np.asarray(w, dtype=np.float64)
+    Co, Ci, kh, kw = w.shape
+    if Ci != lay.C:
+        raise ValueError("channel mismatch")
+    Ho, Wo = lay.H + 2 * pad - kh + 1, lay.W + 2 * pad - kw + 1
+    if Ho < 1 or Wo < 1 or Ho > lay.mp or Wo > lay.mp:
+        raise ValueError("bad convolution geometry")
+    out = natural_layout(lay.N, Co, Ho, Wo, mp=lay.mp)
+    if out.kind != "image":
+        raise ValueError("output does not fit image shards")
+    N, B, mp, nb = lay.N, lay.B, lay.mp, lay.nb
+    need_b = [b for b in range(nb) if any(s[b] >= 0 for s in out.shards)]
+    plan = []
+    for u, lam in enumerate(lay.shards):
+        items = []
+        for r, fs in _rotation_offsets(lam, need_b):
+            for kr in range(kh):
+                for kc in range(kw):
+                    dk, dl = kr - pad, kc - pad
+                    mask = _tap_mask(lay, Ho, Wo, dk, dl)
+                    if not mask.any():
+                        continue
+                    amount = (r * B + dk * mp + dl) % N
+                    pts = {}
+                    for v, mu in enumerate(out.shards):
+                        vec = np.zeros(N)
+                        for b, f in fs.items():
+                            g = mu[b]
+                            if g >= 0:
+                                vec[b * B:(b + 1) * B] = w[g, f, kr, kc] * mask
+                        if vec.any():
+                            pts[v] = vec
+                    if pts:
+                        items.append((amount, pts))
+        plan.append(items)
+    return out, plan
+
+
+def conv2d(be, cts, lay, w, pad=1, stride=1):
+    """Homomorphic conv2d (cross-correlation, zero padding) of an image-sharded
+    input; stride 2 is the stride-1 convolution followed by the downsampling
+    step of the pooling (Section 4.1, strided convolution paragraph)."""
+    out_lay, plan = conv_plan(lay, w, pad)
+    acc = [[] for _ in out_lay.shards]
+    for u, items in enumerate(plan):
+        if not items:
+            continue
+        lvl = be.level(cts[u])
+        rots = be.rotate_hoisted(cts[u], [a for a, _ in items])
+        for rot, (a, pts) in zip(rots, items):
+            for v, vec in pts.items():
+                acc[v].append(be.mul_plain(rot, vec, be.q(lvl)))
+    outs = [be.rescale(_sum(be, terms)) for terms in acc]
+    if stride == 1:
+        return outs, out_lay
+    if stride != 2:
+        raise ValueError("stride must be 1 or 2")
+    return downsample_and_merge(be, outs, out_lay, select=True)
+
+
+# ---------------------------------------------------------------------------
+# average pooling (Section 4.2)
+# ---------------------------------------------------------------------------
+
+def _hmask(lay, i, val):
+    """rot_i of the mask that keeps column 2i of the even rows (valid blocks)."""
+    blk = np.zeros((lay.mp, lay.mp))
+    blk[0:lay.H:2, i] = val
+    return _per_block(lay, blk)
+
+
+def _vmask(lay, j, Wo):
+    """rot_{3j mp/2} of the mask that keeps the left half of row 2j."""
+    blk = np.zeros(lay.B)
+    o = j * lay.mp // 2
+    blk[o:o + Wo] = 1.0
+    return _per_block(lay, blk.reshape(lay.mp, lay.mp))
+
+
+def _fmask(lay, i, j, val):
+    """Fused one-level mask: element (2j, 2i) of each block, after rot_i."""
+    blk = np.zeros((lay.mp, lay.mp))
+    blk[2 * j, i] = val
+    return _per_block(lay, blk)
+
+
+def _per_block(lay, blk, lam=None):
+    """Repeat a block pattern over the blocks that hold a channel (any shard)."""
+    v = np.zeros(lay.N)
+    flat = blk.reshape(-1)
+    valid = [any(s[b] >= 0 for s in lay.shards) for b in range(lay.nb)]
+    for b in range(lay.nb):
+        if valid[b]:
+            v[b * lay.B:(b + 1) * lay.B] = flat
+    return v
+
+
+def downsample(be, cts, lay, select=False, fused=None):
+    """Per-shard downsample: (pool) 2x2 window sums, then horizontal and
+    vertical reduction; (select) the reductions alone keep the top-left element
+    of every 2x2 window (strided convolution).  Returns the shards with an
+    (H/2 x W/2) channel packed at the start of every old block."""
+    mp = lay.mp
+    if select:
+        Ho, Wo, val = (lay.H + 1) // 2, (lay.W + 1) // 2, 1.0
+    else:
+        if lay.H % 2 or lay.W % 2:
+            raise ValueError("average pooling needs even H and W")
+        Ho, Wo, val = lay.H // 2, lay.W // 2, 0.25
+    outs = []
+    for ct in cts:
+        lvl = be.level(ct)
+        if fused is None:
+            use_fused = lvl < 2
+        else:
+            use_fused = fused
+        if lvl < 1:
+            raise ValueError("pooling needs a level")
+        if not select:
+            r = be.rotate_hoisted(ct, [1, mp, mp + 1])
+            D = _sum(be, [ct] + r)
+        else:
+            D = ct
+        rots = be.rotate_hoisted(D, list(range(Wo)))
+        if use_fused:
+            ps = be.q(lvl) / 4.0
+            T = [_sum(be, [be.mul_plain(rots[i], _fmask(lay, i, j, val), ps) for i in range(Wo)])
+                 for j in range(Ho)]
+            moved = [T[0]] + [be.rotate(T[j], 3 * j * mp // 2) for j in range(1, Ho)]
+            outs.append(be.rescale(_sum(be, moved)))
+        else:
+            M1 = be.rescale(_sum(be, [be.mul_plain(rots[i], _hmask(lay, i, val), be.q(lvl)) for i in range(Wo)]))
+            lvl1 = be.level(M1)
+            if lvl1 < 1:
+                raise ValueError("separable pooling needs two levels")
+            rots2 = be.rotate_hoisted(M1, [3 * j * mp // 2 for j in range(Ho)])
+            outs.append(be.rescale(_sum(be, [be.mul_plain(rots2[j], _vmask(lay, j, Wo), be.q(lvl1))
+                                             for j in range(Ho)])))
+    nl = Layout(lay.N, lay.C, Ho, Wo, mp // 2, "image",
+                [[s[b // 4] if b % 4 == 0 else -1 for b in range(4 * lay.nb)] for s in lay.shards])
+    return outs, nl
+
+
+def consolidate(be, cts, lay):
+    """Merge every four consecutive downsampled shards into one,
+    S = S0 + S1>>q + S2>>2q + S3>>3q, q the post-pool block size: shard e of a
+    group moves right by e (new) blocks.  Two shards give two summands and one
+    shard none (Section 4.2, consolidation)."""
+    t = len(cts)
+    Bn = lay.B  # new (post-pool) block size; data sits at block 4b of each shard
+    if t == 1:
+        return cts, lay
+    g = 4 if t >= 4 else t
+    outs, maps = [], []
+    for s0 in range(0, t, g):
+        terms = [cts[s0]] + [be.rotate(cts[s0 + e], -e * Bn) for e in range(1, g)]
+        outs.append(_sum(be, terms))
+        lam = [-1] * lay.nb
+        for e in range(g):
+            src = lay.shards[s0 + e]
+            for b in range(lay.nb // 4):
+                lam[4 * b + e] = src[4 * b]
+        maps.append(lam)
+    return outs, Layout(lay.N, lay.C, lay.H, lay.W, lay.mp, "image", maps)
+
+
+def duplicate(be, ct, lay, d):
+    """S' = S + S>>B' + ... (d summands, shifts by multiples of 4B'/d) for a
+    single shard whose blocks 4b+e (e < 4/d) hold data (Section 4.2,
+    duplication)."""
+    Bn = lay.B
+    step = 4 // d
+    shifts = [-(c * step) * Bn for c in range(1, d)]
+    rots = be.rotate_hoisted(ct, shifts)
+    out = _sum(be, [ct] + rots)
+    lam = list(lay.shards[0])
+    for b in range(lay.nb // 4):
+        for c in range(1, d):
+            for e in range(step):
+                lam[4 * b + c * step + e] = lam[4 * b + e]
+    return out, Layout(lay.N, lay.C, lay.H, lay.W, lay.mp, "image", [lam])
+
+
+def downsample_and_merge(be, cts, lay, select=False, fused=None):
+    outs, nl = downsample(be, cts, lay, select=select, fused=fused)
+    t = len(outs)
+    if t == 1:
+        o, l2 = duplicate(be, outs[0], nl, 4)
+        return [o], l2
+    outs, nl = consolidate(be, outs, nl)
+    if t == 2:
+        o, l2 = duplicate(be, outs[0], nl, 2)
+        return [o], l2
+    return outs, nl
+
+
+def avgpool2x2(be, cts, lay, fused=None):
+    """2x2 average pooling: downsample, consolidate, duplicate (Section 4.2)."""
+    if lay.kind != "image":
+        raise ValueError("image-shard layout expected")
+    return downsample_and_merge(be, cts, lay, select=False, fused=fused)
+
+
+# ---------------------------------------------------------------------------
+# FP64 references (PyTorch semantics)
+# ---------------------------------------------------------------------------
+
+def ref_conv2d(x, w, pad=1, stride=1):
+    """Direct FP64 cross-correlation with zero padding (the paper's Eq. (1))."""
+    x = np.asarray(x, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    C, H, W = x.shape
+    Co, Ci, kh, kw = w.shape
+    xp = np.zeros((C, H + 2 * pad, W + 2 * pad))
+    xp[:, pad:pad + H, pad:pad + W] = x
+    Ho, Wo = H + 2 * pad - kh + 1, W + 2 * pad - kw + 1
+    out = np.zeros((Co, Ho, Wo))
+    for a in range(kh):
+        for b in range(kw):
+            out += np.einsum("gf,fij->gij", w[:, :, a, b], xp[:, a:a + Ho, b:b + Wo])
+    return out[:, ::stride, ::stride]
+
+
+def ref_avgpool2x2(x):
+    C, H, W = x.shape
+    return x[:, : H // 2 * 2, : W // 2 * 2].reshape(C, H // 2, 2, W // 2, 2).mean(axis=(2, 4))

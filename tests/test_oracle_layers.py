@@ -1,0 +1,82 @@
+"""Encrypted oracle end to end (CPU only): decrypted homomorphic conv / pool
+against direct FP64 conv2d / avg_pool2d, max abs error 1e-5, on small rings
+and on the 2N = 2^13 workload (one 32x32x4 image, 3x3 conv 4->4, 2x2 pool)."""
+import numpy as np
+import pytest
+
+from oracle import ckks
+from oracle import he_layers as hl
+
+
+def enc_image(o, x, lay, level, scale, seed):
+    cts = []
+    for u, v in enumerate(hl.pack(x, lay)):
+        cts.append(o.encrypt(o.encode(v, level, scale), seed=seed, index=u))
+    return cts
+
+
+def dec_image(o, cts, lay):
+    return hl.unpack([o.decrypt(c) for c in cts], lay)
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = ckks.Params(8, [60] + [40] * 6, [60, 60, 60], 3)   # P > every digit
+    return p, ckks.Oracle(p, 5)
+
+
+def test_conv_single_shard(small):
+    p, o = small
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, (2, 8, 8))
+    w = rng.normal(0, 0.1, (2, 2, 3, 3))
+    lay = hl.natural_layout(p.N, 2, 8, 8)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 11)
+    outs, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1)
+    assert outs[0].level == 5 and outs[0].scale == 2.0 ** 40
+    assert np.abs(dec_image(o, outs, ol) - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
+def test_conv_image_shards_and_stride2(small):
+    p, o = small
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, (4, 8, 8))     # 2 shards of 2 channels
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    assert len(lay.shards) == 2
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 12)
+    outs, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1, stride=2)
+    assert len(outs) == 1 and outs[0].level == 3
+    assert np.abs(dec_image(o, outs, ol) - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
+
+
+def test_pool_separable_and_fused(small):
+    p, o = small
+    x = np.random.default_rng(2).uniform(-1, 1, (2, 8, 8))
+    lay = hl.natural_layout(p.N, 2, 8, 8)
+    for fused, lvl_out in ((False, 4), (True, 5)):
+        cts = enc_image(o, x, lay, 6, 2.0 ** 40, 13)
+        outs, ol = hl.avgpool2x2(hl.CkksBackend(o), cts, lay, fused=fused)
+        assert outs[0].level == lvl_out
+        assert np.abs(dec_image(o, outs, ol) - hl.ref_avgpool2x2(x)).max() < 1e-5
+
+
+@pytest.mark.slow
+def test_ring_2e13_conv_pool():
+    """2N = 2^13, 3 x 40-bit primes + one 60-bit special prime, scale 2^40: a
+    3x3 conv 4->4 (level 2 -> 1) and the one-level pool (level 1 -> 0, masks at
+    q/4 so the result is decryptable under the 40-bit q_0)."""
+    p = ckks.Params(13, [40, 40, 40], [60], 3)
+    o = ckks.Oracle(p, 2001)
+    rng = np.random.default_rng(1001)
+    x = rng.uniform(-1, 1, (4, 32, 32))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    lay = hl.natural_layout(p.N, 4, 32, 32)
+    be = hl.CkksBackend(o)
+    cts = enc_image(o, x, lay, 2, 2.0 ** 40, 3001)
+    c, cl = hl.conv2d(be, cts, lay, w, pad=1)
+    ref_c = hl.ref_conv2d(x, w, 1)
+    assert np.abs(dec_image(o, c, cl) - ref_c).max() < 1e-5
+    pl_, pll = hl.avgpool2x2(be, c, cl)
+    assert pl_[0].level == 0 and pl_[0].scale == 2.0 ** 38
+    assert np.abs(dec_image(o, pl_, pll) - hl.ref_avgpool2x2(ref_c)).max() < 1e-5

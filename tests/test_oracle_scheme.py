@@ -1,0 +1,162 @@
+"""Pins of the oracle's RNS-CKKS scheme steps (CPU only).
+
+* ModUp (fast base conversion) vs big-integer CRT: every output residue is
+  (X + u*D) mod t for one u in [0, alpha), X the digit's CRT value;
+* ModDown vs big integers: output = floor(X / P) - u for one u in [0, k);
+* rescale vs big integers: output = (X - [X]_{q_l}) / q_l exactly, with the
+  centered residue;
+* encryption/decryption within the fresh-noise bound;
+* rotation commutes with decryption as np.roll; rotation by 0 is the identity;
+  rotations compose; hoisted and one-at-a-time rotations agree bit for bit;
+* plaintext product + rescale decrypts to the slot-wise product.
+"""
+import numpy as np
+import pytest
+
+from oracle import ckks
+
+
+def crt(res, mods):
+    Q = 1
+    for q in mods:
+        Q *= q
+    x = 0
+    for r, q in zip(res, mods):
+        Qi = Q // q
+        x += int(r) * Qi * pow(Qi % q, -1, q)
+    return x % Q, Q
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = ckks.Params(5, [50, 40, 40, 40, 40], [55, 55], 2)   # alpha = 3: digits {0,1,2}, {3,4}
+    return p, ckks.Oracle(p, 77)
+
+
+def test_modup_bigint(small):
+    p, o = small
+    rng = np.random.default_rng(0)
+    level = 4
+    x = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in p.q[: level + 1]])
+    nqp = level + 1 + p.k
+    mods = p.q[: level + 1] + p.p
+    for j in range((level + p.alpha) // p.alpha):
+        out = np.zeros((nqp, p.n), dtype=np.uint64)
+        ckks.lib().orc_modup(p.cref, level, j, ckks.ptr(x), ckks.ptr(out))
+        digit = list(range(j * p.alpha, min((j + 1) * p.alpha, level + 1)))
+        dm = [p.q[i] for i in digit]
+        for c in range(p.n):
+            X, D = crt([x[i, c] for i in digit], dm)
+            us = set()
+            for o_, t in enumerate(mods):
+                if o_ in digit:
+                    assert out[o_, c] == x[o_, c]
+                    continue
+                cand = [u for u in range(len(digit)) if (X + u * D) % t == int(out[o_, c])]
+                assert cand, (j, c, o_)
+                us.add(cand[0])
+            assert len(us) <= 1   # one lift u for the whole coefficient
+
+
+def test_moddown_bigint(small):
+    p, o = small
+    rng = np.random.default_rng(1)
+    level = 3
+    mods = p.q[: level + 1] + p.p
+    x = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in mods])
+    out = np.zeros((level + 1, p.n), dtype=np.uint64)
+    ckks.lib().orc_moddown(p.cref, level, ckks.ptr(x), ckks.ptr(out))
+    P = 1
+    for t in p.p:
+        P *= t
+    for c in range(p.n):
+        X, _ = crt([x[i, c] for i in range(len(mods))], mods)
+        base = X // P
+        cand = [u for u in range(p.k) if all((base - u) % p.q[i] == int(out[i, c]) for i in range(level + 1))]
+        assert cand, c
+
+
+def test_rescale_bigint(small):
+    p, o = small
+    rng = np.random.default_rng(2)
+    level = 4
+    ct = np.stack([np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in p.q[: level + 1]])
+                   for _ in range(2)])
+    out = np.zeros((2, level, p.n), dtype=np.uint64)
+    ckks.lib().orc_rescale(p.cref, level, ckks.ptr(ct), ckks.ptr(out))
+    ql = p.q[level]
+    for poly in range(2):
+        for c in range(p.n):
+            X, _ = crt([ct[poly, i, c] for i in range(level + 1)], p.q[: level + 1])
+            r = X % ql
+            if r > (ql - 1) // 2:
+                r -= ql
+            y = (X - r) // ql
+            assert (X - r) % ql == 0
+            for i in range(level):
+                assert int(out[poly, i, c]) == y % p.q[i]
+
+
+@pytest.fixture(scope="module")
+def med():
+    p = ckks.Params(10, [60, 40, 40, 40, 40, 40], [60, 60], 3)
+    return p, ckks.Oracle(p, 123)
+
+
+def test_encrypt_decrypt(med):
+    p, o = med
+    z = np.random.default_rng(4).uniform(-1, 1, p.N)
+    for level in (0, 2, 5):
+        ct = o.encrypt(o.encode(z, level, 2.0 ** 40), seed=9, index=level)
+        assert ct.data.shape == (2, level + 1, p.n)
+        assert np.abs(o.decrypt(ct) - z).max() < 1e-7
+
+
+def test_encrypt_is_deterministic_and_drops_limbs(med):
+    p, o = med
+    z = np.random.default_rng(5).uniform(-1, 1, p.N)
+    pt5 = o.encode(z, 5, 2.0 ** 40)
+    a = o.encrypt(pt5, seed=3, index=1)
+    b = o.encrypt(pt5, seed=3, index=1)
+    assert (a.data == b.data).all()
+    c = o.encrypt(o.encode(z, 2, 2.0 ** 40), seed=3, index=1)
+    assert (c.data == a.data[:, :3]).all()
+    d = o.encrypt(pt5, seed=3, index=2)
+    assert not (d.data == a.data).all()
+
+
+def test_rotation_invariants(med):
+    p, o = med
+    z = np.random.default_rng(6).uniform(-1, 1, p.N)
+    ct = o.encrypt(o.encode(z, 4, 2.0 ** 40), seed=1)
+    steps = [1, 2, 5, p.N - 1, -3, 64, 0]
+    rots = o.rotate_hoisted(ct, steps)
+    for r, rc in zip(steps, rots):
+        assert np.abs(o.decrypt(rc) - np.roll(z, -r)).max() < 1e-6
+    assert (rots[-1].data == ct.data).all()
+    # one at a time == hoisted, bit for bit (ModUp precedes the automorphism)
+    for r, rc in zip(steps[:3], rots[:3]):
+        assert (o.rotate(ct, r).data == rc.data).all()
+    # composition
+    r2 = o.rotate(o.rotate(ct, 3), 5)
+    assert np.abs(o.decrypt(r2) - np.roll(z, -8)).max() < 1e-6
+    # lower levels (partial last digit, single digit)
+    for level in (0, 1, 3):
+        c2 = o.drop_to(ct, level)
+        assert np.abs(o.decrypt(o.rotate(c2, 7)) - np.roll(z, -7)).max() < 1e-6
+
+
+def test_mul_pt_rescale_add(med):
+    p, o = med
+    rng = np.random.default_rng(7)
+    z, w = rng.uniform(-1, 1, p.N), rng.uniform(-1, 1, p.N)
+    lvl = 5
+    ct = o.encrypt(o.encode(z, lvl, 2.0 ** 40), seed=2)
+    pt = o.encode(w, lvl, float(p.q[lvl]))
+    prod = o.rescale(o.mul_pt(ct, pt))
+    assert prod.level == lvl - 1 and prod.scale == 2.0 ** 40
+    assert np.abs(o.decrypt(prod) - z * w).max() < 1e-6
+    s = o.add(prod, prod)
+    assert np.abs(o.decrypt(s) - 2 * z * w).max() < 1e-6
+    with pytest.raises(ValueError):
+        o.add(prod, ct)
