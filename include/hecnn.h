@@ -1,0 +1,202 @@
+/*
+ * hecnn.h -- C ABI of the MI355X (gfx950) library for homomorphic convolution
+ * and average pooling on RNS-CKKS ciphertexts.
+ *
+ * Source of every operation: "High-Resolution Convolutional Neural Networks on
+ * Homomorphically Encrypted Data via Sharding Ciphertexts" (Maloney et al.,
+ * arXiv 2306.09189).
+ *   - Background, "Homomorphic encryption": ciphertexts over
+ *     Z_Q[x]/(x^n + 1), n = 2N, N real slots, levels, cyclic rotations;
+ *   - Background, "Threat Model": the client encrypts and decrypts, the server
+ *     evaluates with the weights in the clear;
+ *   - Section 4 (packing, sharding, duplication/permutation), Section 4.1
+ *     (convolution), Section 4.2 (average pooling).
+ * The RNS-CKKS conventions the paper leaves to its library are fixed as
+ * follows (and are what "bit-exact" refers to):
+ *   - primes: for each requested size b, the first prime 2^b - j*2n + 1
+ *     (j = 1, 2, ...) not yet taken, in the order q_0..q_L, p_0..p_{k-1};
+ *   - hybrid key switching with dnum digits of alpha = ceil((L+1)/dnum)
+ *     consecutive primes, CRT-idempotent gadget times P, fast base conversion
+ *     on [0, q) residues without correction, ModDown by floor, ModUp before the
+ *     automorphism (so rotate == rotate_hoisted bit for bit);
+ *   - rotation by r > 0 moves slot j+r to slot j (Galois element 5^r mod 2n);
+ *   - rescale rounds with the centered residue of the dropped limb;
+ *   - randomness: ChaCha20 (RFC 8439) streams named (seed, purpose, index),
+ *     fixed-length draws per coefficient; ternary secret, discrete Gaussian
+ *     errors by table inversion;
+ *   - encoding: canonical embedding on real slots, rounded half away from zero
+ *     from a >= 100-bit evaluation of the exact value.
+ *
+ * Conventions of this interface:
+ *   - every handle returned through an `out` pointer is owned by the caller and
+ *     released with the matching *_free; inputs are borrowed, never retained;
+ *   - on error nothing is returned (*out = NULL), the status code says why and
+ *     hec_last_error() gives a message (thread-local, valid until the next
+ *     call on that thread);
+ *   - all device work of a context is ordered on the context's HIP stream;
+ *     calls return after enqueueing, except the ones that hand data back to
+ *     the host (decrypt, export), which synchronize the stream;
+ *   - ciphertexts and plaintexts live in device memory in an internal form;
+ *     export/import use the canonical comparison form: coefficient domain,
+ *     layout [poly][limb][coeff], residues in [0, q_i).
+ * Not thread-safe per context: one thread drives a context at a time.
+ */
+#ifndef HECNN_H
+#define HECNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HEC_OK = 0,
+    HEC_EINVAL = 1,  /* bad argument (sizes, null pointers, parameters)         */
+    HEC_ENOMEM = 2,  /* device or host allocation failed                         */
+    HEC_ELEVEL = 3,  /* level mismatch, or no level left to consume              */
+    HEC_ESCALE = 4,  /* scale mismatch in an addition                            */
+    HEC_ENOKEY = 5,  /* a rotation key the operation needs was not generated     */
+    HEC_ELAYOUT = 6, /* the image layout cannot be planned for this operation    */
+    HEC_EDEVICE = 7, /* HIP runtime error                                        */
+    HEC_EBUSY = 8    /* context already in use                                   */
+} hec_status;
+
+typedef struct hec_ctx hec_ctx;
+typedef struct hec_ct hec_ct;
+typedef struct hec_pt hec_pt;
+typedef struct hec_image hec_image;
+typedef struct hec_conv_plan hec_conv_plan;
+
+/* RNS-CKKS parameters.  Ring degree n = 2^log_n (N = n/2 slots);
+ * ciphertext primes q_0 (q0_bits) and q_1..q_L (q_bits each); k special
+ * primes of p_bits; dnum key-switching digits; sigma the error standard
+ * deviation; secret_dist 0 = uniform ternary (the only one supported).
+ * log_scale is the default encoding scale 2^log_scale used by
+ * he_image_encrypt.  Limits: 10 <= log_n <= 16, L + 1 + k <= 64,
+ * 20 <= bits <= 60, dnum*alpha >= L+1. */
+typedef struct {
+    uint32_t log_n, L, q0_bits, q_bits, k, p_bits, dnum, log_scale;
+    double sigma;
+    uint32_t secret_dist;
+} hec_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Builds the prime chain, the
+ * NTT / base-conversion tables and uploads them. */
+hec_status hec_ctx_create(const hec_params *params, int device, void *hip_stream, hec_ctx **out);
+void hec_ctx_destroy(hec_ctx *ctx);
+const char *hec_last_error(void);
+
+/* The primes of the context: q_0..q_L then p_0..p_{k-1} (L+1+k values). */
+hec_status hec_ctx_primes(const hec_ctx *ctx, uint64_t *primes, size_t cap, size_t *count);
+/* Number of slots N = n/2. */
+uint32_t hec_ctx_slots(const hec_ctx *ctx);
+
+/* ---- keys (Background: threat model; client side) ------------------------- */
+
+/* Secret key, public key and the rotation keys for rot_steps[0..n_steps) from
+ * one seed.  Each key depends only on (seed, its Galois element). */
+hec_status ckks_keygen(hec_ctx *ctx, uint64_t seed, const int32_t *rot_steps, size_t n_steps);
+/* More rotation keys from the seed given to ckks_keygen. */
+hec_status ckks_gen_rotation_keys(hec_ctx *ctx, const int32_t *rot_steps, size_t n_steps);
+/* Device bytes held by the rotation keys. */
+size_t hec_ctx_key_bytes(const hec_ctx *ctx);
+
+/* ---- plaintexts / ciphertexts ---------------------------------------------- */
+
+/* Encode nz <= N real slot values (the rest zero) at `level` and `scale`. */
+hec_status ckks_encode(hec_ctx *ctx, const double *z, size_t nz, uint32_t level, double scale, hec_pt **out);
+/* Public-key encryption of pt with randomness stream index 0 of `seed`. */
+hec_status ckks_encrypt(hec_ctx *ctx, const hec_pt *pt, uint64_t seed, hec_ct **out);
+/* Same with an explicit stream index. */
+hec_status ckks_encrypt_idx(hec_ctx *ctx, const hec_pt *pt, uint64_t seed, uint64_t index, hec_ct **out);
+/* Decrypt and decode the first nz <= N slots into z_out (host).  Synchronizes. */
+hec_status ckks_decrypt(hec_ctx *ctx, const hec_ct *ct, double *z_out, size_t nz);
+
+/* Left rotation by `step` slots (negative = right).  step % N == 0 copies. */
+hec_status ckks_rotate(hec_ctx *ctx, const hec_ct *ct, int32_t step, hec_ct **out);
+/* n rotations of one ciphertext sharing a single ModUp (the "rotations
+ * computed once and cached" of Section 4.1).  outs[0..n) receive new handles. */
+hec_status ckks_rotate_hoisted(hec_ctx *ctx, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
+/* Divide by the last prime and drop it (level - 1, scale / q_level). */
+hec_status ckks_rescale(hec_ctx *ctx, hec_ct *inout);
+/* ct * pt (levels must match; scales multiply). */
+hec_status ckks_mul_pt(hec_ctx *ctx, const hec_ct *ct, const hec_pt *pt, hec_ct **out);
+/* a + b (levels and scales must match). */
+hec_status ckks_add(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
+/* Level and scale of a ciphertext. */
+hec_status ckks_ct_info(const hec_ct *ct, uint32_t *level, double *scale);
+
+/* Canonical export: coeff receives [2][level+1][n] u64 (host).  Synchronizes. */
+hec_status ckks_ct_export(hec_ctx *ctx, const hec_ct *ct, uint64_t *coeff, uint32_t *level, double *scale);
+hec_status ckks_ct_import(hec_ctx *ctx, const uint64_t *coeff, uint32_t level, double scale, hec_ct **out);
+/* Plaintexts as data: [level+1][n] residues, coefficient domain. */
+hec_status ckks_pt_export(hec_ctx *ctx, const hec_pt *pt, uint64_t *coeff, uint32_t *level, double *scale);
+hec_status ckks_pt_import(hec_ctx *ctx, const uint64_t *coeff, uint32_t level, double scale, hec_pt **out);
+/* Signed integer coefficients of an encoding (before reduction into limbs). */
+hec_status ckks_encode_coeffs(hec_ctx *ctx, const double *z, size_t nz, double scale, int64_t *m_out);
+
+/* ---- images (Section 4: packing, sharding, duplication, permutation) ------ */
+
+/* Pack x [C][H][W] (row-major channels, channel-major; zero padding of the
+ * side to a power of two; image shards when m^2 C > N, consecutive d-fold
+ * copies when the image underfills a shard), encode at scale 2^log_scale and
+ * encrypt every shard at `level` with stream (seed, index = shard). */
+hec_status he_image_encrypt(hec_ctx *ctx, const double *x, uint32_t C, uint32_t H, uint32_t W, uint32_t level,
+                            uint64_t seed, hec_image **out);
+/* Decrypt into x_out [C][H][W] in logical channel order.  Synchronizes. */
+hec_status he_image_decrypt(hec_ctx *ctx, const hec_image *img, double *x_out);
+/* Geometry: channels, real side, padded side, number of shards. */
+hec_status he_image_info(const hec_image *img, uint32_t *C, uint32_t *H, uint32_t *W, uint32_t *mp,
+                         uint32_t *n_shards);
+/* Block map of shard u: lam[b] = logical channel of block b (-1 = empty),
+ * N / (mp*mp) entries. */
+hec_status he_image_block_map(const hec_image *img, uint32_t u, int32_t *lam, size_t cap);
+/* Borrowed handle of shard u (valid while img lives). */
+const hec_ct *he_image_shard(const hec_image *img, uint32_t u);
+
+/* Homomorphic conv2d (cross-correlation, zero padding `pad`, stride 1 or 2)
+ * of an image-sharded input with weights w [Co][C][kh][kw] (PyTorch layout,
+ * host doubles), Section 4.1: partial convolutions over hoisted rotations of
+ * every input shard, fused weight x shift-mask plaintexts, one rescale per
+ * output shard; stride 2 = stride-1 convolution + the downsampling of
+ * Section 4.2.  bias must be NULL (reserved).  Consumes one level (three for
+ * stride 2 with the two-level downsample). */
+hec_status he_conv2d_sharded(hec_ctx *ctx, const hec_image *in, const double *w, uint32_t Co, uint32_t kh,
+                             uint32_t kw, uint32_t stride, uint32_t pad, const double *bias, hec_image **out);
+/* The same split in two: plan once (weights encoded and kept in device memory
+ * for the input's layout and level), then run on any image of that layout and
+ * level.  Run is what a server repeats per request. */
+hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const double *w, uint32_t Co, uint32_t kh,
+                                 uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out);
+hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec_image *in, hec_image **out);
+/* Execution mode of plan runs: 0 = batched (hoisted ModUp, rotations of a
+ * shard batched per launch), 1 = plain (every rotation its own ModUp and
+ * launch chain).  Both give identical ciphertexts. */
+hec_status he_conv2d_plan_set_mode(hec_conv_plan *plan, int mode);
+/* Rotation steps a plan (or an avgpool of `like`) needs keys for. */
+hec_status he_conv2d_plan_steps(const hec_conv_plan *plan, int32_t *steps, size_t cap, size_t *count);
+hec_status he_avgpool_steps(hec_ctx *ctx, const hec_image *like, int32_t *steps, size_t cap, size_t *count);
+void he_conv2d_plan_free(hec_conv_plan *plan);
+
+/* 2x2 average pooling, Section 4.2: downsample (2x2 window sums, horizontal
+ * and vertical reduction with masks), consolidate groups of four shards,
+ * duplicate when at most two shards were downsampled.  window must be 2.
+ * Consumes two levels, or one when only one is left (reductions fused). */
+hec_status he_avgpool(hec_ctx *ctx, const hec_image *in, uint32_t window, hec_image **out);
+
+void hec_ct_free(hec_ct *ct);
+void hec_pt_free(hec_pt *pt);
+void hec_image_free(hec_image *img);
+
+/* Wait for all enqueued work of the context. */
+hec_status hec_ctx_sync(hec_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

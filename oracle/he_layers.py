@@ -78,7 +78,7 @@ def natural_layout(N, C, H, W, mp=None):
         if Cp * B <= N:
             d = N // (Cp * B)
             return Layout(N, C, H, W, mp, "image", [[b // d if b // d < C else -1 for b in range(nb)]])
-        t = Cp * B // N
+        t = -(-C // nb)   # no shard is left entirely empty
         return Layout(N, C, H, W, mp, "image",
                       [[u * nb + b if u * nb + b < C else -1 for b in range(nb)] for u in range(t)])
     spc = B // N
@@ -403,9 +403,9 @@ def consolidate(be, cts, lay):
     Bn = lay.B  # new (post-pool) block size; data sits at block 4b of each shard
     if t == 1:
         return cts, lay
-    g = 4 if t >= 4 else t
     outs, maps = [], []
-    for s0 in range(0, t, g):
+    for s0 in range(0, t, 4):
+        g = min(4, t - s0)   # the last group may be short when t is not a multiple of 4
         terms = [cts[s0]] + [be.rotate(cts[s0 + e], -e * Bn) for e in range(1, g)]
         outs.append(_sum(be, terms))
         lam = [-1] * lay.nb

@@ -1,0 +1,120 @@
+// hec_common.h -- internal declarations shared by the host code and the
+// gfx950 kernels of the RNS-CKKS conv/pool library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+// Per-prime constants in device memory.
+struct PrimeC {
+    u64 q;
+    u64 qinv_neg;  // -q^-1 mod 2^64 (Montgomery reduction)
+    u64 r2;        // 2^128 mod q (into Montgomery form)
+    u64 ninv;      // n^-1 mod q
+    u64 ninv_sh;   // Shoup companion of ninv
+};
+
+// Fast base conversion from `nin` limbs to `nout` limbs (ModUp of one digit,
+// or the P -> Q conversion of ModDown):
+//   a_i = [x_i * inv_hat_i]_{q_i},  y_o = sum_i a_i * (hat_i mod t_o)  (mod t_o)
+// hat_m holds (hat_i mod t_o) * 2^64 mod t_o so that one Montgomery reduction
+// of the 128-bit sum gives y_o directly.
+#define HEC_MAX_BCONV_IN 16
+#define HEC_MAX_LIMBS 64
+struct BconvDesc {
+    u32 nin, nout;
+    u32 in_pos[HEC_MAX_BCONV_IN];   // limb positions of the inputs in the source buffer
+    u32 in_prime[HEC_MAX_BCONV_IN];
+    u64 inv_hat[HEC_MAX_BCONV_IN];
+    u64 inv_hat_sh[HEC_MAX_BCONV_IN];
+    u32 out_pos[HEC_MAX_LIMBS];     // limb positions of the outputs in the destination buffer
+    u32 out_prime[HEC_MAX_LIMBS];
+    u64 hat_m[HEC_MAX_BCONV_IN * HEC_MAX_LIMBS];  // [nin][nout]
+};
+
+// Per-level constants of rescale and ModDown.
+struct LevelC {
+    u64 qlinv[HEC_MAX_LIMBS];      // q_level^-1 mod q_i (i < level)
+    u64 qlinv_sh[HEC_MAX_LIMBS];
+    u64 pinv[HEC_MAX_LIMBS];       // P^-1 mod q_i
+    u64 pinv_sh[HEC_MAX_LIMBS];
+};
+
+// Device tables of a context.
+struct DevTables {
+    u32 logn, n, nprimes;
+    const PrimeC *pc;
+    const u64 *tw, *tw_sh;    // psi^brv(k), [prime][n]
+    const u64 *itw, *itw_sh;  // psi^-brv(k), [prime][n]
+};
+
+#define HEC_KS_BATCH 16
+struct KsBatch {
+    const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
+    u64 *out[HEC_KS_BATCH];        // [2][nqp][n]
+    u32 g[HEC_KS_BATCH];
+};
+
+struct CombineBatch {
+    u64 *out[HEC_KS_BATCH];        // [2][nq][n]
+    const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
+    const u64 *y[HEC_KS_BATCH];    // [2][nq][n], NTT form
+    u32 g[HEC_KS_BATCH];
+};
+
+// ---- launchers (hec_kernels.hip) -----------------------------------------
+// NTT / INTT of `nlimbs` limbs of `npolys` polynomials: limb l of poly p sits
+// at base + p*poly_stride + l*n and uses prime pmap[l] (device array).
+void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
+                 hipStream_t st);
+void hec_ntt_inv(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
+                 hipStream_t st);
+
+enum EwOp { EW_ADD = 0, EW_SUB, EW_NEG, EW_MUL_MONT, EW_MAC_MONT, EW_TO_MONT, EW_FROM_MONT, EW_COPY };
+// out = op(a, b) over nlimbs x n per poly (poly strides given separately for out/a/b; b stride may be 0 to
+// broadcast one polynomial over all polys).
+void hec_ew(const DevTables &T, EwOp op, u64 *out, const u64 *a, const u64 *b, size_t so, size_t sa, size_t sb,
+            int npolys, const u32 *pmap, int nlimbs, hipStream_t st);
+
+// out[l][t] = x[t] mod pmap[l] for a signed small polynomial x[n].
+void hec_reduce_i64(const DevTables &T, u64 *out, const int64_t *x, const u32 *pmap, int nlimbs, hipStream_t st);
+
+// ChaCha20 samplers (stream named seed/purpose/index).
+void hec_sample_uniform(const DevTables &T, u64 *out, u64 seed, u32 purpose, u64 index, const u32 *pmap,
+                        int nlimbs, hipStream_t st);
+void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u64 index, int kind,
+                      const u64 *gauss_T, hipStream_t st);
+
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const u64 *src, u64 *dst,
+               size_t src_poly_stride, size_t dst_poly_stride, int npolys, hipStream_t st);
+
+void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
+                  int NLK, hipStream_t st);
+
+void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
+                         const LevelC *lc, const u32 *pmap, hipStream_t st);
+
+void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size_t last_stride, size_t tmp_stride,
+                        int npolys, u32 level, hipStream_t st);
+void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc,
+                        size_t st_, int npolys, u32 level, const LevelC *lc, hipStream_t st);
+
+// swk/pk assembly: b = -a*s + e (+ pm * sigma_g(s) on limbs in [dlo, dhi)), then both b and a into
+// Montgomery form.  sN is s in NTT form (plain), all primes; a, e in NTT form.
+void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g,
+                    u32 dlo, u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st);
+
+// enc: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk in Montgomery form, the rest plain NTT form)
+void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,
+                        const u64 *pk, size_t pk_poly_stride, int nq, hipStream_t st);
+
+// out[k] = in[perm_g(k)] (NTT-domain automorphism) for nlimbs x npolys
+void hec_automorph_ntt(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
+                       u32 g, hipStream_t st);
+
+// dst[p][l] = src[p][l] for nl limbs (generic strided copy)
+void hec_copy_limbs(u64 *dst, const u64 *src, size_t dst_poly_stride, size_t src_poly_stride, int npolys,
+                    size_t limb_elems, hipStream_t st);

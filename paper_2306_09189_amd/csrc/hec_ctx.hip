@@ -1,0 +1,920 @@
+// hec_ctx.hip -- context, keys and the RNS-CKKS ciphertext operations behind
+// the C ABI (include/hecnn.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+#include "hec_internal.h"
+
+using namespace hec;
+
+// purposes of the random streams
+enum { P_SECRET = 1, P_PK_A = 2, P_PK_E = 3, P_SWK_A = 4, P_SWK_E = 5, P_ENC_V = 6, P_ENC_E0 = 7, P_ENC_E1 = 8 };
+
+static thread_local std::string g_err;
+void hec_set_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+extern "C" const char *hec_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// pool
+// ---------------------------------------------------------------------------
+void *DevPool::get(size_t bytes)
+{
+    if (!bytes) bytes = 8;
+    auto it = free_.find(bytes);
+    void *p = nullptr;
+    if (it != free_.end()) {
+        p = it->second;
+        free_.erase(it);
+        bytes_cached -= bytes;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        // give the cached blocks back and retry once
+        for (auto &kv : free_) hipFree(kv.second);
+        free_.clear();
+        bytes_cached = 0;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    }
+    live_[p] = bytes;
+    bytes_live += bytes;
+    return p;
+}
+void DevPool::put(void *p)
+{
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_.emplace(it->second, p);
+    bytes_live -= it->second;
+    bytes_cached += it->second;
+    live_.erase(it);
+}
+void DevPool::release_all()
+{
+    for (auto &kv : free_) hipFree(kv.second);
+    for (auto &kv : live_) hipFree(kv.first);
+    free_.clear();
+    live_.clear();
+    bytes_live = bytes_cached = 0;
+}
+
+uint32_t hec_ctx::galois(int64_t step) const
+{
+    int64_t r = step % (int64_t)N;
+    if (r < 0) r += N;
+    return (uint32_t)powmod(5, (uint64_t)r, 2ull * n);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+static hec_status upload(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    HEC_TRY_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return HEC_OK;
+}
+
+static uint32_t brv(uint32_t x, uint32_t bits)
+{
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+static hec_status build_tables(hec_ctx *c)
+{
+    const uint32_t n = c->n, NLK = c->NLK, L = c->L, k = c->k;
+    const uint64_t r64_q = 0;
+    (void)r64_q;
+    // primes
+    std::vector<PrimeC> pc(NLK);
+    std::vector<u64> tw((size_t)NLK * n), twsh((size_t)NLK * n), itw((size_t)NLK * n), itwsh((size_t)NLK * n);
+    for (uint32_t i = 0; i < NLK; i++) {
+        u64 q = c->mod[i];
+        // -q^-1 mod 2^64 by Newton iteration
+        u64 inv = 1;
+        for (int it = 0; it < 7; it++) inv *= 2 - q * inv;
+        pc[i].q = q;
+        pc[i].qinv_neg = (u64)(0 - inv);
+        u64 r1 = (u64)(((u128)1 << 64) % q);
+        pc[i].r2 = mulmod(r1, r1, q);
+        pc[i].ninv = invmod(n % q, q);
+        pc[i].ninv_sh = shoup_of(pc[i].ninv, q);
+        u64 psi = find_root_2n(q, n), ipsi = invmod(psi, q);
+        std::vector<u64> pw(n), ipw(n);
+        pw[0] = ipw[0] = 1;
+        for (uint32_t t = 1; t < n; t++) {
+            pw[t] = mulmod(pw[t - 1], psi, q);
+            ipw[t] = mulmod(ipw[t - 1], ipsi, q);
+        }
+        for (uint32_t t = 0; t < n; t++) {
+            u64 w = pw[brv(t, c->logn)], iw = ipw[brv(t, c->logn)];
+            tw[(size_t)i * n + t] = w;
+            twsh[(size_t)i * n + t] = shoup_of(w, q);
+            itw[(size_t)i * n + t] = iw;
+            itwsh[(size_t)i * n + t] = shoup_of(iw, q);
+        }
+    }
+    c->d_pc = (PrimeC *)c->pool.get(sizeof(PrimeC) * NLK);
+    c->d_tw = c->alloc((size_t)NLK * n);
+    c->d_twsh = c->alloc((size_t)NLK * n);
+    c->d_itw = c->alloc((size_t)NLK * n);
+    c->d_itwsh = c->alloc((size_t)NLK * n);
+    if (!c->d_pc || !c->d_tw || !c->d_twsh || !c->d_itw || !c->d_itwsh) HEC_FAIL(HEC_ENOMEM, "table allocation");
+    HEC_CHECK(upload(c->d_pc, pc.data(), sizeof(PrimeC) * NLK, c->st));
+    HEC_CHECK(upload(c->d_tw, tw.data(), tw.size() * 8, c->st));
+    HEC_CHECK(upload(c->d_twsh, twsh.data(), twsh.size() * 8, c->st));
+    HEC_CHECK(upload(c->d_itw, itw.data(), itw.size() * 8, c->st));
+    HEC_CHECK(upload(c->d_itwsh, itwsh.data(), itwsh.size() * 8, c->st));
+
+    // limb -> prime maps: identity, then QP_l = q_0..q_l, p_0..p_{k-1} per level
+    std::vector<u32> maps;
+    for (uint32_t i = 0; i < NLK; i++) maps.push_back(i);
+    c->qp_off.resize(L + 1);
+    for (uint32_t l = 0; l <= L; l++) {
+        c->qp_off[l] = maps.size();
+        for (uint32_t i = 0; i <= l; i++) maps.push_back(i);
+        for (uint32_t t = 0; t < k; t++) maps.push_back(L + 1 + t);
+    }
+    c->d_maps = (u32 *)c->pool.get(maps.size() * 4);
+    HEC_CHECK(upload(c->d_maps, maps.data(), maps.size() * 4, c->st));
+
+    // ModUp descriptors [level][digit] and ModDown descriptors [level]
+    c->h_modup.assign((size_t)(L + 1) * c->dnum, BconvDesc{});
+    c->h_moddown.assign(L + 1, BconvDesc{});
+    std::vector<LevelC> lv(L + 1);
+    for (uint32_t l = 0; l <= L; l++) {
+        const uint32_t nq = l + 1, nqp = nq + k;
+        std::vector<uint32_t> qp(nqp);
+        for (uint32_t o = 0; o < nqp; o++) qp[o] = o < nq ? o : L + 1 + (o - nq);
+        const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+        for (uint32_t j = 0; j < beta; j++) {
+            BconvDesc &d = c->h_modup[(size_t)l * c->dnum + j];
+            uint32_t lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, nq);
+            d.nin = hi - lo;
+            for (uint32_t a = 0; a < d.nin; a++) {
+                uint32_t i = lo + a;
+                u64 qi = c->mod[i], hat = 1;
+                for (uint32_t b = lo; b < hi; b++)
+                    if (b != i) hat = mulmod(hat, c->mod[b] % qi, qi);
+                d.in_pos[a] = i;
+                d.in_prime[a] = i;
+                d.inv_hat[a] = invmod(hat, qi);
+                d.inv_hat_sh[a] = shoup_of(d.inv_hat[a], qi);
+            }
+            d.nout = 0;
+            for (uint32_t o = 0; o < nqp; o++) {
+                if (o >= lo && o < hi) continue;
+                d.out_pos[d.nout] = o;
+                d.out_prime[d.nout] = qp[o];
+                d.nout++;
+            }
+            for (uint32_t a = 0; a < d.nin; a++) {
+                uint32_t i = lo + a;
+                for (uint32_t b = 0; b < d.nout; b++) {
+                    u64 t = c->mod[d.out_prime[b]], hat = 1;
+                    for (uint32_t i2 = lo; i2 < hi; i2++)
+                        if (i2 != i) hat = mulmod(hat, c->mod[i2] % t, t);
+                    u64 r1 = (u64)(((u128)1 << 64) % t);
+                    d.hat_m[a * d.nout + b] = mulmod(hat, r1, t);
+                }
+            }
+        }
+        // ModDown: inputs are the k P-limbs (positions nq..nq+k-1 of a QP_l buffer), outputs q_0..q_l
+        BconvDesc &d = c->h_moddown[l];
+        d.nin = k;
+        for (uint32_t t = 0; t < k; t++) {
+            u64 pt = c->mod[L + 1 + t], hat = 1;
+            for (uint32_t t2 = 0; t2 < k; t2++)
+                if (t2 != t) hat = mulmod(hat, c->mod[L + 1 + t2] % pt, pt);
+            d.in_pos[t] = nq + t;
+            d.in_prime[t] = L + 1 + t;
+            d.inv_hat[t] = invmod(hat, pt);
+            d.inv_hat_sh[t] = shoup_of(d.inv_hat[t], pt);
+        }
+        d.nout = nq;
+        for (uint32_t i = 0; i < nq; i++) {
+            d.out_pos[i] = i;
+            d.out_prime[i] = i;
+        }
+        for (uint32_t t = 0; t < k; t++)
+            for (uint32_t i = 0; i < nq; i++) {
+                u64 qi = c->mod[i], hat = 1;
+                for (uint32_t t2 = 0; t2 < k; t2++)
+                    if (t2 != t) hat = mulmod(hat, c->mod[L + 1 + t2] % qi, qi);
+                u64 r1 = (u64)(((u128)1 << 64) % qi);
+                d.hat_m[t * nq + i] = mulmod(hat, r1, qi);
+            }
+        // rescale and ModDown scalars
+        for (uint32_t i = 0; i < nq; i++) {
+            u64 qi = c->mod[i];
+            if (i < l) {
+                lv[l].qlinv[i] = invmod(c->mod[l] % qi, qi);
+                lv[l].qlinv_sh[i] = shoup_of(lv[l].qlinv[i], qi);
+            }
+            u64 P = 1;
+            for (uint32_t t = 0; t < k; t++) P = mulmod(P, c->mod[L + 1 + t] % qi, qi);
+            lv[l].pinv[i] = invmod(P, qi);
+            lv[l].pinv_sh[i] = shoup_of(lv[l].pinv[i], qi);
+        }
+    }
+    c->d_modup = (BconvDesc *)c->pool.get(sizeof(BconvDesc) * c->h_modup.size());
+    c->d_moddown = (BconvDesc *)c->pool.get(sizeof(BconvDesc) * c->h_moddown.size());
+    c->d_lvl = (LevelC *)c->pool.get(sizeof(LevelC) * lv.size());
+    HEC_CHECK(upload(c->d_modup, c->h_modup.data(), sizeof(BconvDesc) * c->h_modup.size(), c->st));
+    HEC_CHECK(upload(c->d_moddown, c->h_moddown.data(), sizeof(BconvDesc) * c->h_moddown.size(), c->st));
+    HEC_CHECK(upload(c->d_lvl, lv.data(), sizeof(LevelC) * lv.size(), c->st));
+
+    std::vector<u64> pm(NLK, 0);
+    for (uint32_t i = 0; i <= L; i++) {
+        u64 P = 1;
+        for (uint32_t t = 0; t < k; t++) P = mulmod(P, c->mod[L + 1 + t] % c->mod[i], c->mod[i]);
+        pm[i] = P;
+    }
+    c->d_pmodq = c->alloc(NLK);
+    HEC_CHECK(upload(c->d_pmodq, pm.data(), NLK * 8, c->st));
+    u64 gT[19];
+    gauss_table(c->prm.sigma, gT);
+    c->d_gauss = c->alloc(19);
+    HEC_CHECK(upload(c->d_gauss, gT, sizeof(gT), c->st));
+
+    c->T.logn = c->logn;
+    c->T.n = n;
+    c->T.nprimes = NLK;
+    c->T.pc = c->d_pc;
+    c->T.tw = c->d_tw;
+    c->T.tw_sh = c->d_twsh;
+    c->T.itw = c->d_itw;
+    c->T.itw_sh = c->d_itwsh;
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    return HEC_OK;
+}
+
+extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_stream, hec_ctx **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) HEC_FAIL(HEC_EINVAL, "params is NULL");
+    if (p->log_n < 5 || p->log_n > 16) HEC_FAIL(HEC_EINVAL, "log_n must be in [5, 16]");
+    if (p->L + 1 + p->k > HEC_MAX_LIMBS) HEC_FAIL(HEC_EINVAL, "too many primes");
+    if (p->k < 1 || p->k > HEC_MAX_BCONV_IN) HEC_FAIL(HEC_EINVAL, "need 1..16 special primes");
+    for (uint32_t b : {p->q0_bits, p->q_bits, p->p_bits})
+        if (b < 20 || b > 60) HEC_FAIL(HEC_EINVAL, "prime sizes must be in [20, 60] bits");
+    if (p->dnum < 1 || p->dnum > p->L + 1) HEC_FAIL(HEC_EINVAL, "dnum must be in [1, L+1]");
+    uint32_t alpha = (p->L + 1 + p->dnum - 1) / p->dnum;
+    if (alpha > HEC_MAX_BCONV_IN) HEC_FAIL(HEC_EINVAL, "digits larger than 16 primes are not supported");
+    if (p->secret_dist != 0) HEC_FAIL(HEC_EINVAL, "only the uniform ternary secret is supported");
+    int ndev = 0;
+    HEC_TRY_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) HEC_FAIL(HEC_EDEVICE, "no HIP device %d", device);
+    HEC_TRY_HIP(hipSetDevice(device));
+
+    std::unique_ptr<hec_ctx> c(new hec_ctx());
+    c->prm = *p;
+    c->dev = device;
+    c->st = (hipStream_t)hip_stream;
+    c->logn = p->log_n;
+    c->n = 1u << p->log_n;
+    c->N = c->n / 2;
+    c->L = p->L;
+    c->k = p->k;
+    c->alpha = alpha;
+    c->dnum = (p->L + 1 + alpha - 1) / alpha;
+    c->NLK = p->L + 1 + p->k;
+    std::vector<uint64_t> taken;
+    for (uint32_t i = 0; i < c->NLK; i++) {
+        uint32_t b = i == 0 ? p->q0_bits : (i <= p->L ? p->q_bits : p->p_bits);
+        uint64_t q = find_prime(b, c->n, taken);
+        if (!q) HEC_FAIL(HEC_EINVAL, "no %u-bit prime = 1 mod 2n left", b);
+        taken.push_back(q);
+    }
+    c->mod = taken;
+    // the exact accumulations need alpha * q_max < 2^64 and k * p_max < 2^64
+    for (uint64_t q : c->mod)
+        if ((u128)q * std::max(alpha, c->k) >= ((u128)1 << 64)) HEC_FAIL(HEC_EINVAL, "primes too large for digits");
+    c->enc.reset(new Encoder(c->logn));
+    hec_status s = build_tables(c.get());
+    if (s != HEC_OK) {
+        c->pool.release_all();
+        return s;
+    }
+    *out = c.release();
+    return HEC_OK;
+}
+
+extern "C" void hec_ctx_destroy(hec_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->dev);
+    hipStreamSynchronize(c->st);
+    c->pool.release_all();
+    delete c;
+}
+
+extern "C" hec_status hec_ctx_sync(hec_ctx *c)
+{
+    if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    return HEC_OK;
+}
+
+extern "C" hec_status hec_ctx_primes(const hec_ctx *c, uint64_t *primes, size_t cap, size_t *count)
+{
+    if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
+    if (count) *count = c->mod.size();
+    if (primes) {
+        if (cap < c->mod.size()) HEC_FAIL(HEC_EINVAL, "capacity too small");
+        memcpy(primes, c->mod.data(), c->mod.size() * 8);
+    }
+    return HEC_OK;
+}
+
+extern "C" uint32_t hec_ctx_slots(const hec_ctx *c) { return c ? c->N : 0; }
+
+extern "C" size_t hec_ctx_key_bytes(const hec_ctx *c)
+{
+    return c ? c->rotkeys.size() * (size_t)c->dnum * 2 * c->NLK * c->n * 8 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale)
+{
+    u64 *d = c->alloc((size_t)2 * (level + 1) * c->n);
+    if (!d) return nullptr;
+    hec_ct *ct = new hec_ct();
+    ct->ctx = c;
+    ct->level = level;
+    ct->scale = scale;
+    ct->d = d;
+    return ct;
+}
+hec_ct *ct_clone(const hec_ct *a)
+{
+    hec_ct *r = ct_new(a->ctx, a->level, a->scale);
+    if (!r) return nullptr;
+    hipMemcpyAsync(r->d, a->d, (size_t)2 * (a->level + 1) * a->ctx->n * 8, hipMemcpyDeviceToDevice, a->ctx->st);
+    return r;
+}
+void ct_free(hec_ct *p)
+{
+    if (!p) return;
+    p->ctx->release(p->d);
+    delete p;
+}
+void pt_free(hec_pt *p)
+{
+    if (!p) return;
+    p->ctx->release(p->d);
+    delete p;
+}
+extern "C" void hec_ct_free(hec_ct *ct) { ct_free(ct); }
+extern "C" void hec_pt_free(hec_pt *pt) { pt_free(pt); }
+
+extern "C" hec_status ckks_ct_info(const hec_ct *ct, uint32_t *level, double *scale)
+{
+    if (!ct) HEC_FAIL(HEC_EINVAL, "ct is NULL");
+    if (level) *level = ct->level;
+    if (scale) *scale = ct->scale;
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+static hec_status gen_swk(hec_ctx *c, uint32_t g)
+{
+    if (c->rotkeys.count(g)) return HEC_OK;
+    const size_t n = c->n, NLK = c->NLK;
+    u64 *key = c->alloc((size_t)c->dnum * 2 * NLK * n);
+    u64 *e = c->alloc(NLK * n);
+    int64_t *es = (int64_t *)c->alloc(n);
+    if (!key || !e || !es) HEC_FAIL(HEC_ENOMEM, "rotation key allocation");
+    for (uint32_t j = 0; j < c->dnum; j++) {
+        u64 *b = key + (size_t)j * 2 * NLK * n, *a = b + NLK * n;
+        uint64_t idx = ((uint64_t)g << 8) | j;
+        hec_sample_uniform(c->T, a, c->key_seed, P_SWK_A, idx, c->idmap(), NLK, c->st);
+        hec_ntt_fwd(c->T, a, 0, 1, c->idmap(), NLK, c->st);
+        hec_sample_small(c->T, es, c->key_seed, P_SWK_E, idx, 1, c->d_gauss, c->st);
+        hec_reduce_i64(c->T, e, es, c->idmap(), NLK, c->st);
+        hec_ntt_fwd(c->T, e, 0, 1, c->idmap(), NLK, c->st);
+        uint32_t dlo = j * c->alpha, dhi = std::min((j + 1) * c->alpha, c->L + 1);
+        hec_key_finish(c->T, b, a, e, c->d_sN, c->d_pmodq, g, dlo, dhi, NLK, c->idmap(), c->st);
+    }
+    c->release(e);
+    c->release(es);
+    HEC_TRY_HIP(hipGetLastError());
+    c->rotkeys[g] = key;
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_keygen(hec_ctx *c, uint64_t seed, const int32_t *steps, size_t nsteps)
+{
+    if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
+    if (nsteps && !steps) HEC_FAIL(HEC_EINVAL, "steps is NULL");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, NLK = c->NLK, nq = c->L + 1;
+    for (auto &kv : c->rotkeys) c->release(kv.second);
+    c->rotkeys.clear();
+    for (auto &kv : c->mask_cache) pt_free(kv.second);
+    c->mask_cache.clear();
+    c->key_seed = seed;
+    if (!c->d_sN) {
+        c->d_sN = c->alloc(NLK * n);
+        c->d_sM = c->alloc(NLK * n);
+        c->d_pk = c->alloc(2 * nq * n);
+    }
+    int64_t *sm = (int64_t *)c->alloc(n);
+    u64 *e = c->alloc(nq * n);
+    if (!c->d_sN || !c->d_sM || !c->d_pk || !sm || !e) HEC_FAIL(HEC_ENOMEM, "key allocation");
+    hec_sample_small(c->T, sm, seed, P_SECRET, 0, 0, c->d_gauss, c->st);
+    hec_reduce_i64(c->T, c->d_sN, sm, c->idmap(), NLK, c->st);
+    hec_ntt_fwd(c->T, c->d_sN, 0, 1, c->idmap(), NLK, c->st);
+    hec_ew(c->T, EW_TO_MONT, c->d_sM, c->d_sN, nullptr, 0, 0, 0, 1, c->idmap(), NLK, c->st);
+    // pk = (-a s + e, a)
+    u64 *b = c->d_pk, *a = c->d_pk + nq * n;
+    hec_sample_uniform(c->T, a, seed, P_PK_A, 0, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, a, 0, 1, c->idmap(), nq, c->st);
+    hec_sample_small(c->T, sm, seed, P_PK_E, 0, 1, c->d_gauss, c->st);
+    hec_reduce_i64(c->T, e, sm, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, e, 0, 1, c->idmap(), nq, c->st);
+    hec_key_finish(c->T, b, a, e, c->d_sN, nullptr, 1, 0, 0, nq, c->idmap(), c->st);
+    c->release(sm);
+    c->release(e);
+    HEC_TRY_HIP(hipGetLastError());
+    c->have_keys = true;
+    return ckks_gen_rotation_keys(c, steps, nsteps);
+}
+
+extern "C" hec_status ckks_gen_rotation_keys(hec_ctx *c, const int32_t *steps, size_t nsteps)
+{
+    if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
+    if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "ckks_keygen has not been called");
+    if (nsteps && !steps) HEC_FAIL(HEC_EINVAL, "steps is NULL");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    for (size_t i = 0; i < nsteps; i++) {
+        uint32_t g = c->galois(steps[i]);
+        if (g == 1) continue;
+        HEC_CHECK(gen_swk(c, g));
+    }
+    return HEC_OK;
+}
+
+bool have_rotkey(hec_ctx *c, int32_t step)
+{
+    uint32_t g = c->galois(step);
+    return g == 1 || c->rotkeys.count(g);
+}
+
+// ---------------------------------------------------------------------------
+// encoding
+// ---------------------------------------------------------------------------
+static hec_status upload_pt(hec_ctx *c, const int64_t *m, uint32_t level, double scale, hec_pt **out)
+{
+    const size_t n = c->n, nq = level + 1;
+    int64_t *dm = (int64_t *)c->alloc(n);
+    u64 *d = c->alloc(nq * n);
+    if (!dm || !d) HEC_FAIL(HEC_ENOMEM, "plaintext allocation");
+    HEC_TRY_HIP(hipMemcpyAsync(dm, m, n * 8, hipMemcpyHostToDevice, c->st));
+    hec_reduce_i64(c->T, d, dm, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, d, 0, 1, c->idmap(), nq, c->st);
+    hec_ew(c->T, EW_TO_MONT, d, d, nullptr, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    // the host buffer may be reused by the caller: wait for the copy
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    c->release(dm);
+    hec_pt *p = new hec_pt();
+    p->ctx = c;
+    p->level = level;
+    p->scale = scale;
+    p->d = d;
+    *out = p;
+    return HEC_OK;
+}
+
+hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size_t nz, uint32_t level, double scale,
+                          std::vector<hec_pt *> &out)
+{
+    const size_t cnt = z.size(), n = c->n;
+    std::vector<int64_t> m(cnt * n);
+    std::vector<char> ok(cnt, 1);
+    unsigned nth = std::max(1u, std::min((unsigned)cnt, std::thread::hardware_concurrency()));
+    if (nth > 32) nth = 32;
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; t++)
+        th.emplace_back([&, t]() {
+            for (size_t i = t; i < cnt; i += nth) ok[i] = c->enc->encode(z[i], nz, scale, &m[i * n]);
+        });
+    for (auto &x : th) x.join();
+    out.assign(cnt, nullptr);
+    for (size_t i = 0; i < cnt; i++) {
+        if (!ok[i]) {
+            for (auto *p : out) pt_free(p);
+            HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62 (scale too large for the values)");
+        }
+        hec_status s = upload_pt(c, &m[i * n], level, scale, &out[i]);
+        if (s != HEC_OK) {
+            for (auto *p : out) pt_free(p);
+            return s;
+        }
+    }
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_encode_coeffs(hec_ctx *c, const double *z, size_t nz, double scale, int64_t *m)
+{
+    if (!c || !m || (nz && !z)) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (nz > c->N) HEC_FAIL(HEC_EINVAL, "more values than slots");
+    if (!c->enc->encode(z, nz, scale, m)) HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62");
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_encode(hec_ctx *c, const double *z, size_t nz, uint32_t level, double scale, hec_pt **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || (nz && !z)) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (nz > c->N) HEC_FAIL(HEC_EINVAL, "more values than slots");
+    if (level > c->L) HEC_FAIL(HEC_ELEVEL, "level above L");
+    if (!(scale > 0)) HEC_FAIL(HEC_EINVAL, "scale must be positive");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    std::vector<hec_pt *> v;
+    HEC_CHECK(pt_encode_many(c, {z}, nz, level, scale, v));
+    *out = v[0];
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_pt_import(hec_ctx *c, const uint64_t *coeff, uint32_t level, double scale, hec_pt **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !coeff) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (level > c->L) HEC_FAIL(HEC_ELEVEL, "level above L");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, nq = level + 1;
+    for (size_t i = 0; i < nq; i++)
+        for (size_t t = 0; t < n; t++)
+            if (coeff[i * n + t] >= c->mod[i]) HEC_FAIL(HEC_EINVAL, "residue not reduced");
+    u64 *d = c->alloc(nq * n);
+    if (!d) HEC_FAIL(HEC_ENOMEM, "plaintext allocation");
+    HEC_TRY_HIP(hipMemcpyAsync(d, coeff, nq * n * 8, hipMemcpyHostToDevice, c->st));
+    hec_ntt_fwd(c->T, d, 0, 1, c->idmap(), nq, c->st);
+    hec_ew(c->T, EW_TO_MONT, d, d, nullptr, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    hec_pt *p = new hec_pt();
+    p->ctx = c;
+    p->level = level;
+    p->scale = scale;
+    p->d = d;
+    *out = p;
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_pt_export(hec_ctx *c, const hec_pt *pt, uint64_t *coeff, uint32_t *level, double *scale)
+{
+    if (!c || !pt || !coeff) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, nq = pt->level + 1;
+    u64 *t = c->alloc(nq * n);
+    if (!t) HEC_FAIL(HEC_ENOMEM, "export buffer");
+    hec_ew(c->T, EW_FROM_MONT, t, pt->d, nullptr, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    hec_ntt_inv(c->T, t, 0, 1, c->idmap(), nq, c->st);
+    HEC_TRY_HIP(hipMemcpyAsync(coeff, t, nq * n * 8, hipMemcpyDeviceToHost, c->st));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    c->release(t);
+    if (level) *level = pt->level;
+    if (scale) *scale = pt->scale;
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// encryption / decryption
+// ---------------------------------------------------------------------------
+extern "C" hec_status ckks_encrypt_idx(hec_ctx *c, const hec_pt *pt, uint64_t seed, uint64_t index, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !pt) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "no public key (call ckks_keygen)");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, nq = pt->level + 1;
+    hec_ct *ct = ct_new(c, pt->level, pt->scale);
+    u64 *buf = c->alloc(4 * nq * n);
+    int64_t *sm = (int64_t *)c->alloc(n);
+    if (!ct || !buf || !sm) HEC_FAIL(HEC_ENOMEM, "encryption buffers");
+    u64 *v = buf, *e0 = buf + nq * n, *e1 = buf + 2 * nq * n, *m = buf + 3 * nq * n;
+    hec_sample_small(c->T, sm, seed, P_ENC_V, index, 0, c->d_gauss, c->st);
+    hec_reduce_i64(c->T, v, sm, c->idmap(), nq, c->st);
+    hec_sample_small(c->T, sm, seed, P_ENC_E0, index, 1, c->d_gauss, c->st);
+    hec_reduce_i64(c->T, e0, sm, c->idmap(), nq, c->st);
+    hec_sample_small(c->T, sm, seed, P_ENC_E1, index, 1, c->d_gauss, c->st);
+    hec_reduce_i64(c->T, e1, sm, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, buf, 0, 1, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, e0, 0, 1, c->idmap(), nq, c->st);
+    hec_ntt_fwd(c->T, e1, 0, 1, c->idmap(), nq, c->st);
+    hec_ew(c->T, EW_FROM_MONT, m, pt->d, nullptr, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    hec_encrypt_finish(c->T, ct->d, v, e0, e1, m, c->d_pk, (size_t)(c->L + 1) * n, nq, c->st);
+    c->release(buf);
+    c->release(sm);
+    HEC_TRY_HIP(hipGetLastError());
+    *out = ct;
+    return HEC_OK;
+}
+extern "C" hec_status ckks_encrypt(hec_ctx *c, const hec_pt *pt, uint64_t seed, hec_ct **out)
+{
+    return ckks_encrypt_idx(c, pt, seed, 0, out);
+}
+
+// centered CRT of [nq][n] residues into doubles (Garner mixed radix)
+static void crt_to_double(const hec_ctx *c, const u64 *res, uint32_t nq, double *out)
+{
+    const size_t n = c->n;
+    std::vector<u64> inv(nq, 0);  // (q_0 ... q_{i-1})^-1 mod q_i
+    for (uint32_t i = 1; i < nq; i++) {
+        u64 qi = c->mod[i], pr = 1;
+        for (uint32_t j = 0; j < i; j++) pr = mulmod(pr, c->mod[j] % qi, qi);
+        inv[i] = invmod(pr, qi);
+    }
+    std::vector<u64> v(nq);
+    for (size_t t = 0; t < n; t++) {
+        for (uint32_t i = 0; i < nq; i++) {
+            u64 qi = c->mod[i];
+            // value of the known digits mod q_i, Horner from the top
+            u64 acc = 0;
+            for (int j = (int)i - 1; j >= 0; j--) acc = (mulmod(acc, c->mod[j] % qi, qi) + v[j] % qi) % qi;
+            u64 r = res[i * n + t];
+            v[i] = mulmod((r + qi - acc) % qi, inv[i] ? inv[i] : 1, qi);
+        }
+        bool negative = 2 * (u128)v[nq - 1] >= (u128)c->mod[nq - 1];
+        long double val = 0;
+        for (int j = (int)nq - 1; j >= 0; j--) {
+            u64 d = negative ? c->mod[j] - 1 - v[j] : v[j];
+            val = val * (long double)c->mod[j] + (long double)d;
+        }
+        out[t] = negative ? (double)(-(val + 1)) : (double)val;
+    }
+}
+
+static hec_status decrypt_coeffs(hec_ctx *c, const hec_ct *ct, std::vector<u64> &res)
+{
+    const size_t n = c->n, nq = ct->level + 1;
+    u64 *t = c->alloc(nq * n);
+    if (!t) HEC_FAIL(HEC_ENOMEM, "decryption buffer");
+    hec_ew(c->T, EW_MUL_MONT, t, ct->d + nq * n, c->d_sM, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    hec_ew(c->T, EW_ADD, t, t, ct->d, 0, 0, 0, 1, c->idmap(), nq, c->st);
+    hec_ntt_inv(c->T, t, 0, 1, c->idmap(), nq, c->st);
+    res.resize(nq * n);
+    HEC_TRY_HIP(hipMemcpyAsync(res.data(), t, nq * n * 8, hipMemcpyDeviceToHost, c->st));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    c->release(t);
+    return HEC_OK;
+}
+
+hec_status decrypt_slots(hec_ctx *c, const hec_ct *ct, double *z, size_t nz)
+{
+    std::vector<u64> res;
+    HEC_CHECK(decrypt_coeffs(c, ct, res));
+    std::vector<double> m(c->n);
+    crt_to_double(c, res.data(), ct->level + 1, m.data());
+    c->enc->decode(m.data(), ct->scale, z, nz);
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_decrypt(hec_ctx *c, const hec_ct *ct, double *z, size_t nz)
+{
+    if (!c || !ct || (nz && !z)) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "no secret key");
+    if (nz > c->N) HEC_FAIL(HEC_EINVAL, "more values than slots");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    return decrypt_slots(c, ct, z, nz);
+}
+
+// ---------------------------------------------------------------------------
+// import / export
+// ---------------------------------------------------------------------------
+extern "C" hec_status ckks_ct_export(hec_ctx *c, const hec_ct *ct, uint64_t *coeff, uint32_t *level, double *scale)
+{
+    if (!c || !ct || !coeff) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, nq = ct->level + 1;
+    u64 *t = c->alloc(2 * nq * n);
+    if (!t) HEC_FAIL(HEC_ENOMEM, "export buffer");
+    HEC_TRY_HIP(hipMemcpyAsync(t, ct->d, 2 * nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+    hec_ntt_inv(c->T, t, nq * n, 2, c->idmap(), nq, c->st);
+    HEC_TRY_HIP(hipMemcpyAsync(coeff, t, 2 * nq * n * 8, hipMemcpyDeviceToHost, c->st));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    c->release(t);
+    if (level) *level = ct->level;
+    if (scale) *scale = ct->scale;
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_ct_import(hec_ctx *c, const uint64_t *coeff, uint32_t level, double scale, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !coeff) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (level > c->L) HEC_FAIL(HEC_ELEVEL, "level above L");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n, nq = level + 1;
+    for (size_t p = 0; p < 2; p++)
+        for (size_t i = 0; i < nq; i++)
+            for (size_t t = 0; t < n; t++)
+                if (coeff[(p * nq + i) * n + t] >= c->mod[i]) HEC_FAIL(HEC_EINVAL, "residue not reduced");
+    hec_ct *ct = ct_new(c, level, scale);
+    if (!ct) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    HEC_TRY_HIP(hipMemcpyAsync(ct->d, coeff, 2 * nq * n * 8, hipMemcpyHostToDevice, c->st));
+    hec_ntt_fwd(c->T, ct->d, nq * n, 2, c->idmap(), nq, c->st);
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    *out = ct;
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rotations (hybrid key switching)
+// ---------------------------------------------------------------------------
+hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt, hec_ct **outs)
+{
+    const size_t n = c->n;
+    const uint32_t lvl = ct->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    std::vector<size_t> todo;
+    for (size_t i = 0; i < cnt; i++) outs[i] = nullptr;
+    for (size_t i = 0; i < cnt; i++) {
+        uint32_t g = c->galois(steps[i]);
+        if (g == 1) continue;
+        if (!c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", steps[i]);
+        todo.push_back(i);
+    }
+    for (size_t i = 0; i < cnt; i++)
+        if (c->galois(steps[i]) == 1) {
+            outs[i] = ct_clone(ct);
+            if (!outs[i]) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+        }
+    if (todo.empty()) return HEC_OK;
+    // ModUp of c1, once
+    const u64 *c0 = ct->d, *c1 = ct->d + nq * n;
+    u64 *cc = c->alloc(nq * n);
+    u64 *D = c->alloc((size_t)beta * nqp * n);
+    if (!cc || !D) HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
+    HEC_TRY_HIP(hipMemcpyAsync(cc, c1, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+    hec_ntt_inv(c->T, cc, 0, 1, c->idmap(), nq, c->st);
+    for (uint32_t j = 0; j < beta; j++) {
+        u64 *Dj = D + (size_t)j * nqp * n;
+        const BconvDesc &hd = c->h_modup[(size_t)lvl * c->dnum + j];
+        hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum + j, hd.nout, cc, Dj, 0, 0, 1, c->st);
+        uint32_t lo = j * c->alpha, hi = lo + hd.nin;
+        hec_ntt_fwd(c->T, Dj, 0, 1, c->qpmap(lvl), (int)lo, c->st);
+        hec_ntt_fwd(c->T, Dj + (size_t)hi * n, 0, 1, c->qpmap(lvl) + hi, (int)(nqp - hi), c->st);
+        HEC_TRY_HIP(hipMemcpyAsync(Dj + (size_t)lo * n, c1 + (size_t)lo * n, (size_t)hd.nin * n * 8,
+                                   hipMemcpyDeviceToDevice, c->st));
+    }
+    c->release(cc);
+    // key switch in batches
+    for (size_t b0 = 0; b0 < todo.size(); b0 += HEC_KS_BATCH) {
+        const int R = (int)std::min((size_t)HEC_KS_BATCH, todo.size() - b0);
+        u64 *e = c->alloc((size_t)R * 2 * nqp * n);
+        u64 *y = c->alloc((size_t)R * 2 * nq * n);
+        if (!e || !y) HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
+        KsBatch kb{};
+        CombineBatch cb{};
+        for (int r = 0; r < R; r++) {
+            size_t i = todo[b0 + r];
+            uint32_t g = c->galois(steps[i]);
+            hec_ct *o = ct_new(c, lvl, ct->scale);
+            if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+            outs[i] = o;
+            kb.key[r] = c->rotkeys[g];
+            kb.out[r] = e + (size_t)r * 2 * nqp * n;
+            kb.g[r] = g;
+            cb.out[r] = o->d;
+            cb.e[r] = kb.out[r];
+            cb.y[r] = y + (size_t)r * 2 * nq * n;
+            cb.g[r] = g;
+        }
+        hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
+        // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine
+        hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
+        hec_bconv(c->T, c->d_moddown + lvl, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, c->st);
+        hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
+        hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        c->release(e);
+        c->release(y);
+    }
+    c->release(D);
+    HEC_TRY_HIP(hipGetLastError());
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt,
+                                          hec_ct **outs)
+{
+    if (!c || !ct || (cnt && (!steps || !outs))) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    hec_status s = ct_rotate_hoisted(c, ct, steps, cnt, outs);
+    if (s != HEC_OK)
+        for (size_t i = 0; i < cnt; i++) {
+            ct_free(outs[i]);
+            outs[i] = nullptr;
+        }
+    return s;
+}
+
+extern "C" hec_status ckks_rotate(hec_ctx *c, const hec_ct *ct, int32_t step, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    return ckks_rotate_hoisted(c, ct, &step, 1, out);
+}
+
+// ---------------------------------------------------------------------------
+// rescale, products, sums
+// ---------------------------------------------------------------------------
+hec_status ct_rescale(hec_ctx *c, hec_ct *ct)
+{
+    if (ct->level == 0) HEC_FAIL(HEC_ELEVEL, "cannot rescale at level 0");
+    const size_t n = c->n;
+    const uint32_t l = ct->level, nq = l + 1;
+    u64 *last = c->alloc(2 * n), *tmp = c->alloc(2 * (size_t)l * n);
+    u64 *o = c->alloc(2 * (size_t)l * n);
+    if (!last || !tmp || !o) HEC_FAIL(HEC_ENOMEM, "rescale buffers");
+    hec_copy_limbs(last, ct->d + (size_t)l * n, n, (size_t)nq * n, 2, n, c->st);
+    hec_ntt_inv(c->T, last, n, 2, c->idmap() + l, 1, c->st);
+    hec_rescale_spread(c->T, last, tmp, n, (size_t)l * n, 2, l, c->st);
+    hec_ntt_fwd(c->T, tmp, (size_t)l * n, 2, c->idmap(), l, c->st);
+    hec_rescale_finish(c->T, o, ct->d, tmp, (size_t)l * n, (size_t)nq * n, (size_t)l * n, 2, l, c->d_lvl + l, c->st);
+    c->release(last);
+    c->release(tmp);
+    c->release(ct->d);
+    ct->d = o;
+    ct->scale /= (double)c->mod[l];
+    ct->level = l - 1;
+    HEC_TRY_HIP(hipGetLastError());
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_rescale(hec_ctx *c, hec_ct *ct)
+{
+    if (!c || !ct) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    return ct_rescale(c, ct);
+}
+
+hec_status ct_mac_pt(hec_ctx *c, hec_ct *acc, const hec_ct *ct, const hec_pt *pt, bool first)
+{
+    if (ct->level != pt->level || acc->level != ct->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in pt product");
+    const size_t n = c->n, nq = ct->level + 1;
+    hec_ew(c->T, first ? EW_MUL_MONT : EW_MAC_MONT, acc->d, ct->d, pt->d, nq * n, nq * n, 0, 2, c->idmap(), nq,
+           c->st);
+    if (first) acc->scale = ct->scale * pt->scale;
+    return HEC_OK;
+}
+
+hec_status ct_add_inplace(hec_ctx *c, hec_ct *acc, const hec_ct *b)
+{
+    if (acc->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in addition");
+    if (acc->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in addition");
+    const size_t n = c->n, nq = acc->level + 1;
+    hec_ew(c->T, EW_ADD, acc->d, acc->d, b->d, nq * n, nq * n, nq * n, 2, c->idmap(), nq, c->st);
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_mul_pt(hec_ctx *c, const hec_ct *ct, const hec_pt *pt, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !ct || !pt) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (ct->level != pt->level) HEC_FAIL(HEC_ELEVEL, "level mismatch");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    hec_ct *o = ct_new(c, ct->level, ct->scale * pt->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    hec_status s = ct_mac_pt(c, o, ct, pt, true);
+    if (s != HEC_OK) { ct_free(o); return s; }
+    *out = o;
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a || !b) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch");
+    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    hec_ct *o = ct_clone(a);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    hec_status s = ct_add_inplace(c, o, b);
+    if (s != HEC_OK) { ct_free(o); return s; }
+    *out = o;
+    return HEC_OK;
+}

@@ -1,0 +1,129 @@
+// hec_internal.h -- host-side structures of the library (not part of the ABI).
+#pragma once
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hecnn.h"
+#include "hec_common.h"
+#include "hec_host.h"
+
+void hec_set_error(const char *fmt, ...);
+
+#define HEC_TRY_HIP(expr)                                                                                          \
+    do {                                                                                                           \
+        hipError_t e_ = (expr);                                                                                    \
+        if (e_ != hipSuccess) {                                                                                    \
+            hec_set_error("HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__);                      \
+            return HEC_EDEVICE;                                                                                    \
+        }                                                                                                          \
+    } while (0)
+
+#define HEC_FAIL(code, ...)                                                                                        \
+    do {                                                                                                           \
+        hec_set_error(__VA_ARGS__);                                                                                \
+        return code;                                                                                               \
+    } while (0)
+
+#define HEC_CHECK(st)                                                                                              \
+    do {                                                                                                           \
+        hec_status s_ = (st);                                                                                      \
+        if (s_ != HEC_OK) return s_;                                                                               \
+    } while (0)
+
+// Device memory pool: exact-size free lists; all users order their work on the
+// context stream, so a block freed after enqueued work may be handed out again
+// to later work on the same stream.
+struct DevPool {
+    std::unordered_multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> live_;
+    size_t bytes_live = 0, bytes_cached = 0;
+    void *get(size_t bytes);
+    void put(void *p);
+    void release_all();
+};
+
+struct Layout {
+    uint32_t N = 0, C = 0, H = 0, W = 0, mp = 0;
+    std::vector<std::vector<int32_t>> maps;  // per shard: block -> logical channel, -1 empty
+    uint32_t B() const { return mp * mp; }
+    uint32_t nb() const { return N / B(); }
+};
+
+struct hec_ctx {
+    hec_params prm{};
+    int dev = 0;
+    hipStream_t st = nullptr;
+    uint32_t logn = 0, n = 0, N = 0, L = 0, k = 0, dnum = 0, alpha = 0, NLK = 0;
+    std::vector<uint64_t> mod;
+    DevPool pool;
+    DevTables T{};
+    // device tables
+    PrimeC *d_pc = nullptr;
+    u64 *d_tw = nullptr, *d_twsh = nullptr, *d_itw = nullptr, *d_itwsh = nullptr;
+    u32 *d_maps = nullptr;           // identity map (NLK) followed by QP maps of every level
+    std::vector<size_t> qp_off;      // offset of level l's QP map in d_maps
+    BconvDesc *d_modup = nullptr;    // [level][digit]
+    BconvDesc *d_moddown = nullptr;  // [level]
+    LevelC *d_lvl = nullptr;         // [level]
+    u64 *d_pmodq = nullptr;          // [P]_{q_i}
+    u64 *d_gauss = nullptr;
+    std::vector<BconvDesc> h_modup, h_moddown;
+    std::unique_ptr<hec::Encoder> enc;
+    // keys
+    bool have_keys = false;
+    uint64_t key_seed = 0;
+    u64 *d_sN = nullptr, *d_sM = nullptr;  // secret, NTT form over all primes (plain / Montgomery)
+    u64 *d_pk = nullptr;                   // [2][L+1][n] Montgomery
+    std::map<uint32_t, u64 *> rotkeys;     // Galois element -> [dnum][2][NLK][n] Montgomery
+    std::map<std::string, hec_pt *> mask_cache;
+    std::mutex mu;
+
+    const u32 *idmap() const { return d_maps; }
+    const u32 *qpmap(uint32_t level) const { return d_maps + qp_off[level]; }
+    size_t limb() const { return (size_t)n; }
+    uint32_t galois(int64_t step) const;
+    u64 *alloc(size_t words) { return (u64 *)pool.get(words * 8); }
+    void release(void *p) { if (p) pool.put(p); }
+};
+
+struct hec_ct {
+    hec_ctx *ctx = nullptr;
+    uint32_t level = 0;
+    double scale = 1.0;
+    u64 *d = nullptr;  // [2][level+1][n], NTT form
+};
+
+struct hec_pt {
+    hec_ctx *ctx = nullptr;
+    uint32_t level = 0;
+    double scale = 1.0;
+    u64 *d = nullptr;  // [level+1][n], NTT form, Montgomery
+};
+
+struct hec_image {
+    hec_ctx *ctx = nullptr;
+    Layout lay;
+    std::vector<hec_ct *> shards;
+};
+
+// ---- internal API (hec_ctx.hip) -------------------------------------------
+hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale);
+hec_ct *ct_clone(const hec_ct *a);
+hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
+hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
+hec_status ct_add_inplace(hec_ctx *c, hec_ct *acc, const hec_ct *b);
+// acc (+)= ct * pt ; first == true writes instead of accumulating
+hec_status ct_mac_pt(hec_ctx *c, hec_ct *acc, const hec_ct *ct, const hec_pt *pt, bool first);
+// encode many slot vectors (in parallel on the host) and upload
+hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size_t nz, uint32_t level, double scale,
+                          std::vector<hec_pt *> &out);
+void pt_free(hec_pt *p);
+void ct_free(hec_ct *p);
+bool have_rotkey(hec_ctx *c, int32_t step);
+
+// ---- layers (hec_layers.cpp) ---------------------------------------------
+Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t mp = 0);

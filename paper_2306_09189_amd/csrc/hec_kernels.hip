@@ -1,0 +1,576 @@
+// hec_kernels.hip -- gfx950 kernels of the RNS-CKKS conv/pool library.
+//
+// Exact integer work on 64-bit prime limbs (all primes < 2^61):
+//   * products by fixed constants (NTT twiddles, base-conversion and rescale
+//     constants) use Shoup's precomputed quotient: q' = hi(a * w'), r = a*w - q'*q;
+//   * products of two variables use Montgomery reduction with one operand
+//     stored in Montgomery form (keys, plaintexts, public key);
+//   * sums of several 128-bit products are accumulated exactly and reduced
+//     once (base conversion, key-switch inner product).
+// Everything runs on the VALU: this is exact modular arithmetic, not a float
+// contraction, so the matrix cores are not used.
+#include "hec_common.h"
+
+#define DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// modular helpers
+// ---------------------------------------------------------------------------
+DEV u64 add_mod(u64 a, u64 b, u64 q)
+{
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+DEV u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+DEV u64 shoup_mul(u64 a, u64 w, u64 wsh, u64 q)
+{
+    u64 qt = __umul64hi(a, wsh);
+    u64 r = a * w - qt * q;
+    return r >= q ? r - q : r;
+}
+// T = hi:lo < q * 2^64  ->  T * 2^-64 mod q
+DEV u64 redc(u64 hi, u64 lo, u64 q, u64 qinv_neg)
+{
+    u64 m = lo * qinv_neg;
+    u64 r = hi + __umul64hi(m, q) + (lo != 0 ? 1 : 0);
+    return r >= q ? r - q : r;
+}
+DEV u64 mont_mul(u64 a, u64 bm, u64 q, u64 qinv_neg) { return redc(__umul64hi(a, bm), a * bm, q, qinv_neg); }
+struct acc128 {
+    u64 lo, hi;
+};
+DEV void mac(acc128 &acc, u64 a, u64 b)
+{
+    u64 lo = a * b, hi = __umul64hi(a, b);
+    acc.lo += lo;
+    acc.hi += hi + (acc.lo < lo ? 1 : 0);
+}
+DEV u32 brev_bits(u32 x, u32 bits) { return __brev(x) >> (32 - bits); }
+// Evaluation-form index of sigma_g: slot k holds a(psi^(2 brv(k) + 1));
+// sigma_g(a) at that root is a(psi^((2 brv(k)+1) g)).
+DEV u32 auto_src(u32 k, u32 g, u32 logn)
+{
+    u32 n2 = 2u << logn;
+    u32 e = 2 * brev_bits(k, logn) + 1;
+    u32 eg = (u32)(((u64)e * g) & (n2 - 1));
+    return brev_bits((eg - 1) >> 1, logn);
+}
+
+// ---------------------------------------------------------------------------
+// NTT: merged Cooley-Tukey forward transform with bit-reversed output
+// (a_hat[k] = a(psi^(2 brv(k) + 1))) and Gentleman-Sande inverse, split into a
+// column pass (the first log2(n1) stages, strides >= n2) and a row pass (the
+// last log2(n2) stages, inside rows of n2 contiguous words), each staged
+// through LDS.  n = n1 * n2.
+// ---------------------------------------------------------------------------
+#define NTT_THREADS 256
+#define NTT_TILE 4096  // words per LDS tile (32 KiB)
+
+static inline void ntt_split(u32 logn, u32 &logn1, u32 &logn2)
+{
+    logn1 = logn / 2;
+    logn2 = logn - logn1;
+}
+
+template <bool INV>
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 logn,
+                                                          u32 logn1, u32 C, DevTables T)
+{
+    extern __shared__ u64 lds[];
+    const u32 limb = blockIdx.y;
+    const u32 pi = pmap[limb];
+    const u32 n2 = 1u << (logn - logn1), n1 = 1u << logn1;
+    u64 *a = base + blockIdx.z * poly_stride + ((size_t)limb << logn);
+    const u64 q = T.pc[pi].q;
+    const u64 *w = (INV ? T.itw : T.tw) + ((size_t)pi << logn);
+    const u64 *wsh = (INV ? T.itw_sh : T.tw_sh) + ((size_t)pi << logn);
+    const u32 c0 = blockIdx.x * C;
+    const u32 tile = n1 * C;
+    for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) {
+        u32 r = e / C, c = e % C;
+        lds[e] = a[(size_t)r * n2 + c0 + c];
+    }
+    __syncthreads();
+    const u32 nbf = (n1 / 2) * C;
+    for (u32 st = 0; st < logn1; st++) {
+        const u32 s = INV ? (logn1 - 1 - st) : st;  // global stage: m = 2^s
+        const u32 m = 1u << s;
+        const u32 tr = n1 >> (s + 1);
+        for (u32 b = threadIdx.x; b < nbf; b += NTT_THREADS) {
+            u32 c = b % C, bi = b / C;
+            u32 grp = bi / tr, off = bi % tr;
+            u32 r = grp * 2 * tr + off;
+            u64 W = w[m + grp], Ws = wsh[m + grp];
+            u64 *x = &lds[r * C + c], *y = &lds[(r + tr) * C + c];
+            u64 U = *x, V = *y;
+            if (!INV) {
+                V = shoup_mul(V, W, Ws, q);
+                *x = add_mod(U, V, q);
+                *y = sub_mod(U, V, q);
+            } else {
+                *x = add_mod(U, V, q);
+                *y = shoup_mul(sub_mod(U, V, q), W, Ws, q);
+            }
+        }
+        __syncthreads();
+    }
+    if (INV) {
+        const u64 ni = T.pc[pi].ninv, nis = T.pc[pi].ninv_sh;
+        for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) {
+            u32 r = e / C, c = e % C;
+            a[(size_t)r * n2 + c0 + c] = shoup_mul(lds[e], ni, nis, q);
+        }
+    } else {
+        for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) {
+            u32 r = e / C, c = e % C;
+            a[(size_t)r * n2 + c0 + c] = lds[e];
+        }
+    }
+}
+
+template <bool INV>
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 logn,
+                                                          u32 logn1, u32 R, DevTables T)
+{
+    extern __shared__ u64 lds[];
+    const u32 limb = blockIdx.y;
+    const u32 pi = pmap[limb];
+    const u32 logn2 = logn - logn1;
+    const u32 n2 = 1u << logn2;
+    u64 *a = base + blockIdx.z * poly_stride + ((size_t)limb << logn) + (size_t)blockIdx.x * R * n2;
+    const u64 q = T.pc[pi].q;
+    const u64 *w = (INV ? T.itw : T.tw) + ((size_t)pi << logn);
+    const u64 *wsh = (INV ? T.itw_sh : T.tw_sh) + ((size_t)pi << logn);
+    const u32 r0 = blockIdx.x * R;
+    const u32 tile = R * n2;
+    for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) lds[e] = a[e];
+    __syncthreads();
+    const u32 half = n2 / 2, nbf = R * half;
+    for (u32 st = 0; st < logn2; st++) {
+        const u32 s2 = INV ? (logn2 - 1 - st) : st;
+        const u32 m = 1u << (logn1 + s2);
+        const u32 t = n2 >> (s2 + 1);
+        for (u32 b = threadIdx.x; b < nbf; b += NTT_THREADS) {
+            u32 row = b / half, bi = b % half;
+            u32 grp = bi / t, off = bi % t;
+            u32 c = grp * 2 * t + off;
+            u32 widx = m + ((r0 + row) << s2) + grp;
+            u64 W = w[widx], Ws = wsh[widx];
+            u64 *x = &lds[row * n2 + c], *y = &lds[row * n2 + c + t];
+            u64 U = *x, V = *y;
+            if (!INV) {
+                V = shoup_mul(V, W, Ws, q);
+                *x = add_mod(U, V, q);
+                *y = sub_mod(U, V, q);
+            } else {
+                *x = add_mod(U, V, q);
+                *y = shoup_mul(sub_mod(U, V, q), W, Ws, q);
+            }
+        }
+        __syncthreads();
+    }
+    for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) a[e] = lds[e];
+}
+
+static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stride, int npolys, const u32 *pmap,
+                       int nlimbs, hipStream_t st)
+{
+    if (nlimbs <= 0 || npolys <= 0) return;
+    u32 logn1, logn2;
+    ntt_split(T.logn, logn1, logn2);
+    u32 n1 = 1u << logn1, n2 = 1u << logn2;
+    u32 C = n2 < 16 ? n2 : 16;
+    u32 R = NTT_TILE / n2;
+    if (R > n1) R = n1;
+    dim3 gc(n2 / C, nlimbs, npolys), gr(n1 / R, nlimbs, npolys);
+    size_t lc = (size_t)n1 * C * 8, lr = (size_t)R * n2 * 8;
+    if (!inv) {
+        hipLaunchKernelGGL(k_ntt_cols<false>, gc, dim3(NTT_THREADS), lc, st, base, poly_stride, pmap, T.logn, logn1,
+                           C, T);
+        hipLaunchKernelGGL(k_ntt_rows<false>, gr, dim3(NTT_THREADS), lr, st, base, poly_stride, pmap, T.logn, logn1,
+                           R, T);
+    } else {
+        hipLaunchKernelGGL(k_ntt_rows<true>, gr, dim3(NTT_THREADS), lr, st, base, poly_stride, pmap, T.logn, logn1, R,
+                           T);
+        hipLaunchKernelGGL(k_ntt_cols<true>, gc, dim3(NTT_THREADS), lc, st, base, poly_stride, pmap, T.logn, logn1, C,
+                           T);
+    }
+}
+
+void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
+                 hipStream_t st)
+{
+    ntt_launch(T, false, base, poly_stride, npolys, pmap, nlimbs, st);
+}
+void hec_ntt_inv(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
+                 hipStream_t st)
+{
+    ntt_launch(T, true, base, poly_stride, npolys, pmap, nlimbs, st);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------
+#define EW_THREADS 256
+__global__ void __launch_bounds__(EW_THREADS) k_ew(int op, u64 *out, const u64 *a, const u64 *b, size_t so, size_t sa,
+                                                   size_t sb, const u32 *pmap, DevTables T)
+{
+    const u32 limb = blockIdx.y, p = blockIdx.z;
+    const PrimeC pc = T.pc[pmap[limb]];
+    const size_t n = T.n;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= n) return;
+    const size_t off = (size_t)limb * n + t;
+    u64 *o = out + p * so + off;
+    const u64 *x = a ? a + p * sa + off : nullptr;
+    const u64 *y = b ? b + p * sb + off : nullptr;
+    switch (op) {
+    case EW_ADD: *o = add_mod(*x, *y, pc.q); break;
+    case EW_SUB: *o = sub_mod(*x, *y, pc.q); break;
+    case EW_NEG: *o = *x ? pc.q - *x : 0; break;
+    case EW_MUL_MONT: *o = mont_mul(*x, *y, pc.q, pc.qinv_neg); break;
+    case EW_MAC_MONT: *o = add_mod(*o, mont_mul(*x, *y, pc.q, pc.qinv_neg), pc.q); break;
+    case EW_TO_MONT: *o = mont_mul(*x, pc.r2, pc.q, pc.qinv_neg); break;
+    case EW_FROM_MONT: *o = redc(0, *x, pc.q, pc.qinv_neg); break;
+    case EW_COPY: *o = *x; break;
+    }
+}
+
+void hec_ew(const DevTables &T, EwOp op, u64 *out, const u64 *a, const u64 *b, size_t so, size_t sa, size_t sb,
+            int npolys, const u32 *pmap, int nlimbs, hipStream_t st)
+{
+    if (nlimbs <= 0 || npolys <= 0) return;
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
+    hipLaunchKernelGGL(k_ew, g, dim3(EW_THREADS), 0, st, (int)op, out, a, b, so, sa, sb, pmap, T);
+}
+
+__global__ void k_reduce_i64(u64 *out, const int64_t *x, const u32 *pmap, DevTables T)
+{
+    const u32 limb = blockIdx.y;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const u64 q = T.pc[pmap[limb]].q;
+    int64_t v = x[t];
+    u64 r;
+    if (v >= 0) r = (u64)v % q;
+    else {
+        u64 m = ((u64)(-(v + 1)) + 1) % q;
+        r = m ? q - m : 0;
+    }
+    out[(size_t)limb * T.n + t] = r;
+}
+
+void hec_reduce_i64(const DevTables &T, u64 *out, const int64_t *x, const u32 *pmap, int nlimbs, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, 1);
+    hipLaunchKernelGGL(k_reduce_i64, g, dim3(EW_THREADS), 0, st, out, x, pmap, T);
+}
+
+__global__ void k_copy_limbs(u64 *dst, const u64 *src, size_t dps, size_t sps, size_t elems)
+{
+    size_t i = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (i >= elems) return;
+    dst[blockIdx.y * dps + i] = src[blockIdx.y * sps + i];
+}
+void hec_copy_limbs(u64 *dst, const u64 *src, size_t dst_poly_stride, size_t src_poly_stride, int npolys,
+                    size_t limb_elems, hipStream_t st)
+{
+    if (!limb_elems || npolys <= 0) return;
+    dim3 g((limb_elems + EW_THREADS - 1) / EW_THREADS, npolys, 1);
+    hipLaunchKernelGGL(k_copy_limbs, g, dim3(EW_THREADS), 0, st, dst, src, dst_poly_stride, src_poly_stride,
+                       limb_elems);
+}
+
+__global__ void k_automorph(u64 *out, const u64 *in, size_t ps, u32 g, DevTables T)
+{
+    const u32 limb = blockIdx.y, p = blockIdx.z;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const size_t off = p * ps + (size_t)limb * T.n;
+    out[off + k] = in[off + auto_src(k, g, T.logn)];
+}
+void hec_automorph_ntt(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
+                       u32 g, hipStream_t st)
+{
+    dim3 gr((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
+    hipLaunchKernelGGL(k_automorph, gr, dim3(EW_THREADS), 0, st, out, in, poly_stride, g, T);
+}
+
+// ---------------------------------------------------------------------------
+// ChaCha20 (RFC 8439) and samplers
+// ---------------------------------------------------------------------------
+DEV u32 rotl(u32 x, int r) { return (x << r) | (x >> (32 - r)); }
+DEV void chacha_block(u64 seed, u32 purpose, u64 index, u32 counter, u32 out[16])
+{
+    u32 s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, (u32)seed, (u32)(seed >> 32), 0u, 0u, 0u,
+                 0u, 0u, 0u, counter, purpose, (u32)index, (u32)(index >> 32)};
+    u32 x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = s[i];
+#define QRD(a, b, c, d)                                                                                            \
+    x[a] += x[b]; x[d] = rotl(x[d] ^ x[a], 16);                                                                    \
+    x[c] += x[d]; x[b] = rotl(x[b] ^ x[c], 12);                                                                    \
+    x[a] += x[b]; x[d] = rotl(x[d] ^ x[a], 8);                                                                     \
+    x[c] += x[d]; x[b] = rotl(x[b] ^ x[c], 7);
+#pragma unroll
+    for (int i = 0; i < 10; i++) {
+        QRD(0, 4, 8, 12) QRD(1, 5, 9, 13) QRD(2, 6, 10, 14) QRD(3, 7, 11, 15)
+        QRD(0, 5, 10, 15) QRD(1, 6, 11, 12) QRD(2, 7, 8, 13) QRD(3, 4, 9, 14)
+    }
+#undef QRD
+#pragma unroll
+    for (int i = 0; i < 16; i++) out[i] = x[i] + s[i];
+}
+
+// x mod q for any 64-bit x, through two Montgomery reductions
+DEV u64 mod64(u64 x, const PrimeC &pc) { return redc(0, mont_mul(x, pc.r2, pc.q, pc.qinv_neg), pc.q, pc.qinv_neg); }
+
+// coefficient c = limb*n + t takes stream words 2c (high half) and 2c+1 (low half); one block = 4 coefficients
+__global__ void k_sample_uniform(u64 *out, u64 seed, u32 purpose, u64 index, const u32 *pmap, u32 nlimbs,
+                                 DevTables T)
+{
+    const u64 blk = (u64)blockIdx.x * EW_THREADS + threadIdx.x;
+    const u64 total = (u64)nlimbs * T.n;
+    if (blk * 4 >= total) return;
+    u32 o[16];
+    chacha_block(seed, purpose, index, (u32)blk, o);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        u64 c = blk * 4 + i;
+        if (c >= total) break;
+        u64 hi = (u64)o[4 * i] | ((u64)o[4 * i + 1] << 32);
+        u64 lo = (u64)o[4 * i + 2] | ((u64)o[4 * i + 3] << 32);
+        u32 limb = (u32)(c >> T.logn);
+        PrimeC pc = T.pc[pmap[limb]];
+        // (hi * 2^64 + lo) mod q: with h = hi mod q the value h:lo < q 2^64, so
+        // redc(h:lo) = value * 2^-64 and one more multiplication by 2^128 mod q
+        // (Montgomery form of 2^64) restores it.
+        u64 h = mod64(hi, pc);
+        u64 v = redc(h, lo, pc.q, pc.qinv_neg);
+        out[c] = mont_mul(v, pc.r2, pc.q, pc.qinv_neg);
+    }
+}
+void hec_sample_uniform(const DevTables &T, u64 *out, u64 seed, u32 purpose, u64 index, const u32 *pmap,
+                        int nlimbs, hipStream_t st)
+{
+    u64 blocks = ((u64)nlimbs * T.n + 3) / 4;
+    dim3 g((blocks + EW_THREADS - 1) / EW_THREADS);
+    hipLaunchKernelGGL(k_sample_uniform, g, dim3(EW_THREADS), 0, st, out, seed, purpose, index, pmap, (u32)nlimbs, T);
+}
+
+// kind 0: ternary, word w -> (w mod 3) - 1; kind 1: Gaussian by table inversion, bit 0 = sign
+#define HEC_GAUSS_K 19
+__global__ void k_sample_small(int64_t *out, u64 seed, u32 purpose, u64 index, int kind, const u64 *gT, DevTables T)
+{
+    const u64 blk = (u64)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (blk * 8 >= T.n) return;
+    u32 o[16];
+    chacha_block(seed, purpose, index, (u32)blk, o);
+    for (int i = 0; i < 8; i++) {
+        u64 t = blk * 8 + i;
+        u64 w = (u64)o[2 * i] | ((u64)o[2 * i + 1] << 32);
+        int64_t v;
+        if (kind == 0) v = (int64_t)(w % 3) - 1;
+        else {
+            u64 r = w >> 1;
+            int64_t mag = HEC_GAUSS_K;
+            for (int j = 0; j < HEC_GAUSS_K; j++)
+                if (r < gT[j]) { mag = j; break; }
+            v = (w & 1) ? -mag : mag;
+        }
+        out[t] = v;
+    }
+}
+void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u64 index, int kind,
+                      const u64 *gauss_T, hipStream_t st)
+{
+    u64 blocks = (T.n + 7) / 8;
+    dim3 g((blocks + EW_THREADS - 1) / EW_THREADS);
+    hipLaunchKernelGGL(k_sample_small, g, dim3(EW_THREADS), 0, st, out, seed, purpose, index, kind, gauss_T, T);
+}
+
+// ---------------------------------------------------------------------------
+// fast base conversion (coefficient form)
+// ---------------------------------------------------------------------------
+#define BC_THREADS 256
+__global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *d, const u64 *src, u64 *dst, size_t sps,
+                                                      size_t dps, DevTables T)
+{
+    __shared__ u64 hm[HEC_MAX_BCONV_IN * HEC_MAX_LIMBS];
+    __shared__ PrimeC opc[HEC_MAX_LIMBS];
+    const u32 nin = d->nin, nout = d->nout;
+    for (u32 i = threadIdx.x; i < nin * nout; i += BC_THREADS) hm[i] = d->hat_m[i];
+    for (u32 i = threadIdx.x; i < nout; i += BC_THREADS) opc[i] = T.pc[d->out_prime[i]];
+    __syncthreads();
+    const size_t t = (size_t)blockIdx.x * BC_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const u64 *s = src + blockIdx.z * sps;
+    u64 *o = dst + blockIdx.z * dps;
+    u64 a[HEC_MAX_BCONV_IN];
+    for (u32 i = 0; i < nin; i++) {
+        u64 q = T.pc[d->in_prime[i]].q;
+        a[i] = shoup_mul(s[(size_t)d->in_pos[i] * T.n + t], d->inv_hat[i], d->inv_hat_sh[i], q);
+    }
+    for (u32 j = 0; j < nout; j++) {
+        acc128 acc = {0, 0};
+        for (u32 i = 0; i < nin; i++) mac(acc, a[i], hm[i * nout + j]);
+        o[(size_t)d->out_pos[j] * T.n + t] = redc(acc.hi, acc.lo, opc[j].q, opc[j].qinv_neg);
+    }
+}
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const u64 *src, u64 *dst,
+               size_t src_poly_stride, size_t dst_poly_stride, int npolys, hipStream_t st)
+{
+    (void)nout_host;
+    dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, 1, npolys);
+    hipLaunchKernelGGL(k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, src, dst, src_poly_stride, dst_poly_stride, T);
+}
+
+// ---------------------------------------------------------------------------
+// key-switch inner product with the automorphism folded into the read:
+//   e_p[o][k] = sum_j D_j[o][perm_g(k)] * key_{g,j,p}[pmap[o]][k]
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *D, u32 beta, u32 nqp,
+                                                         const u32 *pmap, u32 NLK, DevTables T)
+{
+    const u32 o = blockIdx.y, r = blockIdx.z;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const u32 pi = pmap[o];
+    const PrimeC pc = T.pc[pi];
+    const u32 src = auto_src(k, kb.g[r], T.logn);
+    const size_t n = T.n;
+    const u64 *key = kb.key[r];
+    acc128 a0 = {0, 0}, a1 = {0, 0};
+    for (u32 j = 0; j < beta; j++) {
+        u64 d = D[((size_t)j * nqp + o) * n + src];
+        mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
+        mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+    }
+    u64 *out = kb.out[r];
+    out[(size_t)o * n + k] = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
+    out[((size_t)nqp + o) * n + k] = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+}
+void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
+                  int NLK, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nqp, nrot);
+    hipLaunchKernelGGL(k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp, pmap, (u32)NLK, T);
+}
+
+// ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)
+__global__ void k_moddown_combine(CombineBatch cb, const u64 *c0, u32 nq, u32 nqp, const LevelC *lc,
+                                  const u32 *pmap, DevTables T)
+{
+    const u32 i = blockIdx.y % nq, p = blockIdx.y / nq, r = blockIdx.z;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const size_t n = T.n;
+    const u64 q = T.pc[pmap[i]].q;
+    u64 e = cb.e[r][((size_t)p * nqp + i) * n + k];
+    u64 y = cb.y[r][((size_t)p * nq + i) * n + k];
+    u64 v = shoup_mul(sub_mod(e, y, q), lc->pinv[i], lc->pinv_sh[i], q);
+    if (p == 0) v = add_mod(v, c0[(size_t)i * n + auto_src(k, cb.g[r], T.logn)], q);
+    cb.out[r][((size_t)p * nq + i) * n + k] = v;
+}
+void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
+                         const LevelC *lc, const u32 *pmap, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, 2 * nq, nrot);
+    hipLaunchKernelGGL(k_moddown_combine, g, dim3(EW_THREADS), 0, st, cb, c0, (u32)nq, (u32)nqp, lc, pmap, T);
+}
+
+// ---------------------------------------------------------------------------
+// rescale
+// ---------------------------------------------------------------------------
+// tmp[i][t] = (centered last[t]) mod q_i, i < level
+__global__ void k_rescale_spread(const u64 *last, u64 *tmp, size_t ls, size_t ts, u32 level, DevTables T)
+{
+    const u32 i = blockIdx.y, p = blockIdx.z;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const u64 ql = T.pc[level].q;
+    const PrimeC pc = T.pc[i];
+    u64 v = last[p * ls + t];
+    u64 r;
+    if (v <= (ql - 1) / 2) r = mod64(v, pc);
+    else {
+        u64 m = mod64(ql - v, pc);
+        r = m ? pc.q - m : 0;
+    }
+    tmp[p * ts + (size_t)i * T.n + t] = r;
+}
+void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size_t last_stride, size_t tmp_stride,
+                        int npolys, u32 level, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, level, npolys);
+    hipLaunchKernelGGL(k_rescale_spread, g, dim3(EW_THREADS), 0, st, last_coef, tmp, last_stride, tmp_stride, level, T);
+}
+__global__ void k_rescale_finish(u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc, size_t stt,
+                                 const LevelC *lc, DevTables T)
+{
+    const u32 i = blockIdx.y, p = blockIdx.z;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const u64 q = T.pc[i].q;
+    const size_t off = (size_t)i * T.n + t;
+    out[p * so + off] = shoup_mul(sub_mod(c[p * sc + off], tmp[p * stt + off], q), lc->qlinv[i], lc->qlinv_sh[i], q);
+}
+void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc,
+                        size_t st_, int npolys, u32 level, const LevelC *lc, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, level, npolys);
+    hipLaunchKernelGGL(k_rescale_finish, g, dim3(EW_THREADS), 0, st, out, c, tmp, so, sc, st_, lc, T);
+}
+
+// ---------------------------------------------------------------------------
+// key assembly and encryption
+// ---------------------------------------------------------------------------
+__global__ void k_key_finish(u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g, u32 dlo, u32 dhi,
+                             const u32 *pmap, DevTables T)
+{
+    const u32 l = blockIdx.y;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const u32 pi = pmap[l];
+    const PrimeC pc = T.pc[pi];
+    const size_t n = T.n, off = (size_t)l * n + k, soff = (size_t)pi * n;
+    u64 av = a[off];
+    u64 s = sN[soff + k];
+    u64 as = mont_mul(av, mont_mul(s, pc.r2, pc.q, pc.qinv_neg), pc.q, pc.qinv_neg);
+    u64 v = sub_mod(e[off], as, pc.q);
+    if (pm && pi >= dlo && pi < dhi) {
+        u64 sg = sN[soff + auto_src(k, g, T.logn)];
+        u64 pmm = mont_mul(pm[pi], pc.r2, pc.q, pc.qinv_neg);
+        v = add_mod(v, mont_mul(sg, pmm, pc.q, pc.qinv_neg), pc.q);
+    }
+    b[off] = mont_mul(v, pc.r2, pc.q, pc.qinv_neg);
+    a[off] = mont_mul(av, pc.r2, pc.q, pc.qinv_neg);
+}
+void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g, u32 dlo,
+                    u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st)
+{
+    dim3 gr((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, 1);
+    hipLaunchKernelGGL(k_key_finish, gr, dim3(EW_THREADS), 0, st, b, a, e, sN, pm, g, dlo, dhi, pmap, T);
+}
+
+__global__ void k_encrypt_finish(u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m, const u64 *pk,
+                                 size_t pks, u32 nq, DevTables T)
+{
+    const u32 i = blockIdx.y;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const PrimeC pc = T.pc[i];
+    const size_t off = (size_t)i * T.n + k;
+    u64 vv = v[off];
+    u64 c0 = add_mod(add_mod(mont_mul(vv, pk[off], pc.q, pc.qinv_neg), e0[off], pc.q), m[off], pc.q);
+    u64 c1 = add_mod(mont_mul(vv, pk[pks + off], pc.q, pc.qinv_neg), e1[off], pc.q);
+    ct[off] = c0;
+    ct[(size_t)nq * T.n + off] = c1;
+}
+void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,
+                        const u64 *pk, size_t pk_poly_stride, int nq, hipStream_t st)
+{
+    dim3 gr((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
+    hipLaunchKernelGGL(k_encrypt_finish, gr, dim3(EW_THREADS), 0, st, ct, v, e0, e1, m, pk, pk_poly_stride, (u32)nq,
+                       T);
+}

@@ -1,0 +1,778 @@
+// hec_layers.cpp -- image packing, homomorphic conv2d and 2x2 average pooling
+// (Section 4 of the paper) on top of the ciphertext operations.
+//
+// Layout: each channel is a row-major block of B = mp*mp slots (mp = side
+// padded to a power of two); a shard is a ciphertext of N/B blocks with a
+// block map lam[b] = logical channel of block b (-1 = empty).  Duplication
+// (consecutive d-fold copies) and the permutation left by consolidation are
+// both block maps, so a convolution reads K^{lam(b+r), mu(b)} wherever the
+// paper reads K^{tau(i)}.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <sstream>
+
+#include "hec_internal.h"
+
+hec_status decrypt_slots(hec_ctx *c, const hec_ct *ct, double *z, size_t nz);
+
+static uint32_t next_pow2(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t mp)
+{
+    Layout L;
+    L.N = N; L.C = C; L.H = H; L.W = W;
+    L.mp = mp ? mp : next_pow2(std::max(H, W));
+    const uint32_t B = L.B();
+    if (B > N) return L;  // channel shards: not planned here (maps empty)
+    const uint32_t nb = N / B, Cp = next_pow2(C);
+    if ((uint64_t)Cp * B <= N) {
+        uint32_t d = N / (Cp * B);
+        std::vector<int32_t> m(nb);
+        for (uint32_t b = 0; b < nb; b++) m[b] = (b / d < C) ? (int32_t)(b / d) : -1;
+        L.maps.push_back(m);
+    } else {
+        uint32_t t = (C + nb - 1) / nb;  // no shard is left entirely empty
+        for (uint32_t u = 0; u < t; u++) {
+            std::vector<int32_t> m(nb);
+            for (uint32_t b = 0; b < nb; b++) m[b] = (u * nb + b < C) ? (int32_t)(u * nb + b) : -1;
+            L.maps.push_back(m);
+        }
+    }
+    return L;
+}
+
+static void pack_shard(const Layout &L, const double *x, uint32_t u, std::vector<double> &v)
+{
+    const uint32_t B = L.B();
+    v.assign(L.N, 0.0);
+    for (uint32_t b = 0; b < L.nb(); b++) {
+        int32_t f = L.maps[u][b];
+        if (f < 0) continue;
+        for (uint32_t i = 0; i < L.H; i++)
+            for (uint32_t j = 0; j < L.W; j++) v[(size_t)b * B + i * L.mp + j] = x[((size_t)f * L.H + i) * L.W + j];
+    }
+}
+
+static hec_image *image_new(hec_ctx *c, const Layout &L)
+{
+    hec_image *im = new hec_image();
+    im->ctx = c;
+    im->lay = L;
+    return im;
+}
+
+extern "C" void hec_image_free(hec_image *img)
+{
+    if (!img) return;
+    for (auto *s : img->shards) ct_free(s);
+    delete img;
+}
+
+extern "C" hec_status he_image_encrypt(hec_ctx *c, const double *x, uint32_t C, uint32_t H, uint32_t W, uint32_t level,
+                                       uint64_t seed, hec_image **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !x || !C || !H || !W) HEC_FAIL(HEC_EINVAL, "bad image arguments");
+    if (level > c->L) HEC_FAIL(HEC_ELEVEL, "level above L");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    Layout L = natural_layout(c->N, C, H, W);
+    if (L.maps.empty()) HEC_FAIL(HEC_ELAYOUT, "channel of %ux%u does not fit one ciphertext (channel shards)", H, W);
+    std::vector<std::vector<double>> v(L.maps.size());
+    std::vector<const double *> zp;
+    for (uint32_t u = 0; u < L.maps.size(); u++) {
+        pack_shard(L, x, u, v[u]);
+        zp.push_back(v[u].data());
+    }
+    std::vector<hec_pt *> pts;
+    HEC_CHECK(pt_encode_many(c, zp, c->N, level, std::ldexp(1.0, (int)c->prm.log_scale), pts));
+    hec_image *im = image_new(c, L);
+    for (uint32_t u = 0; u < pts.size(); u++) {
+        hec_ct *ct = nullptr;
+        hec_status s = ckks_encrypt_idx(c, pts[u], seed, u, &ct);
+        if (s != HEC_OK) {
+            for (auto *p : pts) pt_free(p);
+            hec_image_free(im);
+            return s;
+        }
+        im->shards.push_back(ct);
+    }
+    for (auto *p : pts) pt_free(p);
+    *out = im;
+    return HEC_OK;
+}
+
+extern "C" hec_status he_image_decrypt(hec_ctx *c, const hec_image *img, double *x)
+{
+    if (!c || !img || !x) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const Layout &L = img->lay;
+    std::vector<char> seen(L.C, 0);
+    std::vector<double> z(c->N);
+    for (uint32_t u = 0; u < L.maps.size(); u++) {
+        bool need = false;
+        for (int32_t f : L.maps[u]) need |= (f >= 0 && !seen[f]);
+        if (!need) continue;
+        HEC_CHECK(decrypt_slots(c, img->shards[u], z.data(), c->N));
+        for (uint32_t b = 0; b < L.nb(); b++) {
+            int32_t f = L.maps[u][b];
+            if (f < 0 || seen[f]) continue;
+            seen[f] = 1;
+            for (uint32_t i = 0; i < L.H; i++)
+                for (uint32_t j = 0; j < L.W; j++)
+                    x[((size_t)f * L.H + i) * L.W + j] = z[(size_t)b * L.B() + i * L.mp + j];
+        }
+    }
+    for (uint32_t f = 0; f < L.C; f++)
+        if (!seen[f]) HEC_FAIL(HEC_ELAYOUT, "channel %u is not present in the image", f);
+    return HEC_OK;
+}
+
+extern "C" hec_status he_image_info(const hec_image *img, uint32_t *C, uint32_t *H, uint32_t *W, uint32_t *mp,
+                                    uint32_t *n_shards)
+{
+    if (!img) HEC_FAIL(HEC_EINVAL, "img is NULL");
+    if (C) *C = img->lay.C;
+    if (H) *H = img->lay.H;
+    if (W) *W = img->lay.W;
+    if (mp) *mp = img->lay.mp;
+    if (n_shards) *n_shards = (uint32_t)img->shards.size();
+    return HEC_OK;
+}
+
+extern "C" hec_status he_image_block_map(const hec_image *img, uint32_t u, int32_t *lam, size_t cap)
+{
+    if (!img || !lam) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (u >= img->lay.maps.size()) HEC_FAIL(HEC_EINVAL, "no shard %u", u);
+    if (cap < img->lay.nb()) HEC_FAIL(HEC_EINVAL, "capacity too small");
+    memcpy(lam, img->lay.maps[u].data(), img->lay.nb() * 4);
+    return HEC_OK;
+}
+
+extern "C" const hec_ct *he_image_shard(const hec_image *img, uint32_t u)
+{
+    return (img && u < img->shards.size()) ? img->shards[u] : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// convolution planning (Section 4.1)
+// ---------------------------------------------------------------------------
+struct ConvItem {
+    int32_t amount;
+    std::vector<std::pair<uint32_t, std::vector<double>>> pts;  // output shard -> slot vector
+};
+
+// Offsets r with, per needed output block b, the input channel lam[b+r] it
+// takes: first the offsets that give every needed block a new channel at
+// once, then block-by-block completion; smallest offset first.
+static bool rotation_offsets(const std::vector<int32_t> &lam, const std::vector<uint32_t> &need_b,
+                             std::vector<std::pair<uint32_t, std::map<uint32_t, int32_t>>> &res)
+{
+    const uint32_t nb = (uint32_t)lam.size();
+    std::set<int32_t> chans;
+    for (int32_t f : lam)
+        if (f >= 0) chans.insert(f);
+    std::map<uint32_t, std::set<int32_t>> cov;
+    std::map<uint32_t, std::map<uint32_t, int32_t>> assign;
+    for (uint32_t r = 0; r < nb; r++) {
+        bool all = true;
+        for (uint32_t b : need_b) {
+            int32_t f = lam[(b + r) % nb];
+            if (f < 0 || cov[b].count(f)) { all = false; break; }
+        }
+        if (!all) continue;
+        for (uint32_t b : need_b) {
+            int32_t f = lam[(b + r) % nb];
+            assign[r][b] = f;
+            cov[b].insert(f);
+        }
+    }
+    for (uint32_t r = 0; r < nb; r++)
+        for (uint32_t b : need_b) {
+            int32_t f = lam[(b + r) % nb];
+            if (f >= 0 && !cov[b].count(f)) {
+                assign[r][b] = f;
+                cov[b].insert(f);
+            }
+        }
+    for (uint32_t b : need_b)
+        if (cov[b] != chans) return false;
+    res.clear();
+    for (auto &kv : assign) res.push_back(kv);
+    return true;
+}
+
+static void tap_mask(const Layout &L, uint32_t Ho, uint32_t Wo, int dk, int dl, std::vector<double> &m, bool &any)
+{
+    m.assign(L.B(), 0.0);
+    any = false;
+    for (int i = 0; i < (int)L.mp; i++)
+        for (int j = 0; j < (int)L.mp; j++) {
+            bool ok = i < (int)Ho && j < (int)Wo && i + dk >= 0 && i + dk < (int)L.H && j + dl >= 0 &&
+                      j + dl < (int)L.W;
+            if (ok) {
+                m[(size_t)i * L.mp + j] = 1.0;
+                any = true;
+            }
+        }
+}
+
+static hec_status conv_items(const Layout &L, const double *w, uint32_t Co, uint32_t kh, uint32_t kw, uint32_t pad,
+                             Layout &out, std::vector<std::vector<ConvItem>> &plan)
+{
+    const int Ho = (int)L.H + 2 * (int)pad - (int)kh + 1, Wo = (int)L.W + 2 * (int)pad - (int)kw + 1;
+    if (Ho < 1 || Wo < 1 || Ho > (int)L.mp || Wo > (int)L.mp) HEC_FAIL(HEC_ELAYOUT, "bad convolution geometry");
+    out = natural_layout(L.N, Co, Ho, Wo, L.mp);
+    if (out.maps.empty()) HEC_FAIL(HEC_ELAYOUT, "output does not fit image shards");
+    const uint32_t N = L.N, B = L.B(), nb = L.nb(), Ci = L.C;
+    std::vector<uint32_t> need_b;
+    for (uint32_t b = 0; b < nb; b++) {
+        bool any = false;
+        for (auto &mu : out.maps) any |= mu[b] >= 0;
+        if (any) need_b.push_back(b);
+    }
+    plan.assign(L.maps.size(), {});
+    std::vector<double> mask;
+    for (uint32_t u = 0; u < L.maps.size(); u++) {
+        std::vector<std::pair<uint32_t, std::map<uint32_t, int32_t>>> offs;
+        if (!rotation_offsets(L.maps[u], need_b, offs)) HEC_FAIL(HEC_ELAYOUT, "layout cannot be convolved");
+        for (auto &ro : offs) {
+            const uint32_t r = ro.first;
+            for (uint32_t kr = 0; kr < kh; kr++)
+                for (uint32_t kc = 0; kc < kw; kc++) {
+                    int dk = (int)kr - (int)pad, dl = (int)kc - (int)pad;
+                    bool any;
+                    tap_mask(L, Ho, Wo, dk, dl, mask, any);
+                    if (!any) continue;
+                    int64_t a = ((int64_t)r * B + (int64_t)dk * L.mp + dl) % (int64_t)N;
+                    if (a < 0) a += N;
+                    ConvItem it;
+                    it.amount = (int32_t)a;
+                    for (uint32_t v = 0; v < out.maps.size(); v++) {
+                        std::vector<double> vec(N, 0.0);
+                        bool nz = false;
+                        for (auto &bf : ro.second) {
+                            int32_t g = out.maps[v][bf.first];
+                            if (g < 0) continue;
+                            double wv = w[(((size_t)g * Ci + bf.second) * kh + kr) * kw + kc];
+                            if (wv == 0.0) continue;
+                            double *dst = &vec[(size_t)bf.first * B];
+                            for (uint32_t e = 0; e < B; e++) dst[e] = wv * mask[e];
+                            nz = true;
+                        }
+                        if (nz) it.pts.emplace_back(v, std::move(vec));
+                    }
+                    if (!it.pts.empty()) plan[u].push_back(std::move(it));
+                }
+        }
+    }
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pooling masks (Section 4.2)
+// ---------------------------------------------------------------------------
+static std::vector<char> valid_blocks(const Layout &L)
+{
+    std::vector<char> v(L.nb(), 0);
+    for (auto &m : L.maps)
+        for (uint32_t b = 0; b < L.nb(); b++) v[b] |= m[b] >= 0;
+    return v;
+}
+
+static std::vector<double> per_block(const Layout &L, const std::vector<double> &blk)
+{
+    std::vector<double> v(L.N, 0.0);
+    auto vb = valid_blocks(L);
+    for (uint32_t b = 0; b < L.nb(); b++)
+        if (vb[b]) std::copy(blk.begin(), blk.end(), v.begin() + (size_t)b * L.B());
+    return v;
+}
+
+// the three mask kinds: 'h' (rot_i of column 2i of even rows), 'v' (rot_{3j mp/2} of the
+// left half of row 2j), 'f' (fused: element (2j, 2i) after rot_i)
+static std::vector<double> pool_mask(const Layout &L, char kind, uint32_t i, uint32_t j, uint32_t Wo, double val)
+{
+    std::vector<double> blk(L.B(), 0.0);
+    if (kind == 'h') {
+        for (uint32_t r = 0; r < L.H; r += 2) blk[(size_t)r * L.mp + i] = val;
+    } else if (kind == 'v') {
+        uint32_t o = j * L.mp / 2;
+        for (uint32_t c = 0; c < Wo; c++) blk[o + c] = 1.0;
+    } else {
+        blk[(size_t)(2 * j) * L.mp + i] = val;
+    }
+    return per_block(L, blk);
+}
+
+static std::string layout_key(const Layout &L)
+{
+    std::ostringstream s;
+    s << L.N << ":" << L.C << ":" << L.H << ":" << L.W << ":" << L.mp;
+    auto vb = valid_blocks(L);
+    s << ":";
+    for (char c : vb) s << (int)c;
+    return s.str();
+}
+
+// cached mask plaintexts (they only depend on the layout, index, level and scale)
+static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::vector<std::pair<uint32_t, uint32_t>> &ij,
+                            uint32_t Wo, double val, uint32_t level, double scale, std::vector<hec_pt *> &out)
+{
+    std::string base = layout_key(L);
+    std::vector<std::string> keys;
+    std::vector<size_t> miss;
+    out.assign(ij.size(), nullptr);
+    for (size_t t = 0; t < ij.size(); t++) {
+        std::ostringstream s;
+        s << base << "|" << kind << "|" << ij[t].first << "|" << ij[t].second << "|" << Wo << "|" << val << "|"
+          << level << "|" << scale;
+        keys.push_back(s.str());
+        auto it = c->mask_cache.find(keys.back());
+        if (it != c->mask_cache.end()) out[t] = it->second;
+        else miss.push_back(t);
+    }
+    if (miss.empty()) return HEC_OK;
+    std::vector<std::vector<double>> vecs;
+    std::vector<const double *> zp;
+    for (size_t t : miss) vecs.push_back(pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val));
+    for (auto &v : vecs) zp.push_back(v.data());
+    std::vector<hec_pt *> pts;
+    HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts));
+    for (size_t a = 0; a < miss.size(); a++) {
+        c->mask_cache[keys[miss[a]]] = pts[a];
+        out[miss[a]] = pts[a];
+    }
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// small helpers over ciphertext lists
+// ---------------------------------------------------------------------------
+static void free_all(std::vector<hec_ct *> &v)
+{
+    for (auto *x : v) ct_free(x);
+    v.clear();
+}
+
+static hec_status sum_into(hec_ctx *c, hec_ct *&acc, hec_ct *t)
+{
+    if (!acc) { acc = t; return HEC_OK; }
+    hec_status s = ct_add_inplace(c, acc, t);
+    ct_free(t);
+    return s;
+}
+
+static hec_status rotate_list(hec_ctx *c, const hec_ct *ct, const std::vector<int32_t> &steps,
+                              std::vector<hec_ct *> &out)
+{
+    out.assign(steps.size(), nullptr);
+    if (steps.empty()) return HEC_OK;
+    return ckks_rotate_hoisted(c, ct, steps.data(), steps.size(), out.data());
+}
+
+// masked sum: acc = sum_t rots[t] * pts[t]
+static hec_status masked_sum(hec_ctx *c, const std::vector<hec_ct *> &rots, const std::vector<hec_pt *> &pts,
+                             hec_ct **out)
+{
+    hec_ct *acc = ct_new(c, rots[0]->level, 1.0);
+    if (!acc) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    for (size_t t = 0; t < rots.size(); t++) {
+        hec_status s = ct_mac_pt(c, acc, rots[t], pts[t], t == 0);
+        if (s != HEC_OK) { ct_free(acc); return s; }
+    }
+    *out = acc;
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// downsample / consolidate / duplicate
+// ---------------------------------------------------------------------------
+struct PoolSteps {
+    std::set<int32_t> steps;
+};
+
+static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                             std::vector<hec_ct *> &out, Layout &nl)
+{
+    const uint32_t mp = L.mp;
+    uint32_t Ho, Wo;
+    double val;
+    if (select) {
+        Ho = (L.H + 1) / 2; Wo = (L.W + 1) / 2; val = 1.0;
+    } else {
+        if (L.H % 2 || L.W % 2) HEC_FAIL(HEC_ELAYOUT, "average pooling needs even H and W");
+        Ho = L.H / 2; Wo = L.W / 2; val = 0.25;
+    }
+    out.clear();
+    for (hec_ct *ct : in) {
+        const uint32_t lvl = ct->level;
+        if (lvl < 1) HEC_FAIL(HEC_ELEVEL, "pooling needs a level");
+        const bool fused = lvl < 2;
+        hec_ct *D = nullptr;
+        if (!select) {
+            std::vector<hec_ct *> r;
+            HEC_CHECK(rotate_list(c, ct, {1, (int32_t)mp, (int32_t)mp + 1}, r));
+            D = ct_clone(ct);
+            for (auto *x : r) HEC_CHECK(sum_into(c, D, x));
+        } else {
+            D = ct_clone(ct);
+        }
+        std::vector<int32_t> hs;
+        for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
+        std::vector<hec_ct *> rots;
+        hec_status s = rotate_list(c, D, hs, rots);
+        ct_free(D);
+        HEC_CHECK(s);
+        if (fused) {
+            const double ps = (double)c->mod[lvl] / 4.0;
+            hec_ct *acc = nullptr;
+            for (uint32_t j = 0; j < Ho; j++) {
+                std::vector<std::pair<uint32_t, uint32_t>> ij;
+                for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, j});
+                std::vector<hec_pt *> pts;
+                HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, ps, pts));
+                hec_ct *T = nullptr;
+                HEC_CHECK(masked_sum(c, rots, pts, &T));
+                if (j > 0) {
+                    hec_ct *m = nullptr;
+                    int32_t st = (int32_t)(3 * j * mp / 2);
+                    s = ckks_rotate(c, T, st, &m);
+                    ct_free(T);
+                    HEC_CHECK(s);
+                    T = m;
+                }
+                HEC_CHECK(sum_into(c, acc, T));
+            }
+            free_all(rots);
+            HEC_CHECK(ct_rescale(c, acc));
+            out.push_back(acc);
+        } else {
+            std::vector<std::pair<uint32_t, uint32_t>> ij;
+            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
+            std::vector<hec_pt *> pts;
+            HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], pts));
+            hec_ct *M1 = nullptr;
+            HEC_CHECK(masked_sum(c, rots, pts, &M1));
+            free_all(rots);
+            HEC_CHECK(ct_rescale(c, M1));
+            const uint32_t l1 = M1->level;
+            if (l1 < 1) { ct_free(M1); HEC_FAIL(HEC_ELEVEL, "separable pooling needs two levels"); }
+            std::vector<int32_t> vs;
+            for (uint32_t j = 0; j < Ho; j++) vs.push_back((int32_t)(3 * j * mp / 2));
+            std::vector<hec_ct *> r2;
+            s = rotate_list(c, M1, vs, r2);
+            ct_free(M1);
+            HEC_CHECK(s);
+            std::vector<std::pair<uint32_t, uint32_t>> jj;
+            for (uint32_t j = 0; j < Ho; j++) jj.push_back({0, j});
+            HEC_CHECK(get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], pts));
+            hec_ct *M2 = nullptr;
+            HEC_CHECK(masked_sum(c, r2, pts, &M2));
+            free_all(r2);
+            HEC_CHECK(ct_rescale(c, M2));
+            out.push_back(M2);
+        }
+    }
+    nl = Layout();
+    nl.N = L.N; nl.C = L.C; nl.H = Ho; nl.W = Wo; nl.mp = mp / 2;
+    for (auto &m : L.maps) {
+        std::vector<int32_t> nm(4 * L.nb(), -1);
+        for (uint32_t b = 0; b < L.nb(); b++) nm[4 * b] = m[b];
+        nl.maps.push_back(nm);
+    }
+    return HEC_OK;
+}
+
+static hec_status duplicate(hec_ctx *c, hec_ct *ct, Layout &L, uint32_t d, hec_ct **out)
+{
+    const int32_t Bn = (int32_t)L.B();
+    const uint32_t step = 4 / d;
+    std::vector<int32_t> sh;
+    for (uint32_t m = 1; m < d; m++) sh.push_back(-(int32_t)(m * step) * Bn);
+    std::vector<hec_ct *> r;
+    HEC_CHECK(rotate_list(c, ct, sh, r));
+    hec_ct *acc = ct_clone(ct);
+    for (auto *x : r) HEC_CHECK(sum_into(c, acc, x));
+    std::vector<int32_t> lam = L.maps[0];
+    for (uint32_t b = 0; b < L.nb() / 4; b++)
+        for (uint32_t m = 1; m < d; m++)
+            for (uint32_t e = 0; e < step; e++) lam[4 * b + m * step + e] = lam[4 * b + e];
+    L.maps[0] = lam;
+    *out = acc;
+    return HEC_OK;
+}
+
+static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                                       std::vector<hec_ct *> &out, Layout &ol)
+{
+    std::vector<hec_ct *> ds;
+    Layout nl;
+    HEC_CHECK(downsample(c, in, L, select, ds, nl));
+    const size_t t = ds.size();
+    out.clear();
+    if (t == 1) {
+        hec_ct *o = nullptr;
+        hec_status s = duplicate(c, ds[0], nl, 4, &o);
+        free_all(ds);
+        HEC_CHECK(s);
+        out.push_back(o);
+        ol = nl;
+        return HEC_OK;
+    }
+    const int32_t Bn = (int32_t)nl.B();
+    Layout cl = nl;
+    cl.maps.clear();
+    for (size_t s0 = 0; s0 < t; s0 += 4) {
+        const size_t g = std::min((size_t)4, t - s0);  // short last group when t % 4 != 0
+        hec_ct *acc = ct_clone(ds[s0]);
+        for (size_t e = 1; e < g; e++) {
+            hec_ct *r = nullptr;
+            HEC_CHECK(ckks_rotate(c, ds[s0 + e], -(int32_t)e * Bn, &r));
+            HEC_CHECK(sum_into(c, acc, r));
+        }
+        std::vector<int32_t> lam(nl.nb(), -1);
+        for (size_t e = 0; e < g; e++)
+            for (uint32_t b = 0; b < nl.nb() / 4; b++) lam[4 * b + e] = nl.maps[s0 + e][4 * b];
+        cl.maps.push_back(lam);
+        out.push_back(acc);
+    }
+    free_all(ds);
+    if (t == 2) {
+        hec_ct *o = nullptr;
+        HEC_CHECK(duplicate(c, out[0], cl, 2, &o));
+        free_all(out);
+        out.push_back(o);
+    }
+    ol = cl;
+    return HEC_OK;
+}
+
+// rotation steps of a pooling step (for key generation)
+static void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps)
+{
+    const uint32_t mp = L.mp;
+    uint32_t Ho = select ? (L.H + 1) / 2 : L.H / 2, Wo = select ? (L.W + 1) / 2 : L.W / 2;
+    if (!select) { steps.insert(1); steps.insert((int32_t)mp); steps.insert((int32_t)mp + 1); }
+    for (uint32_t i = 1; i < Wo; i++) steps.insert((int32_t)i);
+    for (uint32_t j = 1; j < Ho; j++) steps.insert((int32_t)(3 * j * mp / 2));
+    (void)level;
+    const uint32_t N = L.N, Bn = L.B() / 4, t = (uint32_t)L.maps.size();
+    auto neg = [&](int64_t a) { int64_t r = (-a) % (int64_t)N; return (int32_t)(r < 0 ? r + N : r); };
+    if (t == 1) for (uint32_t m = 1; m < 4; m++) steps.insert(neg((int64_t)m * Bn));
+    else {
+        uint32_t g = t >= 4 ? 4 : t;  // the first group is the largest
+        for (uint32_t e = 1; e < g; e++) steps.insert(neg((int64_t)e * Bn));
+        if (t == 2) steps.insert(neg(2 * (int64_t)Bn));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// conv plans
+// ---------------------------------------------------------------------------
+struct hec_conv_plan {
+    hec_ctx *ctx = nullptr;
+    Layout in, out;  // out = unstrided output layout
+    uint32_t level = 0, stride = 1;
+    int mode = 0;
+    struct Item {
+        int32_t amount;
+        std::vector<std::pair<uint32_t, hec_pt *>> pts;
+    };
+    std::vector<std::vector<Item>> items;  // per input shard
+    std::set<int32_t> steps;
+};
+
+extern "C" void he_conv2d_plan_free(hec_conv_plan *p)
+{
+    if (!p) return;
+    for (auto &v : p->items)
+        for (auto &it : v)
+            for (auto &pp : it.pts) pt_free(pp.second);
+    delete p;
+}
+
+static bool same_layout(const Layout &a, const Layout &b)
+{
+    return a.N == b.N && a.C == b.C && a.H == b.H && a.W == b.W && a.mp == b.mp && a.maps == b.maps;
+}
+
+extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, const double *w, uint32_t Co,
+                                            uint32_t kh, uint32_t kw, uint32_t stride, uint32_t pad,
+                                            hec_conv_plan **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !like || !w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
+    if (stride != 1 && stride != 2) HEC_FAIL(HEC_EINVAL, "stride must be 1 or 2");
+    if (like->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    const uint32_t lvl = like->shards[0]->level;
+    for (auto *s : like->shards)
+        if (s->level != lvl) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
+    if (lvl < 1) HEC_FAIL(HEC_ELEVEL, "convolution needs a level");
+    if (stride == 2 && lvl < 2) HEC_FAIL(HEC_ELEVEL, "strided convolution needs two levels");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    std::unique_ptr<hec_conv_plan> p(new hec_conv_plan());
+    p->ctx = c;
+    p->in = like->lay;
+    p->level = lvl;
+    p->stride = stride;
+    std::vector<std::vector<ConvItem>> items;
+    HEC_CHECK(conv_items(like->lay, w, Co, kh, kw, pad, p->out, items));
+    p->items.resize(items.size());
+    std::vector<const double *> zp;
+    for (auto &v : items)
+        for (auto &it : v)
+            for (auto &pp : it.pts) zp.push_back(pp.second.data());
+    std::vector<hec_pt *> pts;
+    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts));
+    size_t q = 0;
+    for (size_t u = 0; u < items.size(); u++)
+        for (auto &it : items[u]) {
+            hec_conv_plan::Item pi;
+            pi.amount = it.amount;
+            for (auto &pp : it.pts) pi.pts.push_back({pp.first, pts[q++]});
+            if (it.amount % (int32_t)c->N) p->steps.insert(it.amount);
+            p->items[u].push_back(std::move(pi));
+        }
+    if (stride == 2) {
+        Layout o = p->out;
+        pool_steps(o, true, lvl - 1, p->steps);
+    }
+    *out = p.release();
+    return HEC_OK;
+}
+
+extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
+{
+    if (!p || (mode != 0 && mode != 1)) HEC_FAIL(HEC_EINVAL, "bad mode");
+    p->mode = mode;
+    return HEC_OK;
+}
+
+extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *steps, size_t cap, size_t *count)
+{
+    if (!p) HEC_FAIL(HEC_EINVAL, "plan is NULL");
+    if (count) *count = p->steps.size();
+    if (steps) {
+        if (cap < p->steps.size()) HEC_FAIL(HEC_EINVAL, "capacity too small");
+        size_t i = 0;
+        for (int32_t s : p->steps) steps[i++] = s;
+    }
+    return HEC_OK;
+}
+
+#define ROT_CHUNK 32
+extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, const hec_image *in, hec_image **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !p || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (!same_layout(p->in, in->lay)) HEC_FAIL(HEC_ELAYOUT, "image layout differs from the plan's");
+    for (auto *s : in->shards)
+        if (s->level != p->level) HEC_FAIL(HEC_ELEVEL, "image level differs from the plan's");
+    for (int32_t s : p->steps)
+        if (!have_rotkey(c, s)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", s);
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t nout = p->out.maps.size();
+    std::vector<hec_ct *> acc(nout, nullptr);
+    std::vector<char> first(nout, 1);
+    for (size_t v = 0; v < nout; v++) {
+        acc[v] = ct_new(c, p->level, 1.0);
+        if (!acc[v]) { free_all(acc); HEC_FAIL(HEC_ENOMEM, "accumulator allocation"); }
+    }
+    hec_status s = HEC_OK;
+    for (size_t u = 0; u < p->items.size() && s == HEC_OK; u++) {
+        const auto &its = p->items[u];
+        for (size_t i0 = 0; i0 < its.size() && s == HEC_OK; i0 += ROT_CHUNK) {
+            size_t cnt = std::min((size_t)ROT_CHUNK, its.size() - i0);
+            std::vector<int32_t> st(cnt);
+            for (size_t t = 0; t < cnt; t++) st[t] = its[i0 + t].amount;
+            std::vector<hec_ct *> rots(cnt, nullptr);
+            if (p->mode == 0) {
+                s = ckks_rotate_hoisted(c, in->shards[u], st.data(), cnt, rots.data());
+            } else {
+                for (size_t t = 0; t < cnt && s == HEC_OK; t++) s = ckks_rotate(c, in->shards[u], st[t], &rots[t]);
+            }
+            for (size_t t = 0; t < cnt && s == HEC_OK; t++)
+                for (auto &pp : its[i0 + t].pts) {
+                    s = ct_mac_pt(c, acc[pp.first], rots[t], pp.second, first[pp.first]);
+                    first[pp.first] = 0;
+                    if (s != HEC_OK) break;
+                }
+            free_all(rots);
+        }
+    }
+    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+        if (first[v]) s = HEC_ELAYOUT, hec_set_error("output shard %zu received no product", v);
+        else s = ct_rescale(c, acc[v]);
+    }
+    if (s != HEC_OK) { free_all(acc); return s; }
+    hec_image *im = new hec_image();
+    im->ctx = c;
+    if (p->stride == 1) {
+        im->lay = p->out;
+        im->shards = acc;
+    } else {
+        s = downsample_and_merge(c, acc, p->out, true, im->shards, im->lay);
+        free_all(acc);
+        if (s != HEC_OK) { hec_image_free(im); return s; }
+    }
+    *out = im;
+    return HEC_OK;
+}
+
+extern "C" hec_status he_conv2d_sharded(hec_ctx *c, const hec_image *in, const double *w, uint32_t Co, uint32_t kh,
+                                        uint32_t kw, uint32_t stride, uint32_t pad, const double *bias,
+                                        hec_image **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (bias) HEC_FAIL(HEC_EINVAL, "bias is reserved and must be NULL");
+    hec_conv_plan *p = nullptr;
+    HEC_CHECK(he_conv2d_plan_create(c, in, w, Co, kh, kw, stride, pad, &p));
+    hec_status s = he_conv2d_plan_run(c, p, in, out);
+    he_conv2d_plan_free(p);
+    return s;
+}
+
+extern "C" hec_status he_avgpool(hec_ctx *c, const hec_image *in, uint32_t window, hec_image **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (window != 2) HEC_FAIL(HEC_EINVAL, "only 2x2 pooling is supported");
+    if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    std::set<int32_t> steps;
+    pool_steps(in->lay, false, in->shards[0]->level, steps);
+    for (int32_t s : steps)
+        if (!have_rotkey(c, s)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", s);
+    hec_image *im = new hec_image();
+    im->ctx = c;
+    hec_status s = downsample_and_merge(c, in->shards, in->lay, false, im->shards, im->lay);
+    if (s != HEC_OK) { hec_image_free(im); return s; }
+    *out = im;
+    return HEC_OK;
+}
+
+extern "C" hec_status he_avgpool_steps(hec_ctx *c, const hec_image *like, int32_t *steps, size_t cap, size_t *count)
+{
+    if (!c || !like || like->shards.empty()) HEC_FAIL(HEC_EINVAL, "bad arguments");
+    std::set<int32_t> st;
+    pool_steps(like->lay, false, like->shards[0]->level, st);
+    if (count) *count = st.size();
+    if (steps) {
+        if (cap < st.size()) HEC_FAIL(HEC_EINVAL, "capacity too small");
+        size_t i = 0;
+        for (int32_t x : st) steps[i++] = x;
+    }
+    return HEC_OK;
+}

@@ -1,0 +1,398 @@
+"""Thin Python binding of libhecnn.so (include/hecnn.h): argument marshalling
+only -- every step of the computation runs in the HIP library.  Raises if the
+library is missing; there is no fallback path."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhecnn.so")
+
+HEC_OK, HEC_EINVAL, HEC_ENOMEM, HEC_ELEVEL, HEC_ESCALE, HEC_ENOKEY, HEC_ELAYOUT, HEC_EDEVICE, HEC_EBUSY = range(9)
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ELEVEL", 4: "ESCALE", 5: "ENOKEY", 6: "ELAYOUT", 7: "EDEVICE",
+          8: "EBUSY"}
+
+# every symbol the header declares
+EXPORTS = [
+    "hec_ctx_create", "hec_ctx_destroy", "hec_last_error", "hec_ctx_primes", "hec_ctx_slots", "ckks_keygen",
+    "ckks_gen_rotation_keys", "hec_ctx_key_bytes", "ckks_encode", "ckks_encrypt", "ckks_encrypt_idx", "ckks_decrypt",
+    "ckks_rotate", "ckks_rotate_hoisted", "ckks_rescale", "ckks_mul_pt", "ckks_add", "ckks_ct_info", "ckks_ct_export",
+    "ckks_ct_import", "ckks_pt_export", "ckks_pt_import", "ckks_encode_coeffs", "he_image_encrypt",
+    "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
+    "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
+    "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "hec_ct_free", "hec_pt_free", "hec_image_free",
+    "hec_ctx_sync",
+]
+
+
+class HecError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("L", ctypes.c_uint32), ("q0_bits", ctypes.c_uint32),
+                ("q_bits", ctypes.c_uint32), ("k", ctypes.c_uint32), ("p_bits", ctypes.c_uint32),
+                ("dnum", ctypes.c_uint32), ("log_scale", ctypes.c_uint32), ("sigma", ctypes.c_double),
+                ("secret_dist", ctypes.c_uint32)]
+
+
+_lib = None
+vp = ctypes.c_void_p
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+i32p = ctypes.POINTER(ctypes.c_int32)
+u32p = ctypes.POINTER(ctypes.c_uint32)
+dblp = ctypes.POINTER(ctypes.c_double)
+szp = ctypes.POINTER(ctypes.c_size_t)
+
+
+def lib():
+    """Load libhecnn.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhecnn.so is not built (run __graft_entry__.build()); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        c, u32, u64, dbl, sz = ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+        P = ctypes.POINTER
+        sig = {
+            "hec_ctx_create": (c, [P(Params), c, vp, P(vp)]),
+            "hec_ctx_destroy": (None, [vp]),
+            "hec_last_error": (ctypes.c_char_p, []),
+            "hec_ctx_primes": (c, [vp, u64p, sz, szp]),
+            "hec_ctx_slots": (u32, [vp]),
+            "ckks_keygen": (c, [vp, u64, i32p, sz]),
+            "ckks_gen_rotation_keys": (c, [vp, i32p, sz]),
+            "hec_ctx_key_bytes": (sz, [vp]),
+            "ckks_encode": (c, [vp, dblp, sz, u32, dbl, P(vp)]),
+            "ckks_encrypt": (c, [vp, vp, u64, P(vp)]),
+            "ckks_encrypt_idx": (c, [vp, vp, u64, u64, P(vp)]),
+            "ckks_decrypt": (c, [vp, vp, dblp, sz]),
+            "ckks_rotate": (c, [vp, vp, ctypes.c_int32, P(vp)]),
+            "ckks_rotate_hoisted": (c, [vp, vp, i32p, sz, P(vp)]),
+            "ckks_rescale": (c, [vp, vp]),
+            "ckks_mul_pt": (c, [vp, vp, vp, P(vp)]),
+            "ckks_add": (c, [vp, vp, vp, P(vp)]),
+            "ckks_ct_info": (c, [vp, u32p, dblp]),
+            "ckks_ct_export": (c, [vp, vp, u64p, u32p, dblp]),
+            "ckks_ct_import": (c, [vp, u64p, u32, dbl, P(vp)]),
+            "ckks_pt_export": (c, [vp, vp, u64p, u32p, dblp]),
+            "ckks_pt_import": (c, [vp, u64p, u32, dbl, P(vp)]),
+            "ckks_encode_coeffs": (c, [vp, dblp, sz, dbl, i64p]),
+            "he_image_encrypt": (c, [vp, dblp, u32, u32, u32, u32, u64, P(vp)]),
+            "he_image_decrypt": (c, [vp, vp, dblp]),
+            "he_image_info": (c, [vp, u32p, u32p, u32p, u32p, u32p]),
+            "he_image_block_map": (c, [vp, u32, i32p, sz]),
+            "he_image_shard": (vp, [vp, u32]),
+            "he_conv2d_sharded": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, dblp, P(vp)]),
+            "he_conv2d_plan_create": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, P(vp)]),
+            "he_conv2d_plan_run": (c, [vp, vp, vp, P(vp)]),
+            "he_conv2d_plan_set_mode": (c, [vp, c]),
+            "he_conv2d_plan_steps": (c, [vp, i32p, sz, szp]),
+            "he_avgpool_steps": (c, [vp, vp, i32p, sz, szp]),
+            "he_conv2d_plan_free": (None, [vp]),
+            "he_avgpool": (c, [vp, vp, u32, P(vp)]),
+            "hec_ct_free": (None, [vp]),
+            "hec_pt_free": (None, [vp]),
+            "hec_image_free": (None, [vp]),
+            "hec_ctx_sync": (c, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != HEC_OK:
+        raise HecError(status, lib().hec_last_error().decode())
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+class Ciphertext:
+    def __init__(self, ctx, handle):
+        self.ctx, self.h = ctx, handle
+
+    def free(self):
+        if self.h:
+            lib().hec_ct_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        lvl, sc = ctypes.c_uint32(), ctypes.c_double()
+        check(lib().ckks_ct_info(self.h, ctypes.byref(lvl), ctypes.byref(sc)))
+        return lvl.value, sc.value
+
+    @property
+    def level(self):
+        return self.info()[0]
+
+    @property
+    def scale(self):
+        return self.info()[1]
+
+    def export(self):
+        """Canonical form: [2][level+1][n] uint64, coefficient domain."""
+        lvl = self.level
+        out = np.zeros((2, lvl + 1, self.ctx.n), dtype=np.uint64)
+        check(lib().ckks_ct_export(self.ctx.h, self.h, _p(out, u64p), None, None))
+        return out
+
+
+class Plaintext:
+    def __init__(self, ctx, handle, level, scale):
+        self.ctx, self.h, self.level, self.scale = ctx, handle, level, scale
+
+    def free(self):
+        if self.h:
+            lib().hec_pt_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self):
+        out = np.zeros((self.level + 1, self.ctx.n), dtype=np.uint64)
+        check(lib().ckks_pt_export(self.ctx.h, self.h, _p(out, u64p), None, None))
+        return out
+
+
+class Image:
+    def __init__(self, ctx, handle):
+        self.ctx, self.h = ctx, handle
+
+    def free(self):
+        if self.h:
+            lib().hec_image_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        v = [ctypes.c_uint32() for _ in range(5)]
+        check(lib().he_image_info(self.h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)  # C, H, W, mp, n_shards
+
+    def block_map(self, u):
+        C, H, W, mp, t = self.info()
+        lam = np.zeros(self.ctx.N // (mp * mp), dtype=np.int32)
+        check(lib().he_image_block_map(self.h, u, _p(lam, i32p), len(lam)))
+        return lam
+
+    def shard_export(self, u):
+        h = lib().he_image_shard(self.h, u)
+        if not h:
+            raise IndexError(u)
+        ct = Ciphertext(self.ctx, h)
+        try:
+            return ct.export()
+        finally:
+            ct.h = None  # borrowed
+
+    def shard_info(self, u):
+        h = lib().he_image_shard(self.h, u)
+        lvl, sc = ctypes.c_uint32(), ctypes.c_double()
+        check(lib().ckks_ct_info(h, ctypes.byref(lvl), ctypes.byref(sc)))
+        return lvl.value, sc.value
+
+    def decrypt(self):
+        C, H, W, mp, t = self.info()
+        x = np.zeros((C, H, W))
+        check(lib().he_image_decrypt(self.ctx.h, self.h, _p(x, dblp)))
+        return x
+
+
+class ConvPlan:
+    def __init__(self, ctx, handle):
+        self.ctx, self.h = ctx, handle
+
+    def free(self):
+        if self.h:
+            lib().he_conv2d_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def steps(self):
+        n = ctypes.c_size_t()
+        check(lib().he_conv2d_plan_steps(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        check(lib().he_conv2d_plan_steps(self.h, _p(out, i32p), len(out), ctypes.byref(n)))
+        return [int(x) for x in out]
+
+    def set_mode(self, mode):
+        check(lib().he_conv2d_plan_set_mode(self.h, int(mode)))
+
+    def run(self, img):
+        out = vp()
+        check(lib().he_conv2d_plan_run(self.ctx.h, self.h, img.h, ctypes.byref(out)))
+        return Image(self.ctx, out.value)
+
+
+class Context:
+    """An RNS-CKKS context on one HIP device; `stream` is a hipStream_t (int or
+    None), e.g. torch.cuda.current_stream().cuda_stream."""
+
+    def __init__(self, log_n, L, q0_bits, q_bits, k, p_bits, dnum, log_scale, sigma=3.2, device=0, stream=None):
+        self.prm = Params(log_n, L, q0_bits, q_bits, k, p_bits, dnum, log_scale, sigma, 0)
+        h = vp()
+        check(lib().hec_ctx_create(ctypes.byref(self.prm), device, stream, ctypes.byref(h)))
+        self.h = h.value
+        self.n = 1 << log_n
+        self.N = self.n // 2
+        self.L, self.k = L, k
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hec_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def primes(self):
+        n = ctypes.c_size_t()
+        check(lib().hec_ctx_primes(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.uint64)
+        check(lib().hec_ctx_primes(self.h, _p(out, u64p), len(out), ctypes.byref(n)))
+        return [int(x) for x in out]
+
+    def keygen(self, seed, steps=()):
+        st = _arr(list(steps) or [0], np.int32)
+        check(lib().ckks_keygen(self.h, seed, _p(st, i32p), len(steps)))
+
+    def gen_rotation_keys(self, steps):
+        st = _arr(list(steps) or [0], np.int32)
+        check(lib().ckks_gen_rotation_keys(self.h, _p(st, i32p), len(steps)))
+
+    def key_bytes(self):
+        return lib().hec_ctx_key_bytes(self.h)
+
+    def encode(self, z, level, scale):
+        z = _arr(z, np.float64)
+        out = vp()
+        check(lib().ckks_encode(self.h, _p(z, dblp), len(z), level, float(scale), ctypes.byref(out)))
+        return Plaintext(self, out.value, level, float(scale))
+
+    def encode_coeffs(self, z, scale):
+        z = _arr(z, np.float64)
+        m = np.zeros(self.n, dtype=np.int64)
+        check(lib().ckks_encode_coeffs(self.h, _p(z, dblp), len(z), float(scale), _p(m, i64p)))
+        return m
+
+    def pt_import(self, coeff, level, scale):
+        coeff = _arr(coeff, np.uint64)
+        out = vp()
+        check(lib().ckks_pt_import(self.h, _p(coeff, u64p), level, float(scale), ctypes.byref(out)))
+        return Plaintext(self, out.value, level, float(scale))
+
+    def encrypt(self, pt, seed, index=0):
+        out = vp()
+        check(lib().ckks_encrypt_idx(self.h, pt.h, seed, index, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def decrypt(self, ct, nz=None):
+        nz = self.N if nz is None else nz
+        z = np.zeros(nz)
+        check(lib().ckks_decrypt(self.h, ct.h, _p(z, dblp), nz))
+        return z
+
+    def ct_import(self, coeff, level, scale):
+        coeff = _arr(coeff, np.uint64)
+        out = vp()
+        check(lib().ckks_ct_import(self.h, _p(coeff, u64p), level, float(scale), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def rotate(self, ct, step):
+        out = vp()
+        check(lib().ckks_rotate(self.h, ct.h, int(step), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def rotate_hoisted(self, ct, steps):
+        st = _arr(steps, np.int32)
+        outs = (vp * len(st))()
+        check(lib().ckks_rotate_hoisted(self.h, ct.h, _p(st, i32p), len(st), outs))
+        return [Ciphertext(self, o) for o in outs]
+
+    def rescale(self, ct):
+        check(lib().ckks_rescale(self.h, ct.h))
+        return ct
+
+    def mul_pt(self, ct, pt):
+        out = vp()
+        check(lib().ckks_mul_pt(self.h, ct.h, pt.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def add(self, a, b):
+        out = vp()
+        check(lib().ckks_add(self.h, a.h, b.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def image_encrypt(self, x, level, seed):
+        x = _arr(x, np.float64)
+        C, H, W = x.shape
+        out = vp()
+        check(lib().he_image_encrypt(self.h, _p(x, dblp), C, H, W, level, seed, ctypes.byref(out)))
+        return Image(self, out.value)
+
+    def conv2d(self, img, w, stride=1, pad=1):
+        w = _arr(w, np.float64)
+        Co, Ci, kh, kw = w.shape
+        out = vp()
+        check(lib().he_conv2d_sharded(self.h, img.h, _p(w, dblp), Co, kh, kw, stride, pad, None,
+                                      ctypes.byref(out)))
+        return Image(self, out.value)
+
+    def conv2d_plan(self, like, w, stride=1, pad=1):
+        w = _arr(w, np.float64)
+        Co, Ci, kh, kw = w.shape
+        out = vp()
+        check(lib().he_conv2d_plan_create(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, ctypes.byref(out)))
+        return ConvPlan(self, out.value)
+
+    def avgpool(self, img):
+        out = vp()
+        check(lib().he_avgpool(self.h, img.h, 2, ctypes.byref(out)))
+        return Image(self, out.value)
+
+    def avgpool_steps(self, img):
+        n = ctypes.c_size_t()
+        check(lib().he_avgpool_steps(self.h, img.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        check(lib().he_avgpool_steps(self.h, img.h, _p(out, i32p), len(out), ctypes.byref(n)))
+        return [int(x) for x in out]
+
+    def sync(self):
+        check(lib().hec_ctx_sync(self.h))

@@ -1,0 +1,224 @@
+"""GPU library vs the CPU oracle, through the C ABI (MI355X).
+
+Bit-exact: prime chain, encoder integers, keys through encryption, hoisted
+and single rotations, rescale, plaintext products, additions, and the full
+conv / pool / strided-conv pipelines on several layouts (duplication, image
+shards, consolidation with permutation).  Decryptions within 1e-5 of FP64.
+Ring sizes span several NTT tiles and the two-pass split.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ckks
+from oracle import he_layers as hl
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(logn, L, q0, qb, k, pb, dnum, log_scale, seed):
+    from paper_2306_09189_amd import hecnn
+    log("ctx logn=%d L=%d k=%d dnum=%d" % (logn, L, k, dnum))
+    ctx = hecnn.Context(logn, L, q0, qb, k, pb, dnum, log_scale, device=0)
+    prm = ckks.Params(logn, [q0] + [qb] * L, [pb] * k, dnum)
+    ctx.keygen(seed)
+    return ctx, prm, ckks.Oracle(prm, seed)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return make(10, 6, 60, 40, 3, 60, 3, 40, 7)
+
+
+def test_primes(small):
+    ctx, prm, o = small
+    assert ctx.primes() == prm.mod
+
+
+@pytest.mark.parametrize("logn", [10, 13, 16])
+def test_encoder_integers(logn):
+    from paper_2306_09189_amd import hecnn
+    ctx = hecnn.Context(logn, 2, 60, 50, 1, 60, 1, 50, device=0)
+    o = ckks.Oracle(ckks.Params(logn, [60, 50, 50], [60], 1), 1)
+    rng = np.random.default_rng(logn)
+    N = 1 << (logn - 1)
+    for scale in (2.0 ** 40, 2.0 ** 50, float(ctx.primes()[2])):
+        z = rng.uniform(-1, 1, N)
+        assert (ctx.encode_coeffs(z, scale) == o.encode_coeffs(z, scale)).all()
+        z = (rng.uniform(0, 1, N) < 0.2) * rng.normal(0, 0.1)
+        assert (ctx.encode_coeffs(z, scale) == o.encode_coeffs(z, scale)).all()
+
+
+def test_import_export_roundtrip(small):
+    ctx, prm, o = small
+    rng = np.random.default_rng(2)
+    lvl = 4
+    coeff = np.stack([np.stack([rng.integers(0, q, prm.n, dtype=np.uint64) for q in prm.q[: lvl + 1]])
+                      for _ in range(2)])
+    ct = ctx.ct_import(coeff, lvl, 2.0 ** 40)
+    assert (ct.export() == coeff).all()
+    pt = ctx.pt_import(coeff[0], lvl, 3.0)
+    assert (pt.export() == coeff[0]).all()
+
+
+def test_encrypt_decrypt_bit_exact(small):
+    ctx, prm, o = small
+    z = np.random.default_rng(3).uniform(-1, 1, prm.N)
+    for lvl, idx in ((6, 0), (3, 5), (0, 2)):
+        pt = ctx.encode(z, lvl, 2.0 ** 40)
+        opt = o.encode(z, lvl, 2.0 ** 40)
+        assert (pt.export() == opt.limbs).all()
+        ct = ctx.encrypt(pt, seed=99, index=idx)
+        oct_ = o.encrypt(opt, seed=99, index=idx)
+        assert (ct.export() == oct_.data).all()
+        assert np.abs(ctx.decrypt(ct) - z).max() < 1e-7
+
+
+def test_rotations_bit_exact(small):
+    ctx, prm, o = small
+    z = np.random.default_rng(4).uniform(-1, 1, prm.N)
+    steps = [1, 2, 3, 17, prm.N - 1, -5, 0, 100, 511]
+    ctx.gen_rotation_keys(steps)
+    for lvl in (6, 4, 2, 0):
+        opt = o.encode(z, lvl, 2.0 ** 40)
+        oct_ = o.encrypt(opt, seed=5, index=lvl)
+        ct = ctx.ct_import(oct_.data, lvl, 2.0 ** 40)
+        rots = ctx.rotate_hoisted(ct, steps)
+        orots = o.rotate_hoisted(oct_, steps)
+        for s, r, orr in zip(steps, rots, orots):
+            assert (r.export() == orr.data).all(), (lvl, s)
+        single = ctx.rotate(ct, 17)
+        assert (single.export() == orots[3].data).all()
+        assert np.abs(ctx.decrypt(rots[0]) - np.roll(z, -1)).max() < 1e-6
+
+
+def test_missing_key_is_reported(small):
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    ct = ctx.encrypt(ctx.encode(np.zeros(4), 2, 2.0 ** 40), seed=1)
+    with pytest.raises(hecnn.HecError) as e:
+        ctx.rotate(ct, 9)
+    assert e.value.status == hecnn.HEC_ENOKEY
+
+
+def test_rescale_mul_add_bit_exact(small):
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    rng = np.random.default_rng(6)
+    z, w = rng.uniform(-1, 1, prm.N), rng.uniform(-1, 1, prm.N)
+    lvl = 5
+    oct_ = o.encrypt(o.encode(z, lvl, 2.0 ** 40), seed=8)
+    opt = o.encode(w, lvl, float(prm.q[lvl]))
+    ct = ctx.ct_import(oct_.data, lvl, 2.0 ** 40)
+    pt = ctx.pt_import(opt.limbs, lvl, float(prm.q[lvl]))
+    prod = ctx.mul_pt(ct, pt)
+    oprod = o.mul_pt(oct_, opt)
+    assert (prod.export() == oprod.data).all()
+    s = ctx.add(prod, prod)
+    assert (s.export() == o.add(oprod, oprod).data).all()
+    ctx.rescale(prod)
+    ores = o.rescale(oprod)
+    assert (prod.export() == ores.data).all()
+    assert prod.level == lvl - 1 and prod.scale == ores.scale
+    assert np.abs(ctx.decrypt(prod) - z * w).max() < 1e-6
+    with pytest.raises(hecnn.HecError) as e:
+        ctx.add(prod, ct)
+    assert e.value.status == hecnn.HEC_ELEVEL
+
+
+def run_pipeline(ctx, prm, o, x, ops, level, seed):
+    """Encrypt x on both sides, apply ops ('conv', w, stride) / ('pool',),
+    compare every shard bit for bit after every op; return final decryption."""
+    C, H, W = x.shape
+    img = ctx.image_encrypt(x, level, seed)
+    lay = hl.natural_layout(prm.N, C, H, W)
+    be = hl.CkksBackend(o)
+    cts = [o.encrypt(o.encode(v, level, 2.0 ** prm_log_scale(ctx)), seed=seed, index=u)
+           for u, v in enumerate(hl.pack(x, lay))]
+    for u in range(len(cts)):
+        assert (img.shard_export(u) == cts[u].data).all(), "encrypt shard %d" % u
+    ref = x
+    for op in ops:
+        if op[0] == "conv":
+            w, stride = op[1], op[2]
+            plan = ctx.conv2d_plan(img, w, stride=stride, pad=1)
+            ctx.gen_rotation_keys(plan.steps())
+            img = plan.run(img)
+            cts, lay = hl.conv2d(be, cts, lay, w, pad=1, stride=stride)
+            ref = hl.ref_conv2d(ref, w, 1, stride)
+        else:
+            ctx.gen_rotation_keys(ctx.avgpool_steps(img))
+            img = ctx.avgpool(img)
+            cts, lay = hl.avgpool2x2(be, cts, lay)
+            ref = hl.ref_avgpool2x2(ref)
+        Cn, Hn, Wn, mp, t = img.info()
+        assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
+        for u in range(t):
+            assert list(img.block_map(u)) == list(lay.shards[u])
+            assert img.shard_info(u) == (cts[u].level, cts[u].scale)
+            assert (img.shard_export(u) == cts[u].data).all(), (op[0], u)
+        log("  op %s ok: %d shards, level %d" % (op[0], t, cts[0].level))
+    got = img.decrypt()
+    assert np.abs(got - ref).max() < 1e-5
+    return got
+
+
+def prm_log_scale(ctx):
+    return ctx.prm.log_scale
+
+
+@pytest.mark.parametrize("shape,ops", [
+    ((4, 8, 8), [("conv", (4, 3), 1), ("pool",)]),                  # d = 2 copies, pool -> dup x4
+    ((4, 16, 16), [("conv", (4, 3), 1), ("pool",)]),                # 2 image shards -> consolidate + dup x2
+    ((8, 16, 16), [("pool",), ("conv", (8, 3), 1)]),                # 4 shards -> 1 permuted, then conv
+    ((16, 16, 16), [("conv", (8, 3), 1), ("pool",)]),               # 8 shards -> 4 -> 1 shard
+    ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv: 4 shards -> 1
+    ((3, 12, 12), [("conv", (5, 3), 1)]),                           # padding of side and channels
+])
+def test_layers_bit_exact(small, shape, ops):
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape))
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("layers", shape, [op[0] for op in ops])
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=31)
+
+
+def test_plain_equals_batched(small):
+    ctx, prm, o = small
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, (8, 16, 16))
+    w = rng.normal(0, 0.1, (8, 8, 3, 3))
+    img = ctx.image_encrypt(x, 5, 3)
+    plan = ctx.conv2d_plan(img, w)
+    ctx.gen_rotation_keys(plan.steps())
+    a = plan.run(img)
+    plan.set_mode(1)
+    b = plan.run(img)
+    for u in range(a.info()[4]):
+        assert (a.shard_export(u) == b.shard_export(u)).all()
+
+
+def test_ring_2e13_conv_pool():
+    """2N = 2^13, q 3 x 40-bit, one 60-bit special prime, scale 2^40: one
+    32x32x4 image, 3x3 conv 4->4 (stride 1, pad 1), then 2x2 average pooling
+    fused into one level; bit-exact with the oracle, 1e-5 against FP64."""
+    ctx, prm, o = make(13, 2, 40, 40, 1, 60, 3, 40, 2001)
+    rng = np.random.default_rng(1001)
+    x = rng.uniform(-1, 1, (4, 32, 32))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    run_pipeline(ctx, prm, o, x, [("conv", w, 1), ("pool",)], 2, seed=3001)
