@@ -115,6 +115,12 @@ void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0
 void hec_automorph_ntt(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
                        u32 g, hipStream_t st);
 
+// centered CRT of [nq][n] residues (coefficient form) into doubles; Mm[i][j] =
+// prod_{k<j} q_k mod q_i in Montgomery form (row stride HEC_MAX_LIMBS), inv[i] =
+// (prod_{k<i} q_k)^-1 mod q_i with its Shoup companion
+void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, const u64 *Mm, const u64 *inv,
+                    const u64 *invsh, hipStream_t st);
+
 // dst[p][l] = src[p][l] for nl limbs (generic strided copy)
 void hec_copy_limbs(u64 *dst, const u64 *src, size_t dst_poly_stride, size_t src_poly_stride, int npolys,
                     size_t limb_elems, hipStream_t st);

@@ -247,6 +247,28 @@ static hec_status build_tables(hec_ctx *c)
     c->d_gauss = c->alloc(19);
     HEC_CHECK(upload(c->d_gauss, gT, sizeof(gT), c->st));
 
+    // Garner tables over q_0..q_L
+    {
+        std::vector<u64> Mm((size_t)HEC_MAX_LIMBS * HEC_MAX_LIMBS, 0), inv(HEC_MAX_LIMBS, 0), invsh(HEC_MAX_LIMBS, 0);
+        for (uint32_t i = 0; i <= L; i++) {
+            u64 qi = c->mod[i], r1 = (u64)(((u128)1 << 64) % qi), pr = 1;
+            for (uint32_t j = 0; j < i; j++) {
+                Mm[(size_t)i * HEC_MAX_LIMBS + j] = mulmod(pr, r1, qi);
+                pr = mulmod(pr, c->mod[j] % qi, qi);
+            }
+            inv[i] = i ? invmod(pr, qi) : 1;
+            invsh[i] = shoup_of(inv[i], qi);
+        }
+        c->d_crt_m = c->alloc(Mm.size());
+        c->d_crt_inv = c->alloc(HEC_MAX_LIMBS);
+        c->d_crt_invsh = c->alloc(HEC_MAX_LIMBS);
+        if (!c->d_crt_m || !c->d_crt_inv || !c->d_crt_invsh) HEC_FAIL(HEC_ENOMEM, "table allocation");
+        HEC_CHECK(upload(c->d_crt_m, Mm.data(), Mm.size() * 8, c->st));
+        HEC_CHECK(upload(c->d_crt_inv, inv.data(), inv.size() * 8, c->st));
+        HEC_CHECK(upload(c->d_crt_invsh, invsh.data(), invsh.size() * 8, c->st));
+        HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    }
+
     c->T.logn = c->logn;
     c->T.n = n;
     c->T.nprimes = NLK;
@@ -634,57 +656,22 @@ extern "C" hec_status ckks_encrypt(hec_ctx *c, const hec_pt *pt, uint64_t seed, 
     return ckks_encrypt_idx(c, pt, seed, 0, out);
 }
 
-// centered CRT of [nq][n] residues into doubles (Garner mixed radix)
-static void crt_to_double(const hec_ctx *c, const u64 *res, uint32_t nq, double *out)
+hec_status decrypt_slots(hec_ctx *c, const hec_ct *ct, double *z, size_t nz)
 {
-    const size_t n = c->n;
-    std::vector<u64> inv(nq, 0);  // (q_0 ... q_{i-1})^-1 mod q_i
-    for (uint32_t i = 1; i < nq; i++) {
-        u64 qi = c->mod[i], pr = 1;
-        for (uint32_t j = 0; j < i; j++) pr = mulmod(pr, c->mod[j] % qi, qi);
-        inv[i] = invmod(pr, qi);
-    }
-    std::vector<u64> v(nq);
-    for (size_t t = 0; t < n; t++) {
-        for (uint32_t i = 0; i < nq; i++) {
-            u64 qi = c->mod[i];
-            // value of the known digits mod q_i, Horner from the top
-            u64 acc = 0;
-            for (int j = (int)i - 1; j >= 0; j--) acc = (mulmod(acc, c->mod[j] % qi, qi) + v[j] % qi) % qi;
-            u64 r = res[i * n + t];
-            v[i] = mulmod((r + qi - acc) % qi, inv[i] ? inv[i] : 1, qi);
-        }
-        bool negative = 2 * (u128)v[nq - 1] >= (u128)c->mod[nq - 1];
-        long double val = 0;
-        for (int j = (int)nq - 1; j >= 0; j--) {
-            u64 d = negative ? c->mod[j] - 1 - v[j] : v[j];
-            val = val * (long double)c->mod[j] + (long double)d;
-        }
-        out[t] = negative ? (double)(-(val + 1)) : (double)val;
-    }
-}
-
-static hec_status decrypt_coeffs(hec_ctx *c, const hec_ct *ct, std::vector<u64> &res)
-{
+    // m = c0 + c1 s, back to coefficients, centered CRT on the device; the
+    // host only runs the final FFT of the decoding (client side)
     const size_t n = c->n, nq = ct->level + 1;
-    u64 *t = c->alloc(nq * n);
+    u64 *t = c->alloc(nq * n + n);
     if (!t) HEC_FAIL(HEC_ENOMEM, "decryption buffer");
+    double *dm = (double *)(t + nq * n);
     hec_ew(c->T, EW_MUL_MONT, t, ct->d + nq * n, c->d_sM, 0, 0, 0, 1, c->idmap(), nq, c->st);
     hec_ew(c->T, EW_ADD, t, t, ct->d, 0, 0, 0, 1, c->idmap(), nq, c->st);
     hec_ntt_inv(c->T, t, 0, 1, c->idmap(), nq, c->st);
-    res.resize(nq * n);
-    HEC_TRY_HIP(hipMemcpyAsync(res.data(), t, nq * n * 8, hipMemcpyDeviceToHost, c->st));
+    hec_crt_double(c->T, t, dm, (int)nq, c->d_crt_m, c->d_crt_inv, c->d_crt_invsh, c->st);
+    std::vector<double> m(n);
+    HEC_TRY_HIP(hipMemcpyAsync(m.data(), dm, n * 8, hipMemcpyDeviceToHost, c->st));
     HEC_TRY_HIP(hipStreamSynchronize(c->st));
     c->release(t);
-    return HEC_OK;
-}
-
-hec_status decrypt_slots(hec_ctx *c, const hec_ct *ct, double *z, size_t nz)
-{
-    std::vector<u64> res;
-    HEC_CHECK(decrypt_coeffs(c, ct, res));
-    std::vector<double> m(c->n);
-    crt_to_double(c, res.data(), ct->level + 1, m.data());
     c->enc->decode(m.data(), ct->scale, z, nz);
     return HEC_OK;
 }

@@ -71,6 +71,7 @@ struct hec_ctx {
     LevelC *d_lvl = nullptr;         // [level]
     u64 *d_pmodq = nullptr;          // [P]_{q_i}
     u64 *d_gauss = nullptr;
+    u64 *d_crt_m = nullptr, *d_crt_inv = nullptr, *d_crt_invsh = nullptr;  // Garner tables (q primes)
     std::vector<BconvDesc> h_modup, h_moddown;
     std::unique_ptr<hec::Encoder> enc;
     // keys

@@ -574,3 +574,39 @@ void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0
     hipLaunchKernelGGL(k_encrypt_finish, gr, dim3(EW_THREADS), 0, st, ct, v, e0, e1, m, pk, pk_poly_stride, (u32)nq,
                        T);
 }
+
+// ---------------------------------------------------------------------------
+// decryption: centered CRT of [nq][n] residues to doubles (Garner mixed radix)
+//   v_i = (r_i - sum_{j<i} v_j prod_{k<j} q_k) * (prod_{k<i} q_k)^-1  mod q_i
+// value = sum_j v_j prod_{k<j} q_k, centered by comparing the top digit with
+// q_top / 2 (for |value| < Q/2 - Q/q_top the test is exact).
+// ---------------------------------------------------------------------------
+__global__ void k_crt_double(const u64 *res, double *out, u32 nq, const u64 *Mm, const u64 *inv, const u64 *invsh,
+                             DevTables T)
+{
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    u64 v[HEC_MAX_LIMBS];
+    for (u32 i = 0; i < nq; i++) {
+        const PrimeC pc = T.pc[i];
+        u64 acc = 0;
+        for (u32 j = 0; j < i; j++) acc = add_mod(acc, mont_mul(v[j], Mm[i * HEC_MAX_LIMBS + j], pc.q, pc.qinv_neg), pc.q);
+        u64 r = res[(size_t)i * T.n + t];
+        v[i] = shoup_mul(sub_mod(r, acc, pc.q), inv[i], invsh[i], pc.q);
+    }
+    const u64 qt = T.pc[nq - 1].q;
+    const bool negative = v[nq - 1] >= (qt + 1) / 2;
+    double val = 0.0;
+    for (int j = (int)nq - 1; j >= 0; j--) {
+        u64 q = T.pc[j].q;
+        u64 d = negative ? q - 1 - v[j] : v[j];
+        val = val * (double)q + (double)d;
+    }
+    out[t] = negative ? -(val + 1.0) : val;
+}
+void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, const u64 *Mm, const u64 *inv,
+                    const u64 *invsh, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS);
+    hipLaunchKernelGGL(k_crt_double, g, dim3(EW_THREADS), 0, st, res, out, (u32)nq, Mm, inv, invsh, T);
+}

@@ -1,0 +1,121 @@
+"""GPU vs oracle at the full ring size 2N = 2^16 (q_0 60-bit + 24 x 50-bit,
+8 x 60-bit special primes, dnum = 3, scale 2^50), in the launch
+configuration bench.py times (batched hoisted rotations, plan runs).
+
+* bit-exact: public-key encryption at level 20, hoisted rotations at levels
+  20 and 24 (full and partial last digit), plaintext MAC + rescale, and one
+  complete 3x3 convolution of a 2-channel 112x112 shard (the per-shard
+  geometry of the 112x112x64 layer: side padded to 128, 2 channels per
+  ciphertext, 17 rotations);
+* decrypted within 1e-5 of FP64: the 32x32x32 image through conv 3x3 32->32
+  and the strided conv 3x3 32->64 (the benchmark step).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ckks
+from oracle import he_layers as hl
+
+pytestmark = pytest.mark.gpu
+
+LOGN, L, Q0, QB, K, PB, DNUM, LS = 16, 24, 60, 50, 8, 60, 3, 50
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2306_09189_amd import hecnn
+    log("2^16 context")
+    ctx = hecnn.Context(LOGN, L, Q0, QB, K, PB, DNUM, LS, device=0)
+    prm = ckks.Params(LOGN, [Q0] + [QB] * L, [PB] * K, DNUM)
+    assert ctx.primes() == prm.mod
+    ctx.keygen(2002)
+    return ctx, prm, ckks.Oracle(prm, 2002)
+
+
+def test_encrypt_and_rotations(full):
+    ctx, prm, o = full
+    z = np.random.default_rng(0).uniform(-1, 1, prm.N)
+    steps = [1, 1024 + 32 - 1, prm.N - 33]
+    ctx.gen_rotation_keys(steps)
+    for lvl in (20, 24):
+        log("level", lvl)
+        pt = ctx.encode(z, lvl, 2.0 ** LS)
+        opt = o.encode(z, lvl, 2.0 ** LS)
+        assert (pt.export() == opt.limbs).all()
+        ct = ctx.encrypt(pt, seed=3002, index=lvl)
+        oct_ = o.encrypt(opt, seed=3002, index=lvl)
+        assert (ct.export() == oct_.data).all()
+        rots = ctx.rotate_hoisted(ct, steps)
+        orots = o.rotate_hoisted(oct_, steps)
+        for s, r, orr in zip(steps, rots, orots):
+            assert (r.export() == orr.data).all(), (lvl, s)
+        assert np.abs(ctx.decrypt(rots[0]) - np.roll(z, -1)).max() < 1e-6
+
+
+def test_mac_rescale(full):
+    ctx, prm, o = full
+    rng = np.random.default_rng(1)
+    lvl = 20
+    z, w = rng.uniform(-1, 1, prm.N), rng.normal(0, 0.05, prm.N)
+    oct_ = o.encrypt(o.encode(z, lvl, 2.0 ** LS), seed=4)
+    opt = o.encode(w, lvl, float(prm.q[lvl]))
+    ct = ctx.ct_import(oct_.data, lvl, 2.0 ** LS)
+    pt = ctx.encode(w, lvl, float(prm.q[lvl]))
+    assert (pt.export() == opt.limbs).all()
+    prod = ctx.rescale(ctx.mul_pt(ct, pt))
+    oprod = o.rescale(o.mul_pt(oct_, opt))
+    assert (prod.export() == oprod.data).all()
+    assert np.abs(ctx.decrypt(prod) - z * w).max() < 1e-9
+
+
+def test_conv_112_shard_bit_exact(full):
+    ctx, prm, o = full
+    rng = np.random.default_rng(2)
+    x = np.clip(rng.normal(0, 1, (2, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (2, 2, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3003)
+    C, H, W, mp, t = img.info()
+    assert (mp, t) == (128, 1)
+    plan = ctx.conv2d_plan(img, w)
+    assert len(plan.steps()) == 17
+    ctx.gen_rotation_keys(plan.steps())
+    out = plan.run(img)
+    log("oracle conv")
+    lay = hl.natural_layout(prm.N, 2, 112, 112)
+    cts = [o.encrypt(o.encode(v, 20, 2.0 ** LS), seed=3003, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    assert (img.shard_export(0) == cts[0].data).all()
+    oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1)
+    assert (out.shard_export(0) == oc[0].data).all()
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
+def test_benchmark_step_accuracy(full):
+    """The benchmark workload end to end, batched and plain, within 1e-5."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(1002)
+    x = rng.uniform(-1, 1, (32, 32, 32))
+    w1 = rng.normal(0, 0.05, (32, 32, 3, 3))
+    w2 = rng.normal(0, 0.05, (64, 32, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3002)
+    p1 = ctx.conv2d_plan(img, w1)
+    ctx.gen_rotation_keys(p1.steps())
+    a = p1.run(img)
+    p1.set_mode(1)
+    a_plain = p1.run(img)
+    assert (a.shard_export(0) == a_plain.shard_export(0)).all()
+    p2 = ctx.conv2d_plan(a, w2, stride=2)
+    ctx.gen_rotation_keys(p2.steps())
+    b = p2.run(a)
+    C, H, W, mp, t = b.info()
+    assert (C, H, W, t) == (64, 16, 16, 1) and b.shard_info(0)[0] == 16
+    ref = hl.ref_conv2d(hl.ref_conv2d(x, w1, 1), w2, 1, 2)
+    err = np.abs(b.decrypt() - ref).max()
+    log("max abs err", err)
+    assert err < 1e-5
