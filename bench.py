@@ -30,6 +30,56 @@ def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Dominant kernel of the step (largest share of GPU time in the rocprofv3
+# kernel trace): the row pass of the 2^16 forward NTT.  One work unit = one
+# 2^16-word limb, which takes 8 butterfly stages x 2^15 butterflies (one
+# modular multiplication each) and moves 2 x 512 KiB (read + write).
+DOMINANT = "k_ntt16_fwd_rows"
+MODMUL_PER_UNIT = 8 * (1 << 15)
+BYTES_PER_UNIT = 2 * (1 << 19)
+# ALU roof: 256 CUs x 64 VALU lanes x 2.4 GHz = 39.3 T lane-instructions/s
+# (the fp64 FMA rate, 78.6 TFLOP/s / 2; 64-bit integer multiply-add issues at
+# the same rate on gfx950); a 64-bit Shoup modular multiplication needs 10
+# integer multiply instructions -> 3.93 T modmul/s.
+PEAK_TMODMUL = 256 * 64 * 2.4e9 / 10 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")
+
+
+def read_traffic():
+    """key: value lines of the committed PMC summary (None if absent)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    return rec
+
+
+def kernel_source_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2306_09189_amd", "csrc", "hec_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def dominant_roofline(launches, units, kms):
+    if not launches or kms <= 0:
+        return None
+    avg_units = units / launches
+    avg_s = kms / launches * 1e-3
+    achieved = avg_units * MODMUL_PER_UNIT / avg_s / 1e12
+    traffic = None
+    rec = read_traffic()
+    if rec and rec.get("source_sha") == kernel_source_sha():
+        traffic = (float(rec["fetch_bytes_per_unit"]) + float(rec["write_bytes_per_unit"])) * avg_units
+    return {"bound": "alu", "kernel": DOMINANT, "achieved": achieved, "peak": PEAK_TMODMUL, "unit": "Tmodmul/s",
+            "frac": achieved / PEAK_TMODMUL, "traffic": traffic,
+            "avg_launch_us": avg_s * 1e6, "launches": launches, "avg_units_per_launch": avg_units,
+            "hbm_equiv_GBps": avg_units * BYTES_PER_UNIT / avg_s / 1e9,
+            "algorithmic_bytes_per_launch": avg_units * BYTES_PER_UNIT}
+
+
 def rotations_per_step():
     # conv1: 32 channel offsets x 9 taps - the zero rotation; conv2 the same;
     # downsampling of 2 shards: 15 horizontal + 15 vertical each; consolidate 1; duplicate 1
@@ -72,6 +122,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=2)
+    ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         eprint("bench.py measures one GPU: this build runs the whole path on a single MI355X "
@@ -88,6 +139,21 @@ def main():
     x = rng.uniform(-1, 1, (32, 32, 32))
     w1 = rng.normal(0, 0.05, (32, 32, 3, 3))
     w2 = rng.normal(0, 0.05, (64, 32, 3, 3))
+    if args.pmc_run:
+        # short run for hardware-counter passes: one conv layer, then a plain
+        # device copy of exactly 256 MiB to calibrate the byte counters
+        ctx.keygen(2002)
+        img = ctx.image_encrypt(x, LEVEL, 3002)
+        p1 = ctx.conv2d_plan(img, w1, stride=1, pad=1)
+        ctx.gen_rotation_keys(p1.steps())
+        o1 = p1.run(img)
+        ctx.sync()
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        eprint("pmc run done", o1.info())
+        return
     t0 = time.perf_counter()
     ctx.keygen(2002)
     img = ctx.image_encrypt(x, LEVEL, 3002)
@@ -118,6 +184,10 @@ def main():
     err = step(check=True)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the dominant kernel is timed launch by launch with HIP events on the
+    # library's stream during the timed steps
+    ctx.prof_start(DOMINANT)
+    first_launch = ctx.prof_launches(DOMINANT)
     t = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -125,8 +195,13 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
+    launches, units, kms = ctx.prof_stop()
     ms_step = wall * 1e3 / args.steps
     value = rotations_per_step() * args.steps / wall
+    roofline = dominant_roofline(launches, units, kms)
+    if roofline:
+        # dispatch range of the timed region in a kernel trace of this same command
+        roofline["trace_dispatch_range"] = [first_launch, first_launch + launches]
 
     # conv-layer latency: batched (hoisted ModUp, 16 rotations per key-switch launch) vs plain
     def conv_ms(mode, reps):
@@ -186,6 +261,7 @@ def main():
         "rot_per_s_single_level20": rot_single,
         "max_abs_err_vs_fp64": err,
         "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_rotations, args.cpu_seconds)

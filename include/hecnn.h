@@ -196,6 +196,19 @@ void hec_image_free(hec_image *img);
 /* Wait for all enqueued work of the context. */
 hec_status hec_ctx_sync(hec_ctx *ctx);
 
+/* ---- diagnostics ---------------------------------------------------------- */
+
+/* Time every launch of the named kernel with HIP events on the context stream
+ * until hec_prof_stop (one kernel at a time per process).  Names:
+ * k_ntt16_fwd_cols, k_ntt16_fwd_rows, k_ntt16_inv_rows, k_ntt16_inv_cols
+ * (units: 2^16-word limbs), k_ks_inner (units: rotation x limb),
+ * k_moddown_combine (units: rotation x output limb), k_bconv (units:
+ * polynomials), k_ew (units: limbs).  Both calls synchronize the stream. */
+hec_status hec_prof_start(hec_ctx *ctx, const char *kernel);
+hec_status hec_prof_stop(hec_ctx *ctx, uint64_t *launches, uint64_t *units, double *total_ms);
+/* Launches of the named kernel since the library was loaded (all contexts). */
+uint64_t hec_prof_launches(const char *kernel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 // gfx950 kernels of the RNS-CKKS conv/pool library.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -120,6 +121,11 @@ void hec_automorph_ntt(const DevTables &T, u64 *out, const u64 *in, size_t poly_
 // (prod_{k<i} q_k)^-1 mod q_i with its Shoup companion
 void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, const u64 *Mm, const u64 *inv,
                     const u64 *invsh, hipStream_t st);
+
+// launch timing of one kernel by name (NULL stops); collect syncs the events
+void hec_prof_select(const char *name);
+int hec_prof_collect(uint64_t *launches, uint64_t *units, double *ms);
+uint64_t hec_prof_count(const char *name);
 
 // dst[p][l] = src[p][l] for nl limbs (generic strided copy)
 void hec_copy_limbs(u64 *dst, const u64 *src, size_t dst_poly_stride, size_t src_poly_stride, int npolys,

@@ -905,3 +905,27 @@ extern "C" hec_status ckks_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec
     *out = o;
     return HEC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// diagnostics
+// ---------------------------------------------------------------------------
+extern "C" hec_status hec_prof_start(hec_ctx *c, const char *kernel)
+{
+    if (!c || !kernel) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    hec_prof_select(kernel);
+    return HEC_OK;
+}
+
+extern "C" uint64_t hec_prof_launches(const char *kernel) { return kernel ? hec_prof_count(kernel) : 0; }
+
+extern "C" hec_status hec_prof_stop(hec_ctx *c, uint64_t *launches, uint64_t *units, double *total_ms)
+{
+    if (!c || !launches || !units || !total_ms) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    if (hec_prof_collect(launches, units, total_ms) != 0) HEC_FAIL(HEC_EDEVICE, "event timing failed");
+    hec_prof_select(nullptr);
+    return HEC_OK;
+}

@@ -9,9 +9,87 @@
 //     once (base conversion, key-switch inner product).
 // Everything runs on the VALU: this is exact modular arithmetic, not a float
 // contraction, so the matrix cores are not used.
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
 #include "hec_common.h"
 
 #define DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// launch timing: while a kernel name is selected, every launch of that kernel
+// is bracketed by HIP events on its stream and its work units are counted.
+// ---------------------------------------------------------------------------
+namespace {
+struct Prof {
+    char name[64] = {0};
+    bool on = false;
+    std::vector<hipEvent_t> pool, used;
+    uint64_t launches = 0, units = 0;
+};
+Prof g_prof;
+// launches of every named kernel since the library was loaded
+std::map<std::string, uint64_t> g_count;
+hipEvent_t prof_event()
+{
+    hipEvent_t e;
+    if (!g_prof.pool.empty()) {
+        e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    g_prof.used.push_back(e);
+    return e;
+}
+}  // namespace
+
+void hec_prof_select(const char *name)
+{
+    for (auto e : g_prof.used) g_prof.pool.push_back(e);
+    g_prof.used.clear();
+    g_prof.launches = g_prof.units = 0;
+    g_prof.on = name && name[0];
+    if (g_prof.on) {
+        strncpy(g_prof.name, name, sizeof(g_prof.name) - 1);
+        g_prof.name[sizeof(g_prof.name) - 1] = 0;
+    }
+}
+int hec_prof_collect(uint64_t *launches, uint64_t *units, double *ms)
+{
+    double tot = 0;
+    for (size_t i = 0; i + 1 < g_prof.used.size(); i += 2) {
+        if (hipEventSynchronize(g_prof.used[i + 1]) != hipSuccess) return -1;
+        float t = 0;
+        if (hipEventElapsedTime(&t, g_prof.used[i], g_prof.used[i + 1]) != hipSuccess) return -1;
+        tot += t;
+    }
+    *launches = g_prof.launches;
+    *units = g_prof.units;
+    *ms = tot;
+    return 0;
+}
+uint64_t hec_prof_count(const char *name)
+{
+    auto it = g_count.find(name);
+    return it == g_count.end() ? 0 : it->second;
+}
+// A timed launch passes its events to the dispatch itself (hipExtLaunchKernelGGL),
+// so the two timestamps bracket the kernel's execution and nothing else.
+#define KLAUNCH(kname, nunits, kernel, grid, block, lds, st, ...)                                                  \
+    do {                                                                                                           \
+        g_count[kname]++;                                                                                          \
+        if (g_prof.on && !strcmp(g_prof.name, kname)) {                                                            \
+            hipEvent_t e0_ = prof_event(), e1_ = prof_event();                                                     \
+            hipExtLaunchKernelGGL(kernel, grid, block, lds, st, e0_, e1_, 0, __VA_ARGS__);                        \
+            g_prof.launches++;                                                                                     \
+            g_prof.units += (nunits);                                                                              \
+        } else {                                                                                                   \
+            hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                                         \
+        }                                                                                                          \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // modular helpers
@@ -172,10 +250,265 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_rows(u64 *base, size_t poly
     for (u32 e = threadIdx.x; e < tile; e += NTT_THREADS) a[e] = lds[e];
 }
 
+// ---------------------------------------------------------------------------
+// n = 2^16: both passes are 256-point transforms done as two radix-16 rounds
+// (16 words per thread in registers, 4 stages per round, one LDS exchange per
+// pass).  A tile is 16 transforms x 256 points: 16 columns in the column pass,
+// 16 rows in the row pass.  Round A holds the points i + 16h (h = 0..15) of a
+// transform, round B the points 16h + i.  Butterflies reduce lazily (Harvey):
+// forward values stay in [0, 4q), inverse values in [0, 2q); outputs are
+// fully reduced.
+// ---------------------------------------------------------------------------
+DEV u64 shoup_lazy(u64 a, u64 w, u64 wsh, u64 q) { return a * w - __umul64hi(a, wsh) * q; }  // [0, 2q)
+DEV void ct_bfly(u64 &x, u64 &y, u64 W, u64 Ws, u64 q2, u64 q)
+{
+    u64 u = x >= q2 ? x - q2 : x;
+    u64 v = shoup_lazy(y, W, Ws, q);
+    x = u + v;
+    y = u - v + q2;
+}
+DEV void gs_bfly(u64 &x, u64 &y, u64 W, u64 Ws, u64 q2, u64 q)
+{
+    u64 u = x, v = y;
+    u64 s = u + v;
+    x = s >= q2 ? s - q2 : s;
+    y = shoup_lazy(u - v + q2, W, Ws, q);
+}
+DEV u64 reduce4(u64 x, u64 q)
+{
+    u64 q2 = 2 * q;
+    x = x >= q2 ? x - q2 : x;
+    return x >= q ? x - q : x;
+}
+
+#define N16_PAD(c) ((c) + ((c) >> 4))  // padded LDS index inside a 256-point row (17 words per 16)
+
+// XCD-aware work order: workgroups are dealt round-robin to the 8 XCDs, each
+// with its own L2.  The flat grid of 16 x nlimbs x npolys tiles is remapped so
+// that each XCD walks one contiguous chunk of (limb, poly, tile) items; the
+// polynomials that share a prime -- and its 1 MiB twiddle table -- then run
+// back to back on the same L2 instead of being spread over all eight.
+struct Ntt16Item {
+    u32 tile, poly, limb;
+};
+DEV Ntt16Item ntt16_item(u32 npolys)
+{
+    const u32 w = blockIdx.x, total = gridDim.x;  // total = 16 * nlimbs * npolys, a multiple of 8
+    const u32 i = (w & 7) * (total >> 3) + (w >> 3);
+    Ntt16Item it;
+    it.tile = i & 15;
+    const u32 rest = i >> 4;
+    it.poly = rest % npolys;
+    it.limb = rest / npolys;
+    return it;
+}
+
+// forward column pass: stages 0..7 over the 256 rows of 16 columns
+__global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+                                                        DevTables T)
+{
+    __shared__ u64 lds[256 * 16];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const u64 q = T.pc[pi].q, q2 = 2 * q;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
+    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
+    const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
+    u64 x[16];
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = a[(size_t)(l + 16 * h) * 256 + col];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int half = 8 >> s;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) {
+                const u32 idx = (1u << s) + (h >> (4 - s));
+                ct_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) lds[(l + 16 * h) * 16 + col] = x[h];
+    __syncthreads();
+    const u32 hb = l;  // round B: rows 16*hb + i
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = lds[(16 * hb + i) * 16 + col];
+#pragma unroll
+    for (int s = 4; s < 8; s++) {
+        const int half = 128 >> s;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) {
+                const u32 idx = (1u << s) + ((16 * hb + i) >> (8 - s));
+                ct_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) a[(size_t)(16 * hb + i) * 256 + col] = x[i];
+}
+
+// forward row pass: stages 8..15 inside 16 rows of 256 words; fully reduced output
+__global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+                                                        DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const u64 q = T.pc[pi].q, q2 = 2 * q;
+    const u32 r0 = it.tile * 16;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
+    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
+    const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
+    const u32 grow = r0 + row;
+    u64 x[16];
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = a[row * 256 + l + 16 * h];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; s2++) {
+        const int half = 8 >> s2;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) {
+                const u32 idx = (256u << s2) + (grow << s2) + (h >> (4 - s2));
+                ct_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
+            }
+    }
+    u64 *lr = lds + row * 272;
+#pragma unroll
+    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = x[h];
+    __syncthreads();
+    const u32 hb = l;
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = lr[N16_PAD(16 * hb + i)];
+#pragma unroll
+    for (int s2 = 4; s2 < 8; s2++) {
+        const int half = 128 >> s2;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) {
+                const u32 idx = (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2));
+                ct_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = reduce4(x[i], q);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = lr[N16_PAD(l + 16 * h)];
+}
+
+// inverse row pass: stages 15..8 (Gentleman-Sande) inside 16 rows
+__global__ void __launch_bounds__(256) k_ntt16_inv_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+                                                        DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const u64 q = T.pc[pi].q, q2 = 2 * q;
+    const u32 r0 = it.tile * 16;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
+    const u64 *w = T.itw + ((size_t)pi << 16), *ws = T.itw_sh + ((size_t)pi << 16);
+    const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
+    const u32 grow = r0 + row;
+    u64 *lr = lds + row * 272;
+    u64 x[16];
+#pragma unroll
+    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = a[row * 256 + l + 16 * h];
+    __syncthreads();
+    const u32 hb = l;
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = lr[N16_PAD(16 * hb + i)];
+#pragma unroll
+    for (int s2 = 7; s2 >= 4; s2--) {
+        const int half = 128 >> s2;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) {
+                const u32 idx = (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2));
+                gs_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = x[i];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = lr[N16_PAD(l + 16 * h)];
+#pragma unroll
+    for (int s2 = 3; s2 >= 0; s2--) {
+        const int half = 8 >> s2;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) {
+                const u32 idx = (256u << s2) + (grow << s2) + (h >> (4 - s2));
+                gs_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = x[h];
+}
+
+// inverse column pass: stages 7..0, then the factor n^-1; fully reduced output
+__global__ void __launch_bounds__(256) k_ntt16_inv_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+                                                        DevTables T)
+{
+    __shared__ u64 lds[256 * 16];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q, q2 = 2 * q;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
+    const u64 *w = T.itw + ((size_t)pi << 16), *ws = T.itw_sh + ((size_t)pi << 16);
+    const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const u32 hb = l;
+    u64 x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = a[(size_t)(16 * hb + i) * 256 + col];
+#pragma unroll
+    for (int s = 7; s >= 4; s--) {
+        const int half = 128 >> s;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) {
+                const u32 idx = (1u << s) + ((16 * hb + i) >> (8 - s));
+                gs_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) lds[(16 * hb + i) * 16 + col] = x[i];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = lds[(l + 16 * h) * 16 + col];
+#pragma unroll
+    for (int s = 3; s >= 0; s--) {
+        const int half = 8 >> s;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) {
+                const u32 idx = (1u << s) + (h >> (4 - s));
+                gs_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
+            }
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) a[(size_t)(l + 16 * h) * 256 + col] = shoup_mul(x[h], pc.ninv, pc.ninv_sh, q);
+}
+
 static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stride, int npolys, const u32 *pmap,
                        int nlimbs, hipStream_t st)
 {
     if (nlimbs <= 0 || npolys <= 0) return;
+    if (T.logn == 16) {
+        const uint64_t limbs = (uint64_t)nlimbs * npolys;
+        dim3 g((u32)(16 * limbs));
+        const u32 np = (u32)npolys;
+        if (!inv) {
+            KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+            KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+        } else {
+            KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+            KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+        }
+        return;
+    }
     u32 logn1, logn2;
     ntt_split(T.logn, logn1, logn2);
     u32 n1 = 1u << logn1, n2 = 1u << logn2;
@@ -241,7 +574,8 @@ void hec_ew(const DevTables &T, EwOp op, u64 *out, const u64 *a, const u64 *b, s
 {
     if (nlimbs <= 0 || npolys <= 0) return;
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
-    hipLaunchKernelGGL(k_ew, g, dim3(EW_THREADS), 0, st, (int)op, out, a, b, so, sa, sb, pmap, T);
+    KLAUNCH("k_ew", (uint64_t)npolys * nlimbs, k_ew, g, dim3(EW_THREADS), 0, st, (int)op, out, a, b, so, sa, sb, pmap,
+            T);
 }
 
 __global__ void k_reduce_i64(u64 *out, const int64_t *x, const u32 *pmap, DevTables T)
@@ -422,18 +756,26 @@ void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const
 {
     (void)nout_host;
     dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, 1, npolys);
-    hipLaunchKernelGGL(k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, src, dst, src_poly_stride, dst_poly_stride, T);
+    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, src, dst, src_poly_stride,
+            dst_poly_stride, T);
 }
 
 // ---------------------------------------------------------------------------
 // key-switch inner product with the automorphism folded into the read:
 //   e_p[o][k] = sum_j D_j[o][perm_g(k)] * key_{g,j,p}[pmap[o]][k]
 // ---------------------------------------------------------------------------
+// Flat grid, XCD-aware: each XCD walks a contiguous run of (limb, rotation,
+// chunk) items, so the hoisted digits of a limb are read from HBM once per
+// XCD and reused from its L2 by every rotation of the batch.
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *D, u32 beta, u32 nqp,
-                                                         const u32 *pmap, u32 NLK, DevTables T)
+                                                         const u32 *pmap, u32 NLK, u32 nrot, u32 nchunks,
+                                                         DevTables T)
 {
-    const u32 o = blockIdx.y, r = blockIdx.z;
-    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    const u32 w = blockIdx.x, total = gridDim.x;
+    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 chunk = i % nchunks, rest = i / nchunks;
+    const u32 r = rest % nrot, o = rest / nrot;
+    const u32 k = chunk * EW_THREADS + threadIdx.x;
     if (k >= T.n) return;
     const u32 pi = pmap[o];
     const PrimeC pc = T.pc[pi];
@@ -453,8 +795,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st)
 {
-    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nqp, nrot);
-    hipLaunchKernelGGL(k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp, pmap, (u32)NLK, T);
+    const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
+    dim3 g(nchunks * (u32)nqp * (u32)nrot);
+    KLAUNCH("k_ks_inner", (uint64_t)nrot * nqp, k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp,
+            pmap, (u32)NLK, (u32)nrot, nchunks, T);
 }
 
 // ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)
@@ -476,7 +820,8 @@ void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, c
                          const LevelC *lc, const u32 *pmap, hipStream_t st)
 {
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, 2 * nq, nrot);
-    hipLaunchKernelGGL(k_moddown_combine, g, dim3(EW_THREADS), 0, st, cb, c0, (u32)nq, (u32)nqp, lc, pmap, T);
+    KLAUNCH("k_moddown_combine", (uint64_t)nrot * 2 * nq, k_moddown_combine, g, dim3(EW_THREADS), 0, st, cb, c0,
+            (u32)nq, (u32)nqp, lc, pmap, T);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@ EXPORTS = [
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "hec_ct_free", "hec_pt_free", "hec_image_free",
-    "hec_ctx_sync",
+    "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches",
 ]
 
 
@@ -99,6 +99,9 @@ def lib():
             "hec_pt_free": (None, [vp]),
             "hec_image_free": (None, [vp]),
             "hec_ctx_sync": (c, [vp]),
+            "hec_prof_start": (c, [vp, ctypes.c_char_p]),
+            "hec_prof_stop": (c, [vp, u64p, u64p, dblp]),
+            "hec_prof_launches": (u64, [ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -396,3 +399,17 @@ class Context:
 
     def sync(self):
         check(lib().hec_ctx_sync(self.h))
+
+    def prof_start(self, kernel):
+        check(lib().hec_prof_start(self.h, kernel.encode()))
+
+    def prof_stop(self):
+        """-> (launches, units, total_ms) of the kernel selected by prof_start."""
+        a, b, t = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        check(lib().hec_prof_stop(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        return a.value, b.value, t.value
+
+    @staticmethod
+    def prof_launches(kernel):
+        """Launches of `kernel` since the library was loaded."""
+        return lib().hec_prof_launches(kernel.encode())
