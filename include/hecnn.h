@@ -158,6 +158,10 @@ hec_status he_image_info(const hec_image *img, uint32_t *C, uint32_t *H, uint32_
 hec_status he_image_block_map(const hec_image *img, uint32_t u, int32_t *lam, size_t cap);
 /* Borrowed handle of shard u (valid while img lives). */
 const hec_ct *he_image_shard(const hec_image *img, uint32_t u);
+/* Channel shards (Section 4, channel side above sqrt(N)): shard u holds rows
+ * part*R .. part*R+R-1 (R = N/mp) of logical channel `channel`.  Fails with
+ * HEC_ELAYOUT on an image-sharded image (use he_image_block_map there). */
+hec_status he_image_channel_shard(const hec_image *img, uint32_t u, int32_t *channel, int32_t *part);
 
 /* Homomorphic conv2d (cross-correlation, zero padding `pad`, stride 1 or 2)
  * of an image-sharded input with weights w [Co][C][kh][kw] (PyTorch layout,

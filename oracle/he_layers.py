@@ -289,11 +289,69 @@ def conv_plan(lay, w, pad):
     return out, plan
 
 
+def conv_plan_channel(lay, w, pad):
+    """Plan of a stride-1 convolution of a channel-sharded input (Section 4.1,
+    "With Channel Shards"): shard (f, v) holds rows v*R .. v*R+R-1 of channel
+    f (R = N/mp).  Every input shard is rotated cyclically by k*mp + l for each
+    tap; output shard (g, v) takes, for each tap, the rows whose source row is
+    in the same shard from rot([M^f]_v) (mask m) and the rows whose source row
+    is in the neighbouring shard v + sign(k) from rot([M^f]_{v+sign k})
+    (complementary mask); rows outside the channel read zero padding."""
+    w = np.asarray(w, dtype=np.float64)
+    Co, Ci, kh, kw = w.shape
+    if Ci != lay.C:
+        raise ValueError("channel mismatch")
+    N, mp, H, W = lay.N, lay.mp, lay.H, lay.W
+    R = N // mp
+    spc = lay.B // N
+    Ho, Wo = H + 2 * pad - kh + 1, W + 2 * pad - kw + 1
+    if Ho < 1 or Wo < 1 or Ho > mp or Wo > mp:
+        raise ValueError("bad convolution geometry")
+    out = Layout(N, Co, Ho, Wo, mp, "channel", [(g, v) for g in range(Co) for v in range(spc)])
+    out_index = {s: u for u, s in enumerate(out.shards)}
+    il = np.arange(R)[:, None]
+    jj = np.arange(mp)[None, :]
+    plan = []
+    for f, vin in lay.shards:
+        items = []
+        for kr in range(kh):
+            for kc in range(kw):
+                dk, dl = kr - pad, kc - pad
+                amount = (dk * mp + dl) % N
+                pts = {}
+                # output shards that read this input shard for this tap: itself, and the shard
+                # whose rows reach into this one (v = vin - sign(dk))
+                cands = [vin] + ([vin - (1 if dk > 0 else -1)] if dk != 0 else [])
+                for v in cands:
+                    if v < 0 or v >= spc:
+                        continue
+                    gi = v * R + il                     # global output row
+                    src = gi + dk                       # global source row
+                    same = (il + dk >= 0) & (il + dk < R)
+                    m = (gi < Ho) & (jj < Wo) & (src >= 0) & (src < H) & (jj + dl >= 0) & (jj + dl < W)
+                    m = m & (same if v == vin else ~same)
+                    if not m.any():
+                        continue
+                    mask = m.astype(np.float64).reshape(-1)
+                    for g in range(Co):
+                        wv = w[g, f, kr, kc]
+                        if wv != 0.0:
+                            pts[out_index[(g, v)]] = wv * mask
+                if pts:
+                    items.append((amount, pts))
+        plan.append(items)
+    return out, plan
+
+
 def conv2d(be, cts, lay, w, pad=1, stride=1):
-    """Homomorphic conv2d (cross-correlation, zero padding) of an image-sharded
-    input; stride 2 is the stride-1 convolution followed by the downsampling
-    step of the pooling (Section 4.1, strided convolution paragraph)."""
-    out_lay, plan = conv_plan(lay, w, pad)
+    """Homomorphic conv2d (cross-correlation, zero padding) of an image- or
+    channel-sharded input; stride 2 is the stride-1 convolution followed by the
+    downsampling step of the pooling (Section 4.1, strided convolution
+    paragraph)."""
+    if lay.kind == "channel":
+        out_lay, plan = conv_plan_channel(lay, w, pad)
+    else:
+        out_lay, plan = conv_plan(lay, w, pad)
     acc = [[] for _ in out_lay.shards]
     for u, items in enumerate(plan):
         if not items:
@@ -434,7 +492,113 @@ def duplicate(be, ct, lay, d):
     return out, Layout(lay.N, lay.C, lay.H, lay.W, lay.mp, "image", [lam])
 
 
+def downsample_channel(be, cts, lay, select=False, fused=None):
+    """Channel shards are downsampled individually (Section 4.2, "With Channel
+    Shards"): 2x2 sums stay inside a shard (R is even), column 2i of the even
+    valid rows goes to column i, the left half of local row 2j to j*mp/2."""
+    N, mp = lay.N, lay.mp
+    R = N // mp
+    if select:
+        Wo, val = (lay.W + 1) // 2, 1.0
+    else:
+        if lay.H % 2 or lay.W % 2:
+            raise ValueError("average pooling needs even H and W")
+        Wo, val = lay.W // 2, 0.25
+    outs = []
+    for ct, (f, v) in zip(cts, lay.shards):
+        lvl = be.level(ct)
+        use_fused = (lvl < 2) if fused is None else fused
+        if lvl < 1:
+            raise ValueError("pooling needs a level")
+        rows = [r for r in range(0, R, 2) if v * R + r < lay.H]   # even local rows of the channel
+        js = [r // 2 for r in rows]
+        if not js:
+            # a shard below the channel's last row: its pooled content is zero
+            z = be.rescale(be.mul_plain(ct, np.zeros(N), be.q(lvl) / 4.0 if use_fused else be.q(lvl)))
+            if not use_fused:
+                z = be.rescale(be.mul_plain(z, np.zeros(N), be.q(be.level(z))))
+            outs.append(z)
+            continue
+        if not select:
+            D = _sum(be, [ct] + be.rotate_hoisted(ct, [1, mp, mp + 1]))
+        else:
+            D = ct
+        rots = be.rotate_hoisted(D, list(range(Wo)))
+
+        def hmask(i):
+            blk = np.zeros((R, mp))
+            blk[rows, i] = val
+            return blk.reshape(-1)
+
+        def vmask(j):
+            blk = np.zeros(N)
+            blk[j * mp // 2: j * mp // 2 + Wo] = 1.0
+            return blk
+
+        def fmask(i, j):
+            blk = np.zeros((R, mp))
+            blk[2 * j, i] = val
+            return blk.reshape(-1)
+
+        if use_fused:
+            ps = be.q(lvl) / 4.0
+            T = [_sum(be, [be.mul_plain(rots[i], fmask(i, j), ps) for i in range(Wo)]) for j in js]
+            moved = [T[0] if js[0] == 0 else be.rotate(T[0], 3 * js[0] * mp // 2)] + \
+                    [be.rotate(T[t], 3 * j * mp // 2) for t, j in enumerate(js) if t > 0]
+            outs.append(be.rescale(_sum(be, moved)))
+        else:
+            M1 = be.rescale(_sum(be, [be.mul_plain(rots[i], hmask(i), be.q(lvl)) for i in range(Wo)]))
+            lvl1 = be.level(M1)
+            if lvl1 < 1:
+                raise ValueError("separable pooling needs two levels")
+            rots2 = be.rotate_hoisted(M1, [3 * j * mp // 2 for j in js])
+            outs.append(be.rescale(_sum(be, [be.mul_plain(rots2[t], vmask(j), be.q(lvl1))
+                                             for t, j in enumerate(js)])))
+    return outs
+
+
+def merge_channel(be, outs, lay, H2, W2):
+    """Consolidate every four consecutive downsampled channel shards (shifts by
+    multiples of N/4); the result is channel-sharded again when a pooled
+    channel still exceeds N slots, image-sharded otherwise.  One channel in two
+    shards is duplicated by two.  No permutation arises."""
+    N, mp = lay.N, lay.mp
+    q = N // 4
+    t = len(outs)
+    res, groups = [], []
+    for s0 in range(0, t, 4):
+        g = min(4, t - s0)
+        terms = [outs[s0]] + [be.rotate(outs[s0 + e], -e * q) for e in range(1, g)]
+        res.append(_sum(be, terms))
+        groups.append(lay.shards[s0:s0 + g])
+    mp2 = mp // 2
+    B2 = mp2 * mp2
+    if B2 > N:
+        shards = [(grp[0][0], grp[0][1] // 4) for grp in groups]
+        return res, Layout(N, lay.C, H2, W2, mp2, "channel", shards)
+    nb = N // B2                       # pooled channels per ciphertext
+    per_ch = B2 // q                   # quarters per pooled channel
+    maps = []
+    for grp in groups:
+        lam = [-1] * nb
+        for e, (f, part) in enumerate(grp):
+            lam[e // per_ch] = f
+        maps.append(lam)
+    out = Layout(N, lay.C, H2, W2, mp2, "image", maps)
+    if t == 2:   # one channel in two shards: duplicate x2
+        res = [_sum(be, [res[0], be.rotate(res[0], -N // 2)])]
+        out = Layout(N, lay.C, H2, W2, mp2, "image", [[maps[0][0]] * nb])
+    return res, out
+
+
 def downsample_and_merge(be, cts, lay, select=False, fused=None):
+    if lay.kind == "channel":
+        outs = downsample_channel(be, cts, lay, select=select, fused=fused)
+        if select:
+            H2, W2 = (lay.H + 1) // 2, (lay.W + 1) // 2
+        else:
+            H2, W2 = lay.H // 2, lay.W // 2
+        return merge_channel(be, outs, lay, H2, W2)
     outs, nl = downsample(be, cts, lay, select=select, fused=fused)
     t = len(outs)
     if t == 1:
@@ -448,9 +612,8 @@ def downsample_and_merge(be, cts, lay, select=False, fused=None):
 
 
 def avgpool2x2(be, cts, lay, fused=None):
-    """2x2 average pooling: downsample, consolidate, duplicate (Section 4.2)."""
-    if lay.kind != "image":
-        raise ValueError("image-shard layout expected")
+    """2x2 average pooling: downsample, consolidate, duplicate (Section 4.2),
+    for image shards and channel shards."""
     return downsample_and_merge(be, cts, lay, select=False, fused=fused)
 
 

@@ -48,9 +48,16 @@ struct DevPool {
 
 struct Layout {
     uint32_t N = 0, C = 0, H = 0, W = 0, mp = 0;
-    std::vector<std::vector<int32_t>> maps;  // per shard: block -> logical channel, -1 empty
+    // image shards: per shard, block -> logical channel (-1 empty)
+    std::vector<std::vector<int32_t>> maps;
+    // channel shards (mp*mp > N): per shard, (channel, part); part v holds rows v*R .. v*R+R-1, R = N/mp
+    bool channel = false;
+    std::vector<std::pair<int32_t, int32_t>> cs;
     uint32_t B() const { return mp * mp; }
     uint32_t nb() const { return N / B(); }
+    uint32_t R() const { return N / mp; }
+    uint32_t spc() const { return B() / N; }
+    size_t shards() const { return channel ? cs.size() : maps.size(); }
 };
 
 struct hec_ctx {

@@ -30,7 +30,13 @@ Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t m
     L.N = N; L.C = C; L.H = H; L.W = W;
     L.mp = mp ? mp : next_pow2(std::max(H, W));
     const uint32_t B = L.B();
-    if (B > N) return L;  // channel shards: not planned here (maps empty)
+    if (B > N) {
+        // channel shards: each channel split into consecutive-row shards
+        L.channel = true;
+        for (uint32_t f = 0; f < C; f++)
+            for (uint32_t v = 0; v < B / N; v++) L.cs.push_back({(int32_t)f, (int32_t)v});
+        return L;
+    }
     const uint32_t nb = N / B, Cp = next_pow2(C);
     if ((uint64_t)Cp * B <= N) {
         uint32_t d = N / (Cp * B);
@@ -52,6 +58,16 @@ static void pack_shard(const Layout &L, const double *x, uint32_t u, std::vector
 {
     const uint32_t B = L.B();
     v.assign(L.N, 0.0);
+    if (L.channel) {
+        const int32_t f = L.cs[u].first, part = L.cs[u].second;
+        const uint32_t R = L.R();
+        for (uint32_t r = 0; r < R; r++) {
+            uint32_t i = part * R + r;
+            if (i >= L.H) break;
+            for (uint32_t j = 0; j < L.W; j++) v[(size_t)r * L.mp + j] = x[((size_t)f * L.H + i) * L.W + j];
+        }
+        return;
+    }
     for (uint32_t b = 0; b < L.nb(); b++) {
         int32_t f = L.maps[u][b];
         if (f < 0) continue;
@@ -84,10 +100,10 @@ extern "C" hec_status he_image_encrypt(hec_ctx *c, const double *x, uint32_t C, 
     if (level > c->L) HEC_FAIL(HEC_ELEVEL, "level above L");
     HEC_TRY_HIP(hipSetDevice(c->dev));
     Layout L = natural_layout(c->N, C, H, W);
-    if (L.maps.empty()) HEC_FAIL(HEC_ELAYOUT, "channel of %ux%u does not fit one ciphertext (channel shards)", H, W);
-    std::vector<std::vector<double>> v(L.maps.size());
+    if (!L.shards()) HEC_FAIL(HEC_ELAYOUT, "empty layout");
+    std::vector<std::vector<double>> v(L.shards());
     std::vector<const double *> zp;
-    for (uint32_t u = 0; u < L.maps.size(); u++) {
+    for (uint32_t u = 0; u < L.shards(); u++) {
         pack_shard(L, x, u, v[u]);
         zp.push_back(v[u].data());
     }
@@ -116,6 +132,18 @@ extern "C" hec_status he_image_decrypt(hec_ctx *c, const hec_image *img, double 
     const Layout &L = img->lay;
     std::vector<char> seen(L.C, 0);
     std::vector<double> z(c->N);
+    if (L.channel) {
+        const uint32_t R = L.R();
+        for (uint32_t u = 0; u < L.cs.size(); u++) {
+            const int32_t f = L.cs[u].first, part = L.cs[u].second;
+            if ((uint32_t)part * R >= L.H) continue;
+            HEC_CHECK(decrypt_slots(c, img->shards[u], z.data(), c->N));
+            for (uint32_t r = 0; r < R && part * R + r < L.H; r++)
+                for (uint32_t j = 0; j < L.W; j++)
+                    x[((size_t)f * L.H + part * R + r) * L.W + j] = z[(size_t)r * L.mp + j];
+            seen[f] = 1;
+        }
+    }
     for (uint32_t u = 0; u < L.maps.size(); u++) {
         bool need = false;
         for (int32_t f : L.maps[u]) need |= (f >= 0 && !seen[f]);
@@ -150,9 +178,20 @@ extern "C" hec_status he_image_info(const hec_image *img, uint32_t *C, uint32_t 
 extern "C" hec_status he_image_block_map(const hec_image *img, uint32_t u, int32_t *lam, size_t cap)
 {
     if (!img || !lam) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (img->lay.channel) HEC_FAIL(HEC_ELAYOUT, "channel-sharded image: use he_image_channel_shard");
     if (u >= img->lay.maps.size()) HEC_FAIL(HEC_EINVAL, "no shard %u", u);
     if (cap < img->lay.nb()) HEC_FAIL(HEC_EINVAL, "capacity too small");
     memcpy(lam, img->lay.maps[u].data(), img->lay.nb() * 4);
+    return HEC_OK;
+}
+
+extern "C" hec_status he_image_channel_shard(const hec_image *img, uint32_t u, int32_t *channel, int32_t *part)
+{
+    if (!img || !channel || !part) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (!img->lay.channel) HEC_FAIL(HEC_ELAYOUT, "image-sharded image: use he_image_block_map");
+    if (u >= img->lay.cs.size()) HEC_FAIL(HEC_EINVAL, "no shard %u", u);
+    *channel = img->lay.cs[u].first;
+    *part = img->lay.cs[u].second;
     return HEC_OK;
 }
 
@@ -276,6 +315,65 @@ static hec_status conv_items(const Layout &L, const double *w, uint32_t Co, uint
     return HEC_OK;
 }
 
+// Channel shards (Section 4.1, "With Channel Shards"): shard (f, v) holds rows
+// v*R .. v*R+R-1 of channel f.  Each input shard is rotated cyclically by
+// k*mp + l per tap; output shard (g, v) takes the rows whose source row lies
+// in its own shard from its own rotation (mask m) and the rows whose source
+// lies in shard v + sign(k) from that shard's rotation (the complement);
+// rows outside the channel read the zero padding.
+static hec_status conv_items_channel(const Layout &L, const double *w, uint32_t Co, uint32_t kh, uint32_t kw,
+                                     uint32_t pad, Layout &out, std::vector<std::vector<ConvItem>> &plan)
+{
+    const int H = (int)L.H, W = (int)L.W, mp = (int)L.mp, R = (int)L.R(), spc = (int)L.spc(), N = (int)L.N;
+    const int Ho = H + 2 * (int)pad - (int)kh + 1, Wo = W + 2 * (int)pad - (int)kw + 1;
+    if (Ho < 1 || Wo < 1 || Ho > mp || Wo > mp) HEC_FAIL(HEC_ELAYOUT, "bad convolution geometry");
+    if ((int)kh / 2 >= R) HEC_FAIL(HEC_ELAYOUT, "kernel taller than a channel shard");
+    out = Layout();
+    out.N = L.N; out.C = Co; out.H = Ho; out.W = Wo; out.mp = L.mp; out.channel = true;
+    for (uint32_t g = 0; g < Co; g++)
+        for (int v = 0; v < spc; v++) out.cs.push_back({(int32_t)g, v});
+    const uint32_t Ci = L.C;
+    plan.assign(L.cs.size(), {});
+    std::vector<double> mask(N);
+    for (size_t u = 0; u < L.cs.size(); u++) {
+        const int f = L.cs[u].first, vin = L.cs[u].second;
+        for (uint32_t kr = 0; kr < kh; kr++)
+            for (uint32_t kc = 0; kc < kw; kc++) {
+                const int dk = (int)kr - (int)pad, dl = (int)kc - (int)pad;
+                int64_t a = ((int64_t)dk * mp + dl) % N;
+                if (a < 0) a += N;
+                ConvItem it;
+                it.amount = (int32_t)a;
+                int cands[2] = {vin, dk > 0 ? vin - 1 : vin + 1};
+                const int ncand = dk != 0 ? 2 : 1;
+                for (int ci = 0; ci < ncand; ci++) {
+                    const int v = cands[ci];
+                    if (v < 0 || v >= spc) continue;
+                    bool any = false;
+                    for (int il = 0; il < R; il++)
+                        for (int j = 0; j < mp; j++) {
+                            const int gi = v * R + il, src = gi + dk;
+                            const bool same = il + dk >= 0 && il + dk < R;
+                            bool ok = gi < Ho && j < Wo && src >= 0 && src < H && j + dl >= 0 && j + dl < W &&
+                                      (v == vin ? same : !same);
+                            mask[(size_t)il * mp + j] = ok ? 1.0 : 0.0;
+                            any |= ok;
+                        }
+                    if (!any) continue;
+                    for (uint32_t g = 0; g < Co; g++) {
+                        const double wv = w[(((size_t)g * Ci + f) * kh + kr) * kw + kc];
+                        if (wv == 0.0) continue;
+                        std::vector<double> vec(N);
+                        for (int e = 0; e < N; e++) vec[e] = wv * mask[e];
+                        it.pts.emplace_back(g * spc + v, std::move(vec));
+                    }
+                }
+                if (!it.pts.empty()) plan[u].push_back(std::move(it));
+            }
+    }
+    return HEC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // pooling masks (Section 4.2)
 // ---------------------------------------------------------------------------
@@ -298,8 +396,24 @@ static std::vector<double> per_block(const Layout &L, const std::vector<double> 
 
 // the three mask kinds: 'h' (rot_i of column 2i of even rows), 'v' (rot_{3j mp/2} of the
 // left half of row 2j), 'f' (fused: element (2j, 2i) after rot_i)
-static std::vector<double> pool_mask(const Layout &L, char kind, uint32_t i, uint32_t j, uint32_t Wo, double val)
+static std::vector<double> pool_mask(const Layout &L, char kind, uint32_t i, uint32_t j, uint32_t Wo, double val,
+                                     int part)
 {
+    if (L.channel) {
+        // one shard of a channel: rows v*R + r of the channel, r < R
+        const uint32_t R = L.R();
+        std::vector<double> v(L.N, 0.0);
+        if (kind == 'h') {
+            for (uint32_t r = 0; r < R; r += 2)
+                if (part * R + r < L.H) v[(size_t)r * L.mp + i] = val;
+        } else if (kind == 'v') {
+            uint32_t o = j * L.mp / 2;
+            for (uint32_t c = 0; c < Wo; c++) v[o + c] = 1.0;
+        } else if (kind == 'f') {
+            v[(size_t)(2 * j) * L.mp + i] = val;
+        }  // 'z': all zero
+        return v;
+    }
     std::vector<double> blk(L.B(), 0.0);
     if (kind == 'h') {
         for (uint32_t r = 0; r < L.H; r += 2) blk[(size_t)r * L.mp + i] = val;
@@ -312,21 +426,26 @@ static std::vector<double> pool_mask(const Layout &L, char kind, uint32_t i, uin
     return per_block(L, blk);
 }
 
-static std::string layout_key(const Layout &L)
+static std::string layout_key(const Layout &L, int part)
 {
     std::ostringstream s;
     s << L.N << ":" << L.C << ":" << L.H << ":" << L.W << ":" << L.mp;
+    if (L.channel) {
+        s << ":ch" << part;
+        return s.str();
+    }
     auto vb = valid_blocks(L);
     s << ":";
     for (char c : vb) s << (int)c;
     return s.str();
 }
 
-// cached mask plaintexts (they only depend on the layout, index, level and scale)
+// cached mask plaintexts (they only depend on the layout, shard part, index, level and scale)
 static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::vector<std::pair<uint32_t, uint32_t>> &ij,
-                            uint32_t Wo, double val, uint32_t level, double scale, std::vector<hec_pt *> &out)
+                            uint32_t Wo, double val, uint32_t level, double scale, std::vector<hec_pt *> &out,
+                            int part = -1)
 {
-    std::string base = layout_key(L);
+    std::string base = layout_key(L, part);
     std::vector<std::string> keys;
     std::vector<size_t> miss;
     out.assign(ij.size(), nullptr);
@@ -342,7 +461,7 @@ static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::v
     if (miss.empty()) return HEC_OK;
     std::vector<std::vector<double>> vecs;
     std::vector<const double *> zp;
-    for (size_t t : miss) vecs.push_back(pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val));
+    for (size_t t : miss) vecs.push_back(pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val, part));
     for (auto &v : vecs) zp.push_back(v.data());
     std::vector<hec_pt *> pts;
     HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts));
@@ -510,10 +629,169 @@ static hec_status duplicate(hec_ctx *c, hec_ct *ct, Layout &L, uint32_t d, hec_c
     return HEC_OK;
 }
 
+// Channel shards are downsampled one by one (Section 4.2, "With Channel
+// Shards"): 2x2 sums stay inside a shard (R is even), column 2i of the even
+// rows that belong to the channel goes to column i, the left half of local row
+// 2j to j*mp/2.  A shard below the channel's last row pools to zero.
+static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                                     std::vector<hec_ct *> &out)
+{
+    const uint32_t mp = L.mp, R = L.R();
+    uint32_t Wo;
+    double val;
+    if (select) {
+        Wo = (L.W + 1) / 2; val = 1.0;
+    } else {
+        if (L.H % 2 || L.W % 2) HEC_FAIL(HEC_ELAYOUT, "average pooling needs even H and W");
+        Wo = L.W / 2; val = 0.25;
+    }
+    out.clear();
+    for (size_t u = 0; u < in.size(); u++) {
+        hec_ct *ct = in[u];
+        const int part = L.cs[u].second;
+        const uint32_t lvl = ct->level;
+        if (lvl < 1) HEC_FAIL(HEC_ELEVEL, "pooling needs a level");
+        const bool fused = lvl < 2;
+        std::vector<uint32_t> js;
+        for (uint32_t r = 0; r < R; r += 2)
+            if (part * R + r < L.H) js.push_back(r / 2);
+        std::vector<hec_pt *> pts;
+        if (js.empty()) {
+            HEC_CHECK(get_masks(c, L, 'z', {{0, 0}}, Wo, val, lvl, fused ? (double)c->mod[lvl] / 4.0 : (double)c->mod[lvl],
+                                pts, part));
+            hec_ct *a = ct_new(c, lvl, 1.0);
+            if (!a) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+            HEC_CHECK(ct_mac_pt(c, a, ct, pts[0], true));
+            HEC_CHECK(ct_rescale(c, a));
+            if (!fused) {
+                HEC_CHECK(get_masks(c, L, 'z', {{0, 0}}, Wo, val, a->level, (double)c->mod[a->level], pts, part));
+                hec_ct *b = ct_new(c, a->level, 1.0);
+                if (!b) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+                HEC_CHECK(ct_mac_pt(c, b, a, pts[0], true));
+                ct_free(a);
+                HEC_CHECK(ct_rescale(c, b));
+                a = b;
+            }
+            out.push_back(a);
+            continue;
+        }
+        hec_ct *D = ct_clone(ct);
+        if (!select) {
+            std::vector<hec_ct *> r;
+            HEC_CHECK(rotate_list(c, ct, {1, (int32_t)mp, (int32_t)mp + 1}, r));
+            for (auto *x : r) HEC_CHECK(sum_into(c, D, x));
+        }
+        std::vector<int32_t> hs;
+        for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
+        std::vector<hec_ct *> rots;
+        hec_status s = rotate_list(c, D, hs, rots);
+        ct_free(D);
+        HEC_CHECK(s);
+        if (fused) {
+            hec_ct *acc = nullptr;
+            for (uint32_t j : js) {
+                std::vector<std::pair<uint32_t, uint32_t>> ij;
+                for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, j});
+                HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, (double)c->mod[lvl] / 4.0, pts, part));
+                hec_ct *T = nullptr;
+                HEC_CHECK(masked_sum(c, rots, pts, &T));
+                if (j > 0) {
+                    hec_ct *m = nullptr;
+                    s = ckks_rotate(c, T, (int32_t)(3 * j * mp / 2), &m);
+                    ct_free(T);
+                    HEC_CHECK(s);
+                    T = m;
+                }
+                HEC_CHECK(sum_into(c, acc, T));
+            }
+            free_all(rots);
+            HEC_CHECK(ct_rescale(c, acc));
+            out.push_back(acc);
+        } else {
+            std::vector<std::pair<uint32_t, uint32_t>> ij;
+            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
+            HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], pts, part));
+            hec_ct *M1 = nullptr;
+            HEC_CHECK(masked_sum(c, rots, pts, &M1));
+            free_all(rots);
+            HEC_CHECK(ct_rescale(c, M1));
+            const uint32_t l1 = M1->level;
+            if (l1 < 1) { ct_free(M1); HEC_FAIL(HEC_ELEVEL, "separable pooling needs two levels"); }
+            std::vector<int32_t> vs;
+            for (uint32_t j : js) vs.push_back((int32_t)(3 * j * mp / 2));
+            std::vector<hec_ct *> r2;
+            s = rotate_list(c, M1, vs, r2);
+            ct_free(M1);
+            HEC_CHECK(s);
+            std::vector<std::pair<uint32_t, uint32_t>> jj;
+            for (uint32_t j : js) jj.push_back({0, j});
+            HEC_CHECK(get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], pts, part));
+            hec_ct *M2 = nullptr;
+            HEC_CHECK(masked_sum(c, r2, pts, &M2));
+            free_all(r2);
+            HEC_CHECK(ct_rescale(c, M2));
+            out.push_back(M2);
+        }
+    }
+    return HEC_OK;
+}
+
+// Consolidate every four consecutive downsampled channel shards (shifts by
+// multiples of N/4).  The result is channel-sharded again while a pooled
+// channel still exceeds N slots, image-sharded otherwise; one channel in two
+// shards is duplicated by two.  No permutation arises.
+static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Layout &L, uint32_t H2, uint32_t W2,
+                                std::vector<hec_ct *> &out, Layout &ol)
+{
+    const uint32_t N = L.N, q4 = N / 4;
+    const size_t t = ds.size();
+    out.clear();
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> groups;
+    for (size_t s0 = 0; s0 < t; s0 += 4) {
+        const size_t g = std::min((size_t)4, t - s0);
+        hec_ct *acc = ct_clone(ds[s0]);
+        for (size_t e = 1; e < g; e++) {
+            hec_ct *r = nullptr;
+            HEC_CHECK(ckks_rotate(c, ds[s0 + e], -(int32_t)(e * q4), &r));
+            HEC_CHECK(sum_into(c, acc, r));
+        }
+        groups.push_back(std::vector<std::pair<int32_t, int32_t>>(L.cs.begin() + s0, L.cs.begin() + s0 + g));
+        out.push_back(acc);
+    }
+    ol = Layout();
+    ol.N = N; ol.C = L.C; ol.H = H2; ol.W = W2; ol.mp = L.mp / 2;
+    const uint32_t B2 = ol.B();
+    if (B2 > N) {
+        ol.channel = true;
+        for (auto &grp : groups) ol.cs.push_back({grp[0].first, grp[0].second / 4});
+        return HEC_OK;
+    }
+    const uint32_t nb = N / B2, per_ch = B2 / q4;
+    for (auto &grp : groups) {
+        std::vector<int32_t> lam(nb, -1);
+        for (size_t e = 0; e < grp.size(); e++) lam[e / per_ch] = grp[e].first;
+        ol.maps.push_back(lam);
+    }
+    if (t == 2) {  // one channel in two shards: duplicate x2
+        hec_ct *r = nullptr;
+        HEC_CHECK(ckks_rotate(c, out[0], -(int32_t)(N / 2), &r));
+        HEC_CHECK(sum_into(c, out[0], r));
+        ol.maps[0] = std::vector<int32_t>(nb, ol.maps[0][0]);
+    }
+    return HEC_OK;
+}
+
 static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
                                        std::vector<hec_ct *> &out, Layout &ol)
 {
     std::vector<hec_ct *> ds;
+    if (L.channel) {
+        HEC_CHECK(downsample_channel(c, in, L, select, ds));
+        const uint32_t H2 = select ? (L.H + 1) / 2 : L.H / 2, W2 = select ? (L.W + 1) / 2 : L.W / 2;
+        hec_status s = merge_channel(c, ds, L, H2, W2, out, ol);
+        free_all(ds);
+        return s;
+    }
     Layout nl;
     HEC_CHECK(downsample(c, in, L, select, ds, nl));
     const size_t t = ds.size();
@@ -564,8 +842,17 @@ static void pool_steps(const Layout &L, bool select, uint32_t level, std::set<in
     for (uint32_t i = 1; i < Wo; i++) steps.insert((int32_t)i);
     for (uint32_t j = 1; j < Ho; j++) steps.insert((int32_t)(3 * j * mp / 2));
     (void)level;
-    const uint32_t N = L.N, Bn = L.B() / 4, t = (uint32_t)L.maps.size();
+    const uint32_t N = L.N;
     auto neg = [&](int64_t a) { int64_t r = (-a) % (int64_t)N; return (int32_t)(r < 0 ? r + N : r); };
+    if (L.channel) {
+        // vertical shifts of every local pooled row; consolidation by N/4; duplication by N/2
+        for (uint32_t j = 1; j < L.R() / 2; j++) steps.insert((int32_t)(3 * j * mp / 2));
+        const size_t t = L.cs.size();
+        for (uint32_t e = 1; e < (t >= 4 ? 4u : (uint32_t)t); e++) steps.insert(neg((int64_t)e * (N / 4)));
+        if (t == 2) steps.insert(neg(N / 2));
+        return;
+    }
+    const uint32_t Bn = L.B() / 4, t = (uint32_t)L.maps.size();
     if (t == 1) for (uint32_t m = 1; m < 4; m++) steps.insert(neg((int64_t)m * Bn));
     else {
         uint32_t g = t >= 4 ? 4 : t;  // the first group is the largest
@@ -601,7 +888,8 @@ extern "C" void he_conv2d_plan_free(hec_conv_plan *p)
 
 static bool same_layout(const Layout &a, const Layout &b)
 {
-    return a.N == b.N && a.C == b.C && a.H == b.H && a.W == b.W && a.mp == b.mp && a.maps == b.maps;
+    return a.N == b.N && a.C == b.C && a.H == b.H && a.W == b.W && a.mp == b.mp && a.maps == b.maps &&
+           a.channel == b.channel && a.cs == b.cs;
 }
 
 extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, const double *w, uint32_t Co,
@@ -625,7 +913,8 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
     p->level = lvl;
     p->stride = stride;
     std::vector<std::vector<ConvItem>> items;
-    HEC_CHECK(conv_items(like->lay, w, Co, kh, kw, pad, p->out, items));
+    if (like->lay.channel) HEC_CHECK(conv_items_channel(like->lay, w, Co, kh, kw, pad, p->out, items));
+    else HEC_CHECK(conv_items(like->lay, w, Co, kh, kw, pad, p->out, items));
     p->items.resize(items.size());
     std::vector<const double *> zp;
     for (auto &v : items)
@@ -681,7 +970,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
     for (int32_t s : p->steps)
         if (!have_rotkey(c, s)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", s);
     HEC_TRY_HIP(hipSetDevice(c->dev));
-    const size_t nout = p->out.maps.size();
+    const size_t nout = p->out.shards();
     std::vector<hec_ct *> acc(nout, nullptr);
     std::vector<char> first(nout, 1);
     for (size_t v = 0; v < nout; v++) {

@@ -22,7 +22,7 @@ EXPORTS = [
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "hec_ct_free", "hec_pt_free", "hec_image_free",
-    "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches",
+    "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
             "hec_prof_start": (c, [vp, ctypes.c_char_p]),
             "hec_prof_stop": (c, [vp, u64p, u64p, dblp]),
             "hec_prof_launches": (u64, [ctypes.c_char_p]),
+            "he_image_channel_shard": (c, [vp, u32, i32p, i32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -200,6 +201,16 @@ class Image:
         v = [ctypes.c_uint32() for _ in range(5)]
         check(lib().he_image_info(self.h, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)  # C, H, W, mp, n_shards
+
+    def channel_shard(self, u):
+        """(channel, part) of shard u of a channel-sharded image."""
+        f, p = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().he_image_channel_shard(self.h, u, ctypes.byref(f), ctypes.byref(p)))
+        return f.value, p.value
+
+    def is_channel_sharded(self):
+        C, H, W, mp, t = self.info()
+        return mp * mp > self.ctx.N
 
     def block_map(self, u):
         C, H, W, mp, t = self.info()

@@ -160,7 +160,10 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed):
         Cn, Hn, Wn, mp, t = img.info()
         assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
         for u in range(t):
-            assert list(img.block_map(u)) == list(lay.shards[u])
+            if lay.kind == "channel":
+                assert img.channel_shard(u) == tuple(lay.shards[u])
+            else:
+                assert list(img.block_map(u)) == list(lay.shards[u])
             assert img.shard_info(u) == (cts[u].level, cts[u].scale)
             assert (img.shard_export(u) == cts[u].data).all(), (op[0], u)
         log("  op %s ok: %d shards, level %d" % (op[0], t, cts[0].level))
@@ -180,6 +183,11 @@ def prm_log_scale(ctx):
     ((16, 16, 16), [("conv", (8, 3), 1), ("pool",)]),               # 8 shards -> 4 -> 1 shard
     ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv: 4 shards -> 1
     ((3, 12, 12), [("conv", (5, 3), 1)]),                           # padding of side and channels
+    # channel shards (N = 512 slots): a 32x32 channel spans 2 shards, 64x64 spans 8
+    ((2, 32, 32), [("conv", (3, 3), 1), ("pool",)]),                # 6 shards -> groups of 4 + short group
+    ((1, 32, 32), [("conv", (1, 3), 1), ("pool",)]),                # one channel in two shards: dup x2
+    ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem, then image shards
+    ((1, 64, 64), [("pool",), ("conv", (2, 3), 1)]),                # 8 shards/channel -> 2 shards/channel
 ])
 def test_layers_bit_exact(small, shape, ops):
     ctx, prm, o = small

@@ -61,6 +61,24 @@ def test_pool_separable_and_fused(small):
         assert np.abs(dec_image(o, outs, ol) - hl.ref_avgpool2x2(x)).max() < 1e-5
 
 
+def test_channel_shards(small):
+    """A 32x32 channel in 2^7-slot shards (8 shards per channel): conv (rows
+    taken from neighbouring shards) then pooling (consolidation)."""
+    p, o = small
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (1, 32, 32))
+    w = rng.normal(0, 0.2, (2, 1, 3, 3))
+    lay = hl.natural_layout(p.N, 1, 32, 32)
+    assert lay.kind == "channel" and len(lay.shards) == 8
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 14)
+    be = hl.CkksBackend(o)
+    c, cl = hl.conv2d(be, cts, lay, w, pad=1)
+    ref = hl.ref_conv2d(x, w, 1)
+    assert np.abs(dec_image(o, c, cl) - ref).max() < 1e-5
+    pl_, pll = hl.avgpool2x2(be, c, cl)
+    assert np.abs(dec_image(o, pl_, pll) - hl.ref_avgpool2x2(ref)).max() < 1e-5
+
+
 @pytest.mark.slow
 def test_ring_2e13_conv_pool():
     """2N = 2^13, 3 x 40-bit primes + one 60-bit special prime, scale 2^40: a

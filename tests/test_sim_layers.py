@@ -149,3 +149,61 @@ def test_rotation_counts_match_paper_shapes():
     # 112x112x64 padded to 128, 2 channels per shard, 32 shards: 2 x 9 offsets per shard
     lay = hl.natural_layout(1 << 15, 64, 112, 112)
     assert len(lay.shards) == 32 and lay.mp == 128
+
+
+# ---- channel shards (Section 4.1 "With Channel Shards", Section 4.2 channel-shard pooling) ----
+
+CH_CASES = [
+    # N, C, H, Co, k, pad, stride
+    (128, 2, 16, 3, 3, 1, 1),    # mp 16: 2 shards per channel
+    (64, 2, 16, 2, 3, 1, 1),     # 4 shards per channel
+    (32, 1, 16, 2, 3, 1, 1),     # 8 shards per channel
+    (64, 3, 14, 2, 3, 1, 1),     # side 14 padded to 16, last rows empty
+    (64, 2, 16, 2, 5, 2, 1),     # 5x5 kernel: shifts of two rows across shards
+    (128, 2, 16, 2, 3, 0, 1),    # no padding
+    (128, 3, 16, 4, 3, 1, 2),    # strided: 2 shards/channel -> image shards
+    (64, 2, 16, 2, 3, 1, 2),     # strided: 4 shards/channel -> one ciphertext per channel
+]
+
+
+@pytest.mark.parametrize("case", CH_CASES)
+def test_channel_shard_conv(case):
+    N, C, H, Co, k, pad, stride = case
+    rng = np.random.default_rng(sum(case))
+    x = rng.uniform(-1, 1, (C, H, H))
+    w = rng.normal(0, 0.3, (Co, C, k, k))
+    lay = hl.natural_layout(N, C, H, H)
+    assert lay.kind == "channel"
+    got, ol, outs = run_conv(N, x, w, pad, stride)
+    ref = hl.ref_conv2d(x, w, pad, stride)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("N,C,H", [(128, 1, 16), (128, 2, 16), (128, 3, 16), (64, 2, 16), (32, 2, 16),
+                                   (64, 1, 12), (128, 2, 14)])
+@pytest.mark.parametrize("fused", [False, True])
+def test_channel_shard_pool(N, C, H, fused):
+    x = np.random.default_rng(N + C + H).uniform(-1, 1, (C, H, H))
+    got, ol, outs = run_pool(N, x, fused=fused)
+    assert np.abs(got - hl.ref_avgpool2x2(x)).max() < 1e-12
+    if C == 1 and (16 * 16) // N == 2:
+        assert ol.kind == "image" and ol.shards == [[0, 0]]   # one channel in two shards: duplicated
+
+
+def test_channel_shard_stem_then_image_conv():
+    """A channel-sharded stem followed by an image-sharded layer (the paper's
+    256-px ResNet-50 input needs both kinds)."""
+    N = 128
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (3, 14, 14))
+    w1 = rng.normal(0, 0.3, (4, 3, 3, 3))
+    w2 = rng.normal(0, 0.3, (4, 4, 3, 3))
+    lay = hl.natural_layout(N, 3, 14, 14)
+    be = hl.SlotSim(N, QS)
+    cts = [(v, 10, 1.0) for v in hl.pack(x, lay)]
+    a, al = hl.conv2d(be, cts, lay, w1, pad=1, stride=2)
+    assert al.kind == "image"
+    b, bl = hl.conv2d(be, a, al, w2, pad=1)
+    ref = hl.ref_conv2d(hl.ref_conv2d(x, w1, 1, 2), w2, 1)
+    assert np.abs(hl.unpack([o[0] for o in b], bl) - ref).max() < 1e-12
