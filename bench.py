@@ -220,6 +220,22 @@ def main():
 
     conv_b = conv_ms(0, 5)
     conv_p = conv_ms(1, max(1, args.plain_reps))
+    conv_l = conv_ms(2, 5)
+
+    # the whole step with lazy ModDown in both convolutions (same rotations,
+    # one ModDown per output shard)
+    p1.set_mode(2)
+    p2.set_mode(2)
+    step()
+    err_lazy = step(check=True)
+    torch.cuda.synchronize()
+    s = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_lazy = (time.perf_counter() - s) * 1e3 / args.steps
+    p1.set_mode(0)
+    p2.set_mode(0)
 
     # isolated rotations at level 20
     ctx.gen_rotation_keys(list(range(1, 33)))
@@ -257,6 +273,10 @@ def main():
                    "rotations_per_step": rotations_per_step()},
         "conv_layer_ms_batched": conv_b,
         "conv_layer_ms_plain": conv_p,
+        "conv_layer_ms_lazy_moddown": conv_l,
+        "ms_per_step_lazy_moddown": ms_lazy,
+        "rot_per_s_lazy_moddown": rotations_per_step() * 1e3 / ms_lazy,
+        "max_abs_err_lazy_moddown": err_lazy,
         "rot_per_s_hoisted_level20": rot_hoisted,
         "rot_per_s_single_level20": rot_single,
         "max_abs_err_vs_fp64": err,

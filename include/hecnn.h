@@ -180,7 +180,12 @@ hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const doub
 hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec_image *in, hec_image **out);
 /* Execution mode of plan runs: 0 = batched (hoisted ModUp, rotations of a
  * shard batched per launch), 1 = plain (every rotation its own ModUp and
- * launch chain).  Both give identical ciphertexts. */
+ * launch chain); both give identical ciphertexts.  2 = lazy ModDown (an
+ * optimisation the paper does not describe: the key-switch products of all
+ * rotations are multiplied by their weights and summed over Q_l and P, then
+ * one ModDown per output shard); it rounds differently, so its ciphertexts
+ * differ from modes 0/1 while decrypting to the same values within the same
+ * error bound.  Returns HEC_EINVAL for any other mode. */
 hec_status he_conv2d_plan_set_mode(hec_conv_plan *plan, int mode);
 /* Rotation steps a plan (or an avgpool of `like`) needs keys for. */
 hec_status he_conv2d_plan_steps(const hec_conv_plan *plan, int32_t *steps, size_t cap, size_t *count);

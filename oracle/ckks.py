@@ -92,6 +92,9 @@ def _declare(L):
         "orc_add": (None, [P, u32, u32, u64p, u64p, u64p]),
         "orc_rescale": (None, [P, u32, u64p, u64p]),
         "orc_ntt_limbs": (None, [P, u32p, u32, u64p]),
+        "orc_keyswitch_raw": (None, [P, u32, u64p, u32, u32p, ctypes.POINTER(u64p), ctypes.POINTER(u64p)]),
+        "orc_mul_limbs": (None, [P, u32p, u32, u64p, u64p, u64p]),
+        "orc_add_limbs": (None, [P, u32p, u32, u64p, u64p, u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -294,3 +297,58 @@ class Oracle:
 
     def drop_to(self, ct, level):
         return Ct(ct.data[:, : level + 1].copy(), level, ct.scale)
+
+    # ---- key-switch products without ModDown (lazy ModDown) ---------------
+    def qp_index(self, level):
+        return list(range(level + 1)) + [self.p.L + 1 + t for t in range(self.p.k)]
+
+    def limbs_qp(self, m, level):
+        """Signed integer coefficients reduced mod q_0..q_level, p_0..p_{k-1}."""
+        pidx = u32arr(self.qp_index(level))
+        out = np.zeros((len(pidx), self.p.n), dtype=np.uint64)
+        lib().orc_reduce_small(self.p.cref, ptr(m, i64p), ptr(pidx, u32p), len(pidx), ptr(out))
+        return out
+
+    def keyswitch_raw(self, ct, steps):
+        """Per step: the key-switch product (e0, e1) over Q_l and P, coefficient
+        form [2][l+1+k][n], before ModDown; None for a zero rotation."""
+        p = self.p
+        todo = [i for i, r in enumerate(steps) if r % p.N]
+        res = [None] * len(steps)
+        if todo:
+            nqp = ct.level + 1 + p.k
+            outs = [np.zeros((2, nqp, p.n), dtype=np.uint64) for _ in todo]
+            gs = u32arr([p.galois(steps[i]) for i in todo])
+            kp = (u64p * len(todo))(*[ptr(self.swk(int(g))[1]) for g in gs])
+            op = (u64p * len(todo))(*[ptr(o) for o in outs])
+            lib().orc_keyswitch_raw(p.cref, ct.level, ptr(np.ascontiguousarray(ct.data)), len(todo), ptr(gs, u32p),
+                                    kp, op)
+            for i, o in zip(todo, outs):
+                res[i] = o
+        return res
+
+    def mul_limbs(self, pidx, a, b):
+        out = np.zeros_like(a)
+        pi = u32arr(pidx)
+        lib().orc_mul_limbs(self.p.cref, ptr(pi, u32p), len(pi), ptr(np.ascontiguousarray(a)),
+                            ptr(np.ascontiguousarray(b)), ptr(out))
+        return out
+
+    def add_limbs(self, pidx, a, b):
+        out = np.zeros_like(a)
+        pi = u32arr(pidx)
+        lib().orc_add_limbs(self.p.cref, ptr(pi, u32p), len(pi), ptr(np.ascontiguousarray(a)),
+                            ptr(np.ascontiguousarray(b)), ptr(out))
+        return out
+
+    def automorph(self, pidx, x, g):
+        out = np.zeros_like(x)
+        pi = u32arr(pidx)
+        lib().orc_automorph(self.p.cref, ptr(pi, u32p), len(pi), g, ptr(np.ascontiguousarray(x)), ptr(out))
+        return out
+
+    def moddown(self, level, x):
+        """[l+1+k][n] over Q_l and P -> [l+1][n] over Q_l (floor ModDown)."""
+        out = np.zeros((level + 1, self.p.n), dtype=np.uint64)
+        lib().orc_moddown(self.p.cref, level, ptr(np.ascontiguousarray(x)), ptr(out))
+        return out

@@ -767,6 +767,70 @@ void orc_rotate_hoisted(const orc_params *p, uint32_t level, const uint64_t *ct,
     free(e);
 }
 
+/* The key-switch products of hoisted rotations without their ModDown:
+ * for each g, e_out[r] (layout [2][level+1+k][n], coefficient form over
+ * q_0..q_level, p_0..p_{k-1}) = sum_j sigma_g(ModUp_j(c1)) * swk_{g,j}.
+ * ModDown of e_out[r], plus sigma_g(c0), is exactly orc_rotate_hoisted. */
+void orc_keyswitch_raw(const orc_params *p, uint32_t level, const uint64_t *ct, uint32_t nrot, const uint32_t *gs,
+                       const uint64_t *const *swk_ntt, uint64_t *const *e_out)
+{
+    uint32_t n = p->n, nq = level + 1, NLK = p->L + 1 + p->k;
+    uint32_t beta = (nq + p->alpha - 1) / p->alpha;
+    uint32_t pidx[ORC_MAXP];
+    uint32_t nqp = qp_list(p, level, pidx);
+    const uint64_t *c1 = ct + (size_t)nq * n;
+    uint64_t *D = malloc(sizeof(uint64_t) * beta * nqp * n);
+    for (uint32_t j = 0; j < beta; j++) orc_modup(p, level, j, c1, D + (size_t)j * nqp * n);
+    for (uint32_t r = 0; r < nrot; r++) {
+        uint32_t g = gs[r];
+        uint64_t *e = e_out[r];
+#pragma omp parallel for
+        for (uint32_t o = 0; o < nqp; o++) {
+            uint32_t pi = pidx[o];
+            uint64_t q = p->mod[pi];
+            uint64_t *acc0 = calloc(n, sizeof(uint64_t)), *acc1 = calloc(n, sizeof(uint64_t));
+            uint64_t *d = malloc(sizeof(uint64_t) * n);
+            for (uint32_t j = 0; j < beta; j++) {
+                orc_automorph(p, &pi, 1, g, D + ((size_t)j * nqp + o) * n, d);
+                orc_ntt(d, n, q, p->psi[pi]);
+                const uint64_t *kb = swk_ntt[r] + ((size_t)j * 2 * NLK + pi) * n;
+                const uint64_t *ka = swk_ntt[r] + ((size_t)j * 2 * NLK + NLK + pi) * n;
+                for (uint32_t c = 0; c < n; c++) {
+                    acc0[c] = addmod(acc0[c], orc_mulmod(d[c], kb[c], q), q);
+                    acc1[c] = addmod(acc1[c], orc_mulmod(d[c], ka[c], q), q);
+                }
+            }
+            orc_intt(acc0, n, q, p->psi[pi]);
+            orc_intt(acc1, n, q, p->psi[pi]);
+            memcpy(e + (size_t)o * n, acc0, sizeof(uint64_t) * n);
+            memcpy(e + (size_t)(nqp + o) * n, acc1, sizeof(uint64_t) * n);
+            free(acc0); free(acc1); free(d);
+        }
+    }
+    free(D);
+}
+
+/* out = a * b limb by limb (polynomial products), limb l modulo mod[pidx[l]] */
+void orc_mul_limbs(const orc_params *p, const uint32_t *pidx, uint32_t nl, const uint64_t *a, const uint64_t *b,
+                   uint64_t *out)
+{
+    uint32_t n = p->n;
+#pragma omp parallel for
+    for (uint32_t l = 0; l < nl; l++)
+        orc_polymul(a + (size_t)l * n, b + (size_t)l * n, out + (size_t)l * n, n, p->mod[pidx[l]], p->psi[pidx[l]]);
+}
+
+/* out = a + b limb by limb, limb l modulo mod[pidx[l]] */
+void orc_add_limbs(const orc_params *p, const uint32_t *pidx, uint32_t nl, const uint64_t *a, const uint64_t *b,
+                   uint64_t *out)
+{
+    uint32_t n = p->n;
+    for (uint32_t l = 0; l < nl; l++) {
+        uint64_t q = p->mod[pidx[l]];
+        for (uint32_t c = 0; c < n; c++) out[(size_t)l * n + c] = addmod(a[(size_t)l * n + c], b[(size_t)l * n + c], q);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* plaintext products, additions, rescale                               */
 /* ------------------------------------------------------------------ */

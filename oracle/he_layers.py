@@ -343,15 +343,72 @@ def conv_plan_channel(lay, w, pad):
     return out, plan
 
 
-def conv2d(be, cts, lay, w, pad=1, stride=1):
+def _accumulate_lazy(be, cts, nout, plan):
+    """Lazy ModDown: every output shard v is
+        (A0 + ModDown(E0), A1 + ModDown(E1)),
+    E_p = sum over the nonzero rotations of pt * e_p (the key-switch product
+    over Q and P, before ModDown), A0 = sum pt * sigma_g(c0) over those
+    rotations plus pt * c0 over zero rotations, A1 = sum pt * c1 over zero
+    rotations.  Same rotations and plaintexts as the per-rotation form; one
+    ModDown per output shard instead of one per rotation."""
+    o = be.o
+    p = o.p
+    lvl = cts[0].level
+    nq = lvl + 1
+    qi, qpi = list(range(nq)), o.qp_index(lvl)
+    nqp = len(qpi)
+    E = [np.zeros((2, nqp, p.n), dtype=np.uint64) for _ in range(nout)]
+    A = [np.zeros((2, nq, p.n), dtype=np.uint64) for _ in range(nout)]
+    used = [False] * nout
+    scale = None
+    for u, items in enumerate(plan):
+        if not items:
+            continue
+        ct = cts[u]
+        ks = o.keyswitch_raw(ct, [a for a, _ in items])
+        for e, (a, pts) in zip(ks, items):
+            g = p.galois(a)
+            for v, vec in pts.items():
+                m = o.encode_coeffs(vec, be.q(lvl))
+                ptq = o.limbs_of(m, lvl)
+                used[v] = True
+                scale = ct.scale * be.q(lvl)
+                if e is None:
+                    for poly in range(2):
+                        A[v][poly] = o.add_limbs(qi, A[v][poly], o.mul_limbs(qi, ptq, ct.data[poly]))
+                else:
+                    ptqp = o.limbs_qp(m, lvl)
+                    for poly in range(2):
+                        E[v][poly] = o.add_limbs(qpi, E[v][poly], o.mul_limbs(qpi, ptqp, e[poly]))
+                    rc0 = o.automorph(qi, ct.data[0], g)
+                    A[v][0] = o.add_limbs(qi, A[v][0], o.mul_limbs(qi, ptq, rc0))
+    outs = []
+    for v in range(nout):
+        if not used[v]:
+            raise ValueError("output shard without products")
+        data = np.stack([o.add_limbs(qi, A[v][poly], o.moddown(lvl, E[v][poly])) for poly in range(2)])
+        from .ckks import Ct
+        outs.append(be.rescale(Ct(data, lvl, scale)))
+    return outs
+
+
+def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False):
     """Homomorphic conv2d (cross-correlation, zero padding) of an image- or
     channel-sharded input; stride 2 is the stride-1 convolution followed by the
     downsampling step of the pooling (Section 4.1, strided convolution
-    paragraph)."""
+    paragraph).  lazy=True accumulates the plaintext products before ModDown
+    (encrypted backend only; the slot simulator computes the same values)."""
     if lay.kind == "channel":
         out_lay, plan = conv_plan_channel(lay, w, pad)
     else:
         out_lay, plan = conv_plan(lay, w, pad)
+    if lazy and isinstance(be, CkksBackend):
+        outs = _accumulate_lazy(be, cts, len(out_lay.shards), plan)
+        if stride == 1:
+            return outs, out_lay
+        if stride != 2:
+            raise ValueError("stride must be 1 or 2")
+        return downsample_and_merge(be, outs, out_lay, select=True)
     acc = [[] for _ in out_lay.shards]
     for u, items in enumerate(plan):
         if not items:

@@ -59,6 +59,19 @@ struct KsBatch {
     u32 g[HEC_KS_BATCH];
 };
 
+// Key switching fused with plaintext products, accumulated before ModDown.
+// Term t is a rotation by g[t] of one ciphertext (key[t] == null when g[t] == 1)
+// whose result is multiplied by pt[t][v] (null: no product) and added into
+// output v.  Outputs are [2][nqp][n] over Q_l and P; the Q limbs carry
+// P * (product), so that one ModDown of the accumulator gives the sum.
+#define HEC_MAC_OUT 4
+struct KsMacBatch {
+    const u64 *key[HEC_KS_BATCH];              // [dnum][2][L+1+k][n], Montgomery form
+    const u64 *pt[HEC_KS_BATCH][HEC_MAC_OUT];  // [nqp][n], Montgomery form
+    u32 g[HEC_KS_BATCH];
+    u64 *E[HEC_MAC_OUT];                       // [2][nqp][n], NTT form
+};
+
 struct CombineBatch {
     u64 *out[HEC_KS_BATCH];        // [2][nq][n]
     const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
@@ -74,7 +87,7 @@ void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, 
 void hec_ntt_inv(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
                  hipStream_t st);
 
-enum EwOp { EW_ADD = 0, EW_SUB, EW_NEG, EW_MUL_MONT, EW_MAC_MONT, EW_TO_MONT, EW_FROM_MONT, EW_COPY };
+enum EwOp { EW_ADD = 0, EW_SUB, EW_NEG, EW_MUL_MONT, EW_MAC_MONT, EW_TO_MONT, EW_FROM_MONT, EW_COPY, EW_ZERO };
 // out = op(a, b) over nlimbs x n per poly (poly strides given separately for out/a/b; b stride may be 0 to
 // broadcast one polynomial over all polys).
 void hec_ew(const DevTables &T, EwOp op, u64 *out, const u64 *a, const u64 *b, size_t so, size_t sa, size_t sb,
@@ -94,6 +107,12 @@ void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const
 
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st);
+
+// E_v (+)= sum_t pt[t][v] * KS_t, KS_t = (sum_j sigma_g(D_j) key_j + P sigma_g(c0), sum_j sigma_g(D_j) key'_j)
+// or P * (c0, c1) for g == 1; ct = [2][nq][n] (NTT form), D = [beta][nqp][n] ModUp of c1 (NTT form),
+// pm[i] = P * 2^64 mod q_i; bit v of `first` set: output v is written instead of accumulated.
+void hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
+                int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
                          const LevelC *lc, const u32 *pmap, hipStream_t st);

@@ -242,6 +242,11 @@ static hec_status build_tables(hec_ctx *c)
     }
     c->d_pmodq = c->alloc(NLK);
     HEC_CHECK(upload(c->d_pmodq, pm.data(), NLK * 8, c->st));
+    // P * 2^64 mod q_i (Montgomery form of P)
+    std::vector<u64> pmm(NLK, 0);
+    for (uint32_t i = 0; i <= L; i++) pmm[i] = (u64)(((u128)pm[i] << 64) % c->mod[i]);
+    c->d_pmodq_m = c->alloc(NLK);
+    HEC_CHECK(upload(c->d_pmodq_m, pmm.data(), NLK * 8, c->st));
     u64 gT[19];
     gauss_table(c->prm.sigma, gT);
     c->d_gauss = c->alloc(19);
@@ -320,9 +325,12 @@ extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_
         taken.push_back(q);
     }
     c->mod = taken;
-    // the exact accumulations need alpha * q_max < 2^64 and k * p_max < 2^64
+    // the exact 128-bit accumulations need m * q_max < 2^64 for m terms of products
+    // below q^2: alpha (ModUp), k (ModDown), dnum + 1 (key switch with the folded
+    // c0 term) and HEC_KS_BATCH (fused plaintext products)
+    const uint32_t mterms = std::max(std::max(alpha, c->k), std::max(c->dnum + 1, (uint32_t)HEC_KS_BATCH));
     for (uint64_t q : c->mod)
-        if ((u128)q * std::max(alpha, c->k) >= ((u128)1 << 64)) HEC_FAIL(HEC_EINVAL, "primes too large for digits");
+        if ((u128)q * mterms >= ((u128)1 << 64)) HEC_FAIL(HEC_EINVAL, "primes too large for digits");
     c->enc.reset(new Encoder(c->logn));
     hec_status s = build_tables(c.get());
     if (s != HEC_OK) {
@@ -501,30 +509,29 @@ bool have_rotkey(hec_ctx *c, int32_t step)
 // ---------------------------------------------------------------------------
 // encoding
 // ---------------------------------------------------------------------------
-static hec_status upload_pt(hec_ctx *c, const int64_t *m, uint32_t level, double scale, hec_pt **out)
+// signed integer coefficients (device) -> plaintext limbs over q_0..q_level
+// (and p_0..p_{k-1} when with_p), evaluation + Montgomery form
+static hec_status make_pt(hec_ctx *c, const int64_t *dm, uint32_t level, double scale, bool with_p, hec_pt **out)
 {
-    const size_t n = c->n, nq = level + 1;
-    int64_t *dm = (int64_t *)c->alloc(n);
-    u64 *d = c->alloc(nq * n);
-    if (!dm || !d) HEC_FAIL(HEC_ENOMEM, "plaintext allocation");
-    HEC_TRY_HIP(hipMemcpyAsync(dm, m, n * 8, hipMemcpyHostToDevice, c->st));
-    hec_reduce_i64(c->T, d, dm, c->idmap(), nq, c->st);
-    hec_ntt_fwd(c->T, d, 0, 1, c->idmap(), nq, c->st);
-    hec_ew(c->T, EW_TO_MONT, d, d, nullptr, 0, 0, 0, 1, c->idmap(), nq, c->st);
-    // the host buffer may be reused by the caller: wait for the copy
-    HEC_TRY_HIP(hipStreamSynchronize(c->st));
-    c->release(dm);
+    const size_t n = c->n, nl = level + 1 + (with_p ? c->k : 0);
+    const u32 *pmap = with_p ? c->qpmap(level) : c->idmap();
+    u64 *d = c->alloc(nl * n);
+    if (!d) HEC_FAIL(HEC_ENOMEM, "plaintext allocation");
+    hec_reduce_i64(c->T, d, dm, pmap, (int)nl, c->st);
+    hec_ntt_fwd(c->T, d, 0, 1, pmap, (int)nl, c->st);
+    hec_ew(c->T, EW_TO_MONT, d, d, nullptr, 0, 0, 0, 1, pmap, (int)nl, c->st);
     hec_pt *p = new hec_pt();
     p->ctx = c;
     p->level = level;
     p->scale = scale;
     p->d = d;
+    p->has_p = with_p;
     *out = p;
     return HEC_OK;
 }
 
 hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size_t nz, uint32_t level, double scale,
-                          std::vector<hec_pt *> &out)
+                          std::vector<hec_pt *> &out, bool with_p)
 {
     const size_t cnt = z.size(), n = c->n;
     std::vector<int64_t> m(cnt * n);
@@ -538,18 +545,33 @@ hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size
         });
     for (auto &x : th) x.join();
     out.assign(cnt, nullptr);
-    for (size_t i = 0; i < cnt; i++) {
-        if (!ok[i]) {
-            for (auto *p : out) pt_free(p);
-            HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62 (scale too large for the values)");
+    for (size_t i = 0; i < cnt; i++)
+        if (!ok[i]) HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62 (scale too large for the values)");
+    // one staging copy for all encodings, in chunks of at most 256 polynomials
+    const size_t chunk = 256;
+    int64_t *dm = (int64_t *)c->alloc(std::min(cnt, chunk) * n);
+    if (!dm) HEC_FAIL(HEC_ENOMEM, "staging allocation");
+    hec_status s = HEC_OK;
+    for (size_t i0 = 0; i0 < cnt && s == HEC_OK; i0 += chunk) {
+        const size_t cc = std::min(chunk, cnt - i0);
+        if (hipMemcpyAsync(dm, &m[i0 * n], cc * n * 8, hipMemcpyHostToDevice, c->st) != hipSuccess) {
+            s = HEC_EDEVICE;
+            hec_set_error("plaintext upload failed");
+            break;
         }
-        hec_status s = upload_pt(c, &m[i * n], level, scale, &out[i]);
-        if (s != HEC_OK) {
-            for (auto *p : out) pt_free(p);
-            return s;
+        for (size_t i = 0; i < cc && s == HEC_OK; i++) s = make_pt(c, dm + i * n, level, scale, with_p, &out[i0 + i]);
+        // the staging buffer and the host copy are reused: wait for the chunk
+        if (hipStreamSynchronize(c->st) != hipSuccess && s == HEC_OK) {
+            s = HEC_EDEVICE;
+            hec_set_error("plaintext upload failed");
         }
     }
-    return HEC_OK;
+    c->release(dm);
+    if (s != HEC_OK) {
+        for (auto *p : out) pt_free(p);
+        out.clear();
+    }
+    return s;
 }
 
 extern "C" hec_status ckks_encode_coeffs(hec_ctx *c, const double *z, size_t nz, double scale, int64_t *m)
@@ -729,6 +751,61 @@ extern "C" hec_status ckks_ct_import(hec_ctx *c, const uint64_t *coeff, uint32_t
 // ---------------------------------------------------------------------------
 // rotations (hybrid key switching)
 // ---------------------------------------------------------------------------
+// ModUp of c1 (hoisted once for all rotations of a ciphertext): D[j] =
+// ModUp of digit j over Q_l and P, NTT form, [beta][nq+k][n]
+hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **Dout)
+{
+    *Dout = nullptr;
+    const size_t n = c->n;
+    const uint32_t lvl = ct->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    const u64 *c1 = ct->d + nq * n;
+    u64 *cc = c->alloc(nq * n);
+    u64 *D = c->alloc((size_t)beta * nqp * n);
+    if (!cc || !D) {
+        c->release(cc);
+        c->release(D);
+        HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
+    }
+    HEC_TRY_HIP(hipMemcpyAsync(cc, c1, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+    hec_ntt_inv(c->T, cc, 0, 1, c->idmap(), nq, c->st);
+    for (uint32_t j = 0; j < beta; j++) {
+        u64 *Dj = D + (size_t)j * nqp * n;
+        const BconvDesc &hd = c->h_modup[(size_t)lvl * c->dnum + j];
+        hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum + j, hd.nout, cc, Dj, 0, 0, 1, c->st);
+        uint32_t lo = j * c->alpha, hi = lo + hd.nin;
+        hec_ntt_fwd(c->T, Dj, 0, 1, c->qpmap(lvl), (int)lo, c->st);
+        hec_ntt_fwd(c->T, Dj + (size_t)hi * n, 0, 1, c->qpmap(lvl) + hi, (int)(nqp - hi), c->st);
+        HEC_TRY_HIP(hipMemcpyAsync(Dj + (size_t)lo * n, c1 + (size_t)lo * n, (size_t)hd.nin * n * 8,
+                                   hipMemcpyDeviceToDevice, c->st));
+    }
+    c->release(cc);
+    *Dout = D;
+    return HEC_OK;
+}
+
+// out = ModDown(E) for E = [2][nq+k][n] over Q_l and P (NTT form); E's P limbs are consumed
+hec_status ct_moddown(hec_ctx *c, uint32_t lvl, u64 *E, hec_ct *out)
+{
+    const size_t n = c->n;
+    const uint32_t nq = lvl + 1, k = c->k, nqp = nq + k;
+    if (out->level != lvl) HEC_FAIL(HEC_ELEVEL, "ModDown output at another level");
+    u64 *y = c->alloc(2 * (size_t)nq * n);
+    if (!y) HEC_FAIL(HEC_ENOMEM, "ModDown buffer");
+    CombineBatch cb{};
+    cb.out[0] = out->d;
+    cb.e[0] = E;
+    cb.y[0] = y;
+    cb.g[0] = 1;
+    hec_ntt_inv(c->T, E + (size_t)nq * n, (size_t)nqp * n, 2, c->qpmap(lvl) + nq, k, c->st);
+    hec_bconv(c->T, c->d_moddown + lvl, nq, E, y, (size_t)nqp * n, (size_t)nq * n, 2, c->st);
+    hec_ntt_fwd(c->T, y, (size_t)nq * n, 2, c->qpmap(lvl), nq, c->st);
+    hec_moddown_combine(c->T, cb, 1, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+    c->release(y);
+    HEC_TRY_HIP(hipGetLastError());
+    return HEC_OK;
+}
+
 hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt, hec_ct **outs)
 {
     const size_t n = c->n;
@@ -748,24 +825,9 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             if (!outs[i]) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
         }
     if (todo.empty()) return HEC_OK;
-    // ModUp of c1, once
-    const u64 *c0 = ct->d, *c1 = ct->d + nq * n;
-    u64 *cc = c->alloc(nq * n);
-    u64 *D = c->alloc((size_t)beta * nqp * n);
-    if (!cc || !D) HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
-    HEC_TRY_HIP(hipMemcpyAsync(cc, c1, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
-    hec_ntt_inv(c->T, cc, 0, 1, c->idmap(), nq, c->st);
-    for (uint32_t j = 0; j < beta; j++) {
-        u64 *Dj = D + (size_t)j * nqp * n;
-        const BconvDesc &hd = c->h_modup[(size_t)lvl * c->dnum + j];
-        hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum + j, hd.nout, cc, Dj, 0, 0, 1, c->st);
-        uint32_t lo = j * c->alpha, hi = lo + hd.nin;
-        hec_ntt_fwd(c->T, Dj, 0, 1, c->qpmap(lvl), (int)lo, c->st);
-        hec_ntt_fwd(c->T, Dj + (size_t)hi * n, 0, 1, c->qpmap(lvl) + hi, (int)(nqp - hi), c->st);
-        HEC_TRY_HIP(hipMemcpyAsync(Dj + (size_t)lo * n, c1 + (size_t)lo * n, (size_t)hd.nin * n * 8,
-                                   hipMemcpyDeviceToDevice, c->st));
-    }
-    c->release(cc);
+    u64 *D = nullptr;
+    HEC_CHECK(ct_modup(c, ct, &D));
+    const u64 *c0 = ct->d;
     // key switch in batches
     for (size_t b0 = 0; b0 < todo.size(); b0 += HEC_KS_BATCH) {
         const int R = (int)std::min((size_t)HEC_KS_BATCH, todo.size() - b0);

@@ -77,6 +77,7 @@ struct hec_ctx {
     BconvDesc *d_moddown = nullptr;  // [level]
     LevelC *d_lvl = nullptr;         // [level]
     u64 *d_pmodq = nullptr;          // [P]_{q_i}
+    u64 *d_pmodq_m = nullptr;        // [P * 2^64]_{q_i}
     u64 *d_gauss = nullptr;
     u64 *d_crt_m = nullptr, *d_crt_inv = nullptr, *d_crt_invsh = nullptr;  // Garner tables (q primes)
     std::vector<BconvDesc> h_modup, h_moddown;
@@ -109,7 +110,8 @@ struct hec_pt {
     hec_ctx *ctx = nullptr;
     uint32_t level = 0;
     double scale = 1.0;
-    u64 *d = nullptr;  // [level+1][n], NTT form, Montgomery
+    u64 *d = nullptr;  // [level+1 (+k)][n], NTT form, Montgomery; q_0..q_level then (optionally) p_0..p_{k-1}
+    bool has_p = false;
 };
 
 struct hec_image {
@@ -126,9 +128,15 @@ hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
 hec_status ct_add_inplace(hec_ctx *c, hec_ct *acc, const hec_ct *b);
 // acc (+)= ct * pt ; first == true writes instead of accumulating
 hec_status ct_mac_pt(hec_ctx *c, hec_ct *acc, const hec_ct *ct, const hec_pt *pt, bool first);
-// encode many slot vectors (in parallel on the host) and upload
+// encode many slot vectors (in parallel on the host) and upload; with_p also
+// reduces the integer coefficients into the special primes (for products
+// accumulated before ModDown)
 hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size_t nz, uint32_t level, double scale,
-                          std::vector<hec_pt *> &out);
+                          std::vector<hec_pt *> &out, bool with_p = false);
+// ModUp of c1 for hoisted key switching: *D = [beta][level+1+k][n] (NTT form), pool memory
+hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **D);
+// out = ModDown(E), E = [2][level+1+k][n] over Q_l and P (NTT form); E's P limbs are overwritten
+hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
 void pt_free(hec_pt *p);
 void ct_free(hec_ct *p);
 bool have_rotkey(hec_ctx *c, int32_t step);

@@ -566,6 +566,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ew(int op, u64 *out, const u64 *
     case EW_TO_MONT: *o = mont_mul(*x, pc.r2, pc.q, pc.qinv_neg); break;
     case EW_FROM_MONT: *o = redc(0, *x, pc.q, pc.qinv_neg); break;
     case EW_COPY: *o = *x; break;
+    case EW_ZERO: *o = 0; break;
     }
 }
 
@@ -801,6 +802,83 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
             pmap, (u32)NLK, (u32)nrot, nchunks, T);
 }
 
+// Key switching fused with the plaintext products of a convolution, summed
+// before ModDown (one ModDown per output instead of one per rotation).  The
+// term sigma_g(c0) of a rotation is folded in as P * sigma_g(c0) on the Q limbs:
+// ModDown(E + P*A) = ModDown(E) + A exactly.  Products are summed into 128 bits
+// and reduced once: < (beta + 1) q^2 for the key switch and < HEC_KS_BATCH q^2
+// for the terms, both below q * 2^64 (checked at context creation).
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nterms, u32 nout, const u64 *D,
+                                                       const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap,
+                                                       const u64 *pm, u32 NLK, u32 first, u32 nchunks, DevTables T)
+{
+    const u32 w = blockIdx.x, total = gridDim.x;
+    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 chunk = i % nchunks, o = i / nchunks;
+    const u32 k = chunk * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const size_t n = T.n;
+    const u32 pi = pmap[o];
+    const PrimeC pc = T.pc[pi];
+    const bool isq = o < nq;
+    const u64 pmo = isq ? pm[o] : 0;
+    acc128 acc[HEC_MAC_OUT][2];
+#pragma unroll
+    for (u32 v = 0; v < HEC_MAC_OUT; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    for (u32 t = 0; t < nterms; t++) {
+        const u32 g = b.g[t];
+        u64 e0, e1;
+        if (g == 1) {
+            if (!isq) continue;  // P * c vanishes modulo the special primes
+            e0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
+            e1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
+        } else {
+            const u32 src = auto_src(k, g, T.logn);
+            const u64 *key = b.key[t];
+            acc128 a0 = {0, 0}, a1 = {0, 0};
+            for (u32 j = 0; j < beta; j++) {
+                u64 d = D[((size_t)j * nqp + o) * n + src];
+                mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
+                mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+            }
+            if (isq) mac(a0, ct[(size_t)o * n + src], pmo);
+            e0 = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
+            e1 = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+        }
+#pragma unroll
+        for (u32 v = 0; v < HEC_MAC_OUT; v++) {
+            if (v >= nout) break;
+            const u64 *pt = b.pt[t][v];
+            if (!pt) continue;
+            const u64 m = pt[(size_t)o * n + k];
+            mac(acc[v][0], e0, m);
+            mac(acc[v][1], e1, m);
+        }
+    }
+#pragma unroll
+    for (u32 v = 0; v < HEC_MAC_OUT; v++) {
+        if (v >= nout) break;
+        u64 r0 = redc(acc[v][0].hi, acc[v][0].lo, pc.q, pc.qinv_neg);
+        u64 r1 = redc(acc[v][1].hi, acc[v][1].lo, pc.q, pc.qinv_neg);
+        u64 *E = b.E[v];
+        const size_t i0 = (size_t)o * n + k, i1 = ((size_t)nqp + o) * n + k;
+        if (!((first >> v) & 1)) {
+            r0 = add_mod(r0, E[i0], pc.q);
+            r1 = add_mod(r1, E[i1], pc.q);
+        }
+        E[i0] = r0;
+        E[i1] = r1;
+    }
+}
+void hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
+                int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st)
+{
+    const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
+    dim3 g(nchunks * (u32)nqp);
+    KLAUNCH("k_ks_mac", (uint64_t)nterms * nqp, k_ks_mac, g, dim3(EW_THREADS), 0, st, b, (u32)nterms, (u32)nout, D,
+            ct, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first, nchunks, T);
+}
+
 // ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)
 __global__ void k_moddown_combine(CombineBatch cb, const u64 *c0, u32 nq, u32 nqp, const LevelC *lc,
                                   const u32 *pmap, DevTables T)
@@ -813,7 +891,7 @@ __global__ void k_moddown_combine(CombineBatch cb, const u64 *c0, u32 nq, u32 nq
     u64 e = cb.e[r][((size_t)p * nqp + i) * n + k];
     u64 y = cb.y[r][((size_t)p * nq + i) * n + k];
     u64 v = shoup_mul(sub_mod(e, y, q), lc->pinv[i], lc->pinv_sh[i], q);
-    if (p == 0) v = add_mod(v, c0[(size_t)i * n + auto_src(k, cb.g[r], T.logn)], q);
+    if (p == 0 && c0) v = add_mod(v, c0[(size_t)i * n + auto_src(k, cb.g[r], T.logn)], q);
     cb.out[r][((size_t)p * nq + i) * n + k] = v;
 }
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,

@@ -921,7 +921,8 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
         for (auto &it : v)
             for (auto &pp : it.pts) zp.push_back(pp.second.data());
     std::vector<hec_pt *> pts;
-    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts));
+    // limbs over Q_l and P: the lazy-ModDown mode multiplies before ModDown
+    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts, true));
     size_t q = 0;
     for (size_t u = 0; u < items.size(); u++)
         for (auto &it : items[u]) {
@@ -941,7 +942,7 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
 
 extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
-    if (!p || (mode != 0 && mode != 1)) HEC_FAIL(HEC_EINVAL, "bad mode");
+    if (!p || mode < 0 || mode > 2) HEC_FAIL(HEC_EINVAL, "bad mode");
     p->mode = mode;
     return HEC_OK;
 }
@@ -956,6 +957,87 @@ extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *step
         for (int32_t s : p->steps) steps[i++] = s;
     }
     return HEC_OK;
+}
+
+// Lazy ModDown: the key-switch products of every rotation are multiplied by
+// their plaintexts and summed over Q_l and P; each output shard then takes one
+// ModDown (instead of one per rotation).  Rotations by zero enter as P * pt * ct.
+// acc[v] receives the ModDown of output v (not yet rescaled).
+static hec_status conv_accumulate_lazy(hec_ctx *c, const hec_conv_plan *p, const hec_image *in,
+                                       std::vector<hec_ct *> &acc)
+{
+    const size_t n = c->n, nout = acc.size();
+    const uint32_t lvl = p->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    std::vector<u64 *> E(nout, nullptr);
+    std::vector<char> used(nout, 0), fresh(nout, 1);
+    hec_status s = HEC_OK;
+    for (size_t v = 0; v < nout && s == HEC_OK; v++)
+        if (!(E[v] = c->alloc(2 * (size_t)nqp * n))) s = HEC_ENOMEM, hec_set_error("accumulator allocation");
+    double scale = 1.0;
+    for (size_t u = 0; u < p->items.size() && s == HEC_OK; u++) {
+        const auto &its = p->items[u];
+        if (its.empty()) continue;
+        const hec_ct *ct = in->shards[u];
+        bool rot = false;
+        for (auto &it : its) rot |= c->galois(it.amount) != 1;
+        u64 *D = nullptr;
+        if (rot && (s = ct_modup(c, ct, &D)) != HEC_OK) break;
+        for (size_t v0 = 0; v0 < nout && s == HEC_OK; v0 += HEC_MAC_OUT) {
+            const size_t nv = std::min((size_t)HEC_MAC_OUT, nout - v0);
+            // the items of this shard with a product for an output of the group
+            std::vector<size_t> terms;
+            for (size_t t = 0; t < its.size(); t++)
+                for (auto &pp : its[t].pts)
+                    if (pp.first >= v0 && pp.first < v0 + nv) {
+                        terms.push_back(t);
+                        break;
+                    }
+            for (size_t b0 = 0; b0 < terms.size(); b0 += HEC_KS_BATCH) {
+                const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
+                KsMacBatch b{};
+                int first = 0;
+                for (size_t j = 0; j < nv; j++) {
+                    b.E[j] = E[v0 + j];
+                    if (fresh[v0 + j]) first |= 1 << j;
+                    fresh[v0 + j] = 0;
+                }
+                for (size_t t = 0; t < nt; t++) {
+                    const auto &it = its[terms[b0 + t]];
+                    const uint32_t g = c->galois(it.amount);
+                    b.g[t] = g;
+                    b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
+                    for (auto &pp : it.pts)
+                        if (pp.first >= v0 && pp.first < v0 + nv) {
+                            if (!pp.second->has_p || pp.second->level != lvl) {
+                                s = HEC_EINVAL;
+                                hec_set_error("plan plaintexts lack the special-prime limbs");
+                                break;
+                            }
+                            b.pt[t][pp.first - v0] = pp.second->d;
+                            used[pp.first] = 1;
+                            scale = ct->scale * pp.second->scale;
+                        }
+                }
+                if (s != HEC_OK) break;
+                hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
+                           c->d_pmodq_m, (int)c->NLK, first, c->st);
+            }
+        }
+        c->release(D);
+    }
+    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+        if (!used[v]) {
+            s = HEC_ELAYOUT;
+            hec_set_error("output shard %zu received no product", v);
+            break;
+        }
+        acc[v]->scale = scale;
+        s = ct_moddown(c, lvl, E[v], acc[v]);
+    }
+    for (auto *e : E) c->release(e);
+    if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("lazy accumulation launch");
+    return s;
 }
 
 #define ROT_CHUNK 32
@@ -978,7 +1060,11 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         if (!acc[v]) { free_all(acc); HEC_FAIL(HEC_ENOMEM, "accumulator allocation"); }
     }
     hec_status s = HEC_OK;
-    for (size_t u = 0; u < p->items.size() && s == HEC_OK; u++) {
+    if (p->mode == 2) {
+        s = conv_accumulate_lazy(c, p, in, acc);
+        std::fill(first.begin(), first.end(), 0);
+    }
+    for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode != 2; u++) {
         const auto &its = p->items[u];
         for (size_t i0 = 0; i0 < its.size() && s == HEC_OK; i0 += ROT_CHUNK) {
             size_t cnt = std::min((size_t)ROT_CHUNK, its.size() - i0);

@@ -7,8 +7,11 @@ configuration bench.py times (batched hoisted rotations, plan runs).
   complete 3x3 convolution of a 2-channel 112x112 shard (the per-shard
   geometry of the 112x112x64 layer: side padded to 128, 2 channels per
   ciphertext, 17 rotations);
+* the same shard convolution with lazy ModDown, bit-exact with the oracle's
+  lazy form;
 * decrypted within 1e-5 of FP64: the 32x32x32 image through conv 3x3 32->32
-  and the strided conv 3x3 32->64 (the benchmark step).
+  and the strided conv 3x3 32->64 (the benchmark step), with per-rotation and
+  with lazy ModDown.
 """
 import sys
 
@@ -96,6 +99,27 @@ def test_conv_112_shard_bit_exact(full):
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
 
 
+def test_conv_112_shard_lazy_bit_exact(full):
+    """The same shard convolution with lazy ModDown (one ModDown for the 17
+    rotations), bit-exact with the oracle's lazy form."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(3)
+    x = np.clip(rng.normal(0, 1, (2, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (2, 2, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3004)
+    plan = ctx.conv2d_plan(img, w)
+    plan.set_mode(2)
+    ctx.gen_rotation_keys(plan.steps())
+    out = plan.run(img)
+    log("oracle lazy conv")
+    lay = hl.natural_layout(prm.N, 2, 112, 112)
+    cts = [o.encrypt(o.encode(v, 20, 2.0 ** LS), seed=3004, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1, lazy=True)
+    assert out.shard_info(0) == (oc[0].level, oc[0].scale)
+    assert (out.shard_export(0) == oc[0].data).all()
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
 def test_benchmark_step_accuracy(full):
     """The benchmark workload end to end, batched and plain, within 1e-5."""
     ctx, prm, o = full
@@ -119,3 +143,11 @@ def test_benchmark_step_accuracy(full):
     err = np.abs(b.decrypt() - ref).max()
     log("max abs err", err)
     assert err < 1e-5
+    # lazy ModDown: other bits, same values within the same bound
+    p1.set_mode(2)
+    p2.set_mode(2)
+    bl = p2.run(p1.run(img))
+    assert bl.shard_info(0) == b.shard_info(0)
+    err_l = np.abs(bl.decrypt() - ref).max()
+    log("lazy max abs err", err_l)
+    assert err_l < 1e-5

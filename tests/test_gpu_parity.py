@@ -132,9 +132,10 @@ def test_rescale_mul_add_bit_exact(small):
     assert e.value.status == hecnn.HEC_ELEVEL
 
 
-def run_pipeline(ctx, prm, o, x, ops, level, seed):
+def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
     """Encrypt x on both sides, apply ops ('conv', w, stride) / ('pool',),
-    compare every shard bit for bit after every op; return final decryption."""
+    compare every shard bit for bit after every op; return final decryption.
+    mode 2 runs the convolutions with lazy ModDown on both sides."""
     C, H, W = x.shape
     img = ctx.image_encrypt(x, level, seed)
     lay = hl.natural_layout(prm.N, C, H, W)
@@ -147,11 +148,12 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed):
     for op in ops:
         if op[0] == "conv":
             w, stride = op[1], op[2]
-            plan = ctx.conv2d_plan(img, w, stride=stride, pad=1)
+            plan = ctx.conv2d_plan(img, w, stride=stride, pad=pad)
+            plan.set_mode(mode)
             ctx.gen_rotation_keys(plan.steps())
             img = plan.run(img)
-            cts, lay = hl.conv2d(be, cts, lay, w, pad=1, stride=stride)
-            ref = hl.ref_conv2d(ref, w, 1, stride)
+            cts, lay = hl.conv2d(be, cts, lay, w, pad=pad, stride=stride, lazy=(mode == 2))
+            ref = hl.ref_conv2d(ref, w, pad, stride)
         else:
             ctx.gen_rotation_keys(ctx.avgpool_steps(img))
             img = ctx.avgpool(img)
@@ -206,6 +208,59 @@ def test_layers_bit_exact(small, shape, ops):
     run_pipeline(ctx, prm, o, x, real_ops, 6, seed=31)
 
 
+@pytest.mark.parametrize("shape,ops", [
+    ((4, 8, 8), [("conv", (4, 3), 1)]),                             # one shard, duplicated copies
+    ((4, 16, 16), [("conv", (16, 3), 1), ("pool",)]),               # 2 shards -> 8 outputs (two groups of 4)
+    ((16, 16, 16), [("conv", (8, 3), 1)]),                          # 8 input shards -> 4 outputs
+    ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv
+    ((2, 32, 32), [("conv", (3, 3), 1), ("pool",)]),                # channel shards
+    ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem in channel shards
+])
+def test_layers_lazy_moddown_bit_exact(small, shape, ops):
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + 100)
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("lazy layers", shape, [op[0] for op in ops])
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=37, mode=2)
+
+
+def test_lazy_zero_rotation_only(small):
+    """A 1x1 convolution of one channel per shard needs only the zero
+    rotation: the lazy path must then equal the batched path bit for bit."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(12)
+    x = rng.uniform(-1, 1, (1, 16, 16))
+    w = rng.normal(0, 0.3, (1, 1, 1, 1))
+    got = run_pipeline(ctx, prm, o, x, [("conv", w, 1)], 5, seed=41, mode=2, pad=0)
+    img = ctx.image_encrypt(x, 5, 41)
+    plan = ctx.conv2d_plan(img, w, pad=0)
+    assert plan.steps() == []
+    a = plan.run(img)
+    plan.set_mode(2)
+    b = plan.run(img)
+    assert (a.shard_export(0) == b.shard_export(0)).all()
+    assert np.abs(got - b.decrypt()).max() == 0
+
+
+def test_plan_mode_rejected(small):
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    img = ctx.image_encrypt(np.zeros((1, 8, 8)), 3, 1)
+    plan = ctx.conv2d_plan(img, np.ones((1, 1, 3, 3)))
+    with pytest.raises(hecnn.HecError) as e:
+        plan.set_mode(3)
+    assert e.value.status == hecnn.HEC_EINVAL
+
+
 def test_plain_equals_batched(small):
     ctx, prm, o = small
     rng = np.random.default_rng(9)
@@ -230,3 +285,4 @@ def test_ring_2e13_conv_pool():
     x = rng.uniform(-1, 1, (4, 32, 32))
     w = rng.normal(0, 0.1, (4, 4, 3, 3))
     run_pipeline(ctx, prm, o, x, [("conv", w, 1), ("pool",)], 2, seed=3001)
+    run_pipeline(ctx, prm, o, x, [("conv", w, 1), ("pool",)], 2, seed=3002, mode=2)

@@ -98,3 +98,32 @@ def test_ring_2e13_conv_pool():
     pl_, pll = hl.avgpool2x2(be, c, cl)
     assert pl_[0].level == 0 and pl_[0].scale == 2.0 ** 38
     assert np.abs(dec_image(o, pl_, pll) - hl.ref_avgpool2x2(ref_c)).max() < 1e-5
+
+
+def test_lazy_moddown_conv(small):
+    """Lazy ModDown (products accumulated over Q*P, one ModDown per output
+    shard) decrypts to the same convolution; with only zero rotations it is
+    bit-identical to the per-rotation form (no key switch involved)."""
+    p, o = small
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 15)
+    be = hl.CkksBackend(o)
+    a, al = hl.conv2d(be, cts, lay, w, pad=1, lazy=True)
+    b, bl = hl.conv2d(be, cts, lay, w, pad=1, lazy=False)
+    ref = hl.ref_conv2d(x, w, 1)
+    ea = np.abs(dec_image(o, a, al) - ref).max()
+    eb = np.abs(dec_image(o, b, bl) - ref).max()
+    assert ea < 1e-5 and eb < 1e-5
+    assert a[0].level == b[0].level and a[0].scale == b[0].scale
+    assert not (a[0].data == b[0].data).all()     # different rounding, different bits
+    # 1x1 kernel on a one-block-per-channel layout with a single channel: only the zero rotation
+    x1 = rng.uniform(-1, 1, (1, 8, 8))
+    w1 = rng.normal(0, 0.1, (1, 1, 1, 1))
+    lay1 = hl.natural_layout(p.N, 1, 8, 8)
+    c1 = enc_image(o, x1, lay1, 6, 2.0 ** 40, 16)
+    la, _ = hl.conv2d(be, c1, lay1, w1, pad=0, lazy=True)
+    lb, _ = hl.conv2d(be, c1, lay1, w1, pad=0, lazy=False)
+    assert (la[0].data == lb[0].data).all()
