@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=2)
+    ap.add_argument("--mode", type=int, default=0, choices=(0, 1, 2),
+                    help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -145,6 +147,7 @@ def main():
         ctx.keygen(2002)
         img = ctx.image_encrypt(x, LEVEL, 3002)
         p1 = ctx.conv2d_plan(img, w1, stride=1, pad=1)
+        p1.set_mode(args.mode)
         ctx.gen_rotation_keys(p1.steps())
         o1 = p1.run(img)
         ctx.sync()
@@ -179,6 +182,8 @@ def main():
             return float(np.abs(y - ref).max())
         return None
 
+    p1.set_mode(args.mode)
+    p2.set_mode(args.mode)
     for _ in range(args.warmup):
         step()
     err = step(check=True)

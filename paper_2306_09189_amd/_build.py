@@ -20,6 +20,7 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-D__HI
 SOURCES = [
     ("hec_kernels.hip", "hip"),
     ("hec_ctx.hip", "hip"),
+    ("hec_encode.hip", "hip"),
     ("hec_layers.cpp", "cxx"),
     ("hec_host.cpp", "cxx"),
 ]

@@ -111,7 +111,8 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 // E_v (+)= sum_t pt[t][v] * KS_t, KS_t = (sum_j sigma_g(D_j) key_j + P sigma_g(c0), sum_j sigma_g(D_j) key'_j)
 // or P * (c0, c1) for g == 1; ct = [2][nq][n] (NTT form), D = [beta][nqp][n] ModUp of c1 (NTT form),
 // pm[i] = P * 2^64 mod q_i; bit v of `first` set: output v is written instead of accumulated.
-void hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
+// Rotations by zero (g == 1) must precede the others; returns false (nothing launched) otherwise.
+bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
                 int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
@@ -140,6 +141,15 @@ void hec_automorph_ntt(const DevTables &T, u64 *out, const u64 *in, size_t poly_
 // (prod_{k<i} q_k)^-1 mod q_i with its Shoup companion
 void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, const u64 *Mm, const u64 *inv,
                     const u64 *invsh, hipStream_t st);
+
+// CKKS slot encoding of `count` vectors (z + i*zstride, nz values each) into signed coefficients
+// m[count][n] (double-double FFT, rounding half away from zero); *flag != 0 afterwards if a
+// coefficient reached 2^62.  work holds count * n double4.
+void hec_encode(const double *z, size_t zstride, u32 nz, u32 count, double scale, const u32 *root,
+                const double4 *tw, double4 *work, int64_t *m, int *flag, u32 logn, hipStream_t st);
+// decoding of centered coefficients m[n] (doubles) into nz slot values; work holds n double2
+void hec_decode(const double *m, double scale, const u32 *root, const double4 *tw, double2 *work, double *z,
+                u32 nz, u32 logn, hipStream_t st);
 
 // launch timing of one kernel by name (NULL stops); collect syncs the events
 void hec_prof_select(const char *name);

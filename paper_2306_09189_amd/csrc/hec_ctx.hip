@@ -271,6 +271,15 @@ static hec_status build_tables(hec_ctx *c)
         HEC_CHECK(upload(c->d_crt_m, Mm.data(), Mm.size() * 8, c->st));
         HEC_CHECK(upload(c->d_crt_inv, inv.data(), inv.size() * 8, c->st));
         HEC_CHECK(upload(c->d_crt_invsh, invsh.data(), invsh.size() * 8, c->st));
+        {
+            EncoderTables et(c->logn);
+            c->d_enc_tw = (double4 *)c->pool.get(et.tw.size() * 8);
+            c->d_enc_root = (u32 *)c->pool.get(et.root.size() * 4);
+            c->d_flag = (int *)c->pool.get(256);
+            if (!c->d_enc_tw || !c->d_enc_root || !c->d_flag) HEC_FAIL(HEC_ENOMEM, "table allocation");
+            HEC_CHECK(upload(c->d_enc_tw, et.tw.data(), et.tw.size() * 8, c->st));
+            HEC_CHECK(upload(c->d_enc_root, et.root.data(), et.root.size() * 4, c->st));
+        }
         HEC_TRY_HIP(hipStreamSynchronize(c->st));
     }
 
@@ -331,7 +340,6 @@ extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_
     const uint32_t mterms = std::max(std::max(alpha, c->k), std::max(c->dnum + 1, (uint32_t)HEC_KS_BATCH));
     for (uint64_t q : c->mod)
         if ((u128)q * mterms >= ((u128)1 << 64)) HEC_FAIL(HEC_EINVAL, "primes too large for digits");
-    c->enc.reset(new Encoder(c->logn));
     hec_status s = build_tables(c.get());
     if (s != HEC_OK) {
         c->pool.release_all();
@@ -530,42 +538,53 @@ static hec_status make_pt(hec_ctx *c, const int64_t *dm, uint32_t level, double 
     return HEC_OK;
 }
 
+// encode `count` slot vectors held in device memory (stride zstride, nz values
+// each) into signed coefficients dm[count][n] on the device; waits for the
+// result of the overflow check
+static hec_status encode_device(hec_ctx *c, const double *dz, size_t zstride, size_t nz, size_t count, double scale,
+                                int64_t *dm)
+{
+    const size_t n = c->n;
+    double4 *work = (double4 *)c->pool.get(count * n * sizeof(double4));
+    if (!work) HEC_FAIL(HEC_ENOMEM, "encoder buffer");
+    hec_encode(dz, zstride, (u32)nz, (u32)count, scale, c->d_enc_root, c->d_enc_tw, work, dm, c->d_flag, c->logn,
+               c->st);
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    c->pool.put(work);
+    if (e != hipSuccess) HEC_FAIL(HEC_EDEVICE, "encoder: %s", hipGetErrorString(e));
+    if (flag) HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62 (scale too large for the values)");
+    return HEC_OK;
+}
+
 hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size_t nz, uint32_t level, double scale,
                           std::vector<hec_pt *> &out, bool with_p)
 {
-    const size_t cnt = z.size(), n = c->n;
-    std::vector<int64_t> m(cnt * n);
-    std::vector<char> ok(cnt, 1);
-    unsigned nth = std::max(1u, std::min((unsigned)cnt, std::thread::hardware_concurrency()));
-    if (nth > 32) nth = 32;
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nth; t++)
-        th.emplace_back([&, t]() {
-            for (size_t i = t; i < cnt; i += nth) ok[i] = c->enc->encode(z[i], nz, scale, &m[i * n]);
-        });
-    for (auto &x : th) x.join();
+    const size_t cnt = z.size(), n = c->n, N = c->N;
     out.assign(cnt, nullptr);
-    for (size_t i = 0; i < cnt; i++)
-        if (!ok[i]) HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62 (scale too large for the values)");
-    // one staging copy for all encodings, in chunks of at most 256 polynomials
-    const size_t chunk = 256;
-    int64_t *dm = (int64_t *)c->alloc(std::min(cnt, chunk) * n);
-    if (!dm) HEC_FAIL(HEC_ENOMEM, "staging allocation");
-    hec_status s = HEC_OK;
+    // slot vectors staged through the device in chunks; encoding, reduction and
+    // NTT all run there
+    const size_t chunk = 64, cmax = std::min(cnt, chunk);
+    std::vector<double> hz(cmax * N, 0.0);
+    double *dz = (double *)c->pool.get(cmax * N * 8);
+    int64_t *dm = (int64_t *)c->alloc(cmax * n);
+    hec_status s = (dz && dm) ? HEC_OK : HEC_ENOMEM;
+    if (s != HEC_OK) hec_set_error("encoder staging allocation");
     for (size_t i0 = 0; i0 < cnt && s == HEC_OK; i0 += chunk) {
         const size_t cc = std::min(chunk, cnt - i0);
-        if (hipMemcpyAsync(dm, &m[i0 * n], cc * n * 8, hipMemcpyHostToDevice, c->st) != hipSuccess) {
+        for (size_t i = 0; i < cc; i++) memcpy(&hz[i * N], z[i0 + i], nz * 8);
+        if (hipMemcpyAsync(dz, hz.data(), cc * N * 8, hipMemcpyHostToDevice, c->st) != hipSuccess) {
             s = HEC_EDEVICE;
             hec_set_error("plaintext upload failed");
             break;
         }
+        // encode_device waits for the stream, so hz may be refilled afterwards
+        s = encode_device(c, dz, N, nz, cc, scale, dm);
         for (size_t i = 0; i < cc && s == HEC_OK; i++) s = make_pt(c, dm + i * n, level, scale, with_p, &out[i0 + i]);
-        // the staging buffer and the host copy are reused: wait for the chunk
-        if (hipStreamSynchronize(c->st) != hipSuccess && s == HEC_OK) {
-            s = HEC_EDEVICE;
-            hec_set_error("plaintext upload failed");
-        }
     }
+    // make_pt's kernels read dm: order the release after them on the stream
+    c->pool.put(dz);
     c->release(dm);
     if (s != HEC_OK) {
         for (auto *p : out) pt_free(p);
@@ -578,8 +597,25 @@ extern "C" hec_status ckks_encode_coeffs(hec_ctx *c, const double *z, size_t nz,
 {
     if (!c || !m || (nz && !z)) HEC_FAIL(HEC_EINVAL, "NULL argument");
     if (nz > c->N) HEC_FAIL(HEC_EINVAL, "more values than slots");
-    if (!c->enc->encode(z, nz, scale, m)) HEC_FAIL(HEC_EINVAL, "encoded coefficient exceeds 2^62");
-    return HEC_OK;
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t n = c->n;
+    double *dz = (double *)c->pool.get(c->N * 8);
+    int64_t *dm = (int64_t *)c->alloc(n);
+    if (!dz || !dm) {
+        c->pool.put(dz);
+        c->release(dm);
+        HEC_FAIL(HEC_ENOMEM, "encoder staging allocation");
+    }
+    hec_status s = HEC_OK;
+    if (nz && hipMemcpyAsync(dz, z, nz * 8, hipMemcpyHostToDevice, c->st) != hipSuccess) s = HEC_EDEVICE;
+    if (s == HEC_OK) s = encode_device(c, dz, c->N, nz, 1, scale, dm);
+    if (s == HEC_OK && (hipMemcpyAsync(m, dm, n * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+                        hipStreamSynchronize(c->st) != hipSuccess))
+        s = HEC_EDEVICE;
+    c->pool.put(dz);
+    c->release(dm);
+    if (s == HEC_EDEVICE) hec_set_error("encoder transfer failed");
+    return s;
 }
 
 extern "C" hec_status ckks_encode(hec_ctx *c, const double *z, size_t nz, uint32_t level, double scale, hec_pt **out)
@@ -680,21 +716,24 @@ extern "C" hec_status ckks_encrypt(hec_ctx *c, const hec_pt *pt, uint64_t seed, 
 
 hec_status decrypt_slots(hec_ctx *c, const hec_ct *ct, double *z, size_t nz)
 {
-    // m = c0 + c1 s, back to coefficients, centered CRT on the device; the
-    // host only runs the final FFT of the decoding (client side)
+    // m = c0 + c1 s, back to coefficients, centered CRT and the decoding FFT
+    // on the device; only the nz slot values come back
     const size_t n = c->n, nq = ct->level + 1;
-    u64 *t = c->alloc(nq * n + n);
+    u64 *t = c->alloc(nq * n + n + 2 * n + c->N);
     if (!t) HEC_FAIL(HEC_ENOMEM, "decryption buffer");
     double *dm = (double *)(t + nq * n);
+    double2 *work = (double2 *)(t + nq * n + n);
+    double *dz = (double *)(t + nq * n + 3 * n);
     hec_ew(c->T, EW_MUL_MONT, t, ct->d + nq * n, c->d_sM, 0, 0, 0, 1, c->idmap(), nq, c->st);
     hec_ew(c->T, EW_ADD, t, t, ct->d, 0, 0, 0, 1, c->idmap(), nq, c->st);
     hec_ntt_inv(c->T, t, 0, 1, c->idmap(), nq, c->st);
     hec_crt_double(c->T, t, dm, (int)nq, c->d_crt_m, c->d_crt_inv, c->d_crt_invsh, c->st);
-    std::vector<double> m(n);
-    HEC_TRY_HIP(hipMemcpyAsync(m.data(), dm, n * 8, hipMemcpyDeviceToHost, c->st));
-    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    hec_decode(dm, ct->scale, c->d_enc_root, c->d_enc_tw, work, dz, (u32)nz, c->logn, c->st);
+    hipError_t e = hipSuccess;
+    if (nz) e = hipMemcpyAsync(z, dz, nz * 8, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     c->release(t);
-    c->enc->decode(m.data(), ct->scale, z, nz);
+    if (e != hipSuccess) HEC_FAIL(HEC_EDEVICE, "decryption: %s", hipGetErrorString(e));
     return HEC_OK;
 }
 

@@ -171,28 +171,12 @@ void sincos_dd(dd x, dd &c, dd &s)
     c = sum;
 }
 
-// round half away from zero of a double-double; |x| < 2^62 assumed
-int64_t round_away(dd x, bool &ok)
-{
-    if (!(std::fabs(x.h) < 4611686018427387904.0)) { ok = false; return 0; }
-    double f = std::floor(x.h);
-    // frac = (x.h - f) + x.l ; x.h - f is exact for |x.h| < 2^52, and zero above
-    double frac = (x.h - f) + x.l;
-    int64_t base = (int64_t)f;
-    // frac may have left [0, 1) through x.l
-    while (frac >= 1.0) { frac -= 1.0; base += 1; }
-    while (frac < 0.0) { frac += 1.0; base -= 1; }
-    if (frac > 0.5) return base + 1;
-    if (frac < 0.5) return base;
-    // exact tie: away from zero
-    return (base >= 0) ? base + 1 : base;
-}
 }  // namespace
 
-Encoder::Encoder(uint32_t logn) : n_(1u << logn)
+EncoderTables::EncoderTables(uint32_t logn)
 {
-    const uint32_t n = n_, twon = 2 * n;
-    ch_.resize(twon); cl_.resize(twon); sh_.resize(twon); sl_.resize(twon);
+    const uint32_t n = 1u << logn, twon = 2 * n;
+    tw.resize(4 * (size_t)twon);
     const uint32_t quarter = n / 2;  // pi/2 in units of pi/n
     for (uint32_t e = 0; e < twon; e++) {
         uint32_t qd = e / quarter, r = e % quarter;
@@ -210,85 +194,17 @@ Encoder::Encoder(uint32_t logn) : n_(1u << logn)
         case 2: C = neg(c); S = neg(s); break;
         default: C = s; S = neg(c); break;
         }
-        ch_[e] = C.h; cl_[e] = C.l; sh_[e] = S.h; sl_[e] = S.l;
+        tw[4 * (size_t)e] = C.h;
+        tw[4 * (size_t)e + 1] = C.l;
+        tw[4 * (size_t)e + 2] = S.h;
+        tw[4 * (size_t)e + 3] = S.l;
     }
-    slot_root_.resize(n / 2);
+    root.resize(n / 2);
     uint64_t f = 1;
     for (uint32_t j = 0; j < n / 2; j++) {
-        slot_root_[j] = (uint32_t)((f - 1) / 2);
+        root[j] = (uint32_t)((f - 1) / 2);
         f = f * 5 % twon;
     }
-}
-
-bool Encoder::encode(const double *z, size_t nz, double scale, int64_t *m) const
-{
-    const uint32_t n = n_, twon = 2 * n;
-    std::vector<dd> re(n, dd{0, 0}), im(n, dd{0, 0});
-    for (uint32_t j = 0; j < n / 2 && j < nz; j++) {
-        uint32_t k = slot_root_[j];
-        re[k] = dd{z[j], 0};            // root zeta^(5^j)
-        re[n - 1 - k] = dd{z[j], 0};    // root zeta^(-5^j): (2n - f - 1)/2 = n - 1 - (f-1)/2
-    }
-    // bit reversal
-    for (uint32_t i = 1, j = 0; i < n; i++) {
-        uint32_t bit = n >> 1;
-        for (; j & bit; bit >>= 1) j ^= bit;
-        j ^= bit;
-        if (i < j) { std::swap(re[i], re[j]); std::swap(im[i], im[j]); }
-    }
-    // X[t] = sum_k v_k exp(-2 pi i k t / n)
-    for (uint32_t len = 2; len <= n; len <<= 1) {
-        uint32_t h = len / 2, step = 2 * (n / len);  // exp(-2 pi i j/len) = angle index 2j(n/len)
-        for (uint32_t i = 0; i < n; i += len)
-            for (uint32_t j = 0; j < h; j++) {
-                uint32_t e = j * step;
-                dd wr = {ch_[e], cl_[e]}, wi = {-sh_[e], -sl_[e]};
-                dd br = re[i + j + h], bi = im[i + j + h];
-                dd vr, vi;
-                if (j == 0) { vr = br; vi = bi; }
-                else {
-                    vr = sub(mul(br, wr), mul(bi, wi));
-                    vi = add(mul(br, wi), mul(bi, wr));
-                }
-                dd ar = re[i + j], ai = im[i + j];
-                re[i + j] = add(ar, vr); im[i + j] = add(ai, vi);
-                re[i + j + h] = sub(ar, vr); im[i + j + h] = sub(ai, vi);
-            }
-    }
-    const double sc = scale / (double)n;  // exact
-    bool ok = true;
-    for (uint32_t t = 0; t < n; t++) {
-        // Re(X_t * exp(-i pi t / n)) = re cos + im sin
-        dd v = add(mul(re[t], dd{ch_[t], cl_[t]}), mul(im[t], dd{sh_[t], sl_[t]}));
-        m[t] = round_away(mul_d(v, sc), ok);
-    }
-    (void)twon;
-    return ok;
-}
-
-void Encoder::decode(const double *m, double scale, double *z, size_t nz) const
-{
-    const uint32_t n = n_;
-    std::vector<std::complex<double>> a(n);
-    for (uint32_t t = 0; t < n; t++) a[t] = std::complex<double>(m[t] * ch_[t], m[t] * sh_[t]);
-    for (uint32_t i = 1, j = 0; i < n; i++) {
-        uint32_t bit = n >> 1;
-        for (; j & bit; bit >>= 1) j ^= bit;
-        j ^= bit;
-        if (i < j) std::swap(a[i], a[j]);
-    }
-    for (uint32_t len = 2; len <= n; len <<= 1) {
-        uint32_t h = len / 2, step = 2 * (n / len);
-        for (uint32_t i = 0; i < n; i += len)
-            for (uint32_t j = 0; j < h; j++) {
-                uint32_t e = j * step;
-                std::complex<double> w(ch_[e], sh_[e]);
-                std::complex<double> u = a[i + j], v = a[i + j + h] * w;
-                a[i + j] = u + v;
-                a[i + j + h] = u - v;
-            }
-    }
-    for (uint32_t j = 0; j < n / 2 && j < nz; j++) z[j] = a[slot_root_[j]].real() / scale;
 }
 
 }  // namespace hec

@@ -20,21 +20,14 @@ uint64_t shoup_of(uint64_t w, uint64_t q);       // floor(w * 2^64 / q)
 // Gaussian cumulative table (sigma, |x| <= 19), 63-bit thresholds.
 void gauss_table(double sigma, uint64_t T[19]);
 
-// Real-slot encoder: m_t = round_half_away(scale * (2/n) sum_j z_j cos(pi (5^j t mod 2n)/n)),
-// evaluated through a length-n double-double FFT over the odd powers of zeta.
-class Encoder {
-public:
-    explicit Encoder(uint32_t logn);
-    // returns false if a coefficient exceeds 2^62 in magnitude
-    bool encode(const double *z, size_t nz, double scale, int64_t *m) const;
-    // z_j = (1/scale) sum_t m_t cos(pi (5^j t mod 2n)/n), double precision
-    void decode(const double *m, double scale, double *z, size_t nz) const;
-    uint32_t n() const { return n_; }
-
-private:
-    uint32_t n_;
-    std::vector<double> ch_, cl_, sh_, sl_;  // cos/sin(pi e / n), e < 2n, as double-double
-    std::vector<uint32_t> slot_root_;        // (5^j mod 2n - 1)/2, j < N
+// Tables of the slot encoder (the transforms run on the GPU): tw[4e .. 4e+3] =
+// cos(pi e / n) and sin(pi e / n) as double-double pairs (hi, lo, hi, lo), e < 2n,
+// from a double-double Taylor evaluation; root[j] = (5^j mod 2n - 1) / 2, j < n/2,
+// the FFT position of the root zeta^(5^j) that carries slot j.
+struct EncoderTables {
+    explicit EncoderTables(uint32_t logn);
+    std::vector<double> tw;
+    std::vector<uint32_t> root;
 };
 
 }  // namespace hec

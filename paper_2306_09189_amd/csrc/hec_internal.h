@@ -81,7 +81,9 @@ struct hec_ctx {
     u64 *d_gauss = nullptr;
     u64 *d_crt_m = nullptr, *d_crt_inv = nullptr, *d_crt_invsh = nullptr;  // Garner tables (q primes)
     std::vector<BconvDesc> h_modup, h_moddown;
-    std::unique_ptr<hec::Encoder> enc;
+    double4 *d_enc_tw = nullptr;     // encoder twiddles cos/sin(pi e/n) as double-double, e < 2n
+    u32 *d_enc_root = nullptr;       // FFT position of the root of each slot
+    int *d_flag = nullptr;           // device status word (encoder overflow)
     // keys
     bool have_keys = false;
     uint64_t key_seed = 0;

@@ -808,75 +808,170 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 // ModDown(E + P*A) = ModDown(E) + A exactly.  Products are summed into 128 bits
 // and reduced once: < (beta + 1) q^2 for the key switch and < HEC_KS_BATCH q^2
 // for the terms, both below q * 2^64 (checked at context creation).
-__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nterms, u32 nout, const u64 *D,
-                                                       const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap,
-                                                       const u64 *pm, u32 NLK, u32 first, u32 nchunks, DevTables T)
+//
+// Each lane takes two adjacent coefficients k, k+1 (k even) so that every
+// access is a 16-byte load: the automorphism maps the pair onto the pair
+// {src, src ^ 1} (k and k+1 differ in the top bit of brv(k), i.e. by n in the
+// exponent 2 brv(k) + 1, which g odd keeps at n: the source index flips its
+// lowest bit).  BETA and NOUT are compile-time so that all loads of a term
+// are issued together; terms [0, nz) are rotations by zero, the rest are not.
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+DEV u64x2 ld2(const u64 *p) { return *(const u64x2 *)p; }
+// streamed once (keys, plaintexts): non-temporal, so that they do not evict the
+// hoisted digits that every rotation of the launch re-reads from L2
+DEV u64x2 ld2_stream(const u64 *p) { return __builtin_nontemporal_load((const u64x2 *)p); }
+DEV void st2(u64 *p, u64x2 v) { *(u64x2 *)p = v; }
+
+template <int BETA, int NOUT>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, const u64 *D,
+                                                       const u64 *ct, u32 beta_rt, u32 nq, u32 nqp,
+                                                       const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
+                                                       u32 nchunks, DevTables T)
 {
     const u32 w = blockIdx.x, total = gridDim.x;
     const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
     const u32 chunk = i % nchunks, o = i / nchunks;
-    const u32 k = chunk * EW_THREADS + threadIdx.x;
+    const u32 k = 2 * (chunk * EW_THREADS + threadIdx.x);
     if (k >= T.n) return;
+    const u32 beta = BETA ? BETA : beta_rt;
     const size_t n = T.n;
     const u32 pi = pmap[o];
     const PrimeC pc = T.pc[pi];
     const bool isq = o < nq;
     const u64 pmo = isq ? pm[o] : 0;
-    acc128 acc[HEC_MAC_OUT][2];
+    acc128 acc[NOUT][2][2];  // [output][poly][coefficient]
 #pragma unroll
-    for (u32 v = 0; v < HEC_MAC_OUT; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
-    for (u32 t = 0; t < nterms; t++) {
-        const u32 g = b.g[t];
-        u64 e0, e1;
-        if (g == 1) {
-            if (!isq) continue;  // P * c vanishes modulo the special primes
-            e0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
-            e1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
-        } else {
-            const u32 src = auto_src(k, g, T.logn);
-            const u64 *key = b.key[t];
-            acc128 a0 = {0, 0}, a1 = {0, 0};
-            for (u32 j = 0; j < beta; j++) {
-                u64 d = D[((size_t)j * nqp + o) * n + src];
-                mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
-                mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+    for (int v = 0; v < NOUT; v++)
+#pragma unroll
+        for (int p = 0; p < 2; p++) acc[v][p][0] = acc[v][p][1] = acc128{0, 0};
+    // rotations by zero: P * (c0, c1)
+    if (isq)
+        for (u32 t = 0; t < nz; t++) {
+            const u64x2 c0 = ld2(ct + (size_t)o * n + k), c1 = ld2(ct + ((size_t)nq + o) * n + k);
+            const u64 e00 = mont_mul(c0.x, pmo, pc.q, pc.qinv_neg), e01 = mont_mul(c0.y, pmo, pc.q, pc.qinv_neg);
+            const u64 e10 = mont_mul(c1.x, pmo, pc.q, pc.qinv_neg), e11 = mont_mul(c1.y, pmo, pc.q, pc.qinv_neg);
+#pragma unroll
+            for (int v = 0; v < NOUT; v++) {
+                const u64 *pt = b.pt[t][v];
+                if (!pt) continue;
+                const u64x2 m = ld2(pt + (size_t)o * n + k);
+                mac(acc[v][0][0], e00, m.x);
+                mac(acc[v][0][1], e01, m.y);
+                mac(acc[v][1][0], e10, m.x);
+                mac(acc[v][1][1], e11, m.y);
             }
-            if (isq) mac(a0, ct[(size_t)o * n + src], pmo);
-            e0 = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
-            e1 = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
         }
+    for (u32 t = nz; t < nterms; t++) {
+        const u32 src = auto_src(k, b.g[t], T.logn);
+        const u32 sb = src & ~1u;
+        const bool sw = src & 1u;
+        const u64 *key = b.key[t];
+        // issue the loads of the input and plaintext limbs together with the key
+        // loads below (addresses always valid; unused values are ignored)
+        const u64x2 c = ld2(ct + (size_t)(isq ? o : 0) * n + sb);
+        u64x2 m[NOUT];
 #pragma unroll
-        for (u32 v = 0; v < HEC_MAC_OUT; v++) {
-            if (v >= nout) break;
+        for (int v = 0; v < NOUT; v++) {
             const u64 *pt = b.pt[t][v];
-            if (!pt) continue;
-            const u64 m = pt[(size_t)o * n + k];
-            mac(acc[v][0], e0, m);
-            mac(acc[v][1], e1, m);
+            m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
+        }
+        acc128 a00 = {0, 0}, a01 = {0, 0}, a10 = {0, 0}, a11 = {0, 0};  // [poly][coefficient]
+#pragma unroll
+        for (u32 j = 0; j < beta; j++) {
+            const u64x2 d = ld2(D + ((size_t)j * nqp + o) * n + sb);
+            const u64x2 kb = ld2_stream(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k);
+            const u64x2 ka = ld2_stream(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k);
+            const u64 d0 = sw ? d.y : d.x, d1 = sw ? d.x : d.y;
+            mac(a00, d0, kb.x);
+            mac(a01, d1, kb.y);
+            mac(a10, d0, ka.x);
+            mac(a11, d1, ka.y);
+        }
+        if (isq) {
+            mac(a00, sw ? c.y : c.x, pmo);
+            mac(a01, sw ? c.x : c.y, pmo);
+        }
+        const u64 e00 = redc(a00.hi, a00.lo, pc.q, pc.qinv_neg), e01 = redc(a01.hi, a01.lo, pc.q, pc.qinv_neg);
+        const u64 e10 = redc(a10.hi, a10.lo, pc.q, pc.qinv_neg), e11 = redc(a11.hi, a11.lo, pc.q, pc.qinv_neg);
+#pragma unroll
+        for (int v = 0; v < NOUT; v++) {
+            if (!b.pt[t][v]) continue;
+            mac(acc[v][0][0], e00, m[v].x);
+            mac(acc[v][0][1], e01, m[v].y);
+            mac(acc[v][1][0], e10, m[v].x);
+            mac(acc[v][1][1], e11, m[v].y);
         }
     }
 #pragma unroll
-    for (u32 v = 0; v < HEC_MAC_OUT; v++) {
-        if (v >= nout) break;
-        u64 r0 = redc(acc[v][0].hi, acc[v][0].lo, pc.q, pc.qinv_neg);
-        u64 r1 = redc(acc[v][1].hi, acc[v][1].lo, pc.q, pc.qinv_neg);
+    for (int v = 0; v < NOUT; v++) {
         u64 *E = b.E[v];
-        const size_t i0 = (size_t)o * n + k, i1 = ((size_t)nqp + o) * n + k;
-        if (!((first >> v) & 1)) {
-            r0 = add_mod(r0, E[i0], pc.q);
-            r1 = add_mod(r1, E[i1], pc.q);
+        if (!E) continue;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            u64 *dst = E + ((size_t)p * nqp + o) * n + k;
+            u64x2 r;
+            r.x = redc(acc[v][p][0].hi, acc[v][p][0].lo, pc.q, pc.qinv_neg);
+            r.y = redc(acc[v][p][1].hi, acc[v][p][1].lo, pc.q, pc.qinv_neg);
+            if (!((first >> v) & 1)) {
+                const u64x2 old = ld2(dst);
+                r.x = add_mod(r.x, old.x, pc.q);
+                r.y = add_mod(r.y, old.y, pc.q);
+            }
+            st2(dst, r);
         }
-        E[i0] = r0;
-        E[i1] = r1;
     }
 }
-void hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
+
+template <int BETA, int NOUT>
+static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
+                          const u64 *D, const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm,
+                          u32 NLK, u32 first, u32 nchunks, const DevTables &T)
+{
+    KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, D, ct, beta, nq,
+            nqp, pmap, pm, NLK, first, nchunks, T);
+}
+template <int NOUT>
+static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
+                        const u64 *D, const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm,
+                        u32 NLK, u32 first, u32 nchunks, const DevTables &T)
+{
+    switch (beta) {
+    case 1: ks_mac_launch<1, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
+    case 2: ks_mac_launch<2, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
+    case 3: ks_mac_launch<3, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
+    case 4: ks_mac_launch<4, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
+    default: ks_mac_launch<0, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    }
+}
+// Work unit of the profiler: one limb (n words) moved to or from HBM, counting
+// each key, plaintext and accumulator limb once and the hoisted digits and the
+// input ciphertext once per launch.
+bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
                 int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st)
 {
-    const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
+    if (nterms < 0 || nterms > HEC_KS_BATCH || nout < 1 || nout > HEC_MAC_OUT) return false;
+    u32 nz = 0;
+    while ((int)nz < nterms && b.g[nz] == 1) nz++;
+    for (int t = (int)nz; t < nterms; t++)
+        if (b.g[t] == 1 || !b.key[t] || !D) return false;  // zero rotations must come first
+    uint64_t units = (nterms > (int)nz ? (uint64_t)beta * nqp : 0) + (uint64_t)nq + (nz ? (uint64_t)nq : 0);
+    for (int t = 0; t < nterms; t++) {
+        if (t >= (int)nz) units += 2ull * beta * nqp;
+        for (int v = 0; v < nout; v++)
+            if (b.pt[t][v]) units += t >= (int)nz ? nqp : nq;
+    }
+    for (int v = 0; v < nout; v++) units += ((first >> v) & 1) ? 2ull * nqp : 4ull * nqp;
+    const u32 nchunks = (T.n / 2 + EW_THREADS - 1) / EW_THREADS;
     dim3 g(nchunks * (u32)nqp);
-    KLAUNCH("k_ks_mac", (uint64_t)nterms * nqp, k_ks_mac, g, dim3(EW_THREADS), 0, st, b, (u32)nterms, (u32)nout, D,
-            ct, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first, nchunks, T);
+    KsMacBatch bb = b;
+    for (int v = nout; v < HEC_MAC_OUT; v++) bb.E[v] = nullptr;
+    if (nout == 1)
+        ks_mac_beta<1>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    else if (nout == 2)
+        ks_mac_beta<2>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    else
+        ks_mac_beta<4>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    return true;
 }
 
 // ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)

@@ -993,6 +993,9 @@ static hec_status conv_accumulate_lazy(hec_ctx *c, const hec_conv_plan *p, const
                         terms.push_back(t);
                         break;
                     }
+            // rotations by zero first (the kernel takes them as a leading run)
+            std::stable_partition(terms.begin(), terms.end(),
+                                  [&](size_t t) { return c->galois(its[t].amount) == 1; });
             for (size_t b0 = 0; b0 < terms.size(); b0 += HEC_KS_BATCH) {
                 const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
                 KsMacBatch b{};
@@ -1020,8 +1023,12 @@ static hec_status conv_accumulate_lazy(hec_ctx *c, const hec_conv_plan *p, const
                         }
                 }
                 if (s != HEC_OK) break;
-                hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
-                           c->d_pmodq_m, (int)c->NLK, first, c->st);
+                if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
+                                c->d_pmodq_m, (int)c->NLK, first, c->st)) {
+                    s = HEC_EINVAL;
+                    hec_set_error("invalid key-switch batch");
+                    break;
+                }
             }
         }
         c->release(D);
