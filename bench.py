@@ -30,27 +30,38 @@ def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Dominant kernel of the step (largest share of GPU time in the rocprofv3
-# kernel trace): the row pass of the 2^16 forward NTT.  One work unit = one
-# 2^16-word limb, which takes 8 butterfly stages x 2^15 butterflies (one
-# modular multiplication each) and moves 2 x 512 KiB (read + write).
-DOMINANT = "k_ntt16_fwd_rows"
-MODMUL_PER_UNIT = 8 * (1 << 15)
-BYTES_PER_UNIT = 2 * (1 << 19)
-# ALU roof: 256 CUs x 64 VALU lanes x 2.4 GHz = 39.3 T lane-instructions/s
-# (the fp64 FMA rate, 78.6 TFLOP/s / 2; 64-bit integer multiply-add issues at
-# the same rate on gfx950); a 64-bit Shoup modular multiplication needs 10
-# integer multiply instructions -> 3.93 T modmul/s.
-PEAK_TMODMUL = 256 * 64 * 2.4e9 / 10 / 1e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")
+# Dominant kernel of the timed step (largest share of GPU time in a rocprofv3
+# kernel trace of this command), per plan mode.
+#  * lazy ModDown (mode 2): the fused key-switch + weight-product kernel
+#    k_ks_mac.  It streams the rotation keys and plaintexts once; its work unit
+#    is one limb (2^16 words = 512 KiB) moved to or from HBM, counting every key,
+#    plaintext and accumulator limb once and the hoisted digits and the input
+#    ciphertext once per launch.  Bound: HBM, 8 TB/s.
+#  * batched / plain (modes 0, 1): the row pass of the 2^16 forward NTT.  One
+#    unit = one limb, 8 butterfly stages x 2^15 butterflies (one modular
+#    multiplication each), 2 x 512 KiB moved.  Bound: the VALU.  256 CUs x 64
+#    lanes x 2.4 GHz = 39.3 T lane-instructions/s (the fp64 FMA rate, 78.6
+#    TFLOP/s / 2; 64-bit integer multiply-add issues at the same rate on gfx950);
+#    a 64-bit Shoup modular multiplication needs 10 integer multiply
+#    instructions -> 3.93 T modmul/s.
+LIMB_BYTES = 8 << LOGN
+KERNELS = {
+    "k_ks_mac": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
+                 "bytes_per_unit": LIMB_BYTES,
+                 "traffic_file": os.path.join(ROOT, "profiles", "ks_mac_2e16_traffic.txt")},
+    "k_ntt16_fwd_rows": {"bound": "alu", "unit": "Tmodmul/s", "peak": 256 * 64 * 2.4e9 / 10 / 1e12,
+                         "per_unit": 8 * (1 << 15) / 1e12, "bytes_per_unit": 2 * LIMB_BYTES,
+                         "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
+}
+DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac"}
 
 
-def read_traffic():
-    """key: value lines of the committed PMC summary (None if absent)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path):
+    """key: value lines of a committed PMC summary (None if absent)."""
+    if not os.path.exists(path):
         return None
     rec = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
@@ -63,21 +74,21 @@ def kernel_source_sha():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def dominant_roofline(launches, units, kms):
+def dominant_roofline(kernel, launches, units, kms):
     if not launches or kms <= 0:
         return None
+    spec = KERNELS[kernel]
     avg_units = units / launches
     avg_s = kms / launches * 1e-3
-    achieved = avg_units * MODMUL_PER_UNIT / avg_s / 1e12
+    achieved = avg_units * spec["per_unit"] / avg_s
     traffic = None
-    rec = read_traffic()
+    rec = read_traffic(spec["traffic_file"])
     if rec and rec.get("source_sha") == kernel_source_sha():
         traffic = (float(rec["fetch_bytes_per_unit"]) + float(rec["write_bytes_per_unit"])) * avg_units
-    return {"bound": "alu", "kernel": DOMINANT, "achieved": achieved, "peak": PEAK_TMODMUL, "unit": "Tmodmul/s",
-            "frac": achieved / PEAK_TMODMUL, "traffic": traffic,
+    return {"bound": spec["bound"], "kernel": kernel, "achieved": achieved, "peak": spec["peak"],
+            "unit": spec["unit"], "frac": achieved / spec["peak"], "traffic": traffic,
             "avg_launch_us": avg_s * 1e6, "launches": launches, "avg_units_per_launch": avg_units,
-            "hbm_equiv_GBps": avg_units * BYTES_PER_UNIT / avg_s / 1e9,
-            "algorithmic_bytes_per_launch": avg_units * BYTES_PER_UNIT}
+            "algorithmic_bytes_per_launch": avg_units * spec["bytes_per_unit"]}
 
 
 def rotations_per_step():
@@ -86,31 +97,57 @@ def rotations_per_step():
     return 287 + 287 + 2 * 30 + 1 + 1
 
 
-def cpu_baseline(n_rot, seconds):
+def cpu_baseline(n_rot, seconds, mode):
     """The CPU oracle (plain C, __int128 arithmetic, OpenMP over limbs) on a
-    bounded sample: batches of n_rot hoisted key-switched rotations of one
-    level-20 ciphertext of the same ring, repeated until `seconds` of CPU work;
-    keys generated outside the timed part."""
+    bounded sample of the same work as the timed step, repeated until `seconds`
+    of CPU work; keys and weight plaintexts prepared outside the timed part.
+    Modes 0/1: batches of n_rot hoisted key-switched rotations of one level-20
+    ciphertext, each multiplied by a weight plaintext and summed.  Mode 2 (lazy
+    ModDown): the key-switch products of n_rot rotations multiplied by the
+    weights over Q*P, summed, and one ModDown."""
     from oracle import ckks
     prm = ckks.Params(LOGN, [Q0] + [QB] * L, [PB] * K, DNUM)
     o = ckks.Oracle(prm, 2002)
     steps = list(range(1, n_rot + 1))
     for s in steps:
         o.swk(prm.galois(s))
-    z = np.random.default_rng(0).uniform(-1, 1, prm.N)
-    ct = o.encrypt(o.encode(z, LEVEL, 2.0 ** LOG_SCALE), seed=1)
+    rng = np.random.default_rng(0)
+    ct = o.encrypt(o.encode(rng.uniform(-1, 1, prm.N), LEVEL, 2.0 ** LOG_SCALE), seed=1)
+    qlev = float(prm.q[LEVEL])
+    ms = [o.encode_coeffs(rng.normal(0, 0.05, prm.N), qlev) for _ in steps]
+    qi, qpi = list(range(LEVEL + 1)), o.qp_index(LEVEL)
+    if mode == 2:
+        pts = [o.limbs_qp(m, LEVEL) for m in ms]
+
+        def work():
+            acc = None
+            for e, pt in zip(o.keyswitch_raw(ct, steps), pts):
+                prod = np.stack([o.mul_limbs(qpi, pt, e[p]) for p in range(2)])
+                acc = prod if acc is None else np.stack([o.add_limbs(qpi, acc[p], prod[p]) for p in range(2)])
+            return [o.moddown(LEVEL, acc[p]) for p in range(2)]
+        what = "lazy-ModDown key-switch products x weights summed over Q*P, one ModDown"
+    else:
+        pts = [o.limbs_of(m, LEVEL) for m in ms]
+
+        def work():
+            acc = None
+            for r, pt in zip(o.rotate_hoisted(ct, steps), pts):
+                prod = np.stack([o.mul_limbs(qi, pt, r.data[p]) for p in range(2)])
+                acc = prod if acc is None else np.stack([o.add_limbs(qi, acc[p], prod[p]) for p in range(2)])
+            return acc
+        what = "hoisted key-switched rotations x weights summed"
     t = time.perf_counter()
     reps = 0
     while True:
-        o.rotate_hoisted(ct, steps)
+        work()
         reps += 1
         dt = time.perf_counter() - t
         if dt >= seconds:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": reps * n_rot / dt, "unit": "key-switched rotations/s", "cores": cores, "kind": "oracle",
-            "sample": "%d x %d hoisted key-switched rotations of one level-20 ciphertext, 2N=2^16, dnum=3, "
-                      "OpenMP over limbs (%.1f s)" % (reps, n_rot, dt)}
+            "sample": "%d x %d rotations of one level-20 ciphertext (%s), 2N=2^16, dnum=3, OpenMP over limbs "
+                      "(%.1f s)" % (reps, n_rot, what, dt)}
 
 
 def main():
@@ -122,7 +159,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=2)
-    ap.add_argument("--mode", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--mode", type=int, default=2, choices=(0, 1, 2),
                     help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
     args = ap.parse_args()
@@ -191,8 +228,9 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # the dominant kernel is timed launch by launch with HIP events on the
     # library's stream during the timed steps
-    ctx.prof_start(DOMINANT)
-    first_launch = ctx.prof_launches(DOMINANT)
+    dom = DOMINANT[args.mode]
+    ctx.prof_start(dom)
+    first_launch = ctx.prof_launches(dom)
     t = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -203,12 +241,14 @@ def main():
     launches, units, kms = ctx.prof_stop()
     ms_step = wall * 1e3 / args.steps
     value = rotations_per_step() * args.steps / wall
-    roofline = dominant_roofline(launches, units, kms)
+    roofline = dominant_roofline(dom, launches, units, kms)
     if roofline:
         # dispatch range of the timed region in a kernel trace of this same command
         roofline["trace_dispatch_range"] = [first_launch, first_launch + launches]
 
-    # conv-layer latency: batched (hoisted ModUp, 16 rotations per key-switch launch) vs plain
+    # conv-layer latency (conv 3x3 32->32) in each plan mode: batched (hoisted
+    # ModUp, 16 rotations per key-switch launch), plain (one launch chain per
+    # rotation) and lazy ModDown (key switch fused with the weight products)
     def conv_ms(mode, reps):
         p1.set_mode(mode)
         im = ctx.image_encrypt(x, LEVEL, 3002)
@@ -220,27 +260,12 @@ def main():
             ctx.sync()
             ts.append((time.perf_counter() - s) * 1e3)
             del o
-        p1.set_mode(0)
+        p1.set_mode(args.mode)
         return float(np.median(ts))
 
     conv_b = conv_ms(0, 5)
     conv_p = conv_ms(1, max(1, args.plain_reps))
     conv_l = conv_ms(2, 5)
-
-    # the whole step with lazy ModDown in both convolutions (same rotations,
-    # one ModDown per output shard)
-    p1.set_mode(2)
-    p2.set_mode(2)
-    step()
-    err_lazy = step(check=True)
-    torch.cuda.synchronize()
-    s = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_lazy = (time.perf_counter() - s) * 1e3 / args.steps
-    p1.set_mode(0)
-    p2.set_mode(0)
 
     # isolated rotations at level 20
     ctx.gen_rotation_keys(list(range(1, 33)))
@@ -279,9 +304,7 @@ def main():
         "conv_layer_ms_batched": conv_b,
         "conv_layer_ms_plain": conv_p,
         "conv_layer_ms_lazy_moddown": conv_l,
-        "ms_per_step_lazy_moddown": ms_lazy,
-        "rot_per_s_lazy_moddown": rotations_per_step() * 1e3 / ms_lazy,
-        "max_abs_err_lazy_moddown": err_lazy,
+        "plan_mode": {0: "batched", 1: "plain", 2: "lazy_moddown"}[args.mode],
         "rot_per_s_hoisted_level20": rot_hoisted,
         "rot_per_s_single_level20": rot_single,
         "max_abs_err_vs_fp64": err,
@@ -289,7 +312,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_rotations, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rotations, args.cpu_seconds, args.mode)
     print(json.dumps(out), flush=True)
 
 
