@@ -197,6 +197,14 @@ void he_conv2d_plan_free(hec_conv_plan *plan);
  * duplicate when at most two shards were downsampled.  window must be 2.
  * Consumes two levels, or one when only one is left (reductions fused). */
 hec_status he_avgpool(hec_ctx *ctx, const hec_image *in, uint32_t window, hec_image **out);
+/* The same with an evaluation mode: 0 = as he_avgpool (every rotation of the
+ * reductions key-switched and ModDown'd on its own); 2 = lazy ModDown (the
+ * masked rotation sums of the reductions multiply the key-switch products
+ * over Q_l and P and take one ModDown per sum -- an optimisation the paper
+ * does not describe; other ciphertext bits, same values within the same
+ * bound).  Other modes: HEC_EINVAL.  Plans in mode 2 use it for their
+ * stride-2 downsampling. */
+hec_status he_avgpool_ex(hec_ctx *ctx, const hec_image *in, uint32_t window, int mode, hec_image **out);
 
 void hec_ct_free(hec_ct *ct);
 void hec_pt_free(hec_pt *pt);

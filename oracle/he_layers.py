@@ -343,17 +343,20 @@ def conv_plan_channel(lay, w, pad):
     return out, plan
 
 
-def _accumulate_lazy(be, cts, nout, plan):
+def _accumulate_lazy(be, cts, nout, plan, pscale=None, rescale=True):
     """Lazy ModDown: every output shard v is
         (A0 + ModDown(E0), A1 + ModDown(E1)),
     E_p = sum over the nonzero rotations of pt * e_p (the key-switch product
     over Q and P, before ModDown), A0 = sum pt * sigma_g(c0) over those
     rotations plus pt * c0 over zero rotations, A1 = sum pt * c1 over zero
     rotations.  Same rotations and plaintexts as the per-rotation form; one
-    ModDown per output shard instead of one per rotation."""
+    ModDown per output shard instead of one per rotation.  Plaintexts are
+    encoded at pscale (default q_level); rescale=False returns the sums."""
     o = be.o
     p = o.p
     lvl = cts[0].level
+    if pscale is None:
+        pscale = be.q(lvl)
     nq = lvl + 1
     qi, qpi = list(range(nq)), o.qp_index(lvl)
     nqp = len(qpi)
@@ -369,10 +372,10 @@ def _accumulate_lazy(be, cts, nout, plan):
         for e, (a, pts) in zip(ks, items):
             g = p.galois(a)
             for v, vec in pts.items():
-                m = o.encode_coeffs(vec, be.q(lvl))
+                m = o.encode_coeffs(vec, pscale)
                 ptq = o.limbs_of(m, lvl)
                 used[v] = True
-                scale = ct.scale * be.q(lvl)
+                scale = ct.scale * pscale
                 if e is None:
                     for poly in range(2):
                         A[v][poly] = o.add_limbs(qi, A[v][poly], o.mul_limbs(qi, ptq, ct.data[poly]))
@@ -388,8 +391,21 @@ def _accumulate_lazy(be, cts, nout, plan):
             raise ValueError("output shard without products")
         data = np.stack([o.add_limbs(qi, A[v][poly], o.moddown(lvl, E[v][poly])) for poly in range(2)])
         from .ckks import Ct
-        outs.append(be.rescale(Ct(data, lvl, scale)))
+        ct = Ct(data, lvl, scale)
+        outs.append(be.rescale(ct) if rescale else ct)
     return outs
+
+
+def _rot_masked_sums(be, ct, steps, masks, pscale, lazy=False):
+    """Per output o: sum_t masks[o][t] * rot(ct, steps[t]) over the hoisted
+    rotations of one ciphertext, not rescaled.  lazy (encrypted backend):
+    the products are taken on the key-switch outputs over Q*P and each output
+    takes one ModDown."""
+    if lazy and isinstance(be, CkksBackend):
+        plan = [[(a, {o: m[t] for o, m in enumerate(masks)}) for t, a in enumerate(steps)]]
+        return _accumulate_lazy(be, [ct], len(masks), plan, pscale=pscale, rescale=False)
+    rots = be.rotate_hoisted(ct, steps)
+    return [_sum(be, [be.mul_plain(rots[t], m[t], pscale) for t in range(len(steps))]) for m in masks]
 
 
 def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False):
@@ -408,7 +424,7 @@ def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False):
             return outs, out_lay
         if stride != 2:
             raise ValueError("stride must be 1 or 2")
-        return downsample_and_merge(be, outs, out_lay, select=True)
+        return downsample_and_merge(be, outs, out_lay, select=True, lazy=True)
     acc = [[] for _ in out_lay.shards]
     for u, items in enumerate(plan):
         if not items:
@@ -463,7 +479,7 @@ def _per_block(lay, blk, lam=None):
     return v
 
 
-def downsample(be, cts, lay, select=False, fused=None):
+def downsample(be, cts, lay, select=False, fused=None, lazy=False):
     """Per-shard downsample: (pool) 2x2 window sums, then horizontal and
     vertical reduction; (select) the reductions alone keep the top-left element
     of every 2x2 window (strided convolution).  Returns the shards with an
@@ -489,21 +505,20 @@ def downsample(be, cts, lay, select=False, fused=None):
             D = _sum(be, [ct] + r)
         else:
             D = ct
-        rots = be.rotate_hoisted(D, list(range(Wo)))
+        hs = list(range(Wo))
         if use_fused:
             ps = be.q(lvl) / 4.0
-            T = [_sum(be, [be.mul_plain(rots[i], _fmask(lay, i, j, val), ps) for i in range(Wo)])
-                 for j in range(Ho)]
+            T = _rot_masked_sums(be, D, hs, [[_fmask(lay, i, j, val) for i in hs] for j in range(Ho)], ps, lazy)
             moved = [T[0]] + [be.rotate(T[j], 3 * j * mp // 2) for j in range(1, Ho)]
             outs.append(be.rescale(_sum(be, moved)))
         else:
-            M1 = be.rescale(_sum(be, [be.mul_plain(rots[i], _hmask(lay, i, val), be.q(lvl)) for i in range(Wo)]))
+            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[_hmask(lay, i, val) for i in hs]], be.q(lvl), lazy)[0])
             lvl1 = be.level(M1)
             if lvl1 < 1:
                 raise ValueError("separable pooling needs two levels")
-            rots2 = be.rotate_hoisted(M1, [3 * j * mp // 2 for j in range(Ho)])
-            outs.append(be.rescale(_sum(be, [be.mul_plain(rots2[j], _vmask(lay, j, Wo), be.q(lvl1))
-                                             for j in range(Ho)])))
+            vs = [3 * j * mp // 2 for j in range(Ho)]
+            outs.append(be.rescale(_rot_masked_sums(be, M1, vs, [[_vmask(lay, j, Wo) for j in range(Ho)]],
+                                                    be.q(lvl1), lazy)[0]))
     nl = Layout(lay.N, lay.C, Ho, Wo, mp // 2, "image",
                 [[s[b // 4] if b % 4 == 0 else -1 for b in range(4 * lay.nb)] for s in lay.shards])
     return outs, nl
@@ -549,7 +564,7 @@ def duplicate(be, ct, lay, d):
     return out, Layout(lay.N, lay.C, lay.H, lay.W, lay.mp, "image", [lam])
 
 
-def downsample_channel(be, cts, lay, select=False, fused=None):
+def downsample_channel(be, cts, lay, select=False, fused=None, lazy=False):
     """Channel shards are downsampled individually (Section 4.2, "With Channel
     Shards"): 2x2 sums stay inside a shard (R is even), column 2i of the even
     valid rows goes to column i, the left half of local row 2j to j*mp/2."""
@@ -580,7 +595,7 @@ def downsample_channel(be, cts, lay, select=False, fused=None):
             D = _sum(be, [ct] + be.rotate_hoisted(ct, [1, mp, mp + 1]))
         else:
             D = ct
-        rots = be.rotate_hoisted(D, list(range(Wo)))
+        hs = list(range(Wo))
 
         def hmask(i):
             blk = np.zeros((R, mp))
@@ -599,18 +614,17 @@ def downsample_channel(be, cts, lay, select=False, fused=None):
 
         if use_fused:
             ps = be.q(lvl) / 4.0
-            T = [_sum(be, [be.mul_plain(rots[i], fmask(i, j), ps) for i in range(Wo)]) for j in js]
+            T = _rot_masked_sums(be, D, hs, [[fmask(i, j) for i in hs] for j in js], ps, lazy)
             moved = [T[0] if js[0] == 0 else be.rotate(T[0], 3 * js[0] * mp // 2)] + \
                     [be.rotate(T[t], 3 * j * mp // 2) for t, j in enumerate(js) if t > 0]
             outs.append(be.rescale(_sum(be, moved)))
         else:
-            M1 = be.rescale(_sum(be, [be.mul_plain(rots[i], hmask(i), be.q(lvl)) for i in range(Wo)]))
+            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[hmask(i) for i in hs]], be.q(lvl), lazy)[0])
             lvl1 = be.level(M1)
             if lvl1 < 1:
                 raise ValueError("separable pooling needs two levels")
-            rots2 = be.rotate_hoisted(M1, [3 * j * mp // 2 for j in js])
-            outs.append(be.rescale(_sum(be, [be.mul_plain(rots2[t], vmask(j), be.q(lvl1))
-                                             for t, j in enumerate(js)])))
+            vs = [3 * j * mp // 2 for j in js]
+            outs.append(be.rescale(_rot_masked_sums(be, M1, vs, [[vmask(j) for j in js]], be.q(lvl1), lazy)[0]))
     return outs
 
 
@@ -648,15 +662,17 @@ def merge_channel(be, outs, lay, H2, W2):
     return res, out
 
 
-def downsample_and_merge(be, cts, lay, select=False, fused=None):
+def downsample_and_merge(be, cts, lay, select=False, fused=None, lazy=False):
+    """Downsample every shard, then consolidate and duplicate (Section 4.2);
+    lazy: the masked rotation sums of the downsampling take one ModDown each."""
     if lay.kind == "channel":
-        outs = downsample_channel(be, cts, lay, select=select, fused=fused)
+        outs = downsample_channel(be, cts, lay, select=select, fused=fused, lazy=lazy)
         if select:
             H2, W2 = (lay.H + 1) // 2, (lay.W + 1) // 2
         else:
             H2, W2 = lay.H // 2, lay.W // 2
         return merge_channel(be, outs, lay, H2, W2)
-    outs, nl = downsample(be, cts, lay, select=select, fused=fused)
+    outs, nl = downsample(be, cts, lay, select=select, fused=fused, lazy=lazy)
     t = len(outs)
     if t == 1:
         o, l2 = duplicate(be, outs[0], nl, 4)
@@ -668,10 +684,10 @@ def downsample_and_merge(be, cts, lay, select=False, fused=None):
     return outs, nl
 
 
-def avgpool2x2(be, cts, lay, fused=None):
+def avgpool2x2(be, cts, lay, fused=None, lazy=False):
     """2x2 average pooling: downsample, consolidate, duplicate (Section 4.2),
-    for image shards and channel shards."""
-    return downsample_and_merge(be, cts, lay, select=False, fused=fused)
+    for image shards and channel shards; lazy as in downsample_and_merge."""
+    return downsample_and_merge(be, cts, lay, select=False, fused=fused, lazy=lazy)
 
 
 # ---------------------------------------------------------------------------

@@ -440,6 +440,13 @@ static std::string layout_key(const Layout &L, int part)
     return s.str();
 }
 
+// one rotation of a ciphertext and the plaintexts its result is multiplied by,
+// per output (index, plaintext)
+struct RotTerm {
+    int32_t amount = 0;
+    std::vector<std::pair<uint32_t, hec_pt *>> pts;
+};
+
 // cached mask plaintexts (they only depend on the layout, shard part, index, level and scale)
 static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::vector<std::pair<uint32_t, uint32_t>> &ij,
                             uint32_t Wo, double val, uint32_t level, double scale, std::vector<hec_pt *> &out,
@@ -464,7 +471,7 @@ static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::v
     for (size_t t : miss) vecs.push_back(pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val, part));
     for (auto &v : vecs) zp.push_back(v.data());
     std::vector<hec_pt *> pts;
-    HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts));
+    HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts, true));
     for (size_t a = 0; a < miss.size(); a++) {
         c->mask_cache[keys[miss[a]]] = pts[a];
         out[miss[a]] = pts[a];
@@ -511,15 +518,214 @@ static hec_status masked_sum(hec_ctx *c, const std::vector<hec_ct *> &rots, cons
     return HEC_OK;
 }
 
+// Lazy ModDown: the key-switch products of every rotation are multiplied by
+// their plaintexts and summed over Q_l and P; each output then takes one
+// ModDown (instead of one per rotation).  Rotations by zero enter as P * pt * ct.
+// out[v] (allocated here, at the inputs' level, not rescaled) = sum over input
+// u and its terms of pt * rot(in[u], amount).  Plaintexts carry the limbs of
+// the special primes.
+static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> &in,
+                                  const std::vector<std::vector<RotTerm>> &terms_of, size_t nout,
+                                  std::vector<hec_ct *> &out)
+{
+    out.assign(nout, nullptr);
+    if (in.empty() || in.size() != terms_of.size()) HEC_FAIL(HEC_EINVAL, "lazy sum: inputs and terms differ");
+    const size_t n = c->n;
+    const uint32_t lvl = in[0]->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    for (auto *ct : in)
+        if (ct->level != lvl) HEC_FAIL(HEC_ELEVEL, "lazy sum over inputs at different levels");
+    std::vector<u64 *> E(nout, nullptr);
+    std::vector<char> used(nout, 0), fresh(nout, 1);
+    hec_status s = HEC_OK;
+    for (size_t v = 0; v < nout && s == HEC_OK; v++)
+        if (!(E[v] = c->alloc(2 * (size_t)nqp * n))) s = HEC_ENOMEM, hec_set_error("accumulator allocation");
+    double scale = 1.0;
+    for (size_t u = 0; u < in.size() && s == HEC_OK; u++) {
+        const auto &its = terms_of[u];
+        if (its.empty()) continue;
+        const hec_ct *ct = in[u];
+        bool rot = false;
+        for (auto &it : its) {
+            const uint32_t g = c->galois(it.amount);
+            if (g != 1 && !c->rotkeys.count(g)) {
+                s = HEC_ENOKEY;
+                hec_set_error("no rotation key for step %d", it.amount);
+            }
+            rot |= g != 1;
+        }
+        if (s != HEC_OK) break;
+        u64 *D = nullptr;
+        if (rot && (s = ct_modup(c, ct, &D)) != HEC_OK) break;
+        for (size_t v0 = 0; v0 < nout && s == HEC_OK; v0 += HEC_MAC_OUT) {
+            const size_t nv = std::min((size_t)HEC_MAC_OUT, nout - v0);
+            // the terms of this input with a product for an output of the group
+            std::vector<size_t> terms;
+            for (size_t t = 0; t < its.size(); t++)
+                for (auto &pp : its[t].pts)
+                    if (pp.first >= v0 && pp.first < v0 + nv) {
+                        terms.push_back(t);
+                        break;
+                    }
+            // rotations by zero first (the kernel takes them as a leading run)
+            std::stable_partition(terms.begin(), terms.end(),
+                                  [&](size_t t) { return c->galois(its[t].amount) == 1; });
+            for (size_t b0 = 0; b0 < terms.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
+                const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
+                KsMacBatch b{};
+                int first = 0;
+                for (size_t j = 0; j < nv; j++) {
+                    b.E[j] = E[v0 + j];
+                    if (fresh[v0 + j]) first |= 1 << j;
+                    fresh[v0 + j] = 0;
+                }
+                for (size_t t = 0; t < nt && s == HEC_OK; t++) {
+                    const auto &it = its[terms[b0 + t]];
+                    const uint32_t g = c->galois(it.amount);
+                    b.g[t] = g;
+                    b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
+                    for (auto &pp : it.pts) {
+                        if (pp.first < v0 || pp.first >= v0 + nv) continue;
+                        if (!pp.second->has_p || pp.second->level != lvl) {
+                            s = HEC_EINVAL;
+                            hec_set_error("plaintexts of a lazy sum need the special-prime limbs at the level");
+                            break;
+                        }
+                        b.pt[t][pp.first - v0] = pp.second->d;
+                        used[pp.first] = 1;
+                        scale = ct->scale * pp.second->scale;
+                    }
+                }
+                if (s != HEC_OK) break;
+                if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
+                                c->d_pmodq_m, (int)c->NLK, first, c->st)) {
+                    s = HEC_EINVAL;
+                    hec_set_error("invalid key-switch batch");
+                }
+            }
+        }
+        c->release(D);
+    }
+    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+        if (!used[v]) {
+            s = HEC_ELAYOUT;
+            hec_set_error("output shard %zu received no product", v);
+            break;
+        }
+        if (!(out[v] = ct_new(c, lvl, scale))) {
+            s = HEC_ENOMEM;
+            hec_set_error("ciphertext allocation");
+            break;
+        }
+        s = ct_moddown(c, lvl, E[v], out[v]);
+    }
+    for (auto *e : E) c->release(e);
+    if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("lazy accumulation launch");
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
+// out[o] (not rescaled) = sum_t masks[o][t] * rot(ct, steps[t]): hoisted
+// rotations then plaintext products, or (lazy) the same products taken on the
+// key-switch outputs with one ModDown per output
+static hec_status rot_masked_sums(hec_ctx *c, const hec_ct *ct, const std::vector<int32_t> &steps,
+                                  const std::vector<std::vector<hec_pt *>> &masks, bool lazy,
+                                  std::vector<hec_ct *> &out)
+{
+    out.clear();
+    if (lazy) {
+        std::vector<std::vector<RotTerm>> terms(1);
+        for (size_t t = 0; t < steps.size(); t++) {
+            RotTerm rt;
+            rt.amount = steps[t];
+            for (size_t o = 0; o < masks.size(); o++) rt.pts.push_back({(uint32_t)o, masks[o][t]});
+            terms[0].push_back(std::move(rt));
+        }
+        return lazy_rotate_mac(c, {ct}, terms, masks.size(), out);
+    }
+    std::vector<hec_ct *> rots;
+    HEC_CHECK(rotate_list(c, ct, steps, rots));
+    hec_status s = HEC_OK;
+    for (size_t o = 0; o < masks.size() && s == HEC_OK; o++) {
+        hec_ct *acc = nullptr;
+        s = masked_sum(c, rots, masks[o], &acc);
+        if (s == HEC_OK) out.push_back(acc);
+    }
+    free_all(rots);
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // downsample / consolidate / duplicate
 // ---------------------------------------------------------------------------
-struct PoolSteps {
-    std::set<int32_t> steps;
-};
+// Reduction of one shard after its 2x2 sums D (Section 4.2): column 2i of the
+// kept rows to column i (hs = 0..Wo-1), then row 2j to row j (js, shifts
+// 3j*mp/2), each a masked sum of hoisted rotations and a rescale; fused (one
+// level left) takes both in one masked sum per row at scale q/4.  `part` >= 0
+// selects the masks of a channel shard.
+static hec_status pool_reduce(hec_ctx *c, const hec_ct *D, const Layout &L, const std::vector<int32_t> &hs,
+                              const std::vector<uint32_t> &js, uint32_t Wo, double val, uint32_t lvl, bool fused,
+                              bool lazy, int part, hec_ct **out)
+{
+    *out = nullptr;
+    const uint32_t mp = L.mp;
+    if (fused) {
+        std::vector<std::vector<hec_pt *>> masks(js.size());
+        for (size_t t = 0; t < js.size(); t++) {
+            std::vector<std::pair<uint32_t, uint32_t>> ij;
+            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, js[t]});
+            HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, (double)c->mod[lvl] / 4.0, masks[t], part));
+        }
+        std::vector<hec_ct *> T;
+        HEC_CHECK(rot_masked_sums(c, D, hs, masks, lazy, T));
+        hec_ct *acc = nullptr;
+        hec_status s = HEC_OK;
+        for (size_t t = 0; t < js.size(); t++) {
+            hec_ct *x = T[t];
+            T[t] = nullptr;
+            if (s == HEC_OK && js[t] > 0) {
+                hec_ct *m = nullptr;
+                s = ckks_rotate(c, x, (int32_t)(3 * js[t] * mp / 2), &m);
+                ct_free(x);
+                x = m;
+            }
+            if (s == HEC_OK) s = sum_into(c, acc, x);
+            else ct_free(x);
+        }
+        if (s == HEC_OK) s = ct_rescale(c, acc);
+        if (s != HEC_OK) { ct_free(acc); return s; }
+        *out = acc;
+        return HEC_OK;
+    }
+    std::vector<std::vector<hec_pt *>> hm(1), vm(1);
+    std::vector<std::pair<uint32_t, uint32_t>> ij, jj;
+    for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
+    HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], hm[0], part));
+    std::vector<hec_ct *> M1;
+    HEC_CHECK(rot_masked_sums(c, D, hs, hm, lazy, M1));
+    hec_status s = ct_rescale(c, M1[0]);
+    if (s == HEC_OK && M1[0]->level < 1) s = HEC_ELEVEL, hec_set_error("separable pooling needs two levels");
+    if (s != HEC_OK) { free_all(M1); return s; }
+    const uint32_t l1 = M1[0]->level;
+    std::vector<int32_t> vs;
+    for (uint32_t j : js) {
+        vs.push_back((int32_t)(3 * j * mp / 2));
+        jj.push_back({0, j});
+    }
+    s = get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], vm[0], part);
+    std::vector<hec_ct *> M2;
+    if (s == HEC_OK) s = rot_masked_sums(c, M1[0], vs, vm, lazy, M2);
+    free_all(M1);
+    HEC_CHECK(s);
+    s = ct_rescale(c, M2[0]);
+    if (s != HEC_OK) { free_all(M2); return s; }
+    *out = M2[0];
+    return HEC_OK;
+}
 
 static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                             std::vector<hec_ct *> &out, Layout &nl)
+                             bool lazy, std::vector<hec_ct *> &out, Layout &nl)
 {
     const uint32_t mp = L.mp;
     uint32_t Ho, Wo;
@@ -546,59 +752,13 @@ static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const 
         }
         std::vector<int32_t> hs;
         for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
-        std::vector<hec_ct *> rots;
-        hec_status s = rotate_list(c, D, hs, rots);
+        std::vector<uint32_t> js;
+        for (uint32_t j = 0; j < Ho; j++) js.push_back(j);
+        hec_ct *o = nullptr;
+        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, lazy, -1, &o);
         ct_free(D);
         HEC_CHECK(s);
-        if (fused) {
-            const double ps = (double)c->mod[lvl] / 4.0;
-            hec_ct *acc = nullptr;
-            for (uint32_t j = 0; j < Ho; j++) {
-                std::vector<std::pair<uint32_t, uint32_t>> ij;
-                for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, j});
-                std::vector<hec_pt *> pts;
-                HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, ps, pts));
-                hec_ct *T = nullptr;
-                HEC_CHECK(masked_sum(c, rots, pts, &T));
-                if (j > 0) {
-                    hec_ct *m = nullptr;
-                    int32_t st = (int32_t)(3 * j * mp / 2);
-                    s = ckks_rotate(c, T, st, &m);
-                    ct_free(T);
-                    HEC_CHECK(s);
-                    T = m;
-                }
-                HEC_CHECK(sum_into(c, acc, T));
-            }
-            free_all(rots);
-            HEC_CHECK(ct_rescale(c, acc));
-            out.push_back(acc);
-        } else {
-            std::vector<std::pair<uint32_t, uint32_t>> ij;
-            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
-            std::vector<hec_pt *> pts;
-            HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], pts));
-            hec_ct *M1 = nullptr;
-            HEC_CHECK(masked_sum(c, rots, pts, &M1));
-            free_all(rots);
-            HEC_CHECK(ct_rescale(c, M1));
-            const uint32_t l1 = M1->level;
-            if (l1 < 1) { ct_free(M1); HEC_FAIL(HEC_ELEVEL, "separable pooling needs two levels"); }
-            std::vector<int32_t> vs;
-            for (uint32_t j = 0; j < Ho; j++) vs.push_back((int32_t)(3 * j * mp / 2));
-            std::vector<hec_ct *> r2;
-            s = rotate_list(c, M1, vs, r2);
-            ct_free(M1);
-            HEC_CHECK(s);
-            std::vector<std::pair<uint32_t, uint32_t>> jj;
-            for (uint32_t j = 0; j < Ho; j++) jj.push_back({0, j});
-            HEC_CHECK(get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], pts));
-            hec_ct *M2 = nullptr;
-            HEC_CHECK(masked_sum(c, r2, pts, &M2));
-            free_all(r2);
-            HEC_CHECK(ct_rescale(c, M2));
-            out.push_back(M2);
-        }
+        out.push_back(o);
     }
     nl = Layout();
     nl.N = L.N; nl.C = L.C; nl.H = Ho; nl.W = Wo; nl.mp = mp / 2;
@@ -634,7 +794,7 @@ static hec_status duplicate(hec_ctx *c, hec_ct *ct, Layout &L, uint32_t d, hec_c
 // rows that belong to the channel goes to column i, the left half of local row
 // 2j to j*mp/2.  A shard below the channel's last row pools to zero.
 static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                     std::vector<hec_ct *> &out)
+                                     bool lazy, std::vector<hec_ct *> &out)
 {
     const uint32_t mp = L.mp, R = L.R();
     uint32_t Wo;
@@ -683,55 +843,11 @@ static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in
         }
         std::vector<int32_t> hs;
         for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
-        std::vector<hec_ct *> rots;
-        hec_status s = rotate_list(c, D, hs, rots);
+        hec_ct *o = nullptr;
+        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, lazy, part, &o);
         ct_free(D);
         HEC_CHECK(s);
-        if (fused) {
-            hec_ct *acc = nullptr;
-            for (uint32_t j : js) {
-                std::vector<std::pair<uint32_t, uint32_t>> ij;
-                for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, j});
-                HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, (double)c->mod[lvl] / 4.0, pts, part));
-                hec_ct *T = nullptr;
-                HEC_CHECK(masked_sum(c, rots, pts, &T));
-                if (j > 0) {
-                    hec_ct *m = nullptr;
-                    s = ckks_rotate(c, T, (int32_t)(3 * j * mp / 2), &m);
-                    ct_free(T);
-                    HEC_CHECK(s);
-                    T = m;
-                }
-                HEC_CHECK(sum_into(c, acc, T));
-            }
-            free_all(rots);
-            HEC_CHECK(ct_rescale(c, acc));
-            out.push_back(acc);
-        } else {
-            std::vector<std::pair<uint32_t, uint32_t>> ij;
-            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
-            HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], pts, part));
-            hec_ct *M1 = nullptr;
-            HEC_CHECK(masked_sum(c, rots, pts, &M1));
-            free_all(rots);
-            HEC_CHECK(ct_rescale(c, M1));
-            const uint32_t l1 = M1->level;
-            if (l1 < 1) { ct_free(M1); HEC_FAIL(HEC_ELEVEL, "separable pooling needs two levels"); }
-            std::vector<int32_t> vs;
-            for (uint32_t j : js) vs.push_back((int32_t)(3 * j * mp / 2));
-            std::vector<hec_ct *> r2;
-            s = rotate_list(c, M1, vs, r2);
-            ct_free(M1);
-            HEC_CHECK(s);
-            std::vector<std::pair<uint32_t, uint32_t>> jj;
-            for (uint32_t j : js) jj.push_back({0, j});
-            HEC_CHECK(get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], pts, part));
-            hec_ct *M2 = nullptr;
-            HEC_CHECK(masked_sum(c, r2, pts, &M2));
-            free_all(r2);
-            HEC_CHECK(ct_rescale(c, M2));
-            out.push_back(M2);
-        }
+        out.push_back(o);
     }
     return HEC_OK;
 }
@@ -782,18 +898,18 @@ static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Lay
 }
 
 static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                       std::vector<hec_ct *> &out, Layout &ol)
+                                       bool lazy, std::vector<hec_ct *> &out, Layout &ol)
 {
     std::vector<hec_ct *> ds;
     if (L.channel) {
-        HEC_CHECK(downsample_channel(c, in, L, select, ds));
+        HEC_CHECK(downsample_channel(c, in, L, select, lazy, ds));
         const uint32_t H2 = select ? (L.H + 1) / 2 : L.H / 2, W2 = select ? (L.W + 1) / 2 : L.W / 2;
         hec_status s = merge_channel(c, ds, L, H2, W2, out, ol);
         free_all(ds);
         return s;
     }
     Layout nl;
-    HEC_CHECK(downsample(c, in, L, select, ds, nl));
+    HEC_CHECK(downsample(c, in, L, select, lazy, ds, nl));
     const size_t t = ds.size();
     out.clear();
     if (t == 1) {
@@ -869,10 +985,7 @@ struct hec_conv_plan {
     Layout in, out;  // out = unstrided output layout
     uint32_t level = 0, stride = 1;
     int mode = 0;
-    struct Item {
-        int32_t amount;
-        std::vector<std::pair<uint32_t, hec_pt *>> pts;
-    };
+    typedef RotTerm Item;
     std::vector<std::vector<Item>> items;  // per input shard
     std::set<int32_t> steps;
 };
@@ -959,94 +1072,6 @@ extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *step
     return HEC_OK;
 }
 
-// Lazy ModDown: the key-switch products of every rotation are multiplied by
-// their plaintexts and summed over Q_l and P; each output shard then takes one
-// ModDown (instead of one per rotation).  Rotations by zero enter as P * pt * ct.
-// acc[v] receives the ModDown of output v (not yet rescaled).
-static hec_status conv_accumulate_lazy(hec_ctx *c, const hec_conv_plan *p, const hec_image *in,
-                                       std::vector<hec_ct *> &acc)
-{
-    const size_t n = c->n, nout = acc.size();
-    const uint32_t lvl = p->level, nq = lvl + 1, nqp = nq + c->k;
-    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
-    std::vector<u64 *> E(nout, nullptr);
-    std::vector<char> used(nout, 0), fresh(nout, 1);
-    hec_status s = HEC_OK;
-    for (size_t v = 0; v < nout && s == HEC_OK; v++)
-        if (!(E[v] = c->alloc(2 * (size_t)nqp * n))) s = HEC_ENOMEM, hec_set_error("accumulator allocation");
-    double scale = 1.0;
-    for (size_t u = 0; u < p->items.size() && s == HEC_OK; u++) {
-        const auto &its = p->items[u];
-        if (its.empty()) continue;
-        const hec_ct *ct = in->shards[u];
-        bool rot = false;
-        for (auto &it : its) rot |= c->galois(it.amount) != 1;
-        u64 *D = nullptr;
-        if (rot && (s = ct_modup(c, ct, &D)) != HEC_OK) break;
-        for (size_t v0 = 0; v0 < nout && s == HEC_OK; v0 += HEC_MAC_OUT) {
-            const size_t nv = std::min((size_t)HEC_MAC_OUT, nout - v0);
-            // the items of this shard with a product for an output of the group
-            std::vector<size_t> terms;
-            for (size_t t = 0; t < its.size(); t++)
-                for (auto &pp : its[t].pts)
-                    if (pp.first >= v0 && pp.first < v0 + nv) {
-                        terms.push_back(t);
-                        break;
-                    }
-            // rotations by zero first (the kernel takes them as a leading run)
-            std::stable_partition(terms.begin(), terms.end(),
-                                  [&](size_t t) { return c->galois(its[t].amount) == 1; });
-            for (size_t b0 = 0; b0 < terms.size(); b0 += HEC_KS_BATCH) {
-                const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
-                KsMacBatch b{};
-                int first = 0;
-                for (size_t j = 0; j < nv; j++) {
-                    b.E[j] = E[v0 + j];
-                    if (fresh[v0 + j]) first |= 1 << j;
-                    fresh[v0 + j] = 0;
-                }
-                for (size_t t = 0; t < nt; t++) {
-                    const auto &it = its[terms[b0 + t]];
-                    const uint32_t g = c->galois(it.amount);
-                    b.g[t] = g;
-                    b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
-                    for (auto &pp : it.pts)
-                        if (pp.first >= v0 && pp.first < v0 + nv) {
-                            if (!pp.second->has_p || pp.second->level != lvl) {
-                                s = HEC_EINVAL;
-                                hec_set_error("plan plaintexts lack the special-prime limbs");
-                                break;
-                            }
-                            b.pt[t][pp.first - v0] = pp.second->d;
-                            used[pp.first] = 1;
-                            scale = ct->scale * pp.second->scale;
-                        }
-                }
-                if (s != HEC_OK) break;
-                if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
-                                c->d_pmodq_m, (int)c->NLK, first, c->st)) {
-                    s = HEC_EINVAL;
-                    hec_set_error("invalid key-switch batch");
-                    break;
-                }
-            }
-        }
-        c->release(D);
-    }
-    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
-        if (!used[v]) {
-            s = HEC_ELAYOUT;
-            hec_set_error("output shard %zu received no product", v);
-            break;
-        }
-        acc[v]->scale = scale;
-        s = ct_moddown(c, lvl, E[v], acc[v]);
-    }
-    for (auto *e : E) c->release(e);
-    if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("lazy accumulation launch");
-    return s;
-}
-
 #define ROT_CHUNK 32
 extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, const hec_image *in, hec_image **out)
 {
@@ -1068,7 +1093,9 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
     }
     hec_status s = HEC_OK;
     if (p->mode == 2) {
-        s = conv_accumulate_lazy(c, p, in, acc);
+        free_all(acc);
+        std::vector<const hec_ct *> ins(in->shards.begin(), in->shards.end());
+        s = lazy_rotate_mac(c, ins, p->items, nout, acc);
         std::fill(first.begin(), first.end(), 0);
     }
     for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode != 2; u++) {
@@ -1103,7 +1130,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         im->lay = p->out;
         im->shards = acc;
     } else {
-        s = downsample_and_merge(c, acc, p->out, true, im->shards, im->lay);
+        s = downsample_and_merge(c, acc, p->out, true, p->mode == 2, im->shards, im->lay);
         free_all(acc);
         if (s != HEC_OK) { hec_image_free(im); return s; }
     }
@@ -1127,9 +1154,15 @@ extern "C" hec_status he_conv2d_sharded(hec_ctx *c, const hec_image *in, const d
 
 extern "C" hec_status he_avgpool(hec_ctx *c, const hec_image *in, uint32_t window, hec_image **out)
 {
+    return he_avgpool_ex(c, in, window, 0, out);
+}
+
+extern "C" hec_status he_avgpool_ex(hec_ctx *c, const hec_image *in, uint32_t window, int mode, hec_image **out)
+{
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (mode != 0 && mode != 2) HEC_FAIL(HEC_EINVAL, "pooling mode must be 0 (per rotation) or 2 (lazy ModDown)");
     if (window != 2) HEC_FAIL(HEC_EINVAL, "only 2x2 pooling is supported");
     if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     HEC_TRY_HIP(hipSetDevice(c->dev));
@@ -1139,7 +1172,7 @@ extern "C" hec_status he_avgpool(hec_ctx *c, const hec_image *in, uint32_t windo
         if (!have_rotkey(c, s)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", s);
     hec_image *im = new hec_image();
     im->ctx = c;
-    hec_status s = downsample_and_merge(c, in->shards, in->lay, false, im->shards, im->lay);
+    hec_status s = downsample_and_merge(c, in->shards, in->lay, false, mode == 2, im->shards, im->lay);
     if (s != HEC_OK) { hec_image_free(im); return s; }
     *out = im;
     return HEC_OK;

@@ -21,7 +21,7 @@ EXPORTS = [
     "ckks_ct_import", "ckks_pt_export", "ckks_pt_import", "ckks_encode_coeffs", "he_image_encrypt",
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
-    "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "hec_ct_free", "hec_pt_free", "hec_image_free",
+    "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "hec_ct_free", "hec_pt_free", "hec_image_free",
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
 ]
 
@@ -95,6 +95,7 @@ def lib():
             "he_avgpool_steps": (c, [vp, vp, i32p, sz, szp]),
             "he_conv2d_plan_free": (None, [vp]),
             "he_avgpool": (c, [vp, vp, u32, P(vp)]),
+            "he_avgpool_ex": (c, [vp, vp, u32, c, P(vp)]),
             "hec_ct_free": (None, [vp]),
             "hec_pt_free": (None, [vp]),
             "hec_image_free": (None, [vp]),
@@ -396,9 +397,12 @@ class Context:
         check(lib().he_conv2d_plan_create(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, ctypes.byref(out)))
         return ConvPlan(self, out.value)
 
-    def avgpool(self, img):
+    def avgpool(self, img, mode=0):
         out = vp()
-        check(lib().he_avgpool(self.h, img.h, 2, ctypes.byref(out)))
+        if mode == 0:
+            check(lib().he_avgpool(self.h, img.h, 2, ctypes.byref(out)))
+        else:
+            check(lib().he_avgpool_ex(self.h, img.h, 2, int(mode), ctypes.byref(out)))
         return Image(self, out.value)
 
     def avgpool_steps(self, img):

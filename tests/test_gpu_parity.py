@@ -156,8 +156,8 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
             ref = hl.ref_conv2d(ref, w, pad, stride)
         else:
             ctx.gen_rotation_keys(ctx.avgpool_steps(img))
-            img = ctx.avgpool(img)
-            cts, lay = hl.avgpool2x2(be, cts, lay)
+            img = ctx.avgpool(img, mode=mode)
+            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode == 2))
             ref = hl.ref_avgpool2x2(ref)
         Cn, Hn, Wn, mp, t = img.info()
         assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
@@ -215,6 +215,9 @@ def test_layers_bit_exact(small, shape, ops):
     ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv
     ((2, 32, 32), [("conv", (3, 3), 1), ("pool",)]),                # channel shards
     ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem in channel shards
+    ((8, 16, 16), [("pool",), ("conv", (8, 3), 1)]),                # 4 shards pooled -> 1 permuted
+    ((1, 64, 64), [("pool",), ("conv", (2, 3), 1)]),                # 8 channel shards pooled
+    ((4, 8, 8), [("pool",), ("pool",)]),                            # the second pool fused (one level)
 ])
 def test_layers_lazy_moddown_bit_exact(small, shape, ops):
     ctx, prm, o = small
@@ -230,7 +233,8 @@ def test_layers_lazy_moddown_bit_exact(small, shape, ops):
         else:
             real_ops.append(op)
     log("lazy layers", shape, [op[0] for op in ops])
-    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=37, mode=2)
+    level = 3 if ops == [("pool",), ("pool",)] else 6
+    run_pipeline(ctx, prm, o, x, real_ops, level, seed=37, mode=2)
 
 
 def test_lazy_zero_rotation_only(small):
@@ -258,6 +262,9 @@ def test_plan_mode_rejected(small):
     plan = ctx.conv2d_plan(img, np.ones((1, 1, 3, 3)))
     with pytest.raises(hecnn.HecError) as e:
         plan.set_mode(3)
+    assert e.value.status == hecnn.HEC_EINVAL
+    with pytest.raises(hecnn.HecError) as e:
+        ctx.avgpool(img, mode=1)
     assert e.value.status == hecnn.HEC_EINVAL
 
 

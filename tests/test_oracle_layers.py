@@ -127,3 +127,39 @@ def test_lazy_moddown_conv(small):
     la, _ = hl.conv2d(be, c1, lay1, w1, pad=0, lazy=True)
     lb, _ = hl.conv2d(be, c1, lay1, w1, pad=0, lazy=False)
     assert (la[0].data == lb[0].data).all()
+
+
+def test_lazy_moddown_pooling(small):
+    """Pooling and strided convolution with the masked rotation sums of the
+    downsampling taken lazily (one ModDown per sum): same values within 1e-5,
+    same levels and scales as the per-rotation form, other bits."""
+    p, o = small
+    rng = np.random.default_rng(8)
+    be = hl.CkksBackend(o)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    for fused, lvl_out in ((False, 4), (True, 5)):
+        cts = enc_image(o, x, lay, 6, 2.0 ** 40, 17)
+        a, al = hl.avgpool2x2(be, cts, lay, fused=fused, lazy=True)
+        b, bl = hl.avgpool2x2(be, cts, lay, fused=fused, lazy=False)
+        assert a[0].level == b[0].level == lvl_out and a[0].scale == b[0].scale
+        assert al.shards == bl.shards
+        ref = hl.ref_avgpool2x2(x)
+        assert np.abs(dec_image(o, a, al) - ref).max() < 1e-5
+        assert not (a[0].data == b[0].data).all()
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 18)
+    s, sl = hl.conv2d(be, cts, lay, w, pad=1, stride=2, lazy=True)
+    assert s[0].level == 3
+    assert np.abs(dec_image(o, s, sl) - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
+
+
+def test_lazy_moddown_channel_pooling(small):
+    p, o = small
+    rng = np.random.default_rng(9)
+    be = hl.CkksBackend(o)
+    x = rng.uniform(-1, 1, (1, 32, 32))
+    lay = hl.natural_layout(p.N, 1, 32, 32)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 19)
+    a, al = hl.avgpool2x2(be, cts, lay, lazy=True)
+    assert np.abs(dec_image(o, a, al) - hl.ref_avgpool2x2(x)).max() < 1e-5
