@@ -53,7 +53,7 @@ KERNELS = {
                          "per_unit": 8 * (1 << 15) / 1e12, "bytes_per_unit": 2 * LIMB_BYTES,
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
 }
-DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac"}
+DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac"}
 
 
 def read_traffic(path):
@@ -159,8 +159,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-reps", type=int, default=2)
-    ap.add_argument("--mode", type=int, default=2, choices=(0, 1, 2),
-                    help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown")
+    ap.add_argument("--mode", type=int, default=2, choices=(0, 1, 2, 3),
+                    help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown, "
+                         "3 baby-step/giant-step with double hoisting")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -231,6 +232,7 @@ def main():
     dom = DOMINANT[args.mode]
     ctx.prof_start(dom)
     first_launch = ctx.prof_launches(dom)
+    ks0 = ctx.keyswitch_count()
     t = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -240,7 +242,10 @@ def main():
     wall = time.perf_counter() - t
     launches, units, kms = ctx.prof_stop()
     ms_step = wall * 1e3 / args.steps
-    value = rotations_per_step() * args.steps / wall
+    # key-switch inner products actually computed in the timed steps (636 per
+    # step in modes 0-2; fewer in mode 3, which trades rotations for giant steps)
+    ks_step = (ctx.keyswitch_count() - ks0) / args.steps
+    value = ks_step * args.steps / wall
     roofline = dominant_roofline(dom, launches, units, kms)
     if roofline:
         # dispatch range of the timed region in a kernel trace of this same command
@@ -266,6 +271,24 @@ def main():
     conv_b = conv_ms(0, 5)
     conv_p = conv_ms(1, max(1, args.plain_reps))
     conv_l = conv_ms(2, 5)
+    conv_g = conv_ms(3, 5)
+
+    # the whole step in the other fast mode (lazy ModDown <-> baby-step/giant-step)
+    other = 3 if args.mode != 3 else 2
+    p1.set_mode(other)
+    p2.set_mode(other)
+    step()
+    err_other = step(check=True)
+    torch.cuda.synchronize()
+    k0 = ctx.keyswitch_count()
+    s = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_other = (time.perf_counter() - s) * 1e3 / args.steps
+    ks_other = (ctx.keyswitch_count() - k0) / args.steps
+    p1.set_mode(args.mode)
+    p2.set_mode(args.mode)
 
     # isolated rotations at level 20
     ctx.gen_rotation_keys(list(range(1, 33)))
@@ -300,11 +323,14 @@ def main():
         "config": {"workload": "2N=2^16, 32x32x32 image at level 20: conv3x3 32->32 s1 + conv3x3 32->64 s2 "
                                "(2 shards -> downsample -> 1 ct), encrypt+decrypt included",
                    "ring_dim": 1 << LOGN, "level": LEVEL, "dnum": DNUM, "special_primes": K,
-                   "rotations_per_step": rotations_per_step()},
+                   "rotations_per_step": rotations_per_step(), "keyswitches_per_step": ks_step},
         "conv_layer_ms_batched": conv_b,
         "conv_layer_ms_plain": conv_p,
         "conv_layer_ms_lazy_moddown": conv_l,
-        "plan_mode": {0: "batched", 1: "plain", 2: "lazy_moddown"}[args.mode],
+        "conv_layer_ms_bsgs": conv_g,
+        "plan_mode": {0: "batched", 1: "plain", 2: "lazy_moddown", 3: "bsgs_double_hoisting"}[args.mode],
+        "other_mode": {"plan_mode": {2: "lazy_moddown", 3: "bsgs_double_hoisting"}[other], "ms_per_step": ms_other,
+                       "keyswitches_per_step": ks_other, "max_abs_err_vs_fp64": err_other},
         "rot_per_s_hoisted_level20": rot_hoisted,
         "rot_per_s_single_level20": rot_single,
         "max_abs_err_vs_fp64": err,

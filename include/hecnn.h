@@ -105,6 +105,9 @@ hec_status ckks_keygen(hec_ctx *ctx, uint64_t seed, const int32_t *rot_steps, si
 hec_status ckks_gen_rotation_keys(hec_ctx *ctx, const int32_t *rot_steps, size_t n_steps);
 /* Device bytes held by the rotation keys. */
 size_t hec_ctx_key_bytes(const hec_ctx *ctx);
+/* Key-switch inner products the context has computed so far (one per
+ * rotation by a nonzero amount, whatever the evaluation mode). */
+uint64_t hec_ctx_keyswitch_count(const hec_ctx *ctx);
 
 /* ---- plaintexts / ciphertexts ---------------------------------------------- */
 
@@ -185,7 +188,16 @@ hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec
  * rotations are multiplied by their weights and summed over Q_l and P, then
  * one ModDown per output shard); it rounds differently, so its ciphertexts
  * differ from modes 0/1 while decrypting to the same values within the same
- * error bound.  Returns HEC_EINVAL for any other mode. */
+ * error bound.  3 = baby-step / giant-step with double hoisting (also beyond
+ * the paper): every rotation amount is a block offset (baby) plus a tap
+ * offset (giant), pt * rot_{b+g}(ct) = rot_g(rot_{-g}(pt) * rot_b(ct)); the
+ * weights rotated back by their giant step multiply the hoisted baby
+ * rotations of each input (lazy ModDown per (giant, output) sum), and each
+ * output sums its giant rotations of those sums with one more lazy ModDown --
+ * babies + giants x outputs key switches instead of one per amount.  Its
+ * plaintexts are encoded on the first switch to mode 3.  Modes 2 and 3 also
+ * take the stride-2 downsampling lazily (he_avgpool_ex mode 2).  Returns
+ * HEC_EINVAL for any other mode. */
 hec_status he_conv2d_plan_set_mode(hec_conv_plan *plan, int mode);
 /* Rotation steps a plan (or an avgpool of `like`) needs keys for. */
 hec_status he_conv2d_plan_steps(const hec_conv_plan *plan, int32_t *steps, size_t cap, size_t *count);

@@ -249,6 +249,17 @@ def conv_plan(lay, w, pad):
     vector}) products.  Output shard v = sum over u and the list of
     pt * rot(ct_u, amount) (Section 4.1, single shard and image shards;
     duplicated / permuted inputs through the block map)."""
+    out, plan = conv_plan_split(lay, w, pad)
+    return out, [[(a, pts) for a, pts, _ in items] for items in plan]
+
+
+def conv_plan_split(lay, w, pad):
+    """conv_plan / conv_plan_channel with every amount split as
+    (baby, giant): amount = baby + giant (mod N), baby the block offset r*B
+    (0 for channel shards), giant the tap offset dk*mp + dl."""
+    if lay.kind == "channel":
+        out, plan = conv_plan_channel(lay, w, pad)
+        return out, [[(a, pts, (0, a)) for a, pts in items] for items in plan]
     if lay.kind != "image":
         raise ValueError("image-shard layout expected")
     w = np.asarray(w, dtype=np.float64)
@@ -274,6 +285,7 @@ def conv_plan(lay, w, pad):
                     if not mask.any():
                         continue
                     amount = (r * B + dk * mp + dl) % N
+                    split = ((r * B) % N, (dk * mp + dl) % N)
                     pts = {}
                     for v, mu in enumerate(out.shards):
                         vec = np.zeros(N)
@@ -284,7 +296,7 @@ def conv_plan(lay, w, pad):
                         if vec.any():
                             pts[v] = vec
                     if pts:
-                        items.append((amount, pts))
+                        items.append((amount, pts, split))
         plan.append(items)
     return out, plan
 
@@ -408,16 +420,80 @@ def _rot_masked_sums(be, ct, steps, masks, pscale, lazy=False):
     return [_sum(be, [be.mul_plain(rots[t], m[t], pscale) for t in range(len(steps))]) for m in masks]
 
 
-def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False):
+def _lazy_rotation_sum(be, terms):
+    """sum of rot(ct, amount) over terms [(ct, amount)] of ciphertexts at one
+    level and scale, with lazy ModDown: A + ModDown(E), E the sum of the
+    key-switch products over Q and P, A the sum of sigma_g(c0) (and of the
+    whole ciphertext for a rotation by zero)."""
+    o = be.o
+    p = o.p
+    lvl = terms[0][0].level
+    qi, qpi = list(range(lvl + 1)), o.qp_index(lvl)
+    E = np.zeros((2, len(qpi), p.n), dtype=np.uint64)
+    A = np.zeros((2, lvl + 1, p.n), dtype=np.uint64)
+    for ct, a in terms:
+        if ct.level != lvl or ct.scale != terms[0][0].scale:
+            raise ValueError("rotation sum over different levels or scales")
+        e = o.keyswitch_raw(ct, [a])[0]
+        if e is None:
+            for poly in range(2):
+                A[poly] = o.add_limbs(qi, A[poly], ct.data[poly])
+        else:
+            for poly in range(2):
+                E[poly] = o.add_limbs(qpi, E[poly], e[poly])
+            A[0] = o.add_limbs(qi, A[0], o.automorph(qi, ct.data[0], p.galois(a)))
+    from .ckks import Ct
+    data = np.stack([o.add_limbs(qi, A[poly], o.moddown(lvl, E[poly])) for poly in range(2)])
+    return Ct(data, lvl, terms[0][0].scale)
+
+
+def _conv_bsgs(be, cts, nout, plan):
+    """Baby-step / giant-step convolution with double hoisting.  Every amount
+    is baby + giant (block offset + tap offset), and
+        pt * rot_{b+g}(ct) = rot_g(roll(pt, g) * rot_b(ct)),
+    so that, per giant g and output v,
+        T_{g,v} = sum over inputs u and babies b of roll(pt, g) * rot_b(ct_u)
+    is formed with lazy ModDown from the hoisted baby rotations of each input
+    (one ModDown per (g, v)), and
+        out_v = sum_g rot_g(T_{g,v})
+    takes one key switch per (g, v) and one more lazy ModDown.  Rotations:
+    (babies per input) + (giants x outputs) instead of one per amount."""
+    keys = sorted({(g, v) for items in plan for _, pts, (_, g) in items for v in pts})
+    kidx = {k: i for i, k in enumerate(keys)}
+    baby_plan = []
+    for items in plan:
+        byb = {}
+        for _, pts, (b, g) in items:
+            for v, vec in pts.items():
+                byb.setdefault(b, {})[kidx[(g, v)]] = np.roll(vec, g)
+        baby_plan.append(sorted(byb.items()))
+    T = _accumulate_lazy(be, cts, len(keys), baby_plan, rescale=False)
+    outs = []
+    for v in range(nout):
+        terms = [(T[kidx[(g, vv)]], g) for g, vv in keys if vv == v]
+        if not terms:
+            raise ValueError("output shard without products")
+        outs.append(be.rescale(_lazy_rotation_sum(be, terms)))
+    return outs
+
+
+def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False, bsgs=False):
     """Homomorphic conv2d (cross-correlation, zero padding) of an image- or
     channel-sharded input; stride 2 is the stride-1 convolution followed by the
     downsampling step of the pooling (Section 4.1, strided convolution
-    paragraph).  lazy=True accumulates the plaintext products before ModDown
-    (encrypted backend only; the slot simulator computes the same values)."""
-    if lay.kind == "channel":
-        out_lay, plan = conv_plan_channel(lay, w, pad)
-    else:
-        out_lay, plan = conv_plan(lay, w, pad)
+    paragraph).  lazy=True accumulates the plaintext products before ModDown;
+    bsgs=True evaluates the same sum by baby and giant steps (_conv_bsgs);
+    both for the encrypted backend only (the slot simulator computes the same
+    values either way), both with lazy downsampling for stride 2."""
+    out_lay, split = conv_plan_split(lay, w, pad)
+    plan = [[(a, pts) for a, pts, _ in items] for items in split]
+    if bsgs and isinstance(be, CkksBackend):
+        outs = _conv_bsgs(be, cts, len(out_lay.shards), split)
+        if stride == 1:
+            return outs, out_lay
+        if stride != 2:
+            raise ValueError("stride must be 1 or 2")
+        return downsample_and_merge(be, outs, out_lay, select=True, lazy=True)
     if lazy and isinstance(be, CkksBackend):
         outs = _accumulate_lazy(be, cts, len(out_lay.shards), plan)
         if stride == 1:

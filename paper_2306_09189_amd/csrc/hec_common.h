@@ -60,13 +60,19 @@ struct KsBatch {
 };
 
 // Key switching fused with plaintext products, accumulated before ModDown.
-// Term t is a rotation by g[t] of one ciphertext (key[t] == null when g[t] == 1)
-// whose result is multiplied by pt[t][v] (null: no product) and added into
-// output v.  Outputs are [2][nqp][n] over Q_l and P; the Q limbs carry
-// P * (product), so that one ModDown of the accumulator gives the sum.
-#define HEC_MAC_OUT 4
+// Term t is a rotation by g[t] of ciphertext ct[t] (key[t] == null when
+// g[t] == 1; D[t] its ModUp, unused then) whose result is multiplied by
+// pt[t][v] (null: no product) and added into output v.  Outputs are
+// [2][nqp][n] over Q_l and P; the Q limbs carry P * (product), so that one
+// ModDown of the accumulator gives the sum.
+// Up to HEC_MAC_OUT outputs per launch, in groups of HEC_MAC_GROUP handled by
+// neighbouring workgroups (which share the key and digit reads through L2).
+#define HEC_MAC_OUT 16
+#define HEC_MAC_GROUP 4
 struct KsMacBatch {
     const u64 *key[HEC_KS_BATCH];              // [dnum][2][L+1+k][n], Montgomery form
+    const u64 *D[HEC_KS_BATCH];                // [beta][nqp][n], ModUp of ct[t]'s c1 (NTT form)
+    const u64 *ct[HEC_KS_BATCH];               // [2][nq][n] (NTT form)
     const u64 *pt[HEC_KS_BATCH][HEC_MAC_OUT];  // [nqp][n], Montgomery form
     u32 g[HEC_KS_BATCH];
     u64 *E[HEC_MAC_OUT];                       // [2][nqp][n], NTT form
@@ -102,18 +108,21 @@ void hec_sample_uniform(const DevTables &T, u64 *out, u64 seed, u32 purpose, u64
 void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u64 index, int kind,
                       const u64 *gauss_T, hipStream_t st);
 
-void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const u64 *src, u64 *dst,
-               size_t src_poly_stride, size_t dst_poly_stride, int npolys, hipStream_t st);
+// Base conversion of npolys polynomials: polynomial z uses descriptor d_desc[z * desc_stride], reads
+// src + z*src_poly_stride and writes dst + z*dst_poly_stride; nout_max bounds the descriptors' nout.
+// copy_in also copies the input limbs to the same positions of the destination.
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int nout_max, const u64 *src, u64 *dst,
+               size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st);
 
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st);
 
 // E_v (+)= sum_t pt[t][v] * KS_t, KS_t = (sum_j sigma_g(D_j) key_j + P sigma_g(c0), sum_j sigma_g(D_j) key'_j)
-// or P * (c0, c1) for g == 1; ct = [2][nq][n] (NTT form), D = [beta][nqp][n] ModUp of c1 (NTT form),
+// or P * (c0, c1) for g == 1, over the terms' own ciphertexts and ModUps (b.ct, b.D);
 // pm[i] = P * 2^64 mod q_i; bit v of `first` set: output v is written instead of accumulated.
 // Rotations by zero (g == 1) must precede the others; returns false (nothing launched) otherwise.
-bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
-                int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
+bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
+                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
                          const LevelC *lc, const u32 *pmap, hipStream_t st);

@@ -378,6 +378,8 @@ extern "C" hec_status hec_ctx_primes(const hec_ctx *c, uint64_t *primes, size_t 
 
 extern "C" uint32_t hec_ctx_slots(const hec_ctx *c) { return c ? c->N : 0; }
 
+extern "C" uint64_t hec_ctx_keyswitch_count(const hec_ctx *c) { return c ? c->ks_count : 0; }
+
 extern "C" size_t hec_ctx_key_bytes(const hec_ctx *c)
 {
     return c ? c->rotkeys.size() * (size_t)c->dnum * 2 * c->NLK * c->n * 8 : 0;
@@ -806,21 +808,40 @@ hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **Dout)
         c->release(D);
         HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
     }
+    // c1 to coefficients; every digit converted to Q_l and P in one launch (its
+    // own limbs copied), then one forward NTT over all digits and limbs (the
+    // digit's own limbs come back to c1's values exactly)
     HEC_TRY_HIP(hipMemcpyAsync(cc, c1, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
     hec_ntt_inv(c->T, cc, 0, 1, c->idmap(), nq, c->st);
-    for (uint32_t j = 0; j < beta; j++) {
-        u64 *Dj = D + (size_t)j * nqp * n;
-        const BconvDesc &hd = c->h_modup[(size_t)lvl * c->dnum + j];
-        hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum + j, hd.nout, cc, Dj, 0, 0, 1, c->st);
-        uint32_t lo = j * c->alpha, hi = lo + hd.nin;
-        hec_ntt_fwd(c->T, Dj, 0, 1, c->qpmap(lvl), (int)lo, c->st);
-        hec_ntt_fwd(c->T, Dj + (size_t)hi * n, 0, 1, c->qpmap(lvl) + hi, (int)(nqp - hi), c->st);
-        HEC_TRY_HIP(hipMemcpyAsync(Dj + (size_t)lo * n, c1 + (size_t)lo * n, (size_t)hd.nin * n * 8,
-                                   hipMemcpyDeviceToDevice, c->st));
-    }
+    uint32_t nout_max = 0;
+    for (uint32_t j = 0; j < beta; j++) nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
+    hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)nout_max, cc, D, 0, (size_t)nqp * n, (int)beta, 1,
+              c->st);
+    hec_ntt_fwd(c->T, D, (size_t)nqp * n, (int)beta, c->qpmap(lvl), (int)nqp, c->st);
     c->release(cc);
     *Dout = D;
     return HEC_OK;
+}
+
+const u64 *ones_qp(hec_ctx *c, uint32_t lvl)
+{
+    auto it = c->ones_qp.find(lvl);
+    if (it != c->ones_qp.end()) return it->second;
+    const size_t n = c->n, nqp = lvl + 1 + c->k;
+    std::vector<u64> h(nqp * n);
+    for (size_t l = 0; l < nqp; l++) {
+        const u64 q = c->mod[l <= lvl ? l : c->L + 1 + (l - lvl - 1)];
+        std::fill(h.begin() + l * n, h.begin() + (l + 1) * n, (u64)(((u128)1 << 64) % q));
+    }
+    u64 *d = c->alloc(nqp * n);
+    if (!d) return nullptr;
+    if (hipMemcpyAsync(d, h.data(), nqp * n * 8, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess) {
+        c->release(d);
+        return nullptr;
+    }
+    c->ones_qp[lvl] = d;
+    return d;
 }
 
 // out = ModDown(E) for E = [2][nq+k][n] over Q_l and P (NTT form); E's P limbs are consumed
@@ -837,7 +858,7 @@ hec_status ct_moddown(hec_ctx *c, uint32_t lvl, u64 *E, hec_ct *out)
     cb.y[0] = y;
     cb.g[0] = 1;
     hec_ntt_inv(c->T, E + (size_t)nq * n, (size_t)nqp * n, 2, c->qpmap(lvl) + nq, k, c->st);
-    hec_bconv(c->T, c->d_moddown + lvl, nq, E, y, (size_t)nqp * n, (size_t)nq * n, 2, c->st);
+    hec_bconv(c->T, c->d_moddown + lvl, 0, nq, E, y, (size_t)nqp * n, (size_t)nq * n, 2, 0, c->st);
     hec_ntt_fwd(c->T, y, (size_t)nq * n, 2, c->qpmap(lvl), nq, c->st);
     hec_moddown_combine(c->T, cb, 1, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
     c->release(y);
@@ -890,9 +911,10 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             cb.g[r] = g;
         }
         hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
+        c->ks_count += (uint64_t)R;
         // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine
         hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
-        hec_bconv(c->T, c->d_moddown + lvl, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, c->st);
+        hec_bconv(c->T, c->d_moddown + lvl, 0, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
         hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
         hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
         c->release(e);

@@ -91,6 +91,8 @@ struct hec_ctx {
     u64 *d_pk = nullptr;                   // [2][L+1][n] Montgomery
     std::map<uint32_t, u64 *> rotkeys;     // Galois element -> [dnum][2][NLK][n] Montgomery
     std::map<std::string, hec_pt *> mask_cache;
+    std::map<uint32_t, u64 *> ones_qp;     // level -> the constant 1 over Q_l and P, Montgomery form
+    uint64_t ks_count = 0;                 // key-switch inner products computed (one per rotation by g != 1)
     std::mutex mu;
 
     const u32 *idmap() const { return d_maps; }
@@ -139,6 +141,8 @@ hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size
 hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **D);
 // out = ModDown(E), E = [2][level+1+k][n] over Q_l and P (NTT form); E's P limbs are overwritten
 hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
+// the plaintext 1 over Q_l and P ([level+1+k][n], Montgomery form), cached per level
+const u64 *ones_qp(hec_ctx *c, uint32_t level);
 void pt_free(hec_pt *p);
 void ct_free(hec_ct *p);
 bool have_rotkey(hec_ctx *c, int32_t step);

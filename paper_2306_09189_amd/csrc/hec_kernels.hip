@@ -728,37 +728,56 @@ void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u
 // fast base conversion (coefficient form)
 // ---------------------------------------------------------------------------
 #define BC_THREADS 256
-__global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *d, const u64 *src, u64 *dst, size_t sps,
-                                                      size_t dps, DevTables T)
+#define BC_OUT 8  // outputs per workgroup (a grid row of workgroups per group of outputs)
+// Workgroup (x, y, z): 256 coefficients, outputs y*BC_OUT .. y*BC_OUT+7 of
+// descriptor dd[z * dstride], source src + z*sps, destination dst + z*dps.
+// With copy_in, the row y = ngroups copies the input limbs to the same
+// positions of the destination (a ModUp digit then holds all its limbs).
+// The inputs a_i stay in registers (loop bounds fixed at compile time); the
+// descriptor fields are uniform over the workgroup.
+__global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 dstride, const u64 *src, u64 *dst,
+                                                      size_t sps, size_t dps, u32 ngroups, u32 copy_in, DevTables T)
 {
-    __shared__ u64 hm[HEC_MAX_BCONV_IN * HEC_MAX_LIMBS];
-    __shared__ PrimeC opc[HEC_MAX_LIMBS];
+    const BconvDesc *d = dd + blockIdx.z * dstride;
+    const size_t n = T.n;
+    const u32 t = blockIdx.x * BC_THREADS + threadIdx.x;
+    if (t >= n) return;
     const u32 nin = d->nin, nout = d->nout;
-    for (u32 i = threadIdx.x; i < nin * nout; i += BC_THREADS) hm[i] = d->hat_m[i];
-    for (u32 i = threadIdx.x; i < nout; i += BC_THREADS) opc[i] = T.pc[d->out_prime[i]];
-    __syncthreads();
-    const size_t t = (size_t)blockIdx.x * BC_THREADS + threadIdx.x;
-    if (t >= T.n) return;
     const u64 *s = src + blockIdx.z * sps;
     u64 *o = dst + blockIdx.z * dps;
-    u64 a[HEC_MAX_BCONV_IN];
-    for (u32 i = 0; i < nin; i++) {
-        u64 q = T.pc[d->in_prime[i]].q;
-        a[i] = shoup_mul(s[(size_t)d->in_pos[i] * T.n + t], d->inv_hat[i], d->inv_hat_sh[i], q);
+    if (blockIdx.y == ngroups) {
+        if (copy_in)
+            for (u32 i = 0; i < nin; i++) o[(size_t)d->in_pos[i] * n + t] = s[(size_t)d->in_pos[i] * n + t];
+        return;
     }
-    for (u32 j = 0; j < nout; j++) {
+    const u32 j0 = blockIdx.y * BC_OUT;
+    if (j0 >= nout) return;
+    const u32 j1 = j0 + BC_OUT < nout ? j0 + BC_OUT : nout;
+    u64 a[HEC_MAX_BCONV_IN];
+#pragma unroll
+    for (u32 i = 0; i < HEC_MAX_BCONV_IN; i++) {
+        a[i] = 0;
+        if (i < nin) {
+            const u64 q = T.pc[d->in_prime[i]].q;
+            a[i] = shoup_mul(s[(size_t)d->in_pos[i] * n + t], d->inv_hat[i], d->inv_hat_sh[i], q);
+        }
+    }
+    for (u32 j = j0; j < j1; j++) {
         acc128 acc = {0, 0};
-        for (u32 i = 0; i < nin; i++) mac(acc, a[i], hm[i * nout + j]);
-        o[(size_t)d->out_pos[j] * T.n + t] = redc(acc.hi, acc.lo, opc[j].q, opc[j].qinv_neg);
+#pragma unroll
+        for (u32 i = 0; i < HEC_MAX_BCONV_IN; i++)
+            if (i < nin) mac(acc, a[i], d->hat_m[i * nout + j]);
+        const PrimeC pc = T.pc[d->out_prime[j]];
+        o[(size_t)d->out_pos[j] * n + t] = redc(acc.hi, acc.lo, pc.q, pc.qinv_neg);
     }
 }
-void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int nout_host, const u64 *src, u64 *dst,
-               size_t src_poly_stride, size_t dst_poly_stride, int npolys, hipStream_t st)
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int nout_max, const u64 *src, u64 *dst,
+               size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st)
 {
-    (void)nout_host;
-    dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, 1, npolys);
-    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, src, dst, src_poly_stride,
-            dst_poly_stride, T);
+    const u32 ngroups = ((u32)nout_max + BC_OUT - 1) / BC_OUT;
+    dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, ngroups + (copy_in ? 1 : 0), npolys);
+    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, (u32)desc_stride, src, dst,
+            src_poly_stride, dst_poly_stride, ngroups, (u32)(copy_in ? 1 : 0), T);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,14 +842,17 @@ DEV u64x2 ld2_stream(const u64 *p) { return __builtin_nontemporal_load((const u6
 DEV void st2(u64 *p, u64x2 v) { *(u64x2 *)p = v; }
 
 template <int BETA, int NOUT>
-__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, const u64 *D,
-                                                       const u64 *ct, u32 beta_rt, u32 nq, u32 nqp,
-                                                       const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
-                                                       u32 nchunks, DevTables T)
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
+                                                       u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
+                                                       u32 first, u32 nchunks, u32 ngroups, DevTables T)
 {
     const u32 w = blockIdx.x, total = gridDim.x;
     const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
-    const u32 chunk = i % nchunks, o = i / nchunks;
+    // output groups of the same (limb, chunk) are neighbours: they run together
+    // on one XCD and share the key and digit reads through its L2
+    const u32 grp = i % ngroups, rest = i / ngroups;
+    const u32 chunk = rest % nchunks, o = rest / nchunks;
+    const u32 vb = grp * NOUT;
     const u32 k = 2 * (chunk * EW_THREADS + threadIdx.x);
     if (k >= T.n) return;
     const u32 beta = BETA ? BETA : beta_rt;
@@ -847,12 +869,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
     // rotations by zero: P * (c0, c1)
     if (isq)
         for (u32 t = 0; t < nz; t++) {
+            const u64 *ct = b.ct[t];
             const u64x2 c0 = ld2(ct + (size_t)o * n + k), c1 = ld2(ct + ((size_t)nq + o) * n + k);
             const u64 e00 = mont_mul(c0.x, pmo, pc.q, pc.qinv_neg), e01 = mont_mul(c0.y, pmo, pc.q, pc.qinv_neg);
             const u64 e10 = mont_mul(c1.x, pmo, pc.q, pc.qinv_neg), e11 = mont_mul(c1.y, pmo, pc.q, pc.qinv_neg);
 #pragma unroll
             for (int v = 0; v < NOUT; v++) {
-                const u64 *pt = b.pt[t][v];
+                const u64 *pt = b.pt[t][vb + v];
                 if (!pt) continue;
                 const u64x2 m = ld2(pt + (size_t)o * n + k);
                 mac(acc[v][0][0], e00, m.x);
@@ -865,14 +888,14 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
         const u32 src = auto_src(k, b.g[t], T.logn);
         const u32 sb = src & ~1u;
         const bool sw = src & 1u;
-        const u64 *key = b.key[t];
+        const u64 *key = b.key[t], *D = b.D[t], *ct = b.ct[t];
         // issue the loads of the input and plaintext limbs together with the key
         // loads below (addresses always valid; unused values are ignored)
         const u64x2 c = ld2(ct + (size_t)(isq ? o : 0) * n + sb);
         u64x2 m[NOUT];
 #pragma unroll
         for (int v = 0; v < NOUT; v++) {
-            const u64 *pt = b.pt[t][v];
+            const u64 *pt = b.pt[t][vb + v];
             m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
         }
         acc128 a00 = {0, 0}, a01 = {0, 0}, a10 = {0, 0}, a11 = {0, 0};  // [poly][coefficient]
@@ -895,7 +918,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
         const u64 e10 = redc(a10.hi, a10.lo, pc.q, pc.qinv_neg), e11 = redc(a11.hi, a11.lo, pc.q, pc.qinv_neg);
 #pragma unroll
         for (int v = 0; v < NOUT; v++) {
-            if (!b.pt[t][v]) continue;
+            if (!b.pt[t][vb + v]) continue;
             mac(acc[v][0][0], e00, m[v].x);
             mac(acc[v][0][1], e01, m[v].y);
             mac(acc[v][1][0], e10, m[v].x);
@@ -904,7 +927,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
     }
 #pragma unroll
     for (int v = 0; v < NOUT; v++) {
-        u64 *E = b.E[v];
+        u64 *E = b.E[vb + v];
         if (!E) continue;
 #pragma unroll
         for (int p = 0; p < 2; p++) {
@@ -912,7 +935,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
             u64x2 r;
             r.x = redc(acc[v][p][0].hi, acc[v][p][0].lo, pc.q, pc.qinv_neg);
             r.y = redc(acc[v][p][1].hi, acc[v][p][1].lo, pc.q, pc.qinv_neg);
-            if (!((first >> v) & 1)) {
+            if (!((first >> (vb + v)) & 1)) {
                 const u64x2 old = ld2(dst);
                 r.x = add_mod(r.x, old.x, pc.q);
                 r.y = add_mod(r.y, old.y, pc.q);
@@ -923,54 +946,73 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
 }
 
 template <int BETA, int NOUT>
-static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
-                          const u64 *D, const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm,
-                          u32 NLK, u32 first, u32 nchunks, const DevTables &T)
+static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
+                          u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
+                          u32 ngroups, const DevTables &T)
 {
-    KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, D, ct, beta, nq,
-            nqp, pmap, pm, NLK, first, nchunks, T);
+    KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp,
+            pmap, pm, NLK, first, nchunks, ngroups, T);
 }
 template <int NOUT>
-static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
-                        const u64 *D, const u64 *ct, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm,
-                        u32 NLK, u32 first, u32 nchunks, const DevTables &T)
+static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
+                        u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
+                        u32 ngroups, const DevTables &T)
 {
+#define KSM_ARGS g, units, st, b, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
     switch (beta) {
-    case 1: ks_mac_launch<1, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
-    case 2: ks_mac_launch<2, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
-    case 3: ks_mac_launch<3, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
-    case 4: ks_mac_launch<4, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T); break;
-    default: ks_mac_launch<0, NOUT>(g, units, st, b, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    case 1: ks_mac_launch<1, NOUT>(KSM_ARGS); break;
+    case 2: ks_mac_launch<2, NOUT>(KSM_ARGS); break;
+    case 3: ks_mac_launch<3, NOUT>(KSM_ARGS); break;
+    case 4: ks_mac_launch<4, NOUT>(KSM_ARGS); break;
+    default: ks_mac_launch<0, NOUT>(KSM_ARGS);
     }
+#undef KSM_ARGS
 }
 // Work unit of the profiler: one limb (n words) moved to or from HBM, counting
-// each key, plaintext and accumulator limb once and the hoisted digits and the
-// input ciphertext once per launch.
-bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, const u64 *D, const u64 *ct,
-                int beta, int nq, int nqp, const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st)
+// each key, plaintext and accumulator limb once and the hoisted digits and
+// the input ciphertext of each distinct input once per launch (the output
+// groups re-read them from L2).
+bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
+                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st)
 {
     if (nterms < 0 || nterms > HEC_KS_BATCH || nout < 1 || nout > HEC_MAC_OUT) return false;
     u32 nz = 0;
     while ((int)nz < nterms && b.g[nz] == 1) nz++;
-    for (int t = (int)nz; t < nterms; t++)
-        if (b.g[t] == 1 || !b.key[t] || !D) return false;  // zero rotations must come first
-    uint64_t units = (nterms > (int)nz ? (uint64_t)beta * nqp : 0) + (uint64_t)nq + (nz ? (uint64_t)nq : 0);
     for (int t = 0; t < nterms; t++) {
+        if (!b.ct[t]) return false;
+        if (t >= (int)nz && (b.g[t] == 1 || !b.key[t] || !b.D[t])) return false;  // zero rotations come first
+    }
+    uint64_t units = 0;
+    for (int t = 0; t < nterms; t++) {
+        bool new_ct = true, new_d = t >= (int)nz;
+        for (int s = 0; s < t; s++) {
+            if (b.ct[s] == b.ct[t]) new_ct = false;
+            if (s >= (int)nz && b.D[s] == b.D[t]) new_d = false;
+        }
+        if (new_ct) units += (uint64_t)nq * (t < (int)nz ? 2 : 1);
+        if (new_d) units += (uint64_t)beta * nqp;
         if (t >= (int)nz) units += 2ull * beta * nqp;
         for (int v = 0; v < nout; v++)
             if (b.pt[t][v]) units += t >= (int)nz ? nqp : nq;
     }
     for (int v = 0; v < nout; v++) units += ((first >> v) & 1) ? 2ull * nqp : 4ull * nqp;
     const u32 nchunks = (T.n / 2 + EW_THREADS - 1) / EW_THREADS;
-    dim3 g(nchunks * (u32)nqp);
+    // outputs per workgroup: 1, 2 or a group of HEC_MAC_GROUP (the last group padded with empty outputs)
+    const u32 per = nout <= 2 ? (u32)nout : HEC_MAC_GROUP;
+    const u32 ngroups = ((u32)nout + per - 1) / per;
+    dim3 g(nchunks * (u32)nqp * ngroups);
     KsMacBatch bb = b;
-    for (int v = nout; v < HEC_MAC_OUT; v++) bb.E[v] = nullptr;
-    if (nout == 1)
-        ks_mac_beta<1>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
-    else if (nout == 2)
-        ks_mac_beta<2>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+    for (int v = nout; v < HEC_MAC_OUT; v++) {
+        bb.E[v] = nullptr;
+        for (int t = 0; t < HEC_KS_BATCH; t++) bb.pt[t][v] = nullptr;
+    }
+    if (per == 1)
+        ks_mac_beta<1>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+    else if (per == 2)
+        ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     else
-        ks_mac_beta<4>(g, units, st, bb, nz, nterms, D, ct, beta, nq, nqp, pmap, pm, NLK, first, nchunks, T);
+        ks_mac_beta<HEC_MAC_GROUP>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks,
+                                   ngroups, T);
     return true;
 }
 

@@ -205,6 +205,7 @@ extern "C" const hec_ct *he_image_shard(const hec_image *img, uint32_t u)
 // ---------------------------------------------------------------------------
 struct ConvItem {
     int32_t amount;
+    int32_t baby, giant;  // amount = baby + giant (mod N): block offset r*B (0 for channel shards), tap offset
     std::vector<std::pair<uint32_t, std::vector<double>>> pts;  // output shard -> slot vector
 };
 
@@ -292,8 +293,12 @@ static hec_status conv_items(const Layout &L, const double *w, uint32_t Co, uint
                     if (!any) continue;
                     int64_t a = ((int64_t)r * B + (int64_t)dk * L.mp + dl) % (int64_t)N;
                     if (a < 0) a += N;
+                    int64_t gi = ((int64_t)dk * L.mp + dl) % (int64_t)N;
+                    if (gi < 0) gi += N;
                     ConvItem it;
                     it.amount = (int32_t)a;
+                    it.baby = (int32_t)(((int64_t)r * B) % (int64_t)N);
+                    it.giant = (int32_t)gi;
                     for (uint32_t v = 0; v < out.maps.size(); v++) {
                         std::vector<double> vec(N, 0.0);
                         bool nz = false;
@@ -344,6 +349,8 @@ static hec_status conv_items_channel(const Layout &L, const double *w, uint32_t 
                 if (a < 0) a += N;
                 ConvItem it;
                 it.amount = (int32_t)a;
+                it.baby = 0;
+                it.giant = (int32_t)a;
                 int cands[2] = {vin, dk > 0 ? vin - 1 : vin + 1};
                 const int ncand = dk != 0 ? 2 : 1;
                 for (int ci = 0; ci < ncand; ci++) {
@@ -584,6 +591,8 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                     const uint32_t g = c->galois(it.amount);
                     b.g[t] = g;
                     b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
+                    b.D[t] = D;
+                    b.ct[t] = ct->d;
                     for (auto &pp : it.pts) {
                         if (pp.first < v0 || pp.first >= v0 + nv) continue;
                         if (!pp.second->has_p || pp.second->level != lvl) {
@@ -597,11 +606,12 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                     }
                 }
                 if (s != HEC_OK) break;
-                if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, D, ct->d, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
+                if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
                                 c->d_pmodq_m, (int)c->NLK, first, c->st)) {
                     s = HEC_EINVAL;
                     hec_set_error("invalid key-switch batch");
                 }
+                for (size_t t = 0; t < nt; t++) c->ks_count += b.g[t] != 1;
             }
         }
         c->release(D);
@@ -659,6 +669,75 @@ static hec_status rot_masked_sums(hec_ctx *c, const hec_ct *ct, const std::vecto
 // ---------------------------------------------------------------------------
 // downsample / consolidate / duplicate
 // ---------------------------------------------------------------------------
+// out (allocated here, not rescaled) = sum over terms of rot(ct_t, amount_t)
+// for ciphertexts at one level and scale, with lazy ModDown: every rotated
+// ciphertext takes its own ModUp, the key-switch products are summed over Q_l
+// and P, and the sum takes one ModDown.
+static hec_status lazy_rotation_sum(hec_ctx *c, const std::vector<std::pair<const hec_ct *, int32_t>> &terms_in,
+                                    hec_ct **out)
+{
+    *out = nullptr;
+    if (terms_in.empty()) HEC_FAIL(HEC_EINVAL, "empty rotation sum");
+    const size_t n = c->n;
+    const uint32_t lvl = terms_in[0].first->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    const double scale = terms_in[0].first->scale;
+    auto terms = terms_in;
+    for (auto &t : terms) {
+        if (t.first->level != lvl || t.first->scale != scale)
+            HEC_FAIL(HEC_ELEVEL, "rotation sum over different levels or scales");
+        const uint32_t g = c->galois(t.second);
+        if (g != 1 && !c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", t.second);
+    }
+    std::stable_partition(terms.begin(), terms.end(),
+                          [&](const std::pair<const hec_ct *, int32_t> &t) { return c->galois(t.second) == 1; });
+    const u64 *one = ones_qp(c, lvl);
+    u64 *E = c->alloc(2 * (size_t)nqp * n);
+    if (!one || !E) {
+        c->release(E);
+        HEC_FAIL(HEC_ENOMEM, "rotation-sum buffers");
+    }
+    hec_status s = HEC_OK;
+    for (size_t b0 = 0; b0 < terms.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
+        const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
+        KsMacBatch b{};
+        std::vector<u64 *> Ds;
+        b.E[0] = E;
+        for (size_t t = 0; t < nt && s == HEC_OK; t++) {
+            const hec_ct *ct = terms[b0 + t].first;
+            const uint32_t g = c->galois(terms[b0 + t].second);
+            b.g[t] = g;
+            b.ct[t] = ct->d;
+            b.pt[t][0] = one;
+            if (g != 1) {
+                u64 *D = nullptr;
+                s = ct_modup(c, ct, &D);
+                if (s != HEC_OK) break;
+                Ds.push_back(D);
+                b.D[t] = D;
+                b.key[t] = c->rotkeys[g];
+            }
+        }
+        if (s == HEC_OK && !hec_ks_mac(c->T, b, (int)nt, 1, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
+                                       c->d_pmodq_m, (int)c->NLK, b0 == 0 ? 1 : 0, c->st)) {
+            s = HEC_EINVAL;
+            hec_set_error("invalid key-switch batch");
+        }
+        c->ks_count += Ds.size();
+        for (auto *D : Ds) c->release(D);
+    }
+    hec_ct *o = nullptr;
+    if (s == HEC_OK && !(o = ct_new(c, lvl, scale))) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+    if (s == HEC_OK) s = ct_moddown(c, lvl, E, o);
+    c->release(E);
+    if (s != HEC_OK) {
+        ct_free(o);
+        return s;
+    }
+    *out = o;
+    return HEC_OK;
+}
+
 // Reduction of one shard after its 2x2 sums D (Section 4.2): column 2i of the
 // kept rows to column i (hs = 0..Wo-1), then row 2j to row j (js, shifts
 // 3j*mp/2), each a masked sum of hoisted rotations and a rescale; fused (one
@@ -988,14 +1067,24 @@ struct hec_conv_plan {
     typedef RotTerm Item;
     std::vector<std::vector<Item>> items;  // per input shard
     std::set<int32_t> steps;
+    // what the baby-step / giant-step form is rebuilt from
+    std::vector<double> w;
+    uint32_t Co = 0, kh = 0, kw = 0, pad = 0;
+    // baby-step / giant-step form, built on the first switch to mode 3: per
+    // input shard one term per baby (block offset) whose products go into the
+    // sums T_k, k -> (giant, output shard) = gv[k]
+    bool bsgs_ready = false;
+    std::vector<std::pair<int32_t, uint32_t>> gv;
+    std::vector<std::vector<RotTerm>> bsgs;
 };
 
 extern "C" void he_conv2d_plan_free(hec_conv_plan *p)
 {
     if (!p) return;
-    for (auto &v : p->items)
-        for (auto &it : v)
-            for (auto &pp : it.pts) pt_free(pp.second);
+    for (auto *set : {&p->items, &p->bsgs})
+        for (auto &v : *set)
+            for (auto &it : v)
+                for (auto &pp : it.pts) pt_free(pp.second);
     delete p;
 }
 
@@ -1003,6 +1092,59 @@ static bool same_layout(const Layout &a, const Layout &b)
 {
     return a.N == b.N && a.C == b.C && a.H == b.H && a.W == b.W && a.mp == b.mp && a.maps == b.maps &&
            a.channel == b.channel && a.cs == b.cs;
+}
+
+// Baby-step / giant-step form of a plan.  pt * rot_{b+g}(ct) = rot_g(pt'' * rot_b(ct))
+// with pt''[i] = pt[i - g] (the weights rotated back by the giant step), so
+// that T_{g,v} = sum over inputs and babies of pt'' * rot_b(ct) needs only the
+// hoisted baby rotations of each input, and output v = sum_g rot_g(T_{g,v}).
+static hec_status build_bsgs(hec_ctx *c, hec_conv_plan *p)
+{
+    if (p->bsgs_ready) return HEC_OK;
+    std::vector<std::vector<ConvItem>> items;
+    Layout out;
+    if (p->in.channel) HEC_CHECK(conv_items_channel(p->in, p->w.data(), p->Co, p->kh, p->kw, p->pad, out, items));
+    else HEC_CHECK(conv_items(p->in, p->w.data(), p->Co, p->kh, p->kw, p->pad, out, items));
+    const size_t N = c->N;
+    std::map<std::pair<int32_t, uint32_t>, uint32_t> idx;
+    for (auto &v : items)
+        for (auto &it : v)
+            for (auto &pp : it.pts) idx[{it.giant, pp.first}] = 0;
+    std::vector<std::pair<int32_t, uint32_t>> gv;
+    for (auto &kv : idx) {
+        kv.second = (uint32_t)gv.size();
+        gv.push_back(kv.first);
+    }
+    // per input: baby -> list of (sum index, rotated weight vector)
+    std::vector<std::map<int32_t, std::vector<std::pair<uint32_t, std::vector<double>>>>> byb(items.size());
+    size_t nvec = 0;
+    for (size_t u = 0; u < items.size(); u++)
+        for (auto &it : items[u])
+            for (auto &pp : it.pts) {
+                std::vector<double> r(N);
+                for (size_t i = 0; i < N; i++) r[(i + (size_t)it.giant) % N] = pp.second[i];
+                byb[u][it.baby].push_back({idx[{it.giant, pp.first}], std::move(r)});
+                nvec++;
+            }
+    std::vector<const double *> zp;
+    zp.reserve(nvec);
+    for (auto &m : byb)
+        for (auto &kv : m)
+            for (auto &e : kv.second) zp.push_back(e.second.data());
+    std::vector<hec_pt *> pts;
+    HEC_CHECK(pt_encode_many(c, zp, N, p->level, (double)c->mod[p->level], pts, true));
+    size_t q = 0;
+    p->bsgs.assign(items.size(), {});
+    for (size_t u = 0; u < items.size(); u++)
+        for (auto &kv : byb[u]) {
+            RotTerm t;
+            t.amount = kv.first;
+            for (auto &e : kv.second) t.pts.push_back({e.first, pts[q++]});
+            p->bsgs[u].push_back(std::move(t));
+        }
+    p->gv = gv;
+    p->bsgs_ready = true;
+    return HEC_OK;
 }
 
 extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, const double *w, uint32_t Co,
@@ -1042,9 +1184,16 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
             hec_conv_plan::Item pi;
             pi.amount = it.amount;
             for (auto &pp : it.pts) pi.pts.push_back({pp.first, pts[q++]});
-            if (it.amount % (int32_t)c->N) p->steps.insert(it.amount);
+            // keys for every mode: the amounts, and their baby and giant parts
+            for (int32_t a : {it.amount, it.baby, it.giant})
+                if (a % (int32_t)c->N) p->steps.insert(a);
             p->items[u].push_back(std::move(pi));
         }
+    p->w.assign(w, w + (size_t)Co * like->lay.C * kh * kw);
+    p->Co = Co;
+    p->kh = kh;
+    p->kw = kw;
+    p->pad = pad;
     if (stride == 2) {
         Layout o = p->out;
         pool_steps(o, true, lvl - 1, p->steps);
@@ -1055,7 +1204,11 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
 
 extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
-    if (!p || mode < 0 || mode > 2) HEC_FAIL(HEC_EINVAL, "bad mode");
+    if (!p || mode < 0 || mode > 3) HEC_FAIL(HEC_EINVAL, "bad mode");
+    if (mode == 3) {
+        HEC_TRY_HIP(hipSetDevice(p->ctx->dev));
+        HEC_CHECK(build_bsgs(p->ctx, p));
+    }
     p->mode = mode;
     return HEC_OK;
 }
@@ -1092,13 +1245,29 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         if (!acc[v]) { free_all(acc); HEC_FAIL(HEC_ENOMEM, "accumulator allocation"); }
     }
     hec_status s = HEC_OK;
+    std::vector<const hec_ct *> ins(in->shards.begin(), in->shards.end());
     if (p->mode == 2) {
         free_all(acc);
-        std::vector<const hec_ct *> ins(in->shards.begin(), in->shards.end());
         s = lazy_rotate_mac(c, ins, p->items, nout, acc);
         std::fill(first.begin(), first.end(), 0);
+    } else if (p->mode == 3) {
+        // baby steps: T_k = sum of pt'' * rot_baby(ct_u) (one ModDown per k);
+        // giant steps: output v = sum_k rot_giant(T_k) over the k of v (one more ModDown)
+        free_all(acc);
+        acc.assign(nout, nullptr);
+        std::vector<hec_ct *> T;
+        s = lazy_rotate_mac(c, ins, p->bsgs, p->gv.size(), T);
+        for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+            std::vector<std::pair<const hec_ct *, int32_t>> terms;
+            for (size_t k = 0; k < p->gv.size(); k++)
+                if (p->gv[k].second == v) terms.push_back({T[k], p->gv[k].first});
+            if (terms.empty()) s = HEC_ELAYOUT, hec_set_error("output shard %zu received no product", v);
+            else s = lazy_rotation_sum(c, terms, &acc[v]);
+        }
+        free_all(T);
+        std::fill(first.begin(), first.end(), 0);
     }
-    for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode != 2; u++) {
+    for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode < 2; u++) {
         const auto &its = p->items[u];
         for (size_t i0 = 0; i0 < its.size() && s == HEC_OK; i0 += ROT_CHUNK) {
             size_t cnt = std::min((size_t)ROT_CHUNK, its.size() - i0);
@@ -1130,7 +1299,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         im->lay = p->out;
         im->shards = acc;
     } else {
-        s = downsample_and_merge(c, acc, p->out, true, p->mode == 2, im->shards, im->lay);
+        s = downsample_and_merge(c, acc, p->out, true, p->mode >= 2, im->shards, im->lay);
         free_all(acc);
         if (s != HEC_OK) { hec_image_free(im); return s; }
     }

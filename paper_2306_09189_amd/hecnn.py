@@ -16,7 +16,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ELEVEL", 4: "ESCALE", 5: "ENOKE
 # every symbol the header declares
 EXPORTS = [
     "hec_ctx_create", "hec_ctx_destroy", "hec_last_error", "hec_ctx_primes", "hec_ctx_slots", "ckks_keygen",
-    "ckks_gen_rotation_keys", "hec_ctx_key_bytes", "ckks_encode", "ckks_encrypt", "ckks_encrypt_idx", "ckks_decrypt",
+    "ckks_gen_rotation_keys", "hec_ctx_key_bytes", "hec_ctx_keyswitch_count", "ckks_encode", "ckks_encrypt", "ckks_encrypt_idx", "ckks_decrypt",
     "ckks_rotate", "ckks_rotate_hoisted", "ckks_rescale", "ckks_mul_pt", "ckks_add", "ckks_ct_info", "ckks_ct_export",
     "ckks_ct_import", "ckks_pt_export", "ckks_pt_import", "ckks_encode_coeffs", "he_image_encrypt",
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
@@ -67,6 +67,7 @@ def lib():
             "ckks_keygen": (c, [vp, u64, i32p, sz]),
             "ckks_gen_rotation_keys": (c, [vp, i32p, sz]),
             "hec_ctx_key_bytes": (sz, [vp]),
+            "hec_ctx_keyswitch_count": (u64, [vp]),
             "ckks_encode": (c, [vp, dblp, sz, u32, dbl, P(vp)]),
             "ckks_encrypt": (c, [vp, vp, u64, P(vp)]),
             "ckks_encrypt_idx": (c, [vp, vp, u64, u64, P(vp)]),
@@ -314,6 +315,9 @@ class Context:
 
     def key_bytes(self):
         return lib().hec_ctx_key_bytes(self.h)
+
+    def keyswitch_count(self):
+        return int(lib().hec_ctx_keyswitch_count(self.h))
 
     def encode(self, z, level, scale):
         z = _arr(z, np.float64)

@@ -120,6 +120,28 @@ def test_conv_112_shard_lazy_bit_exact(full):
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
 
 
+def test_conv_112_shard_bsgs_bit_exact(full):
+    """The same shard convolution in baby-step / giant-step form (double
+    hoisting: babies are the block offsets 0 and B, giants the 9 tap offsets),
+    bit-exact with the oracle's form."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(4)
+    x = np.clip(rng.normal(0, 1, (2, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (2, 2, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3005)
+    plan = ctx.conv2d_plan(img, w)
+    plan.set_mode(3)
+    ctx.gen_rotation_keys(plan.steps())
+    out = plan.run(img)
+    log("oracle bsgs conv")
+    lay = hl.natural_layout(prm.N, 2, 112, 112)
+    cts = [o.encrypt(o.encode(v, 20, 2.0 ** LS), seed=3005, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1, bsgs=True)
+    assert out.shard_info(0) == (oc[0].level, oc[0].scale)
+    assert (out.shard_export(0) == oc[0].data).all()
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
 def test_benchmark_step_accuracy(full):
     """The benchmark workload end to end, batched and plain, within 1e-5."""
     ctx, prm, o = full
@@ -151,3 +173,12 @@ def test_benchmark_step_accuracy(full):
     err_l = np.abs(bl.decrypt() - ref).max()
     log("lazy max abs err", err_l)
     assert err_l < 1e-5
+    # baby-step / giant-step (double hoisting)
+    p1.set_mode(3)
+    p2.set_mode(3)
+    ctx.gen_rotation_keys(p1.steps() + p2.steps())
+    bb = p2.run(p1.run(img))
+    assert bb.shard_info(0) == b.shard_info(0)
+    err_b = np.abs(bb.decrypt() - ref).max()
+    log("bsgs max abs err", err_b)
+    assert err_b < 1e-5

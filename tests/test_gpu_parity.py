@@ -152,12 +152,12 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
             plan.set_mode(mode)
             ctx.gen_rotation_keys(plan.steps())
             img = plan.run(img)
-            cts, lay = hl.conv2d(be, cts, lay, w, pad=pad, stride=stride, lazy=(mode == 2))
+            cts, lay = hl.conv2d(be, cts, lay, w, pad=pad, stride=stride, lazy=(mode == 2), bsgs=(mode == 3))
             ref = hl.ref_conv2d(ref, w, pad, stride)
         else:
             ctx.gen_rotation_keys(ctx.avgpool_steps(img))
-            img = ctx.avgpool(img, mode=mode)
-            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode == 2))
+            img = ctx.avgpool(img, mode=min(mode, 2))
+            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode >= 2))
             ref = hl.ref_avgpool2x2(ref)
         Cn, Hn, Wn, mp, t = img.info()
         assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
@@ -237,6 +237,33 @@ def test_layers_lazy_moddown_bit_exact(small, shape, ops):
     run_pipeline(ctx, prm, o, x, real_ops, level, seed=37, mode=2)
 
 
+@pytest.mark.parametrize("shape,ops", [
+    ((4, 8, 8), [("conv", (4, 3), 1)]),                             # one shard, duplicated copies
+    ((4, 16, 16), [("conv", (16, 3), 1), ("pool",)]),               # 2 shards -> 8 outputs: 72 (giant, output) sums
+    ((16, 16, 16), [("conv", (8, 3), 1)]),                          # 8 input shards summed before the giant steps
+    ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv
+    ((2, 32, 32), [("conv", (3, 3), 1), ("pool",)]),                # channel shards: baby 0 only
+    ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem in channel shards
+    ((3, 12, 12), [("conv", (5, 5), 1)]),                           # 5x5 kernel, padded channels
+])
+def test_layers_bsgs_bit_exact(small, shape, ops):
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + 200)
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("bsgs layers", shape, [op[0] for op in ops])
+    pad = 2 if shape == (3, 12, 12) else 1
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=43, mode=3, pad=pad)
+
+
 def test_lazy_zero_rotation_only(small):
     """A 1x1 convolution of one channel per shard needs only the zero
     rotation: the lazy path must then equal the batched path bit for bit."""
@@ -261,7 +288,7 @@ def test_plan_mode_rejected(small):
     img = ctx.image_encrypt(np.zeros((1, 8, 8)), 3, 1)
     plan = ctx.conv2d_plan(img, np.ones((1, 1, 3, 3)))
     with pytest.raises(hecnn.HecError) as e:
-        plan.set_mode(3)
+        plan.set_mode(4)
     assert e.value.status == hecnn.HEC_EINVAL
     with pytest.raises(hecnn.HecError) as e:
         ctx.avgpool(img, mode=1)

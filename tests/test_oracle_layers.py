@@ -163,3 +163,53 @@ def test_lazy_moddown_channel_pooling(small):
     cts = enc_image(o, x, lay, 6, 2.0 ** 40, 19)
     a, al = hl.avgpool2x2(be, cts, lay, lazy=True)
     assert np.abs(dec_image(o, a, al) - hl.ref_avgpool2x2(x)).max() < 1e-5
+
+
+def test_bsgs_conv(small):
+    """Baby-step / giant-step convolution with double hoisting: the same
+    convolution within 1e-5 (image shards, stride 2, channel shards), same
+    level and scale; with only zero babies and zero giants (1x1 kernel, one
+    channel per shard) it equals the lazy form bit for bit."""
+    p, o = small
+    rng = np.random.default_rng(10)
+    be = hl.CkksBackend(o)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 20)
+    a, al = hl.conv2d(be, cts, lay, w, pad=1, bsgs=True)
+    b, bl = hl.conv2d(be, cts, lay, w, pad=1, lazy=True)
+    assert a[0].level == b[0].level and a[0].scale == b[0].scale and al.shards == bl.shards
+    assert np.abs(dec_image(o, a, al) - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+    s, sl = hl.conv2d(be, cts, lay, w, pad=1, stride=2, bsgs=True)
+    assert np.abs(dec_image(o, s, sl) - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
+    xc = rng.uniform(-1, 1, (1, 32, 32))
+    wc = rng.normal(0, 0.2, (2, 1, 3, 3))
+    lc = hl.natural_layout(p.N, 1, 32, 32)
+    cc = enc_image(o, xc, lc, 6, 2.0 ** 40, 21)
+    c, cl = hl.conv2d(be, cc, lc, wc, pad=1, bsgs=True)
+    assert np.abs(dec_image(o, c, cl) - hl.ref_conv2d(xc, wc, 1)).max() < 1e-5
+    x1 = rng.uniform(-1, 1, (1, 8, 8))
+    w1 = rng.normal(0, 0.1, (1, 1, 1, 1))
+    l1 = hl.natural_layout(p.N, 1, 8, 8)
+    c1 = enc_image(o, x1, l1, 6, 2.0 ** 40, 22)
+    za, _ = hl.conv2d(be, c1, l1, w1, pad=0, bsgs=True)
+    zb, _ = hl.conv2d(be, c1, l1, w1, pad=0, lazy=True)
+    assert (za[0].data == zb[0].data).all()
+
+
+def test_bsgs_split_identity():
+    """pt * rot_{b+g}(x) == rot_g(roll(pt, g) * rot_b(x)) on slot vectors, for
+    every (amount, split) of a plan: the identity the giant steps rest on."""
+    N = 256
+    rng = np.random.default_rng(11)
+    lay = hl.natural_layout(N, 4, 8, 8)
+    w = rng.normal(0, 1, (4, 4, 3, 3))
+    _, plan = hl.conv_plan_split(lay, w, 1)
+    x = rng.normal(0, 1, N)
+    rot = lambda v, a: np.roll(v, -a)   # slot j <- slot j + a
+    for items in plan:
+        for a, pts, (b, g) in items:
+            assert (b + g - a) % N == 0 and b % lay.B == 0
+            for vec in pts.values():
+                assert np.allclose(vec * rot(x, a), rot(np.roll(vec, g) * rot(x, b), g))
