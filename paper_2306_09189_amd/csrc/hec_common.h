@@ -65,10 +65,9 @@ struct KsBatch {
 // pt[t][v] (null: no product) and added into output v.  Outputs are
 // [2][nqp][n] over Q_l and P; the Q limbs carry P * (product), so that one
 // ModDown of the accumulator gives the sum.
-// Up to HEC_MAC_OUT outputs per launch, in groups of HEC_MAC_GROUP handled by
-// neighbouring workgroups (which share the key and digit reads through L2).
-#define HEC_MAC_OUT 16
-#define HEC_MAC_GROUP 4
+// Up to HEC_MAC_OUT outputs per launch (more than two: in groups handled by
+// neighbouring workgroups, which share the key and digit reads through L2).
+#define HEC_MAC_OUT 20
 struct KsMacBatch {
     const u64 *key[HEC_KS_BATCH];              // [dnum][2][L+1+k][n], Montgomery form
     const u64 *D[HEC_KS_BATCH];                // [beta][nqp][n], ModUp of ct[t]'s c1 (NTT form)

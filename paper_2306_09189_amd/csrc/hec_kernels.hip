@@ -945,6 +945,100 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
     }
 }
 
+// The same for many outputs: one coefficient per lane and up to KSW_OUT
+// outputs per workgroup (`per` of them used), so that the key-switch product
+// of a term is computed once for that many outputs; output groups of the same
+// (limb, chunk) are neighbours and share the key and digit reads through L2.
+#define KSW_OUT 8
+template <int BETA>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
+                                                         u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
+                                                         u32 first, u32 nchunks, u32 ngroups, u32 per, u32 nout,
+                                                         DevTables T)
+{
+    const u32 w = blockIdx.x, total = gridDim.x;
+    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 grp = i % ngroups, rest = i / ngroups;
+    const u32 chunk = rest % nchunks, o = rest / nchunks;
+    const u32 vb = grp * per;
+    const u32 k = chunk * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const u32 beta = BETA ? BETA : beta_rt;
+    const size_t n = T.n;
+    const u32 pi = pmap[o];
+    const PrimeC pc = T.pc[pi];
+    const bool isq = o < nq;
+    const u64 pmo = isq ? pm[o] : 0;
+    const u32 nv = vb + per <= nout ? per : (vb < nout ? nout - vb : 0);
+    acc128 acc[KSW_OUT][2];
+#pragma unroll
+    for (int v = 0; v < KSW_OUT; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    if (isq)
+        for (u32 t = 0; t < nz; t++) {
+            const u64 *ct = b.ct[t];
+            const u64 e0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
+            const u64 e1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
+#pragma unroll
+            for (u32 v = 0; v < KSW_OUT; v++) {
+                if (v >= nv) break;
+                const u64 *pt = b.pt[t][vb + v];
+                if (!pt) continue;
+                const u64 m = pt[(size_t)o * n + k];
+                mac(acc[v][0], e0, m);
+                mac(acc[v][1], e1, m);
+            }
+        }
+    for (u32 t = nz; t < nterms; t++) {
+        const u32 src = auto_src(k, b.g[t], T.logn);
+        const u64 *key = b.key[t], *D = b.D[t], *ct = b.ct[t];
+        const u64 c = ct[(size_t)(isq ? o : 0) * n + src];
+        u64 m[KSW_OUT];
+#pragma unroll
+        for (u32 v = 0; v < KSW_OUT; v++) {
+            const u64 *pt = v < nv ? b.pt[t][vb + v] : nullptr;
+            m[v] = pt ? __builtin_nontemporal_load(pt + (size_t)o * n + k) : 0;
+        }
+        acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+        for (u32 j = 0; j < beta; j++) {
+            const u64 d = D[((size_t)j * nqp + o) * n + src];
+            mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
+            mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+        }
+        if (isq) mac(a0, c, pmo);
+        const u64 e0 = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), e1 = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+#pragma unroll
+        for (u32 v = 0; v < KSW_OUT; v++) {
+            if (v >= nv) break;
+            if (!b.pt[t][vb + v]) continue;
+            mac(acc[v][0], e0, m[v]);
+            mac(acc[v][1], e1, m[v]);
+        }
+    }
+#pragma unroll
+    for (u32 v = 0; v < KSW_OUT; v++) {
+        if (v >= nv) break;
+        u64 *E = b.E[vb + v];
+        if (!E) continue;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            u64 *dst = E + ((size_t)p * nqp + o) * n + k;
+            u64 r = redc(acc[v][p].hi, acc[v][p].lo, pc.q, pc.qinv_neg);
+            if (!((first >> (vb + v)) & 1)) r = add_mod(r, *dst, pc.q);
+            *dst = r;
+        }
+    }
+}
+
+template <int BETA>
+static void ks_mac_w_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
+                            u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
+                            u32 nchunks, u32 ngroups, u32 per, u32 nout, const DevTables &T)
+{
+    KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp, pmap,
+            pm, NLK, first, nchunks, ngroups, per, nout, T);
+}
+
 template <int BETA, int NOUT>
 static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
                           u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
@@ -996,23 +1090,37 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
             if (b.pt[t][v]) units += t >= (int)nz ? nqp : nq;
     }
     for (int v = 0; v < nout; v++) units += ((first >> v) & 1) ? 2ull * nqp : 4ull * nqp;
-    const u32 nchunks = (T.n / 2 + EW_THREADS - 1) / EW_THREADS;
-    // outputs per workgroup: 1, 2 or a group of HEC_MAC_GROUP (the last group padded with empty outputs)
-    const u32 per = nout <= 2 ? (u32)nout : HEC_MAC_GROUP;
-    const u32 ngroups = ((u32)nout + per - 1) / per;
-    dim3 g(nchunks * (u32)nqp * ngroups);
     KsMacBatch bb = b;
     for (int v = nout; v < HEC_MAC_OUT; v++) {
         bb.E[v] = nullptr;
         for (int t = 0; t < HEC_KS_BATCH; t++) bb.pt[t][v] = nullptr;
     }
+    if (nout > 2) {
+        // many outputs: one coefficient per lane, groups of at most KSW_OUT outputs of even size
+        const u32 ng = ((u32)nout + KSW_OUT - 1) / KSW_OUT, per = ((u32)nout + ng - 1) / ng;
+        const u32 nch = (T.n + EW_THREADS - 1) / EW_THREADS;
+        dim3 g(nch * (u32)nqp * ng);
+#define KSW_ARGS g, units, st, bb, nz, (u32)nterms, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first, \
+                 nch, ng, per, (u32)nout, T
+        switch (beta) {
+        case 1: ks_mac_w_launch<1>(KSW_ARGS); break;
+        case 2: ks_mac_w_launch<2>(KSW_ARGS); break;
+        case 3: ks_mac_w_launch<3>(KSW_ARGS); break;
+        case 4: ks_mac_w_launch<4>(KSW_ARGS); break;
+        default: ks_mac_w_launch<0>(KSW_ARGS);
+        }
+#undef KSW_ARGS
+        return true;
+    }
+    const u32 nchunks = (T.n / 2 + EW_THREADS - 1) / EW_THREADS;
+    // outputs per workgroup: 1 or 2, two coefficients per lane
+    const u32 per = (u32)nout;
+    const u32 ngroups = 1;
+    dim3 g(nchunks * (u32)nqp * ngroups);
     if (per == 1)
         ks_mac_beta<1>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
-    else if (per == 2)
-        ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     else
-        ks_mac_beta<HEC_MAC_GROUP>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks,
-                                   ngroups, T);
+        ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     return true;
 }
 
