@@ -214,8 +214,11 @@ hec_status he_avgpool(hec_ctx *ctx, const hec_image *in, uint32_t window, hec_im
  * masked rotation sums of the reductions multiply the key-switch products
  * over Q_l and P and take one ModDown per sum -- an optimisation the paper
  * does not describe; other ciphertext bits, same values within the same
- * bound).  Other modes: HEC_EINVAL.  Plans in mode 2 use it for their
- * stride-2 downsampling. */
+ * bound); 3 = as 2, except that masked sums of at least 32 rotations are
+ * evaluated by baby and giant steps (amount = (i mod G) + (i - i mod G) in
+ * units of the stage's shift, G = ceil(sqrt(count)); masks rotated back by the
+ * giant step), also beyond the paper.  Other modes: HEC_EINVAL.  Plans in
+ * modes 2 and 3 use the same mode for their stride-2 downsampling. */
 hec_status he_avgpool_ex(hec_ctx *ctx, const hec_image *in, uint32_t window, int mode, hec_image **out);
 
 void hec_ct_free(hec_ct *ct);

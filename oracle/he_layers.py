@@ -408,11 +408,39 @@ def _accumulate_lazy(be, cts, nout, plan, pscale=None, rescale=True):
     return outs
 
 
-def _rot_masked_sums(be, ct, steps, masks, pscale, lazy=False):
+def bsgs_split(steps, unit):
+    """Baby / giant split of rotation amounts steps[t] = idx_t * unit: with
+    G = ceil(sqrt(max idx + 1)), baby = (idx mod G) * unit and giant =
+    (idx - idx mod G) * unit."""
+    idx = [a // unit for a in steps]
+    if any(i * unit != a for i, a in zip(idx, steps)):
+        raise ValueError("amounts are not multiples of the unit")
+    n = max(idx) + 1
+    G = 1
+    while G * G < n:
+        G += 1
+    return [((i % G) * unit, (i - i % G) * unit) for i in idx]
+
+
+# masked sums of fewer rotations stay lazy in the baby-step / giant-step mode:
+# below this size the ModUp/ModDown of the giant sums cost more than the key
+# switches they save
+BSGS_MIN_STEPS = 32
+
+
+def _rot_masked_sums(be, ct, steps, masks, pscale, lazy=False, bsgs=False, unit=1):
     """Per output o: sum_t masks[o][t] * rot(ct, steps[t]) over the hoisted
     rotations of one ciphertext, not rescaled.  lazy (encrypted backend):
     the products are taken on the key-switch outputs over Q*P and each output
-    takes one ModDown."""
+    takes one ModDown.  bsgs (encrypted backend): baby-step / giant-step over
+    the split of bsgs_split(steps, unit), as in _conv_bsgs, when there are at
+    least BSGS_MIN_STEPS amounts (lazy otherwise)."""
+    if bsgs and len(steps) < BSGS_MIN_STEPS:
+        bsgs, lazy = False, True
+    if bsgs and isinstance(be, CkksBackend):
+        split = bsgs_split(steps, unit)
+        plan = [[(a, {o: m[t] for o, m in enumerate(masks)}, split[t]) for t, a in enumerate(steps)]]
+        return _conv_bsgs(be, [ct], len(masks), plan, pscale=pscale, rescale=False)
     if lazy and isinstance(be, CkksBackend):
         plan = [[(a, {o: m[t] for o, m in enumerate(masks)}) for t, a in enumerate(steps)]]
         return _accumulate_lazy(be, [ct], len(masks), plan, pscale=pscale, rescale=False)
@@ -447,7 +475,7 @@ def _lazy_rotation_sum(be, terms):
     return Ct(data, lvl, terms[0][0].scale)
 
 
-def _conv_bsgs(be, cts, nout, plan):
+def _conv_bsgs(be, cts, nout, plan, pscale=None, rescale=True):
     """Baby-step / giant-step convolution with double hoisting.  Every amount
     is baby + giant (block offset + tap offset), and
         pt * rot_{b+g}(ct) = rot_g(roll(pt, g) * rot_b(ct)),
@@ -467,13 +495,14 @@ def _conv_bsgs(be, cts, nout, plan):
             for v, vec in pts.items():
                 byb.setdefault(b, {})[kidx[(g, v)]] = np.roll(vec, g)
         baby_plan.append(sorted(byb.items()))
-    T = _accumulate_lazy(be, cts, len(keys), baby_plan, rescale=False)
+    T = _accumulate_lazy(be, cts, len(keys), baby_plan, pscale=pscale, rescale=False)
     outs = []
     for v in range(nout):
         terms = [(T[kidx[(g, vv)]], g) for g, vv in keys if vv == v]
         if not terms:
             raise ValueError("output shard without products")
-        outs.append(be.rescale(_lazy_rotation_sum(be, terms)))
+        o = _lazy_rotation_sum(be, terms)
+        outs.append(be.rescale(o) if rescale else o)
     return outs
 
 
@@ -493,7 +522,7 @@ def conv2d(be, cts, lay, w, pad=1, stride=1, lazy=False, bsgs=False):
             return outs, out_lay
         if stride != 2:
             raise ValueError("stride must be 1 or 2")
-        return downsample_and_merge(be, outs, out_lay, select=True, lazy=True)
+        return downsample_and_merge(be, outs, out_lay, select=True, bsgs=True)
     if lazy and isinstance(be, CkksBackend):
         outs = _accumulate_lazy(be, cts, len(out_lay.shards), plan)
         if stride == 1:
@@ -555,7 +584,7 @@ def _per_block(lay, blk, lam=None):
     return v
 
 
-def downsample(be, cts, lay, select=False, fused=None, lazy=False):
+def downsample(be, cts, lay, select=False, fused=None, lazy=False, bsgs=False):
     """Per-shard downsample: (pool) 2x2 window sums, then horizontal and
     vertical reduction; (select) the reductions alone keep the top-left element
     of every 2x2 window (strided convolution).  Returns the shards with an
@@ -584,17 +613,19 @@ def downsample(be, cts, lay, select=False, fused=None, lazy=False):
         hs = list(range(Wo))
         if use_fused:
             ps = be.q(lvl) / 4.0
-            T = _rot_masked_sums(be, D, hs, [[_fmask(lay, i, j, val) for i in hs] for j in range(Ho)], ps, lazy)
+            T = _rot_masked_sums(be, D, hs, [[_fmask(lay, i, j, val) for i in hs] for j in range(Ho)], ps, lazy,
+                                 bsgs)
             moved = [T[0]] + [be.rotate(T[j], 3 * j * mp // 2) for j in range(1, Ho)]
             outs.append(be.rescale(_sum(be, moved)))
         else:
-            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[_hmask(lay, i, val) for i in hs]], be.q(lvl), lazy)[0])
+            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[_hmask(lay, i, val) for i in hs]], be.q(lvl), lazy,
+                                             bsgs)[0])
             lvl1 = be.level(M1)
             if lvl1 < 1:
                 raise ValueError("separable pooling needs two levels")
             vs = [3 * j * mp // 2 for j in range(Ho)]
             outs.append(be.rescale(_rot_masked_sums(be, M1, vs, [[_vmask(lay, j, Wo) for j in range(Ho)]],
-                                                    be.q(lvl1), lazy)[0]))
+                                                    be.q(lvl1), lazy, bsgs, 3 * mp // 2)[0]))
     nl = Layout(lay.N, lay.C, Ho, Wo, mp // 2, "image",
                 [[s[b // 4] if b % 4 == 0 else -1 for b in range(4 * lay.nb)] for s in lay.shards])
     return outs, nl
@@ -640,7 +671,7 @@ def duplicate(be, ct, lay, d):
     return out, Layout(lay.N, lay.C, lay.H, lay.W, lay.mp, "image", [lam])
 
 
-def downsample_channel(be, cts, lay, select=False, fused=None, lazy=False):
+def downsample_channel(be, cts, lay, select=False, fused=None, lazy=False, bsgs=False):
     """Channel shards are downsampled individually (Section 4.2, "With Channel
     Shards"): 2x2 sums stay inside a shard (R is even), column 2i of the even
     valid rows goes to column i, the left half of local row 2j to j*mp/2."""
@@ -690,17 +721,18 @@ def downsample_channel(be, cts, lay, select=False, fused=None, lazy=False):
 
         if use_fused:
             ps = be.q(lvl) / 4.0
-            T = _rot_masked_sums(be, D, hs, [[fmask(i, j) for i in hs] for j in js], ps, lazy)
+            T = _rot_masked_sums(be, D, hs, [[fmask(i, j) for i in hs] for j in js], ps, lazy, bsgs)
             moved = [T[0] if js[0] == 0 else be.rotate(T[0], 3 * js[0] * mp // 2)] + \
                     [be.rotate(T[t], 3 * j * mp // 2) for t, j in enumerate(js) if t > 0]
             outs.append(be.rescale(_sum(be, moved)))
         else:
-            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[hmask(i) for i in hs]], be.q(lvl), lazy)[0])
+            M1 = be.rescale(_rot_masked_sums(be, D, hs, [[hmask(i) for i in hs]], be.q(lvl), lazy, bsgs)[0])
             lvl1 = be.level(M1)
             if lvl1 < 1:
                 raise ValueError("separable pooling needs two levels")
             vs = [3 * j * mp // 2 for j in js]
-            outs.append(be.rescale(_rot_masked_sums(be, M1, vs, [[vmask(j) for j in js]], be.q(lvl1), lazy)[0]))
+            outs.append(be.rescale(_rot_masked_sums(be, M1, vs, [[vmask(j) for j in js]], be.q(lvl1), lazy, bsgs,
+                                                    3 * mp // 2)[0]))
     return outs
 
 
@@ -738,17 +770,18 @@ def merge_channel(be, outs, lay, H2, W2):
     return res, out
 
 
-def downsample_and_merge(be, cts, lay, select=False, fused=None, lazy=False):
+def downsample_and_merge(be, cts, lay, select=False, fused=None, lazy=False, bsgs=False):
     """Downsample every shard, then consolidate and duplicate (Section 4.2);
-    lazy: the masked rotation sums of the downsampling take one ModDown each."""
+    lazy: the masked rotation sums of the downsampling take one ModDown each;
+    bsgs: they are evaluated by baby and giant steps."""
     if lay.kind == "channel":
-        outs = downsample_channel(be, cts, lay, select=select, fused=fused, lazy=lazy)
+        outs = downsample_channel(be, cts, lay, select=select, fused=fused, lazy=lazy, bsgs=bsgs)
         if select:
             H2, W2 = (lay.H + 1) // 2, (lay.W + 1) // 2
         else:
             H2, W2 = lay.H // 2, lay.W // 2
         return merge_channel(be, outs, lay, H2, W2)
-    outs, nl = downsample(be, cts, lay, select=select, fused=fused, lazy=lazy)
+    outs, nl = downsample(be, cts, lay, select=select, fused=fused, lazy=lazy, bsgs=bsgs)
     t = len(outs)
     if t == 1:
         o, l2 = duplicate(be, outs[0], nl, 4)
@@ -760,10 +793,10 @@ def downsample_and_merge(be, cts, lay, select=False, fused=None, lazy=False):
     return outs, nl
 
 
-def avgpool2x2(be, cts, lay, fused=None, lazy=False):
+def avgpool2x2(be, cts, lay, fused=None, lazy=False, bsgs=False):
     """2x2 average pooling: downsample, consolidate, duplicate (Section 4.2),
-    for image shards and channel shards; lazy as in downsample_and_merge."""
-    return downsample_and_merge(be, cts, lay, select=False, fused=fused, lazy=lazy)
+    for image shards and channel shards; lazy / bsgs as in downsample_and_merge."""
+    return downsample_and_merge(be, cts, lay, select=False, fused=fused, lazy=lazy, bsgs=bsgs)
 
 
 # ---------------------------------------------------------------------------

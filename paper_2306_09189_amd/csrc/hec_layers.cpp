@@ -457,7 +457,7 @@ struct RotTerm {
 // cached mask plaintexts (they only depend on the layout, shard part, index, level and scale)
 static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::vector<std::pair<uint32_t, uint32_t>> &ij,
                             uint32_t Wo, double val, uint32_t level, double scale, std::vector<hec_pt *> &out,
-                            int part = -1)
+                            int part = -1, const std::vector<int32_t> *rolls = nullptr)
 {
     std::string base = layout_key(L, part);
     std::vector<std::string> keys;
@@ -466,7 +466,7 @@ static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::v
     for (size_t t = 0; t < ij.size(); t++) {
         std::ostringstream s;
         s << base << "|" << kind << "|" << ij[t].first << "|" << ij[t].second << "|" << Wo << "|" << val << "|"
-          << level << "|" << scale;
+          << level << "|" << scale << "|" << (rolls ? (*rolls)[t] : 0);
         keys.push_back(s.str());
         auto it = c->mask_cache.find(keys.back());
         if (it != c->mask_cache.end()) out[t] = it->second;
@@ -475,7 +475,17 @@ static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::v
     if (miss.empty()) return HEC_OK;
     std::vector<std::vector<double>> vecs;
     std::vector<const double *> zp;
-    for (size_t t : miss) vecs.push_back(pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val, part));
+    for (size_t t : miss) {
+        std::vector<double> v = pool_mask(L, kind, ij[t].first, ij[t].second, Wo, val, part);
+        const size_t N = v.size(), r = rolls ? (size_t)(((*rolls)[t] % (int64_t)N + N) % N) : 0;
+        if (r) {
+            // the mask rotated back by a giant step: slot i takes slot i - r
+            std::vector<double> w(N);
+            for (size_t i = 0; i < N; i++) w[(i + r) % N] = v[i];
+            v.swap(w);
+        }
+        vecs.push_back(std::move(v));
+    }
     for (auto &v : vecs) zp.push_back(v.data());
     std::vector<hec_pt *> pts;
     HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts, true));
@@ -738,6 +748,95 @@ static hec_status lazy_rotation_sum(hec_ctx *c, const std::vector<std::pair<cons
     return HEC_OK;
 }
 
+// Baby / giant split of rotation amounts steps[t] = idx_t * unit: with
+// G = ceil(sqrt(max idx + 1)), baby = (idx mod G) * unit, giant = (idx - idx mod G) * unit.
+static void bsgs_split(const std::vector<int32_t> &steps, int32_t unit, std::vector<int32_t> &baby,
+                       std::vector<int32_t> &giant)
+{
+    int32_t n = 1;
+    for (int32_t a : steps) n = std::max(n, a / unit + 1);
+    int32_t G = 1;
+    while (G * G < n) G++;
+    baby.clear();
+    giant.clear();
+    for (int32_t a : steps) {
+        const int32_t i = a / unit;
+        baby.push_back((i % G) * unit);
+        giant.push_back((i - i % G) * unit);
+    }
+}
+
+// Baby-step / giant-step evaluation (double hoisting): T_k = lazy sums of the
+// baby terms of every input (one ModDown per k), then output v = the lazy sum
+// of rot_{gv[k].first}(T_k) over the k with gv[k].second == v.  Not rescaled.
+static hec_status bsgs_eval(hec_ctx *c, const std::vector<const hec_ct *> &ins,
+                            const std::vector<std::vector<RotTerm>> &babies,
+                            const std::vector<std::pair<int32_t, uint32_t>> &gv, size_t nout,
+                            std::vector<hec_ct *> &out)
+{
+    out.assign(nout, nullptr);
+    std::vector<hec_ct *> T;
+    HEC_CHECK(lazy_rotate_mac(c, ins, babies, gv.size(), T));
+    hec_status s = HEC_OK;
+    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+        std::vector<std::pair<const hec_ct *, int32_t>> terms;
+        for (size_t k = 0; k < gv.size(); k++)
+            if (gv[k].second == v) terms.push_back({T[k], gv[k].first});
+        if (terms.empty()) s = HEC_ELAYOUT, hec_set_error("output %zu received no product", v);
+        else s = lazy_rotation_sum(c, terms, &out[v]);
+    }
+    free_all(T);
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
+// out[o] (not rescaled) = sum_t masks[o][t] * rot(ct, baby[t] + giant[t]) by
+// baby and giant steps; masks[o][t] must already be rotated back by giant[t]
+static hec_status bsgs_masked_sums(hec_ctx *c, const hec_ct *ct, const std::vector<int32_t> &baby,
+                                   const std::vector<int32_t> &giant,
+                                   const std::vector<std::vector<hec_pt *>> &masks, std::vector<hec_ct *> &out)
+{
+    std::map<std::pair<int32_t, uint32_t>, uint32_t> idx;
+    for (size_t t = 0; t < baby.size(); t++)
+        for (size_t o = 0; o < masks.size(); o++) idx[{giant[t], (uint32_t)o}] = 0;
+    std::vector<std::pair<int32_t, uint32_t>> gv;
+    for (auto &kv : idx) {
+        kv.second = (uint32_t)gv.size();
+        gv.push_back(kv.first);
+    }
+    std::map<int32_t, RotTerm> byb;
+    for (size_t t = 0; t < baby.size(); t++) {
+        RotTerm &rt = byb[baby[t]];
+        rt.amount = baby[t];
+        for (size_t o = 0; o < masks.size(); o++) rt.pts.push_back({idx[{giant[t], (uint32_t)o}], masks[o][t]});
+    }
+    std::vector<std::vector<RotTerm>> babies(1);
+    for (auto &kv : byb) babies[0].push_back(kv.second);
+    return bsgs_eval(c, {ct}, babies, gv, masks.size(), out);
+}
+
+// One masked-sum stage of the pooling in evaluation mode `mode` (0 per
+// rotation, 2 lazy ModDown, 3 baby-step / giant-step); masks[o][t] are fetched
+// by get_mask(o, rolls) with the giant-step rolls in mode 3 (null otherwise).
+// Sums of fewer than BSGS_MIN_STEPS rotations stay lazy in mode 3: below that
+// the ModUp/ModDown of the giant sums cost more than the key switches saved.
+#define BSGS_MIN_STEPS 32
+template <class GetMasks>
+static hec_status pool_stage(hec_ctx *c, const hec_ct *ct, const std::vector<int32_t> &steps, int32_t unit,
+                             size_t nout, int mode, GetMasks get_masks_for, std::vector<hec_ct *> &out)
+{
+    std::vector<std::vector<hec_pt *>> masks(nout);
+    if (mode == 3 && steps.size() < BSGS_MIN_STEPS) mode = 2;
+    if (mode == 3) {
+        std::vector<int32_t> baby, giant;
+        bsgs_split(steps, unit, baby, giant);
+        for (size_t o = 0; o < nout; o++) HEC_CHECK(get_masks_for(o, &giant, masks[o]));
+        return bsgs_masked_sums(c, ct, baby, giant, masks, out);
+    }
+    for (size_t o = 0; o < nout; o++) HEC_CHECK(get_masks_for(o, nullptr, masks[o]));
+    return rot_masked_sums(c, ct, steps, masks, mode == 2, out);
+}
+
 // Reduction of one shard after its 2x2 sums D (Section 4.2): column 2i of the
 // kept rows to column i (hs = 0..Wo-1), then row 2j to row j (js, shifts
 // 3j*mp/2), each a masked sum of hoisted rotations and a rescale; fused (one
@@ -745,19 +844,20 @@ static hec_status lazy_rotation_sum(hec_ctx *c, const std::vector<std::pair<cons
 // selects the masks of a channel shard.
 static hec_status pool_reduce(hec_ctx *c, const hec_ct *D, const Layout &L, const std::vector<int32_t> &hs,
                               const std::vector<uint32_t> &js, uint32_t Wo, double val, uint32_t lvl, bool fused,
-                              bool lazy, int part, hec_ct **out)
+                              int mode, int part, hec_ct **out)
 {
     *out = nullptr;
     const uint32_t mp = L.mp;
     if (fused) {
-        std::vector<std::vector<hec_pt *>> masks(js.size());
-        for (size_t t = 0; t < js.size(); t++) {
-            std::vector<std::pair<uint32_t, uint32_t>> ij;
-            for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, js[t]});
-            HEC_CHECK(get_masks(c, L, 'f', ij, Wo, val, lvl, (double)c->mod[lvl] / 4.0, masks[t], part));
-        }
         std::vector<hec_ct *> T;
-        HEC_CHECK(rot_masked_sums(c, D, hs, masks, lazy, T));
+        HEC_CHECK(pool_stage(c, D, hs, 1, js.size(), mode,
+                             [&](size_t t, const std::vector<int32_t> *rolls, std::vector<hec_pt *> &m) {
+                                 std::vector<std::pair<uint32_t, uint32_t>> ij;
+                                 for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, js[t]});
+                                 return get_masks(c, L, 'f', ij, Wo, val, lvl, (double)c->mod[lvl] / 4.0, m, part,
+                                                  rolls);
+                             },
+                             T));
         hec_ct *acc = nullptr;
         hec_status s = HEC_OK;
         for (size_t t = 0; t < js.size(); t++) {
@@ -777,12 +877,14 @@ static hec_status pool_reduce(hec_ctx *c, const hec_ct *D, const Layout &L, cons
         *out = acc;
         return HEC_OK;
     }
-    std::vector<std::vector<hec_pt *>> hm(1), vm(1);
     std::vector<std::pair<uint32_t, uint32_t>> ij, jj;
     for (uint32_t i = 0; i < Wo; i++) ij.push_back({i, 0});
-    HEC_CHECK(get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], hm[0], part));
     std::vector<hec_ct *> M1;
-    HEC_CHECK(rot_masked_sums(c, D, hs, hm, lazy, M1));
+    HEC_CHECK(pool_stage(c, D, hs, 1, 1, mode,
+                         [&](size_t, const std::vector<int32_t> *rolls, std::vector<hec_pt *> &m) {
+                             return get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], m, part, rolls);
+                         },
+                         M1));
     hec_status s = ct_rescale(c, M1[0]);
     if (s == HEC_OK && M1[0]->level < 1) s = HEC_ELEVEL, hec_set_error("separable pooling needs two levels");
     if (s != HEC_OK) { free_all(M1); return s; }
@@ -792,9 +894,12 @@ static hec_status pool_reduce(hec_ctx *c, const hec_ct *D, const Layout &L, cons
         vs.push_back((int32_t)(3 * j * mp / 2));
         jj.push_back({0, j});
     }
-    s = get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], vm[0], part);
     std::vector<hec_ct *> M2;
-    if (s == HEC_OK) s = rot_masked_sums(c, M1[0], vs, vm, lazy, M2);
+    s = pool_stage(c, M1[0], vs, (int32_t)(3 * mp / 2), 1, mode,
+                   [&](size_t, const std::vector<int32_t> *rolls, std::vector<hec_pt *> &m) {
+                       return get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], m, part, rolls);
+                   },
+                   M2);
     free_all(M1);
     HEC_CHECK(s);
     s = ct_rescale(c, M2[0]);
@@ -804,7 +909,7 @@ static hec_status pool_reduce(hec_ctx *c, const hec_ct *D, const Layout &L, cons
 }
 
 static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                             bool lazy, std::vector<hec_ct *> &out, Layout &nl)
+                             int mode, std::vector<hec_ct *> &out, Layout &nl)
 {
     const uint32_t mp = L.mp;
     uint32_t Ho, Wo;
@@ -834,7 +939,7 @@ static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const 
         std::vector<uint32_t> js;
         for (uint32_t j = 0; j < Ho; j++) js.push_back(j);
         hec_ct *o = nullptr;
-        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, lazy, -1, &o);
+        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, mode, -1, &o);
         ct_free(D);
         HEC_CHECK(s);
         out.push_back(o);
@@ -873,7 +978,7 @@ static hec_status duplicate(hec_ctx *c, hec_ct *ct, Layout &L, uint32_t d, hec_c
 // rows that belong to the channel goes to column i, the left half of local row
 // 2j to j*mp/2.  A shard below the channel's last row pools to zero.
 static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                     bool lazy, std::vector<hec_ct *> &out)
+                                     int mode, std::vector<hec_ct *> &out)
 {
     const uint32_t mp = L.mp, R = L.R();
     uint32_t Wo;
@@ -923,7 +1028,7 @@ static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in
         std::vector<int32_t> hs;
         for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
         hec_ct *o = nullptr;
-        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, lazy, part, &o);
+        hec_status s = pool_reduce(c, D, L, hs, js, Wo, val, lvl, fused, mode, part, &o);
         ct_free(D);
         HEC_CHECK(s);
         out.push_back(o);
@@ -977,18 +1082,18 @@ static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Lay
 }
 
 static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                       bool lazy, std::vector<hec_ct *> &out, Layout &ol)
+                                       int mode, std::vector<hec_ct *> &out, Layout &ol)
 {
     std::vector<hec_ct *> ds;
     if (L.channel) {
-        HEC_CHECK(downsample_channel(c, in, L, select, lazy, ds));
+        HEC_CHECK(downsample_channel(c, in, L, select, mode, ds));
         const uint32_t H2 = select ? (L.H + 1) / 2 : L.H / 2, W2 = select ? (L.W + 1) / 2 : L.W / 2;
         hec_status s = merge_channel(c, ds, L, H2, W2, out, ol);
         free_all(ds);
         return s;
     }
     Layout nl;
-    HEC_CHECK(downsample(c, in, L, select, lazy, ds, nl));
+    HEC_CHECK(downsample(c, in, L, select, mode, ds, nl));
     const size_t t = ds.size();
     out.clear();
     if (t == 1) {
@@ -1299,7 +1404,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         im->lay = p->out;
         im->shards = acc;
     } else {
-        s = downsample_and_merge(c, acc, p->out, true, p->mode >= 2, im->shards, im->lay);
+        s = downsample_and_merge(c, acc, p->out, true, p->mode >= 2 ? p->mode : 0, im->shards, im->lay);
         free_all(acc);
         if (s != HEC_OK) { hec_image_free(im); return s; }
     }
@@ -1331,7 +1436,8 @@ extern "C" hec_status he_avgpool_ex(hec_ctx *c, const hec_image *in, uint32_t wi
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
-    if (mode != 0 && mode != 2) HEC_FAIL(HEC_EINVAL, "pooling mode must be 0 (per rotation) or 2 (lazy ModDown)");
+    if (mode != 0 && mode != 2 && mode != 3)
+        HEC_FAIL(HEC_EINVAL, "pooling mode must be 0 (per rotation), 2 (lazy ModDown) or 3 (baby-step/giant-step)");
     if (window != 2) HEC_FAIL(HEC_EINVAL, "only 2x2 pooling is supported");
     if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     HEC_TRY_HIP(hipSetDevice(c->dev));
@@ -1341,7 +1447,7 @@ extern "C" hec_status he_avgpool_ex(hec_ctx *c, const hec_image *in, uint32_t wi
         if (!have_rotkey(c, s)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", s);
     hec_image *im = new hec_image();
     im->ctx = c;
-    hec_status s = downsample_and_merge(c, in->shards, in->lay, false, mode == 2, im->shards, im->lay);
+    hec_status s = downsample_and_merge(c, in->shards, in->lay, false, mode, im->shards, im->lay);
     if (s != HEC_OK) { hec_image_free(im); return s; }
     *out = im;
     return HEC_OK;

@@ -156,8 +156,8 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
             ref = hl.ref_conv2d(ref, w, pad, stride)
         else:
             ctx.gen_rotation_keys(ctx.avgpool_steps(img))
-            img = ctx.avgpool(img, mode=min(mode, 2))
-            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode >= 2))
+            img = ctx.avgpool(img, mode=mode if mode >= 2 else 0)
+            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode == 2), bsgs=(mode == 3))
             ref = hl.ref_avgpool2x2(ref)
         Cn, Hn, Wn, mp, t = img.info()
         assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
@@ -245,6 +245,9 @@ def test_layers_lazy_moddown_bit_exact(small, shape, ops):
     ((2, 32, 32), [("conv", (3, 3), 1), ("pool",)]),                # channel shards: baby 0 only
     ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem in channel shards
     ((3, 12, 12), [("conv", (5, 5), 1)]),                           # 5x5 kernel, padded channels
+    ((8, 16, 16), [("pool",), ("conv", (8, 3), 1)]),                # 4 shards pooled by baby/giant steps
+    ((1, 64, 64), [("pool",), ("conv", (2, 3), 1)]),                # channel shards pooled
+    ((4, 8, 8), [("pool",), ("pool",)]),                            # the second pool fused (one level)
 ])
 def test_layers_bsgs_bit_exact(small, shape, ops):
     ctx, prm, o = small
@@ -261,7 +264,8 @@ def test_layers_bsgs_bit_exact(small, shape, ops):
             real_ops.append(op)
     log("bsgs layers", shape, [op[0] for op in ops])
     pad = 2 if shape == (3, 12, 12) else 1
-    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=43, mode=3, pad=pad)
+    level = 3 if ops == [("pool",), ("pool",)] else 6
+    run_pipeline(ctx, prm, o, x, real_ops, level, seed=43, mode=3, pad=pad)
 
 
 def test_lazy_zero_rotation_only(small):
@@ -290,9 +294,10 @@ def test_plan_mode_rejected(small):
     with pytest.raises(hecnn.HecError) as e:
         plan.set_mode(4)
     assert e.value.status == hecnn.HEC_EINVAL
-    with pytest.raises(hecnn.HecError) as e:
-        ctx.avgpool(img, mode=1)
-    assert e.value.status == hecnn.HEC_EINVAL
+    for bad in (1, 4):
+        with pytest.raises(hecnn.HecError) as e:
+            ctx.avgpool(img, mode=bad)
+        assert e.value.status == hecnn.HEC_EINVAL
 
 
 def test_plain_equals_batched(small):

@@ -213,3 +213,49 @@ def test_bsgs_split_identity():
             assert (b + g - a) % N == 0 and b % lay.B == 0
             for vec in pts.values():
                 assert np.allclose(vec * rot(x, a), rot(np.roll(vec, g) * rot(x, b), g))
+
+
+def test_bsgs_split():
+    assert hl.bsgs_split(list(range(16)), 1)[:6] == [(0, 0), (1, 0), (2, 0), (3, 0), (0, 4), (1, 4)]
+    sp = hl.bsgs_split([24 * j for j in range(9)], 24)      # G = 3
+    assert sp[4] == (24, 72) and sp[8] == (48, 144)
+    for steps, unit in ((list(range(56)), 1), ([6 * j for j in (0, 2, 5, 7)], 6)):
+        for a, (b, g) in zip(steps, hl.bsgs_split(steps, unit)):
+            assert a == b + g and b % unit == 0 and g % unit == 0
+
+
+def test_bsgs_pooling(small, monkeypatch):
+    """Pooling (separable, fused, channel shards) with the masked rotation
+    sums evaluated by baby and giant steps (threshold lowered so that the
+    small shapes take that path)."""
+    p, o = small
+    monkeypatch.setattr(hl, "BSGS_MIN_STEPS", 2)
+    rng = np.random.default_rng(12)
+    be = hl.CkksBackend(o)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    for fused, lvl_out in ((False, 4), (True, 5)):
+        cts = enc_image(o, x, lay, 6, 2.0 ** 40, 23)
+        a, al = hl.avgpool2x2(be, cts, lay, fused=fused, bsgs=True)
+        b, _ = hl.avgpool2x2(be, cts, lay, fused=fused, lazy=True)
+        assert a[0].level == lvl_out
+        assert not (a[0].data == b[0].data).all()
+        assert np.abs(dec_image(o, a, al) - hl.ref_avgpool2x2(x)).max() < 1e-5
+    xc = rng.uniform(-1, 1, (1, 32, 32))
+    lc = hl.natural_layout(p.N, 1, 32, 32)
+    cc = enc_image(o, xc, lc, 6, 2.0 ** 40, 24)
+    a, al = hl.avgpool2x2(be, cc, lc, bsgs=True)
+    assert np.abs(dec_image(o, a, al) - hl.ref_avgpool2x2(xc)).max() < 1e-5
+
+
+def test_bsgs_pooling_threshold(small):
+    """Below BSGS_MIN_STEPS amounts the baby-step / giant-step mode pools
+    exactly like the lazy mode."""
+    p, o = small
+    x = np.random.default_rng(13).uniform(-1, 1, (4, 8, 8))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    be = hl.CkksBackend(o)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 25)
+    a, _ = hl.avgpool2x2(be, cts, lay, bsgs=True)
+    b, _ = hl.avgpool2x2(be, cts, lay, lazy=True)
+    assert (a[0].data == b[0].data).all()
