@@ -221,6 +221,18 @@ hec_status he_avgpool(hec_ctx *ctx, const hec_image *in, uint32_t window, hec_im
  * modes 2 and 3 use the same mode for their stride-2 downsampling. */
 hec_status he_avgpool_ex(hec_ctx *ctx, const hec_image *in, uint32_t window, int mode, hec_image **out);
 
+/* Linear layer (Section 4.3, "Linear"): W is [O][C*H*W] over the input in
+ * its logical [C][H][W] order (pool = 0), or [O][C] for the pool-linear layer
+ * (pool = 1: global average pooling folded into the weights as W[o][f]/(H*W)
+ * on every valid position of channel f).  Output o is the dot product of its
+ * weights with the image: the shard products are summed and rescaled, the
+ * slots summed by rotate-and-add (rotations N/2, ..., 2, 1, keys from
+ * he_linear_steps), and the result masked onto slot o; the O masked results
+ * are summed into *out (one ciphertext, two levels consumed, O <= N).  A
+ * channel held in several blocks is read from its first block only. */
+hec_status he_linear(hec_ctx *ctx, const hec_image *in, const double *W, uint32_t O, int pool, hec_ct **out);
+hec_status he_linear_steps(hec_ctx *ctx, const hec_image *like, int32_t *steps, size_t cap, size_t *count);
+
 void hec_ct_free(hec_ct *ct);
 void hec_pt_free(hec_pt *pt);
 void hec_image_free(hec_image *img);

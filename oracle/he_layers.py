@@ -800,6 +800,90 @@ def avgpool2x2(be, cts, lay, fused=None, lazy=False, bsgs=False):
 
 
 # ---------------------------------------------------------------------------
+# linear and pool-linear layers (Section 4.3, "Linear")
+# ---------------------------------------------------------------------------
+
+def linear_vectors(lay, W, pool=False):
+    """Per output o and shard u: the slot vector that multiplies shard u for
+    output o (None where it is zero).  Linear: W is [O][C*H*W] over the input
+    in [C][H][W] order; pool-linear: W is [O][C] and every valid position of
+    channel f carries W[o][f] / (H*W) (the global average pool folded into the
+    weights).  A channel held in several blocks (duplicated copies) is read
+    from its first block in shard-then-block order only."""
+    W = np.asarray(W, dtype=np.float64)
+    O = W.shape[0]
+    C, H, Wd, N, mp = lay.C, lay.H, lay.W, lay.N, lay.mp
+    if pool:
+        if W.shape[1] != C:
+            raise ValueError("pool-linear weights must be [O][C]")
+        Wf = np.repeat(W / float(H * Wd), H * Wd, axis=1).reshape(O, C, H, Wd)
+    else:
+        if W.shape[1] != C * H * Wd:
+            raise ValueError("linear weights must be [O][C*H*W]")
+        Wf = W.reshape(O, C, H, Wd)
+    vecs = [[None] * len(lay.shards) for _ in range(O)]
+    if lay.kind == "channel":
+        R = N // mp
+        for u, (f, part) in enumerate(lay.shards):
+            rows = [r for r in range(R) if part * R + r < H]
+            if not rows:
+                continue
+            for o in range(O):
+                v = np.zeros(N)
+                for r in rows:
+                    v[r * mp: r * mp + Wd] = Wf[o, f, part * R + r]
+                vecs[o][u] = v
+        return vecs
+    seen = set()
+    place = []
+    for u, lam in enumerate(lay.shards):
+        for b, f in enumerate(lam):
+            if f >= 0 and f not in seen:
+                seen.add(f)
+                place.append((u, b, f))
+    if len(seen) != C:
+        raise ValueError("channel missing from the layout")
+    for o in range(O):
+        for u, b, f in place:
+            if vecs[o][u] is None:
+                vecs[o][u] = np.zeros(N)
+            blk = np.zeros((mp, mp))
+            blk[:H, :Wd] = Wf[o, f]
+            vecs[o][u][b * lay.B:(b + 1) * lay.B] = blk.reshape(-1)
+    return vecs
+
+
+def linear(be, cts, lay, W, pool=False):
+    """Each output o: the products of the shards with its weight vectors are
+    summed and rescaled, then summed over all slots by rotate-and-add with
+    rotations N/2, N/4, ..., 1 (every slot then holds the dot product), and
+    masked onto slot o; the masked outputs are summed into one ciphertext and
+    rescaled.  Two levels; output o sits in slot o."""
+    vecs = linear_vectors(lay, W, pool)
+    N = lay.N
+    outs = []
+    for o, per_shard in enumerate(vecs):
+        prods = [be.mul_plain(cts[u], v, be.q(be.level(cts[u]))) for u, v in enumerate(per_shard) if v is not None]
+        acc = be.rescale(_sum(be, prods))
+        k = N // 2
+        while k >= 1:
+            acc = be.add(acc, be.rotate(acc, k))
+            k //= 2
+        e = np.zeros(N)
+        e[o] = 1.0
+        outs.append(be.mul_plain(acc, e, be.q(be.level(acc))))
+    return be.rescale(_sum(be, outs))
+
+
+def ref_linear(x, W, pool=False):
+    """FP64 reference: W @ x.flatten(), or W @ mean over H, W (pool-linear)."""
+    x = np.asarray(x, dtype=np.float64)
+    if pool:
+        return np.asarray(W, dtype=np.float64) @ x.mean(axis=(1, 2))
+    return np.asarray(W, dtype=np.float64) @ x.reshape(-1)
+
+
+# ---------------------------------------------------------------------------
 # FP64 references (PyTorch semantics)
 # ---------------------------------------------------------------------------
 

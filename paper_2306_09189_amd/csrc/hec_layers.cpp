@@ -1466,3 +1466,143 @@ extern "C" hec_status he_avgpool_steps(hec_ctx *c, const hec_image *like, int32_
     }
     return HEC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// linear and pool-linear layers (Section 4.3, "Linear")
+// ---------------------------------------------------------------------------
+// Slot vectors of the weights: vec[o][u] multiplies shard u for output o
+// (empty = zero).  Linear: W is [O][C*H*W] over the input in [C][H][W] order;
+// pool-linear: W is [O][C], and every valid position of channel f carries
+// W[o][f] / (H*W).  A channel held in several blocks is read from its first
+// block in shard-then-block order only.
+static hec_status linear_vectors(const Layout &L, const double *W, uint32_t O, bool pool,
+                                 std::vector<std::vector<std::vector<double>>> &vec)
+{
+    const uint32_t C = L.C, H = L.H, Wd = L.W, N = L.N, mp = L.mp;
+    auto weight = [&](uint32_t o, uint32_t f, uint32_t i, uint32_t j) {
+        return pool ? W[(size_t)o * C + f] / (double)(H * Wd) : W[(((size_t)o * C + f) * H + i) * Wd + j];
+    };
+    vec.assign(O, std::vector<std::vector<double>>(L.shards()));
+    if (L.channel) {
+        const uint32_t R = L.R();
+        for (size_t u = 0; u < L.cs.size(); u++) {
+            const uint32_t f = (uint32_t)L.cs[u].first, part = (uint32_t)L.cs[u].second;
+            if (part * R >= H) continue;
+            for (uint32_t o = 0; o < O; o++) {
+                std::vector<double> v(N, 0.0);
+                for (uint32_t r = 0; r < R && part * R + r < H; r++)
+                    for (uint32_t j = 0; j < Wd; j++) v[(size_t)r * mp + j] = weight(o, f, part * R + r, j);
+                vec[o][u] = std::move(v);
+            }
+        }
+        return HEC_OK;
+    }
+    std::vector<char> seen(C, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> place;  // (shard, block) per first occurrence
+    std::vector<uint32_t> chan;
+    for (uint32_t u = 0; u < L.maps.size(); u++)
+        for (uint32_t b = 0; b < L.nb(); b++) {
+            const int32_t f = L.maps[u][b];
+            if (f >= 0 && !seen[f]) {
+                seen[f] = 1;
+                place.push_back({u, b});
+                chan.push_back((uint32_t)f);
+            }
+        }
+    if (place.size() != C) HEC_FAIL(HEC_ELAYOUT, "channel missing from the layout");
+    for (uint32_t o = 0; o < O; o++)
+        for (size_t t = 0; t < place.size(); t++) {
+            auto &v = vec[o][place[t].first];
+            if (v.empty()) v.assign(N, 0.0);
+            const size_t base = (size_t)place[t].second * L.B();
+            for (uint32_t i = 0; i < H; i++)
+                for (uint32_t j = 0; j < Wd; j++) v[base + (size_t)i * mp + j] = weight(o, chan[t], i, j);
+        }
+    return HEC_OK;
+}
+
+extern "C" hec_status he_linear_steps(hec_ctx *c, const hec_image *like, int32_t *steps, size_t cap, size_t *count)
+{
+    if (!c || !like) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    std::vector<int32_t> st;
+    for (uint32_t k = c->N / 2; k >= 1; k /= 2) st.push_back((int32_t)k);
+    if (count) *count = st.size();
+    if (steps) {
+        if (cap < st.size()) HEC_FAIL(HEC_EINVAL, "capacity too small");
+        for (size_t i = 0; i < st.size(); i++) steps[i] = st[i];
+    }
+    return HEC_OK;
+}
+
+extern "C" hec_status he_linear(hec_ctx *c, const hec_image *in, const double *W, uint32_t O, int pool, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !in || !W || !O) HEC_FAIL(HEC_EINVAL, "bad linear arguments");
+    if (O > c->N) HEC_FAIL(HEC_EINVAL, "more outputs than slots");
+    if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    const uint32_t lvl = in->shards[0]->level;
+    for (auto *s : in->shards)
+        if (s->level != lvl || s->scale != in->shards[0]->scale) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
+    if (lvl < 2) HEC_FAIL(HEC_ELEVEL, "the linear layer needs two levels");
+    for (uint32_t k = c->N / 2; k >= 1; k /= 2)
+        if (!have_rotkey(c, (int32_t)k)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %u", k);
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    std::vector<std::vector<std::vector<double>>> vec;
+    HEC_CHECK(linear_vectors(in->lay, W, O, pool != 0, vec));
+    // weight plaintexts at scale q_l, one-hot masks at scale q_{l-1}
+    std::vector<const double *> zp;
+    std::vector<std::pair<uint32_t, uint32_t>> which;
+    for (uint32_t o = 0; o < O; o++)
+        for (uint32_t u = 0; u < vec[o].size(); u++)
+            if (!vec[o][u].empty()) {
+                zp.push_back(vec[o][u].data());
+                which.push_back({o, u});
+            }
+    std::vector<hec_pt *> wpts, mpts;
+    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], wpts));
+    std::vector<std::vector<double>> onehot(O, std::vector<double>(c->N, 0.0));
+    std::vector<const double *> mz;
+    for (uint32_t o = 0; o < O; o++) {
+        onehot[o][o] = 1.0;
+        mz.push_back(onehot[o].data());
+    }
+    hec_status s = pt_encode_many(c, mz, c->N, lvl - 1, (double)c->mod[lvl - 1], mpts);
+    hec_ct *res = nullptr;
+    size_t w = 0;
+    for (uint32_t o = 0; o < O && s == HEC_OK; o++) {
+        hec_ct *acc = ct_new(c, lvl, 1.0);
+        if (!acc) { s = HEC_ENOMEM; hec_set_error("ciphertext allocation"); break; }
+        bool first = true;
+        for (; w < which.size() && which[w].first == o && s == HEC_OK; w++) {
+            s = ct_mac_pt(c, acc, in->shards[which[w].second], wpts[w], first);
+            first = false;
+        }
+        if (s == HEC_OK && first) s = HEC_ELAYOUT, hec_set_error("output %u has no weights", o);
+        if (s == HEC_OK) s = ct_rescale(c, acc);
+        // rotate-and-add over all slots: every slot ends with the dot product
+        for (uint32_t k = c->N / 2; k >= 1 && s == HEC_OK; k /= 2) {
+            hec_ct *r = nullptr;
+            s = ckks_rotate(c, acc, (int32_t)k, &r);
+            if (s == HEC_OK) s = ct_add_inplace(c, acc, r);
+            ct_free(r);
+        }
+        if (s == HEC_OK) {
+            hec_ct *m = ct_new(c, acc->level, 1.0);
+            if (!m) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+            else s = ct_mac_pt(c, m, acc, mpts[o], true);
+            if (s == HEC_OK) s = sum_into(c, res, m);
+            else ct_free(m);
+        }
+        ct_free(acc);
+    }
+    if (s == HEC_OK) s = ct_rescale(c, res);
+    for (auto *p : wpts) pt_free(p);
+    for (auto *p : mpts) pt_free(p);
+    if (s != HEC_OK) {
+        ct_free(res);
+        return s;
+    }
+    *out = res;
+    return HEC_OK;
+}

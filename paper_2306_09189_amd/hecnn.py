@@ -21,7 +21,7 @@ EXPORTS = [
     "ckks_ct_import", "ckks_pt_export", "ckks_pt_import", "ckks_encode_coeffs", "he_image_encrypt",
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
-    "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "hec_ct_free", "hec_pt_free", "hec_image_free",
+    "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
 ]
 
@@ -94,6 +94,8 @@ def lib():
             "he_conv2d_plan_set_mode": (c, [vp, c]),
             "he_conv2d_plan_steps": (c, [vp, i32p, sz, szp]),
             "he_avgpool_steps": (c, [vp, vp, i32p, sz, szp]),
+            "he_linear_steps": (c, [vp, vp, i32p, sz, szp]),
+            "he_linear": (c, [vp, vp, dblp, u32, c, P(vp)]),
             "he_conv2d_plan_free": (None, [vp]),
             "he_avgpool": (c, [vp, vp, u32, P(vp)]),
             "he_avgpool_ex": (c, [vp, vp, u32, c, P(vp)]),
@@ -414,6 +416,20 @@ class Context:
         check(lib().he_avgpool_steps(self.h, img.h, None, 0, ctypes.byref(n)))
         out = np.zeros(n.value, dtype=np.int32)
         check(lib().he_avgpool_steps(self.h, img.h, _p(out, i32p), len(out), ctypes.byref(n)))
+        return [int(x) for x in out]
+
+    def linear(self, img, W, pool=False):
+        """Linear (W [O][C*H*W]) or pool-linear (W [O][C]) layer: one ciphertext, output o in slot o."""
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        out = vp()
+        check(lib().he_linear(self.h, img.h, _p(W, dblp), W.shape[0], int(bool(pool)), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def linear_steps(self, img):
+        n = ctypes.c_size_t()
+        check(lib().he_linear_steps(self.h, img.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        check(lib().he_linear_steps(self.h, img.h, _p(out, i32p), len(out), ctypes.byref(n)))
         return [int(x) for x in out]
 
     def sync(self):

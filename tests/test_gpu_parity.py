@@ -325,3 +325,26 @@ def test_ring_2e13_conv_pool():
     w = rng.normal(0, 0.1, (4, 4, 3, 3))
     run_pipeline(ctx, prm, o, x, [("conv", w, 1), ("pool",)], 2, seed=3001)
     run_pipeline(ctx, prm, o, x, [("conv", w, 1), ("pool",)], 2, seed=3002, mode=2)
+
+
+@pytest.mark.parametrize("shape,pool,O", [((4, 8, 8), False, 3), ((4, 8, 8), True, 5), ((8, 16, 16), True, 10),
+                                          ((1, 32, 32), True, 4)])
+def test_linear_bit_exact(small, shape, pool, O):
+    """Linear and pool-linear layers (rotate-and-add dot products) bit-exact
+    with the oracle; decrypted within 1e-5 of W @ x."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + O)
+    x = rng.uniform(-1, 1, shape)
+    C, H, W = shape
+    Wt = rng.normal(0, 0.1, (O, C) if pool else (O, C * H * W))
+    img = ctx.image_encrypt(x, 5, 47)
+    ctx.gen_rotation_keys(ctx.linear_steps(img))
+    out = ctx.linear(img, Wt, pool)
+    lay = hl.natural_layout(prm.N, C, H, W)
+    cts = [o.encrypt(o.encode(v, 5, 2.0 ** prm_log_scale(ctx)), seed=47, index=u)
+           for u, v in enumerate(hl.pack(x, lay))]
+    ref = hl.linear(hl.CkksBackend(o), cts, lay, Wt, pool)
+    assert out.info() == (ref.level, ref.scale)
+    assert (out.export() == ref.data).all()
+    got = ctx.decrypt(out)
+    assert np.abs(got[:O] - hl.ref_linear(x, Wt, pool)).max() < 1e-5

@@ -259,3 +259,21 @@ def test_bsgs_pooling_threshold(small):
     a, _ = hl.avgpool2x2(be, cts, lay, bsgs=True)
     b, _ = hl.avgpool2x2(be, cts, lay, lazy=True)
     assert (a[0].data == b[0].data).all()
+
+
+def test_linear_and_pool_linear(small):
+    """Linear (dot products by rotate-and-add over all slots, outputs masked
+    into slots 0..O-1) and pool-linear, decrypted within 1e-5 of W @ x."""
+    p, o = small
+    rng = np.random.default_rng(14)
+    be = hl.CkksBackend(o)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 26)
+    for pool, O in ((False, 3), (True, 5)):
+        W = rng.normal(0, 0.1, (O, 4) if pool else (O, 4 * 64))
+        out = hl.linear(be, cts, lay, W, pool)
+        assert out.level == 4 and out.scale == 2.0 ** 40
+        got = o.decrypt(out)
+        assert np.abs(got[:O] - hl.ref_linear(x, W, pool)).max() < 1e-5
+        assert np.abs(got[O:]).max() < 1e-5

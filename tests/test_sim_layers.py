@@ -207,3 +207,23 @@ def test_channel_shard_stem_then_image_conv():
     b, bl = hl.conv2d(be, a, al, w2, pad=1)
     ref = hl.ref_conv2d(hl.ref_conv2d(x, w1, 1, 2), w2, 1)
     assert np.abs(hl.unpack([o[0] for o in b], bl) - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("shape,pool", [((4, 8, 8), False), ((4, 8, 8), True), ((8, 16, 16), True),
+                                        ((2, 4, 4), False), ((1, 32, 32), True), ((1, 32, 32), False)])
+def test_linear_slot_sim(shape, pool):
+    """Linear and pool-linear on cleartext slots equal W @ x (duplicated,
+    multi-shard and channel-shard layouts)."""
+    N = 256
+    rng = np.random.default_rng(sum(shape) + pool)
+    x = rng.uniform(-1, 1, shape)
+    C, H, W = shape
+    O = 5
+    Wt = rng.normal(0, 0.1, (O, C) if pool else (O, C * H * W))
+    lay = hl.natural_layout(N, C, H, W)
+    sim = hl.SlotSim(N, [2.0 ** 40] * 10)
+    cts = [(v, 6, 2.0 ** 40) for v in hl.pack(x, lay)]
+    out = hl.linear(sim, cts, lay, Wt, pool)
+    assert out[1] == 4
+    assert np.allclose(out[0][:O], hl.ref_linear(x, Wt, pool), atol=1e-12)
+    assert np.allclose(out[0][O:], 0)
