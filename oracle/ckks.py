@@ -83,6 +83,7 @@ def _declare(L):
         "orc_keygen_secret": (None, [P, u64, i64p]),
         "orc_keygen_pk": (None, [P, u64, dbl, i64p, u64p]),
         "orc_keygen_swk": (None, [P, u64, dbl, i64p, u32, u64p]),
+        "orc_keygen_relin": (None, [P, u64, dbl, i64p, u64p]),
         "orc_encrypt": (None, [P, u64p, dbl, u64p, u32, u64, u64, u64p]),
         "orc_decrypt": (None, [P, i64p, u64p, u32, u64p]),
         "orc_modup": (None, [P, u32, u32, u64p, u64p]),
@@ -170,6 +171,7 @@ class Oracle:
         self.pk = np.zeros((2, params.L + 1, n), dtype=np.uint64)
         lib().orc_keygen_pk(params.cref, seed, params.sigma, ptr(self.s, i64p), ptr(self.pk))
         self._swk = {}
+        self._rlk = None
 
     # ---- keys -----------------------------------------------------------
     def swk(self, g):
@@ -184,6 +186,19 @@ class Oracle:
             lib().orc_ntt_limbs(p.cref, ptr(pidx, u32p), 2 * p.dnum * nl, ptr(kn))
             self._swk[g] = (k, kn)
         return self._swk[g]
+
+    def relin_key(self):
+        """Relinearization key (s^2 target), coefficient and NTT forms [dnum][2][L+1+k][n]."""
+        if self._rlk is None:
+            p = self.p
+            nl = p.L + 1 + p.k
+            k = np.zeros((p.dnum, 2, nl, p.n), dtype=np.uint64)
+            lib().orc_keygen_relin(p.cref, self.seed, p.sigma, ptr(self.s, i64p), ptr(k))
+            kn = k.copy()
+            pidx = u32arr(list(range(nl)) * (2 * p.dnum))
+            lib().orc_ntt_limbs(p.cref, ptr(pidx, u32p), 2 * p.dnum * nl, ptr(kn))
+            self._rlk = (k, kn)
+        return self._rlk
 
     # ---- encoding ---------------------------------------------------------
     def encode_coeffs(self, z, scale):
@@ -351,4 +366,69 @@ class Oracle:
         """[l+1+k][n] over Q_l and P -> [l+1][n] over Q_l (floor ModDown)."""
         out = np.zeros((level + 1, self.p.n), dtype=np.uint64)
         lib().orc_moddown(self.p.cref, level, ptr(np.ascontiguousarray(x)), ptr(out))
+        return out
+
+    # ---- ciphertext products (tensor product and relinearization) -----------
+    def mul_ct(self, a, b):
+        """a * b for ciphertexts at one level: (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0,
+        a1 b1), then d2 key-switched from s^2 to s with the relinearization key:
+        (d0 + ModDown(e0), d1 + ModDown(e1)), e = sum_j ModUp_j(d2) * rlk_j.
+        Scale a.scale * b.scale; not rescaled."""
+        if a.level != b.level:
+            raise ValueError("level mismatch")
+        lvl = a.level
+        qi = list(range(lvl + 1))
+        d0 = self.mul_limbs(qi, a.data[0], b.data[0])
+        d1 = self.add_limbs(qi, self.mul_limbs(qi, a.data[0], b.data[1]), self.mul_limbs(qi, a.data[1], b.data[0]))
+        d2 = self.mul_limbs(qi, a.data[1], b.data[1])
+        p = self.p
+        nqp = lvl + 1 + p.k
+        e = np.zeros((2, nqp, p.n), dtype=np.uint64)
+        tmp = np.ascontiguousarray(np.stack([d0, d2]))   # the key switch reads the second polynomial
+        gs = u32arr([1])
+        kp = (u64p * 1)(ptr(self.relin_key()[1]))
+        op = (u64p * 1)(ptr(e))
+        lib().orc_keyswitch_raw(p.cref, lvl, ptr(tmp), 1, ptr(gs, u32p), kp, op)
+        data = np.stack([self.add_limbs(qi, d0, self.moddown(lvl, e[0])),
+                         self.add_limbs(qi, d1, self.moddown(lvl, e[1]))])
+        return Ct(data, lvl, a.scale * b.scale)
+
+    def const_coeffs(self, value, scale):
+        """A constant in every slot encodes as the constant polynomial
+        round_half_away(value * scale) (both doubles; the product taken exactly)."""
+        from fractions import Fraction
+        x = Fraction(float(value)) * Fraction(float(scale))
+        r = int(abs(x) + Fraction(1, 2))          # floor(|x| + 1/2): half away from zero
+        r = r if x >= 0 else -r
+        if abs(r) >= 1 << 62:
+            raise OverflowError("constant exceeds 2^62")
+        m = np.zeros(self.p.n, dtype=np.int64)
+        m[0] = r
+        return m
+
+    def add_const(self, ct, value, scale=None):
+        """ct + value (a constant in every slot), encoded at the ciphertext's scale."""
+        m = self.const_coeffs(value, ct.scale if scale is None else scale)
+        pt = self.limbs_of(m, ct.level)
+        qi = list(range(ct.level + 1))
+        return Ct(np.stack([self.add_limbs(qi, ct.data[0], pt), ct.data[1].copy()]), ct.level, ct.scale)
+
+    def mul_const(self, ct, value, pscale):
+        """ct * value (constant in every slot) encoded at pscale; scale ct.scale * pscale."""
+        m = self.const_coeffs(value, pscale)
+        return self.mul_pt(ct, Pt(self.limbs_of(m, ct.level), ct.level, pscale))
+
+    def sub(self, a, b):
+        if a.level != b.level or a.scale != b.scale:
+            raise ValueError("level or scale mismatch")
+        qi = list(range(a.level + 1))
+        return Ct(np.stack([self.add_limbs(qi, a.data[t], self.neg_limbs(qi, b.data[t])) for t in range(2)]),
+                  a.level, a.scale)
+
+    def neg_limbs(self, pidx, x):
+        out = np.zeros_like(x)
+        for i, l in enumerate(pidx):
+            q = np.uint64(self.p.mod[l])
+            nz = x[i] != 0
+            out[i][nz] = q - x[i][nz]
         return out

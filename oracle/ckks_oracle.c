@@ -587,6 +587,46 @@ void orc_keygen_swk(const orc_params *p, uint64_t seed, double sigma, const int6
     free(sr); free(sg); free(e);
 }
 
+/* Relinearization key: the key-switching key of orc_keygen_swk with s^2 in
+ * place of sigma_g(s) (the target of the d2 s^2 term of a product), random
+ * streams indexed by the digit alone (Galois elements are odd, so the index
+ * (g << 8) | j of a rotation key never takes these values). */
+void orc_keygen_relin(const orc_params *p, uint64_t seed, double sigma, const int64_t *s, uint64_t *rlk)
+{
+    uint32_t n = p->n, nl = p->L + 1 + p->k;
+    uint32_t pidx[ORC_MAXP];
+    for (uint32_t i = 0; i < nl; i++) pidx[i] = i;
+    uint64_t *sr = malloc(sizeof(uint64_t) * n * nl), *s2 = malloc(sizeof(uint64_t) * n * nl);
+    orc_reduce_small(p, s, pidx, nl, sr);
+#pragma omp parallel for
+    for (uint32_t l = 0; l < nl; l++)
+        orc_polymul(sr + (size_t)l * n, sr + (size_t)l * n, s2 + (size_t)l * n, n, p->mod[l], p->psi[l]);
+    int64_t *e = malloc(sizeof(int64_t) * n);
+    for (uint32_t j = 0; j < p->dnum; j++) {
+        uint64_t *b = rlk + (size_t)j * 2 * nl * n, *a = b + (size_t)nl * n;
+        orc_sample_uniform(p, seed, P_SWK_A, j, pidx, nl, a);
+        orc_sample_gauss(seed, P_SWK_E, j, n, sigma, e);
+        uint64_t *er = malloc(sizeof(uint64_t) * n * nl);
+        orc_reduce_small(p, e, pidx, nl, er);
+#pragma omp parallel for
+        for (uint32_t l = 0; l < nl; l++) {
+            uint64_t q = p->mod[l];
+            size_t o = (size_t)l * n;
+            orc_polymul(a + o, sr + o, b + o, n, q, p->psi[l]);
+            uint64_t Pm = 1;
+            for (uint32_t t = 0; t < p->k; t++) Pm = orc_mulmod(Pm, p->mod[p->L + 1 + t] % q, q);
+            int in_digit = l <= p->L && l / p->alpha == j;
+            for (uint32_t t = 0; t < n; t++) {
+                uint64_t v = addmod(submod(0, b[o + t], q), er[o + t], q);
+                if (in_digit) v = addmod(v, orc_mulmod(Pm, s2[o + t], q), q);
+                b[o + t] = v;
+            }
+        }
+        free(er);
+    }
+    free(sr); free(s2); free(e);
+}
+
 /* ct = (v b + e0 + m, v a + e1) restricted to q_0..q_level; m is [level+1][n] */
 void orc_encrypt(const orc_params *p, const uint64_t *pk, double sigma, const uint64_t *m, uint32_t level,
                  uint64_t seed, uint64_t index, uint64_t *ct)

@@ -884,6 +884,177 @@ def ref_linear(x, W, pool=False):
 
 
 # ---------------------------------------------------------------------------
+# polynomial activations in the Chebyshev basis (Section 4.3, GELU)
+# ---------------------------------------------------------------------------
+
+def cheb_divide(c, g):
+    """p = q * T_g + r for p = sum_j c[j] T_j with g <= deg p < 2g, from
+    T_j = 2 T_g T_{j-g} - T_{2g-j} (j > g): q[0] = c[g], q[j-g] = 2 c[j] and
+    r[2g-j] -= c[j] for j > g; r starts as c[0..g-1].  Plain loops in
+    ascending j, so that any implementation doing the same IEEE operations
+    gets the same doubles."""
+    d = len(c) - 1
+    q = [0.0] * (d - g + 1)
+    r = [float(x) for x in c[:g]]
+    q[0] = float(c[g])
+    for j in range(g + 1, d + 1):
+        q[j - g] = 2.0 * float(c[j])
+        r[2 * g - j] = r[2 * g - j] - float(c[j])
+    return q, r
+
+
+def cheb_baby_size(d):
+    """Baby-step size m: the smallest power of two with m * m >= d + 1."""
+    m = 1
+    while m * m < d + 1:
+        m *= 2
+    return m
+
+
+class ChebEval:
+    """Evaluation of p(y) = sum_k c_k T_k(y), y = (2x - (a + b)) / (b - a),
+    on an encrypted x (oracle ciphertexts).
+
+    Scales: every ciphertext at level l carries the nominal scale S[l], with
+    S[l0] the input's scale and S[l-1] = S[l]^2 / q_l, so that the product
+    of two level-l ciphertexts, rescaled, has exactly scale S[l-1].  A
+    constant multiplies at the scale S[l-1] q_l / S[l'] that brings a
+    level-l' operand (l' = l) to S[l-1] after the rescale; level adjustments
+    drop limbs, then multiply by 1 in the same way.  Products, constant
+    products and adjustments set the nominal scale of their result to S[l].
+
+    Basis: T_1 = y, T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_{k+1} T_k - T_1
+    for k < m (m = cheb_baby_size(deg)), and the giant powers T_{2m},
+    T_{4m}, ... by doubling.  A polynomial of degree < m is the sum of
+    c_j T_j (constants folded in by a constant product each); a larger one
+    is split by cheb_divide at the largest giant power g <= deg and
+    evaluated as q(y) T_g + r(y)."""
+
+    def __init__(self, be, x, a, b):
+        self.be, self.o = be, be.o
+        self.S = {x.level: x.scale}
+        l = x.level
+        while l > 0:
+            self.S[l - 1] = (self.S[l] * self.S[l]) / self.o.p.q[l]
+            l -= 1
+        self.a, self.b = float(a), float(b)
+        self.x = x
+
+    def _const_mul(self, ct, value):
+        """ct (level l, scale S[l]) * value -> level l-1, scale S[l-1]."""
+        l = ct.level
+        pscale = self.S[l - 1] * float(self.o.p.q[l]) / self.S[l]
+        r = self.o.rescale(self.o.mul_const(ct, value, pscale))
+        return type(r)(r.data, r.level, self.S[l - 1])
+
+    def adjust(self, ct, level):
+        if ct.level == level:
+            return ct
+        if ct.level < level:
+            raise ValueError("cannot raise a level")
+        return self._const_mul(self.o.drop_to(ct, level + 1), 1.0)
+
+    def mul(self, u, v):
+        l = min(u.level, v.level)
+        u, v = self.adjust(u, l), self.adjust(v, l)
+        r = self.o.rescale(self.o.mul_ct(u, v))
+        assert r.scale == self.S[l - 1]
+        return r
+
+    def add(self, u, v):
+        l = min(u.level, v.level)
+        return self.o.add(self.adjust(u, l), self.adjust(v, l))
+
+    def affine(self):
+        """y = alpha x + beta, alpha = 2 / (b - a), beta = -(a + b) / (b - a)."""
+        alpha = 2.0 / (self.b - self.a)
+        beta = -(self.a + self.b) / (self.b - self.a)
+        y = self._const_mul(self.x, alpha)
+        return self.o.add_const(y, beta)
+
+    def basis(self, y, m, d):
+        T = {1: y}
+        for k in range(2, min(m, d + 1)):
+            if k % 2 == 0:
+                p = self.mul(T[k // 2], T[k // 2])
+                T[k] = self.o.add_const(self.o.add(p, p), -1.0)
+            else:
+                h = k // 2
+                p = self.mul(T[h + 1], T[h])
+                T[k] = self.o.sub(self.o.add(p, p), self.adjust(T[1], p.level))
+        g = m
+        while g <= d:
+            h = g // 2
+            p = self.mul(T[h], T[h])
+            T[g] = self.o.add_const(self.o.add(p, p), -1.0)
+            g *= 2
+        return T
+
+    def lin(self, c, T):
+        """sum_j c[j] T_j for j >= 1 (constant products), plus c[0]; a plain
+        float when no c[j], j >= 1, is nonzero."""
+        js = [j for j in range(1, len(c)) if c[j] != 0.0]
+        if not js:
+            return float(c[0])
+        top = min(T[j].level for j in js) - 1
+        acc = None
+        for j in js:
+            t = self._const_mul(self.adjust(T[j], top + 1), c[j])
+            acc = t if acc is None else self.o.add(acc, t)
+        return self.o.add_const(acc, c[0]) if c[0] != 0.0 else acc
+
+    def _sum(self, u, v):
+        """u + v where either may be a plain float."""
+        if isinstance(u, float) and isinstance(v, float):
+            return u + v
+        if isinstance(u, float):
+            u, v = v, u
+        if isinstance(v, float):
+            return self.o.add_const(u, v) if v != 0.0 else u
+        return self.add(u, v)
+
+    def ev(self, c, T, m):
+        d = len(c) - 1
+        if d < m:
+            return self.lin(c, T)
+        g = m
+        while 2 * g <= d:
+            g *= 2
+        q, r = cheb_divide(c, g)
+        Q = self.ev(q, T, m)
+        if isinstance(Q, float):
+            P = self._const_mul(T[g], Q) if Q != 0.0 else 0.0
+        else:
+            P = self.mul(Q, T[g])
+        R = self.ev(r, T, m)
+        return self._sum(P, R)
+
+    def run(self, coeffs):
+        c = [float(v) for v in coeffs]
+        d = len(c) - 1
+        if d < 1:
+            raise ValueError("degree must be at least 1")
+        m = cheb_baby_size(d)
+        y = self.affine()
+        T = self.basis(y, m, d)
+        r = self.ev(c, T, m)
+        if isinstance(r, float):
+            raise ValueError("constant polynomial")
+        return r
+
+
+def cheb_eval(be, ct, coeffs, a, b):
+    """Encrypted p(x) = sum_k coeffs[k] T_k((2x - a - b)/(b - a)) (ChebEval)."""
+    return ChebEval(be, ct, a, b).run(coeffs)
+
+
+def ref_cheb(x, coeffs, a, b):
+    """FP64 reference of the same polynomial."""
+    y = (2.0 * np.asarray(x, dtype=np.float64) - (a + b)) / (b - a)
+    return np.polynomial.chebyshev.chebval(y, np.asarray(coeffs, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
 # FP64 references (PyTorch semantics)
 # ---------------------------------------------------------------------------
 
