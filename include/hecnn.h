@@ -131,6 +131,24 @@ hec_status ckks_rescale(hec_ctx *ctx, hec_ct *inout);
 hec_status ckks_mul_pt(hec_ctx *ctx, const hec_ct *ct, const hec_pt *pt, hec_ct **out);
 /* a + b (levels and scales must match). */
 hec_status ckks_add(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
+/* a - b (levels and scales must match). */
+hec_status ckks_sub(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
+/* Ciphertext product (the multiplications of the polynomial activation,
+ * Section 4.3 "GELU" and Appendix "Polynomial Approximation"): tensor product
+ * (a0 b0, a0 b1 + a1 b0, a1 b1), the s^2 part key-switched to s with the
+ * relinearization key (hybrid key switching as for rotations; key target
+ * s^2, random streams of the Galois element 0, generated from the keygen
+ * seed on first use and kept by the context).  Levels must match; scale
+ * a.scale * b.scale; not rescaled.  HEC_ENOKEY before ckks_keygen. */
+hec_status ckks_mul(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
+/* ct * value in every slot: value encoded at pscale as the constant polynomial
+ * round_half_away(value * pscale) (the exact product of the two doubles; HEC_EINVAL
+ * at or above 2^62); scale ct.scale * pscale, not rescaled. */
+hec_status ckks_mul_const(hec_ctx *ctx, const hec_ct *ct, double value, double pscale, hec_ct **out);
+/* ct + value in every slot, encoded the same way at the ciphertext's scale. */
+hec_status ckks_add_const(hec_ctx *ctx, const hec_ct *ct, double value, hec_ct **out);
+/* The first level+1 limbs of ct (level <= ct's level; scale kept). */
+hec_status ckks_drop(hec_ctx *ctx, const hec_ct *ct, uint32_t level, hec_ct **out);
 /* Level and scale of a ciphertext. */
 hec_status ckks_ct_info(const hec_ct *ct, uint32_t *level, double *scale);
 
@@ -232,6 +250,25 @@ hec_status he_avgpool_ex(hec_ctx *ctx, const hec_image *in, uint32_t window, int
  * channel held in several blocks is read from its first block only. */
 hec_status he_linear(hec_ctx *ctx, const hec_image *in, const double *W, uint32_t O, int pool, hec_ct **out);
 hec_status he_linear_steps(hec_ctx *ctx, const hec_image *like, int32_t *steps, size_t cap, size_t *count);
+
+/* Polynomial activation (Section 4.3 "GELU"; Appendix "Polynomial
+ * Approximation"): p(x) = sum_k coeffs[k] T_k(y), y = (2x - a - b)/(b - a),
+ * the Chebyshev expansion over [a, b] (degree ncoeffs - 1, 1..4095),
+ * evaluated slotwise with the basis T_1 = y, T_{2k} = 2 T_k^2 - 1,
+ * T_{2k+1} = 2 T_{k+1} T_k - T_1 up to the baby size m (smallest power of two
+ * with m^2 > degree), giant powers T_{2m}, T_{4m}, ... and recursive division
+ * by the largest giant power (T_j = 2 T_g T_{j-g} - T_{2g-j}).  Every product
+ * is rescaled; the nominal scale of level l is S[l-1] = S[l]^2 / q_l from the
+ * input's, constants multiply at S[l-1] q_l / S[l], level adjustments drop
+ * limbs and multiply by 1.  Degree 59 consumes 7 levels.  Errors: HEC_EINVAL
+ * (bad coefficients or interval, constant polynomial), HEC_ELEVEL (too few
+ * levels), HEC_ENOKEY (no keys). */
+hec_status he_cheb_eval(hec_ctx *ctx, const hec_ct *x, const double *coeffs, size_t ncoeffs, double a, double b,
+                        hec_ct **out);
+/* The same on every shard of an image (layout kept; slots outside the image
+ * get p(0)). */
+hec_status he_image_cheb_eval(hec_ctx *ctx, const hec_image *in, const double *coeffs, size_t ncoeffs, double a,
+                              double b, hec_image **out);
 
 void hec_ct_free(hec_ct *ct);
 void hec_pt_free(hec_pt *pt);

@@ -22,6 +22,7 @@ SOURCES = [
     ("hec_ctx.hip", "hip"),
     ("hec_encode.hip", "hip"),
     ("hec_layers.cpp", "cxx"),
+    ("hec_poly.cpp", "cxx"),
     ("hec_host.cpp", "cxx"),
 ]
 

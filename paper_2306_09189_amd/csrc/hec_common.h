@@ -131,10 +131,21 @@ void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size
 void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc,
                         size_t st_, int npolys, u32 level, const LevelC *lc, hipStream_t st);
 
-// swk/pk assembly: b = -a*s + e (+ pm * sigma_g(s) on limbs in [dlo, dhi)), then both b and a into
-// Montgomery form.  sN is s in NTT form (plain), all primes; a, e in NTT form.
-void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g,
-                    u32 dlo, u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st);
+// swk/pk assembly: b = -a*s + e (+ pm * sigma_g(s) on limbs in [dlo, dhi); pm * tgt instead when tgt is
+// given), then both b and a into Montgomery form.  sN is s in NTT form (plain), all primes; a, e, tgt in
+// NTT form.
+void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *tgt, const u64 *pm,
+                    u32 g, u32 dlo, u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st);
+
+// per-limb constants (limb l = prime l) with Shoup companions
+struct ScalarArg {
+    u64 v[HEC_MAX_LIMBS];
+    u64 vsh[HEC_MAX_LIMBS];
+};
+// out = in * v_l on nlimbs limbs of npolys polynomials; out = in + v_l on nlimbs limbs of one polynomial
+void hec_scalar_mul(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
+                    const ScalarArg &sa, hipStream_t st);
+void hec_scalar_add(const DevTables &T, u64 *out, const u64 *in, int nlimbs, const ScalarArg &sa, hipStream_t st);
 
 // enc: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk in Montgomery form, the rest plain NTT form)
 void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,

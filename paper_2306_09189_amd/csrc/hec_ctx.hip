@@ -382,7 +382,7 @@ extern "C" uint64_t hec_ctx_keyswitch_count(const hec_ctx *c) { return c ? c->ks
 
 extern "C" size_t hec_ctx_key_bytes(const hec_ctx *c)
 {
-    return c ? c->rotkeys.size() * (size_t)c->dnum * 2 * c->NLK * c->n * 8 : 0;
+    return c ? (c->rotkeys.size() + (c->rlk ? 1 : 0)) * (size_t)c->dnum * 2 * c->NLK * c->n * 8 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -432,9 +432,12 @@ extern "C" hec_status ckks_ct_info(const hec_ct *ct, uint32_t *level, double *sc
 // ---------------------------------------------------------------------------
 // keys
 // ---------------------------------------------------------------------------
-static hec_status gen_swk(hec_ctx *c, uint32_t g)
+// Key-switching key to s for Galois element g (target sigma_g(s)); with tgt
+// (NTT form, all primes) the target is tgt instead and g = 0 (the
+// relinearization key, target s^2): random streams (g << 8) | digit.
+static hec_status gen_swk(hec_ctx *c, uint32_t g, const u64 *tgt = nullptr, u64 **out = nullptr)
 {
-    if (c->rotkeys.count(g)) return HEC_OK;
+    if (!tgt && c->rotkeys.count(g)) return HEC_OK;
     const size_t n = c->n, NLK = c->NLK;
     u64 *key = c->alloc((size_t)c->dnum * 2 * NLK * n);
     u64 *e = c->alloc(NLK * n);
@@ -449,12 +452,30 @@ static hec_status gen_swk(hec_ctx *c, uint32_t g)
         hec_reduce_i64(c->T, e, es, c->idmap(), NLK, c->st);
         hec_ntt_fwd(c->T, e, 0, 1, c->idmap(), NLK, c->st);
         uint32_t dlo = j * c->alpha, dhi = std::min((j + 1) * c->alpha, c->L + 1);
-        hec_key_finish(c->T, b, a, e, c->d_sN, c->d_pmodq, g, dlo, dhi, NLK, c->idmap(), c->st);
+        hec_key_finish(c->T, b, a, e, c->d_sN, tgt, c->d_pmodq, g, dlo, dhi, NLK, c->idmap(), c->st);
     }
     c->release(e);
     c->release(es);
     HEC_TRY_HIP(hipGetLastError());
-    c->rotkeys[g] = key;
+    if (out) *out = key;
+    else c->rotkeys[g] = key;
+    return HEC_OK;
+}
+
+// relinearization key (target s^2), generated on first use from the key seed
+static hec_status relin_key(hec_ctx *c, const u64 **key)
+{
+    if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "no keys");
+    if (!c->rlk) {
+        const size_t n = c->n, NLK = c->NLK;
+        u64 *s2 = c->alloc(NLK * n);
+        if (!s2) HEC_FAIL(HEC_ENOMEM, "key allocation");
+        hec_ew(c->T, EW_MUL_MONT, s2, c->d_sN, c->d_sM, 0, 0, 0, 1, c->idmap(), (int)NLK, c->st);
+        hec_status s = gen_swk(c, 0, s2, &c->rlk);
+        c->release(s2);
+        HEC_CHECK(s);
+    }
+    *key = c->rlk;
     return HEC_OK;
 }
 
@@ -466,6 +487,8 @@ extern "C" hec_status ckks_keygen(hec_ctx *c, uint64_t seed, const int32_t *step
     const size_t n = c->n, NLK = c->NLK, nq = c->L + 1;
     for (auto &kv : c->rotkeys) c->release(kv.second);
     c->rotkeys.clear();
+    c->release(c->rlk);
+    c->rlk = nullptr;
     for (auto &kv : c->mask_cache) pt_free(kv.second);
     c->mask_cache.clear();
     c->key_seed = seed;
@@ -488,7 +511,7 @@ extern "C" hec_status ckks_keygen(hec_ctx *c, uint64_t seed, const int32_t *step
     hec_sample_small(c->T, sm, seed, P_PK_E, 0, 1, c->d_gauss, c->st);
     hec_reduce_i64(c->T, e, sm, c->idmap(), nq, c->st);
     hec_ntt_fwd(c->T, e, 0, 1, c->idmap(), nq, c->st);
-    hec_key_finish(c->T, b, a, e, c->d_sN, nullptr, 1, 0, 0, nq, c->idmap(), c->st);
+    hec_key_finish(c->T, b, a, e, c->d_sN, nullptr, nullptr, 1, 0, 0, nq, c->idmap(), c->st);
     c->release(sm);
     c->release(e);
     HEC_TRY_HIP(hipGetLastError());
@@ -1051,4 +1074,211 @@ extern "C" hec_status hec_prof_stop(hec_ctx *c, uint64_t *launches, uint64_t *un
     if (hec_prof_collect(launches, units, total_ms) != 0) HEC_FAIL(HEC_EDEVICE, "event timing failed");
     hec_prof_select(nullptr);
     return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ciphertext products (tensor product + relinearization) and constants
+// ---------------------------------------------------------------------------
+// a * b = (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1); d2 (a term in s^2) is
+// switched to s with the relinearization key: ModUp(d2), inner product with
+// the key over Q_l and P, ModDown, added to (d0, d1).  Scale a.scale * b.scale.
+hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    *out = nullptr;
+    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in ciphertext product");
+    const u64 *rlk = nullptr;
+    HEC_CHECK(relin_key(c, &rlk));
+    const size_t n = c->n;
+    const uint32_t lvl = a->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    const size_t P = (size_t)nq * n;
+    // t = [d0][d2][d1]: a ciphertext view (d0, d2) whose second polynomial is the one ModUp reads
+    u64 *t = c->alloc(3 * P), *bm = c->alloc(2 * P), *E = c->alloc(2 * (size_t)nqp * n);
+    hec_ct *o = ct_new(c, lvl, a->scale * b->scale);
+    if (!t || !bm || !E || !o) {
+        c->release(t);
+        c->release(bm);
+        c->release(E);
+        ct_free(o);
+        HEC_FAIL(HEC_ENOMEM, "ciphertext product buffers");
+    }
+    hec_ew(c->T, EW_TO_MONT, bm, b->d, nullptr, P, P, 0, 2, c->idmap(), (int)nq, c->st);
+    hec_ew(c->T, EW_MUL_MONT, t, a->d, bm, P, P, P, 2, c->idmap(), (int)nq, c->st);  // d0, d2
+    hec_ew(c->T, EW_MUL_MONT, t + 2 * P, a->d, bm + P, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
+    hec_ew(c->T, EW_MAC_MONT, t + 2 * P, a->d + P, bm, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
+    hec_ct view;
+    view.ctx = c;
+    view.level = lvl;
+    view.d = t;
+    u64 *D = nullptr;
+    hec_status s = ct_modup(c, &view, &D);
+    if (s == HEC_OK) {
+        KsBatch kb{};
+        kb.key[0] = rlk;
+        kb.out[0] = E;
+        kb.g[0] = 1;
+        hec_ks_inner(c->T, kb, 1, D, (int)beta, (int)nqp, c->qpmap(lvl), (int)c->NLK, c->st);
+        c->ks_count += 1;
+        s = ct_moddown(c, lvl, E, o);
+    }
+    if (s == HEC_OK) {
+        // (d0, d1) at t and t + 2P
+        hec_ew(c->T, EW_ADD, o->d, o->d, t, P, P, 2 * P, 2, c->idmap(), (int)nq, c->st);
+        if (hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("ciphertext product launch failed");
+    }
+    c->release(D);
+    c->release(t);
+    c->release(bm);
+    c->release(E);
+    if (s != HEC_OK) {
+        ct_free(o);
+        return s;
+    }
+    *out = o;
+    return HEC_OK;
+}
+
+// A constant in every slot encodes as the constant polynomial
+// round_half_away(value * scale), the product of the two doubles taken
+// exactly (53-bit mantissas multiplied in 128 bits).
+hec_status const_coeff(double value, double scale, int64_t *r)
+{
+    if (!std::isfinite(value) || !std::isfinite(scale)) HEC_FAIL(HEC_EINVAL, "constant or scale not finite");
+    *r = 0;
+    if (value == 0.0 || scale == 0.0) return HEC_OK;
+    int ea, eb;
+    double fa = std::frexp(std::fabs(value), &ea), fb = std::frexp(std::fabs(scale), &eb);
+    const u128 P = (u128)(uint64_t)std::ldexp(fa, 53) * (u128)(uint64_t)std::ldexp(fb, 53);
+    const int e = ea + eb - 106;  // |value * scale| = P * 2^e
+    u128 m;
+    if (e >= 0) {
+        if (e >= 62 || (P >> (62 - e)) != 0) HEC_FAIL(HEC_EINVAL, "constant exceeds 2^62");
+        m = P << e;
+    } else if (-e >= 120) {
+        m = 0;
+    } else {
+        const int s = -e;
+        m = (P + ((u128)1 << (s - 1))) >> s;
+    }
+    if (m >= ((u128)1 << 62)) HEC_FAIL(HEC_EINVAL, "constant exceeds 2^62");
+    const bool neg = (value < 0) != (scale < 0);
+    *r = neg ? -(int64_t)m : (int64_t)m;
+    return HEC_OK;
+}
+
+static void scalar_arg(const hec_ctx *c, int64_t r, uint32_t nlimbs, ScalarArg &sa)
+{
+    for (uint32_t l = 0; l < nlimbs; l++) {
+        const u64 q = c->mod[l];
+        u64 v = (u64)(r >= 0 ? (u128)r % q : (q - (u64)((u128)(-(r + 1)) % q) - 1));
+        sa.v[l] = v;
+        sa.vsh[l] = (u64)(((u128)v << 64) / q);
+    }
+}
+
+hec_status ct_mul_const(hec_ctx *c, const hec_ct *a, double value, double pscale, hec_ct **out)
+{
+    *out = nullptr;
+    int64_t r;
+    HEC_CHECK(const_coeff(value, pscale, &r));
+    hec_ct *o = ct_new(c, a->level, a->scale * pscale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    ScalarArg sa;
+    scalar_arg(c, r, a->level + 1, sa);
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_scalar_mul(c->T, o->d, a->d, P, 2, (int)a->level + 1, sa, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale, hec_ct **out)
+{
+    *out = nullptr;
+    int64_t r;
+    HEC_CHECK(const_coeff(value, scale, &r));
+    hec_ct *o = ct_clone(a);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    ScalarArg sa;
+    scalar_arg(c, r, a->level + 1, sa);
+    hec_scalar_add(c->T, o->d, a->d, (int)a->level + 1, sa, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+hec_status ct_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    *out = nullptr;
+    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in subtraction");
+    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in subtraction");
+    hec_ct *o = ct_new(c, a->level, a->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_ew(c->T, EW_SUB, o->d, a->d, b->d, P, P, P, 2, c->idmap(), (int)a->level + 1, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+// the first level+1 limbs of both polynomials (modulus dropped, scale kept)
+hec_status ct_drop(hec_ctx *c, const hec_ct *a, uint32_t level, hec_ct **out)
+{
+    *out = nullptr;
+    if (level > a->level) HEC_FAIL(HEC_ELEVEL, "cannot raise a level");
+    hec_ct *o = ct_new(c, level, a->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    hec_copy_limbs(o->d, a->d, (size_t)(level + 1) * c->n, (size_t)(a->level + 1) * c->n, 2,
+                   (size_t)(level + 1) * c->n, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+#define HEC_ABI_OUT1(call)                                                                                         \
+    do {                                                                                                           \
+        HEC_TRY_HIP(hipSetDevice(c->dev));                                                                         \
+        hec_status s_ = (call);                                                                                    \
+        if (s_ == HEC_OK && hipGetLastError() != hipSuccess) {                                                     \
+            ct_free(*out);                                                                                         \
+            *out = nullptr;                                                                                        \
+            HEC_FAIL(HEC_EDEVICE, "kernel launch failed");                                                         \
+        }                                                                                                          \
+        return s_;                                                                                                 \
+    } while (0)
+
+extern "C" hec_status ckks_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a || !b) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_mul(c, a, b, out));
+}
+
+extern "C" hec_status ckks_mul_const(hec_ctx *c, const hec_ct *a, double value, double pscale, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_mul_const(c, a, value, pscale, out));
+}
+
+extern "C" hec_status ckks_add_const(hec_ctx *c, const hec_ct *a, double value, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_add_const(c, a, value, a->scale, out));
+}
+
+extern "C" hec_status ckks_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a || !b) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_sub(c, a, b, out));
+}
+
+extern "C" hec_status ckks_drop(hec_ctx *c, const hec_ct *a, uint32_t level, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_drop(c, a, level, out));
 }

@@ -90,6 +90,7 @@ struct hec_ctx {
     u64 *d_sN = nullptr, *d_sM = nullptr;  // secret, NTT form over all primes (plain / Montgomery)
     u64 *d_pk = nullptr;                   // [2][L+1][n] Montgomery
     std::map<uint32_t, u64 *> rotkeys;     // Galois element -> [dnum][2][NLK][n] Montgomery
+    u64 *rlk = nullptr;                    // relinearization key (target s^2), same layout
     std::map<std::string, hec_pt *> mask_cache;
     std::map<uint32_t, u64 *> ones_qp;     // level -> the constant 1 over Q_l and P, Montgomery form
     uint64_t ks_count = 0;                 // key-switch inner products computed (one per rotation by g != 1)
@@ -143,6 +144,16 @@ hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **D);
 hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
 // the plaintext 1 over Q_l and P ([level+1+k][n], Montgomery form), cached per level
 const u64 *ones_qp(hec_ctx *c, uint32_t level);
+// ciphertext product with relinearization (not rescaled), scale a.scale * b.scale
+hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
+// the constant polynomial round_half_away(value * scale) (exact product), |r| < 2^62
+hec_status const_coeff(double value, double scale, int64_t *r);
+// a * value (value encoded at pscale; result scale a.scale * pscale)
+hec_status ct_mul_const(hec_ctx *c, const hec_ct *a, double value, double pscale, hec_ct **out);
+// a + value (value encoded at `scale`)
+hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale, hec_ct **out);
+hec_status ct_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
+hec_status ct_drop(hec_ctx *c, const hec_ct *a, uint32_t level, hec_ct **out);
 void pt_free(hec_pt *p);
 void ct_free(hec_ct *p);
 bool have_rotkey(hec_ctx *c, int32_t step);

@@ -1193,8 +1193,8 @@ void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *t
 // ---------------------------------------------------------------------------
 // key assembly and encryption
 // ---------------------------------------------------------------------------
-__global__ void k_key_finish(u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g, u32 dlo, u32 dhi,
-                             const u32 *pmap, DevTables T)
+__global__ void k_key_finish(u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *tgt, const u64 *pm, u32 g,
+                             u32 dlo, u32 dhi, const u32 *pmap, DevTables T)
 {
     const u32 l = blockIdx.y;
     const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
@@ -1207,18 +1207,18 @@ __global__ void k_key_finish(u64 *b, u64 *a, const u64 *e, const u64 *sN, const 
     u64 as = mont_mul(av, mont_mul(s, pc.r2, pc.q, pc.qinv_neg), pc.q, pc.qinv_neg);
     u64 v = sub_mod(e[off], as, pc.q);
     if (pm && pi >= dlo && pi < dhi) {
-        u64 sg = sN[soff + auto_src(k, g, T.logn)];
+        u64 sg = tgt ? tgt[soff + k] : sN[soff + auto_src(k, g, T.logn)];
         u64 pmm = mont_mul(pm[pi], pc.r2, pc.q, pc.qinv_neg);
         v = add_mod(v, mont_mul(sg, pmm, pc.q, pc.qinv_neg), pc.q);
     }
     b[off] = mont_mul(v, pc.r2, pc.q, pc.qinv_neg);
     a[off] = mont_mul(av, pc.r2, pc.q, pc.qinv_neg);
 }
-void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *pm, u32 g, u32 dlo,
-                    u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st)
+void hec_key_finish(const DevTables &T, u64 *b, u64 *a, const u64 *e, const u64 *sN, const u64 *tgt, const u64 *pm,
+                    u32 g, u32 dlo, u32 dhi, int nlimbs, const u32 *pmap, hipStream_t st)
 {
     dim3 gr((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, 1);
-    hipLaunchKernelGGL(k_key_finish, gr, dim3(EW_THREADS), 0, st, b, a, e, sN, pm, g, dlo, dhi, pmap, T);
+    hipLaunchKernelGGL(k_key_finish, gr, dim3(EW_THREADS), 0, st, b, a, e, sN, tgt, pm, g, dlo, dhi, pmap, T);
 }
 
 __global__ void k_encrypt_finish(u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m, const u64 *pk,
@@ -1277,4 +1277,30 @@ void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, con
 {
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS);
     hipLaunchKernelGGL(k_crt_double, g, dim3(EW_THREADS), 0, st, res, out, (u32)nq, Mm, inv, invsh, T);
+}
+
+// ---------------------------------------------------------------------------
+// products with and sums of constant polynomials (a constant in every slot
+// encodes as a constant polynomial, whose evaluations are all equal)
+// ---------------------------------------------------------------------------
+__global__ void k_scalar(int op, u64 *out, const u64 *in, size_t ps, ScalarArg sa, DevTables T)
+{
+    const u32 l = blockIdx.y, p = blockIdx.z;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const u64 q = T.pc[l].q;
+    const size_t off = p * ps + (size_t)l * T.n + t;
+    const u64 x = in[off];
+    out[off] = op == 0 ? shoup_mul(x, sa.v[l], sa.vsh[l], q) : add_mod(x, sa.v[l], q);
+}
+void hec_scalar_mul(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
+                    const ScalarArg &sa, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
+    hipLaunchKernelGGL(k_scalar, g, dim3(EW_THREADS), 0, st, 0, out, in, poly_stride, sa, T);
+}
+void hec_scalar_add(const DevTables &T, u64 *out, const u64 *in, int nlimbs, const ScalarArg &sa, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, 1);
+    hipLaunchKernelGGL(k_scalar, g, dim3(EW_THREADS), 0, st, 1, out, in, (size_t)0, sa, T);
 }

@@ -23,6 +23,7 @@ EXPORTS = [
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
+    "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
 ]
 
 
@@ -77,6 +78,13 @@ def lib():
             "ckks_rescale": (c, [vp, vp]),
             "ckks_mul_pt": (c, [vp, vp, vp, P(vp)]),
             "ckks_add": (c, [vp, vp, vp, P(vp)]),
+            "ckks_sub": (c, [vp, vp, vp, P(vp)]),
+            "ckks_mul": (c, [vp, vp, vp, P(vp)]),
+            "ckks_mul_const": (c, [vp, vp, dbl, dbl, P(vp)]),
+            "ckks_add_const": (c, [vp, vp, dbl, P(vp)]),
+            "ckks_drop": (c, [vp, vp, u32, P(vp)]),
+            "he_cheb_eval": (c, [vp, vp, dblp, sz, dbl, dbl, P(vp)]),
+            "he_image_cheb_eval": (c, [vp, vp, dblp, sz, dbl, dbl, P(vp)]),
             "ckks_ct_info": (c, [vp, u32p, dblp]),
             "ckks_ct_export": (c, [vp, vp, u64p, u32p, dblp]),
             "ckks_ct_import": (c, [vp, u64p, u32, dbl, P(vp)]),
@@ -379,6 +387,43 @@ class Context:
     def add(self, a, b):
         out = vp()
         check(lib().ckks_add(self.h, a.h, b.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def sub(self, a, b):
+        out = vp()
+        check(lib().ckks_sub(self.h, a.h, b.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def mul(self, a, b):
+        """Ciphertext product with relinearization (not rescaled)."""
+        out = vp()
+        check(lib().ckks_mul(self.h, a.h, b.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def mul_const(self, ct, value, pscale):
+        out = vp()
+        check(lib().ckks_mul_const(self.h, ct.h, float(value), float(pscale), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def add_const(self, ct, value):
+        out = vp()
+        check(lib().ckks_add_const(self.h, ct.h, float(value), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def drop(self, ct, level):
+        out = vp()
+        check(lib().ckks_drop(self.h, ct.h, int(level), ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def cheb_eval(self, x, coeffs, a, b):
+        """sum_k coeffs[k] T_k((2x - a - b)/(b - a)) on a ciphertext or, slotwise, on every shard of an image."""
+        cf = _arr(coeffs, np.float64)
+        out = vp()
+        if isinstance(x, Image):
+            check(lib().he_image_cheb_eval(self.h, x.h, _p(cf, dblp), len(cf), float(a), float(b),
+                                           ctypes.byref(out)))
+            return Image(self, out.value)
+        check(lib().he_cheb_eval(self.h, x.h, _p(cf, dblp), len(cf), float(a), float(b), ctypes.byref(out)))
         return Ciphertext(self, out.value)
 
     def image_encrypt(self, x, level, seed):
