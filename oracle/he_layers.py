@@ -915,20 +915,27 @@ class ChebEval:
     """Evaluation of p(y) = sum_k c_k T_k(y), y = (2x - (a + b)) / (b - a),
     on an encrypted x (oracle ciphertexts).
 
+    Map: on [a, b] = [-1, 1], y = x and no level is spent (an affine map in
+    front of the activation folds into the preceding convolution's weights and
+    bias, as batch normalization does, Sec. 4.3); otherwise y = alpha x + beta
+    costs one constant product.
+
     Scales: every ciphertext at level l carries the nominal scale S[l], with
     S[l0] the input's scale and S[l-1] = S[l]^2 / q_l, so that the product
     of two level-l ciphertexts, rescaled, has exactly scale S[l-1].  A
-    constant multiplies at the scale S[l-1] q_l / S[l'] that brings a
-    level-l' operand (l' = l) to S[l-1] after the rescale; level adjustments
-    drop limbs, then multiply by 1 in the same way.  Products, constant
-    products and adjustments set the nominal scale of their result to S[l].
+    constant multiplies a level-l' operand (l' = l, or a ciphertext dropped
+    to l) at S[l-1] q_l / (the operand's scale), which brings it to S[l-1]
+    after the rescale; level adjustments drop limbs, then multiply by 1 in
+    the same way.  Results are given the nominal scale of their level.
 
     Basis: T_1 = y, T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_{k+1} T_k - T_1
     for k < m (m = cheb_baby_size(deg)), and the giant powers T_{2m},
-    T_{4m}, ... by doubling.  A polynomial of degree < m is the sum of
-    c_j T_j (constants folded in by a constant product each); a larger one
-    is split by cheb_divide at the largest giant power g <= deg and
-    evaluated as q(y) T_g + r(y)."""
+    T_{4m}, ... by doubling (the recurrences of the Chebyshev polynomials in
+    the Appendix, Polynomial Approximation).  A polynomial of degree < m is
+    c_0 plus the sum of the constant products c_j T_j, each T_j dropped to one
+    common level and the sum rescaled once; a larger one is split by
+    cheb_divide at the largest giant power g <= deg and evaluated as
+    q(y) T_g + r(y)."""
 
     def __init__(self, be, x, a, b):
         self.be, self.o = be, be.o
@@ -939,20 +946,32 @@ class ChebEval:
             l -= 1
         self.a, self.b = float(a), float(b)
         self.x = x
+        self._adj = {}
+
+    def _const_mul_raw(self, ct, value):
+        """ct (level l) * value at S[l-1] q_l / ct.scale, not rescaled; nominal
+        scale S[l-1] q_l."""
+        l = ct.level
+        pscale = self.S[l - 1] * float(self.o.p.q[l]) / ct.scale
+        r = self.o.mul_const(ct, value, pscale)
+        return type(r)(r.data, r.level, self.S[l - 1] * float(self.o.p.q[l]))
 
     def _const_mul(self, ct, value):
-        """ct (level l, scale S[l]) * value -> level l-1, scale S[l-1]."""
+        """ct (level l) * value -> level l-1, scale S[l-1]."""
         l = ct.level
-        pscale = self.S[l - 1] * float(self.o.p.q[l]) / self.S[l]
-        r = self.o.rescale(self.o.mul_const(ct, value, pscale))
+        r = self.o.rescale(self._const_mul_raw(ct, value))
         return type(r)(r.data, r.level, self.S[l - 1])
 
     def adjust(self, ct, level):
+        """ct brought down to `level` (a cached result per ciphertext and level)."""
         if ct.level == level:
             return ct
         if ct.level < level:
             raise ValueError("cannot raise a level")
-        return self._const_mul(self.o.drop_to(ct, level + 1), 1.0)
+        key = (id(ct), level)
+        if key not in self._adj:
+            self._adj[key] = (ct, self._const_mul(self.o.drop_to(ct, level + 1), 1.0))
+        return self._adj[key][1]
 
     def mul(self, u, v):
         l = min(u.level, v.level)
@@ -966,7 +985,10 @@ class ChebEval:
         return self.o.add(self.adjust(u, l), self.adjust(v, l))
 
     def affine(self):
-        """y = alpha x + beta, alpha = 2 / (b - a), beta = -(a + b) / (b - a)."""
+        """y = alpha x + beta, alpha = 2 / (b - a), beta = -(a + b) / (b - a);
+        y = x on [-1, 1]."""
+        if self.a == -1.0 and self.b == 1.0:
+            return self.x
         alpha = 2.0 / (self.b - self.a)
         beta = -(self.a + self.b) / (self.b - self.a)
         y = self._const_mul(self.x, alpha)
@@ -991,17 +1013,22 @@ class ChebEval:
         return T
 
     def lin(self, c, T):
-        """sum_j c[j] T_j for j >= 1 (constant products), plus c[0]; a plain
-        float when no c[j], j >= 1, is nonzero."""
+        """c[0] + sum_j c[j] T_j (j >= 1, c[j] != 0): every T_j dropped to the
+        level above the lowest one's, multiplied by c[j], summed, rescaled
+        once; a plain float when no c[j], j >= 1, is nonzero."""
         js = [j for j in range(1, len(c)) if c[j] != 0.0]
         if not js:
             return float(c[0])
         top = min(T[j].level for j in js) - 1
+        if top < 0:
+            raise ValueError("out of levels")
         acc = None
         for j in js:
-            t = self._const_mul(self.adjust(T[j], top + 1), c[j])
+            t = self._const_mul_raw(self.o.drop_to(T[j], top + 1), c[j])
             acc = t if acc is None else self.o.add(acc, t)
-        return self.o.add_const(acc, c[0]) if c[0] != 0.0 else acc
+        r = self.o.rescale(acc)
+        r = type(r)(r.data, r.level, self.S[top])
+        return self.o.add_const(r, c[0]) if c[0] != 0.0 else r
 
     def _sum(self, u, v):
         """u + v where either may be a plain float."""

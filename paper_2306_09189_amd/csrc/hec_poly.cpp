@@ -3,17 +3,24 @@
 // approximation over a fixed interval evaluated with ciphertext products),
 // with baby-step/giant-step splitting of the polynomial.
 //
+// Map: y = (2x - a - b)/(b - a) costs one constant product, except on
+// [a, b] = [-1, 1], where y = x (an affine map in front of the activation
+// folds into the previous convolution, as batch normalization does, so
+// degree 59 takes depth 6 and degree 27 depth 5).
+//
 // Scale management: every ciphertext at level l carries the nominal scale
 // S[l], S[l0] the input's scale and S[l-1] = S[l]^2 / q_l, so the rescaled
 // product of two level-l ciphertexts has exactly S[l-1].  A constant product
-// on a level-l ciphertext encodes the constant at S[l-1] q_l / S[l] and sets
-// the result's nominal scale to S[l-1] after the rescale; a level adjustment
-// drops limbs to l+1 and multiplies by the constant 1 in the same way.
+// on a level-l ciphertext (or one dropped to level l) encodes the constant at
+// S[l-1] q_l / (its scale) and sets the result's nominal scale to S[l-1]
+// after the rescale; a level adjustment drops limbs to l+1 and multiplies by
+// the constant 1 in the same way.
 //
 // Basis: T_1 = y, T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_{k+1} T_k - T_1 for
 // k < m (m the smallest power of two with m^2 >= deg + 1) and the giant
-// powers T_{2m}, T_{4m}, ... by doubling.  A polynomial of degree < m is the
-// sum of its constant products with the T_j; a larger one is divided by the
+// powers T_{2m}, T_{4m}, ... by doubling.  A polynomial of degree < m is c_0
+// plus the constant products c_j T_j, every T_j dropped to one level and the
+// sum rescaled once; a larger one is divided by the
 // largest giant power T_g <= its degree (T_j = 2 T_g T_{j-g} - T_{2g-j}),
 // p = q T_g + r, and q, r are evaluated the same way.
 #include <algorithm>
@@ -76,27 +83,49 @@ struct ChebEval {
         for (uint32_t l = x->level; l > 0; l--) S[l - 1] = (S[l] * S[l]) / (double)c->mod[l];
     }
 
+    // ct (level l) * value at S[l-1] q_l / ct.scale, not rescaled; nominal scale S[l-1] q_l
+    Ct const_mul_raw(const Ct &ct, double value)
+    {
+        const uint32_t l = ct->level;
+        if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
+        const double pscale = S[l - 1] * (double)c->mod[l] / ct->scale;
+        hec_ct *o = nullptr;
+        PTRY(ct_mul_const(c, ct.get(), value, pscale, &o));
+        Ct r = wrap(o);
+        r->scale = S[l - 1] * (double)c->mod[l];
+        return r;
+    }
+
     // ct (level l) * value, rescaled to level l-1 at the nominal scale S[l-1]
     Ct const_mul(const Ct &ct, double value)
     {
         const uint32_t l = ct->level;
-        if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
-        const double pscale = S[l - 1] * (double)c->mod[l] / S[l];
-        hec_ct *o = nullptr;
-        PTRY(ct_mul_const(c, ct.get(), value, pscale, &o));
-        Ct r = wrap(o);
+        Ct r = const_mul_raw(ct, value);
         PTRY(ct_rescale(c, r.get()));
         r->scale = S[l - 1];
         return r;
     }
 
+    Ct drop(const Ct &ct, uint32_t level)
+    {
+        hec_ct *o = nullptr;
+        PTRY(ct_drop(c, ct.get(), level, &o));
+        return wrap(o);
+    }
+
+    // ct brought down to `level`: limbs dropped to level + 1, times 1 (cached per ciphertext and level; the
+    // cache keeps the source alive, so its address is not reused)
+    std::map<std::pair<const hec_ct *, uint32_t>, std::pair<Ct, Ct>> adj;
     Ct adjust(const Ct &ct, uint32_t level)
     {
         if (ct->level == level) return ct;
         if (ct->level < level) PFAIL(HEC_ELEVEL, "cannot raise a level");
-        hec_ct *o = nullptr;
-        PTRY(ct_drop(c, ct.get(), level + 1, &o));
-        return const_mul(wrap(o), 1.0);
+        auto key = std::make_pair((const hec_ct *)ct.get(), level);
+        auto it = adj.find(key);
+        if (it != adj.end()) return it->second.second;
+        Ct r = const_mul(drop(ct, level + 1), 1.0);
+        adj[key] = std::make_pair(ct, r);
+        return r;
     }
 
     Ct mul(const Ct &u0, const Ct &v0)
@@ -142,9 +171,10 @@ struct ChebEval {
         return wrap(o);
     }
 
-    // y = alpha x + beta maps [a, b] onto [-1, 1]
+    // y = alpha x + beta maps [a, b] onto [-1, 1]; on [-1, 1] itself y = x (no level spent)
     Ct affine()
     {
+        if (a == -1.0 && b == 1.0) return x;
         const double alpha = 2.0 / (b - a);
         const double beta = -(a + b) / (b - a);
         return add_const(const_mul(x, alpha), beta);
@@ -179,11 +209,14 @@ struct ChebEval {
         for (uint32_t j : js) lo = std::min(lo, T[j]->level);
         if (lo == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         const uint32_t top = lo - 1;
+        // every T_j dropped to top + 1 and multiplied by c_j, the sum rescaled once
         Ct acc;
         for (uint32_t j : js) {
-            Ct t = const_mul(adjust(T[j], top + 1), cf[j]);
+            Ct t = const_mul_raw(T[j]->level == top + 1 ? T[j] : drop(T[j], top + 1), cf[j]);
             acc = acc ? add_raw(acc, t) : t;
         }
+        PTRY(ct_rescale(c, acc.get()));
+        acc->scale = S[top];
         return Val::of(cf[0] != 0.0 ? add_const(acc, cf[0]) : acc);
     }
 

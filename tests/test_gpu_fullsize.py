@@ -182,3 +182,41 @@ def test_benchmark_step_accuracy(full):
     err_b = np.abs(bb.decrypt() - ref).max()
     log("bsgs max abs err", err_b)
     assert err_b < 1e-5
+
+
+def test_mul_ct_full(full):
+    """Relinearized ciphertext product at level 20 (three digits), bit-exact."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(7)
+    z1, z2 = rng.uniform(-1, 1, prm.N), rng.uniform(-1, 1, prm.N)
+    a = o.encrypt(o.encode(z1, 20, 2.0 ** LS), seed=71)
+    b = o.encrypt(o.encode(z2, 20, 2.0 ** LS), seed=72)
+    log("mul_ct 2^16")
+    g = ctx.mul(ctx.ct_import(a.data, 20, a.scale), ctx.ct_import(b.data, 20, b.scale))
+    ref = o.mul_ct(a, b)
+    assert (g.export() == ref.data).all()
+    assert np.abs(ctx.decrypt(ctx.rescale(g)) - z1 * z2).max() < 1e-9
+
+
+def test_gelu_degree59_full(full):
+    """GELU on [-15, 15] (the paper's bound for ResNet-50) as the degree-59
+    Chebyshev interpolant, its map onto [-1, 1] folded into the input: depth 6
+    from level 20, every bit equal to the oracle's, within 1e-6 of the FP64
+    polynomial and 2e-4 of GELU itself (the paper's table: 0.0002 on [-16, 16])."""
+    ctx, prm, o = full
+    from numpy.polynomial import chebyshev as C
+
+    def gelu(x):
+        return 0.5 * x * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (x + 0.044715 * x ** 3)))
+    coef = C.chebinterpolate(lambda y: gelu(15.0 * y), 59)
+    z = np.random.default_rng(8).uniform(-1, 1, prm.N)
+    ct = o.encrypt(o.encode(z, 20, 2.0 ** LS), seed=81)
+    log("gelu 2^16 gpu")
+    g = ctx.cheb_eval(ctx.ct_import(ct.data, 20, ct.scale), coef, -1.0, 1.0)
+    assert g.level == 14
+    dec = ctx.decrypt(g)
+    assert np.abs(dec - hl.ref_cheb(z, coef, -1.0, 1.0)).max() < 1e-6
+    assert np.abs(dec - gelu(15.0 * z)).max() < 2e-4
+    log("gelu 2^16 oracle")
+    ref = hl.ChebEval(hl.CkksBackend(o), ct, -1.0, 1.0).run(coef)
+    assert (g.export() == ref.data).all()

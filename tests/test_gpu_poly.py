@@ -122,6 +122,21 @@ def test_cheb_eval_bit_exact(deep, deg):
     assert np.abs(ctx.decrypt(g) - hl.ref_cheb(z, coef, a, b)).max() < 1e-5
 
 
+@pytest.mark.parametrize("deg,depth", [(59, 6), (27, 5)])
+def test_cheb_eval_unit_interval_bit_exact(deep, deg, depth):
+    """On [-1, 1] (map folded into the previous layer): the paper's depths, bits
+    equal to the oracle's."""
+    ctx, prm, o = deep
+    coef = C.chebinterpolate(lambda y: gelu(8.0 * y), deg)
+    z = np.random.default_rng(deg + 7).uniform(-1, 1, prm.N)
+    ct = o.encrypt(o.encode(z, 12, 2.0 ** 40), seed=80 + deg)
+    ref = hl.ChebEval(hl.CkksBackend(o), ct, -1.0, 1.0).run(coef)
+    g = ctx.cheb_eval(ctx.ct_import(ct.data, 12, ct.scale), coef, -1.0, 1.0)
+    assert 12 - g.level == depth and g.level == ref.level and g.scale == ref.scale
+    assert (g.export() == ref.data).all()
+    assert np.abs(ctx.decrypt(g) - hl.ref_cheb(z, coef, -1.0, 1.0)).max() < 1e-5
+
+
 def test_cheb_eval_errors(deep):
     from paper_2306_09189_amd import hecnn
     ctx, prm, o = deep

@@ -90,4 +90,22 @@ def test_cheb_eval_gelu(deep, deg):
     assert r.scale == ev.S[r.level]
     assert np.abs(o.decrypt(r) - hl.ref_cheb(z, coef, a, b)).max() < 1e-5
     if deg == 59:
-        assert ct.level - r.level == 7
+        assert ct.level - r.level == 7      # six for the polynomial, one for the map onto [-1, 1]
+
+
+@pytest.mark.parametrize("deg,depth", [(59, 6), (27, 5), (13, 4)])
+def test_cheb_depth_on_unit_interval(deep, deg, depth):
+    """On [-1, 1] (the map folded into the previous layer) the evaluation spends
+    exactly the multiplicative depth the paper gives: 6 for degree 59, 5 for
+    degree 27 (Appendix, Polynomial Approximation) -- ceil(log2(deg + 1)) --
+    and stays within 1e-5 of the FP64 polynomial (GELU over [-8, 8] rescaled
+    into the coefficients)."""
+    p, o = deep
+    coef = C.chebinterpolate(lambda y: gelu(8.0 * y), deg)
+    z = np.random.default_rng(deg + 1).uniform(-0.9, 0.9, p.N)
+    ct = o.encrypt(o.encode(z, 12, 2.0 ** 40), seed=5)
+    ev = hl.ChebEval(hl.CkksBackend(o), ct, -1.0, 1.0)
+    r = ev.run(coef)
+    assert ct.level - r.level == depth
+    assert r.scale == ev.S[r.level]
+    assert np.abs(o.decrypt(r) - hl.ref_cheb(z, coef, -1.0, 1.0)).max() < 1e-5
