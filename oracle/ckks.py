@@ -295,6 +295,13 @@ class Oracle:
                          ptr(out))
         return Ct(out, ct.level, ct.scale * pt.scale)
 
+    def add_pt(self, ct, pt):
+        """ct + pt (plaintext at the ciphertext's level and scale): pt added to c0."""
+        if pt.level != ct.level or pt.scale != ct.scale:
+            raise ValueError("level/scale mismatch")
+        qi = list(range(ct.level + 1))
+        return Ct(np.stack([self.add_limbs(qi, ct.data[0], pt.limbs), ct.data[1].copy()]), ct.level, ct.scale)
+
     def add(self, a, b):
         if a.level != b.level or a.scale != b.scale:
             raise ValueError("level/scale mismatch")

@@ -156,6 +156,10 @@ class SlotSim:
         assert a[1] == b[1]
         return (a[0] + b[0], a[1], a[2])
 
+    def add_plain(self, ct, vec):
+        v, lvl, sc = ct
+        return (v + vec, lvl, sc)
+
     def rescale(self, ct):
         v, lvl, sc = ct
         assert lvl > 0
@@ -186,6 +190,9 @@ class CkksBackend:
 
     def add(self, a, b):
         return self.o.add(a, b)
+
+    def add_plain(self, ct, vec):
+        return self.o.add_pt(ct, self.o.encode(vec, ct.level, ct.scale))
 
     def rescale(self, ct):
         return self.o.rescale(ct)
@@ -1079,6 +1086,60 @@ def ref_cheb(x, coeffs, a, b):
     """FP64 reference of the same polynomial."""
     y = (2.0 * np.asarray(x, dtype=np.float64) - (a + b)) / (b - a)
     return np.polynomial.chebyshev.chebval(y, np.asarray(coeffs, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# bias, batch-norm folding and the basic block (Section 4.3)
+# ---------------------------------------------------------------------------
+
+def add_bias(be, cts, lay, bias):
+    """Per-channel bias: the plaintext of an image whose channel f is bias[f]
+    on every valid pixel (packed like the input), added to every shard."""
+    bias = np.asarray(bias, dtype=np.float64)
+    x = np.broadcast_to(bias[:, None, None], (lay.C, lay.H, lay.W))
+    return [be.add_plain(ct, v) for ct, v in zip(cts, pack(x, lay))]
+
+
+def fold_bn(w, gamma, shift, div=1.0):
+    """Inference batch norm y = gamma * conv(x, w) + shift folded into the
+    convolution (Section 4.3, Batch Normalization), and the result divided by
+    div (the map of [-div, div] onto [-1, 1] in front of the activation):
+    weights w[o] * (gamma[o] / div), bias shift[o] / div."""
+    w = np.asarray(w, dtype=np.float64)
+    s = np.asarray(gamma, dtype=np.float64) / float(div)
+    return w * s[:, None, None, None], np.asarray(shift, dtype=np.float64) / float(div)
+
+
+def basic_block(be, cts, lay, w1, bn1, w2, bn2, bound, coeffs, lazy=False, bsgs=False):
+    """conv(w1) with batch norm bn1 = (gamma, shift) folded and divided by the
+    activation bound -> GELU as the Chebyshev series coeffs on [-1, 1] (the
+    expansion of GELU(bound * y)) -> conv(w2) with bn2 folded -> 2x2 average
+    pooling; same padding (k // 2), stride 1.  bn2 may be None (no bias)."""
+    k = np.asarray(w1).shape[2]
+    w1f, b1f = fold_bn(w1, bn1[0], bn1[1], bound)
+    cts, lay = conv2d(be, cts, lay, w1f, pad=k // 2, stride=1, lazy=lazy, bsgs=bsgs)
+    cts = add_bias(be, cts, lay, b1f)
+    cts = [ChebEval(be, ct, -1.0, 1.0).run(coeffs) for ct in cts]
+    k2 = np.asarray(w2).shape[2]
+    if bn2 is None:
+        w2f = np.asarray(w2, dtype=np.float64)
+    else:
+        w2f, b2f = fold_bn(w2, bn2[0], bn2[1], 1.0)
+    cts, lay = conv2d(be, cts, lay, w2f, pad=k2 // 2, stride=1, lazy=lazy, bsgs=bsgs)
+    if bn2 is not None:
+        cts = add_bias(be, cts, lay, b2f)
+    return avgpool2x2(be, cts, lay, lazy=lazy, bsgs=bsgs)
+
+
+def ref_basic_block(x, w1, bn1, w2, bn2, bound, coeffs):
+    """FP64 reference of basic_block (the activation as the same polynomial)."""
+    k, k2 = np.asarray(w1).shape[2], np.asarray(w2).shape[2]
+    u = ref_conv2d(x, w1, pad=k // 2) * np.asarray(bn1[0])[:, None, None] + np.asarray(bn1[1])[:, None, None]
+    a = ref_cheb(u / bound, coeffs, -1.0, 1.0)
+    v = ref_conv2d(a, w2, pad=k2 // 2)
+    if bn2 is not None:
+        v = v * np.asarray(bn2[0])[:, None, None] + np.asarray(bn2[1])[:, None, None]
+    return ref_avgpool2x2(v)
 
 
 # ---------------------------------------------------------------------------
