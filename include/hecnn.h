@@ -10,7 +10,9 @@
  *   - Background, "Threat Model": the client encrypts and decrypts, the server
  *     evaluates with the weights in the clear;
  *   - Section 4 (packing, sharding, duplication/permutation), Section 4.1
- *     (convolution), Section 4.2 (average pooling).
+ *     (convolution), Section 4.2 (average pooling), Section 4.3 (batch
+ *     normalization folded into convolutions, linear and pool-linear layers,
+ *     GELU) and the Appendix on polynomial approximation (Chebyshev basis).
  * The RNS-CKKS conventions the paper leaves to its library are fixed as
  * follows (and are what "bit-exact" refers to):
  *   - primes: for each requested size b, the first prime 2^b - j*2n + 1
@@ -68,6 +70,7 @@ typedef struct hec_ct hec_ct;
 typedef struct hec_pt hec_pt;
 typedef struct hec_image hec_image;
 typedef struct hec_conv_plan hec_conv_plan;
+typedef struct hec_block hec_block;
 
 /* RNS-CKKS parameters.  Ring degree n = 2^log_n (N = n/2 slots);
  * ciphertext primes q_0 (q0_bits) and q_1..q_L (q_bits each); k special
@@ -88,6 +91,9 @@ typedef struct {
  * (a hipStream_t; NULL = the default stream).  Builds the prime chain, the
  * NTT / base-conversion tables and uploads them. */
 hec_status hec_ctx_create(const hec_params *params, int device, void *hip_stream, hec_ctx **out);
+/* Waits for the context's stream and frees its device memory.  Every handle of
+ * the context (ciphertexts, plaintexts, images, plans, blocks) must have been
+ * freed before: they refer to the context's memory pool. */
 void hec_ctx_destroy(hec_ctx *ctx);
 const char *hec_last_error(void);
 
@@ -131,6 +137,9 @@ hec_status ckks_rescale(hec_ctx *ctx, hec_ct *inout);
 hec_status ckks_mul_pt(hec_ctx *ctx, const hec_ct *ct, const hec_pt *pt, hec_ct **out);
 /* a + b (levels and scales must match). */
 hec_status ckks_add(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
+/* ct + pt (pt at the ciphertext's level and scale: HEC_ELEVEL / HEC_ESCALE
+ * otherwise; special-prime limbs of pt, if any, are ignored). */
+hec_status ckks_add_pt(hec_ctx *ctx, const hec_ct *ct, const hec_pt *pt, hec_ct **out);
 /* a - b (levels and scales must match). */
 hec_status ckks_sub(hec_ctx *ctx, const hec_ct *a, const hec_ct *b, hec_ct **out);
 /* Ciphertext product (the multiplications of the polynomial activation,
@@ -269,6 +278,31 @@ hec_status he_cheb_eval(hec_ctx *ctx, const hec_ct *x, const double *coeffs, siz
  * get p(0)). */
 hec_status he_image_cheb_eval(hec_ctx *ctx, const hec_image *in, const double *coeffs, size_t ncoeffs, double a,
                               double b, hec_image **out);
+
+/* Per-channel bias (the shift of an inference batch norm folded into the
+ * preceding convolution, Section 4.3 "Batch Normalization"): bias[C] of the
+ * image's logical channels, packed like the image (channel f's value on every
+ * valid pixel of its blocks, zero elsewhere), encoded at each shard's level
+ * and scale and added.  Shards must share level and scale. */
+hec_status he_image_add_bias(hec_ctx *ctx, const hec_image *in, const double *bias, hec_image **out);
+
+/* Basic block of the encrypted ResNets (Section 4.3; Section 4.1 and 4.2 for
+ * its layers): conv k x k (w1 [C1][C][k][k], stride 1, padding k/2) with the
+ * batch norm bn1 = [gamma[C1], shift[C1]] folded into weights and bias and
+ * divided by `bound` (the map of [-bound, bound] onto [-1, 1]), the
+ * activation as the Chebyshev series coeffs on [-1, 1] (for GELU: the
+ * expansion of GELU(bound * y)), conv w2 [C2][C1][k][k] with bn2 folded (NULL:
+ * no batch norm, no bias), 2x2 average pooling.  Folding: w'[o] = w[o] *
+ * (gamma[o] / d), bias'[o] = shift[o] / d (d = bound, then 1).  mode as for
+ * convolution plans (0..3); the pooling uses mode 2 or 3 when the block does,
+ * else 0.  `like` fixes the input layout and level; he_block_steps lists the
+ * rotation keys.  Levels: conv 1, activation (degree 59: 6), conv 1, pooling. */
+hec_status he_block_create(hec_ctx *ctx, const hec_image *like, const double *w1, uint32_t C1, const double *bn1,
+                           const double *w2, uint32_t C2, const double *bn2, uint32_t k, double bound,
+                           const double *coeffs, size_t ncoeffs, int mode, hec_block **out);
+hec_status he_block_steps(const hec_block *block, int32_t *steps, size_t cap, size_t *count);
+hec_status he_block_run(hec_ctx *ctx, const hec_block *block, const hec_image *in, hec_image **out);
+void he_block_free(hec_block *block);
 
 void hec_ct_free(hec_ct *ct);
 void hec_pt_free(hec_pt *pt);

@@ -23,6 +23,7 @@ SOURCES = [
     ("hec_encode.hip", "hip"),
     ("hec_layers.cpp", "cxx"),
     ("hec_poly.cpp", "cxx"),
+    ("hec_block.cpp", "cxx"),
     ("hec_host.cpp", "cxx"),
 ]
 

@@ -1282,3 +1282,32 @@ extern "C" hec_status ckks_drop(hec_ctx *c, const hec_ct *a, uint32_t level, hec
     if (!c || !a) HEC_FAIL(HEC_EINVAL, "NULL argument");
     HEC_ABI_OUT1(ct_drop(c, a, level, out));
 }
+
+hec_status ct_add_pt(hec_ctx *c, const hec_ct *a, const hec_pt *pt, hec_ct **out)
+{
+    *out = nullptr;
+    if (a->level != pt->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in plaintext addition");
+    if (a->scale != pt->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in plaintext addition");
+    const size_t nq = a->level + 1;
+    u64 *t = c->alloc(nq * c->n);
+    hec_ct *o = ct_clone(a);
+    if (!t || !o) {
+        c->release(t);
+        ct_free(o);
+        HEC_FAIL(HEC_ENOMEM, "plaintext addition buffers");
+    }
+    // the plaintext's Q limbs out of Montgomery form, added to c0
+    hec_ew(c->T, EW_FROM_MONT, t, pt->d, nullptr, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
+    hec_ew(c->T, EW_ADD, o->d, o->d, t, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
+    c->release(t);
+    *out = o;
+    return HEC_OK;
+}
+
+extern "C" hec_status ckks_add_pt(hec_ctx *c, const hec_ct *a, const hec_pt *pt, hec_ct **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !a || !pt) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_ABI_OUT1(ct_add_pt(c, a, pt, out));
+}

@@ -3,6 +3,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -158,5 +159,27 @@ void pt_free(hec_pt *p);
 void ct_free(hec_ct *p);
 bool have_rotkey(hec_ctx *c, int32_t step);
 
+// ct + pt (pt at the ciphertext's level and scale, without special-prime limbs)
+hec_status ct_add_pt(hec_ctx *c, const hec_ct *a, const hec_pt *pt, hec_ct **out);
+
+// ---- polynomial evaluation (hec_poly.cpp) ----------------------------------
+// level and scale of the Chebyshev evaluation of a (level, scale) input, from a
+// run over levels and scales only (also checks the constants and the level budget)
+hec_status cheb_levels(hec_ctx *c, uint32_t level, double scale, const double *coeffs, size_t n, double a, double b,
+                       uint32_t *out_level, double *out_scale);
+// the evaluation of every ciphertext of `in` (new handles in out)
+hec_status cheb_image(hec_ctx *c, const std::vector<hec_ct *> &in, const double *coeffs, size_t n, double a, double b,
+                      std::vector<hec_ct *> &out);
+
 // ---- layers (hec_layers.cpp) ---------------------------------------------
 Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t mp = 0);
+// rotation steps of 2x2 pooling (select: the downsampling of a strided convolution) at `level`
+void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps);
+// convolution plan for an image of layout `lay` at `level` (what he_conv2d_plan_create builds from an image)
+hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t level, const double *w, uint32_t Co, uint32_t kh,
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out);
+// output layout of a plan (before the downsampling of a strided one)
+const Layout &conv_plan_out(const hec_conv_plan *p);
+// in + the per-channel bias (new handles in out)
+hec_status image_add_bias(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, const double *bias,
+                          std::vector<hec_ct *> &out);

@@ -1134,7 +1134,7 @@ static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &
 }
 
 // rotation steps of a pooling step (for key generation)
-static void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps)
+void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps)
 {
     const uint32_t mp = L.mp;
     uint32_t Ho = select ? (L.H + 1) / 2 : L.H / 2, Wo = select ? (L.W + 1) / 2 : L.W / 2;
@@ -1259,22 +1259,33 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !like || !w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
-    if (stride != 1 && stride != 2) HEC_FAIL(HEC_EINVAL, "stride must be 1 or 2");
     if (like->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     const uint32_t lvl = like->shards[0]->level;
     for (auto *s : like->shards)
         if (s->level != lvl) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
+    return conv_plan_create(c, like->lay, lvl, w, Co, kh, kw, stride, pad, out);
+}
+
+const Layout &conv_plan_out(const hec_conv_plan *p) { return p->out; }
+
+hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const double *w, uint32_t Co, uint32_t kh,
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out)
+{
+    *out = nullptr;
+    if (!w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
+    if (stride != 1 && stride != 2) HEC_FAIL(HEC_EINVAL, "stride must be 1 or 2");
+    if (!lay.shards()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     if (lvl < 1) HEC_FAIL(HEC_ELEVEL, "convolution needs a level");
     if (stride == 2 && lvl < 2) HEC_FAIL(HEC_ELEVEL, "strided convolution needs two levels");
     HEC_TRY_HIP(hipSetDevice(c->dev));
     std::unique_ptr<hec_conv_plan> p(new hec_conv_plan());
     p->ctx = c;
-    p->in = like->lay;
+    p->in = lay;
     p->level = lvl;
     p->stride = stride;
     std::vector<std::vector<ConvItem>> items;
-    if (like->lay.channel) HEC_CHECK(conv_items_channel(like->lay, w, Co, kh, kw, pad, p->out, items));
-    else HEC_CHECK(conv_items(like->lay, w, Co, kh, kw, pad, p->out, items));
+    if (lay.channel) HEC_CHECK(conv_items_channel(lay, w, Co, kh, kw, pad, p->out, items));
+    else HEC_CHECK(conv_items(lay, w, Co, kh, kw, pad, p->out, items));
     p->items.resize(items.size());
     std::vector<const double *> zp;
     for (auto &v : items)
@@ -1294,7 +1305,7 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
                 if (a % (int32_t)c->N) p->steps.insert(a);
             p->items[u].push_back(std::move(pi));
         }
-    p->w.assign(w, w + (size_t)Co * like->lay.C * kh * kw);
+    p->w.assign(w, w + (size_t)Co * lay.C * kh * kw);
     p->Co = Co;
     p->kh = kh;
     p->kw = kw;
@@ -1604,5 +1615,56 @@ extern "C" hec_status he_linear(hec_ctx *c, const hec_image *in, const double *W
         return s;
     }
     *out = res;
+    return HEC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-channel bias (batch norm's shift folded into the convolution, Section
+// 4.3): the packed image whose channel f is bias[f] on every valid pixel,
+// encoded at each shard's level and scale and added
+// ---------------------------------------------------------------------------
+hec_status image_add_bias(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, const double *bias,
+                          std::vector<hec_ct *> &out)
+{
+    out.clear();
+    if (in.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    for (auto *s : in)
+        if (s->level != in[0]->level || s->scale != in[0]->scale) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
+    for (uint32_t f = 0; f < L.C; f++)
+        if (!std::isfinite(bias[f])) HEC_FAIL(HEC_EINVAL, "bias %u not finite", f);
+    std::vector<double> x((size_t)L.C * L.H * L.W);
+    for (uint32_t f = 0; f < L.C; f++) std::fill(x.begin() + (size_t)f * L.H * L.W, x.begin() + (size_t)(f + 1) * L.H * L.W, bias[f]);
+    std::vector<std::vector<double>> v(in.size());
+    std::vector<const double *> zp;
+    for (uint32_t u = 0; u < in.size(); u++) {
+        pack_shard(L, x.data(), u, v[u]);
+        zp.push_back(v[u].data());
+    }
+    std::vector<hec_pt *> pts;
+    HEC_CHECK(pt_encode_many(c, zp, c->N, in[0]->level, in[0]->scale, pts));
+    hec_status s = HEC_OK;
+    for (size_t u = 0; u < in.size() && s == HEC_OK; u++) {
+        hec_ct *o = nullptr;
+        s = ct_add_pt(c, in[u], pts[u], &o);
+        if (s == HEC_OK) out.push_back(o);
+    }
+    for (auto *p : pts) pt_free(p);
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
+extern "C" hec_status he_image_add_bias(hec_ctx *c, const hec_image *in, const double *bias, hec_image **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !in || !bias) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    hec_image *im = image_new(c, in->lay);
+    hec_status s = image_add_bias(c, in->shards, in->lay, bias, im->shards);
+    if (s != HEC_OK) {
+        hec_image_free(im);
+        return s;
+    }
+    *out = im;
     return HEC_OK;
 }

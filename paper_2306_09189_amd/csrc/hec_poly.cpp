@@ -70,17 +70,41 @@ struct Val {
     }
 };
 
+// dry: levels and scales only (ciphertexts without device data), to learn the
+// output level and check the level budget and constants before any launch
 struct ChebEval {
     hec_ctx *c;
     Ct x;
     double a, b;
+    bool dry;
     std::vector<double> S;  // nominal scale per level
 
-    ChebEval(hec_ctx *ctx, Ct in, double lo, double hi) : c(ctx), x(std::move(in)), a(lo), b(hi)
+    ChebEval(hec_ctx *ctx, Ct in, double lo, double hi, bool dry_run = false)
+        : c(ctx), x(std::move(in)), a(lo), b(hi), dry(dry_run)
     {
         S.assign(x->level + 1, 0.0);
         S[x->level] = x->scale;
         for (uint32_t l = x->level; l > 0; l--) S[l - 1] = (S[l] * S[l]) / (double)c->mod[l];
+    }
+
+    Ct meta(uint32_t level, double scale)
+    {
+        hec_ct *o = new hec_ct();
+        o->ctx = c;
+        o->level = level;
+        o->scale = scale;
+        return wrap(o);
+    }
+
+    void rescale(const Ct &ct)
+    {
+        if (!dry) {
+            PTRY(ct_rescale(c, ct.get()));
+            return;
+        }
+        if (ct->level == 0) PFAIL(HEC_ELEVEL, "cannot rescale at level 0");
+        ct->scale /= (double)c->mod[ct->level];
+        ct->level -= 1;
     }
 
     // ct (level l) * value at S[l-1] q_l / ct.scale, not rescaled; nominal scale S[l-1] q_l
@@ -89,9 +113,16 @@ struct ChebEval {
         const uint32_t l = ct->level;
         if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         const double pscale = S[l - 1] * (double)c->mod[l] / ct->scale;
-        hec_ct *o = nullptr;
-        PTRY(ct_mul_const(c, ct.get(), value, pscale, &o));
-        Ct r = wrap(o);
+        Ct r;
+        if (dry) {
+            int64_t m;
+            PTRY(const_coeff(value, pscale, &m));
+            r = meta(l, 0.0);
+        } else {
+            hec_ct *o = nullptr;
+            PTRY(ct_mul_const(c, ct.get(), value, pscale, &o));
+            r = wrap(o);
+        }
         r->scale = S[l - 1] * (double)c->mod[l];
         return r;
     }
@@ -101,13 +132,17 @@ struct ChebEval {
     {
         const uint32_t l = ct->level;
         Ct r = const_mul_raw(ct, value);
-        PTRY(ct_rescale(c, r.get()));
+        rescale(r);
         r->scale = S[l - 1];
         return r;
     }
 
     Ct drop(const Ct &ct, uint32_t level)
     {
+        if (dry) {
+            if (level > ct->level) PFAIL(HEC_ELEVEL, "cannot raise a level");
+            return meta(level, ct->scale);
+        }
         hec_ct *o = nullptr;
         PTRY(ct_drop(c, ct.get(), level, &o));
         return wrap(o);
@@ -133,10 +168,15 @@ struct ChebEval {
         const uint32_t l = std::min(u0->level, v0->level);
         if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         Ct u = adjust(u0, l), v = adjust(v0, l);
-        hec_ct *o = nullptr;
-        PTRY(ct_mul(c, u.get(), v.get(), &o));
-        Ct r = wrap(o);
-        PTRY(ct_rescale(c, r.get()));
+        Ct r;
+        if (dry) {
+            r = meta(l, u->scale * v->scale);
+        } else {
+            hec_ct *o = nullptr;
+            PTRY(ct_mul(c, u.get(), v.get(), &o));
+            r = wrap(o);
+        }
+        rescale(r);
         if (r->scale != S[l - 1]) PFAIL(HEC_ESCALE, "product scale off the scale table");
         return r;
     }
@@ -144,6 +184,7 @@ struct ChebEval {
     Ct add_raw(const Ct &u, const Ct &v)
     {
         if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch in addition");
+        if (dry) return meta(u->level, u->scale);
         hec_ct *o = ct_clone(u.get());
         if (!o) PFAIL(HEC_ENOMEM, "ciphertext allocation");
         Ct r = wrap(o);
@@ -159,6 +200,11 @@ struct ChebEval {
 
     Ct add_const(const Ct &u, double v)
     {
+        if (dry) {
+            int64_t m;
+            PTRY(const_coeff(v, u->scale, &m));
+            return meta(u->level, u->scale);
+        }
         hec_ct *o = nullptr;
         PTRY(ct_add_const(c, u.get(), v, u->scale, &o));
         return wrap(o);
@@ -166,6 +212,10 @@ struct ChebEval {
 
     Ct sub(const Ct &u, const Ct &v)
     {
+        if (dry) {
+            if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch");
+            return meta(u->level, u->scale);
+        }
         hec_ct *o = nullptr;
         PTRY(ct_sub(c, u.get(), v.get(), &o));
         return wrap(o);
@@ -215,7 +265,7 @@ struct ChebEval {
             Ct t = const_mul_raw(T[j]->level == top + 1 ? T[j] : drop(T[j], top + 1), cf[j]);
             acc = acc ? add_raw(acc, t) : t;
         }
-        PTRY(ct_rescale(c, acc.get()));
+        rescale(acc);
         acc->scale = S[top];
         return Val::of(cf[0] != 0.0 ? add_const(acc, cf[0]) : acc);
     }
@@ -287,13 +337,22 @@ hec_status check_args(hec_ctx *c, const double *coeffs, size_t n, double a, doub
     return HEC_OK;
 }
 
-// the evaluation of one ciphertext; x is borrowed
-hec_status cheb_one(hec_ctx *c, const hec_ct *x, const std::vector<double> &cf, double a, double b, hec_ct **out)
+// the evaluation of one ciphertext (x borrowed), or with dry its level and scale only
+hec_status cheb_one(hec_ctx *c, const hec_ct *x, const std::vector<double> &cf, double a, double b, bool dry,
+                    hec_ct **out)
 {
     try {
-        hec_ct *xc = ct_clone(x);
-        if (!xc) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-        ChebEval ev(c, wrap(xc), a, b);
+        hec_ct *xc = nullptr;
+        if (dry) {
+            xc = new hec_ct();
+            xc->ctx = c;
+            xc->level = x->level;
+            xc->scale = x->scale;
+        } else {
+            xc = ct_clone(x);
+            if (!xc) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+        }
+        ChebEval ev(c, wrap(xc), a, b, dry);
         Ct r = ev.run(cf);
         // move the result's storage into a handle of its own
         hec_ct *o = new hec_ct(*r);
@@ -309,22 +368,60 @@ hec_status cheb_one(hec_ctx *c, const hec_ct *x, const std::vector<double> &cf, 
 
 }  // namespace
 
+hec_status cheb_levels(hec_ctx *c, uint32_t level, double scale, const double *coeffs, size_t n, double a, double b,
+                       uint32_t *out_level, double *out_scale)
+{
+    HEC_CHECK(check_args(c, coeffs, n, a, b));
+    hec_ct x;
+    x.ctx = c;
+    x.level = level;
+    x.scale = scale;
+    hec_ct *r = nullptr;
+    HEC_CHECK(cheb_one(c, &x, std::vector<double>(coeffs, coeffs + n), a, b, true, &r));
+    *out_level = r->level;
+    if (out_scale) *out_scale = r->scale;
+    delete r;
+    return HEC_OK;
+}
+
+hec_status cheb_image(hec_ctx *c, const std::vector<hec_ct *> &in, const double *coeffs, size_t n, double a, double b,
+                      std::vector<hec_ct *> &out)
+{
+    HEC_CHECK(check_args(c, coeffs, n, a, b));
+    std::vector<double> cf(coeffs, coeffs + n);
+    out.clear();
+    for (const hec_ct *x : in) {
+        hec_ct *o = nullptr;
+        hec_status s = cheb_one(c, x, cf, a, b, true, &o);  // levels and constants first
+        delete o;
+        o = nullptr;
+        if (s == HEC_OK) s = cheb_one(c, x, cf, a, b, false, &o);
+        if (s != HEC_OK) {
+            for (auto *p : out) ct_free(p);
+            out.clear();
+            return s;
+        }
+        out.push_back(o);
+    }
+    if (hipGetLastError() != hipSuccess) {
+        for (auto *p : out) ct_free(p);
+        out.clear();
+        HEC_FAIL(HEC_EDEVICE, "kernel launch failed");
+    }
+    return HEC_OK;
+}
+
 extern "C" hec_status he_cheb_eval(hec_ctx *c, const hec_ct *x, const double *coeffs, size_t ncoeffs, double a,
                                    double b, hec_ct **out)
 {
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !x) HEC_FAIL(HEC_EINVAL, "NULL argument");
-    HEC_CHECK(check_args(c, coeffs, ncoeffs, a, b));
     HEC_TRY_HIP(hipSetDevice(c->dev));
-    std::vector<double> cf(coeffs, coeffs + ncoeffs);
-    hec_status s = cheb_one(c, x, cf, a, b, out);
-    if (s == HEC_OK && hipGetLastError() != hipSuccess) {
-        ct_free(*out);
-        *out = nullptr;
-        HEC_FAIL(HEC_EDEVICE, "kernel launch failed");
-    }
-    return s;
+    std::vector<hec_ct *> o;
+    HEC_CHECK(cheb_image(c, {const_cast<hec_ct *>(x)}, coeffs, ncoeffs, a, b, o));
+    *out = o[0];
+    return HEC_OK;
 }
 
 extern "C" hec_status he_image_cheb_eval(hec_ctx *c, const hec_image *in, const double *coeffs, size_t ncoeffs,
@@ -334,23 +431,11 @@ extern "C" hec_status he_image_cheb_eval(hec_ctx *c, const hec_image *in, const 
     *out = nullptr;
     if (!c || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
     if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
-    HEC_CHECK(check_args(c, coeffs, ncoeffs, a, b));
     HEC_TRY_HIP(hipSetDevice(c->dev));
-    std::vector<double> cf(coeffs, coeffs + ncoeffs);
     hec_image *im = new hec_image();
     im->ctx = c;
     im->lay = in->lay;
-    hec_status s = HEC_OK;
-    for (const hec_ct *x : in->shards) {
-        hec_ct *o = nullptr;
-        s = cheb_one(c, x, cf, a, b, &o);
-        if (s != HEC_OK) break;
-        im->shards.push_back(o);
-    }
-    if (s == HEC_OK && hipGetLastError() != hipSuccess) {
-        s = HEC_EDEVICE;
-        hec_set_error("kernel launch failed");
-    }
+    hec_status s = cheb_image(c, in->shards, coeffs, ncoeffs, a, b, im->shards);
     if (s != HEC_OK) {
         hec_image_free(im);
         return s;

@@ -24,6 +24,7 @@ EXPORTS = [
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
+    "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
 ]
 
 
@@ -85,6 +86,12 @@ def lib():
             "ckks_drop": (c, [vp, vp, u32, P(vp)]),
             "he_cheb_eval": (c, [vp, vp, dblp, sz, dbl, dbl, P(vp)]),
             "he_image_cheb_eval": (c, [vp, vp, dblp, sz, dbl, dbl, P(vp)]),
+            "ckks_add_pt": (c, [vp, vp, vp, P(vp)]),
+            "he_image_add_bias": (c, [vp, vp, dblp, P(vp)]),
+            "he_block_create": (c, [vp, vp, dblp, u32, dblp, dblp, u32, dblp, u32, dbl, dblp, sz, c, P(vp)]),
+            "he_block_steps": (c, [vp, i32p, sz, szp]),
+            "he_block_run": (c, [vp, vp, vp, P(vp)]),
+            "he_block_free": (None, [vp]),
             "ckks_ct_info": (c, [vp, u32p, dblp]),
             "ckks_ct_export": (c, [vp, vp, u64p, u32p, dblp]),
             "ckks_ct_import": (c, [vp, u64p, u32, dbl, P(vp)]),
@@ -137,20 +144,38 @@ def _p(a, t):
     return a.ctypes.data_as(t)
 
 
-class Ciphertext:
-    def __init__(self, ctx, handle):
-        self.ctx, self.h = ctx, handle
+class _Handle:
+    """A native handle that belongs to a context.  The context's native
+    destruction waits until every handle of it is freed: objects collected
+    together as cyclic garbage (for instance a script's globals at interpreter
+    exit) are finalized in no particular order, and a handle freed after its
+    context would touch freed memory."""
+    _free_fn = None
+
+    def __init__(self, ctx, handle, owned=True):
+        self.ctx, self.h, self._owned = ctx, handle, bool(owned and handle)
+        if self._owned:
+            ctx._retain()
 
     def free(self):
         if self.h:
-            lib().hec_ct_free(self.h)
-            self.h = None
+            h, self.h = self.h, None
+            if self._owned:
+                self._owned = False
+                try:
+                    getattr(lib(), self._free_fn)(h)
+                finally:
+                    self.ctx._release()
 
     def __del__(self):
         try:
             self.free()
         except Exception:
             pass
+
+
+class Ciphertext(_Handle):
+    _free_fn = "hec_ct_free"
 
     def info(self):
         lvl, sc = ctypes.c_uint32(), ctypes.c_double()
@@ -173,20 +198,12 @@ class Ciphertext:
         return out
 
 
-class Plaintext:
+class Plaintext(_Handle):
+    _free_fn = "hec_pt_free"
+
     def __init__(self, ctx, handle, level, scale):
-        self.ctx, self.h, self.level, self.scale = ctx, handle, level, scale
-
-    def free(self):
-        if self.h:
-            lib().hec_pt_free(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.free()
-        except Exception:
-            pass
+        super().__init__(ctx, handle)
+        self.level, self.scale = level, scale
 
     def export(self):
         out = np.zeros((self.level + 1, self.ctx.n), dtype=np.uint64)
@@ -194,20 +211,8 @@ class Plaintext:
         return out
 
 
-class Image:
-    def __init__(self, ctx, handle):
-        self.ctx, self.h = ctx, handle
-
-    def free(self):
-        if self.h:
-            lib().hec_image_free(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.free()
-        except Exception:
-            pass
+class Image(_Handle):
+    _free_fn = "hec_image_free"
 
     def info(self):
         v = [ctypes.c_uint32() for _ in range(5)]
@@ -234,11 +239,7 @@ class Image:
         h = lib().he_image_shard(self.h, u)
         if not h:
             raise IndexError(u)
-        ct = Ciphertext(self.ctx, h)
-        try:
-            return ct.export()
-        finally:
-            ct.h = None  # borrowed
+        return Ciphertext(self.ctx, h, owned=False).export()
 
     def shard_info(self, u):
         h = lib().he_image_shard(self.h, u)
@@ -253,20 +254,24 @@ class Image:
         return x
 
 
-class ConvPlan:
-    def __init__(self, ctx, handle):
-        self.ctx, self.h = ctx, handle
+class Block(_Handle):
+    _free_fn = "he_block_free"
 
-    def free(self):
-        if self.h:
-            lib().he_conv2d_plan_free(self.h)
-            self.h = None
+    def steps(self):
+        n = ctypes.c_size_t()
+        check(lib().he_block_steps(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int32)
+        check(lib().he_block_steps(self.h, _p(out, i32p), len(out), ctypes.byref(n)))
+        return [int(x) for x in out]
 
-    def __del__(self):
-        try:
-            self.free()
-        except Exception:
-            pass
+    def run(self, img):
+        out = vp()
+        check(lib().he_block_run(self.ctx.h, self.h, img.h, ctypes.byref(out)))
+        return Image(self.ctx, out.value)
+
+
+class ConvPlan(_Handle):
+    _free_fn = "he_conv2d_plan_free"
 
     def steps(self):
         n = ctypes.c_size_t()
@@ -296,11 +301,30 @@ class Context:
         self.n = 1 << log_n
         self.N = self.n // 2
         self.L, self.k = L, k
+        self._live, self._close_pending = 0, False
+
+    def _retain(self):
+        self._live += 1
+
+    def _release(self):
+        self._live -= 1
+        if self._live == 0 and self._close_pending:
+            self._destroy()
+
+    def _destroy(self):
+        h, self.h = self.h, None
+        self._close_pending = False
+        if h:
+            lib().hec_ctx_destroy(h)
 
     def close(self):
+        """Destroy the native context, or, while handles of it are alive, when
+        the last of them is freed."""
         if getattr(self, "h", None):
-            lib().hec_ctx_destroy(self.h)
-            self.h = None
+            if getattr(self, "_live", 0) > 0:
+                self._close_pending = True
+            else:
+                self._destroy()
 
     def __del__(self):
         try:
@@ -425,6 +449,33 @@ class Context:
             return Image(self, out.value)
         check(lib().he_cheb_eval(self.h, x.h, _p(cf, dblp), len(cf), float(a), float(b), ctypes.byref(out)))
         return Ciphertext(self, out.value)
+
+    def add_pt(self, ct, pt):
+        out = vp()
+        check(lib().ckks_add_pt(self.h, ct.h, pt.h, ctypes.byref(out)))
+        return Ciphertext(self, out.value)
+
+    def add_bias(self, img, bias):
+        """Per-channel bias on every valid pixel of each channel."""
+        b = _arr(bias, np.float64)
+        out = vp()
+        check(lib().he_image_add_bias(self.h, img.h, _p(b, dblp), ctypes.byref(out)))
+        return Image(self, out.value)
+
+    def block(self, like, w1, bn1, w2, bn2, bound, coeffs, mode=0):
+        """Basic block: conv(w1, bn1 folded) -> activation series on [-1, 1] -> conv(w2, bn2) -> 2x2 avg pool.
+        bn = (gamma, shift) per output channel; bn2 may be None."""
+        w1, w2 = _arr(w1, np.float64), _arr(w2, np.float64)
+        C1, C2, k = w1.shape[0], w2.shape[0], w1.shape[2]
+        b1 = _arr(np.concatenate([np.asarray(bn1[0], np.float64), np.asarray(bn1[1], np.float64)]), np.float64)
+        b2 = None if bn2 is None else _arr(np.concatenate([np.asarray(bn2[0], np.float64),
+                                                           np.asarray(bn2[1], np.float64)]), np.float64)
+        cf = _arr(coeffs, np.float64)
+        out = vp()
+        check(lib().he_block_create(self.h, like.h, _p(w1, dblp), C1, _p(b1, dblp), _p(w2, dblp), C2,
+                                    None if b2 is None else _p(b2, dblp), k, float(bound), _p(cf, dblp), len(cf),
+                                    int(mode), ctypes.byref(out)))
+        return Block(self, out.value)
 
     def image_encrypt(self, x, level, seed):
         x = _arr(x, np.float64)
