@@ -307,6 +307,49 @@ def main():
     ctx.sync()
     rot_single = 32 / (time.perf_counter() - s)
 
+    # GELU as the degree-59 Chebyshev interpolant over [-15, 15] (its map onto
+    # [-1, 1] folded into the input) on one ciphertext at level 20, and the
+    # conv -> bias -> GELU -> conv -> pool block on a 16x32x32 CIFAR stage
+    from numpy.polynomial import chebyshev as Cheb
+
+    def gelu(v):
+        return 0.5 * v * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (v + 0.044715 * v ** 3)))
+    bound = 15.0
+    coef = Cheb.chebinterpolate(lambda y: gelu(bound * y), 59)
+    zg = rng.uniform(-1, 1, ctx.N)
+    ctg = ctx.encrypt(ctx.encode(zg, LEVEL, 2.0 ** LOG_SCALE), 6)
+    ts = []
+    for _ in range(5):
+        ctx.sync()
+        s = time.perf_counter()
+        g = ctx.cheb_eval(ctg, coef, -1.0, 1.0)
+        ctx.sync()
+        ts.append((time.perf_counter() - s) * 1e3)
+    gelu_ms = float(np.median(ts))
+    gelu_err = float(np.abs(ctx.decrypt(g) - gelu(bound * zg)).max())
+    gelu_levels = LEVEL - g.level
+    del g, ctg
+    xb = rng.uniform(-1, 1, (16, 32, 32))
+    wb1, wb2 = rng.normal(0, 1 / 12.0, (16, 16, 3, 3)), rng.normal(0, 1 / 12.0, (16, 16, 3, 3))
+    bn1 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
+    bn2 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
+    imb = ctx.image_encrypt(xb, LEVEL, 7)
+    bmode = args.mode if args.mode >= 2 else 2
+    blk = ctx.block(imb, wb1, bn1, wb2, bn2, bound, coef, mode=bmode)
+    ctx.gen_rotation_keys(blk.steps())
+    ts = []
+    for _ in range(4):
+        ctx.sync()
+        k0 = ctx.keyswitch_count()
+        s = time.perf_counter()
+        ob = blk.run(imb)
+        ctx.sync()
+        ts.append((time.perf_counter() - s) * 1e3)
+        ks_block = ctx.keyswitch_count() - k0
+    block_ms = float(np.median(ts[1:]))
+    block_err = float(np.abs(ob.decrypt() - hl.ref_basic_block(xb, wb1, bn1, wb2, bn2, bound, coef)).max())
+    del ob, blk, imb
+
     out = {
         "metric": "key-switched rotations/sec + HE conv-layer ms at 2N=2^16; batched vs plain",
         "value": value,
@@ -333,6 +376,13 @@ def main():
                        "keyswitches_per_step": ks_other, "max_abs_err_vs_fp64": err_other},
         "rot_per_s_hoisted_level20": rot_hoisted,
         "rot_per_s_single_level20": rot_single,
+        "gelu_deg59_ms_per_ct_level20": gelu_ms,
+        "gelu_levels": gelu_levels,
+        "gelu_max_abs_err_vs_gelu": gelu_err,
+        "block_16x32x32_ms": block_ms,
+        "block_plan_mode": bmode,
+        "block_keyswitches": ks_block,
+        "block_max_abs_err_vs_fp64": block_err,
         "max_abs_err_vs_fp64": err,
         "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
         "roofline": roofline,
