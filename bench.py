@@ -163,6 +163,9 @@ def main():
                     help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown, "
                          "3 baby-step/giant-step with double hoisting")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
+    ap.add_argument("--profile-run", choices=("gelu", "block"),
+                    help="for kernel traces: five degree-59 GELU evaluations on one level-20 ciphertext, or five "
+                         "runs of the 16x32x32 block, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         eprint("bench.py measures one GPU: this build runs the whole path on a single MI355X "
@@ -179,6 +182,31 @@ def main():
     x = rng.uniform(-1, 1, (32, 32, 32))
     w1 = rng.normal(0, 0.05, (32, 32, 3, 3))
     w2 = rng.normal(0, 0.05, (64, 32, 3, 3))
+    if args.profile_run:
+        from numpy.polynomial import chebyshev as Cheb
+
+        def gelu_f(v):
+            return 0.5 * v * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (v + 0.044715 * v ** 3)))
+        coef = Cheb.chebinterpolate(lambda y: gelu_f(15.0 * y), 59)
+        ctx.keygen(2002)
+        if args.profile_run == "gelu":
+            ct = ctx.encrypt(ctx.encode(rng.uniform(-1, 1, ctx.N), LEVEL, 2.0 ** LOG_SCALE), 6)
+            for _ in range(5):
+                r = ctx.cheb_eval(ct, coef, -1.0, 1.0)
+                del r
+        else:
+            xb = rng.uniform(-1, 1, (16, 32, 32))
+            wb1, wb2 = rng.normal(0, 1 / 12.0, (16, 16, 3, 3)), rng.normal(0, 1 / 12.0, (16, 16, 3, 3))
+            bn = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
+            imb = ctx.image_encrypt(xb, LEVEL, 7)
+            blk = ctx.block(imb, wb1, bn, wb2, bn, 15.0, coef, mode=args.mode if args.mode >= 2 else 2)
+            ctx.gen_rotation_keys(blk.steps())
+            for _ in range(5):
+                ob = blk.run(imb)
+                del ob
+        ctx.sync()
+        eprint("profile run done")
+        return
     if args.pmc_run:
         # short run for hardware-counter passes: one conv layer, then a plain
         # device copy of exactly 256 MiB to calibrate the byte counters

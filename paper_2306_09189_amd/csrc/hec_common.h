@@ -92,8 +92,9 @@ void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, 
 void hec_ntt_inv(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
                  hipStream_t st);
 
-enum EwOp { EW_ADD = 0, EW_SUB, EW_NEG, EW_MUL_MONT, EW_MAC_MONT, EW_TO_MONT, EW_FROM_MONT, EW_COPY, EW_ZERO };
-// out = op(a, b) over nlimbs x n per poly (poly strides given separately for out/a/b; b stride may be 0 to
+enum EwOp { EW_ADD = 0, EW_SUB, EW_NEG, EW_MUL_MONT, EW_MAC_MONT, EW_TO_MONT, EW_FROM_MONT, EW_COPY, EW_ZERO,
+            EW_DBL_SUB };
+// out = op(a, b) over nlimbs x n per poly (EW_DBL_SUB: 2a - b) (poly strides given separately for out/a/b; b stride may be 0 to
 // broadcast one polynomial over all polys).
 void hec_ew(const DevTables &T, EwOp op, u64 *out, const u64 *a, const u64 *b, size_t so, size_t sa, size_t sb,
             int npolys, const u32 *pmap, int nlimbs, hipStream_t st);
@@ -142,10 +143,14 @@ struct ScalarArg {
     u64 v[HEC_MAX_LIMBS];
     u64 vsh[HEC_MAX_LIMBS];
 };
-// out = in * v_l on nlimbs limbs of npolys polynomials; out = in + v_l on nlimbs limbs of one polynomial
-void hec_scalar_mul(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
-                    const ScalarArg &sa, hipStream_t st);
-void hec_scalar_add(const DevTables &T, u64 *out, const u64 *in, int nlimbs, const ScalarArg &sa, hipStream_t st);
+enum ScalarOp { SC_MUL = 0, SC_ADD, SC_MAC, SC_DBL_ADD };
+// per limb l < nlimbs of npolys polynomials (in read with its own poly stride):
+// SC_MUL out = in * v_l; SC_ADD out = in + v_l on poly 0, in on poly 1;
+// SC_MAC out (+)= in * v_l (first != 0: written); SC_DBL_ADD out = 2 in + v_l on poly 0, 2 in on poly 1
+void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t out_poly_stride,
+                size_t in_poly_stride, int npolys, int nlimbs, int first, const ScalarArg &sa, hipStream_t st);
+// ciphertext tensor product of a, b ([2][nq][n] each): t = [a0 b0][a1 b1][a0 b1 + a1 b0]
+void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, hipStream_t st);
 
 // enc: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk in Montgomery form, the rest plain NTT form)
 void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,

@@ -1093,19 +1093,15 @@ hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
     const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
     const size_t P = (size_t)nq * n;
     // t = [d0][d2][d1]: a ciphertext view (d0, d2) whose second polynomial is the one ModUp reads
-    u64 *t = c->alloc(3 * P), *bm = c->alloc(2 * P), *E = c->alloc(2 * (size_t)nqp * n);
+    u64 *t = c->alloc(3 * P), *E = c->alloc(2 * (size_t)nqp * n);
     hec_ct *o = ct_new(c, lvl, a->scale * b->scale);
-    if (!t || !bm || !E || !o) {
+    if (!t || !E || !o) {
         c->release(t);
-        c->release(bm);
         c->release(E);
         ct_free(o);
         HEC_FAIL(HEC_ENOMEM, "ciphertext product buffers");
     }
-    hec_ew(c->T, EW_TO_MONT, bm, b->d, nullptr, P, P, 0, 2, c->idmap(), (int)nq, c->st);
-    hec_ew(c->T, EW_MUL_MONT, t, a->d, bm, P, P, P, 2, c->idmap(), (int)nq, c->st);  // d0, d2
-    hec_ew(c->T, EW_MUL_MONT, t + 2 * P, a->d, bm + P, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
-    hec_ew(c->T, EW_MAC_MONT, t + 2 * P, a->d + P, bm, 0, 0, 0, 1, c->idmap(), (int)nq, c->st);
+    hec_tensor(c->T, t, a->d, b->d, (int)nq, c->st);
     hec_ct view;
     view.ctx = c;
     view.level = lvl;
@@ -1128,7 +1124,6 @@ hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
     }
     c->release(D);
     c->release(t);
-    c->release(bm);
     c->release(E);
     if (s != HEC_OK) {
         ct_free(o);
@@ -1178,16 +1173,38 @@ static void scalar_arg(const hec_ctx *c, int64_t r, uint32_t nlimbs, ScalarArg &
 
 hec_status ct_mul_const(hec_ctx *c, const hec_ct *a, double value, double pscale, hec_ct **out)
 {
+    return ct_mul_const_at(c, a, a->level, value, pscale, out);
+}
+
+// a's first level+1 limbs (a dropped to `level`) times the constant
+hec_status ct_mul_const_at(hec_ctx *c, const hec_ct *a, uint32_t level, double value, double pscale, hec_ct **out)
+{
     *out = nullptr;
+    if (level > a->level) HEC_FAIL(HEC_ELEVEL, "cannot raise a level");
     int64_t r;
     HEC_CHECK(const_coeff(value, pscale, &r));
-    hec_ct *o = ct_new(c, a->level, a->scale * pscale);
+    hec_ct *o = ct_new(c, level, a->scale * pscale);
     if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
     ScalarArg sa;
-    scalar_arg(c, r, a->level + 1, sa);
-    const size_t P = (size_t)(a->level + 1) * c->n;
-    hec_scalar_mul(c->T, o->d, a->d, P, 2, (int)a->level + 1, sa, c->st);
+    scalar_arg(c, r, level + 1, sa);
+    hec_scalar(c->T, SC_MUL, o->d, a->d, (size_t)(level + 1) * c->n, (size_t)(a->level + 1) * c->n, 2,
+               (int)level + 1, 0, sa, c->st);
     *out = o;
+    return HEC_OK;
+}
+
+// acc (+)= a (dropped to acc's level) * value encoded at pscale; first: written, acc's scale set to
+// a.scale * pscale
+hec_status ct_mac_const(hec_ctx *c, hec_ct *acc, const hec_ct *a, double value, double pscale, bool first)
+{
+    if (acc->level > a->level) HEC_FAIL(HEC_ELEVEL, "cannot raise a level");
+    int64_t r;
+    HEC_CHECK(const_coeff(value, pscale, &r));
+    ScalarArg sa;
+    scalar_arg(c, r, acc->level + 1, sa);
+    hec_scalar(c->T, SC_MAC, acc->d, a->d, (size_t)(acc->level + 1) * c->n, (size_t)(a->level + 1) * c->n, 2,
+               (int)acc->level + 1, first ? 1 : 0, sa, c->st);
+    if (first) acc->scale = a->scale * pscale;
     return HEC_OK;
 }
 
@@ -1196,11 +1213,56 @@ hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale,
     *out = nullptr;
     int64_t r;
     HEC_CHECK(const_coeff(value, scale, &r));
-    hec_ct *o = ct_clone(a);
+    hec_ct *o = ct_new(c, a->level, a->scale);
     if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
     ScalarArg sa;
     scalar_arg(c, r, a->level + 1, sa);
-    hec_scalar_add(c->T, o->d, a->d, (int)a->level + 1, sa, c->st);
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_scalar(c->T, SC_ADD, o->d, a->d, P, P, 2, (int)a->level + 1, 0, sa, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+// 2a + value (encoded at a's scale)
+hec_status ct_dbl_add_const(hec_ctx *c, const hec_ct *a, double value, hec_ct **out)
+{
+    *out = nullptr;
+    int64_t r;
+    HEC_CHECK(const_coeff(value, a->scale, &r));
+    hec_ct *o = ct_new(c, a->level, a->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    ScalarArg sa;
+    scalar_arg(c, r, a->level + 1, sa);
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_scalar(c->T, SC_DBL_ADD, o->d, a->d, P, P, 2, (int)a->level + 1, 0, sa, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+// 2a - b (levels and scales must match)
+hec_status ct_dbl_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    *out = nullptr;
+    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in subtraction");
+    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in subtraction");
+    hec_ct *o = ct_new(c, a->level, a->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_ew(c->T, EW_DBL_SUB, o->d, a->d, b->d, P, P, P, 2, c->idmap(), (int)a->level + 1, c->st);
+    *out = o;
+    return HEC_OK;
+}
+
+// a + b out of place (levels and scales must match)
+hec_status ct_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
+{
+    *out = nullptr;
+    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in addition");
+    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in addition");
+    hec_ct *o = ct_new(c, a->level, a->scale);
+    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+    const size_t P = (size_t)(a->level + 1) * c->n;
+    hec_ew(c->T, EW_ADD, o->d, a->d, b->d, P, P, P, 2, c->idmap(), (int)a->level + 1, c->st);
     *out = o;
     return HEC_OK;
 }

@@ -567,6 +567,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ew(int op, u64 *out, const u64 *
     case EW_FROM_MONT: *o = redc(0, *x, pc.q, pc.qinv_neg); break;
     case EW_COPY: *o = *x; break;
     case EW_ZERO: *o = 0; break;
+    case EW_DBL_SUB: *o = sub_mod(add_mod(*x, *x, pc.q), *y, pc.q); break;
     }
 }
 
@@ -1283,24 +1284,63 @@ void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, con
 // products with and sums of constant polynomials (a constant in every slot
 // encodes as a constant polynomial, whose evaluations are all equal)
 // ---------------------------------------------------------------------------
-__global__ void k_scalar(int op, u64 *out, const u64 *in, size_t ps, ScalarArg sa, DevTables T)
+// op (poly p of out; in read with its own poly stride, so that a ciphertext
+// at a higher level can be read as if dropped):
+//   SC_MUL  out = in * v_l
+//   SC_ADD  out = in + v_l on poly 0, in on poly 1
+//   SC_MAC  out (+)= in * v_l (first: written)
+//   SC_DBL_ADD out = 2 in + v_l on poly 0, 2 in on poly 1
+__global__ void k_scalar(int op, u64 *out, const u64 *in, size_t pso, size_t psi, int first, ScalarArg sa,
+                         DevTables T)
 {
     const u32 l = blockIdx.y, p = blockIdx.z;
     const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (t >= T.n) return;
     const u64 q = T.pc[l].q;
-    const size_t off = p * ps + (size_t)l * T.n + t;
-    const u64 x = in[off];
-    out[off] = op == 0 ? shoup_mul(x, sa.v[l], sa.vsh[l], q) : add_mod(x, sa.v[l], q);
+    const size_t lo = (size_t)l * T.n + t;
+    const u64 x = in[p * psi + lo];
+    u64 *o = out + p * pso + lo;
+    switch (op) {
+    case SC_MUL: *o = shoup_mul(x, sa.v[l], sa.vsh[l], q); break;
+    case SC_ADD: *o = p == 0 ? add_mod(x, sa.v[l], q) : x; break;
+    case SC_MAC: {
+        const u64 y = shoup_mul(x, sa.v[l], sa.vsh[l], q);
+        *o = first ? y : add_mod(*o, y, q);
+        break;
+    }
+    case SC_DBL_ADD: {
+        const u64 d = add_mod(x, x, q);
+        *o = p == 0 ? add_mod(d, sa.v[l], q) : d;
+        break;
+    }
+    }
 }
-void hec_scalar_mul(const DevTables &T, u64 *out, const u64 *in, size_t poly_stride, int npolys, int nlimbs,
-                    const ScalarArg &sa, hipStream_t st)
+void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t out_poly_stride,
+                size_t in_poly_stride, int npolys, int nlimbs, int first, const ScalarArg &sa, hipStream_t st)
 {
+    if (nlimbs <= 0 || npolys <= 0) return;
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
-    hipLaunchKernelGGL(k_scalar, g, dim3(EW_THREADS), 0, st, 0, out, in, poly_stride, sa, T);
+    KLAUNCH("k_scalar", (uint64_t)npolys * nlimbs, k_scalar, g, dim3(EW_THREADS), 0, st, (int)op, out, in,
+            out_poly_stride, in_poly_stride, first, sa, T);
 }
-void hec_scalar_add(const DevTables &T, u64 *out, const u64 *in, int nlimbs, const ScalarArg &sa, hipStream_t st)
+
+// ciphertext tensor product in one pass: t = [a0 b0][a1 b1][a0 b1 + a1 b0]
+// (all plain evaluation form; b taken into Montgomery form in registers)
+__global__ void __launch_bounds__(EW_THREADS) k_tensor(u64 *t, const u64 *a, const u64 *b, size_t P, DevTables T)
 {
-    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, 1);
-    hipLaunchKernelGGL(k_scalar, g, dim3(EW_THREADS), 0, st, 1, out, in, (size_t)0, sa, T);
+    const u32 l = blockIdx.y;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const PrimeC pc = T.pc[l];
+    const size_t off = (size_t)l * T.n + k;
+    const u64 a0 = a[off], a1 = a[P + off];
+    const u64 b0 = mont_mul(b[off], pc.r2, pc.q, pc.qinv_neg), b1 = mont_mul(b[P + off], pc.r2, pc.q, pc.qinv_neg);
+    t[off] = mont_mul(a0, b0, pc.q, pc.qinv_neg);
+    t[P + off] = mont_mul(a1, b1, pc.q, pc.qinv_neg);
+    t[2 * P + off] = add_mod(mont_mul(a0, b1, pc.q, pc.qinv_neg), mont_mul(a1, b0, pc.q, pc.qinv_neg), pc.q);
+}
+void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, hipStream_t st)
+{
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
+    KLAUNCH("k_tensor", (uint64_t)nq, k_tensor, g, dim3(EW_THREADS), 0, st, t, a, b, (size_t)nq * T.n, T);
 }

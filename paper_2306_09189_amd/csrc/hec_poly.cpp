@@ -107,11 +107,12 @@ struct ChebEval {
         ct->level -= 1;
     }
 
-    // ct (level l) * value at S[l-1] q_l / ct.scale, not rescaled; nominal scale S[l-1] q_l
-    Ct const_mul_raw(const Ct &ct, double value)
+    // ct dropped to level l (l <= ct's level) times value at S[l-1] q_l / ct.scale, not rescaled; nominal
+    // scale S[l-1] q_l
+    Ct const_mul_raw(const Ct &ct, double value, uint32_t l)
     {
-        const uint32_t l = ct->level;
         if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
+        if (l > ct->level) PFAIL(HEC_ELEVEL, "cannot raise a level");
         const double pscale = S[l - 1] * (double)c->mod[l] / ct->scale;
         Ct r;
         if (dry) {
@@ -120,32 +121,21 @@ struct ChebEval {
             r = meta(l, 0.0);
         } else {
             hec_ct *o = nullptr;
-            PTRY(ct_mul_const(c, ct.get(), value, pscale, &o));
+            PTRY(ct_mul_const_at(c, ct.get(), l, value, pscale, &o));
             r = wrap(o);
         }
         r->scale = S[l - 1] * (double)c->mod[l];
         return r;
     }
 
-    // ct (level l) * value, rescaled to level l-1 at the nominal scale S[l-1]
-    Ct const_mul(const Ct &ct, double value)
+    // ct dropped to level l (default: its own) times value, rescaled to level l-1 at the nominal scale S[l-1]
+    Ct const_mul(const Ct &ct, double value, uint32_t l = UINT32_MAX)
     {
-        const uint32_t l = ct->level;
-        Ct r = const_mul_raw(ct, value);
+        if (l == UINT32_MAX) l = ct->level;
+        Ct r = const_mul_raw(ct, value, l);
         rescale(r);
         r->scale = S[l - 1];
         return r;
-    }
-
-    Ct drop(const Ct &ct, uint32_t level)
-    {
-        if (dry) {
-            if (level > ct->level) PFAIL(HEC_ELEVEL, "cannot raise a level");
-            return meta(level, ct->scale);
-        }
-        hec_ct *o = nullptr;
-        PTRY(ct_drop(c, ct.get(), level, &o));
-        return wrap(o);
     }
 
     // ct brought down to `level`: limbs dropped to level + 1, times 1 (cached per ciphertext and level; the
@@ -158,7 +148,7 @@ struct ChebEval {
         auto key = std::make_pair((const hec_ct *)ct.get(), level);
         auto it = adj.find(key);
         if (it != adj.end()) return it->second.second;
-        Ct r = const_mul(drop(ct, level + 1), 1.0);
+        Ct r = const_mul(ct, 1.0, level + 1);
         adj[key] = std::make_pair(ct, r);
         return r;
     }
@@ -185,11 +175,9 @@ struct ChebEval {
     {
         if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch in addition");
         if (dry) return meta(u->level, u->scale);
-        hec_ct *o = ct_clone(u.get());
-        if (!o) PFAIL(HEC_ENOMEM, "ciphertext allocation");
-        Ct r = wrap(o);
-        PTRY(ct_add_inplace(c, r.get(), v.get()));
-        return r;
+        hec_ct *o = nullptr;
+        PTRY(ct_add(c, u.get(), v.get(), &o));
+        return wrap(o);
     }
 
     Ct add(const Ct &u, const Ct &v)
@@ -207,6 +195,31 @@ struct ChebEval {
         }
         hec_ct *o = nullptr;
         PTRY(ct_add_const(c, u.get(), v, u->scale, &o));
+        return wrap(o);
+    }
+
+    // 2u + v (v at u's scale)
+    Ct dbl_add_const(const Ct &u, double v)
+    {
+        if (dry) {
+            int64_t m;
+            PTRY(const_coeff(v, u->scale, &m));
+            return meta(u->level, u->scale);
+        }
+        hec_ct *o = nullptr;
+        PTRY(ct_dbl_add_const(c, u.get(), v, &o));
+        return wrap(o);
+    }
+
+    // 2u - v
+    Ct dbl_sub(const Ct &u, const Ct &v)
+    {
+        if (dry) {
+            if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch");
+            return meta(u->level, u->scale);
+        }
+        hec_ct *o = nullptr;
+        PTRY(ct_dbl_sub(c, u.get(), v.get(), &o));
         return wrap(o);
     }
 
@@ -236,16 +249,16 @@ struct ChebEval {
         for (uint32_t k = 2; k < std::min(m, d + 1); k++) {
             if (k % 2 == 0) {
                 Ct p = mul(T[k / 2], T[k / 2]);
-                T[k] = add_const(add_raw(p, p), -1.0);
+                T[k] = dbl_add_const(p, -1.0);
             } else {
                 const uint32_t h = k / 2;
                 Ct p = mul(T[h + 1], T[h]);
-                T[k] = sub(add_raw(p, p), adjust(T[1], p->level));
+                T[k] = dbl_sub(p, adjust(T[1], p->level));
             }
         }
         for (uint32_t g = m; g <= d; g *= 2) {
             Ct p = mul(T[g / 2], T[g / 2]);
-            T[g] = add_const(add_raw(p, p), -1.0);
+            T[g] = dbl_add_const(p, -1.0);
         }
     }
 
@@ -259,12 +272,24 @@ struct ChebEval {
         for (uint32_t j : js) lo = std::min(lo, T[j]->level);
         if (lo == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         const uint32_t top = lo - 1;
-        // every T_j dropped to top + 1 and multiplied by c_j, the sum rescaled once
+        // every T_j dropped to top + 1 and multiplied by c_j, accumulated in one buffer, the sum rescaled once
+        const uint32_t l = top + 1;
         Ct acc;
-        for (uint32_t j : js) {
-            Ct t = const_mul_raw(T[j]->level == top + 1 ? T[j] : drop(T[j], top + 1), cf[j]);
-            acc = acc ? add_raw(acc, t) : t;
+        if (dry) {
+            for (uint32_t j : js) const_mul_raw(T[j], cf[j], l);
+            acc = meta(l, 0.0);
+        } else {
+            hec_ct *o = ct_new(c, l, 1.0);
+            if (!o) PFAIL(HEC_ENOMEM, "ciphertext allocation");
+            acc = wrap(o);
+            bool first = true;
+            for (uint32_t j : js) {
+                const double pscale = S[l - 1] * (double)c->mod[l] / T[j]->scale;
+                PTRY(ct_mac_const(c, acc.get(), T[j].get(), cf[j], pscale, first));
+                first = false;
+            }
         }
+        acc->scale = S[l - 1] * (double)c->mod[l];
         rescale(acc);
         acc->scale = S[top];
         return Val::of(cf[0] != 0.0 ? add_const(acc, cf[0]) : acc);
