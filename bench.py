@@ -68,10 +68,24 @@ def read_traffic(path):
     return rec
 
 
-def kernel_source_sha():
+# source regions whose text decides a kernel's code: the modular helpers and
+# the kernel itself with its launcher (a change elsewhere in the file leaves a
+# recorded PMC measurement valid)
+SOURCE_REGIONS = {
+    "k_ks_mac": ("typedef u64 u64x2 __attribute__((ext_vector_type(2)));", "__global__ void k_moddown_combine("),
+    "k_ntt16_fwd_rows": ("// NTT: merged Cooley-Tukey forward transform", "void hec_ntt_fwd("),
+}
+
+
+def kernel_source_sha(kernel):
     import hashlib
-    src = os.path.join(ROOT, "paper_2306_09189_amd", "csrc", "hec_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    src = open(os.path.join(ROOT, "paper_2306_09189_amd", "csrc", "hec_kernels.hip")).read()
+    h0 = src.index("DEV u64 add_mod(")
+    h1 = src.index("// NTT: merged Cooley-Tukey forward transform")
+    a, b = SOURCE_REGIONS[kernel]
+    i = src.index(a)
+    j = src.index(b, i)
+    return hashlib.sha256((src[h0:h1] + src[i:j]).encode()).hexdigest()[:16]
 
 
 def dominant_roofline(kernel, launches, units, kms):
@@ -83,7 +97,7 @@ def dominant_roofline(kernel, launches, units, kms):
     achieved = avg_units * spec["per_unit"] / avg_s
     traffic = None
     rec = read_traffic(spec["traffic_file"])
-    if rec and rec.get("source_sha") == kernel_source_sha():
+    if rec and rec.get("source_sha") == kernel_source_sha(kernel):
         traffic = (float(rec["fetch_bytes_per_unit"]) + float(rec["write_bytes_per_unit"])) * avg_units
     return {"bound": spec["bound"], "kernel": kernel, "achieved": achieved, "peak": spec["peak"],
             "unit": spec["unit"], "frac": achieved / spec["peak"], "traffic": traffic,
@@ -215,8 +229,13 @@ def main():
         p1 = ctx.conv2d_plan(img, w1, stride=1, pad=1)
         p1.set_mode(args.mode)
         ctx.gen_rotation_keys(p1.steps())
+        dom = DOMINANT[args.mode]
+        ctx.prof_start(dom)
         o1 = p1.run(img)
         ctx.sync()
+        launches, units, kms = ctx.prof_stop()
+        eprint("pmc run: %s launches %d algorithmic units %d (%d bytes each)"
+               % (dom, launches, units, KERNELS[dom]["bytes_per_unit"]))
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
