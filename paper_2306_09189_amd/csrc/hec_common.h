@@ -108,11 +108,12 @@ void hec_sample_uniform(const DevTables &T, u64 *out, u64 seed, u32 purpose, u64
 void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u64 index, int kind,
                       const u64 *gauss_T, hipStream_t st);
 
-// Base conversion of npolys polynomials: polynomial z uses descriptor d_desc[z * desc_stride], reads
-// src + z*src_poly_stride and writes dst + z*dst_poly_stride; nout_max bounds the descriptors' nout.
-// copy_in also copies the input limbs to the same positions of the destination.
-void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int nout_max, const u64 *src, u64 *dst,
-               size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st);
+// Base conversion of npolys polynomials in groups of `group` that share a source: polynomial z uses
+// descriptor d_desc[(z % group) * desc_stride], reads src + (z / group)*src_poly_stride and writes
+// dst + z*dst_poly_stride; nout_max bounds the descriptors' nout.  copy_in also copies the input limbs
+// to the same positions of the destination.
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int group, int nout_max, const u64 *src,
+               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st);
 
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st);

@@ -815,36 +815,44 @@ extern "C" hec_status ckks_ct_import(hec_ctx *c, const uint64_t *coeff, uint32_t
 // ---------------------------------------------------------------------------
 // rotations (hybrid key switching)
 // ---------------------------------------------------------------------------
-// ModUp of c1 (hoisted once for all rotations of a ciphertext): D[j] =
-// ModUp of digit j over Q_l and P, NTT form, [beta][nq+k][n]
-hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **Dout)
+// ModUp of c1 (hoisted once for all rotations of a ciphertext) of cnt
+// ciphertexts at one level: D_i[j] = ModUp of digit j of ct i over Q_l and P,
+// NTT form, at Dall + (i * beta + j) * (nq + k) * n.  One inverse NTT over all
+// inputs, one base-conversion launch for all digits of all inputs (their own
+// limbs copied), one forward NTT over everything: small launches leave most
+// of the GPU idle, so batching ciphertexts pays.
+hec_status ct_modup_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, u64 **Dall)
 {
-    *Dout = nullptr;
-    const size_t n = c->n;
-    const uint32_t lvl = ct->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    *Dall = nullptr;
+    if (cts.empty()) return HEC_OK;
+    const size_t n = c->n, cnt = cts.size();
+    const uint32_t lvl = cts[0]->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    for (auto *ct : cts)
+        if (ct->level != lvl) HEC_FAIL(HEC_ELEVEL, "ModUp of ciphertexts at different levels");
     const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
-    const u64 *c1 = ct->d + nq * n;
-    u64 *cc = c->alloc(nq * n);
-    u64 *D = c->alloc((size_t)beta * nqp * n);
+    u64 *cc = c->alloc(cnt * nq * n);
+    u64 *D = c->alloc(cnt * beta * nqp * n);
     if (!cc || !D) {
         c->release(cc);
         c->release(D);
         HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
     }
-    // c1 to coefficients; every digit converted to Q_l and P in one launch (its
-    // own limbs copied), then one forward NTT over all digits and limbs (the
-    // digit's own limbs come back to c1's values exactly)
-    HEC_TRY_HIP(hipMemcpyAsync(cc, c1, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
-    hec_ntt_inv(c->T, cc, 0, 1, c->idmap(), nq, c->st);
+    // c1 to coefficients; every digit converted to Q_l and P with its own limbs
+    // copied, then one forward NTT (the digit's own limbs come back to c1's values)
+    for (size_t i = 0; i < cnt; i++)
+        HEC_TRY_HIP(hipMemcpyAsync(cc + i * nq * n, cts[i]->d + nq * n, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+    hec_ntt_inv(c->T, cc, nq * n, (int)cnt, c->idmap(), nq, c->st);
     uint32_t nout_max = 0;
     for (uint32_t j = 0; j < beta; j++) nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
-    hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)nout_max, cc, D, 0, (size_t)nqp * n, (int)beta, 1,
-              c->st);
-    hec_ntt_fwd(c->T, D, (size_t)nqp * n, (int)beta, c->qpmap(lvl), (int)nqp, c->st);
+    hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)beta, (int)nout_max, cc, D, nq * n,
+              (size_t)nqp * n, (int)(cnt * beta), 1, c->st);
+    hec_ntt_fwd(c->T, D, (size_t)nqp * n, (int)(cnt * beta), c->qpmap(lvl), (int)nqp, c->st);
     c->release(cc);
-    *Dout = D;
+    *Dall = D;
     return HEC_OK;
 }
+
+hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **Dout) { return ct_modup_many(c, {ct}, Dout); }
 
 const u64 *ones_qp(hec_ctx *c, uint32_t lvl)
 {
@@ -867,27 +875,39 @@ const u64 *ones_qp(hec_ctx *c, uint32_t lvl)
     return d;
 }
 
-// out = ModDown(E) for E = [2][nq+k][n] over Q_l and P (NTT form); E's P limbs are consumed
-hec_status ct_moddown(hec_ctx *c, uint32_t lvl, u64 *E, hec_ct *out)
+// outs[i] = ModDown(E_i) for E_i = [2][nq+k][n] over Q_l and P (NTT form) at
+// Eall + i * 2 (nq+k) n, all at one level; the P limbs of Eall are consumed.
+// One launch per stage for all of them (combine in groups of HEC_KS_BATCH).
+hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vector<hec_ct *> &outs)
 {
-    const size_t n = c->n;
+    if (outs.empty()) return HEC_OK;
+    const size_t n = c->n, cnt = outs.size();
     const uint32_t nq = lvl + 1, k = c->k, nqp = nq + k;
-    if (out->level != lvl) HEC_FAIL(HEC_ELEVEL, "ModDown output at another level");
-    u64 *y = c->alloc(2 * (size_t)nq * n);
+    for (auto *o : outs)
+        if (o->level != lvl) HEC_FAIL(HEC_ELEVEL, "ModDown output at another level");
+    u64 *y = c->alloc(cnt * 2 * (size_t)nq * n);
     if (!y) HEC_FAIL(HEC_ENOMEM, "ModDown buffer");
-    CombineBatch cb{};
-    cb.out[0] = out->d;
-    cb.e[0] = E;
-    cb.y[0] = y;
-    cb.g[0] = 1;
-    hec_ntt_inv(c->T, E + (size_t)nq * n, (size_t)nqp * n, 2, c->qpmap(lvl) + nq, k, c->st);
-    hec_bconv(c->T, c->d_moddown + lvl, 0, nq, E, y, (size_t)nqp * n, (size_t)nq * n, 2, 0, c->st);
-    hec_ntt_fwd(c->T, y, (size_t)nq * n, 2, c->qpmap(lvl), nq, c->st);
-    hec_moddown_combine(c->T, cb, 1, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+    hec_ntt_inv(c->T, Eall + (size_t)nq * n, (size_t)nqp * n, (int)(2 * cnt), c->qpmap(lvl) + nq, k, c->st);
+    hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, Eall, y, (size_t)nqp * n, (size_t)nq * n, (int)(2 * cnt), 0,
+              c->st);
+    hec_ntt_fwd(c->T, y, (size_t)nq * n, (int)(2 * cnt), c->qpmap(lvl), nq, c->st);
+    for (size_t b0 = 0; b0 < cnt; b0 += HEC_KS_BATCH) {
+        const size_t nb = std::min((size_t)HEC_KS_BATCH, cnt - b0);
+        CombineBatch cb{};
+        for (size_t r = 0; r < nb; r++) {
+            cb.out[r] = outs[b0 + r]->d;
+            cb.e[r] = Eall + (b0 + r) * 2 * (size_t)nqp * n;
+            cb.y[r] = y + (b0 + r) * 2 * (size_t)nq * n;
+            cb.g[r] = 1;
+        }
+        hec_moddown_combine(c->T, cb, (int)nb, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+    }
     c->release(y);
     HEC_TRY_HIP(hipGetLastError());
     return HEC_OK;
 }
+
+hec_status ct_moddown(hec_ctx *c, uint32_t lvl, u64 *E, hec_ct *out) { return ct_moddown_many(c, lvl, E, {out}); }
 
 hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt, hec_ct **outs)
 {
@@ -937,7 +957,7 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
         c->ks_count += (uint64_t)R;
         // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine
         hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
-        hec_bconv(c->T, c->d_moddown + lvl, 0, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
+        hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
         hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
         hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
         c->release(e);

@@ -141,8 +141,12 @@ hec_status pt_encode_many(hec_ctx *c, const std::vector<const double *> &z, size
                           std::vector<hec_pt *> &out, bool with_p = false);
 // ModUp of c1 for hoisted key switching: *D = [beta][level+1+k][n] (NTT form), pool memory
 hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **D);
+// the same for several ciphertexts at one level in one set of launches: *Dall = [cnt][beta][level+1+k][n]
+hec_status ct_modup_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, u64 **Dall);
 // out = ModDown(E), E = [2][level+1+k][n] over Q_l and P (NTT form); E's P limbs are overwritten
 hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
+// outs[i] = ModDown(Eall + i * 2 (level+1+k) n) for several outputs (allocated at `level`) in one set of launches
+hec_status ct_moddown_many(hec_ctx *c, uint32_t level, u64 *Eall, const std::vector<hec_ct *> &outs);
 // the plaintext 1 over Q_l and P ([level+1+k][n], Montgomery form), cached per level
 const u64 *ones_qp(hec_ctx *c, uint32_t level);
 // ciphertext product with relinearization (not rescaled), scale a.scale * b.scale

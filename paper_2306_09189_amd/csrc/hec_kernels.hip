@@ -731,20 +731,23 @@ void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u
 #define BC_THREADS 256
 #define BC_OUT 8  // outputs per workgroup (a grid row of workgroups per group of outputs)
 // Workgroup (x, y, z): 256 coefficients, outputs y*BC_OUT .. y*BC_OUT+7 of
-// descriptor dd[z * dstride], source src + z*sps, destination dst + z*dps.
+// descriptor dd[(z % group) * dstride], source src + (z / group)*sps,
+// destination dst + z*dps (groups of `group` polynomials share a source, e.g.
+// the digits of one ModUp).
 // With copy_in, the row y = ngroups copies the input limbs to the same
 // positions of the destination (a ModUp digit then holds all its limbs).
 // The inputs a_i stay in registers (loop bounds fixed at compile time); the
 // descriptor fields are uniform over the workgroup.
-__global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 dstride, const u64 *src, u64 *dst,
-                                                      size_t sps, size_t dps, u32 ngroups, u32 copy_in, DevTables T)
+__global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 dstride, u32 group, const u64 *src,
+                                                      u64 *dst, size_t sps, size_t dps, u32 ngroups, u32 copy_in,
+                                                      DevTables T)
 {
-    const BconvDesc *d = dd + blockIdx.z * dstride;
+    const BconvDesc *d = dd + (blockIdx.z % group) * dstride;
     const size_t n = T.n;
     const u32 t = blockIdx.x * BC_THREADS + threadIdx.x;
     if (t >= n) return;
     const u32 nin = d->nin, nout = d->nout;
-    const u64 *s = src + blockIdx.z * sps;
+    const u64 *s = src + (blockIdx.z / group) * sps;
     u64 *o = dst + blockIdx.z * dps;
     if (blockIdx.y == ngroups) {
         if (copy_in)
@@ -772,13 +775,14 @@ __global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 d
         o[(size_t)d->out_pos[j] * n + t] = redc(acc.hi, acc.lo, pc.q, pc.qinv_neg);
     }
 }
-void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int nout_max, const u64 *src, u64 *dst,
-               size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st)
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int group, int nout_max, const u64 *src,
+               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st)
 {
+    if (npolys <= 0 || group <= 0) return;
     const u32 ngroups = ((u32)nout_max + BC_OUT - 1) / BC_OUT;
     dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, ngroups + (copy_in ? 1 : 0), npolys);
-    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, (u32)desc_stride, src, dst,
-            src_poly_stride, dst_poly_stride, ngroups, (u32)(copy_in ? 1 : 0), T);
+    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, (u32)desc_stride, (u32)group,
+            src, dst, src_poly_stride, dst_poly_stride, ngroups, (u32)(copy_in ? 1 : 0), T);
 }
 
 // ---------------------------------------------------------------------------

@@ -552,28 +552,33 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
     const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
     for (auto *ct : in)
         if (ct->level != lvl) HEC_FAIL(HEC_ELEVEL, "lazy sum over inputs at different levels");
-    std::vector<u64 *> E(nout, nullptr);
+    // inputs with a rotation by a nonzero amount: their ModUps in one batch
+    std::vector<const hec_ct *> mu;
+    std::vector<size_t> mu_of(in.size(), SIZE_MAX);
+    for (size_t u = 0; u < in.size(); u++) {
+        bool rot = false;
+        for (auto &it : terms_of[u]) {
+            const uint32_t g = c->galois(it.amount);
+            if (g != 1 && !c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", it.amount);
+            rot |= g != 1;
+        }
+        if (rot) {
+            mu_of[u] = mu.size();
+            mu.push_back(in[u]);
+        }
+    }
+    // accumulators of all outputs in one buffer, so that their ModDowns batch
+    u64 *Eall = c->alloc(nout * 2 * (size_t)nqp * n);
+    if (!Eall) HEC_FAIL(HEC_ENOMEM, "accumulator allocation");
+    u64 *Dall = nullptr;
+    hec_status s = ct_modup_many(c, mu, &Dall);
     std::vector<char> used(nout, 0), fresh(nout, 1);
-    hec_status s = HEC_OK;
-    for (size_t v = 0; v < nout && s == HEC_OK; v++)
-        if (!(E[v] = c->alloc(2 * (size_t)nqp * n))) s = HEC_ENOMEM, hec_set_error("accumulator allocation");
     double scale = 1.0;
     for (size_t u = 0; u < in.size() && s == HEC_OK; u++) {
         const auto &its = terms_of[u];
         if (its.empty()) continue;
         const hec_ct *ct = in[u];
-        bool rot = false;
-        for (auto &it : its) {
-            const uint32_t g = c->galois(it.amount);
-            if (g != 1 && !c->rotkeys.count(g)) {
-                s = HEC_ENOKEY;
-                hec_set_error("no rotation key for step %d", it.amount);
-            }
-            rot |= g != 1;
-        }
-        if (s != HEC_OK) break;
-        u64 *D = nullptr;
-        if (rot && (s = ct_modup(c, ct, &D)) != HEC_OK) break;
+        const u64 *D = mu_of[u] == SIZE_MAX ? nullptr : Dall + mu_of[u] * beta * (size_t)nqp * n;
         for (size_t v0 = 0; v0 < nout && s == HEC_OK; v0 += HEC_MAC_OUT) {
             const size_t nv = std::min((size_t)HEC_MAC_OUT, nout - v0);
             // the terms of this input with a product for an output of the group
@@ -592,7 +597,7 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                 KsMacBatch b{};
                 int first = 0;
                 for (size_t j = 0; j < nv; j++) {
-                    b.E[j] = E[v0 + j];
+                    b.E[j] = Eall + (v0 + j) * 2 * (size_t)nqp * n;
                     if (fresh[v0 + j]) first |= 1 << j;
                     fresh[v0 + j] = 0;
                 }
@@ -624,7 +629,6 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                 for (size_t t = 0; t < nt; t++) c->ks_count += b.g[t] != 1;
             }
         }
-        c->release(D);
     }
     for (size_t v = 0; v < nout && s == HEC_OK; v++) {
         if (!used[v]) {
@@ -635,11 +639,11 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
         if (!(out[v] = ct_new(c, lvl, scale))) {
             s = HEC_ENOMEM;
             hec_set_error("ciphertext allocation");
-            break;
         }
-        s = ct_moddown(c, lvl, E[v], out[v]);
     }
-    for (auto *e : E) c->release(e);
+    if (s == HEC_OK) s = ct_moddown_many(c, lvl, Eall, out);
+    c->release(Dall);
+    c->release(Eall);
     if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("lazy accumulation launch");
     if (s != HEC_OK) free_all(out);
     return s;
@@ -683,69 +687,76 @@ static hec_status rot_masked_sums(hec_ctx *c, const hec_ct *ct, const std::vecto
 // for ciphertexts at one level and scale, with lazy ModDown: every rotated
 // ciphertext takes its own ModUp, the key-switch products are summed over Q_l
 // and P, and the sum takes one ModDown.
-static hec_status lazy_rotation_sum(hec_ctx *c, const std::vector<std::pair<const hec_ct *, int32_t>> &terms_in,
-                                    hec_ct **out)
+typedef std::vector<std::pair<const hec_ct *, int32_t>> RotSum;
+static hec_status lazy_rotation_sums(hec_ctx *c, const std::vector<RotSum> &sums, std::vector<hec_ct *> &out)
 {
-    *out = nullptr;
-    if (terms_in.empty()) HEC_FAIL(HEC_EINVAL, "empty rotation sum");
+    const size_t nout = sums.size();
+    out.assign(nout, nullptr);
+    if (!nout) return HEC_OK;
+    for (auto &sm : sums)
+        if (sm.empty()) HEC_FAIL(HEC_EINVAL, "empty rotation sum");
     const size_t n = c->n;
-    const uint32_t lvl = terms_in[0].first->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t lvl = sums[0][0].first->level, nq = lvl + 1, nqp = nq + c->k;
     const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
-    const double scale = terms_in[0].first->scale;
-    auto terms = terms_in;
-    for (auto &t : terms) {
-        if (t.first->level != lvl || t.first->scale != scale)
-            HEC_FAIL(HEC_ELEVEL, "rotation sum over different levels or scales");
-        const uint32_t g = c->galois(t.second);
-        if (g != 1 && !c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", t.second);
-    }
-    std::stable_partition(terms.begin(), terms.end(),
-                          [&](const std::pair<const hec_ct *, int32_t> &t) { return c->galois(t.second) == 1; });
-    const u64 *one = ones_qp(c, lvl);
-    u64 *E = c->alloc(2 * (size_t)nqp * n);
-    if (!one || !E) {
-        c->release(E);
-        HEC_FAIL(HEC_ENOMEM, "rotation-sum buffers");
-    }
-    hec_status s = HEC_OK;
-    for (size_t b0 = 0; b0 < terms.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
-        const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
-        KsMacBatch b{};
-        std::vector<u64 *> Ds;
-        b.E[0] = E;
-        for (size_t t = 0; t < nt && s == HEC_OK; t++) {
-            const hec_ct *ct = terms[b0 + t].first;
-            const uint32_t g = c->galois(terms[b0 + t].second);
-            b.g[t] = g;
-            b.ct[t] = ct->d;
-            b.pt[t][0] = one;
-            if (g != 1) {
-                u64 *D = nullptr;
-                s = ct_modup(c, ct, &D);
-                if (s != HEC_OK) break;
-                Ds.push_back(D);
-                b.D[t] = D;
-                b.key[t] = c->rotkeys[g];
+    // the distinct ciphertexts rotated by a nonzero amount: their ModUps in one batch
+    std::vector<const hec_ct *> mu;
+    std::map<const hec_ct *, size_t> mi;
+    for (auto &sm : sums) {
+        const double scale = sm[0].first->scale;
+        for (auto &t : sm) {
+            if (t.first->level != lvl || t.first->scale != scale)
+                HEC_FAIL(HEC_ELEVEL, "rotation sum over different levels or scales");
+            const uint32_t g = c->galois(t.second);
+            if (g == 1) continue;
+            if (!c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", t.second);
+            if (!mi.count(t.first)) {
+                mi[t.first] = mu.size();
+                mu.push_back(t.first);
             }
         }
-        if (s == HEC_OK && !hec_ks_mac(c->T, b, (int)nt, 1, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
-                                       c->d_pmodq_m, (int)c->NLK, b0 == 0 ? 1 : 0, c->st)) {
-            s = HEC_EINVAL;
-            hec_set_error("invalid key-switch batch");
+    }
+    const u64 *one = ones_qp(c, lvl);
+    u64 *Eall = c->alloc(nout * 2 * (size_t)nqp * n);
+    if (!one || !Eall) {
+        c->release(Eall);
+        HEC_FAIL(HEC_ENOMEM, "rotation-sum buffers");
+    }
+    u64 *Dall = nullptr;
+    hec_status s = ct_modup_many(c, mu, &Dall);
+    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
+        RotSum terms = sums[v];
+        std::stable_partition(terms.begin(), terms.end(),
+                              [&](const std::pair<const hec_ct *, int32_t> &t) { return c->galois(t.second) == 1; });
+        for (size_t b0 = 0; b0 < terms.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
+            const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
+            KsMacBatch b{};
+            b.E[0] = Eall + v * 2 * (size_t)nqp * n;
+            for (size_t t = 0; t < nt; t++) {
+                const hec_ct *ct = terms[b0 + t].first;
+                const uint32_t g = c->galois(terms[b0 + t].second);
+                b.g[t] = g;
+                b.ct[t] = ct->d;
+                b.pt[t][0] = one;
+                if (g != 1) {
+                    b.D[t] = Dall + mi[ct] * beta * (size_t)nqp * n;
+                    b.key[t] = c->rotkeys[g];
+                    c->ks_count++;
+                }
+            }
+            if (!hec_ks_mac(c->T, b, (int)nt, 1, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl), c->d_pmodq_m,
+                            (int)c->NLK, b0 == 0 ? 1 : 0, c->st)) {
+                s = HEC_EINVAL;
+                hec_set_error("invalid key-switch batch");
+            }
         }
-        c->ks_count += Ds.size();
-        for (auto *D : Ds) c->release(D);
     }
-    hec_ct *o = nullptr;
-    if (s == HEC_OK && !(o = ct_new(c, lvl, scale))) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
-    if (s == HEC_OK) s = ct_moddown(c, lvl, E, o);
-    c->release(E);
-    if (s != HEC_OK) {
-        ct_free(o);
-        return s;
-    }
-    *out = o;
-    return HEC_OK;
+    for (size_t v = 0; v < nout && s == HEC_OK; v++)
+        if (!(out[v] = ct_new(c, lvl, sums[v][0].first->scale))) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+    if (s == HEC_OK) s = ct_moddown_many(c, lvl, Eall, out);
+    c->release(Dall);
+    c->release(Eall);
+    if (s != HEC_OK) free_all(out);
+    return s;
 }
 
 // Baby / giant split of rotation amounts steps[t] = idx_t * unit: with
@@ -777,14 +788,13 @@ static hec_status bsgs_eval(hec_ctx *c, const std::vector<const hec_ct *> &ins,
     out.assign(nout, nullptr);
     std::vector<hec_ct *> T;
     HEC_CHECK(lazy_rotate_mac(c, ins, babies, gv.size(), T));
+    std::vector<RotSum> sums(nout);
+    for (size_t k = 0; k < gv.size(); k++)
+        if (gv[k].second < nout) sums[gv[k].second].push_back({T[k], gv[k].first});
     hec_status s = HEC_OK;
-    for (size_t v = 0; v < nout && s == HEC_OK; v++) {
-        std::vector<std::pair<const hec_ct *, int32_t>> terms;
-        for (size_t k = 0; k < gv.size(); k++)
-            if (gv[k].second == v) terms.push_back({T[k], gv[k].first});
-        if (terms.empty()) s = HEC_ELAYOUT, hec_set_error("output %zu received no product", v);
-        else s = lazy_rotation_sum(c, terms, &out[v]);
-    }
+    for (size_t v = 0; v < nout && s == HEC_OK; v++)
+        if (sums[v].empty()) s = HEC_ELAYOUT, hec_set_error("output %zu received no product", v);
+    if (s == HEC_OK) s = lazy_rotation_sums(c, sums, out);
     free_all(T);
     if (s != HEC_OK) free_all(out);
     return s;
@@ -1370,17 +1380,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         // baby steps: T_k = sum of pt'' * rot_baby(ct_u) (one ModDown per k);
         // giant steps: output v = sum_k rot_giant(T_k) over the k of v (one more ModDown)
         free_all(acc);
-        acc.assign(nout, nullptr);
-        std::vector<hec_ct *> T;
-        s = lazy_rotate_mac(c, ins, p->bsgs, p->gv.size(), T);
-        for (size_t v = 0; v < nout && s == HEC_OK; v++) {
-            std::vector<std::pair<const hec_ct *, int32_t>> terms;
-            for (size_t k = 0; k < p->gv.size(); k++)
-                if (p->gv[k].second == v) terms.push_back({T[k], p->gv[k].first});
-            if (terms.empty()) s = HEC_ELAYOUT, hec_set_error("output shard %zu received no product", v);
-            else s = lazy_rotation_sum(c, terms, &acc[v]);
-        }
-        free_all(T);
+        s = bsgs_eval(c, ins, p->bsgs, p->gv, nout, acc);
         std::fill(first.begin(), first.end(), 0);
     }
     for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode < 2; u++) {
