@@ -348,3 +348,31 @@ def test_linear_bit_exact(small, shape, pool, O):
     assert (out.export() == ref.data).all()
     got = ctx.decrypt(out)
     assert np.abs(got[:O] - hl.ref_linear(x, Wt, pool)).max() < 1e-5
+
+
+@pytest.mark.parametrize("shape,ops,pad,mode", [
+    ((2, 8, 16), [("conv", (3, 3), 1), ("pool",)], 1, 0),           # non-square image
+    ((2, 16, 8), [("conv", (2, 3), 1), ("pool",)], 1, 3),           # tall image, baby/giant steps
+    ((4, 8, 8), [("conv", (4, 1), 1)], 0, 0),                       # 1x1 kernel (Eq. (2) channel mixing)
+    ((4, 8, 8), [("conv", (4, 1), 1)], 0, 3),
+    ((3, 8, 8), [("conv", (2, 3), 1)], 0, 2),                       # no padding
+    ((1, 2, 2), [("pool",)], 1, 0),                                 # smallest image: pools to one pixel
+    ((1, 2, 2), [("pool",)], 1, 3),
+    ((5, 6, 6), [("conv", (3, 5), 1), ("pool",)], 2, 2),            # 5x5 kernel, pad 2, odd channel count
+])
+def test_layers_edge_shapes_bit_exact(small, shape, ops, pad, mode):
+    """Degenerate and ragged shapes in every evaluation mode: bit for bit with the oracle."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + 7 * mode + pad)
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("edge", shape, [op[0] for op in ops], "pad", pad, "mode", mode)
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=41, mode=mode, pad=pad)
