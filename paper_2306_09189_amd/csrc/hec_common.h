@@ -56,6 +56,7 @@ struct DevTables {
 struct KsBatch {
     const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
     u64 *out[HEC_KS_BATCH];        // [2][nqp][n]
+    const u64 *D[HEC_KS_BATCH];    // this entry's own hoisted digits (null: the launch's shared D)
     u32 g[HEC_KS_BATCH];
 };
 
@@ -146,12 +147,13 @@ struct ScalarArg {
 };
 enum ScalarOp { SC_MUL = 0, SC_ADD, SC_MAC, SC_DBL_ADD };
 // per limb l < nlimbs of npolys polynomials (in read with its own poly stride):
-// SC_MUL out = in * v_l; SC_ADD out = in + v_l on poly 0, in on poly 1;
-// SC_MAC out (+)= in * v_l (first != 0: written); SC_DBL_ADD out = 2 in + v_l on poly 0, 2 in on poly 1
+// SC_MUL out = in * v_l; SC_ADD out = in + v_l on even polys (the c0 of a ciphertext), in on odd ones;
+// SC_MAC out (+)= in * v_l (first != 0: written); SC_DBL_ADD out = 2 in + v_l on even polys, 2 in on odd ones
 void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t out_poly_stride,
                 size_t in_poly_stride, int npolys, int nlimbs, int first, const ScalarArg &sa, hipStream_t st);
-// ciphertext tensor product of a, b ([2][nq][n] each): t = [a0 b0][a1 b1][a0 b1 + a1 b0]
-void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, hipStream_t st);
+// tensor products of cnt ciphertext pairs (a_i, b_i at a + 2i nq n, b + 2i nq n):
+// t_i = [a0 b0][a1 b1][a0 b1 + a1 b0] at t + 3i nq n
+void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, int cnt, hipStream_t st);
 
 // enc: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk in Montgomery form, the rest plain NTT form)
 void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,

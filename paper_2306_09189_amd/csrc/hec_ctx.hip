@@ -463,7 +463,7 @@ static hec_status gen_swk(hec_ctx *c, uint32_t g, const u64 *tgt = nullptr, u64 
 }
 
 // relinearization key (target s^2), generated on first use from the key seed
-static hec_status relin_key(hec_ctx *c, const u64 **key)
+hec_status relin_key(hec_ctx *c, const u64 **key)
 {
     if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "no keys");
     if (!c->rlk) {
@@ -992,26 +992,39 @@ extern "C" hec_status ckks_rotate(hec_ctx *c, const hec_ct *ct, int32_t step, he
 // ---------------------------------------------------------------------------
 // rescale, products, sums
 // ---------------------------------------------------------------------------
-hec_status ct_rescale(hec_ctx *c, hec_ct *ct)
+// npolys polynomials [npolys][l+1][n] at level l divided by q_l: *d replaced
+// by [npolys][l][n] (the old buffer released)
+hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys)
 {
-    if (ct->level == 0) HEC_FAIL(HEC_ELEVEL, "cannot rescale at level 0");
-    const size_t n = c->n;
-    const uint32_t l = ct->level, nq = l + 1;
-    u64 *last = c->alloc(2 * n), *tmp = c->alloc(2 * (size_t)l * n);
-    u64 *o = c->alloc(2 * (size_t)l * n);
-    if (!last || !tmp || !o) HEC_FAIL(HEC_ENOMEM, "rescale buffers");
-    hec_copy_limbs(last, ct->d + (size_t)l * n, n, (size_t)nq * n, 2, n, c->st);
-    hec_ntt_inv(c->T, last, n, 2, c->idmap() + l, 1, c->st);
-    hec_rescale_spread(c->T, last, tmp, n, (size_t)l * n, 2, l, c->st);
-    hec_ntt_fwd(c->T, tmp, (size_t)l * n, 2, c->idmap(), l, c->st);
-    hec_rescale_finish(c->T, o, ct->d, tmp, (size_t)l * n, (size_t)nq * n, (size_t)l * n, 2, l, c->d_lvl + l, c->st);
+    if (l == 0) HEC_FAIL(HEC_ELEVEL, "cannot rescale at level 0");
+    const size_t n = c->n, np = (size_t)npolys;
+    const uint32_t nq = l + 1;
+    u64 *last = c->alloc(np * n), *tmp = c->alloc(np * l * n), *o = c->alloc(np * l * n);
+    if (!last || !tmp || !o) {
+        c->release(last);
+        c->release(tmp);
+        c->release(o);
+        HEC_FAIL(HEC_ENOMEM, "rescale buffers");
+    }
+    hec_copy_limbs(last, *d + (size_t)l * n, n, (size_t)nq * n, npolys, n, c->st);
+    hec_ntt_inv(c->T, last, n, npolys, c->idmap() + l, 1, c->st);
+    hec_rescale_spread(c->T, last, tmp, n, (size_t)l * n, npolys, l, c->st);
+    hec_ntt_fwd(c->T, tmp, (size_t)l * n, npolys, c->idmap(), l, c->st);
+    hec_rescale_finish(c->T, o, *d, tmp, (size_t)l * n, (size_t)nq * n, (size_t)l * n, npolys, l, c->d_lvl + l,
+                       c->st);
     c->release(last);
     c->release(tmp);
-    c->release(ct->d);
-    ct->d = o;
-    ct->scale /= (double)c->mod[l];
-    ct->level = l - 1;
+    c->release(*d);
+    *d = o;
     HEC_TRY_HIP(hipGetLastError());
+    return HEC_OK;
+}
+
+hec_status ct_rescale(hec_ctx *c, hec_ct *ct)
+{
+    HEC_CHECK(rescale_polys(c, &ct->d, ct->level, 2));
+    ct->scale /= (double)c->mod[ct->level];
+    ct->level -= 1;
     return HEC_OK;
 }
 
@@ -1121,7 +1134,7 @@ hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
         ct_free(o);
         HEC_FAIL(HEC_ENOMEM, "ciphertext product buffers");
     }
-    hec_tensor(c->T, t, a->d, b->d, (int)nq, c->st);
+    hec_tensor(c->T, t, a->d, b->d, (int)nq, 1, c->st);
     hec_ct view;
     view.ctx = c;
     view.level = lvl;
@@ -1181,7 +1194,7 @@ hec_status const_coeff(double value, double scale, int64_t *r)
     return HEC_OK;
 }
 
-static void scalar_arg(const hec_ctx *c, int64_t r, uint32_t nlimbs, ScalarArg &sa)
+void scalar_arg(const hec_ctx *c, int64_t r, uint32_t nlimbs, ScalarArg &sa)
 {
     for (uint32_t l = 0; l < nlimbs; l++) {
         const u64 q = c->mod[l];

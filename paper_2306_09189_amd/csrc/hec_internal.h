@@ -131,6 +131,10 @@ hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale);
 hec_ct *ct_clone(const hec_ct *a);
 hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
 hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
+// npolys polynomials [npolys][l+1][n] at level l divided by q_l (*d replaced by [npolys][l][n])
+hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys);
+// the per-limb residues of the integer r (and Shoup companions) for limbs 0..nlimbs-1
+void scalar_arg(const hec_ctx *c, int64_t r, uint32_t nlimbs, ScalarArg &sa);
 hec_status ct_add_inplace(hec_ctx *c, hec_ct *acc, const hec_ct *b);
 // acc (+)= ct * pt ; first == true writes instead of accumulating
 hec_status ct_mac_pt(hec_ctx *c, hec_ct *acc, const hec_ct *ct, const hec_pt *pt, bool first);
@@ -149,6 +153,8 @@ hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
 hec_status ct_moddown_many(hec_ctx *c, uint32_t level, u64 *Eall, const std::vector<hec_ct *> &outs);
 // the plaintext 1 over Q_l and P ([level+1+k][n], Montgomery form), cached per level
 const u64 *ones_qp(hec_ctx *c, uint32_t level);
+// the relinearization key (target s^2), generated from the key seed on first use
+hec_status relin_key(hec_ctx *c, const u64 **key);
 // ciphertext product with relinearization (not rescaled), scale a.scale * b.scale
 hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
 // the constant polynomial round_half_away(value * scale) (exact product), |r| < 2^62

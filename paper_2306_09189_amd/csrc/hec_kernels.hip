@@ -807,9 +807,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *
     const u32 src = auto_src(k, kb.g[r], T.logn);
     const size_t n = T.n;
     const u64 *key = kb.key[r];
+    const u64 *Dr = kb.D[r] ? kb.D[r] : D;
     acc128 a0 = {0, 0}, a1 = {0, 0};
     for (u32 j = 0; j < beta; j++) {
-        u64 d = D[((size_t)j * nqp + o) * n + src];
+        u64 d = Dr[((size_t)j * nqp + o) * n + src];
         mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
         mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
     }
@@ -1291,9 +1292,9 @@ void hec_crt_double(const DevTables &T, const u64 *res, double *out, int nq, con
 // op (poly p of out; in read with its own poly stride, so that a ciphertext
 // at a higher level can be read as if dropped):
 //   SC_MUL  out = in * v_l
-//   SC_ADD  out = in + v_l on poly 0, in on poly 1
+//   SC_ADD  out = in + v_l on even polys (c0 of each ciphertext), in on odd ones
 //   SC_MAC  out (+)= in * v_l (first: written)
-//   SC_DBL_ADD out = 2 in + v_l on poly 0, 2 in on poly 1
+//   SC_DBL_ADD out = 2 in + v_l on even polys, 2 in on odd ones
 __global__ void k_scalar(int op, u64 *out, const u64 *in, size_t pso, size_t psi, int first, ScalarArg sa,
                          DevTables T)
 {
@@ -1306,7 +1307,7 @@ __global__ void k_scalar(int op, u64 *out, const u64 *in, size_t pso, size_t psi
     u64 *o = out + p * pso + lo;
     switch (op) {
     case SC_MUL: *o = shoup_mul(x, sa.v[l], sa.vsh[l], q); break;
-    case SC_ADD: *o = p == 0 ? add_mod(x, sa.v[l], q) : x; break;
+    case SC_ADD: *o = (p & 1) == 0 ? add_mod(x, sa.v[l], q) : x; break;
     case SC_MAC: {
         const u64 y = shoup_mul(x, sa.v[l], sa.vsh[l], q);
         *o = first ? y : add_mod(*o, y, q);
@@ -1314,7 +1315,7 @@ __global__ void k_scalar(int op, u64 *out, const u64 *in, size_t pso, size_t psi
     }
     case SC_DBL_ADD: {
         const u64 d = add_mod(x, x, q);
-        *o = p == 0 ? add_mod(d, sa.v[l], q) : d;
+        *o = (p & 1) == 0 ? add_mod(d, sa.v[l], q) : d;
         break;
     }
     }
@@ -1328,23 +1329,28 @@ void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t
             out_poly_stride, in_poly_stride, first, sa, T);
 }
 
-// ciphertext tensor product in one pass: t = [a0 b0][a1 b1][a0 b1 + a1 b0]
-// (all plain evaluation form; b taken into Montgomery form in registers)
+// ciphertext tensor products in one pass: t_z = [a0 b0][a1 b1][a0 b1 + a1 b0]
+// for pair z = blockIdx.z (all plain evaluation form; b taken into Montgomery
+// form in registers)
 __global__ void __launch_bounds__(EW_THREADS) k_tensor(u64 *t, const u64 *a, const u64 *b, size_t P, DevTables T)
 {
-    const u32 l = blockIdx.y;
+    const u32 l = blockIdx.y, z = blockIdx.z;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (k >= T.n) return;
     const PrimeC pc = T.pc[l];
     const size_t off = (size_t)l * T.n + k;
+    a += 2 * z * P;
+    b += 2 * z * P;
+    t += 3 * z * P;
     const u64 a0 = a[off], a1 = a[P + off];
     const u64 b0 = mont_mul(b[off], pc.r2, pc.q, pc.qinv_neg), b1 = mont_mul(b[P + off], pc.r2, pc.q, pc.qinv_neg);
     t[off] = mont_mul(a0, b0, pc.q, pc.qinv_neg);
     t[P + off] = mont_mul(a1, b1, pc.q, pc.qinv_neg);
     t[2 * P + off] = add_mod(mont_mul(a0, b1, pc.q, pc.qinv_neg), mont_mul(a1, b0, pc.q, pc.qinv_neg), pc.q);
 }
-void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, hipStream_t st)
+void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, int cnt, hipStream_t st)
 {
-    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
-    KLAUNCH("k_tensor", (uint64_t)nq, k_tensor, g, dim3(EW_THREADS), 0, st, t, a, b, (size_t)nq * T.n, T);
+    if (cnt <= 0) return;
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, cnt);
+    KLAUNCH("k_tensor", (uint64_t)nq * cnt, k_tensor, g, dim3(EW_THREADS), 0, st, t, a, b, (size_t)nq * T.n, T);
 }

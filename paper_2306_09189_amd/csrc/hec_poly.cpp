@@ -1,7 +1,10 @@
 // hec_poly.cpp -- polynomial evaluation on ciphertexts in the Chebyshev basis
-// (the activation of the encrypted network, Sec. II-C: a polynomial
-// approximation over a fixed interval evaluated with ciphertext products),
-// with baby-step/giant-step splitting of the polynomial.
+// (the GELU activation of the encrypted network, Section 4.3 and the Appendix
+// on polynomial approximation), with baby-step/giant-step splitting of the
+// polynomial.  The S shards of an image go through the evaluation together:
+// every operation is one set of launches over all of them (they share levels,
+// scales and coefficients), so the small per-ciphertext launches of a long
+// dependency chain become S times larger.
 //
 // Map: y = (2x - a - b)/(b - a) costs one constant product, except on
 // [a, b] = [-1, 1], where y = x (an affine map in front of the activation
@@ -20,9 +23,9 @@
 // k < m (m the smallest power of two with m^2 >= deg + 1) and the giant
 // powers T_{2m}, T_{4m}, ... by doubling.  A polynomial of degree < m is c_0
 // plus the constant products c_j T_j, every T_j dropped to one level and the
-// sum rescaled once; a larger one is divided by the
-// largest giant power T_g <= its degree (T_j = 2 T_g T_{j-g} - T_{2g-j}),
-// p = q T_g + r, and q, r are evaluated the same way.
+// sum rescaled once; a larger one is divided by the largest giant power
+// T_g <= its degree (T_j = 2 T_g T_{j-g} - T_{2g-j}), p = q T_g + r, and q, r
+// are evaluated the same way.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -47,10 +50,21 @@ struct Fail {
         throw Fail{code};                                                                                          \
     } while (0)
 
-using Ct = std::shared_ptr<hec_ct>;
-Ct wrap(hec_ct *p) { return Ct(p, ct_free); }
+// S ciphertexts at one level and nominal scale, contiguous: d = [S][2][level+1][n]
+// (no device data in a dry run)
+struct Batch {
+    hec_ctx *c = nullptr;
+    uint32_t level = 0;
+    double scale = 1.0;
+    u64 *d = nullptr;
+    ~Batch()
+    {
+        if (c && d) c->release(d);
+    }
+};
+using Ct = std::shared_ptr<Batch>;
 
-// a ciphertext or a plain constant (sums of constants stay on the host)
+// a ciphertext batch or a plain constant (sums of constants stay on the host)
 struct Val {
     bool is_const = false;
     double c = 0.0;
@@ -70,41 +84,55 @@ struct Val {
     }
 };
 
-// dry: levels and scales only (ciphertexts without device data), to learn the
-// output level and check the level budget and constants before any launch
+// dry: levels and scales only, to learn the output level and check the level
+// budget and constants before any launch
 struct ChebEval {
     hec_ctx *c;
     Ct x;
+    uint32_t S;
     double a, b;
     bool dry;
-    std::vector<double> S;  // nominal scale per level
+    size_t n;
+    std::vector<double> S_;  // nominal scale per level
 
-    ChebEval(hec_ctx *ctx, Ct in, double lo, double hi, bool dry_run = false)
-        : c(ctx), x(std::move(in)), a(lo), b(hi), dry(dry_run)
+    ChebEval(hec_ctx *ctx, Ct in, uint32_t count, double lo, double hi, bool dry_run)
+        : c(ctx), x(std::move(in)), S(count), a(lo), b(hi), dry(dry_run), n(ctx->n)
     {
-        S.assign(x->level + 1, 0.0);
-        S[x->level] = x->scale;
-        for (uint32_t l = x->level; l > 0; l--) S[l - 1] = (S[l] * S[l]) / (double)c->mod[l];
+        S_.assign(x->level + 1, 0.0);
+        S_[x->level] = x->scale;
+        for (uint32_t l = x->level; l > 0; l--) S_[l - 1] = (S_[l] * S_[l]) / (double)c->mod[l];
     }
 
-    Ct meta(uint32_t level, double scale)
+    size_t P(uint32_t level) const { return (size_t)(level + 1) * n; }  // one polynomial
+
+    Ct make(uint32_t level, double scale)
     {
-        hec_ct *o = new hec_ct();
-        o->ctx = c;
-        o->level = level;
-        o->scale = scale;
-        return wrap(o);
+        Ct r = std::make_shared<Batch>();
+        r->c = c;
+        r->level = level;
+        r->scale = scale;
+        if (!dry) {
+            r->d = c->alloc((size_t)S * 2 * P(level));
+            if (!r->d) PFAIL(HEC_ENOMEM, "ciphertext allocation");
+        }
+        return r;
     }
 
     void rescale(const Ct &ct)
     {
-        if (!dry) {
-            PTRY(ct_rescale(c, ct.get()));
-            return;
-        }
         if (ct->level == 0) PFAIL(HEC_ELEVEL, "cannot rescale at level 0");
+        if (!dry) PTRY(rescale_polys(c, &ct->d, ct->level, (int)(2 * S)));
         ct->scale /= (double)c->mod[ct->level];
         ct->level -= 1;
+    }
+
+    ScalarArg scalar(double value, double scale, uint32_t nlimbs)
+    {
+        int64_t m;
+        PTRY(const_coeff(value, scale, &m));
+        ScalarArg sa;
+        if (!dry) scalar_arg(c, m, nlimbs, sa);
+        return sa;
     }
 
     // ct dropped to level l (l <= ct's level) times value at S[l-1] q_l / ct.scale, not rescaled; nominal
@@ -113,18 +141,11 @@ struct ChebEval {
     {
         if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         if (l > ct->level) PFAIL(HEC_ELEVEL, "cannot raise a level");
-        const double pscale = S[l - 1] * (double)c->mod[l] / ct->scale;
-        Ct r;
-        if (dry) {
-            int64_t m;
-            PTRY(const_coeff(value, pscale, &m));
-            r = meta(l, 0.0);
-        } else {
-            hec_ct *o = nullptr;
-            PTRY(ct_mul_const_at(c, ct.get(), l, value, pscale, &o));
-            r = wrap(o);
-        }
-        r->scale = S[l - 1] * (double)c->mod[l];
+        const double pscale = S_[l - 1] * (double)c->mod[l] / ct->scale;
+        const ScalarArg sa = scalar(value, pscale, l + 1);
+        Ct r = make(l, S_[l - 1] * (double)c->mod[l]);
+        if (!dry)
+            hec_scalar(c->T, SC_MUL, r->d, ct->d, P(l), P(ct->level), (int)(2 * S), (int)l + 1, 0, sa, c->st);
         return r;
     }
 
@@ -134,22 +155,82 @@ struct ChebEval {
         if (l == UINT32_MAX) l = ct->level;
         Ct r = const_mul_raw(ct, value, l);
         rescale(r);
-        r->scale = S[l - 1];
+        r->scale = S_[l - 1];
         return r;
     }
 
-    // ct brought down to `level`: limbs dropped to level + 1, times 1 (cached per ciphertext and level; the
-    // cache keeps the source alive, so its address is not reused)
-    std::map<std::pair<const hec_ct *, uint32_t>, std::pair<Ct, Ct>> adj;
+    // ct brought down to `level`: limbs dropped to level + 1, times 1 (cached per batch and level; the cache
+    // keeps the source alive, so its address is not reused)
+    std::map<std::pair<const Batch *, uint32_t>, std::pair<Ct, Ct>> adj;
     Ct adjust(const Ct &ct, uint32_t level)
     {
         if (ct->level == level) return ct;
         if (ct->level < level) PFAIL(HEC_ELEVEL, "cannot raise a level");
-        auto key = std::make_pair((const hec_ct *)ct.get(), level);
+        auto key = std::make_pair((const Batch *)ct.get(), level);
         auto it = adj.find(key);
         if (it != adj.end()) return it->second.second;
         Ct r = const_mul(ct, 1.0, level + 1);
         adj[key] = std::make_pair(ct, r);
+        return r;
+    }
+
+    // relinearized products of the S pairs: tensor product, ModUp of the s^2
+    // parts, key switch with the relinearization key, ModDown, added to (d0, d1)
+    Ct product(const Ct &u, const Ct &v)
+    {
+        const uint32_t l = u->level, nq = l + 1, nqp = nq + c->k;
+        const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+        Ct r = make(l, u->scale * v->scale);
+        if (dry) return r;
+        const u64 *rlk = nullptr;
+        PTRY(relin_key(c, &rlk));
+        const size_t p = P(l);
+        // t_i = [d0][d2][d1]: a ciphertext view (d0, d2) whose second polynomial is the one ModUp reads
+        u64 *t = c->alloc((size_t)S * 3 * p), *E = c->alloc((size_t)S * 2 * nqp * n);
+        if (!t || !E) {
+            c->release(t);
+            c->release(E);
+            PFAIL(HEC_ENOMEM, "ciphertext product buffers");
+        }
+        hec_tensor(c->T, t, u->d, v->d, (int)nq, (int)S, c->st);
+        std::vector<hec_ct> tv(S), ov(S);
+        std::vector<const hec_ct *> tp(S);
+        std::vector<hec_ct *> op(S);
+        for (uint32_t i = 0; i < S; i++) {
+            tv[i].ctx = ov[i].ctx = c;
+            tv[i].level = ov[i].level = l;
+            tv[i].d = t + (size_t)i * 3 * p;
+            ov[i].d = r->d + (size_t)i * 2 * p;
+            tp[i] = &tv[i];
+            op[i] = &ov[i];
+        }
+        u64 *D = nullptr;
+        hec_status s = ct_modup_many(c, tp, &D);
+        for (uint32_t b0 = 0; b0 < S && s == HEC_OK; b0 += HEC_KS_BATCH) {
+            const uint32_t R = std::min((uint32_t)HEC_KS_BATCH, S - b0);
+            KsBatch kb{};
+            for (uint32_t q = 0; q < R; q++) {
+                kb.key[q] = rlk;
+                kb.out[q] = E + (size_t)(b0 + q) * 2 * nqp * n;
+                kb.D[q] = D + (size_t)(b0 + q) * beta * nqp * n;
+                kb.g[q] = 1;
+            }
+            hec_ks_inner(c->T, kb, (int)R, nullptr, (int)beta, (int)nqp, c->qpmap(l), (int)c->NLK, c->st);
+        }
+        c->ks_count += S;
+        if (s == HEC_OK) s = ct_moddown_many(c, l, E, op);
+        if (s == HEC_OK) {
+            // (d0, d1) of pair i at t_i and t_i + 2p
+            hec_ew(c->T, EW_ADD, r->d, r->d, t, 2 * p, 2 * p, 3 * p, (int)S, c->idmap(), (int)nq, c->st);
+            hec_ew(c->T, EW_ADD, r->d + p, r->d + p, t + 2 * p, 2 * p, 2 * p, 3 * p, (int)S, c->idmap(), (int)nq,
+                   c->st);
+        }
+        for (auto &h : tv) h.d = nullptr;
+        for (auto &h : ov) h.d = nullptr;
+        c->release(D);
+        c->release(t);
+        c->release(E);
+        PTRY(s);
         return r;
     }
 
@@ -158,80 +239,40 @@ struct ChebEval {
         const uint32_t l = std::min(u0->level, v0->level);
         if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         Ct u = adjust(u0, l), v = adjust(v0, l);
-        Ct r;
-        if (dry) {
-            r = meta(l, u->scale * v->scale);
-        } else {
-            hec_ct *o = nullptr;
-            PTRY(ct_mul(c, u.get(), v.get(), &o));
-            r = wrap(o);
-        }
+        Ct r = product(u, v);
         rescale(r);
-        if (r->scale != S[l - 1]) PFAIL(HEC_ESCALE, "product scale off the scale table");
+        if (r->scale != S_[l - 1]) PFAIL(HEC_ESCALE, "product scale off the scale table");
         return r;
     }
 
-    Ct add_raw(const Ct &u, const Ct &v)
+    Ct ew(EwOp op, const Ct &u, const Ct &v)
     {
-        if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch in addition");
-        if (dry) return meta(u->level, u->scale);
-        hec_ct *o = nullptr;
-        PTRY(ct_add(c, u.get(), v.get(), &o));
-        return wrap(o);
+        if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch");
+        Ct r = make(u->level, u->scale);
+        if (!dry) {
+            const size_t p = P(u->level);
+            hec_ew(c->T, op, r->d, u->d, v->d, p, p, p, (int)(2 * S), c->idmap(), (int)u->level + 1, c->st);
+        }
+        return r;
     }
 
     Ct add(const Ct &u, const Ct &v)
     {
         const uint32_t l = std::min(u->level, v->level);
-        return add_raw(adjust(u, l), adjust(v, l));
+        return ew(EW_ADD, adjust(u, l), adjust(v, l));
     }
 
-    Ct add_const(const Ct &u, double v)
+    // u + v, or 2u + v with dbl (v encoded at u's scale)
+    Ct add_const(const Ct &u, double v, bool dbl = false)
     {
-        if (dry) {
-            int64_t m;
-            PTRY(const_coeff(v, u->scale, &m));
-            return meta(u->level, u->scale);
+        const ScalarArg sa = scalar(v, u->scale, u->level + 1);
+        Ct r = make(u->level, u->scale);
+        if (!dry) {
+            const size_t p = P(u->level);
+            hec_scalar(c->T, dbl ? SC_DBL_ADD : SC_ADD, r->d, u->d, p, p, (int)(2 * S), (int)u->level + 1, 0, sa,
+                       c->st);
         }
-        hec_ct *o = nullptr;
-        PTRY(ct_add_const(c, u.get(), v, u->scale, &o));
-        return wrap(o);
-    }
-
-    // 2u + v (v at u's scale)
-    Ct dbl_add_const(const Ct &u, double v)
-    {
-        if (dry) {
-            int64_t m;
-            PTRY(const_coeff(v, u->scale, &m));
-            return meta(u->level, u->scale);
-        }
-        hec_ct *o = nullptr;
-        PTRY(ct_dbl_add_const(c, u.get(), v, &o));
-        return wrap(o);
-    }
-
-    // 2u - v
-    Ct dbl_sub(const Ct &u, const Ct &v)
-    {
-        if (dry) {
-            if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch");
-            return meta(u->level, u->scale);
-        }
-        hec_ct *o = nullptr;
-        PTRY(ct_dbl_sub(c, u.get(), v.get(), &o));
-        return wrap(o);
-    }
-
-    Ct sub(const Ct &u, const Ct &v)
-    {
-        if (dry) {
-            if (u->level != v->level || u->scale != v->scale) PFAIL(HEC_ESCALE, "level/scale mismatch");
-            return meta(u->level, u->scale);
-        }
-        hec_ct *o = nullptr;
-        PTRY(ct_sub(c, u.get(), v.get(), &o));
-        return wrap(o);
+        return r;
     }
 
     // y = alpha x + beta maps [a, b] onto [-1, 1]; on [-1, 1] itself y = x (no level spent)
@@ -249,16 +290,16 @@ struct ChebEval {
         for (uint32_t k = 2; k < std::min(m, d + 1); k++) {
             if (k % 2 == 0) {
                 Ct p = mul(T[k / 2], T[k / 2]);
-                T[k] = dbl_add_const(p, -1.0);
+                T[k] = add_const(p, -1.0, true);  // 2 T_{k/2}^2 - 1
             } else {
                 const uint32_t h = k / 2;
                 Ct p = mul(T[h + 1], T[h]);
-                T[k] = dbl_sub(p, adjust(T[1], p->level));
+                T[k] = ew(EW_DBL_SUB, p, adjust(T[1], p->level));  // 2 T_{h+1} T_h - T_1
             }
         }
         for (uint32_t g = m; g <= d; g *= 2) {
             Ct p = mul(T[g / 2], T[g / 2]);
-            T[g] = dbl_add_const(p, -1.0);
+            T[g] = add_const(p, -1.0, true);
         }
     }
 
@@ -271,27 +312,20 @@ struct ChebEval {
         uint32_t lo = UINT32_MAX;
         for (uint32_t j : js) lo = std::min(lo, T[j]->level);
         if (lo == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
-        const uint32_t top = lo - 1;
+        const uint32_t top = lo - 1, l = top + 1;
         // every T_j dropped to top + 1 and multiplied by c_j, accumulated in one buffer, the sum rescaled once
-        const uint32_t l = top + 1;
-        Ct acc;
-        if (dry) {
-            for (uint32_t j : js) const_mul_raw(T[j], cf[j], l);
-            acc = meta(l, 0.0);
-        } else {
-            hec_ct *o = ct_new(c, l, 1.0);
-            if (!o) PFAIL(HEC_ENOMEM, "ciphertext allocation");
-            acc = wrap(o);
-            bool first = true;
-            for (uint32_t j : js) {
-                const double pscale = S[l - 1] * (double)c->mod[l] / T[j]->scale;
-                PTRY(ct_mac_const(c, acc.get(), T[j].get(), cf[j], pscale, first));
-                first = false;
-            }
+        Ct acc = make(l, S_[l - 1] * (double)c->mod[l]);
+        bool first = true;
+        for (uint32_t j : js) {
+            const double pscale = S_[l - 1] * (double)c->mod[l] / T[j]->scale;
+            const ScalarArg sa = scalar(cf[j], pscale, l + 1);
+            if (!dry)
+                hec_scalar(c->T, SC_MAC, acc->d, T[j]->d, P(l), P(T[j]->level), (int)(2 * S), (int)l + 1,
+                           first ? 1 : 0, sa, c->st);
+            first = false;
         }
-        acc->scale = S[l - 1] * (double)c->mod[l];
         rescale(acc);
-        acc->scale = S[top];
+        acc->scale = S_[top];
         return Val::of(cf[0] != 0.0 ? add_const(acc, cf[0]) : acc);
     }
 
@@ -362,27 +396,18 @@ hec_status check_args(hec_ctx *c, const double *coeffs, size_t n, double a, doub
     return HEC_OK;
 }
 
-// the evaluation of one ciphertext (x borrowed), or with dry its level and scale only
-hec_status cheb_one(hec_ctx *c, const hec_ct *x, const std::vector<double> &cf, double a, double b, bool dry,
-                    hec_ct **out)
+// levels and scales only: output level and scale of an input (level, scale)
+hec_status cheb_dry(hec_ctx *c, uint32_t level, double scale, const std::vector<double> &cf, double a, double b,
+                    uint32_t *out_level, double *out_scale)
 {
     try {
-        hec_ct *xc = nullptr;
-        if (dry) {
-            xc = new hec_ct();
-            xc->ctx = c;
-            xc->level = x->level;
-            xc->scale = x->scale;
-        } else {
-            xc = ct_clone(x);
-            if (!xc) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-        }
-        ChebEval ev(c, wrap(xc), a, b, dry);
+        Ct x = std::make_shared<Batch>();
+        x->level = level;
+        x->scale = scale;
+        ChebEval ev(c, x, 1, a, b, true);
         Ct r = ev.run(cf);
-        // move the result's storage into a handle of its own
-        hec_ct *o = new hec_ct(*r);
-        r->d = nullptr;
-        *out = o;
+        *out_level = r->level;
+        if (out_scale) *out_scale = r->scale;
         return HEC_OK;
     } catch (const Fail &f) {
         return f.s;
@@ -397,43 +422,61 @@ hec_status cheb_levels(hec_ctx *c, uint32_t level, double scale, const double *c
                        uint32_t *out_level, double *out_scale)
 {
     HEC_CHECK(check_args(c, coeffs, n, a, b));
-    hec_ct x;
-    x.ctx = c;
-    x.level = level;
-    x.scale = scale;
-    hec_ct *r = nullptr;
-    HEC_CHECK(cheb_one(c, &x, std::vector<double>(coeffs, coeffs + n), a, b, true, &r));
-    *out_level = r->level;
-    if (out_scale) *out_scale = r->scale;
-    delete r;
-    return HEC_OK;
+    return cheb_dry(c, level, scale, std::vector<double>(coeffs, coeffs + n), a, b, out_level, out_scale);
 }
 
 hec_status cheb_image(hec_ctx *c, const std::vector<hec_ct *> &in, const double *coeffs, size_t n, double a, double b,
                       std::vector<hec_ct *> &out)
 {
-    HEC_CHECK(check_args(c, coeffs, n, a, b));
-    std::vector<double> cf(coeffs, coeffs + n);
     out.clear();
-    for (const hec_ct *x : in) {
-        hec_ct *o = nullptr;
-        hec_status s = cheb_one(c, x, cf, a, b, true, &o);  // levels and constants first
-        delete o;
-        o = nullptr;
-        if (s == HEC_OK) s = cheb_one(c, x, cf, a, b, false, &o);
-        if (s != HEC_OK) {
-            for (auto *p : out) ct_free(p);
-            out.clear();
-            return s;
+    HEC_CHECK(check_args(c, coeffs, n, a, b));
+    if (in.empty()) HEC_FAIL(HEC_ELAYOUT, "nothing to evaluate");
+    const uint32_t lvl = in[0]->level;
+    const double scale = in[0]->scale;
+    for (auto *x : in)
+        if (x->level != lvl || x->scale != scale) HEC_FAIL(HEC_ELEVEL, "ciphertexts at different levels or scales");
+    std::vector<double> cf(coeffs, coeffs + n);
+    uint32_t olvl = 0;
+    HEC_CHECK(cheb_dry(c, lvl, scale, cf, a, b, &olvl, nullptr));  // levels and constants before any launch
+    const uint32_t S = (uint32_t)in.size();
+    const size_t pc = (size_t)2 * (lvl + 1) * c->n;
+    hec_status s = HEC_OK;
+    try {
+        // the shards side by side, evaluated together, then handed out one by one
+        Ct x = std::make_shared<Batch>();
+        x->c = c;
+        x->level = lvl;
+        x->scale = scale;
+        x->d = c->alloc((size_t)S * pc);
+        if (!x->d) PFAIL(HEC_ENOMEM, "ciphertext allocation");
+        for (uint32_t i = 0; i < S; i++)
+            if (hipMemcpyAsync(x->d + i * pc, in[i]->d, pc * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+                PFAIL(HEC_EDEVICE, "shard copy");
+        ChebEval ev(c, x, S, a, b, false);
+        Ct r = ev.run(cf);
+        const size_t po = (size_t)2 * (r->level + 1) * c->n;
+        for (uint32_t i = 0; i < S; i++) {
+            hec_ct *o = ct_new(c, r->level, r->scale);
+            if (!o) PFAIL(HEC_ENOMEM, "ciphertext allocation");
+            out.push_back(o);
+            if (hipMemcpyAsync(o->d, r->d + i * po, po * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+                PFAIL(HEC_EDEVICE, "result copy");
         }
-        out.push_back(o);
+    } catch (const Fail &f) {
+        s = f.s;
+    } catch (const std::bad_alloc &) {
+        s = HEC_ENOMEM;
+        hec_set_error("host allocation");
     }
-    if (hipGetLastError() != hipSuccess) {
+    if (s == HEC_OK && hipGetLastError() != hipSuccess) {
+        s = HEC_EDEVICE;
+        hec_set_error("kernel launch failed");
+    }
+    if (s != HEC_OK) {
         for (auto *p : out) ct_free(p);
         out.clear();
-        HEC_FAIL(HEC_EDEVICE, "kernel launch failed");
     }
-    return HEC_OK;
+    return s;
 }
 
 extern "C" hec_status he_cheb_eval(hec_ctx *c, const hec_ct *x, const double *coeffs, size_t ncoeffs, double a,
