@@ -234,15 +234,85 @@ struct ChebEval {
         return r;
     }
 
-    Ct mul(const Ct &u0, const Ct &v0)
+    Ct mul(const Ct &u0, const Ct &v0) { return muls({{u0, v0}})[0]; }
+
+    // several independent rescaled products, each at the lower level of its
+    // operands; those at one level go as one batch: the operands are gathered
+    // side by side, multiplied, rescaled and split again
+    std::vector<Ct> muls(const std::vector<std::pair<Ct, Ct>> &pairs)
     {
-        const uint32_t l = std::min(u0->level, v0->level);
-        if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
-        Ct u = adjust(u0, l), v = adjust(v0, l);
-        Ct r = product(u, v);
-        rescale(r);
-        if (r->scale != S_[l - 1]) PFAIL(HEC_ESCALE, "product scale off the scale table");
-        return r;
+        std::vector<Ct> out(pairs.size());
+        std::map<uint32_t, std::vector<size_t>> by_level;
+        for (size_t i = 0; i < pairs.size(); i++)
+            by_level[std::min(pairs[i].first->level, pairs[i].second->level)].push_back(i);
+        for (auto &kv : by_level) {
+            const uint32_t l = kv.first;
+            const std::vector<size_t> &idx = kv.second;
+            const size_t K = idx.size();
+            if (l == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
+            std::vector<Ct> us, vs;
+            for (size_t i : idx) {
+                us.push_back(adjust(pairs[i].first, l));
+                vs.push_back(adjust(pairs[i].second, l));
+            }
+            Ct r;
+            if (K == 1) {
+                r = product(us[0], vs[0]);
+                rescale(r);
+            } else {
+                Ct U = gather(us), V = gather(vs);
+                const uint32_t S0 = S;
+                S = S0 * (uint32_t)K;
+                try {
+                    r = product(U, V);
+                    rescale(r);
+                } catch (...) {
+                    S = S0;
+                    throw;
+                }
+                S = S0;
+            }
+            if (r->scale != S_[l - 1]) PFAIL(HEC_ESCALE, "product scale off the scale table");
+            std::vector<Ct> parts = K == 1 ? std::vector<Ct>{r} : split(r, K);
+            for (size_t j = 0; j < K; j++) out[idx[j]] = parts[j];
+        }
+        return out;
+    }
+
+    // K batches at one level and scale side by side (and back)
+    Ct gather(const std::vector<Ct> &xs)
+    {
+        const uint32_t S0 = S;
+        S = S0 * (uint32_t)xs.size();
+        Ct g;
+        try {
+            g = make(xs[0]->level, xs[0]->scale);
+        } catch (...) {
+            S = S0;
+            throw;
+        }
+        S = S0;
+        if (!dry) {
+            const size_t bytes = (size_t)S * 2 * P(xs[0]->level) * 8;
+            for (size_t i = 0; i < xs.size(); i++)
+                if (hipMemcpyAsync((char *)g->d + i * bytes, xs[i]->d, bytes, hipMemcpyDeviceToDevice, c->st) !=
+                    hipSuccess)
+                    PFAIL(HEC_EDEVICE, "gather copy");
+        }
+        return g;
+    }
+    std::vector<Ct> split(const Ct &g, size_t K)
+    {
+        std::vector<Ct> out;
+        const size_t bytes = (size_t)S * 2 * P(g->level) * 8;
+        for (size_t i = 0; i < K; i++) {
+            Ct r = make(g->level, g->scale);
+            if (!dry && hipMemcpyAsync(r->d, (const char *)g->d + i * bytes, bytes, hipMemcpyDeviceToDevice, c->st) !=
+                            hipSuccess)
+                PFAIL(HEC_EDEVICE, "split copy");
+            out.push_back(r);
+        }
+        return out;
     }
 
     Ct ew(EwOp op, const Ct &u, const Ct &v)
@@ -284,22 +354,36 @@ struct ChebEval {
         return add_const(const_mul(x, alpha), beta);
     }
 
+    // T_k for 2 <= k < min(m, d + 1) and the giant powers T_m, T_2m, ... <= d.  The
+    // products of one doubling round (T_k for 2^i < k <= 2^(i+1), all from
+    // T_1..T_(2^i)) are independent and taken as one batch; the giant powers
+    // of the same round join it.
     void basis(const Ct &y, uint32_t m, uint32_t d, std::map<uint32_t, Ct> &T)
     {
         T[1] = y;
-        for (uint32_t k = 2; k < std::min(m, d + 1); k++) {
-            if (k % 2 == 0) {
-                Ct p = mul(T[k / 2], T[k / 2]);
-                T[k] = add_const(p, -1.0, true);  // 2 T_{k/2}^2 - 1
-            } else {
-                const uint32_t h = k / 2;
-                Ct p = mul(T[h + 1], T[h]);
-                T[k] = ew(EW_DBL_SUB, p, adjust(T[1], p->level));  // 2 T_{h+1} T_h - T_1
+        const uint32_t top = std::min(m, d + 1);  // babies are T_k, k < top
+        for (uint32_t lo = 1; lo < std::max(top - 1, m); lo *= 2) {
+            std::vector<uint32_t> ks;
+            for (uint32_t k = lo + 1; k <= 2 * lo; k++)
+                if (k < top || (k == m && m <= d)) ks.push_back(k);
+            if (ks.empty()) break;
+            std::vector<std::pair<Ct, Ct>> pairs;
+            for (uint32_t k : ks)
+                pairs.push_back(k % 2 == 0 ? std::make_pair(T[k / 2], T[k / 2]) : std::make_pair(T[k / 2 + 1], T[k / 2]));
+            std::vector<Ct> ps = muls(pairs);
+            for (size_t i = 0; i < ks.size(); i++) {
+                const uint32_t k = ks[i];
+                if (k % 2 == 0) T[k] = add_const(ps[i], -1.0, true);  // 2 T_{k/2}^2 - 1
+                else T[k] = ew(EW_DBL_SUB, ps[i], adjust(T[1], ps[i]->level));  // 2 T_{h+1} T_h - T_1
             }
         }
-        for (uint32_t g = m; g <= d; g *= 2) {
+        for (uint32_t g = 2 * m; g <= d; g *= 2) {
             Ct p = mul(T[g / 2], T[g / 2]);
             T[g] = add_const(p, -1.0, true);
+        }
+        if (m <= d && !T.count(m)) {
+            Ct p = mul(T[m / 2], T[m / 2]);
+            T[m] = add_const(p, -1.0, true);
         }
     }
 
@@ -337,20 +421,102 @@ struct ChebEval {
         return Val::of(add(u.ct, v.ct));
     }
 
-    Val ev(const std::vector<double> &cf, std::map<uint32_t, Ct> &T, uint32_t m)
+    // The division tree of the polynomial: leaves are the baby-step
+    // combinations (evaluated as the tree is built, they need no product),
+    // inner nodes q T_g + r.  The products q T_g are then taken in rounds by
+    // their depth in the tree, those of one round (and one level) as one batch;
+    // every value is the one the depth-first order gives.
+    struct Node {
+        int kind = 0;  // 0 value, 1 product Q * T_g, 2 sum
+        Val v;
+        bool done = false;
+        int a = -1, b = -1;  // product: Q node; sum: P and R nodes
+        uint32_t g = 0, height = 0;
+    };
+    std::vector<Node> nodes;
+
+    int leaf(Val v)
+    {
+        Node nd;
+        nd.v = std::move(v);
+        nd.done = true;
+        nodes.push_back(nd);
+        return (int)nodes.size() - 1;
+    }
+
+    int build(const std::vector<double> &cf, std::map<uint32_t, Ct> &T, uint32_t m)
     {
         const uint32_t d = (uint32_t)cf.size() - 1;
-        if (d < m) return lin(cf, T);
+        if (d < m) return leaf(lin(cf, T));
         uint32_t g = m;
         while (2 * g <= d) g *= 2;
         std::vector<double> q, r;
         cheb_divide(cf, g, q, r);
-        Val Q = ev(q, T, m);
-        Val P;
-        if (Q.is_const) P = Q.c != 0.0 ? Val::of(const_mul(T[g], Q.c)) : Val::constant(0.0);
-        else P = Val::of(mul(Q.ct, T[g]));
-        Val R = ev(r, T, m);
-        return sum(P, R);
+        const int Q = build(q, T, m);
+        int P;
+        if (nodes[Q].kind == 0 && nodes[Q].v.is_const) {
+            const double qc = nodes[Q].v.c;
+            P = leaf(qc != 0.0 ? Val::of(const_mul(T[g], qc)) : Val::constant(0.0));
+        } else {
+            Node nd;
+            nd.kind = 1;
+            nd.a = Q;
+            nd.g = g;
+            nd.height = nodes[Q].height + 1;
+            nodes.push_back(nd);
+            P = (int)nodes.size() - 1;
+        }
+        const int R = build(r, T, m);
+        Node nd;
+        nd.kind = 2;
+        nd.a = P;
+        nd.b = R;
+        nd.height = std::max(nodes[P].height, nodes[R].height);
+        nodes.push_back(nd);
+        return (int)nodes.size() - 1;
+    }
+
+    // the value of a node whose products are all taken
+    Val value(int i)
+    {
+        Node &nd = nodes[i];
+        if (nd.done) return nd.v;
+        if (nd.kind != 2) PFAIL(HEC_EINVAL, "product evaluated out of order");
+        Val pv = value(nd.a), rv = value(nd.b);
+        nodes[i].v = sum(pv, rv);
+        nodes[i].done = true;
+        return nodes[i].v;
+    }
+
+    Val ev(const std::vector<double> &cf, std::map<uint32_t, Ct> &T, uint32_t m)
+    {
+        nodes.clear();
+        const int root = build(cf, T, m);
+        uint32_t H = 0;
+        for (auto &nd : nodes)
+            if (nd.kind == 1) H = std::max(H, nd.height);
+        for (uint32_t h = 1; h <= H; h++) {
+            std::vector<int> ids;
+            std::vector<std::pair<Ct, Ct>> pairs;
+            for (int i = 0; i < (int)nodes.size(); i++)
+                if (nodes[i].kind == 1 && nodes[i].height == h) {
+                    Val q = value(nodes[i].a);
+                    if (q.is_const) {  // a quotient that summed to a constant: a constant product
+                        nodes[i].v = q.c != 0.0 ? Val::of(const_mul(T[nodes[i].g], q.c)) : Val::constant(0.0);
+                        nodes[i].done = true;
+                        continue;
+                    }
+                    ids.push_back(i);
+                    pairs.push_back({q.ct, T[nodes[i].g]});
+                }
+            if (ids.empty()) continue;
+            std::vector<Ct> ps = muls(pairs);
+            for (size_t j = 0; j < ids.size(); j++) {
+                nodes[ids[j]].v = Val::of(ps[j]);
+                nodes[ids[j]].done = true;
+            }
+        }
+        return value(root);
     }
 
     // p = q T_g + r for g <= deg p < 2g; ascending j, each step one IEEE operation
