@@ -220,3 +220,31 @@ def test_gelu_degree59_full(full):
     log("gelu 2^16 oracle")
     ref = hl.ChebEval(hl.CkksBackend(o), ct, -1.0, 1.0).run(coef)
     assert (g.export() == ref.data).all()
+
+
+@pytest.mark.parametrize("C,mode", [(16, 3), (64, 2)])
+def test_block_full(full, C, mode):
+    """conv -> bias -> GELU (degree 59, bound 15) -> conv -> bias -> pool on a CxHxW
+    CIFAR stage at level 20 (64 channels: two shards, evaluated as one batch):
+    within 1e-6 of the FP64 block with the same polynomial, 10 levels spent."""
+    ctx, prm, o = full
+    from numpy.polynomial import chebyshev as Cheb
+
+    def gelu(x):
+        return 0.5 * x * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (x + 0.044715 * x ** 3)))
+    rng = np.random.default_rng(C + mode)
+    x = rng.uniform(-1, 1, (C, 32, 32))
+    w1 = rng.normal(0, 1.0 / np.sqrt(9 * C), (C, C, 3, 3))
+    w2 = rng.normal(0, 1.0 / np.sqrt(9 * C), (C, C, 3, 3))
+    b1 = (rng.uniform(0.5, 1.5, C), rng.normal(0, 0.5, C))
+    b2 = (rng.uniform(0.5, 1.5, C), rng.normal(0, 0.5, C))
+    coef = Cheb.chebinterpolate(lambda y: gelu(15.0 * y), 59)
+    img = ctx.image_encrypt(x, 20, 91)
+    assert img.info()[-1] == C // 32 or C < 32
+    log("block %dx32x32 mode %d" % (C, mode))
+    blk = ctx.block(img, w1, b1, w2, b2, 15.0, coef, mode=mode)
+    ctx.gen_rotation_keys(blk.steps())
+    out = blk.run(img)
+    assert out.shard_info(0)[0] == 10
+    ref = hl.ref_basic_block(x, w1, b1, w2, b2, 15.0, coef)
+    assert np.abs(out.decrypt() - ref).max() < 1e-6
