@@ -248,3 +248,28 @@ def test_block_full(full, C, mode):
     assert out.shard_info(0)[0] == 10
     ref = hl.ref_basic_block(x, w1, b1, w2, b2, 15.0, coef)
     assert np.abs(out.decrypt() - ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("level,mode", [(2, 0), (2, 3), (24, 2), (11, 3)])
+def test_conv_uneven_levels_bit_exact(full, level, mode):
+    """3x3 convolution of a 2-channel 112x112 shard at the extreme and middle
+    levels of the chain (limb counts 3, 12 and 25; one, two and three key-switch
+    digits), bit for bit with the oracle in the per-rotation, lazy and
+    baby-step/giant-step forms."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(level + 10 * mode)
+    x = np.clip(rng.normal(0, 1, (2, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (2, 2, 3, 3))
+    img = ctx.image_encrypt(x, level, 3100 + level)
+    plan = ctx.conv2d_plan(img, w)
+    plan.set_mode(mode)
+    ctx.gen_rotation_keys(plan.steps())
+    log("conv level %d mode %d" % (level, mode))
+    out = plan.run(img)
+    lay = hl.natural_layout(prm.N, 2, 112, 112)
+    cts = [o.encrypt(o.encode(v, level, 2.0 ** LS), seed=3100 + level, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    assert (img.shard_export(0) == cts[0].data).all()
+    oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1, lazy=(mode == 2), bsgs=(mode == 3))
+    assert out.shard_info(0) == (oc[0].level, oc[0].scale)
+    assert (out.shard_export(0) == oc[0].data).all()
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
