@@ -1226,21 +1226,6 @@ hec_status ct_mul_const_at(hec_ctx *c, const hec_ct *a, uint32_t level, double v
     return HEC_OK;
 }
 
-// acc (+)= a (dropped to acc's level) * value encoded at pscale; first: written, acc's scale set to
-// a.scale * pscale
-hec_status ct_mac_const(hec_ctx *c, hec_ct *acc, const hec_ct *a, double value, double pscale, bool first)
-{
-    if (acc->level > a->level) HEC_FAIL(HEC_ELEVEL, "cannot raise a level");
-    int64_t r;
-    HEC_CHECK(const_coeff(value, pscale, &r));
-    ScalarArg sa;
-    scalar_arg(c, r, acc->level + 1, sa);
-    hec_scalar(c->T, SC_MAC, acc->d, a->d, (size_t)(acc->level + 1) * c->n, (size_t)(a->level + 1) * c->n, 2,
-               (int)acc->level + 1, first ? 1 : 0, sa, c->st);
-    if (first) acc->scale = a->scale * pscale;
-    return HEC_OK;
-}
-
 hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale, hec_ct **out)
 {
     *out = nullptr;
@@ -1252,50 +1237,6 @@ hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale,
     scalar_arg(c, r, a->level + 1, sa);
     const size_t P = (size_t)(a->level + 1) * c->n;
     hec_scalar(c->T, SC_ADD, o->d, a->d, P, P, 2, (int)a->level + 1, 0, sa, c->st);
-    *out = o;
-    return HEC_OK;
-}
-
-// 2a + value (encoded at a's scale)
-hec_status ct_dbl_add_const(hec_ctx *c, const hec_ct *a, double value, hec_ct **out)
-{
-    *out = nullptr;
-    int64_t r;
-    HEC_CHECK(const_coeff(value, a->scale, &r));
-    hec_ct *o = ct_new(c, a->level, a->scale);
-    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-    ScalarArg sa;
-    scalar_arg(c, r, a->level + 1, sa);
-    const size_t P = (size_t)(a->level + 1) * c->n;
-    hec_scalar(c->T, SC_DBL_ADD, o->d, a->d, P, P, 2, (int)a->level + 1, 0, sa, c->st);
-    *out = o;
-    return HEC_OK;
-}
-
-// 2a - b (levels and scales must match)
-hec_status ct_dbl_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
-{
-    *out = nullptr;
-    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in subtraction");
-    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in subtraction");
-    hec_ct *o = ct_new(c, a->level, a->scale);
-    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-    const size_t P = (size_t)(a->level + 1) * c->n;
-    hec_ew(c->T, EW_DBL_SUB, o->d, a->d, b->d, P, P, P, 2, c->idmap(), (int)a->level + 1, c->st);
-    *out = o;
-    return HEC_OK;
-}
-
-// a + b out of place (levels and scales must match)
-hec_status ct_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
-{
-    *out = nullptr;
-    if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch in addition");
-    if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in addition");
-    hec_ct *o = ct_new(c, a->level, a->scale);
-    if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-    const size_t P = (size_t)(a->level + 1) * c->n;
-    hec_ew(c->T, EW_ADD, o->d, a->d, b->d, P, P, P, 2, c->idmap(), (int)a->level + 1, c->st);
     *out = o;
     return HEC_OK;
 }

@@ -166,12 +166,6 @@ hec_status ct_add_const(hec_ctx *c, const hec_ct *a, double value, double scale,
 hec_status ct_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
 // a's first level+1 limbs (a dropped to `level`) * value at pscale
 hec_status ct_mul_const_at(hec_ctx *c, const hec_ct *a, uint32_t level, double value, double pscale, hec_ct **out);
-// acc (+)= a (dropped to acc's level) * value at pscale; first: written and acc.scale = a.scale * pscale
-hec_status ct_mac_const(hec_ctx *c, hec_ct *acc, const hec_ct *a, double value, double pscale, bool first);
-// 2a + value (at a's scale); 2a - b; a + b (new handles)
-hec_status ct_dbl_add_const(hec_ctx *c, const hec_ct *a, double value, hec_ct **out);
-hec_status ct_dbl_sub(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
-hec_status ct_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out);
 hec_status ct_drop(hec_ctx *c, const hec_ct *a, uint32_t level, hec_ct **out);
 void pt_free(hec_pt *p);
 void ct_free(hec_ct *p);
