@@ -273,3 +273,26 @@ def test_conv_uneven_levels_bit_exact(full, level, mode):
     assert out.shard_info(0) == (oc[0].level, oc[0].scale)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
+def test_stem_channel_shards_full(full):
+    """The ImageNet stem shape: a 3x224x224 image (side padded to 256, so each
+    channel spans two shards) through a 3x3 stride-2 convolution 3 -> 8
+    (channel-shard rotations across neighbouring shards, downsampling, merge
+    into image shards of 112x112) in baby-step/giant-step mode; within 1e-5 of
+    FP64 after decryption."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(224)
+    x = rng.uniform(-1, 1, (3, 224, 224))
+    w = rng.normal(0, 0.05, (8, 3, 3, 3))
+    img = ctx.image_encrypt(x, 20, 4224)
+    C, H, W, mp, t = img.info()
+    assert (mp, t) == (256, 6) and img.is_channel_sharded()
+    plan = ctx.conv2d_plan(img, w, stride=2, pad=1)
+    plan.set_mode(3)
+    ctx.gen_rotation_keys(plan.steps())
+    log("stem conv, %d rotation keys" % len(plan.steps()))
+    out = plan.run(img)
+    Co, Ho, Wo, mpo, to = out.info()
+    assert (Co, Ho, Wo) == (8, 112, 112)
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
