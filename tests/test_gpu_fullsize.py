@@ -296,3 +296,29 @@ def test_stem_channel_shards_full(full):
     Co, Ho, Wo, mpo, to = out.info()
     assert (Co, Ho, Wo) == (8, 112, 112)
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_imagenet_layer_shards_full(full, mode):
+    """The 112x112x64 layer's geometry with 8 channels: four image shards of two
+    padded 128x128 channels, 3x3 conv 8 -> 8 (every output shard sums all input
+    shards), then 2x2 average pooling (downsampling, consolidation of the four
+    shards, duplication); within 1e-5 of FP64 after decryption.  (All 64
+    channels need 18432 weight plaintexts, 267 GiB over Q and P at level 20:
+    more than the HBM next to the rotation keys.)"""
+    ctx, prm, o = full
+    rng = np.random.default_rng(112 + mode)
+    x = np.clip(rng.normal(0, 1, (8, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (8, 8, 3, 3))
+    img = ctx.image_encrypt(x, 20, 5112)
+    assert img.info()[3:] == (128, 4)
+    plan = ctx.conv2d_plan(img, w)
+    plan.set_mode(mode)
+    ctx.gen_rotation_keys(plan.steps())
+    log("112x112x8 conv mode %d" % mode)
+    y = plan.run(img)
+    ctx.gen_rotation_keys(ctx.avgpool_steps(y))
+    z = ctx.avgpool(y, mode=mode)
+    assert z.info()[:3] == (8, 56, 56)
+    ref = hl.ref_avgpool2x2(hl.ref_conv2d(x, w, 1))
+    assert np.abs(z.decrypt() - ref).max() < 1e-5
