@@ -207,6 +207,15 @@ hec_status he_conv2d_sharded(hec_ctx *ctx, const hec_image *in, const double *w,
  * level.  Run is what a server repeats per request. */
 hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const double *w, uint32_t Co, uint32_t kh,
                                  uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out);
+/* With flags = HEC_PLAN_Q_ONLY the weight plaintexts are kept over Q_l only
+ * (21 instead of 29 limbs at level 20 with 8 special primes): such a plan
+ * runs in modes 0 and 1 only (he_conv2d_plan_set_mode returns HEC_EINVAL for
+ * 2 and 3).  For layers whose plaintexts would not fit in HBM otherwise, e.g.
+ * the 112x112x64 layer's 18432 plaintexts (267 GiB over Q and P, 193 GiB
+ * over Q).  Other flag bits: HEC_EINVAL. */
+#define HEC_PLAN_Q_ONLY 1u
+hec_status he_conv2d_plan_create_ex(hec_ctx *ctx, const hec_image *like, const double *w, uint32_t Co, uint32_t kh,
+                                    uint32_t kw, uint32_t stride, uint32_t pad, uint32_t flags, hec_conv_plan **out);
 hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec_image *in, hec_image **out);
 /* Execution mode of plan runs: 0 = batched (hoisted ModUp, rotations of a
  * shard batched per launch), 1 = plain (every rotation its own ModUp and

@@ -189,7 +189,7 @@ Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t m
 void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps);
 // convolution plan for an image of layout `lay` at `level` (what he_conv2d_plan_create builds from an image)
 hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t level, const double *w, uint32_t Co, uint32_t kh,
-                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out);
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only = false);
 // output layout of a plan (before the downsampling of a strided one)
 const Layout &conv_plan_out(const hec_conv_plan *p);
 // in + the per-channel bias (new handles in out)

@@ -1179,6 +1179,7 @@ struct hec_conv_plan {
     Layout in, out;  // out = unstrided output layout
     uint32_t level = 0, stride = 1;
     int mode = 0;
+    bool q_only = false;  // weight plaintexts over Q only: modes 0 and 1
     typedef RotTerm Item;
     std::vector<std::vector<Item>> items;  // per input shard
     std::set<int32_t> steps;
@@ -1276,10 +1277,25 @@ extern "C" hec_status he_conv2d_plan_create(hec_ctx *c, const hec_image *like, c
     return conv_plan_create(c, like->lay, lvl, w, Co, kh, kw, stride, pad, out);
 }
 
+extern "C" hec_status he_conv2d_plan_create_ex(hec_ctx *c, const hec_image *like, const double *w, uint32_t Co,
+                                               uint32_t kh, uint32_t kw, uint32_t stride, uint32_t pad,
+                                               uint32_t flags, hec_conv_plan **out)
+{
+    if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !like || !w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
+    if (flags & ~(uint32_t)HEC_PLAN_Q_ONLY) HEC_FAIL(HEC_EINVAL, "unknown plan flags");
+    if (like->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    const uint32_t lvl = like->shards[0]->level;
+    for (auto *s : like->shards)
+        if (s->level != lvl) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
+    return conv_plan_create(c, like->lay, lvl, w, Co, kh, kw, stride, pad, out, (flags & HEC_PLAN_Q_ONLY) != 0);
+}
+
 const Layout &conv_plan_out(const hec_conv_plan *p) { return p->out; }
 
 hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const double *w, uint32_t Co, uint32_t kh,
-                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out)
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only)
 {
     *out = nullptr;
     if (!w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
@@ -1302,8 +1318,10 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
         for (auto &it : v)
             for (auto &pp : it.pts) zp.push_back(pp.second.data());
     std::vector<hec_pt *> pts;
-    // limbs over Q_l and P: the lazy-ModDown mode multiplies before ModDown
-    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts, true));
+    // limbs over Q_l and P: the lazy-ModDown mode multiplies before ModDown (over Q_l only for a plan that
+    // runs per rotation, a quarter less memory)
+    p->q_only = q_only;
+    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts, !q_only));
     size_t q = 0;
     for (size_t u = 0; u < items.size(); u++)
         for (auto &it : items[u]) {
@@ -1331,6 +1349,7 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
 extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
     if (!p || mode < 0 || mode > 3) HEC_FAIL(HEC_EINVAL, "bad mode");
+    if (p->q_only && mode >= 2) HEC_FAIL(HEC_EINVAL, "plan without special-prime limbs runs in modes 0 and 1 only");
     if (mode == 3) {
         HEC_TRY_HIP(hipSetDevice(p->ctx->dev));
         HEC_CHECK(build_bsgs(p->ctx, p));

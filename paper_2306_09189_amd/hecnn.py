@@ -25,6 +25,7 @@ EXPORTS = [
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
+    "he_conv2d_plan_create_ex",
 ]
 
 
@@ -106,6 +107,7 @@ def lib():
             "he_conv2d_sharded": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, dblp, P(vp)]),
             "he_conv2d_plan_create": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, P(vp)]),
             "he_conv2d_plan_run": (c, [vp, vp, vp, P(vp)]),
+            "he_conv2d_plan_create_ex": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, u32, P(vp)]),
             "he_conv2d_plan_set_mode": (c, [vp, c]),
             "he_conv2d_plan_steps": (c, [vp, i32p, sz, szp]),
             "he_avgpool_steps": (c, [vp, vp, i32p, sz, szp]),
@@ -492,11 +494,17 @@ class Context:
                                       ctypes.byref(out)))
         return Image(self, out.value)
 
-    def conv2d_plan(self, like, w, stride=1, pad=1):
+    def conv2d_plan(self, like, w, stride=1, pad=1, q_only=False):
+        """q_only: weight plaintexts over Q only (modes 0 and 1), for layers too large otherwise."""
         w = _arr(w, np.float64)
         Co, Ci, kh, kw = w.shape
         out = vp()
-        check(lib().he_conv2d_plan_create(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, ctypes.byref(out)))
+        if q_only:
+            check(lib().he_conv2d_plan_create_ex(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, 1,
+                                                 ctypes.byref(out)))
+        else:
+            check(lib().he_conv2d_plan_create(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad,
+                                              ctypes.byref(out)))
         return ConvPlan(self, out.value)
 
     def avgpool(self, img, mode=0):

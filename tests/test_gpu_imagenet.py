@@ -1,0 +1,64 @@
+"""The 112x112x64 layer at full size on one MI355X (2N = 2^16, level 20):
+3x3 conv 64 -> 64 over 32 image shards of two padded 128x128 channels, then
+2x2 average pooling.  Its 18432 weight plaintexts are kept over Q only
+(193 GiB); decryption within 1e-5 of FP64."""
+import ctypes
+import gc
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import he_layers as hl
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def free_hbm():
+    hip = ctypes.CDLL("libamdhip64.so")
+    free, total = ctypes.c_size_t(), ctypes.c_size_t()
+    if hip.hipMemGetInfo(ctypes.byref(free), ctypes.byref(total)) != 0:
+        return 0
+    return free.value
+
+
+def test_imagenet_layer_full():
+    from paper_2306_09189_amd import hecnn
+    gc.collect()
+    need = 230 << 30
+    if free_hbm() < need:
+        pytest.skip("needs %d GiB of free device memory, %d GiB free" % (need >> 30, free_hbm() >> 30))
+    ctx = hecnn.Context(16, 24, 60, 50, 8, 60, 3, 50, device=0)
+    ctx.keygen(2024)
+    rng = np.random.default_rng(1003)
+    x = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (64, 64, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3003)
+    assert img.info() == (64, 112, 112, 128, 32)
+    t = time.perf_counter()
+    plan = ctx.conv2d_plan(img, w, q_only=True)
+    ctx.sync()
+    log("plan: 18432 plaintexts in %.1f s" % (time.perf_counter() - t))
+    ctx.gen_rotation_keys(plan.steps())
+    t = time.perf_counter()
+    y = plan.run(img)
+    ctx.sync()
+    log("conv 64->64 over 32 shards: %.0f ms" % ((time.perf_counter() - t) * 1e3))
+    del plan
+    gc.collect()
+    ctx.gen_rotation_keys(ctx.avgpool_steps(y))
+    t = time.perf_counter()
+    z = ctx.avgpool(y)
+    ctx.sync()
+    log("pool: %.0f ms" % ((time.perf_counter() - t) * 1e3))
+    assert z.info()[:3] == (64, 56, 56)
+    ref = hl.ref_avgpool2x2(hl.ref_conv2d(x, w, 1))
+    err = np.abs(z.decrypt() - ref).max()
+    log("max abs err %.3g" % err)
+    assert err < 1e-5

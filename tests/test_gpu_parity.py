@@ -376,3 +376,27 @@ def test_layers_edge_shapes_bit_exact(small, shape, ops, pad, mode):
             real_ops.append(op)
     log("edge", shape, [op[0] for op in ops], "pad", pad, "mode", mode)
     run_pipeline(ctx, prm, o, x, real_ops, 6, seed=41, mode=mode, pad=pad)
+
+
+def test_q_only_plan(small):
+    """A plan whose weight plaintexts are kept over Q only gives the same
+    ciphertexts as a full plan in modes 0 and 1 and refuses modes 2 and 3."""
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    rng = np.random.default_rng(77)
+    x = rng.uniform(-1, 1, (4, 16, 16))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    img = ctx.image_encrypt(x, 6, 77)
+    full = ctx.conv2d_plan(img, w)
+    qo = ctx.conv2d_plan(img, w, q_only=True)
+    ctx.gen_rotation_keys(full.steps())
+    assert qo.steps() == full.steps()
+    a = full.run(img)
+    for mode in (0, 1):
+        qo.set_mode(mode)
+        b = qo.run(img)
+        for u in range(a.info()[-1]):
+            assert (a.shard_export(u) == b.shard_export(u)).all()
+    for mode in (2, 3):
+        with pytest.raises(hecnn.HecError):
+            qo.set_mode(mode)
