@@ -78,6 +78,16 @@ struct KsMacBatch {
     u64 *E[HEC_MAC_OUT];                       // [2][nqp][n], NTT form
 };
 
+// Plaintext products of several rotated ciphertexts summed into several
+// outputs in one pass: out_v (+)= sum_t ct_t * pt[t][v] over the Q limbs.
+#define HEC_MAC_TERMS 16
+#define HEC_MAC_OUTS 8
+struct MacBatch {
+    const u64 *ct[HEC_MAC_TERMS];                // [2][nq][n], NTT form
+    const u64 *pt[HEC_MAC_TERMS][HEC_MAC_OUTS];  // Q limbs first, NTT + Montgomery form (null: no product)
+    u64 *out[HEC_MAC_OUTS];                      // [2][nq][n]
+};
+
 struct CombineBatch {
     u64 *out[HEC_KS_BATCH];        // [2][nq][n]
     const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
@@ -125,6 +135,10 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 // Rotations by zero (g == 1) must precede the others; returns false (nothing launched) otherwise.
 bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
                 const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
+
+// the products of b (nterms <= HEC_MAC_TERMS, nout <= HEC_MAC_OUTS) summed in 128 bits and reduced once
+// (the same residues as multiply-accumulating them one at a time); bit v of `first`: output v written
+void hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st);
 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
                          const LevelC *lc, const u32 *pmap, hipStream_t st);

@@ -1130,6 +1130,54 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
     return true;
 }
 
+// Sums of plaintext products over Q: each lane one coefficient of one limb, the
+// products of all terms for up to HEC_MAC_OUTS outputs accumulated in 128 bits
+// (< HEC_MAC_TERMS q^2 < q 2^64) and reduced once, so every rotated input is
+// read once per group of outputs.
+__global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms, u32 nout, u32 nq, u32 first,
+                                                          DevTables T)
+{
+    const u32 o = blockIdx.y;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const PrimeC pc = T.pc[o];
+    const size_t n = T.n, off = (size_t)o * n + k;
+    acc128 acc[HEC_MAC_OUTS][2];
+#pragma unroll
+    for (int v = 0; v < HEC_MAC_OUTS; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    for (u32 t = 0; t < nterms; t++) {
+        const u64 *ct = b.ct[t];
+        const u64 c0 = ct[off], c1 = ct[(size_t)nq * n + off];
+#pragma unroll
+        for (int v = 0; v < HEC_MAC_OUTS; v++) {
+            const u64 *pt = b.pt[t][v];
+            if (!pt) continue;
+            const u64 m = pt[off];
+            mac(acc[v][0], c0, m);
+            mac(acc[v][1], c1, m);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < HEC_MAC_OUTS; v++) {
+        u64 *out = b.out[v];
+        if ((u32)v >= nout || !out) continue;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            u64 *dst = out + (size_t)p * nq * n + off;
+            u64 r = redc(acc[v][p].hi, acc[v][p].lo, pc.q, pc.qinv_neg);
+            if (!((first >> v) & 1)) r = add_mod(r, *dst, pc.q);
+            *dst = r;
+        }
+    }
+}
+void hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st)
+{
+    if (nterms <= 0 || nout <= 0) return;
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
+    KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms, g, dim3(EW_THREADS), 0, st, b, (u32)nterms, (u32)nout,
+            (u32)nq, (u32)first, T);
+}
+
 // ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)
 __global__ void k_moddown_combine(CombineBatch cb, const u64 *c0, u32 nq, u32 nqp, const LevelC *lc,
                                   const u32 *pmap, DevTables T)

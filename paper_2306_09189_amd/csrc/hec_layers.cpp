@@ -1370,6 +1370,56 @@ extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *step
     return HEC_OK;
 }
 
+// acc[v] (+)= sum over the chunk's rotations t of rots[t] * (plaintext of term
+// i0 + t for v): output groups of HEC_MAC_OUTS, term batches of HEC_MAC_TERMS,
+// one launch each; first[v] set: output v not written yet (cleared here)
+static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots,
+                                const std::vector<hec_conv_plan::Item> &its, size_t i0, std::vector<hec_ct *> &acc,
+                                std::vector<char> &first)
+{
+    const size_t nout = acc.size(), cnt = rots.size();
+    const uint32_t lvl = rots[0]->level;
+    for (size_t t = 0; t < cnt; t++)
+        for (auto &pp : its[i0 + t].pts)
+            if (pp.second->level != lvl || rots[t]->level != lvl || acc[pp.first]->level != lvl)
+                HEC_FAIL(HEC_ELEVEL, "level mismatch in pt product");
+    for (size_t v0 = 0; v0 < nout; v0 += HEC_MAC_OUTS) {
+        const size_t nv = std::min((size_t)HEC_MAC_OUTS, nout - v0);
+        for (size_t t0 = 0; t0 < cnt; t0 += HEC_MAC_TERMS) {
+            const size_t nt = std::min((size_t)HEC_MAC_TERMS, cnt - t0);
+            MacBatch b{};
+            bool any = false;
+            for (size_t t = 0; t < nt; t++) {
+                b.ct[t] = rots[t0 + t]->d;
+                for (auto &pp : its[i0 + t0 + t].pts)
+                    if (pp.first >= v0 && pp.first < v0 + nv) {
+                        b.pt[t][pp.first - v0] = pp.second->d;
+                        any = true;
+                    }
+            }
+            if (!any) continue;
+            int fbits = 0;
+            for (size_t j = 0; j < nv; j++) {
+                bool used = false;
+                for (size_t t = 0; t < nt && !used; t++) used = b.pt[t][j] != nullptr;
+                if (!used) continue;
+                b.out[j] = acc[v0 + j]->d;
+                if (first[v0 + j]) {
+                    fbits |= 1 << j;
+                    first[v0 + j] = 0;
+                    for (size_t t = 0; t < nt; t++)
+                        if (b.pt[t][j]) {
+                            acc[v0 + j]->scale = rots[t0 + t]->scale * its[i0 + t0 + t].pts[0].second->scale;
+                            break;
+                        }
+                }
+            }
+            hec_mac_terms(c->T, b, (int)nt, (int)nv, (int)lvl + 1, fbits, c->st);
+        }
+    }
+    return HEC_OK;
+}
+
 #define ROT_CHUNK 32
 extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, const hec_image *in, hec_image **out)
 {
@@ -1414,12 +1464,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
             } else {
                 for (size_t t = 0; t < cnt && s == HEC_OK; t++) s = ckks_rotate(c, in->shards[u], st[t], &rots[t]);
             }
-            for (size_t t = 0; t < cnt && s == HEC_OK; t++)
-                for (auto &pp : its[i0 + t].pts) {
-                    s = ct_mac_pt(c, acc[pp.first], rots[t], pp.second, first[pp.first]);
-                    first[pp.first] = 0;
-                    if (s != HEC_OK) break;
-                }
+            if (s == HEC_OK) s = mac_rotations(c, rots, its, i0, acc, first);
             free_all(rots);
         }
     }
