@@ -396,6 +396,22 @@ def main():
     block_ms = float(np.median(ts[1:]))
     block_err = float(np.abs(ob.decrypt() - hl.ref_basic_block(xb, wb1, bn1, wb2, bn2, bound, coef)).max())
     del ob, blk, imb
+    # the classifier head of a CIFAR ResNet: global average pooling of a
+    # 64x8x8 stage folded into a 64 -> 10 linear layer (rotate-and-add)
+    xl = rng.uniform(-1, 1, (64, 8, 8))
+    wl = rng.normal(0, 0.1, (10, 64))
+    iml = ctx.image_encrypt(xl, LEVEL, 8)
+    ctx.gen_rotation_keys(ctx.linear_steps(iml))
+    ts = []
+    for _ in range(4):
+        ctx.sync()
+        s = time.perf_counter()
+        ol = ctx.linear(iml, wl, True)
+        ctx.sync()
+        ts.append((time.perf_counter() - s) * 1e3)
+    linear_ms = float(np.median(ts[1:]))
+    linear_err = float(np.abs(ctx.decrypt(ol)[:10] - hl.ref_linear(xl, wl, True)).max())
+    del ol, iml
 
     out = {
         "metric": "key-switched rotations/sec + HE conv-layer ms at 2N=2^16; batched vs plain",
@@ -430,6 +446,8 @@ def main():
         "block_plan_mode": bmode,
         "block_keyswitches": ks_block,
         "block_max_abs_err_vs_fp64": block_err,
+        "pool_linear_64x8x8_to_10_ms": linear_ms,
+        "pool_linear_max_abs_err_vs_fp64": linear_err,
         "max_abs_err_vs_fp64": err,
         "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
         "roofline": roofline,

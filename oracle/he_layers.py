@@ -16,8 +16,7 @@ N/B blocks.  Each shard carries a block map lam[b] = logical channel held by
 block b (-1 for an empty block); duplication and the permutation introduced by
 pooling are both just block maps.
 
-Readings of passages that are silent, garbled or ambiguous (each repeated in
-DESIGN.md):
+Readings of passages that are silent, garbled or ambiguous:
   * duplicated channels are stored as consecutive copies, [M0, M0, M1, M1, ...],
     the order the pooling duplication step produces;
   * the offsets of a convolution are found by the two-phase rule in
@@ -31,7 +30,12 @@ DESIGN.md):
     equation repeats S_2 and writes m^2 for the post-pool block size);
     duplication by d shifts by multiples of B/d;
   * when only one level is left, the two reductions are fused into one
-    masked sum (masks combined non-homomorphically) with masks at scale q/4.
+    masked sum (masks combined non-homomorphically) with masks at scale q/4;
+  * a convolution's weight plaintexts may be built in basis-mask form: the
+    plaintext of a tap is, block by block, a weight times the tap's mask, so
+    it is sum_b round(w_b q_l / 2^s) * E_b with E_b the encoding of the mask
+    restricted to block b at scale 2^s (an exact integer combination of a few
+    basis polynomials instead of one encoding per weight plaintext).
 """
 import math
 
@@ -169,12 +173,66 @@ class SlotSim:
         return ct[1]
 
 
+class BlockVec(np.ndarray):
+    """A slot vector that is, block by block, a weight times one common 0/1
+    mask of B slots: vec[b*B:(b+1)*B] = wb[b] * mask (the weight plaintext of
+    one convolution tap, Section 4.1).  Arrays derived from it (rolls,
+    products, slices) are plain vectors again."""
+
+    def __new__(cls, N, B, mask):
+        obj = np.zeros(N).view(cls)
+        obj.B, obj.mask, obj.wb = B, mask, {}
+        return obj
+
+    def __array_finalize__(self, obj):
+        self.B, self.mask, self.wb = None, None, {}
+
+    def set_block(self, b, w):
+        self[b * self.B:(b + 1) * self.B] = w * self.mask
+        self.wb[b] = float(w)
+
+
 class CkksBackend:
     """Encrypted oracle ciphertexts; a plaintext product encodes the slot
-    vector at the requested scale, at the ciphertext's level."""
+    vector at the requested scale, at the ciphertext's level.  With basis = s
+    the block-masked weight vectors of a convolution are built in basis-mask
+    form instead (`pt_coeffs`)."""
 
-    def __init__(self, oracle):
+    def __init__(self, oracle, basis=None):
         self.o = oracle
+        self.basis = basis
+        self._E = {}
+
+    def _basis_poly(self, vec, b):
+        """E_b: the encoding of vec's mask restricted to block b at scale 2^s."""
+        key = (vec.mask.tobytes(), vec.B, b)
+        if key not in self._E:
+            z = np.zeros(len(vec))
+            z[b * vec.B:(b + 1) * vec.B] = vec.mask
+            self._E[key] = self.o.encode_coeffs(z, 2.0 ** self.basis)
+        return self._E[key]
+
+    def pt_coeffs(self, vec, pscale):
+        """Integer coefficients of the plaintext of vec at pscale.  Exact
+        encoding, or for a block-masked vector with basis = s:
+        sum over its blocks of round_half_away(w_b * pscale / 2^s) * E_b,
+        every weight rounded as a constant (exact product) and the sum taken
+        over the integers."""
+        if self.basis is None or getattr(vec, "mask", None) is None:
+            return self.o.encode_coeffs(vec, pscale)
+        wscale = float(pscale) / 2.0 ** self.basis
+        m = np.zeros(self.o.p.n, dtype=np.int64)
+        bound = 0
+        for b, w in sorted(vec.wb.items()):
+            wh = int(self.o.const_coeffs(w, wscale)[0])
+            if wh == 0:
+                continue
+            E = self._basis_poly(vec, b)
+            bound += abs(wh) * int(np.abs(E).max())
+            if bound >= 1 << 62:
+                raise OverflowError("basis plaintext coefficient exceeds 2^62")
+            m += wh * E
+        return m
 
     def q(self, level):
         return float(self.o.p.q[level])
@@ -186,7 +244,9 @@ class CkksBackend:
         return self.o.rotate(ct, r)
 
     def mul_plain(self, ct, vec, pscale):
-        return self.o.mul_pt(ct, self.o.encode(vec, ct.level, pscale))
+        from .ckks import Pt
+        m = self.pt_coeffs(vec, pscale)
+        return self.o.mul_pt(ct, Pt(self.o.limbs_of(m, ct.level), ct.level, float(pscale), m))
 
     def add(self, a, b):
         return self.o.add(a, b)
@@ -295,11 +355,11 @@ def conv_plan_split(lay, w, pad):
                     split = ((r * B) % N, (dk * mp + dl) % N)
                     pts = {}
                     for v, mu in enumerate(out.shards):
-                        vec = np.zeros(N)
+                        vec = BlockVec(N, B, mask)
                         for b, f in fs.items():
                             g = mu[b]
                             if g >= 0:
-                                vec[b * B:(b + 1) * B] = w[g, f, kr, kc] * mask
+                                vec.set_block(b, w[g, f, kr, kc])
                         if vec.any():
                             pts[v] = vec
                     if pts:
@@ -391,7 +451,7 @@ def _accumulate_lazy(be, cts, nout, plan, pscale=None, rescale=True):
         for e, (a, pts) in zip(ks, items):
             g = p.galois(a)
             for v, vec in pts.items():
-                m = o.encode_coeffs(vec, pscale)
+                m = be.pt_coeffs(vec, pscale)
                 ptq = o.limbs_of(m, lvl)
                 used[v] = True
                 scale = ct.scale * pscale
@@ -493,6 +553,8 @@ def _conv_bsgs(be, cts, nout, plan, pscale=None, rescale=True):
         out_v = sum_g rot_g(T_{g,v})
     takes one key switch per (g, v) and one more lazy ModDown.  Rotations:
     (babies per input) + (giants x outputs) instead of one per amount."""
+    if getattr(be, "basis", None) is not None:
+        raise ValueError("basis-mask plaintexts are not taken by the baby-step/giant-step form")
     keys = sorted({(g, v) for items in plan for _, pts, (_, g) in items for v in pts})
     kidx = {k: i for i, k in enumerate(keys)}
     baby_plan = []

@@ -277,3 +277,64 @@ def test_linear_and_pool_linear(small):
         got = o.decrypt(out)
         assert np.abs(got[:O] - hl.ref_linear(x, W, pool)).max() < 1e-5
         assert np.abs(got[O:]).max() < 1e-5
+
+
+def test_basis_plaintext_pins(small):
+    """Basis-mask plaintexts (a weight per block times the encoding of the
+    tap's mask on that block at 2^s) against the exact encoding of the same
+    slot vector: per coefficient within 1/2 + |w^|/2 + 2^(s-1) (rounding of
+    the weight, of the basis polynomial and of the exact encoding; every mask
+    coefficient of sigma^-1 is at most 1), and decoded within the triangle
+    bound 2^(s-1)/scale + |w^| n / (2 scale) per block."""
+    p, o = small
+    rng = np.random.default_rng(31)
+    lay = hl.natural_layout(p.N, 4, 4, 4)     # blocks of 16 slots, channels duplicated
+    x = np.zeros((4, 4, 4))
+    w = rng.normal(0, 0.3, (4, 4, 3, 3))
+    out, plan = hl.conv_plan_split(lay, w, 1)
+    s = 20
+    be = hl.CkksBackend(o, basis=s)
+    pscale = be.q(5)
+    vecs = [vec for items in plan for _, pts, _ in items for vec in pts.values()]
+    assert vecs and all(v.mask is not None for v in vecs)
+    for vec in vecs[:12]:
+        mb = be.pt_coeffs(vec, pscale)
+        me = o.encode_coeffs(np.asarray(vec), pscale)
+        wh = {b: int(o.const_coeffs(wv, pscale / 2.0 ** s)[0]) for b, wv in vec.wb.items()}
+        tol = sum(0.5 + abs(h) / 2.0 + 2.0 ** (s - 1) for h in wh.values()) + 0.5
+        assert np.abs(mb - me).max() <= tol
+        dec = o.decode(mb.astype(np.float64), pscale)
+        for b, h in wh.items():
+            blk = slice(b * vec.B, (b + 1) * vec.B)
+            bnd = 2.0 ** (s - 1) / pscale + abs(h) * p.n / (2 * pscale)
+            assert np.abs(dec[blk] - np.asarray(vec)[blk]).max() <= bnd * len(wh)
+    # a derived (rolled) vector is a plain vector again: exact encoding
+    r = np.roll(vecs[0], 3)
+    assert getattr(r, "mask", None) is None
+    assert (be.pt_coeffs(r, pscale) == o.encode_coeffs(np.asarray(r), pscale)).all()
+
+
+def test_basis_conv(small):
+    """Convolutions with basis-mask plaintexts, per rotation and with lazy
+    ModDown, decrypt within 1e-5 of FP64 on an image-sharded input (two
+    shards) and give other ciphertexts than exact encoding; the
+    baby-step/giant-step form refuses them."""
+    p, o = small
+    rng = np.random.default_rng(32)
+    x = rng.uniform(-1, 1, (4, 8, 8))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    lay = hl.natural_layout(p.N, 4, 8, 8)
+    assert len(lay.shards) == 2
+    cts = enc_image(o, x, lay, 6, 2.0 ** 40, 33)
+    ref = hl.ref_conv2d(x, w, 1)
+    beb = hl.CkksBackend(o, basis=20)
+    a, al = hl.conv2d(beb, cts, lay, w, pad=1)
+    la, _ = hl.conv2d(beb, cts, lay, w, pad=1, lazy=True)
+    e, _ = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1)
+    for outs in (a, la):
+        assert outs[0].level == 5 and outs[0].scale == 2.0 ** 40
+        assert np.abs(dec_image(o, outs, al) - ref).max() < 1e-5
+    assert not (a[0].data == e[0].data).all()
+    assert not (a[0].data == la[0].data).all()
+    with pytest.raises(ValueError):
+        hl.conv2d(beb, cts, lay, w, pad=1, bsgs=True)
