@@ -212,8 +212,23 @@ hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const doub
  * runs in modes 0 and 1 only (he_conv2d_plan_set_mode returns HEC_EINVAL for
  * 2 and 3).  For layers whose plaintexts would not fit in HBM otherwise, e.g.
  * the 112x112x64 layer's 18432 plaintexts (267 GiB over Q and P, 193 GiB
- * over Q).  Other flag bits: HEC_EINVAL. */
+ * over Q).  Unknown flag bits: HEC_EINVAL. */
 #define HEC_PLAN_Q_ONLY 1u
+/* With flags = HEC_PLAN_BASIS | HEC_PLAN_BASIS_SCALE(s), 1 <= s <= 50, the
+ * weight plaintexts are kept in basis-mask form (Section 4.1: the plaintext
+ * of a tap is, block by block, a kernel weight times the tap's mask, and the
+ * masks are combined with the weights outside the encryption): per tap and
+ * block b of a shard the mask restricted to b, encoded at 2^s over Q_l and P
+ * (E_b), and per product the integers w^_b = round_half_away(w_b q_l / 2^s);
+ * the plaintext is sum_b w^_b E_b, formed inside the product kernels.  Memory
+ * taps x blocks x limbs instead of one plaintext per product (the
+ * 112x112x64 layer: 261 MiB instead of 267 GiB), at the price of the
+ * rounding of w^_b (2^(s-1) / q_l absolute per weight) and of E_b (relative
+ * 2^-s).  Needs an image-sharded input with at most 4 blocks per shard
+ * (HEC_ELAYOUT otherwise); runs in modes 0, 1 and 2 (he_conv2d_plan_set_mode
+ * returns HEC_EINVAL for 3); excludes HEC_PLAN_Q_ONLY (HEC_EINVAL). */
+#define HEC_PLAN_BASIS 2u
+#define HEC_PLAN_BASIS_SCALE(s) ((uint32_t)(s) << 8)
 hec_status he_conv2d_plan_create_ex(hec_ctx *ctx, const hec_image *like, const double *w, uint32_t Co, uint32_t kh,
                                     uint32_t kw, uint32_t stride, uint32_t pad, uint32_t flags, hec_conv_plan **out);
 hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec_image *in, hec_image **out);

@@ -78,6 +78,20 @@ struct KsMacBatch {
     u64 *E[HEC_MAC_OUT];                       // [2][nqp][n], NTT form
 };
 
+// Weight plaintexts in basis-mask form: the plaintext of a term for an output
+// is sum_b w_b * E_{tap,b} over the blocks b of a shard, E_{tap,b} the encoded
+// mask of the term's tap restricted to block b; the product kernels read the
+// basis polynomials of a term once and form every output's plaintext in
+// registers.  With E null the plaintext pointers point at plaintexts; with E
+// set they point at the weight rows [nb][nqp] (Montgomery form) of each
+// (term, output).
+#define HEC_BASIS_NB 4
+struct BasisArg {
+    const u64 *E;            // [taps][nb][nqp][n], NTT + Montgomery form
+    u32 tap[HEC_KS_BATCH];   // tap of each term
+    u32 nb, nqp;             // blocks per shard; limbs of a basis polynomial and stride of a weight row
+};
+
 // Plaintext products of several rotated ciphertexts summed into several
 // outputs in one pass: out_v (+)= sum_t ct_t * pt[t][v] over the Q limbs.
 #define HEC_MAC_TERMS 16
@@ -133,12 +147,15 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 // or P * (c0, c1) for g == 1, over the terms' own ciphertexts and ModUps (b.ct, b.D);
 // pm[i] = P * 2^64 mod q_i; bit v of `first` set: output v is written instead of accumulated.
 // Rotations by zero (g == 1) must precede the others; returns false (nothing launched) otherwise.
+// ba (nullable): the plaintexts in basis-mask form.
 bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
-                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st);
+                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st, const BasisArg *ba = nullptr);
 
 // the products of b (nterms <= HEC_MAC_TERMS, nout <= HEC_MAC_OUTS) summed in 128 bits and reduced once
 // (the same residues as multiply-accumulating them one at a time); bit v of `first`: output v written
-void hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st);
+// false (nothing launched) for sizes out of range
+bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st,
+                   const BasisArg *ba = nullptr);
 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
                          const LevelC *lc, const u32 *pmap, hipStream_t st);

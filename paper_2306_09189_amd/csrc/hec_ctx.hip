@@ -415,7 +415,7 @@ void ct_free(hec_ct *p)
 void pt_free(hec_pt *p)
 {
     if (!p) return;
-    p->ctx->release(p->d);
+    if (!p->borrowed) p->ctx->release(p->d);
     delete p;
 }
 extern "C" void hec_ct_free(hec_ct *ct) { ct_free(ct); }

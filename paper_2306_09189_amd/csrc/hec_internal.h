@@ -118,6 +118,7 @@ struct hec_pt {
     double scale = 1.0;
     u64 *d = nullptr;  // [level+1 (+k)][n], NTT form, Montgomery; q_0..q_level then (optionally) p_0..p_{k-1}
     bool has_p = false;
+    bool borrowed = false;  // d points into memory owned elsewhere (not released with the plaintext)
 };
 
 struct hec_image {
@@ -188,8 +189,10 @@ Layout natural_layout(uint32_t N, uint32_t C, uint32_t H, uint32_t W, uint32_t m
 // rotation steps of 2x2 pooling (select: the downsampling of a strided convolution) at `level`
 void pool_steps(const Layout &L, bool select, uint32_t level, std::set<int32_t> &steps);
 // convolution plan for an image of layout `lay` at `level` (what he_conv2d_plan_create builds from an image)
+// basis > 0: weight plaintexts in basis-mask form with the masks encoded at 2^basis
 hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t level, const double *w, uint32_t Co, uint32_t kh,
-                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only = false);
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only = false,
+                            uint32_t basis = 0);
 // output layout of a plan (before the downsampling of a strided one)
 const Layout &conv_plan_out(const hec_conv_plan *p);
 // in + the per-channel bias (new handles in out)

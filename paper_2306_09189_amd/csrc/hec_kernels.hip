@@ -113,13 +113,32 @@ DEV u64 redc(u64 hi, u64 lo, u64 q, u64 qinv_neg)
     u64 r = hi + __umul64hi(m, q) + (lo != 0 ? 1 : 0);
     return r >= q ? r - q : r;
 }
-DEV u64 mont_mul(u64 a, u64 bm, u64 q, u64 qinv_neg) { return redc(__umul64hi(a, bm), a * bm, q, qinv_neg); }
+// 64 x 64 -> 128 bits from four 32 x 32 -> 64 products, each partial sum
+// folded into the next product's addend (no carry is lost: a 32 x 32 product
+// plus two 32-bit addends stays below 2^64).  The separate a * b and
+// __umul64hi(a, b) would take six multiplies.
+DEV void mul128(u64 a, u64 b, u64 &lo, u64 &hi)
+{
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 t = (u64)a0 * b1 + (p00 >> 32);
+    const u64 t2 = (u64)a1 * b0 + (u32)t;
+    lo = (u64)(u32)p00 | (t2 << 32);
+    hi = (u64)a1 * b1 + (t >> 32) + (t2 >> 32);
+}
+DEV u64 mont_mul(u64 a, u64 bm, u64 q, u64 qinv_neg)
+{
+    u64 lo, hi;
+    mul128(a, bm, lo, hi);
+    return redc(hi, lo, q, qinv_neg);
+}
 struct acc128 {
     u64 lo, hi;
 };
 DEV void mac(acc128 &acc, u64 a, u64 b)
 {
-    u64 lo = a * b, hi = __umul64hi(a, b);
+    u64 lo, hi;
+    mul128(a, b, lo, hi);
     acc.lo += lo;
     acc.hi += hi + (acc.lo < lo ? 1 : 0);
 }
@@ -847,8 +866,49 @@ DEV u64x2 ld2(const u64 *p) { return *(const u64x2 *)p; }
 DEV u64x2 ld2_stream(const u64 *p) { return __builtin_nontemporal_load((const u64x2 *)p); }
 DEV void st2(u64 *p, u64x2 v) { *(u64x2 *)p = v; }
 
-template <int BETA, int NOUT>
-__global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
+// Basis-mask plaintexts: the basis polynomials of term t at (limb o, offset k)
+// are loaded once per term; a (term, output) plaintext value is then
+// sum_b W[b][o] * E_b (both Montgomery form, < HEC_BASIS_NB q^2) reduced once,
+// which is the Montgomery form of sum_b w_b * E_b mod q.
+DEV void basis_load1(const BasisArg &ba, u32 t, u32 o, u32 k, size_t n, u64 *eb)
+{
+    const u64 *Et = ba.E + ((size_t)ba.tap[t] * ba.nb * ba.nqp + o) * n + k;
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++) eb[b] = b < ba.nb ? Et[(size_t)b * ba.nqp * n] : 0;
+}
+DEV void basis_load2(const BasisArg &ba, u32 t, u32 o, u32 k, size_t n, u64x2 *eb)
+{
+    const u64 *Et = ba.E + ((size_t)ba.tap[t] * ba.nb * ba.nqp + o) * n + k;
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++) eb[b] = b < ba.nb ? ld2(Et + (size_t)b * ba.nqp * n) : u64x2{0, 0};
+}
+DEV u64 basis_pt1(const u64 *W, const u64 *eb, const BasisArg &ba, u32 o, const PrimeC &pc)
+{
+    acc128 a = {0, 0};
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++)
+        if (b < ba.nb) mac(a, eb[b], W[(size_t)b * ba.nqp + o]);
+    return redc(a.hi, a.lo, pc.q, pc.qinv_neg);
+}
+DEV u64x2 basis_pt2(const u64 *W, const u64x2 *eb, const BasisArg &ba, u32 o, const PrimeC &pc)
+{
+    acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++)
+        if (b < ba.nb) {
+            const u64 w = W[(size_t)b * ba.nqp + o];
+            mac(a0, eb[b].x, w);
+            mac(a1, eb[b].y, w);
+        }
+    return u64x2{redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), redc(a1.hi, a1.lo, pc.q, pc.qinv_neg)};
+}
+
+// one output per workgroup with plaintexts as given: at most 96 registers,
+// five waves per SIMD (the kernel is bound by its key stream and needs the
+// waves to cover latency)
+template <int BETA, int NOUT, bool BASIS>
+__global__ void __launch_bounds__(EW_THREADS) __attribute__((amdgpu_waves_per_eu(NOUT == 1 && !BASIS ? 5 : 4)))
+k_ks_mac(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
                                                        u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
                                                        u32 first, u32 nchunks, u32 ngroups, DevTables T)
 {
@@ -879,11 +939,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
             const u64x2 c0 = ld2(ct + (size_t)o * n + k), c1 = ld2(ct + ((size_t)nq + o) * n + k);
             const u64 e00 = mont_mul(c0.x, pmo, pc.q, pc.qinv_neg), e01 = mont_mul(c0.y, pmo, pc.q, pc.qinv_neg);
             const u64 e10 = mont_mul(c1.x, pmo, pc.q, pc.qinv_neg), e11 = mont_mul(c1.y, pmo, pc.q, pc.qinv_neg);
+            u64x2 eb[HEC_BASIS_NB];
+            if (BASIS) basis_load2(ba, t, o, k, n, eb);
 #pragma unroll
             for (int v = 0; v < NOUT; v++) {
                 const u64 *pt = b.pt[t][vb + v];
                 if (!pt) continue;
-                const u64x2 m = ld2(pt + (size_t)o * n + k);
+                const u64x2 m = BASIS ? basis_pt2(pt, eb, ba, o, pc) : ld2(pt + (size_t)o * n + k);
                 mac(acc[v][0][0], e00, m.x);
                 mac(acc[v][0][1], e01, m.y);
                 mac(acc[v][1][0], e10, m.x);
@@ -899,10 +961,20 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
         // loads below (addresses always valid; unused values are ignored)
         const u64x2 c = ld2(ct + (size_t)(isq ? o : 0) * n + sb);
         u64x2 m[NOUT];
+        if (BASIS) {
+            u64x2 eb[HEC_BASIS_NB];
+            basis_load2(ba, t, o, k, n, eb);
 #pragma unroll
-        for (int v = 0; v < NOUT; v++) {
-            const u64 *pt = b.pt[t][vb + v];
-            m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
+            for (int v = 0; v < NOUT; v++) {
+                const u64 *W = b.pt[t][vb + v];
+                m[v] = W ? basis_pt2(W, eb, ba, o, pc) : u64x2{0, 0};
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NOUT; v++) {
+                const u64 *pt = b.pt[t][vb + v];
+                m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
+            }
         }
         acc128 a00 = {0, 0}, a01 = {0, 0}, a10 = {0, 0}, a11 = {0, 0};  // [poly][coefficient]
 #pragma unroll
@@ -956,8 +1028,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac(KsMacBatch b, u32 nz, u32
 // of a term is computed once for that many outputs; output groups of the same
 // (limb, chunk) are neighbours and share the key and digit reads through L2.
 #define KSW_OUT 8
-template <int BETA>
-__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
+template <int BETA, bool BASIS>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
                                                          u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
                                                          u32 first, u32 nchunks, u32 ngroups, u32 per, u32 nout,
                                                          DevTables T)
@@ -984,12 +1056,14 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u
             const u64 *ct = b.ct[t];
             const u64 e0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
             const u64 e1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
+            u64 eb[HEC_BASIS_NB];
+            if (BASIS) basis_load1(ba, t, o, k, n, eb);
 #pragma unroll
             for (u32 v = 0; v < KSW_OUT; v++) {
                 if (v >= nv) break;
                 const u64 *pt = b.pt[t][vb + v];
                 if (!pt) continue;
-                const u64 m = pt[(size_t)o * n + k];
+                const u64 m = BASIS ? basis_pt1(pt, eb, ba, o, pc) : pt[(size_t)o * n + k];
                 mac(acc[v][0], e0, m);
                 mac(acc[v][1], e1, m);
             }
@@ -999,10 +1073,20 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u
         const u64 *key = b.key[t], *D = b.D[t], *ct = b.ct[t];
         const u64 c = ct[(size_t)(isq ? o : 0) * n + src];
         u64 m[KSW_OUT];
+        if (BASIS) {
+            u64 eb[HEC_BASIS_NB];
+            basis_load1(ba, t, o, k, n, eb);
 #pragma unroll
-        for (u32 v = 0; v < KSW_OUT; v++) {
-            const u64 *pt = v < nv ? b.pt[t][vb + v] : nullptr;
-            m[v] = pt ? __builtin_nontemporal_load(pt + (size_t)o * n + k) : 0;
+            for (u32 v = 0; v < KSW_OUT; v++) {
+                const u64 *W = v < nv ? b.pt[t][vb + v] : nullptr;
+                m[v] = W ? basis_pt1(W, eb, ba, o, pc) : 0;
+            }
+        } else {
+#pragma unroll
+            for (u32 v = 0; v < KSW_OUT; v++) {
+                const u64 *pt = v < nv ? b.pt[t][vb + v] : nullptr;
+                m[v] = pt ? __builtin_nontemporal_load(pt + (size_t)o * n + k) : 0;
+            }
         }
         acc128 a0 = {0, 0}, a1 = {0, 0};
 #pragma unroll
@@ -1037,28 +1121,36 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u
 }
 
 template <int BETA>
-static void ks_mac_w_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms,
-                            u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
-                            u32 nchunks, u32 ngroups, u32 per, u32 nout, const DevTables &T)
+static void ks_mac_w_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
+                            u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
+                            u32 first, u32 nchunks, u32 ngroups, u32 per, u32 nout, const DevTables &T)
 {
-    KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp, pmap,
-            pm, NLK, first, nchunks, ngroups, per, nout, T);
+    if (ba)
+        KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA, true>), g, dim3(EW_THREADS), 0, st, b, *ba, nz, nterms, beta,
+                nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
+    else
+        KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA, false>), g, dim3(EW_THREADS), 0, st, b, BasisArg{}, nz, nterms,
+                beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
 }
 
 template <int BETA, int NOUT>
-static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
-                          u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
-                          u32 ngroups, const DevTables &T)
+static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
+                          u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
+                          u32 nchunks, u32 ngroups, const DevTables &T)
 {
-    KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp,
-            pmap, pm, NLK, first, nchunks, ngroups, T);
+    if (ba)
+        KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT, true>), g, dim3(EW_THREADS), 0, st, b, *ba, nz, nterms,
+                beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+    else
+        KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT, false>), g, dim3(EW_THREADS), 0, st, b, BasisArg{}, nz,
+                nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
 }
 template <int NOUT>
-static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
-                        u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
-                        u32 ngroups, const DevTables &T)
+static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
+                        u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
+                        u32 nchunks, u32 ngroups, const DevTables &T)
 {
-#define KSM_ARGS g, units, st, b, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
+#define KSM_ARGS g, units, st, b, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
     switch (beta) {
     case 1: ks_mac_launch<1, NOUT>(KSM_ARGS); break;
     case 2: ks_mac_launch<2, NOUT>(KSM_ARGS); break;
@@ -1073,9 +1165,10 @@ static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch
 // the input ciphertext of each distinct input once per launch (the output
 // groups re-read them from L2).
 bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
-                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st)
+                const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st, const BasisArg *ba)
 {
     if (nterms < 0 || nterms > HEC_KS_BATCH || nout < 1 || nout > HEC_MAC_OUT) return false;
+    if (ba && (!ba->E || ba->nb < 1 || ba->nb > HEC_BASIS_NB || (int)ba->nqp != nqp)) return false;
     u32 nz = 0;
     while ((int)nz < nterms && b.g[nz] == 1) nz++;
     for (int t = 0; t < nterms; t++) {
@@ -1092,8 +1185,14 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
         if (new_ct) units += (uint64_t)nq * (t < (int)nz ? 2 : 1);
         if (new_d) units += (uint64_t)beta * nqp;
         if (t >= (int)nz) units += 2ull * beta * nqp;
-        for (int v = 0; v < nout; v++)
-            if (b.pt[t][v]) units += t >= (int)nz ? nqp : nq;
+        if (ba) {
+            bool new_tap = true;
+            for (int s = 0; s < t; s++) new_tap &= ba->tap[s] != ba->tap[t];
+            if (new_tap) units += (uint64_t)ba->nb * (t >= (int)nz ? nqp : nq);
+        } else {
+            for (int v = 0; v < nout; v++)
+                if (b.pt[t][v]) units += t >= (int)nz ? nqp : nq;
+        }
     }
     for (int v = 0; v < nout; v++) units += ((first >> v) & 1) ? 2ull * nqp : 4ull * nqp;
     KsMacBatch bb = b;
@@ -1106,7 +1205,7 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
         const u32 ng = ((u32)nout + KSW_OUT - 1) / KSW_OUT, per = ((u32)nout + ng - 1) / ng;
         const u32 nch = (T.n + EW_THREADS - 1) / EW_THREADS;
         dim3 g(nch * (u32)nqp * ng);
-#define KSW_ARGS g, units, st, bb, nz, (u32)nterms, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first, \
+#define KSW_ARGS g, units, st, bb, ba, nz, (u32)nterms, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first, \
                  nch, ng, per, (u32)nout, T
         switch (beta) {
         case 1: ks_mac_w_launch<1>(KSW_ARGS); break;
@@ -1124,9 +1223,9 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
     const u32 ngroups = 1;
     dim3 g(nchunks * (u32)nqp * ngroups);
     if (per == 1)
-        ks_mac_beta<1>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+        ks_mac_beta<1>(g, units, st, bb, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     else
-        ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+        ks_mac_beta<2>(g, units, st, bb, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     return true;
 }
 
@@ -1134,8 +1233,9 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
 // products of all terms for up to HEC_MAC_OUTS outputs accumulated in 128 bits
 // (< HEC_MAC_TERMS q^2 < q 2^64) and reduced once, so every rotated input is
 // read once per group of outputs.
-__global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms, u32 nout, u32 nq, u32 first,
-                                                          DevTables T)
+template <bool BASIS>
+__global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, BasisArg ba, u32 nterms, u32 nout, u32 nq,
+                                                          u32 first, DevTables T)
 {
     const u32 o = blockIdx.y;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
@@ -1148,11 +1248,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms
     for (u32 t = 0; t < nterms; t++) {
         const u64 *ct = b.ct[t];
         const u64 c0 = ct[off], c1 = ct[(size_t)nq * n + off];
+        u64 eb[HEC_BASIS_NB];
+        if (BASIS) basis_load1(ba, t, o, (u32)k, n, eb);
 #pragma unroll
         for (int v = 0; v < HEC_MAC_OUTS; v++) {
             const u64 *pt = b.pt[t][v];
             if (!pt) continue;
-            const u64 m = pt[off];
+            const u64 m = BASIS ? basis_pt1(pt, eb, ba, o, pc) : pt[off];
             mac(acc[v][0], c0, m);
             mac(acc[v][1], c1, m);
         }
@@ -1170,12 +1272,19 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms
         }
     }
 }
-void hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st)
+bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st,
+                   const BasisArg *ba)
 {
-    if (nterms <= 0 || nout <= 0) return;
+    if (nterms <= 0 || nterms > HEC_MAC_TERMS || nout <= 0 || nout > HEC_MAC_OUTS) return false;
+    if (ba && (!ba->E || ba->nb < 1 || ba->nb > HEC_BASIS_NB || (int)ba->nqp < nq)) return false;
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
-    KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms, g, dim3(EW_THREADS), 0, st, b, (u32)nterms, (u32)nout,
-            (u32)nq, (u32)first, T);
+    if (ba)
+        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms<true>, g, dim3(EW_THREADS), 0, st, b, *ba,
+                (u32)nterms, (u32)nout, (u32)nq, (u32)first, T);
+    else
+        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms<false>, g, dim3(EW_THREADS), 0, st, b, BasisArg{},
+                (u32)nterms, (u32)nout, (u32)nq, (u32)first, T);
+    return true;
 }
 
 // ModDown tail: out_p[i] = (e_p[i] - y_p[i]) * P^-1 (+ sigma_g(c0)[i] for p = 0)

@@ -207,6 +207,10 @@ struct ConvItem {
     int32_t amount;
     int32_t baby, giant;  // amount = baby + giant (mod N): block offset r*B (0 for channel shards), tap offset
     std::vector<std::pair<uint32_t, std::vector<double>>> pts;  // output shard -> slot vector
+    // image shards: the tap (kr * kw + kc) and, per entry of pts, its nonzero
+    // block weights (block, weight): the slot vector is weight * tap mask per block
+    int32_t tap = -1;
+    std::vector<std::vector<std::pair<uint32_t, double>>> bw;
 };
 
 // Offsets r with, per needed output block b, the input channel lam[b+r] it
@@ -299,9 +303,10 @@ static hec_status conv_items(const Layout &L, const double *w, uint32_t Co, uint
                     it.amount = (int32_t)a;
                     it.baby = (int32_t)(((int64_t)r * B) % (int64_t)N);
                     it.giant = (int32_t)gi;
+                    it.tap = (int32_t)(kr * kw + kc);
                     for (uint32_t v = 0; v < out.maps.size(); v++) {
                         std::vector<double> vec(N, 0.0);
-                        bool nz = false;
+                        std::vector<std::pair<uint32_t, double>> bw;
                         for (auto &bf : ro.second) {
                             int32_t g = out.maps[v][bf.first];
                             if (g < 0) continue;
@@ -309,9 +314,12 @@ static hec_status conv_items(const Layout &L, const double *w, uint32_t Co, uint
                             if (wv == 0.0) continue;
                             double *dst = &vec[(size_t)bf.first * B];
                             for (uint32_t e = 0; e < B; e++) dst[e] = wv * mask[e];
-                            nz = true;
+                            bw.push_back({bf.first, wv});
                         }
-                        if (nz) it.pts.emplace_back(v, std::move(vec));
+                        if (!bw.empty()) {
+                            it.pts.emplace_back(v, std::move(vec));
+                            it.bw.push_back(std::move(bw));
+                        }
                     }
                     if (!it.pts.empty()) plan[u].push_back(std::move(it));
                 }
@@ -452,6 +460,7 @@ static std::string layout_key(const Layout &L, int part)
 struct RotTerm {
     int32_t amount = 0;
     std::vector<std::pair<uint32_t, hec_pt *>> pts;
+    int32_t tap = -1;  // basis-mask plans: the tap whose basis polynomials the weight rows of pts combine
 };
 
 // cached mask plaintexts (they only depend on the layout, shard part, index, level and scale)
@@ -541,9 +550,10 @@ static hec_status masked_sum(hec_ctx *c, const std::vector<hec_ct *> &rots, cons
 // out[v] (allocated here, at the inputs' level, not rescaled) = sum over input
 // u and its terms of pt * rot(in[u], amount).  Plaintexts carry the limbs of
 // the special primes.
+// bt (nullable): the plaintexts are weight rows of a basis-mask plan (E, nb, nqp set; taps from the terms)
 static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> &in,
                                   const std::vector<std::vector<RotTerm>> &terms_of, size_t nout,
-                                  std::vector<hec_ct *> &out)
+                                  std::vector<hec_ct *> &out, const BasisArg *bt = nullptr)
 {
     out.assign(nout, nullptr);
     if (in.empty() || in.size() != terms_of.size()) HEC_FAIL(HEC_EINVAL, "lazy sum: inputs and terms differ");
@@ -595,6 +605,7 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
             for (size_t b0 = 0; b0 < terms.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
                 const size_t nt = std::min((size_t)HEC_KS_BATCH, terms.size() - b0);
                 KsMacBatch b{};
+                BasisArg ba = bt ? *bt : BasisArg{};
                 int first = 0;
                 for (size_t j = 0; j < nv; j++) {
                     b.E[j] = Eall + (v0 + j) * 2 * (size_t)nqp * n;
@@ -608,6 +619,14 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                     b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
                     b.D[t] = D;
                     b.ct[t] = ct->d;
+                    if (bt) {
+                        if (it.tap < 0) {
+                            s = HEC_EINVAL;
+                            hec_set_error("basis-mask term without a tap");
+                            break;
+                        }
+                        ba.tap[t] = (u32)it.tap;
+                    }
                     for (auto &pp : it.pts) {
                         if (pp.first < v0 || pp.first >= v0 + nv) continue;
                         if (!pp.second->has_p || pp.second->level != lvl) {
@@ -622,7 +641,7 @@ static hec_status lazy_rotate_mac(hec_ctx *c, const std::vector<const hec_ct *> 
                 }
                 if (s != HEC_OK) break;
                 if (!hec_ks_mac(c->T, b, (int)nt, (int)nv, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl),
-                                c->d_pmodq_m, (int)c->NLK, first, c->st)) {
+                                c->d_pmodq_m, (int)c->NLK, first, c->st, bt ? &ba : nullptr)) {
                     s = HEC_EINVAL;
                     hec_set_error("invalid key-switch batch");
                 }
@@ -1180,6 +1199,11 @@ struct hec_conv_plan {
     uint32_t level = 0, stride = 1;
     int mode = 0;
     bool q_only = false;  // weight plaintexts over Q only: modes 0 and 1
+    // basis-mask form (basis = s > 0): the plaintexts of items are borrowed
+    // handles on weight rows of Wt ([nb][nqp] Montgomery residues of
+    // round(w_b q_l / 2^s) per block), E the tap masks per block at 2^s
+    uint32_t basis = 0, nbasis = 0;
+    u64 *E = nullptr, *Wt = nullptr;
     typedef RotTerm Item;
     std::vector<std::vector<Item>> items;  // per input shard
     std::set<int32_t> steps;
@@ -1201,6 +1225,8 @@ extern "C" void he_conv2d_plan_free(hec_conv_plan *p)
         for (auto &v : *set)
             for (auto &it : v)
                 for (auto &pp : it.pts) pt_free(pp.second);
+    p->ctx->release(p->E);
+    p->ctx->release(p->Wt);
     delete p;
 }
 
@@ -1284,18 +1310,94 @@ extern "C" hec_status he_conv2d_plan_create_ex(hec_ctx *c, const hec_image *like
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !like || !w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
-    if (flags & ~(uint32_t)HEC_PLAN_Q_ONLY) HEC_FAIL(HEC_EINVAL, "unknown plan flags");
+    if (flags & ~(uint32_t)(HEC_PLAN_Q_ONLY | HEC_PLAN_BASIS | HEC_PLAN_BASIS_SCALE(0xffu)))
+        HEC_FAIL(HEC_EINVAL, "unknown plan flags");
+    const uint32_t bs = (flags >> 8) & 0xffu;
+    if ((flags & HEC_PLAN_BASIS) && (bs < 1 || bs > 50))
+        HEC_FAIL(HEC_EINVAL, "basis-mask plan needs a mask scale 2^s with 1 <= s <= 50");
+    if (!(flags & HEC_PLAN_BASIS) && bs) HEC_FAIL(HEC_EINVAL, "mask scale without HEC_PLAN_BASIS");
+    if ((flags & HEC_PLAN_BASIS) && (flags & HEC_PLAN_Q_ONLY))
+        HEC_FAIL(HEC_EINVAL, "HEC_PLAN_BASIS and HEC_PLAN_Q_ONLY exclude each other");
     if (like->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     const uint32_t lvl = like->shards[0]->level;
     for (auto *s : like->shards)
         if (s->level != lvl) HEC_FAIL(HEC_ELEVEL, "shards at different levels");
-    return conv_plan_create(c, like->lay, lvl, w, Co, kh, kw, stride, pad, out, (flags & HEC_PLAN_Q_ONLY) != 0);
+    return conv_plan_create(c, like->lay, lvl, w, Co, kh, kw, stride, pad, out, (flags & HEC_PLAN_Q_ONLY) != 0,
+                            (flags & HEC_PLAN_BASIS) ? bs : 0);
+}
+
+// The basis-mask form of a plan's weight plaintexts: per tap and block the
+// mask of the tap restricted to the block, encoded at 2^s over Q_l and P
+// (E, [taps][nb][nqp][n]); per (item, output) a weight row of nb * nqp
+// Montgomery residues of round_half_away(w_b * q_l / 2^s) (0 for blocks
+// without a weight); each item's plaintexts become borrowed handles on their
+// rows.  sum_b round(w_b q_l / 2^s) * E_b is then the plaintext, exactly.
+static hec_status build_basis(hec_ctx *c, hec_conv_plan *p, const std::vector<std::vector<ConvItem>> &items,
+                              uint32_t s)
+{
+    const Layout &L = p->in;
+    const uint32_t lvl = p->level, N = c->N, B = L.B(), nb = L.nb(), ntap = p->kh * p->kw;
+    const uint32_t nq = lvl + 1, nqp = nq + c->k;
+    const size_t n = c->n;
+    const int Ho = (int)L.H + 2 * (int)p->pad - (int)p->kh + 1, Wo = (int)L.W + 2 * (int)p->pad - (int)p->kw + 1;
+    // basis polynomials
+    std::vector<std::vector<double>> zs;
+    std::vector<const double *> zp;
+    std::vector<double> mask;
+    for (uint32_t t = 0; t < ntap; t++) {
+        bool any;
+        tap_mask(L, Ho, Wo, (int)(t / p->kw) - (int)p->pad, (int)(t % p->kw) - (int)p->pad, mask, any);
+        for (uint32_t b = 0; b < nb; b++) {
+            std::vector<double> z(N, 0.0);
+            std::copy(mask.begin(), mask.begin() + B, z.begin() + (size_t)b * B);
+            zs.push_back(std::move(z));
+        }
+    }
+    for (auto &z : zs) zp.push_back(z.data());
+    std::vector<hec_pt *> bp;
+    HEC_CHECK(pt_encode_many(c, zp, N, lvl, std::ldexp(1.0, (int)s), bp, true));
+    p->E = c->alloc(zs.size() * nqp * n);
+    hec_status st = p->E ? HEC_OK : HEC_ENOMEM;
+    for (size_t i = 0; i < bp.size() && st == HEC_OK; i++)
+        if (hipMemcpyAsync(p->E + i * nqp * n, bp[i]->d, nqp * n * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+            st = HEC_EDEVICE;
+    for (auto *q : bp) pt_free(q);
+    if (st != HEC_OK) HEC_FAIL(st, "basis polynomial storage");
+    // weight rows
+    std::vector<u64> primes(nqp);
+    for (uint32_t i = 0; i < nqp; i++) primes[i] = c->mod[i < nq ? i : c->L + 1 + (i - nq)];
+    const double wscale = (double)c->mod[lvl] / std::ldexp(1.0, (int)s);
+    size_t rows = 0;
+    for (auto &v : items)
+        for (auto &it : v) rows += it.pts.size();
+    std::vector<u64> hw(rows * nb * nqp, 0);
+    size_t r = 0;
+    for (auto &v : items)
+        for (auto &it : v)
+            for (size_t e = 0; e < it.pts.size(); e++, r++)
+                for (auto &bw : it.bw[e]) {
+                    int64_t wh;
+                    HEC_CHECK(const_coeff(bw.second, wscale, &wh));
+                    for (uint32_t i = 0; i < nqp; i++) {
+                        const u64 q = primes[i], mag = (u64)(wh < 0 ? -wh : wh) % q;
+                        const u64 res = wh < 0 && mag ? q - mag : mag;
+                        hw[((size_t)r * nb + bw.first) * nqp + i] = (u64)(((hec::u128)res << 64) % q);
+                    }
+                }
+    p->Wt = c->alloc(hw.size());
+    if (!p->Wt) HEC_FAIL(HEC_ENOMEM, "weight rows");
+    HEC_TRY_HIP(hipMemcpyAsync(p->Wt, hw.data(), hw.size() * 8, hipMemcpyHostToDevice, c->st));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    p->basis = s;
+    p->nbasis = nb;
+    return HEC_OK;
 }
 
 const Layout &conv_plan_out(const hec_conv_plan *p) { return p->out; }
 
 hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const double *w, uint32_t Co, uint32_t kh,
-                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only)
+                            uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out, bool q_only,
+                            uint32_t basis)
 {
     *out = nullptr;
     if (!w || !Co || !kh || !kw) HEC_FAIL(HEC_EINVAL, "bad convolution arguments");
@@ -1313,31 +1415,58 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
     if (lay.channel) HEC_CHECK(conv_items_channel(lay, w, Co, kh, kw, pad, p->out, items));
     else HEC_CHECK(conv_items(lay, w, Co, kh, kw, pad, p->out, items));
     p->items.resize(items.size());
-    std::vector<const double *> zp;
-    for (auto &v : items)
-        for (auto &it : v)
-            for (auto &pp : it.pts) zp.push_back(pp.second.data());
+    p->w.assign(w, w + (size_t)Co * lay.C * kh * kw);
+    p->Co = Co;
+    p->kh = kh;
+    p->kw = kw;
+    p->pad = pad;
     std::vector<hec_pt *> pts;
-    // limbs over Q_l and P: the lazy-ModDown mode multiplies before ModDown (over Q_l only for a plan that
-    // runs per rotation, a quarter less memory)
     p->q_only = q_only;
-    HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts, !q_only));
+    if (basis) {
+        if (lay.channel) HEC_FAIL(HEC_ELAYOUT, "basis-mask plaintexts need an image-sharded input");
+        if (lay.nb() > HEC_BASIS_NB)
+            HEC_FAIL(HEC_ELAYOUT, "basis-mask plaintexts take at most %d blocks per shard (layout has %u)",
+                     HEC_BASIS_NB, lay.nb());
+        if (hec_status bs = build_basis(c, p.get(), items, basis)) {
+            c->release(p->E);
+            c->release(p->Wt);
+            return bs;
+        }
+        const uint32_t nqp = lvl + 1 + c->k;
+        size_t r = 0;
+        for (auto &v : items)
+            for (auto &it : v)
+                for (size_t e = 0; e < it.pts.size(); e++, r++) {
+                    hec_pt *h = new hec_pt();
+                    h->ctx = c;
+                    h->level = lvl;
+                    h->scale = (double)c->mod[lvl];
+                    h->d = p->Wt + r * p->nbasis * nqp;
+                    h->has_p = true;
+                    h->borrowed = true;
+                    pts.push_back(h);
+                }
+    } else {
+        std::vector<const double *> zp;
+        for (auto &v : items)
+            for (auto &it : v)
+                for (auto &pp : it.pts) zp.push_back(pp.second.data());
+        // limbs over Q_l and P: the lazy-ModDown mode multiplies before ModDown (over Q_l only for a plan that
+        // runs per rotation, a quarter less memory)
+        HEC_CHECK(pt_encode_many(c, zp, c->N, lvl, (double)c->mod[lvl], pts, !q_only));
+    }
     size_t q = 0;
     for (size_t u = 0; u < items.size(); u++)
         for (auto &it : items[u]) {
             hec_conv_plan::Item pi;
             pi.amount = it.amount;
+            pi.tap = basis ? it.tap : -1;
             for (auto &pp : it.pts) pi.pts.push_back({pp.first, pts[q++]});
             // keys for every mode: the amounts, and their baby and giant parts
             for (int32_t a : {it.amount, it.baby, it.giant})
                 if (a % (int32_t)c->N) p->steps.insert(a);
             p->items[u].push_back(std::move(pi));
         }
-    p->w.assign(w, w + (size_t)Co * lay.C * kh * kw);
-    p->Co = Co;
-    p->kh = kh;
-    p->kw = kw;
-    p->pad = pad;
     if (stride == 2) {
         Layout o = p->out;
         pool_steps(o, true, lvl - 1, p->steps);
@@ -1350,6 +1479,7 @@ extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
     if (!p || mode < 0 || mode > 3) HEC_FAIL(HEC_EINVAL, "bad mode");
     if (p->q_only && mode >= 2) HEC_FAIL(HEC_EINVAL, "plan without special-prime limbs runs in modes 0 and 1 only");
+    if (p->basis && mode == 3) HEC_FAIL(HEC_EINVAL, "basis-mask plan runs in modes 0, 1 and 2");
     if (mode == 3) {
         HEC_TRY_HIP(hipSetDevice(p->ctx->dev));
         HEC_CHECK(build_bsgs(p->ctx, p));
@@ -1375,7 +1505,7 @@ extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *step
 // one launch each; first[v] set: output v not written yet (cleared here)
 static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots,
                                 const std::vector<hec_conv_plan::Item> &its, size_t i0, std::vector<hec_ct *> &acc,
-                                std::vector<char> &first)
+                                std::vector<char> &first, const BasisArg *bt)
 {
     const size_t nout = acc.size(), cnt = rots.size();
     const uint32_t lvl = rots[0]->level;
@@ -1388,9 +1518,14 @@ static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots,
         for (size_t t0 = 0; t0 < cnt; t0 += HEC_MAC_TERMS) {
             const size_t nt = std::min((size_t)HEC_MAC_TERMS, cnt - t0);
             MacBatch b{};
+            BasisArg ba = bt ? *bt : BasisArg{};
             bool any = false;
             for (size_t t = 0; t < nt; t++) {
                 b.ct[t] = rots[t0 + t]->d;
+                if (bt) {
+                    if (its[i0 + t0 + t].tap < 0) HEC_FAIL(HEC_EINVAL, "basis-mask term without a tap");
+                    ba.tap[t] = (u32)its[i0 + t0 + t].tap;
+                }
                 for (auto &pp : its[i0 + t0 + t].pts)
                     if (pp.first >= v0 && pp.first < v0 + nv) {
                         b.pt[t][pp.first - v0] = pp.second->d;
@@ -1414,7 +1549,8 @@ static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots,
                         }
                 }
             }
-            hec_mac_terms(c->T, b, (int)nt, (int)nv, (int)lvl + 1, fbits, c->st);
+            if (!hec_mac_terms(c->T, b, (int)nt, (int)nv, (int)lvl + 1, fbits, c->st, bt ? &ba : nullptr))
+                HEC_FAIL(HEC_EINVAL, "invalid plaintext-product batch");
         }
     }
     return HEC_OK;
@@ -1441,9 +1577,16 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
     }
     hec_status s = HEC_OK;
     std::vector<const hec_ct *> ins(in->shards.begin(), in->shards.end());
+    BasisArg bt{};
+    if (p->basis) {
+        bt.E = p->E;
+        bt.nb = p->nbasis;
+        bt.nqp = p->level + 1 + c->k;
+    }
+    const BasisArg *btp = p->basis ? &bt : nullptr;
     if (p->mode == 2) {
         free_all(acc);
-        s = lazy_rotate_mac(c, ins, p->items, nout, acc);
+        s = lazy_rotate_mac(c, ins, p->items, nout, acc, btp);
         std::fill(first.begin(), first.end(), 0);
     } else if (p->mode == 3) {
         // baby steps: T_k = sum of pt'' * rot_baby(ct_u) (one ModDown per k);
@@ -1464,7 +1607,7 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
             } else {
                 for (size_t t = 0; t < cnt && s == HEC_OK; t++) s = ckks_rotate(c, in->shards[u], st[t], &rots[t]);
             }
-            if (s == HEC_OK) s = mac_rotations(c, rots, its, i0, acc, first);
+            if (s == HEC_OK) s = mac_rotations(c, rots, its, i0, acc, first, btp);
             free_all(rots);
         }
     }

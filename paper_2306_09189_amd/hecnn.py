@@ -494,13 +494,15 @@ class Context:
                                       ctypes.byref(out)))
         return Image(self, out.value)
 
-    def conv2d_plan(self, like, w, stride=1, pad=1, q_only=False):
-        """q_only: weight plaintexts over Q only (modes 0 and 1), for layers too large otherwise."""
+    def conv2d_plan(self, like, w, stride=1, pad=1, q_only=False, basis=None):
+        """q_only: weight plaintexts over Q only (modes 0 and 1), for layers too large otherwise.
+        basis = s: weight plaintexts in basis-mask form, tap masks per block encoded at 2^s (modes 0-2)."""
         w = _arr(w, np.float64)
         Co, Ci, kh, kw = w.shape
         out = vp()
-        if q_only:
-            check(lib().he_conv2d_plan_create_ex(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, 1,
+        flags = (1 if q_only else 0) | ((2 | (int(basis) << 8)) if basis is not None else 0)
+        if flags:
+            check(lib().he_conv2d_plan_create_ex(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad, flags,
                                                  ctypes.byref(out)))
         else:
             check(lib().he_conv2d_plan_create(self.h, like.h, _p(w, dblp), Co, kh, kw, stride, pad,

@@ -2,7 +2,8 @@
 3x3 conv 64 -> 64 over 32 image shards of two padded 128x128 channels, then
 2x2 average pooling.  Its 18432 weight plaintexts are kept over Q only
 (193 GiB); the pooling runs per rotation and by baby and giant steps;
-decryption within 1e-5 of FP64."""
+decryption within 1e-5 of FP64.  The same layer with its plaintexts in
+basis-mask form (lazy ModDown and batched)."""
 import ctypes
 import gc
 import sys
@@ -65,3 +66,40 @@ def test_imagenet_layer_full():
         log("max abs err %.3g" % err)
         assert err < 1e-5
         del z
+
+
+def test_imagenet_layer_basis():
+    """The same layer with its weight plaintexts in basis-mask form (18 tap
+    masks per block encoded at 2^28 over Q and P, 261 MiB, instead of 18432
+    plaintexts): lazy ModDown and batched per-rotation evaluation, both
+    decrypting within 1e-5 of FP64."""
+    from paper_2306_09189_amd import hecnn
+    gc.collect()
+    need = 64 << 30
+    if free_hbm() < need:
+        pytest.skip("needs %d GiB of free device memory, %d GiB free" % (need >> 30, free_hbm() >> 30))
+    ctx = hecnn.Context(16, 24, 60, 50, 8, 60, 3, 50, device=0)
+    ctx.keygen(2024)
+    rng = np.random.default_rng(1004)
+    x = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (64, 64, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3004)
+    t = time.perf_counter()
+    plan = ctx.conv2d_plan(img, w, basis=28)
+    ctx.sync()
+    log("basis plan: %.2f s" % (time.perf_counter() - t))
+    ctx.gen_rotation_keys(plan.steps())
+    ref = hl.ref_conv2d(x, w, 1)
+    for mode, name in ((2, "lazy ModDown"), (0, "batched")):
+        plan.set_mode(mode)
+        y = plan.run(img)      # first run: caches and pool warm
+        ctx.sync()
+        del y
+        t = time.perf_counter()
+        y = plan.run(img)
+        ctx.sync()
+        log("conv 64->64 over 32 shards, basis-mask, %s: %.1f ms" % (name, (time.perf_counter() - t) * 1e3))
+        err = np.abs(y.decrypt() - ref).max()
+        log("max abs err %.3g" % err)
+        assert err < 1e-5
+        del y

@@ -132,14 +132,15 @@ def test_rescale_mul_add_bit_exact(small):
     assert e.value.status == hecnn.HEC_ELEVEL
 
 
-def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
+def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1, basis=None, tol=1e-5):
     """Encrypt x on both sides, apply ops ('conv', w, stride) / ('pool',),
     compare every shard bit for bit after every op; return final decryption.
-    mode 2 runs the convolutions with lazy ModDown on both sides."""
+    mode 2 runs the convolutions with lazy ModDown on both sides; basis = s
+    builds their weight plaintexts in basis-mask form on both sides."""
     C, H, W = x.shape
     img = ctx.image_encrypt(x, level, seed)
     lay = hl.natural_layout(prm.N, C, H, W)
-    be = hl.CkksBackend(o)
+    be = hl.CkksBackend(o, basis=basis)
     cts = [o.encrypt(o.encode(v, level, 2.0 ** prm_log_scale(ctx)), seed=seed, index=u)
            for u, v in enumerate(hl.pack(x, lay))]
     for u in range(len(cts)):
@@ -148,7 +149,7 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
     for op in ops:
         if op[0] == "conv":
             w, stride = op[1], op[2]
-            plan = ctx.conv2d_plan(img, w, stride=stride, pad=pad)
+            plan = ctx.conv2d_plan(img, w, stride=stride, pad=pad, basis=basis)
             plan.set_mode(mode)
             ctx.gen_rotation_keys(plan.steps())
             img = plan.run(img)
@@ -170,7 +171,7 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1):
             assert (img.shard_export(u) == cts[u].data).all(), (op[0], u)
         log("  op %s ok: %d shards, level %d" % (op[0], t, cts[0].level))
     got = img.decrypt()
-    assert np.abs(got - ref).max() < 1e-5
+    assert np.abs(got - ref).max() < tol
     return got
 
 
@@ -376,6 +377,65 @@ def test_layers_edge_shapes_bit_exact(small, shape, ops, pad, mode):
             real_ops.append(op)
     log("edge", shape, [op[0] for op in ops], "pad", pad, "mode", mode)
     run_pipeline(ctx, prm, o, x, real_ops, 6, seed=41, mode=mode, pad=pad)
+
+
+@pytest.mark.parametrize("shape,ops,mode", [
+    ((4, 16, 16), [("conv", (4, 3), 1), ("pool",)], 0),             # 2 shards of 2 blocks -> 2 outputs
+    ((4, 16, 16), [("conv", (4, 3), 1)], 1),                        # per rotation, unbatched
+    ((4, 16, 16), [("conv", (2, 3), 1)], 2),                        # lazy, one output shard
+    ((4, 16, 16), [("conv", (4, 3), 1), ("pool",)], 2),             # lazy, two outputs
+    ((4, 16, 16), [("conv", (16, 3), 1)], 2),                       # lazy, 8 outputs (wide kernel)
+    ((16, 16, 16), [("conv", (8, 3), 1)], 0),                       # 8 inputs -> 4 outputs, batched
+    ((16, 16, 16), [("conv", (8, 3), 1)], 2),
+    ((4, 16, 16), [("conv", (8, 3), 2)], 2),                        # strided
+    ((2, 32, 32), [("pool",), ("conv", (4, 3), 1)], 0),             # channel shards pooled, then basis conv
+])
+def test_basis_plan_bit_exact(small, shape, ops, mode):
+    """Weight plaintexts in basis-mask form (tap masks per block encoded at
+    2^20, weights rounded at q_l / 2^20) bit for bit with the oracle building
+    the same integer plaintexts, in the batched, plain and lazy modes.  With
+    40-bit primes the form itself is coarse: per product the weight is off by
+    up to 2^19 / q_l ~ 5e-7 and the mask by the decoded rounding of its
+    encoding, ~ sqrt(n/2) * 0.3 * 2^-20 ~ 6e-6 RMS, so the decrypted
+    convolution is held to 5e-5 instead of 1e-5 (the 50-bit primes of the
+    2^16 parameters at 2^28 meet 1e-5)."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + 300 + mode)
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("basis layers", shape, [op[0] for op in ops], mode)
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=41, mode=mode, basis=20, tol=5e-5)
+
+
+def test_basis_plan_errors(small):
+    """Basis-mask plans refuse mode 3, more than 4 blocks per shard, channel
+    shards and the Q-only flag."""
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    rng = np.random.default_rng(78)
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    img = ctx.image_encrypt(rng.uniform(-1, 1, (4, 16, 16)), 6, 78)
+    plan = ctx.conv2d_plan(img, w, basis=20)
+    with pytest.raises(hecnn.HecError):
+        plan.set_mode(3)
+    with pytest.raises(hecnn.HecError):
+        ctx.conv2d_plan(img, w, basis=20, q_only=True)
+    with pytest.raises(hecnn.HecError):
+        ctx.conv2d_plan(img, w, basis=0)
+    small_img = ctx.image_encrypt(rng.uniform(-1, 1, (4, 8, 8)), 6, 79)    # 8 blocks of 64 slots
+    with pytest.raises(hecnn.HecError):
+        ctx.conv2d_plan(small_img, w, basis=20)
+    ch_img = ctx.image_encrypt(rng.uniform(-1, 1, (1, 32, 32)), 6, 80)     # one channel in two shards
+    with pytest.raises(hecnn.HecError):
+        ctx.conv2d_plan(ch_img, rng.normal(0, 0.1, (1, 1, 3, 3)), basis=20)
 
 
 def test_q_only_plan(small):
