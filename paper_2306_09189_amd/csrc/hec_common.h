@@ -106,6 +106,7 @@ struct CombineBatch {
     u64 *out[HEC_KS_BATCH];        // [2][nq][n]
     const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
     const u64 *y[HEC_KS_BATCH];    // [2][nq][n], NTT form
+    const u64 *c0[HEC_KS_BATCH];   // this entry's own c0 (null: the launch's shared c0)
     u32 g[HEC_KS_BATCH];
 };
 

@@ -968,6 +968,77 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     return HEC_OK;
 }
 
+static void free_all_cts(std::vector<hec_ct *> &v)
+{
+    for (auto *&p : v) {
+        ct_free(p);
+        p = nullptr;
+    }
+}
+
+hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, int32_t step, std::vector<hec_ct *> &outs)
+{
+    outs.assign(cts.size(), nullptr);
+    if (cts.empty()) return HEC_OK;
+    const size_t n = c->n;
+    const uint32_t lvl = cts[0]->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    for (auto *ct : cts)
+        if (ct->level != lvl) HEC_FAIL(HEC_ELEVEL, "batched rotation of ciphertexts at different levels");
+    const uint32_t g = c->galois(step);
+    if (g == 1) {
+        for (size_t i = 0; i < cts.size(); i++)
+            if (!(outs[i] = ct_clone(cts[i]))) {
+                free_all_cts(outs);
+                HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+            }
+        return HEC_OK;
+    }
+    if (!c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", step);
+    u64 *Dall = nullptr;
+    HEC_CHECK(ct_modup_many(c, cts, &Dall));
+    hec_status s = HEC_OK;
+    for (size_t b0 = 0; b0 < cts.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
+        const int R = (int)std::min((size_t)HEC_KS_BATCH, cts.size() - b0);
+        u64 *e = c->alloc((size_t)R * 2 * nqp * n);
+        u64 *y = c->alloc((size_t)R * 2 * nq * n);
+        KsBatch kb{};
+        CombineBatch cb{};
+        for (int r = 0; r < R && e && y; r++) {
+            const size_t i = b0 + r;
+            if (!(outs[i] = ct_new(c, lvl, cts[i]->scale))) break;
+            kb.key[r] = c->rotkeys[g];
+            kb.out[r] = e + (size_t)r * 2 * nqp * n;
+            kb.D[r] = Dall + i * beta * (size_t)nqp * n;
+            kb.g[r] = g;
+            cb.out[r] = outs[i]->d;
+            cb.e[r] = kb.out[r];
+            cb.y[r] = y + (size_t)r * 2 * nq * n;
+            cb.c0[r] = cts[i]->d;
+            cb.g[r] = g;
+        }
+        bool ok = e && y;
+        for (int r = 0; r < R; r++) ok = ok && outs[b0 + r];
+        if (!ok) {
+            s = HEC_ENOMEM;
+            hec_set_error("key-switch buffers");
+        } else {
+            hec_ks_inner(c->T, kb, R, nullptr, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
+            c->ks_count += (uint64_t)R;
+            hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
+            hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
+            hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
+            hec_moddown_combine(c->T, cb, R, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        }
+        c->release(e);
+        c->release(y);
+    }
+    c->release(Dall);
+    if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("batched rotation launch");
+    if (s != HEC_OK) free_all_cts(outs);
+    return s;
+}
+
 extern "C" hec_status ckks_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt,
                                           hec_ct **outs)
 {

@@ -132,6 +132,9 @@ hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale);
 hec_ct *ct_clone(const hec_ct *a);
 hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
 hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
+// every ciphertext (all at one level) rotated by `step`: one batched ModUp, key
+// switch and ModDown; the same ciphertexts as one rotation at a time
+hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, int32_t step, std::vector<hec_ct *> &outs);
 // npolys polynomials [npolys][l+1][n] at level l divided by q_l (*d replaced by [npolys][l][n])
 hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys);
 // the per-limb residues of the integer r (and Shoup companions) for limbs 0..nlimbs-1

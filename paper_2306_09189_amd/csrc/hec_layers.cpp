@@ -1788,32 +1788,35 @@ extern "C" hec_status he_linear(hec_ctx *c, const hec_image *in, const double *W
     hec_status s = pt_encode_many(c, mz, c->N, lvl - 1, (double)c->mod[lvl - 1], mpts);
     hec_ct *res = nullptr;
     size_t w = 0;
+    // per output: the products summed over the shards, rescaled
+    std::vector<hec_ct *> acc(O, nullptr);
     for (uint32_t o = 0; o < O && s == HEC_OK; o++) {
-        hec_ct *acc = ct_new(c, lvl, 1.0);
-        if (!acc) { s = HEC_ENOMEM; hec_set_error("ciphertext allocation"); break; }
+        acc[o] = ct_new(c, lvl, 1.0);
+        if (!acc[o]) { s = HEC_ENOMEM; hec_set_error("ciphertext allocation"); break; }
         bool first = true;
         for (; w < which.size() && which[w].first == o && s == HEC_OK; w++) {
-            s = ct_mac_pt(c, acc, in->shards[which[w].second], wpts[w], first);
+            s = ct_mac_pt(c, acc[o], in->shards[which[w].second], wpts[w], first);
             first = false;
         }
         if (s == HEC_OK && first) s = HEC_ELAYOUT, hec_set_error("output %u has no weights", o);
-        if (s == HEC_OK) s = ct_rescale(c, acc);
-        // rotate-and-add over all slots: every slot ends with the dot product
-        for (uint32_t k = c->N / 2; k >= 1 && s == HEC_OK; k /= 2) {
-            hec_ct *r = nullptr;
-            s = ckks_rotate(c, acc, (int32_t)k, &r);
-            if (s == HEC_OK) s = ct_add_inplace(c, acc, r);
-            ct_free(r);
-        }
-        if (s == HEC_OK) {
-            hec_ct *m = ct_new(c, acc->level, 1.0);
-            if (!m) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
-            else s = ct_mac_pt(c, m, acc, mpts[o], true);
-            if (s == HEC_OK) s = sum_into(c, res, m);
-            else ct_free(m);
-        }
-        ct_free(acc);
+        if (s == HEC_OK) s = ct_rescale(c, acc[o]);
     }
+    // rotate-and-add over all slots, every slot ending with its dot product;
+    // the O sums rotate together, one batched key switch per step
+    for (uint32_t k = c->N / 2; k >= 1 && s == HEC_OK; k /= 2) {
+        std::vector<hec_ct *> rots;
+        s = ct_rotate_many(c, std::vector<const hec_ct *>(acc.begin(), acc.end()), (int32_t)k, rots);
+        for (uint32_t o = 0; o < O && s == HEC_OK; o++) s = ct_add_inplace(c, acc[o], rots[o]);
+        free_all(rots);
+    }
+    for (uint32_t o = 0; o < O && s == HEC_OK; o++) {
+        hec_ct *m = ct_new(c, acc[o]->level, 1.0);
+        if (!m) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+        else s = ct_mac_pt(c, m, acc[o], mpts[o], true);
+        if (s == HEC_OK) s = sum_into(c, res, m);
+        else ct_free(m);
+    }
+    free_all(acc);
     if (s == HEC_OK) s = ct_rescale(c, res);
     for (auto *p : wpts) pt_free(p);
     for (auto *p : mpts) pt_free(p);
