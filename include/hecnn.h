@@ -224,8 +224,9 @@ hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const doub
  * taps x blocks x limbs instead of one plaintext per product (the
  * 112x112x64 layer: 261 MiB instead of 267 GiB), at the price of the
  * rounding of w^_b (2^(s-1) / q_l absolute per weight) and of E_b (relative
- * 2^-s).  Needs an image-sharded input with at most 4 blocks per shard
- * (HEC_ELAYOUT otherwise); runs in modes 0, 1 and 2 (he_conv2d_plan_set_mode
+ * 2^-s).  Needs an image-sharded input with at most 2 blocks per shard
+ * (HEC_ELAYOUT otherwise), |w^_b| < 2^31 and primes of at least 37 bits
+ * (HEC_EINVAL otherwise); runs in modes 0, 1 and 2 (he_conv2d_plan_set_mode
  * returns HEC_EINVAL for 3); excludes HEC_PLAN_Q_ONLY (HEC_EINVAL). */
 #define HEC_PLAN_BASIS 2u
 #define HEC_PLAN_BASIS_SCALE(s) ((uint32_t)(s) << 8)

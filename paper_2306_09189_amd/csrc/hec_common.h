@@ -80,12 +80,12 @@ struct KsMacBatch {
 
 // Weight plaintexts in basis-mask form: the plaintext of a term for an output
 // is sum_b w_b * E_{tap,b} over the blocks b of a shard, E_{tap,b} the encoded
-// mask of the term's tap restricted to block b; the product kernels read the
-// basis polynomials of a term once and form every output's plaintext in
-// registers.  With E null the plaintext pointers point at plaintexts; with E
-// set they point at the weight rows [nb][nqp] (Montgomery form) of each
-// (term, output).
-#define HEC_BASIS_NB 4
+// mask of the term's tap restricted to block b and w_b a small integer; the
+// product kernels read the basis polynomials of a term once and combine them
+// with every output's weights in registers.  With E null the plaintext
+// pointers point at plaintexts; with E set they point at the nb weights
+// (int64_t, |w| < 2^31) of each (term, output).
+#define HEC_BASIS_NB 2
 struct BasisArg {
     const u64 *E;            // [taps][nb][nqp][n], NTT + Montgomery form
     u32 tap[HEC_KS_BATCH];   // tap of each term

@@ -866,51 +866,13 @@ DEV u64x2 ld2(const u64 *p) { return *(const u64x2 *)p; }
 DEV u64x2 ld2_stream(const u64 *p) { return __builtin_nontemporal_load((const u64x2 *)p); }
 DEV void st2(u64 *p, u64x2 v) { *(u64x2 *)p = v; }
 
-// Basis-mask plaintexts: the basis polynomials of term t at (limb o, offset k)
-// are loaded once per term; a (term, output) plaintext value is then
-// sum_b W[b][o] * E_b (both Montgomery form, < HEC_BASIS_NB q^2) reduced once,
-// which is the Montgomery form of sum_b w_b * E_b mod q.
-DEV void basis_load1(const BasisArg &ba, u32 t, u32 o, u32 k, size_t n, u64 *eb)
-{
-    const u64 *Et = ba.E + ((size_t)ba.tap[t] * ba.nb * ba.nqp + o) * n + k;
-#pragma unroll
-    for (u32 b = 0; b < HEC_BASIS_NB; b++) eb[b] = b < ba.nb ? Et[(size_t)b * ba.nqp * n] : 0;
-}
-DEV void basis_load2(const BasisArg &ba, u32 t, u32 o, u32 k, size_t n, u64x2 *eb)
-{
-    const u64 *Et = ba.E + ((size_t)ba.tap[t] * ba.nb * ba.nqp + o) * n + k;
-#pragma unroll
-    for (u32 b = 0; b < HEC_BASIS_NB; b++) eb[b] = b < ba.nb ? ld2(Et + (size_t)b * ba.nqp * n) : u64x2{0, 0};
-}
-DEV u64 basis_pt1(const u64 *W, const u64 *eb, const BasisArg &ba, u32 o, const PrimeC &pc)
-{
-    acc128 a = {0, 0};
-#pragma unroll
-    for (u32 b = 0; b < HEC_BASIS_NB; b++)
-        if (b < ba.nb) mac(a, eb[b], W[(size_t)b * ba.nqp + o]);
-    return redc(a.hi, a.lo, pc.q, pc.qinv_neg);
-}
-DEV u64x2 basis_pt2(const u64 *W, const u64x2 *eb, const BasisArg &ba, u32 o, const PrimeC &pc)
-{
-    acc128 a0 = {0, 0}, a1 = {0, 0};
-#pragma unroll
-    for (u32 b = 0; b < HEC_BASIS_NB; b++)
-        if (b < ba.nb) {
-            const u64 w = W[(size_t)b * ba.nqp + o];
-            mac(a0, eb[b].x, w);
-            mac(a1, eb[b].y, w);
-        }
-    return u64x2{redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), redc(a1.hi, a1.lo, pc.q, pc.qinv_neg)};
-}
-
 // one output per workgroup with plaintexts as given: at most 96 registers,
 // five waves per SIMD (the kernel is bound by its key stream and needs the
 // waves to cover latency)
-template <int BETA, int NOUT, bool BASIS>
-__global__ void __launch_bounds__(EW_THREADS) __attribute__((amdgpu_waves_per_eu(NOUT == 1 && !BASIS ? 5 : 4)))
-k_ks_mac(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
-                                                       u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
-                                                       u32 first, u32 nchunks, u32 ngroups, DevTables T)
+template <int BETA, int NOUT>
+__global__ void __launch_bounds__(EW_THREADS) __attribute__((amdgpu_waves_per_eu(NOUT == 1 ? 5 : 4)))
+k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
+         u32 first, u32 nchunks, u32 ngroups, DevTables T)
 {
     const u32 w = blockIdx.x, total = gridDim.x;
     const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
@@ -939,13 +901,11 @@ k_ks_mac(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
             const u64x2 c0 = ld2(ct + (size_t)o * n + k), c1 = ld2(ct + ((size_t)nq + o) * n + k);
             const u64 e00 = mont_mul(c0.x, pmo, pc.q, pc.qinv_neg), e01 = mont_mul(c0.y, pmo, pc.q, pc.qinv_neg);
             const u64 e10 = mont_mul(c1.x, pmo, pc.q, pc.qinv_neg), e11 = mont_mul(c1.y, pmo, pc.q, pc.qinv_neg);
-            u64x2 eb[HEC_BASIS_NB];
-            if (BASIS) basis_load2(ba, t, o, k, n, eb);
 #pragma unroll
             for (int v = 0; v < NOUT; v++) {
                 const u64 *pt = b.pt[t][vb + v];
                 if (!pt) continue;
-                const u64x2 m = BASIS ? basis_pt2(pt, eb, ba, o, pc) : ld2(pt + (size_t)o * n + k);
+                const u64x2 m = ld2(pt + (size_t)o * n + k);
                 mac(acc[v][0][0], e00, m.x);
                 mac(acc[v][0][1], e01, m.y);
                 mac(acc[v][1][0], e10, m.x);
@@ -961,20 +921,10 @@ k_ks_mac(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
         // loads below (addresses always valid; unused values are ignored)
         const u64x2 c = ld2(ct + (size_t)(isq ? o : 0) * n + sb);
         u64x2 m[NOUT];
-        if (BASIS) {
-            u64x2 eb[HEC_BASIS_NB];
-            basis_load2(ba, t, o, k, n, eb);
 #pragma unroll
-            for (int v = 0; v < NOUT; v++) {
-                const u64 *W = b.pt[t][vb + v];
-                m[v] = W ? basis_pt2(W, eb, ba, o, pc) : u64x2{0, 0};
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < NOUT; v++) {
-                const u64 *pt = b.pt[t][vb + v];
-                m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
-            }
+        for (int v = 0; v < NOUT; v++) {
+            const u64 *pt = b.pt[t][vb + v];
+            m[v] = ld2_stream((pt ? pt : ct) + (size_t)(pt ? o : 0) * n + k);
         }
         acc128 a00 = {0, 0}, a01 = {0, 0}, a10 = {0, 0}, a11 = {0, 0};  // [poly][coefficient]
 #pragma unroll
@@ -1028,8 +978,8 @@ k_ks_mac(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
 // of a term is computed once for that many outputs; output groups of the same
 // (limb, chunk) are neighbours and share the key and digit reads through L2.
 #define KSW_OUT 8
-template <int BETA, bool BASIS>
-__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
+template <int BETA>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq,
                                                          u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
                                                          u32 first, u32 nchunks, u32 ngroups, u32 per, u32 nout,
                                                          DevTables T)
@@ -1056,14 +1006,12 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, BasisArg 
             const u64 *ct = b.ct[t];
             const u64 e0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
             const u64 e1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
-            u64 eb[HEC_BASIS_NB];
-            if (BASIS) basis_load1(ba, t, o, k, n, eb);
 #pragma unroll
             for (u32 v = 0; v < KSW_OUT; v++) {
                 if (v >= nv) break;
                 const u64 *pt = b.pt[t][vb + v];
                 if (!pt) continue;
-                const u64 m = BASIS ? basis_pt1(pt, eb, ba, o, pc) : pt[(size_t)o * n + k];
+                const u64 m = pt[(size_t)o * n + k];
                 mac(acc[v][0], e0, m);
                 mac(acc[v][1], e1, m);
             }
@@ -1073,20 +1021,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, BasisArg 
         const u64 *key = b.key[t], *D = b.D[t], *ct = b.ct[t];
         const u64 c = ct[(size_t)(isq ? o : 0) * n + src];
         u64 m[KSW_OUT];
-        if (BASIS) {
-            u64 eb[HEC_BASIS_NB];
-            basis_load1(ba, t, o, k, n, eb);
 #pragma unroll
-            for (u32 v = 0; v < KSW_OUT; v++) {
-                const u64 *W = v < nv ? b.pt[t][vb + v] : nullptr;
-                m[v] = W ? basis_pt1(W, eb, ba, o, pc) : 0;
-            }
-        } else {
-#pragma unroll
-            for (u32 v = 0; v < KSW_OUT; v++) {
-                const u64 *pt = v < nv ? b.pt[t][vb + v] : nullptr;
-                m[v] = pt ? __builtin_nontemporal_load(pt + (size_t)o * n + k) : 0;
-            }
+        for (u32 v = 0; v < KSW_OUT; v++) {
+            const u64 *pt = v < nv ? b.pt[t][vb + v] : nullptr;
+            m[v] = pt ? __builtin_nontemporal_load(pt + (size_t)o * n + k) : 0;
         }
         acc128 a0 = {0, 0}, a1 = {0, 0};
 #pragma unroll
@@ -1120,37 +1058,159 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_mac_w(KsMacBatch b, BasisArg 
     }
 }
 
+// Basis-mask plaintexts (BasisArg): for term t the basis polynomials E_b are
+// read once and y_{b,p} = x_p * E_b mod q formed for all outputs of the
+// workgroup (x the key-switch output, or P * c for a rotation by zero); output
+// v then adds sum_b w_{t,v,b} y_{b,p} with the weights small signed integers
+// (|w| < 2^31, checked when the plan is built): 64 x 32-bit products summed
+// exactly in 128-bit two's complement (|sum| < 64 * 2^91 = 2^97 for at most 16
+// terms of 4 blocks), reduced once with the offset q * 2^62 (>= 2^97 for
+// q >= 2^35, so the sum is non-negative and below q * 2^64), which is
+// congruent to 0.  The residues equal (sum_b w_b E_b) * x mod q exactly.
+DEV void smac(acc128 &acc, u64 y, int64_t w)
+{
+    const u32 a = (u32)(w < 0 ? -w : w);
+    const u64 p0 = (u64)(u32)y * a;
+    const u64 p1 = (u64)(u32)(y >> 32) * a + (p0 >> 32);
+    const u64 lo = (u64)(u32)p0 | (p1 << 32), hi = p1 >> 32;
+    if (w >= 0) {
+        acc.lo += lo;
+        acc.hi += hi + (acc.lo < lo ? 1 : 0);
+    } else {
+        const u64 borrow = acc.lo < lo ? 1 : 0;
+        acc.lo -= lo;
+        acc.hi -= hi + borrow;
+    }
+}
+// acc mod q in [0, q): redc of acc + q 2^62 is acc * 2^-64, times (2^64)^2 mod q in Montgomery form
+DEV u64 sfinal(acc128 acc, const PrimeC &pc)
+{
+    const u64 klo = pc.q << 62, khi = pc.q >> 2;
+    acc.lo += klo;
+    acc.hi += khi + (acc.lo < klo ? 1 : 0);
+    return mont_mul(redc(acc.hi, acc.lo, pc.q, pc.qinv_neg), pc.r2, pc.q, pc.qinv_neg);
+}
+DEV void basis_y(const BasisArg &ba, u32 t, u32 o, u32 k, size_t n, u64 x0, u64 x1, const PrimeC &pc,
+                 u64 (&y)[HEC_BASIS_NB][2])
+{
+    const u64 *Et = ba.E + ((size_t)ba.tap[t] * ba.nb * ba.nqp + o) * n + k;
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++) {
+        const u64 e = b < ba.nb ? Et[(size_t)b * ba.nqp * n] : 0;
+        y[b][0] = mont_mul(x0, e, pc.q, pc.qinv_neg);
+        y[b][1] = mont_mul(x1, e, pc.q, pc.qinv_neg);
+    }
+}
+DEV void basis_add(acc128 (&acc)[2], const int64_t *W, const BasisArg &ba, const u64 (&y)[HEC_BASIS_NB][2])
+{
+#pragma unroll
+    for (u32 b = 0; b < HEC_BASIS_NB; b++)
+        if (b < ba.nb) {
+            smac(acc[0], y[b][0], W[b]);
+            smac(acc[1], y[b][1], W[b]);
+        }
+}
+
+// Key switching fused with basis-mask plaintext products: the layout of
+// k_ks_mac_w (one coefficient per lane, up to KSW_OUT outputs per workgroup);
+// pt[t][v] points at the nb signed weights of (term t, output v).
+template <int BETA>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_mac_basis(KsMacBatch b, BasisArg ba, u32 nz, u32 nterms,
+                                                             u32 beta_rt, u32 nq, u32 nqp, const u32 *pmap,
+                                                             const u64 *pm, u32 NLK, u32 first, u32 nchunks,
+                                                             u32 ngroups, u32 per, u32 nout, DevTables T)
+{
+    const u32 w = blockIdx.x, total = gridDim.x;
+    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 grp = i % ngroups, rest = i / ngroups;
+    const u32 chunk = rest % nchunks, o = rest / nchunks;
+    const u32 vb = grp * per;
+    const u32 k = chunk * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const u32 beta = BETA ? BETA : beta_rt;
+    const size_t n = T.n;
+    const u32 pi = pmap[o];
+    const PrimeC pc = T.pc[pi];
+    const bool isq = o < nq;
+    const u64 pmo = isq ? pm[o] : 0;
+    const u32 nv = vb + per <= nout ? per : (vb < nout ? nout - vb : 0);
+    acc128 acc[KSW_OUT][2];
+#pragma unroll
+    for (int v = 0; v < KSW_OUT; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    for (u32 t = 0; t < nterms; t++) {
+        const u64 *ct = b.ct[t];
+        u64 x0, x1;
+        if (t < nz) {
+            // rotation by zero: P * (c0, c1) on the Q limbs, nothing on the P limbs
+            if (!isq) continue;
+            x0 = mont_mul(ct[(size_t)o * n + k], pmo, pc.q, pc.qinv_neg);
+            x1 = mont_mul(ct[((size_t)nq + o) * n + k], pmo, pc.q, pc.qinv_neg);
+        } else {
+            const u32 src = auto_src(k, b.g[t], T.logn);
+            const u64 *key = b.key[t], *D = b.D[t];
+            const u64 c = ct[(size_t)(isq ? o : 0) * n + src];
+            acc128 a0 = {0, 0}, a1 = {0, 0};
+#pragma unroll
+            for (u32 j = 0; j < beta; j++) {
+                const u64 d = D[((size_t)j * nqp + o) * n + src];
+                mac(a0, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k));
+                mac(a1, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k));
+            }
+            if (isq) mac(a0, c, pmo);
+            x0 = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
+            x1 = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+        }
+        u64 y[HEC_BASIS_NB][2];
+        basis_y(ba, t, o, k, n, x0, x1, pc, y);
+#pragma unroll
+        for (u32 v = 0; v < KSW_OUT; v++) {
+            if (v >= nv) break;
+            const int64_t *W = (const int64_t *)b.pt[t][vb + v];
+            if (W) basis_add(acc[v], W, ba, y);
+        }
+    }
+#pragma unroll
+    for (u32 v = 0; v < KSW_OUT; v++) {
+        if (v >= nv) break;
+        u64 *E = b.E[vb + v];
+        if (!E) continue;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            u64 *dst = E + ((size_t)p * nqp + o) * n + k;
+            u64 r = sfinal(acc[v][p], pc);
+            if (!((first >> (vb + v)) & 1)) r = add_mod(r, *dst, pc.q);
+            *dst = r;
+        }
+    }
+}
+
 template <int BETA>
 static void ks_mac_w_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
                             u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
                             u32 first, u32 nchunks, u32 ngroups, u32 per, u32 nout, const DevTables &T)
 {
     if (ba)
-        KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA, true>), g, dim3(EW_THREADS), 0, st, b, *ba, nz, nterms, beta,
-                nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
+        KLAUNCH("k_ks_mac", units, (k_ks_mac_basis<BETA>), g, dim3(EW_THREADS), 0, st, b, *ba, nz, nterms, beta, nq,
+                nqp, pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
     else
-        KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA, false>), g, dim3(EW_THREADS), 0, st, b, BasisArg{}, nz, nterms,
-                beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
+        KLAUNCH("k_ks_mac", units, (k_ks_mac_w<BETA>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp,
+                pmap, pm, NLK, first, nchunks, ngroups, per, nout, T);
 }
 
 template <int BETA, int NOUT>
-static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
-                          u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
-                          u32 nchunks, u32 ngroups, const DevTables &T)
+static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
+                          u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
+                          u32 ngroups, const DevTables &T)
 {
-    if (ba)
-        KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT, true>), g, dim3(EW_THREADS), 0, st, b, *ba, nz, nterms,
-                beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
-    else
-        KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT, false>), g, dim3(EW_THREADS), 0, st, b, BasisArg{}, nz,
-                nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+    KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp,
+            pmap, pm, NLK, first, nchunks, ngroups, T);
 }
 template <int NOUT>
-static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, const BasisArg *ba, u32 nz,
-                        u32 nterms, u32 beta, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first,
-                        u32 nchunks, u32 ngroups, const DevTables &T)
+static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
+                        u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
+                        u32 ngroups, const DevTables &T)
 {
-#define KSM_ARGS g, units, st, b, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
+#define KSM_ARGS g, units, st, b, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
     switch (beta) {
     case 1: ks_mac_launch<1, NOUT>(KSM_ARGS); break;
     case 2: ks_mac_launch<2, NOUT>(KSM_ARGS); break;
@@ -1200,8 +1260,9 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
         bb.E[v] = nullptr;
         for (int t = 0; t < HEC_KS_BATCH; t++) bb.pt[t][v] = nullptr;
     }
-    if (nout > 2) {
-        // many outputs: one coefficient per lane, groups of at most KSW_OUT outputs of even size
+    if (nout > 2 || ba) {
+        // many outputs (or basis-mask plaintexts): one coefficient per lane, groups of at most KSW_OUT
+        // outputs of even size
         const u32 ng = ((u32)nout + KSW_OUT - 1) / KSW_OUT, per = ((u32)nout + ng - 1) / ng;
         const u32 nch = (T.n + EW_THREADS - 1) / EW_THREADS;
         dim3 g(nch * (u32)nqp * ng);
@@ -1223,9 +1284,9 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
     const u32 ngroups = 1;
     dim3 g(nchunks * (u32)nqp * ngroups);
     if (per == 1)
-        ks_mac_beta<1>(g, units, st, bb, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+        ks_mac_beta<1>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     else
-        ks_mac_beta<2>(g, units, st, bb, ba, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+        ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     return true;
 }
 
@@ -1233,9 +1294,8 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
 // products of all terms for up to HEC_MAC_OUTS outputs accumulated in 128 bits
 // (< HEC_MAC_TERMS q^2 < q 2^64) and reduced once, so every rotated input is
 // read once per group of outputs.
-template <bool BASIS>
-__global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, BasisArg ba, u32 nterms, u32 nout, u32 nq,
-                                                          u32 first, DevTables T)
+__global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms, u32 nout, u32 nq, u32 first,
+                                                          DevTables T)
 {
     const u32 o = blockIdx.y;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
@@ -1248,13 +1308,11 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, BasisArg b
     for (u32 t = 0; t < nterms; t++) {
         const u64 *ct = b.ct[t];
         const u64 c0 = ct[off], c1 = ct[(size_t)nq * n + off];
-        u64 eb[HEC_BASIS_NB];
-        if (BASIS) basis_load1(ba, t, o, (u32)k, n, eb);
 #pragma unroll
         for (int v = 0; v < HEC_MAC_OUTS; v++) {
             const u64 *pt = b.pt[t][v];
             if (!pt) continue;
-            const u64 m = BASIS ? basis_pt1(pt, eb, ba, o, pc) : pt[off];
+            const u64 m = pt[off];
             mac(acc[v][0], c0, m);
             mac(acc[v][1], c1, m);
         }
@@ -1272,6 +1330,41 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, BasisArg b
         }
     }
 }
+// the same with basis-mask plaintexts: pt[t][v] points at the nb signed weights of (term t, output v)
+__global__ void __launch_bounds__(EW_THREADS) k_mac_terms_basis(MacBatch b, BasisArg ba, u32 nterms, u32 nout, u32 nq,
+                                                                u32 first, DevTables T)
+{
+    const u32 o = blockIdx.y;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const PrimeC pc = T.pc[o];
+    const size_t n = T.n, off = (size_t)o * n + k;
+    acc128 acc[HEC_MAC_OUTS][2];
+#pragma unroll
+    for (int v = 0; v < HEC_MAC_OUTS; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    for (u32 t = 0; t < nterms; t++) {
+        const u64 *ct = b.ct[t];
+        u64 y[HEC_BASIS_NB][2];
+        basis_y(ba, t, o, k, n, ct[off], ct[(size_t)nq * n + off], pc, y);
+#pragma unroll
+        for (int v = 0; v < HEC_MAC_OUTS; v++) {
+            const int64_t *W = (const int64_t *)b.pt[t][v];
+            if (W) basis_add(acc[v], W, ba, y);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < HEC_MAC_OUTS; v++) {
+        u64 *out = b.out[v];
+        if ((u32)v >= nout || !out) continue;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            u64 *dst = out + (size_t)p * nq * n + off;
+            u64 r = sfinal(acc[v][p], pc);
+            if (!((first >> v) & 1)) r = add_mod(r, *dst, pc.q);
+            *dst = r;
+        }
+    }
+}
 bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, int nq, int first, hipStream_t st,
                    const BasisArg *ba)
 {
@@ -1279,11 +1372,11 @@ bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, 
     if (ba && (!ba->E || ba->nb < 1 || ba->nb > HEC_BASIS_NB || (int)ba->nqp < nq)) return false;
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, 1);
     if (ba)
-        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms<true>, g, dim3(EW_THREADS), 0, st, b, *ba,
+        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms_basis, g, dim3(EW_THREADS), 0, st, b, *ba,
                 (u32)nterms, (u32)nout, (u32)nq, (u32)first, T);
     else
-        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms<false>, g, dim3(EW_THREADS), 0, st, b, BasisArg{},
-                (u32)nterms, (u32)nout, (u32)nq, (u32)first, T);
+        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms, g, dim3(EW_THREADS), 0, st, b, (u32)nterms,
+                (u32)nout, (u32)nq, (u32)first, T);
     return true;
 }
 

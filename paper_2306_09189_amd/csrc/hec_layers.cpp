@@ -1200,8 +1200,8 @@ struct hec_conv_plan {
     int mode = 0;
     bool q_only = false;  // weight plaintexts over Q only: modes 0 and 1
     // basis-mask form (basis = s > 0): the plaintexts of items are borrowed
-    // handles on weight rows of Wt ([nb][nqp] Montgomery residues of
-    // round(w_b q_l / 2^s) per block), E the tap masks per block at 2^s
+    // handles on weight rows of Wt (the nb integers round(w_b q_l / 2^s), as
+    // int64_t), E the tap masks per block at 2^s
     uint32_t basis = 0, nbasis = 0;
     u64 *E = nullptr, *Wt = nullptr;
     typedef RotTerm Item;
@@ -1328,10 +1328,12 @@ extern "C" hec_status he_conv2d_plan_create_ex(hec_ctx *c, const hec_image *like
 
 // The basis-mask form of a plan's weight plaintexts: per tap and block the
 // mask of the tap restricted to the block, encoded at 2^s over Q_l and P
-// (E, [taps][nb][nqp][n]); per (item, output) a weight row of nb * nqp
-// Montgomery residues of round_half_away(w_b * q_l / 2^s) (0 for blocks
-// without a weight); each item's plaintexts become borrowed handles on their
-// rows.  sum_b round(w_b q_l / 2^s) * E_b is then the plaintext, exactly.
+// (E, [taps][nb][nqp][n]); per (item, output) a weight row of the nb integers
+// round_half_away(w_b * q_l / 2^s) (0 for blocks without a weight); each
+// item's plaintexts become borrowed handles on their rows.
+// sum_b round(w_b q_l / 2^s) * E_b is then the plaintext, exactly.  The
+// product kernels take the weights as signed 32-bit factors and offset their
+// sums by q * 2^62: |w^| < 2^31 and every prime >= 2^36 are required.
 static hec_status build_basis(hec_ctx *c, hec_conv_plan *p, const std::vector<std::vector<ConvItem>> &items,
                               uint32_t s)
 {
@@ -1364,13 +1366,14 @@ static hec_status build_basis(hec_ctx *c, hec_conv_plan *p, const std::vector<st
     for (auto *q : bp) pt_free(q);
     if (st != HEC_OK) HEC_FAIL(st, "basis polynomial storage");
     // weight rows
-    std::vector<u64> primes(nqp);
-    for (uint32_t i = 0; i < nqp; i++) primes[i] = c->mod[i < nq ? i : c->L + 1 + (i - nq)];
+    for (uint32_t i = 0; i < nqp; i++)
+        if (c->mod[i < nq ? i : c->L + 1 + (i - nq)] < (1ull << 36))
+            HEC_FAIL(HEC_EINVAL, "basis-mask plaintexts need primes of at least 37 bits");
     const double wscale = (double)c->mod[lvl] / std::ldexp(1.0, (int)s);
     size_t rows = 0;
     for (auto &v : items)
         for (auto &it : v) rows += it.pts.size();
-    std::vector<u64> hw(rows * nb * nqp, 0);
+    std::vector<int64_t> hw(rows * nb, 0);
     size_t r = 0;
     for (auto &v : items)
         for (auto &it : v)
@@ -1378,11 +1381,10 @@ static hec_status build_basis(hec_ctx *c, hec_conv_plan *p, const std::vector<st
                 for (auto &bw : it.bw[e]) {
                     int64_t wh;
                     HEC_CHECK(const_coeff(bw.second, wscale, &wh));
-                    for (uint32_t i = 0; i < nqp; i++) {
-                        const u64 q = primes[i], mag = (u64)(wh < 0 ? -wh : wh) % q;
-                        const u64 res = wh < 0 && mag ? q - mag : mag;
-                        hw[((size_t)r * nb + bw.first) * nqp + i] = (u64)(((hec::u128)res << 64) % q);
-                    }
+                    if (wh >= (1ll << 31) || wh <= -(1ll << 31))
+                        HEC_FAIL(HEC_EINVAL, "weight %g too large for basis-mask plaintexts at 2^%u (|w q_l / 2^s| must "
+                                 "stay below 2^31)", bw.second, s);
+                    hw[(size_t)r * nb + bw.first] = wh;
                 }
     p->Wt = c->alloc(hw.size());
     if (!p->Wt) HEC_FAIL(HEC_ENOMEM, "weight rows");
@@ -1432,7 +1434,6 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
             c->release(p->Wt);
             return bs;
         }
-        const uint32_t nqp = lvl + 1 + c->k;
         size_t r = 0;
         for (auto &v : items)
             for (auto &it : v)
@@ -1441,7 +1442,7 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
                     h->ctx = c;
                     h->level = lvl;
                     h->scale = (double)c->mod[lvl];
-                    h->d = p->Wt + r * p->nbasis * nqp;
+                    h->d = p->Wt + r * p->nbasis;
                     h->has_p = true;
                     h->borrowed = true;
                     pts.push_back(h);

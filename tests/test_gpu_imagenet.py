@@ -70,9 +70,12 @@ def test_imagenet_layer_full():
 
 def test_imagenet_layer_basis():
     """The same layer with its weight plaintexts in basis-mask form (18 tap
-    masks per block encoded at 2^28 over Q and P, 261 MiB, instead of 18432
+    masks per block encoded at 2^27 over Q and P, 261 MiB, instead of 18432
     plaintexts): lazy ModDown and batched per-rotation evaluation, both
-    decrypting within 1e-5 of FP64."""
+    decrypting within 1e-5 of FP64.  2^27 is the measured best mask scale
+    here (max error 4.8e-5, 2.2e-5, 1.2e-5, 7.3e-6, 8.3e-6 at 2^24 ... 2^28:
+    the masks' encoding error falls and the weights' rounding error grows
+    with the scale)."""
     from paper_2306_09189_amd import hecnn
     gc.collect()
     need = 64 << 30
@@ -85,7 +88,7 @@ def test_imagenet_layer_basis():
     w = rng.normal(0, 0.05, (64, 64, 3, 3))
     img = ctx.image_encrypt(x, 20, 3004)
     t = time.perf_counter()
-    plan = ctx.conv2d_plan(img, w, basis=28)
+    plan = ctx.conv2d_plan(img, w, basis=27)
     ctx.sync()
     log("basis plan: %.2f s" % (time.perf_counter() - t))
     ctx.gen_rotation_keys(plan.steps())

@@ -416,7 +416,7 @@ def test_basis_plan_bit_exact(small, shape, ops, mode):
 
 
 def test_basis_plan_errors(small):
-    """Basis-mask plans refuse mode 3, more than 4 blocks per shard, channel
+    """Basis-mask plans refuse mode 3, more than 2 blocks per shard, channel
     shards and the Q-only flag."""
     from paper_2306_09189_amd import hecnn
     ctx, prm, o = small
@@ -430,7 +430,7 @@ def test_basis_plan_errors(small):
         ctx.conv2d_plan(img, w, basis=20, q_only=True)
     with pytest.raises(hecnn.HecError):
         ctx.conv2d_plan(img, w, basis=0)
-    small_img = ctx.image_encrypt(rng.uniform(-1, 1, (4, 8, 8)), 6, 79)    # 8 blocks of 64 slots
+    small_img = ctx.image_encrypt(rng.uniform(-1, 1, (4, 8, 8)), 6, 79)    # 8 blocks of 64 slots (at most 2)
     with pytest.raises(hecnn.HecError):
         ctx.conv2d_plan(small_img, w, basis=20)
     ch_img = ctx.image_encrypt(rng.uniform(-1, 1, (1, 32, 32)), 6, 80)     # one channel in two shards
