@@ -322,3 +322,40 @@ def test_imagenet_layer_shards_full(full, mode):
     assert z.info()[:3] == (8, 56, 56)
     ref = hl.ref_avgpool2x2(hl.ref_conv2d(x, w, 1))
     assert np.abs(z.decrypt() - ref).max() < 1e-5
+
+
+def test_mixed_level_instances(full):
+    """Thirteen image instances of the paper's CIFAR and ImageNet shapes, each
+    at its own level drawn uniformly from 2..24 (seeded): one 64x112x112 (32
+    shards, basis-mask plaintexts at 2^27, batched), four 16x56x56 (two
+    shards each) and eight 32x32x32 (one shard each; both with lazy ModDown),
+    48 ciphertexts in all; each through a 3x3 convolution with c_o = c_i and
+    its rescale on the same context, decrypting within 1e-5 of FP64 one level
+    lower."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(4004)
+    shapes = [(64, 112, 112)] + [(16, 56, 56)] * 4 + [(32, 32, 32)] * 8
+    levels = rng.integers(2, 25, size=len(shapes))
+    total = 0
+    for i, (shape, level) in enumerate(zip(shapes, levels)):
+        level = int(level)
+        C = shape[0]
+        x = np.clip(rng.normal(0, 1, shape), -4, 4) if C == 64 else rng.uniform(-1, 1, shape)
+        w = rng.normal(0, 0.05, (C, C, 3, 3))
+        img = ctx.image_encrypt(x, level, 6000 + i)
+        total += img.info()[-1]
+        if C == 64:
+            plan = ctx.conv2d_plan(img, w, basis=27)
+            plan.set_mode(0)
+        else:
+            plan = ctx.conv2d_plan(img, w)
+            plan.set_mode(2)
+        ctx.gen_rotation_keys(plan.steps())
+        log("instance %d: %s at level %d, %d shards" % (i, shape, level, img.info()[-1]))
+        y = plan.run(img)
+        del plan
+        assert all(y.shard_info(u)[0] == level - 1 for u in range(y.info()[-1]))
+        err = np.abs(y.decrypt() - hl.ref_conv2d(x, w, 1)).max()
+        log("  max abs err %.3g" % err)
+        assert err < 1e-5
+    assert total == 48
