@@ -359,3 +359,42 @@ def test_mixed_level_instances(full):
         log("  max abs err %.3g" % err)
         assert err < 1e-5
     assert total == 48
+
+
+def test_request_shapes_full_width(full):
+    """The two request shapes of the serving mix at full width, level 20:
+    a CIFAR request (3x32x32, channels padded to 4 and duplicated) through
+    conv 3x3 3 -> 32 and 2x2 pooling, and an ImageNet request (3x224x224, each
+    channel in two shards) through the stem conv 3x3 stride 2, 3 -> 64 (128
+    unstrided output shards, 6912 weight plaintexts kept over Q only,
+    downsampled and merged into 32 image shards of 112x112); both within 1e-5
+    of FP64."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(5005)
+    x = rng.uniform(-1, 1, (3, 32, 32))
+    w = rng.normal(0, 0.05, (32, 3, 3, 3))
+    img = ctx.image_encrypt(x, 20, 7001)
+    plan = ctx.conv2d_plan(img, w)
+    plan.set_mode(2)
+    ctx.gen_rotation_keys(plan.steps())
+    y = plan.run(img)
+    ctx.gen_rotation_keys(ctx.avgpool_steps(y))
+    z = ctx.avgpool(y, mode=2)
+    assert z.info()[:3] == (32, 16, 16)
+    err = np.abs(z.decrypt() - hl.ref_avgpool2x2(hl.ref_conv2d(x, w, 1))).max()
+    log("CIFAR request: max abs err %.3g" % err)
+    assert err < 1e-5
+    del plan, y, z
+    x = rng.uniform(-1, 1, (3, 224, 224))
+    w = rng.normal(0, 0.05, (64, 3, 3, 3))
+    img = ctx.image_encrypt(x, 20, 7002)
+    assert img.info()[3:] == (256, 6)
+    plan = ctx.conv2d_plan(img, w, stride=2, q_only=True)
+    ctx.gen_rotation_keys(plan.steps())
+    log("stem 3 -> 64: %d rotation keys" % len(plan.steps()))
+    y = plan.run(img)
+    del plan
+    assert y.info() == (64, 112, 112, 128, 32)
+    err = np.abs(y.decrypt() - hl.ref_conv2d(x, w, 1, 2)).max()
+    log("ImageNet request stem: max abs err %.3g" % err)
+    assert err < 1e-5
