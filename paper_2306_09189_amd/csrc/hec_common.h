@@ -183,6 +183,18 @@ enum ScalarOp { SC_MUL = 0, SC_ADD, SC_MAC, SC_DBL_ADD };
 // SC_MAC out (+)= in * v_l (first != 0: written); SC_DBL_ADD out = 2 in + v_l on even polys, 2 in on odd ones
 void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t out_poly_stride,
                 size_t in_poly_stride, int npolys, int nlimbs, int first, const ScalarArg &sa, hipStream_t st);
+// out = sum_j in_j * c_j over up to HEC_LIN_TERMS inputs, limbs l < nlimbs <= HEC_LIN_LIMBS of npolys
+// polynomials (input j read with its own poly stride); c_j per limb in Montgomery form; the products
+// summed in 128 bits and reduced once (the residues of multiply-accumulating them one at a time)
+#define HEC_LIN_TERMS 8
+#define HEC_LIN_LIMBS 32
+struct LinArg {
+    const u64 *in[HEC_LIN_TERMS];
+    size_t ps[HEC_LIN_TERMS];
+    u64 cm[HEC_LIN_TERMS][HEC_LIN_LIMBS];
+};
+bool hec_lincomb(const DevTables &T, u64 *out, size_t out_poly_stride, int npolys, int nlimbs, const LinArg &a,
+                 int nterms, hipStream_t st);
 // tensor products of cnt ciphertext pairs (a_i, b_i at a + 2i nq n, b + 2i nq n):
 // t_i = [a0 b0][a1 b1][a0 b1 + a1 b0] at t + 3i nq n
 void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, int cnt, hipStream_t st);

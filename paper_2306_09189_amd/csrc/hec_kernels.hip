@@ -1580,6 +1580,27 @@ void hec_scalar(const DevTables &T, ScalarOp op, u64 *out, const u64 *in, size_t
             out_poly_stride, in_poly_stride, first, sa, T);
 }
 
+__global__ void __launch_bounds__(EW_THREADS) k_lincomb(u64 *out, size_t pso, LinArg a, u32 nt, DevTables T)
+{
+    const u32 l = blockIdx.y, p = blockIdx.z;
+    const size_t t = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (t >= T.n) return;
+    const PrimeC pc = T.pc[l];
+    const size_t lo = (size_t)l * T.n + t;
+    acc128 acc = {0, 0};
+    for (u32 j = 0; j < nt; j++) mac(acc, a.in[j][p * a.ps[j] + lo], a.cm[j][l]);
+    out[p * pso + lo] = redc(acc.hi, acc.lo, pc.q, pc.qinv_neg);
+}
+bool hec_lincomb(const DevTables &T, u64 *out, size_t out_poly_stride, int npolys, int nlimbs, const LinArg &a,
+                 int nterms, hipStream_t st)
+{
+    if (nterms < 1 || nterms > HEC_LIN_TERMS || nlimbs < 1 || nlimbs > HEC_LIN_LIMBS || npolys < 1) return false;
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nlimbs, npolys);
+    KLAUNCH("k_lincomb", (uint64_t)npolys * nlimbs, k_lincomb, g, dim3(EW_THREADS), 0, st, out, out_poly_stride, a,
+            (u32)nterms, T);
+    return true;
+}
+
 // ciphertext tensor products in one pass: t_z = [a0 b0][a1 b1][a0 b1 + a1 b0]
 // for pair z = blockIdx.z (all plain evaluation form; b taken into Montgomery
 // form in registers)

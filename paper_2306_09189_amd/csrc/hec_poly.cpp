@@ -397,17 +397,29 @@ struct ChebEval {
         for (uint32_t j : js) lo = std::min(lo, T[j]->level);
         if (lo == 0) PFAIL(HEC_ELEVEL, "polynomial evaluation ran out of levels");
         const uint32_t top = lo - 1, l = top + 1;
-        // every T_j dropped to top + 1 and multiplied by c_j, accumulated in one buffer, the sum rescaled once
+        // every T_j dropped to top + 1 and multiplied by c_j, summed in one pass (one launch for up to
+        // HEC_LIN_TERMS terms), the sum rescaled once
         Ct acc = make(l, S_[l - 1] * (double)c->mod[l]);
+        const bool fused = js.size() <= HEC_LIN_TERMS && l + 1 <= HEC_LIN_LIMBS;
+        LinArg la{};
         bool first = true;
-        for (uint32_t j : js) {
+        for (size_t i = 0; i < js.size(); i++) {
+            const uint32_t j = js[i];
             const double pscale = S_[l - 1] * (double)c->mod[l] / T[j]->scale;
             const ScalarArg sa = scalar(cf[j], pscale, l + 1);
-            if (!dry)
+            if (dry) continue;
+            if (fused) {
+                la.in[i] = T[j]->d;
+                la.ps[i] = P(T[j]->level);
+                for (uint32_t r = 0; r <= l; r++) la.cm[i][r] = (u64)(((hec::u128)sa.v[r] << 64) % c->mod[r]);
+            } else {
                 hec_scalar(c->T, SC_MAC, acc->d, T[j]->d, P(l), P(T[j]->level), (int)(2 * S), (int)l + 1,
                            first ? 1 : 0, sa, c->st);
+            }
             first = false;
         }
+        if (!dry && fused && !hec_lincomb(c->T, acc->d, P(l), (int)(2 * S), (int)l + 1, la, (int)js.size(), c->st))
+            PFAIL(HEC_EINVAL, "invalid linear-combination launch");
         rescale(acc);
         acc->scale = S_[top];
         return Val::of(cf[0] != 0.0 ? add_const(acc, cf[0]) : acc);
