@@ -39,7 +39,8 @@ void *DevPool::get(size_t bytes)
         free_.erase(it);
         bytes_cached -= bytes;
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
-        // give the cached blocks back and retry once
+        // give the cached blocks back (once the queued work that may still use them is done) and retry once
+        (void)hipDeviceSynchronize();
         for (auto &kv : free_) hipFree(kv.second);
         free_.clear();
         bytes_cached = 0;

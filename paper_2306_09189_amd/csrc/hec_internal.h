@@ -37,7 +37,9 @@ void hec_set_error(const char *fmt, ...);
 
 // Device memory pool: exact-size free lists; all users order their work on the
 // context stream, so a block freed after enqueued work may be handed out again
-// to later work on the same stream.
+// to later work on the same stream.  When the device is out of memory the
+// cached blocks go back to it (after its queued work is done) and the
+// allocation is tried once more.
 struct DevPool {
     std::unordered_multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> live_;
