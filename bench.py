@@ -412,6 +412,30 @@ def main():
     linear_ms = float(np.median(ts[1:]))
     linear_err = float(np.abs(ctx.decrypt(ol)[:10] - hl.ref_linear(xl, wl, True)).max())
     del ol, iml
+    # a 112x112x64 stage of an ImageNet ResNet (32 shards of two padded
+    # 128x128 channels): conv 3x3 64->64 with basis-mask weight plaintexts
+    # (masks at 2^27), then 2x2 pooling with lazy ModDown; second calls timed
+    xi = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
+    wi = rng.normal(0, 0.05, (64, 64, 3, 3))
+    imi = ctx.image_encrypt(xi, LEVEL, 9)
+    pi = ctx.conv2d_plan(imi, wi, basis=27)
+    ctx.gen_rotation_keys(pi.steps())
+    ctx.gen_rotation_keys(ctx.avgpool_steps(imi))
+    inet = {}
+    for name, fn in (("conv", lambda: pi.run(imi)), ("pool", lambda: ctx.avgpool(yi, 2))):
+        r = fn()
+        ctx.sync()
+        del r
+        s = time.perf_counter()
+        r = fn()
+        ctx.sync()
+        inet[name] = (time.perf_counter() - s) * 1e3
+        if name == "conv":
+            yi = r
+        else:
+            zi = r
+    inet_err = float(np.abs(zi.decrypt() - hl.ref_avgpool2x2(hl.ref_conv2d(xi, wi, 1))).max())
+    del pi, yi, zi, imi
 
     out = {
         "metric": "key-switched rotations/sec + HE conv-layer ms at 2N=2^16; batched vs plain",
@@ -448,6 +472,9 @@ def main():
         "block_max_abs_err_vs_fp64": block_err,
         "pool_linear_64x8x8_to_10_ms": linear_ms,
         "pool_linear_max_abs_err_vs_fp64": linear_err,
+        "imagenet_112x112x64_conv_ms_basis_mask": inet["conv"],
+        "imagenet_112x112x64_pool_ms_lazy": inet["pool"],
+        "imagenet_112x112x64_max_abs_err_vs_fp64": inet_err,
         "max_abs_err_vs_fp64": err,
         "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
         "roofline": roofline,
