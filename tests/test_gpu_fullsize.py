@@ -8,7 +8,7 @@ configuration bench.py times (batched hoisted rotations, plan runs).
   geometry of the 112x112x64 layer: side padded to 128, 2 channels per
   ciphertext, 17 rotations);
 * the same shard convolution with lazy ModDown, bit-exact with the oracle's
-  lazy form;
+  lazy form, and with basis-mask weight plaintexts (batched and lazy);
 * decrypted within 1e-5 of FP64: the 32x32x32 image through conv 3x3 32->32
   and the strided conv 3x3 32->64 (the benchmark step), with per-rotation and
   with lazy ModDown.
@@ -118,6 +118,31 @@ def test_conv_112_shard_lazy_bit_exact(full):
     assert out.shard_info(0) == (oc[0].level, oc[0].scale)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+
+
+def test_conv_112_shard_basis_bit_exact(full):
+    """The same shard convolution with basis-mask weight plaintexts (masks per
+    tap and block encoded at 2^27, weights rounded at q_l / 2^27), batched and
+    with lazy ModDown: bit-exact with the oracle building the same integer
+    plaintexts."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(4)
+    x = np.clip(rng.normal(0, 1, (2, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (2, 2, 3, 3))
+    img = ctx.image_encrypt(x, 20, 3005)
+    plan = ctx.conv2d_plan(img, w, basis=27)
+    ctx.gen_rotation_keys(plan.steps())
+    lay = hl.natural_layout(prm.N, 2, 112, 112)
+    cts = [o.encrypt(o.encode(v, 20, 2.0 ** LS), seed=3005, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    be = hl.CkksBackend(o, basis=27)
+    for mode in (0, 2):
+        plan.set_mode(mode)
+        out = plan.run(img)
+        log("oracle basis-mask conv, mode %d" % mode)
+        oc, ol = hl.conv2d(be, cts, lay, w, pad=1, lazy=(mode == 2))
+        assert out.shard_info(0) == (oc[0].level, oc[0].scale)
+        assert (out.shard_export(0) == oc[0].data).all()
+        assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
 
 
 def test_conv_112_shard_bsgs_bit_exact(full):
