@@ -182,8 +182,8 @@ def main():
                          "runs of the 16x32x32 block, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        eprint("bench.py measures one GPU: this build runs the whole path on a single MI355X "
-               "(multi-GPU sharding is a design note, not an implementation); use --gpus 1")
+        eprint("bench.py measures one GPU: the whole path runs on a single MI355X "
+               "(sharding across GPUs is described, not implemented); use --gpus 1")
         sys.exit(2)
 
     import torch
