@@ -161,6 +161,26 @@ bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, 
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,
                          const LevelC *lc, const u32 *pmap, hipStream_t st);
 
+// Rescale of npolys polynomials at level l by q_l with its last two steps
+// fused into the forward NTT (2N = 2^16 only): the column pass reads the
+// dropped limb's coefficients (last, coefficient form, poly stride ls) and
+// reduces their centered values mod each q_i, the row pass writes
+// out_i = (c_i - NTT(r)_i) q_l^-1 (c and out with their poly strides); tmp
+// ([npolys][l][n]) holds the column pass's output; pmap the identity map of
+// the Q limbs.  Same residues as spread + NTT + finish.  Returns false
+// (nothing launched) for another ring size.
+struct RescaleFuse {
+    const u64 *last;
+    size_t ls;
+    const u64 *c;
+    size_t cs;
+    u64 *out;
+    size_t os;
+    const LevelC *lc;
+    u32 level;
+};
+bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
+                         hipStream_t st);
 void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size_t last_stride, size_t tmp_stride,
                         int npolys, u32 level, hipStream_t st);
 void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc,

@@ -1080,10 +1080,15 @@ hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys)
     }
     hec_copy_limbs(last, *d + (size_t)l * n, n, (size_t)nq * n, npolys, n, c->st);
     hec_ntt_inv(c->T, last, n, npolys, c->idmap() + l, 1, c->st);
-    hec_rescale_spread(c->T, last, tmp, n, (size_t)l * n, npolys, l, c->st);
-    hec_ntt_fwd(c->T, tmp, (size_t)l * n, npolys, c->idmap(), l, c->st);
-    hec_rescale_finish(c->T, o, *d, tmp, (size_t)l * n, (size_t)nq * n, (size_t)l * n, npolys, l, c->d_lvl + l,
-                       c->st);
+    // (c_i - [centered last]_{q_i}) * q_l^-1: the reduction folded into the
+    // forward NTT's loads and the last step into its stores where the ring allows
+    const RescaleFuse f{last, n, *d, (size_t)nq * n, o, (size_t)l * n, c->d_lvl + l, l};
+    if (!hec_ntt_fwd_rescale(c->T, tmp, npolys, c->idmap(), f, c->st)) {
+        hec_rescale_spread(c->T, last, tmp, n, (size_t)l * n, npolys, l, c->st);
+        hec_ntt_fwd(c->T, tmp, (size_t)l * n, npolys, c->idmap(), l, c->st);
+        hec_rescale_finish(c->T, o, *d, tmp, (size_t)l * n, (size_t)nq * n, (size_t)l * n, npolys, l, c->d_lvl + l,
+                           c->st);
+    }
     c->release(last);
     c->release(tmp);
     c->release(*d);

@@ -301,6 +301,7 @@ DEV u64 reduce4(u64 x, u64 q)
 }
 
 #define N16_PAD(c) ((c) + ((c) >> 4))  // padded LDS index inside a 256-point row (17 words per 16)
+DEV u64 mod64(u64 x, const PrimeC &pc);
 
 // XCD-aware work order: workgroups are dealt round-robin to the 8 XCDs, each
 // with its own L2.  The flat grid of 16 x nlimbs x npolys tiles is remapped so
@@ -322,9 +323,11 @@ DEV Ntt16Item ntt16_item(u32 npolys)
     return it;
 }
 
-// forward column pass: stages 0..7 over the 256 rows of 16 columns
+// forward column pass: stages 0..7 over the 256 rows of 16 columns (RS: the
+// input is the centered dropped limb of a rescale, reduced mod this limb's prime)
+template <bool RS>
 __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
-                                                        DevTables T)
+                                                        RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[256 * 16];
     const Ntt16Item it = ntt16_item(npolys);
@@ -334,8 +337,24 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_s
     const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
     const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
     u64 x[16];
+    if (RS) {
+        const PrimeC pc = T.pc[pi];
+        const u64 ql = T.pc[f.level].q;
+        const u64 *src = f.last + it.poly * f.ls + it.tile * 16;
 #pragma unroll
-    for (int h = 0; h < 16; h++) x[h] = a[(size_t)(l + 16 * h) * 256 + col];
+        for (int h = 0; h < 16; h++) {
+            const u64 v = src[(size_t)(l + 16 * h) * 256 + col];
+            if (v <= (ql - 1) / 2) {
+                x[h] = mod64(v, pc);
+            } else {
+                const u64 m = mod64(ql - v, pc);
+                x[h] = m ? q - m : 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < 16; h++) x[h] = a[(size_t)(l + 16 * h) * 256 + col];
+    }
 #pragma unroll
     for (int s = 0; s < 4; s++) {
         const int half = 8 >> s;
@@ -366,9 +385,11 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_s
     for (int i = 0; i < 16; i++) a[(size_t)(16 * hb + i) * 256 + col] = x[i];
 }
 
-// forward row pass: stages 8..15 inside 16 rows of 256 words; fully reduced output
+// forward row pass: stages 8..15 inside 16 rows of 256 words; fully reduced
+// output (RS: written as (c - output) q_l^-1 to the rescaled polynomial)
+template <bool RS>
 __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
-                                                        DevTables T)
+                                                        RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
     const Ntt16Item it = ntt16_item(npolys);
@@ -412,8 +433,18 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
 #pragma unroll
     for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = reduce4(x[i], q);
     __syncthreads();
+    if (RS) {
+        const size_t off = ((size_t)it.limb << 16) + (size_t)r0 * 256 + row * 256;
+        const u64 *cp = f.c + it.poly * f.cs + off;
+        u64 *op = f.out + it.poly * f.os + off;
+        const u64 qi = f.lc->qlinv[it.limb], qis = f.lc->qlinv_sh[it.limb];
 #pragma unroll
-    for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = lr[N16_PAD(l + 16 * h)];
+        for (int h = 0; h < 16; h++)
+            op[l + 16 * h] = shoup_mul(sub_mod(cp[l + 16 * h], lr[N16_PAD(l + 16 * h)], q), qi, qis, q);
+    } else {
+#pragma unroll
+        for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = lr[N16_PAD(l + 16 * h)];
+    }
 }
 
 // inverse row pass: stages 15..8 (Gentleman-Sande) inside 16 rows
@@ -520,8 +551,10 @@ static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stri
         dim3 g((u32)(16 * limbs));
         const u32 np = (u32)npolys;
         if (!inv) {
-            KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
-            KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+            KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
+                    np, RescaleFuse{}, T);
+            KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
+                    np, RescaleFuse{}, T);
         } else {
             KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
             KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
@@ -549,6 +582,19 @@ static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stri
     }
 }
 
+bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
+                         hipStream_t st)
+{
+    if (T.logn != 16 || npolys <= 0 || f.level == 0) return false;
+    const u32 l = f.level;
+    const uint64_t limbs = (uint64_t)l * npolys;
+    dim3 g((u32)(16 * limbs));
+    const size_t ps = (size_t)l << 16;
+    const u32 np = (u32)npolys;
+    KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, T);
+    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, T);
+    return true;
+}
 void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
                  hipStream_t st)
 {
