@@ -329,7 +329,8 @@ def test_ring_2e13_conv_pool():
 
 
 @pytest.mark.parametrize("shape,pool,O", [((4, 8, 8), False, 3), ((4, 8, 8), True, 5), ((8, 16, 16), True, 10),
-                                          ((1, 32, 32), True, 4)])
+                                          ((1, 32, 32), True, 4),
+                                          ((8, 16, 16), True, 20)])   # outputs rotated in two key-switch batches
 def test_linear_bit_exact(small, shape, pool, O):
     """Linear and pool-linear layers (rotate-and-add dot products) bit-exact
     with the oracle; decrypted within 1e-5 of W @ x."""
