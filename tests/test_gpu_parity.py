@@ -191,6 +191,7 @@ def prm_log_scale(ctx):
     ((1, 32, 32), [("conv", (1, 3), 1), ("pool",)]),                # one channel in two shards: dup x2
     ((3, 28, 28), [("conv", (4, 3), 2), ("conv", (4, 3), 1)]),      # strided stem, then image shards
     ((1, 64, 64), [("pool",), ("conv", (2, 3), 1)]),                # 8 shards/channel -> 2 shards/channel
+    ((4, 16, 16), [("conv", (32, 3), 1)]),                          # 16 outputs: two groups of 8 per launch
 ])
 def test_layers_bit_exact(small, shape, ops):
     ctx, prm, o = small
