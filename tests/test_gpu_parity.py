@@ -391,6 +391,8 @@ def test_layers_edge_shapes_bit_exact(small, shape, ops, pad, mode):
     ((16, 16, 16), [("conv", (8, 3), 1)], 2),
     ((4, 16, 16), [("conv", (8, 3), 2)], 2),                        # strided
     ((2, 32, 32), [("pool",), ("conv", (4, 3), 1)], 0),             # channel shards pooled, then basis conv
+    ((4, 16, 16), [("conv", (32, 3), 1)], 0),                       # 16 outputs: two groups of 8 per launch
+    ((4, 16, 16), [("conv", (48, 3), 1)], 2),                       # 24 outputs: two lazy passes over the terms
 ])
 def test_basis_plan_bit_exact(small, shape, ops, mode):
     """Weight plaintexts in basis-mask form (tap masks per block encoded at
