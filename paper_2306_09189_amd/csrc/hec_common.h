@@ -107,6 +107,7 @@ struct CombineBatch {
     const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
     const u64 *y[HEC_KS_BATCH];    // [2][nq][n], NTT form
     const u64 *c0[HEC_KS_BATCH];   // this entry's own c0 (null: the launch's shared c0)
+    const u64 *add[HEC_KS_BATCH][2];  // [nq][n] added to poly 0 / 1 of the entry as is (null: nothing)
     u32 g[HEC_KS_BATCH];
 };
 

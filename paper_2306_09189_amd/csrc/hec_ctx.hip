@@ -879,7 +879,8 @@ const u64 *ones_qp(hec_ctx *c, uint32_t lvl)
 // outs[i] = ModDown(E_i) for E_i = [2][nq+k][n] over Q_l and P (NTT form) at
 // Eall + i * 2 (nq+k) n, all at one level; the P limbs of Eall are consumed.
 // One launch per stage for all of them (combine in groups of HEC_KS_BATCH).
-hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vector<hec_ct *> &outs)
+hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vector<hec_ct *> &outs,
+                           const std::vector<std::array<const u64 *, 2>> *adds)
 {
     if (outs.empty()) return HEC_OK;
     const size_t n = c->n, cnt = outs.size();
@@ -900,6 +901,10 @@ hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vecto
             cb.e[r] = Eall + (b0 + r) * 2 * (size_t)nqp * n;
             cb.y[r] = y + (b0 + r) * 2 * (size_t)nq * n;
             cb.g[r] = 1;
+            if (adds) {
+                cb.add[r][0] = (*adds)[b0 + r][0];
+                cb.add[r][1] = (*adds)[b0 + r][1];
+            }
         }
         hec_moddown_combine(c->T, cb, (int)nb, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
     }
@@ -1225,12 +1230,11 @@ hec_status ct_mul(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec_ct **out)
         kb.g[0] = 1;
         hec_ks_inner(c->T, kb, 1, D, (int)beta, (int)nqp, c->qpmap(lvl), (int)c->NLK, c->st);
         c->ks_count += 1;
-        s = ct_moddown(c, lvl, E, o);
-    }
-    if (s == HEC_OK) {
-        // (d0, d1) at t and t + 2P
-        hec_ew(c->T, EW_ADD, o->d, o->d, t, P, P, 2 * P, 2, c->idmap(), (int)nq, c->st);
-        if (hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("ciphertext product launch failed");
+        // ModDown of the key-switched d2 plus (d0, d1), which sit at t and t + 2P
+        const std::vector<std::array<const u64 *, 2>> adds{{t, t + 2 * P}};
+        s = ct_moddown_many(c, lvl, E, {o}, &adds);
+        if (s == HEC_OK && hipGetLastError() != hipSuccess)
+            s = HEC_EDEVICE, hec_set_error("ciphertext product launch failed");
     }
     c->release(D);
     c->release(t);

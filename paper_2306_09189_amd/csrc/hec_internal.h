@@ -1,5 +1,6 @@
 // hec_internal.h -- host-side structures of the library (not part of the ABI).
 #pragma once
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -155,8 +156,10 @@ hec_status ct_modup(hec_ctx *c, const hec_ct *ct, u64 **D);
 hec_status ct_modup_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, u64 **Dall);
 // out = ModDown(E), E = [2][level+1+k][n] over Q_l and P (NTT form); E's P limbs are overwritten
 hec_status ct_moddown(hec_ctx *c, uint32_t level, u64 *E, hec_ct *out);
-// outs[i] = ModDown(Eall + i * 2 (level+1+k) n) for several outputs (allocated at `level`) in one set of launches
-hec_status ct_moddown_many(hec_ctx *c, uint32_t level, u64 *Eall, const std::vector<hec_ct *> &outs);
+// outs[i] = ModDown(Eall + i * 2 (level+1+k) n) for several outputs (allocated at `level`) in one set of
+// launches; with adds, (*adds)[i][p] ([level+1][n]) is added to polynomial p of output i in the same pass
+hec_status ct_moddown_many(hec_ctx *c, uint32_t level, u64 *Eall, const std::vector<hec_ct *> &outs,
+                           const std::vector<std::array<const u64 *, 2>> *adds = nullptr);
 // the plaintext 1 over Q_l and P ([level+1+k][n], Montgomery form), cached per level
 const u64 *ones_qp(hec_ctx *c, uint32_t level);
 // the relinearization key (target s^2), generated from the key seed on first use

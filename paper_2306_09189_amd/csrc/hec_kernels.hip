@@ -1440,6 +1440,7 @@ __global__ void k_moddown_combine(CombineBatch cb, const u64 *c0, u32 nq, u32 nq
     u64 v = shoup_mul(sub_mod(e, y, q), lc->pinv[i], lc->pinv_sh[i], q);
     const u64 *c0r = cb.c0[r] ? cb.c0[r] : c0;
     if (p == 0 && c0r) v = add_mod(v, c0r[(size_t)i * n + auto_src(k, cb.g[r], T.logn)], q);
+    if (cb.add[r][p]) v = add_mod(v, cb.add[r][p][(size_t)i * n + k], q);
     cb.out[r][((size_t)p * nq + i) * n + k] = v;
 }
 void hec_moddown_combine(const DevTables &T, const CombineBatch &cb, int nrot, const u64 *c0, int nq, int nqp,

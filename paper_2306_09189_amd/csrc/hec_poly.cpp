@@ -218,13 +218,10 @@ struct ChebEval {
             hec_ks_inner(c->T, kb, (int)R, nullptr, (int)beta, (int)nqp, c->qpmap(l), (int)c->NLK, c->st);
         }
         c->ks_count += S;
-        if (s == HEC_OK) s = ct_moddown_many(c, l, E, op);
-        if (s == HEC_OK) {
-            // (d0, d1) of pair i at t_i and t_i + 2p
-            hec_ew(c->T, EW_ADD, r->d, r->d, t, 2 * p, 2 * p, 3 * p, (int)S, c->idmap(), (int)nq, c->st);
-            hec_ew(c->T, EW_ADD, r->d + p, r->d + p, t + 2 * p, 2 * p, 2 * p, 3 * p, (int)S, c->idmap(), (int)nq,
-                   c->st);
-        }
+        // ModDown of every key-switched d2 plus its (d0, d1), at t_i and t_i + 2p
+        std::vector<std::array<const u64 *, 2>> adds(S);
+        for (uint32_t i = 0; i < S; i++) adds[i] = {t + (size_t)i * 3 * p, t + (size_t)i * 3 * p + 2 * p};
+        if (s == HEC_OK) s = ct_moddown_many(c, l, E, op, &adds);
         for (auto &h : tv) h.d = nullptr;
         for (auto &h : ov) h.d = nullptr;
         c->release(D);
