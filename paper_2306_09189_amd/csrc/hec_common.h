@@ -180,6 +180,10 @@ struct RescaleFuse {
     const LevelC *lc;
     u32 level;
 };
+// inverse NTT of nlimbs limbs of npolys polynomials read from src (poly stride
+// src_stride) and written to dst (dst_stride); 2N = 2^16 only (false otherwise)
+bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64 *src, size_t src_stride,
+                      int npolys, const u32 *pmap, int nlimbs, hipStream_t st);
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
                          hipStream_t st);
 void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size_t last_stride, size_t tmp_stride,

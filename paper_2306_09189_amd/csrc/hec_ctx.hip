@@ -1083,8 +1083,10 @@ hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys)
         c->release(o);
         HEC_FAIL(HEC_ENOMEM, "rescale buffers");
     }
-    hec_copy_limbs(last, *d + (size_t)l * n, n, (size_t)nq * n, npolys, n, c->st);
-    hec_ntt_inv(c->T, last, n, npolys, c->idmap() + l, 1, c->st);
+    if (!hec_ntt_inv_from(c->T, last, n, *d + (size_t)l * n, (size_t)nq * n, npolys, c->idmap() + l, 1, c->st)) {
+        hec_copy_limbs(last, *d + (size_t)l * n, n, (size_t)nq * n, npolys, n, c->st);
+        hec_ntt_inv(c->T, last, n, npolys, c->idmap() + l, 1, c->st);
+    }
     // (c_i - [centered last]_{q_i}) * q_l^-1: the reduction folded into the
     // forward NTT's loads and the last step into its stores where the ring allows
     const RescaleFuse f{last, n, *d, (size_t)nq * n, o, (size_t)l * n, c->d_lvl + l, l};

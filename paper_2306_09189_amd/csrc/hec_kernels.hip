@@ -447,9 +447,11 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
     }
 }
 
-// inverse row pass: stages 15..8 (Gentleman-Sande) inside 16 rows
+// inverse row pass: stages 15..8 (Gentleman-Sande) inside 16 rows (OOP: the
+// input read from src with its own poly stride, the output written to base)
+template <bool OOP>
 __global__ void __launch_bounds__(256) k_ntt16_inv_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
-                                                        DevTables T)
+                                                        const u64 *src, size_t src_stride, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
     const Ntt16Item it = ntt16_item(npolys);
@@ -462,8 +464,9 @@ __global__ void __launch_bounds__(256) k_ntt16_inv_rows(u64 *base, size_t poly_s
     const u32 grow = r0 + row;
     u64 *lr = lds + row * 272;
     u64 x[16];
+    const u64 *in = OOP ? src + it.poly * src_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256 : a;
 #pragma unroll
-    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = a[row * 256 + l + 16 * h];
+    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = in[row * 256 + l + 16 * h];
     __syncthreads();
     const u32 hb = l;
 #pragma unroll
@@ -556,7 +559,8 @@ static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stri
             KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
                     np, RescaleFuse{}, T);
         } else {
-            KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+            KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
+                    np, nullptr, (size_t)0, T);
             KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
         }
         return;
@@ -582,6 +586,18 @@ static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stri
     }
 }
 
+bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64 *src, size_t src_stride,
+                      int npolys, const u32 *pmap, int nlimbs, hipStream_t st)
+{
+    if (T.logn != 16 || npolys <= 0 || nlimbs <= 0) return false;
+    const uint64_t limbs = (uint64_t)nlimbs * npolys;
+    dim3 g((u32)(16 * limbs));
+    const u32 np = (u32)npolys;
+    KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<true>, g, dim3(256), 0, st, dst, dst_stride, pmap, np, src,
+            src_stride, T);
+    KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, dst, dst_stride, pmap, np, T);
+    return true;
+}
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
                          hipStream_t st)
 {
