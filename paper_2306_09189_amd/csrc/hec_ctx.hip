@@ -840,9 +840,18 @@ hec_status ct_modup_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, u64
     }
     // c1 to coefficients; every digit converted to Q_l and P with its own limbs
     // copied, then one forward NTT (the digit's own limbs come back to c1's values)
-    for (size_t i = 0; i < cnt; i++)
-        HEC_TRY_HIP(hipMemcpyAsync(cc + i * nq * n, cts[i]->d + nq * n, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
-    hec_ntt_inv(c->T, cc, nq * n, (int)cnt, c->idmap(), nq, c->st);
+    // inputs at one stride from each other (a single one, or views into one
+    // batch) go straight into the inverse NTT; others are copied first
+    const ptrdiff_t stride = cnt > 1 ? cts[1]->d - cts[0]->d : 0;
+    bool uniform = stride >= 0;
+    for (size_t i = 1; i < cnt && uniform; i++) uniform = cts[i]->d == cts[0]->d + (ptrdiff_t)i * stride;
+    if (!uniform || !hec_ntt_inv_from(c->T, cc, nq * n, cts[0]->d + nq * n, (size_t)stride, (int)cnt, c->idmap(),
+                                      (int)nq, c->st)) {
+        for (size_t i = 0; i < cnt; i++)
+            HEC_TRY_HIP(
+                hipMemcpyAsync(cc + i * nq * n, cts[i]->d + nq * n, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+        hec_ntt_inv(c->T, cc, nq * n, (int)cnt, c->idmap(), nq, c->st);
+    }
     uint32_t nout_max = 0;
     for (uint32_t j = 0; j < beta; j++) nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
     hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)beta, (int)nout_max, cc, D, nq * n,
