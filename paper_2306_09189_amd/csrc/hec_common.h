@@ -223,6 +223,14 @@ bool hec_lincomb(const DevTables &T, u64 *out, size_t out_poly_stride, int npoly
 // tensor products of cnt ciphertext pairs (a_i, b_i at a + 2i nq n, b + 2i nq n):
 // t_i = [a0 b0][a1 b1][a0 b1 + a1 b0] at t + 3i nq n
 void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, int cnt, hipStream_t st);
+// the same for nitems <= HEC_TENSOR_ITEMS separate batches of per pairs each
+// (pair z = item z / per, index z % per in it), the results contiguous in t
+#define HEC_TENSOR_ITEMS 16
+struct TensorItems {
+    const u64 *a[HEC_TENSOR_ITEMS];
+    const u64 *b[HEC_TENSOR_ITEMS];
+};
+bool hec_tensor_items(const DevTables &T, u64 *t, const TensorItems &it, int nitems, int per, int nq, hipStream_t st);
 
 // enc: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk in Montgomery form, the rest plain NTT form)
 void hec_encrypt_finish(const DevTables &T, u64 *ct, const u64 *v, const u64 *e0, const u64 *e1, const u64 *m,

@@ -1683,6 +1683,29 @@ __global__ void __launch_bounds__(EW_THREADS) k_tensor(u64 *t, const u64 *a, con
     t[P + off] = mont_mul(a1, b1, pc.q, pc.qinv_neg);
     t[2 * P + off] = add_mod(mont_mul(a0, b1, pc.q, pc.qinv_neg), mont_mul(a1, b0, pc.q, pc.qinv_neg), pc.q);
 }
+__global__ void __launch_bounds__(EW_THREADS) k_tensor_items(u64 *t, TensorItems it, u32 per, size_t P, DevTables T)
+{
+    const u32 l = blockIdx.y, z = blockIdx.z;
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const PrimeC pc = T.pc[l];
+    const size_t off = (size_t)l * T.n + k;
+    const u64 *a = it.a[z / per] + 2 * (z % per) * P, *b = it.b[z / per] + 2 * (z % per) * P;
+    t += 3 * z * P;
+    const u64 a0 = a[off], a1 = a[P + off];
+    const u64 b0 = mont_mul(b[off], pc.r2, pc.q, pc.qinv_neg), b1 = mont_mul(b[P + off], pc.r2, pc.q, pc.qinv_neg);
+    t[off] = mont_mul(a0, b0, pc.q, pc.qinv_neg);
+    t[P + off] = mont_mul(a1, b1, pc.q, pc.qinv_neg);
+    t[2 * P + off] = add_mod(mont_mul(a0, b1, pc.q, pc.qinv_neg), mont_mul(a1, b0, pc.q, pc.qinv_neg), pc.q);
+}
+bool hec_tensor_items(const DevTables &T, u64 *t, const TensorItems &it, int nitems, int per, int nq, hipStream_t st)
+{
+    if (nitems < 1 || nitems > HEC_TENSOR_ITEMS || per < 1 || nq < 1) return false;
+    dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, nitems * per);
+    KLAUNCH("k_tensor", (uint64_t)nq * nitems * per, k_tensor_items, g, dim3(EW_THREADS), 0, st, t, it, (u32)per,
+            (size_t)nq * T.n, T);
+    return true;
+}
 void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, int cnt, hipStream_t st)
 {
     if (cnt <= 0) return;

@@ -175,9 +175,11 @@ struct ChebEval {
     }
 
     // relinearized products of the S pairs: tensor product, ModUp of the s^2
-    // parts, key switch with the relinearization key, ModDown, added to (d0, d1)
-    Ct product(const Ct &u, const Ct &v)
+    // parts, key switch with the relinearization key, ModDown, added to (d0, d1);
+    // the pairs are the items' batches one after the other (S / items.size() each)
+    Ct product(const std::vector<Ct> &us, const std::vector<Ct> &vs)
     {
+        const Ct &u = us[0], &v = vs[0];
         const uint32_t l = u->level, nq = l + 1, nqp = nq + c->k;
         const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
         Ct r = make(l, u->scale * v->scale);
@@ -192,7 +194,20 @@ struct ChebEval {
             c->release(E);
             PFAIL(HEC_ENOMEM, "ciphertext product buffers");
         }
-        hec_tensor(c->T, t, u->d, v->d, (int)nq, (int)S, c->st);
+        if (us.size() == 1) {
+            hec_tensor(c->T, t, u->d, v->d, (int)nq, (int)S, c->st);
+        } else {
+            TensorItems ti{};
+            for (size_t j = 0; j < us.size(); j++) {
+                ti.a[j] = us[j]->d;
+                ti.b[j] = vs[j]->d;
+            }
+            if (!hec_tensor_items(c->T, t, ti, (int)us.size(), (int)(S / us.size()), (int)nq, c->st)) {
+                c->release(t);
+                c->release(E);
+                PFAIL(HEC_EINVAL, "invalid tensor batch");
+            }
+        }
         std::vector<hec_ct> tv(S), ov(S);
         std::vector<const hec_ct *> tp(S);
         std::vector<hec_ct *> op(S);
@@ -254,10 +269,16 @@ struct ChebEval {
             }
             Ct r;
             if (K == 1) {
-                r = product(us[0], vs[0]);
+                r = product(us, vs);
                 rescale(r);
             } else {
-                Ct U = gather(us), V = gather(vs);
+                // the operands read in place (items of the tensor launch) or, beyond
+                // HEC_TENSOR_ITEMS of them, gathered side by side first
+                std::vector<Ct> U = us, V = vs;
+                if (K > HEC_TENSOR_ITEMS) {
+                    U = {gather(us)};
+                    V = {gather(vs)};
+                }
                 const uint32_t S0 = S;
                 S = S0 * (uint32_t)K;
                 try {
