@@ -83,6 +83,7 @@ def _declare(L):
         "orc_keygen_secret": (None, [P, u64, i64p]),
         "orc_keygen_pk": (None, [P, u64, dbl, i64p, u64p]),
         "orc_keygen_swk": (None, [P, u64, dbl, i64p, u32, u64p]),
+        "orc_keygen_swk_limbs": (None, [P, u64, dbl, i64p, u32, u32p, u32, u64p]),
         "orc_keygen_relin": (None, [P, u64, dbl, i64p, u64p]),
         "orc_encrypt": (None, [P, u64p, dbl, u64p, u32, u64, u64, u64p]),
         "orc_decrypt": (None, [P, i64p, u64p, u32, u64p]),
@@ -162,9 +163,14 @@ class Ct:
 class Oracle:
     """The CPU oracle: keys, encoding, encryption and the evaluation steps."""
 
-    def __init__(self, params, seed):
+    def __init__(self, params, seed, key_level=None):
+        """key_level: generate the rotation keys over Q_{key_level} and P only
+        (the other limbs stay zero and are never read), for tests that rotate
+        at low levels of a large parameter set; rotations above that level
+        are refused."""
         self.p = params
         self.seed = seed
+        self.key_level = key_level
         n = params.n
         self.s = np.zeros(n, dtype=np.int64)
         lib().orc_keygen_secret(params.cref, seed, ptr(self.s, i64p))
@@ -176,6 +182,8 @@ class Oracle:
     # ---- keys -----------------------------------------------------------
     def swk(self, g):
         """Rotation key for Galois element g, coefficient form [dnum][2][L+1+k][n]."""
+        if g not in self._swk and self.key_level is not None:
+            self._swk[g] = (None, self._swk_limbs(g, self.qp_index(self.key_level)))
         if g not in self._swk:
             p = self.p
             nl = p.L + 1 + p.k
@@ -186,6 +194,29 @@ class Oracle:
             lib().orc_ntt_limbs(p.cref, ptr(pidx, u32p), 2 * p.dnum * nl, ptr(kn))
             self._swk[g] = (k, kn)
         return self._swk[g]
+
+    def swk_limbs_coeff(self, g, pidx):
+        """The rotation key of g generated on the listed primes only (coefficient
+        form, full layout, other limbs zero)."""
+        p = self.p
+        k = np.zeros((p.dnum, 2, p.L + 1 + p.k, p.n), dtype=np.uint64)
+        pl = u32arr(pidx)
+        lib().orc_keygen_swk_limbs(p.cref, self.seed, p.sigma, ptr(self.s, i64p), g, ptr(pl, u32p), len(pl), ptr(k))
+        return k
+
+    def _swk_limbs(self, g, pidx):
+        # NTT form of the listed limbs only (np.zeros pages never written stay unallocated)
+        p = self.p
+        k = self.swk_limbs_coeff(g, pidx)
+        sel = np.ascontiguousarray(k[:, :, pidx, :]).reshape(-1, p.n)
+        pl = u32arr(list(pidx) * (2 * p.dnum))
+        lib().orc_ntt_limbs(p.cref, ptr(pl, u32p), len(pl), ptr(sel))
+        k[:, :, pidx, :] = sel.reshape(p.dnum, 2, len(pidx), p.n)
+        return k
+
+    def _check_key_level(self, level):
+        if self.key_level is not None and level > self.key_level:
+            raise ValueError("rotation keys were generated up to level %d only" % self.key_level)
 
     def relin_key(self):
         """Relinearization key (s^2 target), coefficient and NTT forms [dnum][2][L+1+k][n]."""
@@ -260,6 +291,7 @@ class Oracle:
 
     # ---- evaluation ---------------------------------------------------------
     def rotate_hoisted(self, ct, steps):
+        self._check_key_level(ct.level)
         p = self.p
         outs, gs, keys = [], [], []
         res = [None] * len(steps)
@@ -334,6 +366,7 @@ class Oracle:
     def keyswitch_raw(self, ct, steps):
         """Per step: the key-switch product (e0, e1) over Q_l and P, coefficient
         form [2][l+1+k][n], before ModDown; None for a zero rotation."""
+        self._check_key_level(ct.level)
         p = self.p
         todo = [i for i, r in enumerate(steps) if r % p.N]
         res = [None] * len(steps)

@@ -587,6 +587,50 @@ void orc_keygen_swk(const orc_params *p, uint64_t seed, double sigma, const int6
     free(sr); free(sg); free(e);
 }
 
+/* The same key restricted to the primes pidx[0..nl) (any subset of all
+ * L+1+k): every limb of a key depends only on its own prime's stream words
+ * (uniform draws at word 2 n i of the stream for prime i) and on the shared
+ * secret and error polynomials, so the listed limbs equal those of
+ * orc_keygen_swk; the others are left untouched.  Same layout
+ * [dnum][2][L+1+k][n].  For tests that rotate only at low levels. */
+void orc_keygen_swk_limbs(const orc_params *p, uint64_t seed, double sigma, const int64_t *s, uint32_t g,
+                          const uint32_t *pidx, uint32_t nl, uint64_t *swk)
+{
+    uint32_t n = p->n, NLK = p->L + 1 + p->k;
+    int64_t *e = malloc(sizeof(int64_t) * n);
+    for (uint32_t j = 0; j < p->dnum; j++) {
+        uint64_t idx = ((uint64_t)g << 8) | j;
+        orc_sample_gauss(seed, P_SWK_E, idx, n, sigma, e);
+#pragma omp parallel for
+        for (uint32_t l = 0; l < nl; l++) {
+            uint32_t pi = pidx[l];
+            uint64_t q = p->mod[pi];
+            uint64_t *b = swk + ((size_t)j * 2 * NLK + pi) * n, *a = b + (size_t)NLK * n;
+            uint64_t *w = malloc(sizeof(uint64_t) * 2 * n), *sr = malloc(sizeof(uint64_t) * n);
+            uint64_t *sg = malloc(sizeof(uint64_t) * n), *er = malloc(sizeof(uint64_t) * n);
+            orc_stream_u64(seed, P_SWK_A, idx, 2ull * pi * n, 2ull * n, w);
+            for (uint32_t t = 0; t < n; t++) {
+                u128 v = ((u128)w[2 * t] << 64) | w[2 * t + 1];
+                a[t] = (uint64_t)(v % q);
+            }
+            orc_reduce_small(p, s, &pi, 1, sr);
+            orc_automorph(p, &pi, 1, g, sr, sg);
+            orc_reduce_small(p, e, &pi, 1, er);
+            orc_polymul(a, sr, b, n, q, p->psi[pi]);
+            uint64_t Pm = 1;
+            for (uint32_t t = 0; t < p->k; t++) Pm = orc_mulmod(Pm, p->mod[p->L + 1 + t] % q, q);
+            int in_digit = pi <= p->L && pi / p->alpha == j;
+            for (uint32_t t = 0; t < n; t++) {
+                uint64_t v = addmod(submod(0, b[t], q), er[t], q);
+                if (in_digit) v = addmod(v, orc_mulmod(Pm, sg[t], q), q);
+                b[t] = v;
+            }
+            free(w); free(sr); free(sg); free(er);
+        }
+    }
+    free(e);
+}
+
 /* Relinearization key: the key-switching key of orc_keygen_swk with s^2 in
  * place of sigma_g(s) (the target of the d2 s^2 term of a product), random
  * streams indexed by the digit alone (Galois elements are odd, so the index

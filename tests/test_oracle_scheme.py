@@ -160,3 +160,82 @@ def test_mul_pt_rescale_add(med):
     assert np.abs(o.decrypt(s) - 2 * z * w).max() < 1e-6
     with pytest.raises(ValueError):
         o.add(prod, ct)
+
+
+def negacyclic(a, b, q):
+    """Schoolbook product in Z_q[x]/(x^n + 1) with Python integers."""
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        ai = int(a[i])
+        if ai == 0:
+            continue
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] += ai * int(b[j])
+            else:
+                out[k - n] -= ai * int(b[j])
+    return [v % q for v in out]
+
+
+def test_keyswitch_raw_pins(small):
+    """The key-switch product before ModDown (lazy ModDown's building block):
+    (1) it is sum_j sigma_g(ModUp_j(c1)) * swk_{g,j} over Q_l and P, recomputed
+    with the schoolbook negacyclic product and Python integers; (2) ModDown of
+    it plus sigma_g(c0) is the rotation itself, bit for bit, at full and
+    partial-digit levels."""
+    p, o = small
+    rng = np.random.default_rng(11)
+    z = rng.uniform(-1, 1, p.N)
+    for level in (4, 2):
+        ct = o.encrypt(o.encode(z, level, 2.0 ** 30), seed=5, index=level)
+        steps = [1, 3, -2]
+        raw = o.keyswitch_raw(ct, steps)
+        rots = o.rotate_hoisted(ct, steps)
+        qp = o.qp_index(level)
+        nqp = len(qp)
+        beta = (level + p.alpha) // p.alpha
+        D = []
+        for j in range(beta):
+            out = np.zeros((nqp, p.n), dtype=np.uint64)
+            ckks.lib().orc_modup(p.cref, level, j, ckks.ptr(np.ascontiguousarray(ct.data[1])), ckks.ptr(out))
+            D.append(out)
+        for s, e, rc in zip(steps, raw, rots):
+            g = p.galois(s)
+            kc = o.swk(g)[0]                     # coefficient form [dnum][2][L+1+k][n]
+            for o_, pi in enumerate(qp):
+                q = p.mod[pi]
+                acc0, acc1 = [0] * p.n, [0] * p.n
+                for j in range(beta):
+                    d = o.automorph([pi], D[j][o_:o_ + 1], g)[0]
+                    acc0 = [(x + y) % q for x, y in zip(acc0, negacyclic(d, kc[j][0][pi], q))]
+                    acc1 = [(x + y) % q for x, y in zip(acc1, negacyclic(d, kc[j][1][pi], q))]
+                assert [int(v) for v in e[0][o_]] == acc0, (level, s, pi)
+                assert [int(v) for v in e[1][o_]] == acc1, (level, s, pi)
+            qi = list(range(level + 1))
+            c0g = o.automorph(qi, ct.data[0], g)
+            f0 = o.add_limbs(qi, c0g, o.moddown(level, e[0]))
+            f1 = o.moddown(level, e[1])
+            assert (f0 == rc.data[0]).all() and (f1 == rc.data[1]).all(), (level, s)
+
+
+def test_keygen_limb_subset(med):
+    """Keys generated on a subset of the primes (for low-level tests of large
+    parameter sets) equal the full keys on those limbs, and rotations with
+    them equal rotations with the full keys bit for bit."""
+    p, o = med
+    g = p.galois(3)
+    full = o.swk(g)[0]
+    pidx = o.qp_index(2)
+    sub = o.swk_limbs_coeff(g, pidx)
+    assert (sub[:, :, pidx, :] == full[:, :, pidx, :]).all()
+    others = [i for i in range(p.L + 1 + p.k) if i not in pidx]
+    assert not sub[:, :, others, :].any()
+    o2 = ckks.Oracle(p, o.seed, key_level=2)
+    z = np.random.default_rng(8).uniform(-1, 1, p.N)
+    ct = o.encrypt(o.encode(z, 2, 2.0 ** 40), seed=6)
+    for a, b in zip(o.rotate_hoisted(ct, [3, 1]), o2.rotate_hoisted(ct, [3, 1])):
+        assert (a.data == b.data).all()
+    with pytest.raises(ValueError):
+        o2.rotate(o.encrypt(o.encode(z, 3, 2.0 ** 40), seed=6), 3)
