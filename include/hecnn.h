@@ -198,8 +198,12 @@ hec_status he_image_channel_shard(const hec_image *img, uint32_t u, int32_t *cha
  * host doubles), Section 4.1: partial convolutions over hoisted rotations of
  * every input shard, fused weight x shift-mask plaintexts, one rescale per
  * output shard; stride 2 = stride-1 convolution + the downsampling of
- * Section 4.2.  bias must be NULL (reserved).  Consumes one level (three for
- * stride 2 with the two-level downsample). */
+ * Section 4.2.  w holds Co x C x kh x kw doubles, C the input image's channel
+ * count (he_image_info).  bias (nullable): Co doubles, the per-channel shift
+ * of an inference batch norm folded into the convolution (Section 4.3,
+ * "Batch Normalization"), added to the output as he_image_add_bias does (one
+ * plaintext per output shard at the output's level and scale).  Consumes one
+ * level (three for stride 2 with the two-level downsample). */
 hec_status he_conv2d_sharded(hec_ctx *ctx, const hec_image *in, const double *w, uint32_t Co, uint32_t kh,
                              uint32_t kw, uint32_t stride, uint32_t pad, const double *bias, hec_image **out);
 /* The same split in two: plan once (weights encoded and kept in device memory
@@ -348,6 +352,14 @@ hec_status hec_prof_start(hec_ctx *ctx, const char *kernel);
 hec_status hec_prof_stop(hec_ctx *ctx, uint64_t *launches, uint64_t *units, double *total_ms);
 /* Launches of the named kernel since the library was loaded (all contexts). */
 uint64_t hec_prof_launches(const char *kernel);
+/* The thresholds of the discrete Gaussian sampler (Background, "Homomorphic
+ * encryption": the error polynomials of keys and encryptions; sigma as in
+ * hec_params): T[i] = floor(2^63 * sum_{|x| <= i} w(x) / sum_{|x| <= 19} w(x)),
+ * w(x) = exp(-x^2 / (2 sigma^2)), i < 19; a draw takes the 63-bit value v and
+ * returns the smallest i with v < T[i] (19 if none), signed by one more bit.
+ * Host only (no device needed); cap >= 19; HEC_EINVAL for sigma outside
+ * [2, 8], which hec_ctx_create rejects too. */
+hec_status hec_gauss_table(double sigma, uint64_t *T, size_t cap);
 
 #ifdef __cplusplus
 }

@@ -249,7 +249,7 @@ static hec_status build_tables(hec_ctx *c)
     c->d_pmodq_m = c->alloc(NLK);
     HEC_CHECK(upload(c->d_pmodq_m, pmm.data(), NLK * 8, c->st));
     u64 gT[19];
-    gauss_table(c->prm.sigma, gT);
+    if (!gauss_table(c->prm.sigma, gT)) HEC_FAIL(HEC_EINVAL, "sigma must be in [2, 8]");
     c->d_gauss = c->alloc(19);
     HEC_CHECK(upload(c->d_gauss, gT, sizeof(gT), c->st));
 
@@ -310,6 +310,7 @@ extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_
     uint32_t alpha = (p->L + 1 + p->dnum - 1) / p->dnum;
     if (alpha > HEC_MAX_BCONV_IN) HEC_FAIL(HEC_EINVAL, "digits larger than 16 primes are not supported");
     if (p->secret_dist != 0) HEC_FAIL(HEC_EINVAL, "only the uniform ternary secret is supported");
+    if (!(p->sigma >= 2.0 && p->sigma <= 8.0)) HEC_FAIL(HEC_EINVAL, "sigma must be in [2, 8]");
     int ndev = 0;
     HEC_TRY_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) HEC_FAIL(HEC_EDEVICE, "no HIP device %d", device);
@@ -378,6 +379,15 @@ extern "C" hec_status hec_ctx_primes(const hec_ctx *c, uint64_t *primes, size_t 
 }
 
 extern "C" uint32_t hec_ctx_slots(const hec_ctx *c) { return c ? c->N : 0; }
+
+extern "C" hec_status hec_gauss_table(double sigma, uint64_t *T, size_t cap)
+{
+    if (!T || cap < 19) HEC_FAIL(HEC_EINVAL, "the table has 19 entries");
+    u64 t[19];
+    if (!gauss_table(sigma, t)) HEC_FAIL(HEC_EINVAL, "sigma must be in [2, 8]");
+    memcpy(T, t, sizeof(t));
+    return HEC_OK;
+}
 
 extern "C" uint64_t hec_ctx_keyswitch_count(const hec_ctx *c) { return c ? c->ks_count : 0; }
 

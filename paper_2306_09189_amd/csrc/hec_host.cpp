@@ -80,20 +80,6 @@ uint64_t find_root_2n(uint64_t q, uint32_t n)
 
 uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
 
-void gauss_table(double sigma, uint64_t T[19])
-{
-    long double w[20], tot = 0;
-    for (int i = 0; i <= 19; i++) {
-        w[i] = (i ? 2.0L : 1.0L) * expl(-(long double)(i * i) / (2.0L * sigma * sigma));
-        tot += w[i];
-    }
-    long double acc = 0;
-    for (int i = 0; i < 19; i++) {
-        acc += w[i];
-        T[i] = (uint64_t)floorl(acc / tot * 9223372036854775808.0L);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // double-double arithmetic (Dekker / Knuth error-free transformations)
 // ---------------------------------------------------------------------------
@@ -171,7 +157,64 @@ void sincos_dd(dd x, dd &c, dd &s)
     c = sum;
 }
 
+// exp(x) for x <= 0 in double-double: x = k ln 2 + r (|r| <= ln2 / 2), exp(r / 2^8)
+// by its Taylor series, squared eight times, scaled by 2^k
+const dd LN2 = {6.931471805599452862e-01, 2.319046813846299558e-17};
+dd exp_dd(dd x)
+{
+    const double k = std::nearbyint(x.h / LN2.h);
+    dd r = sub(x, mul_d(LN2, k));
+    r = {std::ldexp(r.h, -8), std::ldexp(r.l, -8)};
+    dd term = {1.0, 0.0}, sum = term;
+    for (int i = 1; i < 30; i++) {
+        term = div_d(mul(term, r), (double)i);
+        sum = add(sum, term);
+        if (std::fabs(term.h) < 1e-40) break;
+    }
+    for (int i = 0; i < 8; i++) sum = mul(sum, sum);
+    return {std::ldexp(sum.h, (int)k), std::ldexp(sum.l, (int)k)};
+}
+inline dd div_dd(dd a, dd b)
+{
+    double q1 = a.h / b.h;
+    dd r = sub(a, mul_d(b, q1));
+    double q2 = r.h / b.h;
+    r = sub(r, mul_d(b, q2));
+    double q3 = r.h / b.h;
+    return add(quick(q1, q2), dd{q3, 0.0});
+}
+// floor of a non-negative double-double below 2^64
+uint64_t floor_dd(dd x)
+{
+    const double fh = std::floor(x.h);
+    dd f = two_sum(x.h - fh, x.l);  // x.h - fh is exact
+    double ff = std::floor(f.h);
+    if (ff == f.h && f.l < 0) ff -= 1;
+    return (uint64_t)fh + (uint64_t)(int64_t)ff;
+}
+
 }  // namespace
+
+// T[i] = floor(2^63 * sum_{|x| <= i} w(x) / sum_{|x| <= 19} w(x)), w(x) = exp(-x^2 / (2 sigma^2)),
+// evaluated in double-double (about 100 bits): the thresholds of the table inversion sampler
+bool gauss_table(double sigma, uint64_t T[19])
+{
+    if (!(sigma >= 2.0 && sigma <= 8.0)) return false;
+    const dd den = mul_d(two_prod(sigma, sigma), 2.0);
+    dd w[20], tot = {0.0, 0.0};
+    for (int i = 0; i <= 19; i++) {
+        w[i] = exp_dd(neg(div_dd(dd{(double)(i * i), 0.0}, den)));
+        if (i) w[i] = mul_d(w[i], 2.0);
+        tot = add(tot, w[i]);
+    }
+    dd acc = {0.0, 0.0};
+    for (int i = 0; i < 19; i++) {
+        acc = add(acc, w[i]);
+        dd v = div_dd(acc, tot);
+        T[i] = floor_dd({std::ldexp(v.h, 63), std::ldexp(v.l, 63)});
+    }
+    return true;
+}
 
 EncoderTables::EncoderTables(uint32_t logn)
 {

@@ -17,8 +17,10 @@ uint64_t find_prime(uint32_t bits, uint32_t n, const std::vector<uint64_t> &take
 uint64_t find_root_2n(uint64_t q, uint32_t n);  // element of order 2n
 uint64_t shoup_of(uint64_t w, uint64_t q);       // floor(w * 2^64 / q)
 
-// Gaussian cumulative table (sigma, |x| <= 19), 63-bit thresholds.
-void gauss_table(double sigma, uint64_t T[19]);
+// Gaussian cumulative table (sigma, |x| <= 19), 63-bit thresholds, exact unless
+// a threshold lies within ~2^-40 of an integer; false for sigma outside [2, 8]
+// (below 2 the tail beyond 19 is too small for the ~100-bit evaluation).
+bool gauss_table(double sigma, uint64_t T[19]);
 
 // Tables of the slot encoder (the transforms run on the GPU): tw[4e .. 4e+3] =
 // cos(pi e / n) and sin(pi e / n) as double-double pairs (hi, lo, hi, lo), e < 2n,

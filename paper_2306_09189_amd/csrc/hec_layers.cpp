@@ -1637,11 +1637,20 @@ extern "C" hec_status he_conv2d_sharded(hec_ctx *c, const hec_image *in, const d
 {
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (bias) HEC_FAIL(HEC_EINVAL, "bias is reserved and must be NULL");
     hec_conv_plan *p = nullptr;
     HEC_CHECK(he_conv2d_plan_create(c, in, w, Co, kh, kw, stride, pad, &p));
-    hec_status s = he_conv2d_plan_run(c, p, in, out);
+    hec_image *conv = nullptr;
+    hec_status s = he_conv2d_plan_run(c, p, in, &conv);
     he_conv2d_plan_free(p);
+    if (s != HEC_OK || !bias) {
+        *out = conv;
+        return s;
+    }
+    // the shift of a folded batch norm: one plaintext per output shard at the
+    // output's level and scale (after the downsampling of a strided
+    // convolution, which only selects pixels)
+    s = he_image_add_bias(c, conv, bias, out);
+    hec_image_free(conv);
     return s;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
-    "he_conv2d_plan_create_ex",
+    "he_conv2d_plan_create_ex", "hec_gauss_table",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
             "hec_prof_stop": (c, [vp, u64p, u64p, dblp]),
             "hec_prof_launches": (u64, [ctypes.c_char_p]),
             "he_image_channel_shard": (c, [vp, u32, i32p, i32p]),
+            "hec_gauss_table": (c, [dbl, u64p, sz]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -131,6 +132,13 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def gauss_table(sigma):
+    """The 19 thresholds of the library's discrete Gaussian sampler (host only)."""
+    T = np.zeros(19, dtype=np.uint64)
+    check(lib().hec_gauss_table(float(sigma), _p(T, u64p), len(T)))
+    return T
 
 
 def check(status):
@@ -248,6 +256,15 @@ class Image(_Handle):
         lvl, sc = ctypes.c_uint32(), ctypes.c_double()
         check(lib().ckks_ct_info(h, ctypes.byref(lvl), ctypes.byref(sc)))
         return lvl.value, sc.value
+
+    def shard_decrypt(self, u):
+        """The N slot values of shard u (client side: decrypt and decode)."""
+        h = lib().he_image_shard(self.h, u)
+        if not h:
+            raise IndexError(u)
+        z = np.zeros(self.ctx.N)
+        check(lib().ckks_decrypt(self.ctx.h, h, _p(z, dblp), len(z)))
+        return z
 
     def decrypt(self):
         C, H, W, mp, t = self.info()
@@ -486,18 +503,33 @@ class Context:
         check(lib().he_image_encrypt(self.h, _p(x, dblp), C, H, W, level, seed, ctypes.byref(out)))
         return Image(self, out.value)
 
-    def conv2d(self, img, w, stride=1, pad=1):
+    @staticmethod
+    def _conv_weights(img, w):
         w = _arr(w, np.float64)
+        if w.ndim != 4:
+            raise ValueError("weights must be [Co][Ci][kh][kw]")
+        if w.shape[1] != img.info()[0]:
+            raise ValueError("weights have %d input channels, the image %d" % (w.shape[1], img.info()[0]))
+        return w
+
+    def conv2d(self, img, w, stride=1, pad=1, bias=None):
+        """bias: Co per-channel shifts (a folded batch norm) added to the output, or None."""
+        w = self._conv_weights(img, w)
         Co, Ci, kh, kw = w.shape
+        b = None
+        if bias is not None:
+            b = _arr(bias, np.float64)
+            if b.shape != (Co,):
+                raise ValueError("bias must hold Co = %d values" % Co)
         out = vp()
-        check(lib().he_conv2d_sharded(self.h, img.h, _p(w, dblp), Co, kh, kw, stride, pad, None,
-                                      ctypes.byref(out)))
+        check(lib().he_conv2d_sharded(self.h, img.h, _p(w, dblp), Co, kh, kw, stride, pad,
+                                      None if b is None else _p(b, dblp), ctypes.byref(out)))
         return Image(self, out.value)
 
     def conv2d_plan(self, like, w, stride=1, pad=1, q_only=False, basis=None):
         """q_only: weight plaintexts over Q only (modes 0 and 1), for layers too large otherwise.
         basis = s: weight plaintexts in basis-mask form, tap masks per block encoded at 2^s (modes 0-2)."""
-        w = _arr(w, np.float64)
+        w = self._conv_weights(like, w)
         Co, Ci, kh, kw = w.shape
         out = vp()
         flags = (1 if q_only else 0) | ((2 | (int(basis) << 8)) if basis is not None else 0)

@@ -70,6 +70,38 @@ def test_add_bias_bit_exact(deep, shape):
     assert np.abs(out.decrypt() - (x + bias[:, None, None])).max() < 1e-6
 
 
+@pytest.mark.parametrize("shape,Co,stride", [((4, 16, 16), 4, 1), ((4, 16, 16), 8, 2), ((3, 8, 8), 5, 1)])
+def test_conv_bias_bit_exact(deep, shape, Co, stride):
+    """he_conv2d_sharded with its bias argument (the shift of a folded batch
+    norm, Section 4.3): the oracle's convolution followed by its per-channel
+    bias addition, bit for bit; a bias of the wrong length is refused by the
+    binding, weights whose input-channel count differs from the image's too."""
+    ctx, prm, o = deep
+    rng = np.random.default_rng(sum(shape) + Co)
+    x = rng.uniform(-1, 1, shape)
+    w = rng.normal(0, 0.2, (Co, shape[0], 3, 3))
+    bias = rng.normal(0, 0.5, Co)
+    img, cts, lay = encrypt_both(ctx, prm, o, x, 6, 22)
+    plan = ctx.conv2d_plan(img, w, stride=stride)
+    ctx.gen_rotation_keys(plan.steps())
+    out = ctx.conv2d(img, w, stride=stride, bias=bias)
+    be = hl.CkksBackend(o)
+    oc, ol = hl.conv2d(be, cts, lay, w, pad=1, stride=stride)
+    oc = hl.add_bias(be, oc, ol, bias)
+    assert out.info()[4] == len(oc)
+    for u in range(len(oc)):
+        assert out.shard_info(u) == (oc[u].level, oc[u].scale)
+        assert (out.shard_export(u) == oc[u].data).all(), u
+    ref = hl.ref_conv2d(x, w, 1, stride) + bias[:, None, None]
+    assert np.abs(out.decrypt() - ref).max() < 1e-5
+    with pytest.raises(ValueError):
+        ctx.conv2d(img, w, stride=stride, bias=bias[:-1])
+    with pytest.raises(ValueError):
+        ctx.conv2d(img, w[:, :-1], stride=stride)
+    with pytest.raises(ValueError):
+        ctx.conv2d_plan(img, w[:, :-1])
+
+
 def block_case(ctx, prm, o, shape, Co, mode, seed, bn2=True):
     rng = np.random.default_rng(seed)
     C_, H, W = shape

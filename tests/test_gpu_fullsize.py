@@ -18,6 +18,7 @@ import sys
 import numpy as np
 import pytest
 
+from checks import check_ct_decrypt_vs_oracle, check_decrypt_vs_oracle
 from oracle import ckks
 from oracle import he_layers as hl
 
@@ -60,6 +61,7 @@ def test_encrypt_and_rotations(full):
         for s, r, orr in zip(steps, rots, orots):
             assert (r.export() == orr.data).all(), (lvl, s)
         assert np.abs(ctx.decrypt(rots[0]) - np.roll(z, -1)).max() < 1e-6
+        check_ct_decrypt_vs_oracle(ctx, rots[0], o, orots[0])
 
 
 def test_mac_rescale(full):
@@ -76,6 +78,7 @@ def test_mac_rescale(full):
     oprod = o.rescale(o.mul_pt(oct_, opt))
     assert (prod.export() == oprod.data).all()
     assert np.abs(ctx.decrypt(prod) - z * w).max() < 1e-9
+    check_ct_decrypt_vs_oracle(ctx, prod, o, oprod)
 
 
 def test_conv_112_shard_bit_exact(full):
@@ -97,6 +100,7 @@ def test_conv_112_shard_bit_exact(full):
     oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+    check_decrypt_vs_oracle(out, o, oc)
 
 
 def test_conv_112_shard_lazy_bit_exact(full):
@@ -118,6 +122,7 @@ def test_conv_112_shard_lazy_bit_exact(full):
     assert out.shard_info(0) == (oc[0].level, oc[0].scale)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+    check_decrypt_vs_oracle(out, o, oc)
 
 
 def test_conv_112_shard_basis_bit_exact(full):
@@ -143,6 +148,7 @@ def test_conv_112_shard_basis_bit_exact(full):
         assert out.shard_info(0) == (oc[0].level, oc[0].scale)
         assert (out.shard_export(0) == oc[0].data).all()
         assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+        check_decrypt_vs_oracle(out, o, oc)
 
 
 def test_conv_112_shard_bsgs_bit_exact(full):
@@ -165,6 +171,44 @@ def test_conv_112_shard_bsgs_bit_exact(full):
     assert out.shard_info(0) == (oc[0].level, oc[0].scale)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+    check_decrypt_vs_oracle(out, o, oc)
+
+
+@pytest.mark.timeout(900)
+def test_conv_112_four_shards_eight_outputs_bit_exact(full):
+    """Four input shards (8 channels of 112x112, two per ciphertext) into
+    eight output shards (16 channels) at level 11 (two key-switch digits), in
+    the batched, lazy-ModDown and baby-step/giant-step forms: every output
+    sums all four inputs, so the product kernels run with eight outputs per
+    launch (the many-output key-switch kernel in the lazy forms); every
+    output shard bit-exact with the oracle and its decryption within 2^-20 of
+    the oracle's."""
+    ctx, prm, o = full
+    rng = np.random.default_rng(6)
+    x = np.clip(rng.normal(0, 1, (8, 112, 112)), -4, 4)
+    w = rng.normal(0, 0.05, (16, 8, 3, 3))
+    lvl = 11
+    img = ctx.image_encrypt(x, lvl, 3006)
+    assert img.info()[4] == 4
+    lay = hl.natural_layout(prm.N, 8, 112, 112)
+    cts = [o.encrypt(o.encode(v, lvl, 2.0 ** LS), seed=3006, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    for u in range(4):
+        assert (img.shard_export(u) == cts[u].data).all()
+    plan = ctx.conv2d_plan(img, w)
+    ctx.gen_rotation_keys(plan.steps())
+    ref = hl.ref_conv2d(x, w, 1)
+    for mode in (0, 2, 3):
+        plan.set_mode(mode)
+        out = plan.run(img)
+        log("oracle 4 -> 8 shard conv, mode %d" % mode)
+        oc, ol = hl.conv2d(hl.CkksBackend(o), cts, lay, w, pad=1, lazy=(mode == 2), bsgs=(mode == 3))
+        assert out.info()[4] == len(oc) == 8
+        for v in range(8):
+            assert out.shard_info(v) == (oc[v].level, oc[v].scale)
+            assert list(out.block_map(v)) == list(ol.shards[v])
+            assert (out.shard_export(v) == oc[v].data).all(), (mode, v)
+        assert np.abs(out.decrypt() - ref).max() < 1e-5
+        check_decrypt_vs_oracle(out, o, oc)
 
 
 def test_benchmark_step_accuracy(full):
@@ -298,6 +342,7 @@ def test_conv_uneven_levels_bit_exact(full, level, mode):
     assert out.shard_info(0) == (oc[0].level, oc[0].scale)
     assert (out.shard_export(0) == oc[0].data).all()
     assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1)).max() < 1e-5
+    check_decrypt_vs_oracle(out, o, oc)
 
 
 def test_stem_channel_shards_full(full):

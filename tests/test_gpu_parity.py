@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+from checks import check_ct_decrypt_vs_oracle, check_decrypt_vs_oracle, prm_log_scale, run_pipeline
 from oracle import ckks
 from oracle import he_layers as hl
 
@@ -130,53 +131,6 @@ def test_rescale_mul_add_bit_exact(small):
     with pytest.raises(hecnn.HecError) as e:
         ctx.add(prod, ct)
     assert e.value.status == hecnn.HEC_ELEVEL
-
-
-def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1, basis=None, tol=1e-5):
-    """Encrypt x on both sides, apply ops ('conv', w, stride) / ('pool',),
-    compare every shard bit for bit after every op; return final decryption.
-    mode 2 runs the convolutions with lazy ModDown on both sides; basis = s
-    builds their weight plaintexts in basis-mask form on both sides."""
-    C, H, W = x.shape
-    img = ctx.image_encrypt(x, level, seed)
-    lay = hl.natural_layout(prm.N, C, H, W)
-    be = hl.CkksBackend(o, basis=basis)
-    cts = [o.encrypt(o.encode(v, level, 2.0 ** prm_log_scale(ctx)), seed=seed, index=u)
-           for u, v in enumerate(hl.pack(x, lay))]
-    for u in range(len(cts)):
-        assert (img.shard_export(u) == cts[u].data).all(), "encrypt shard %d" % u
-    ref = x
-    for op in ops:
-        if op[0] == "conv":
-            w, stride = op[1], op[2]
-            plan = ctx.conv2d_plan(img, w, stride=stride, pad=pad, basis=basis)
-            plan.set_mode(mode)
-            ctx.gen_rotation_keys(plan.steps())
-            img = plan.run(img)
-            cts, lay = hl.conv2d(be, cts, lay, w, pad=pad, stride=stride, lazy=(mode == 2), bsgs=(mode == 3))
-            ref = hl.ref_conv2d(ref, w, pad, stride)
-        else:
-            ctx.gen_rotation_keys(ctx.avgpool_steps(img))
-            img = ctx.avgpool(img, mode=mode if mode >= 2 else 0)
-            cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode == 2), bsgs=(mode == 3))
-            ref = hl.ref_avgpool2x2(ref)
-        Cn, Hn, Wn, mp, t = img.info()
-        assert t == len(cts) and (Hn, Wn, mp) == (lay.H, lay.W, lay.mp)
-        for u in range(t):
-            if lay.kind == "channel":
-                assert img.channel_shard(u) == tuple(lay.shards[u])
-            else:
-                assert list(img.block_map(u)) == list(lay.shards[u])
-            assert img.shard_info(u) == (cts[u].level, cts[u].scale)
-            assert (img.shard_export(u) == cts[u].data).all(), (op[0], u)
-        log("  op %s ok: %d shards, level %d" % (op[0], t, cts[0].level))
-    got = img.decrypt()
-    assert np.abs(got - ref).max() < tol
-    return got
-
-
-def prm_log_scale(ctx):
-    return ctx.prm.log_scale
 
 
 @pytest.mark.parametrize("shape,ops", [
