@@ -53,7 +53,7 @@ KERNELS = {
                          "per_unit": 8 * (1 << 15) / 1e12, "bytes_per_unit": 2 * LIMB_BYTES,
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
 }
-DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac"}
+DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac", 4: "k_ntt16_fwd_rows"}
 
 
 def read_traffic(path):
@@ -115,10 +115,10 @@ def cpu_baseline(n_rot, seconds, mode):
     """The CPU oracle (plain C, __int128 arithmetic, OpenMP over limbs) on a
     bounded sample of the same work as the timed step, repeated until `seconds`
     of CPU work; keys and weight plaintexts prepared outside the timed part.
-    Modes 0/1: batches of n_rot hoisted key-switched rotations of one level-20
-    ciphertext, each multiplied by a weight plaintext and summed.  Mode 2 (lazy
-    ModDown): the key-switch products of n_rot rotations multiplied by the
-    weights over Q*P, summed, and one ModDown."""
+    Modes 0/1/4: batches of n_rot hoisted key-switched rotations of one
+    level-20 ciphertext, each multiplied by a weight plaintext and summed.
+    Mode 2 (lazy ModDown): the key-switch products of n_rot rotations
+    multiplied by the weights over Q*P, summed, and one ModDown."""
     from oracle import ckks
     prm = ckks.Params(LOGN, [Q0] + [QB] * L, [PB] * K, DNUM)
     o = ckks.Oracle(prm, 2002)
@@ -158,10 +158,91 @@ def cpu_baseline(n_rot, seconds, mode):
         dt = time.perf_counter() - t
         if dt >= seconds:
             break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": reps * n_rot / dt, "unit": "key-switched rotations/s", "cores": cores, "kind": "oracle",
-            "sample": "%d x %d rotations of one level-20 ciphertext (%s), 2N=2^16, dnum=3, OpenMP over limbs "
-                      "(%.1f s)" % (reps, n_rot, what, dt)}
+    return {"value": reps * n_rot / dt, "what": what, "reps": reps, "seconds": dt}
+
+
+def host_cpu():
+    """nproc and the CPU model of this host (lscpu)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=20).stdout.strip())
+    except Exception:
+        nproc = os.cpu_count()
+    return nproc, model
+
+
+def cpu_baseline_runs(n_rot, seconds, mode):
+    """The oracle timed single-threaded and with OpenMP on the host's threads,
+    each in its own process (OMP_NUM_THREADS is read at OpenMP start-up)."""
+    import subprocess
+    nproc, model = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc or 1))
+    res = {}
+    for label, nt in (("single_thread", 1), ("openmp", threads)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(nt))
+        code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+                "print(json.dumps(bench.cpu_baseline(%d, %f, %d)))" % (ROOT, n_rot, seconds, mode))
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError("cpu baseline failed: %s" % r.stderr[-2000:])
+        res[label] = dict(json.loads(r.stdout.strip().splitlines()[-1]), threads=nt)
+    o = res["openmp"]
+    return {"value": o["value"], "unit": "key-switched rotations/s", "cores": o["threads"], "kind": "oracle",
+            "sample": "%d x %d rotations of one level-20 ciphertext (%s), 2N=2^16, dnum=3 (%.1f s); "
+                      "OpenMP over limbs" % (o["reps"], n_rot, o["what"], o["seconds"]),
+            "single_thread_value": res["single_thread"]["value"],
+            "single_thread_sample": "%d x %d rotations (%.1f s)" % (res["single_thread"]["reps"], n_rot,
+                                                                   res["single_thread"]["seconds"]),
+            "host_nproc": nproc, "host_cpu_model": model}
+
+
+def timed(ctx, fn, reps, warm=1):
+    """Median wall ms of fn() over reps calls (after warm untimed ones), the
+    device drained before and after each."""
+    for _ in range(warm):
+        r = fn()
+        ctx.sync()
+        del r
+    ts = []
+    for _ in range(reps):
+        ctx.sync()
+        t = time.perf_counter()
+        r = fn()
+        ctx.sync()
+        ts.append((time.perf_counter() - t) * 1e3)
+        del r
+    return float(np.median(ts))
+
+
+def rotation_roofline(rate, level):
+    """Roofline fractions of complete hoisted key-switched rotations at `level`
+    (2N = 2^16, dnum = 3, k = 8): algorithmic bytes per rotation 4 (l+1) + 2 beta
+    (l+1+k) limbs (ciphertext in and out, the key), modular multiplications of
+    an extra hoisted rotation (key-switch inner product, ModDown: INTT of the
+    P limbs, P -> Q conversion, NTT) at 10 VALU multiply instructions each."""
+    nq, k, alpha = level + 1, K, 9
+    beta = (nq + alpha - 1) // alpha
+    limbs = 4 * nq + 2 * beta * (nq + k)
+    nbytes = limbs * LIMB_BYTES
+    n, logn = 1 << LOGN, LOGN
+    modmul = (2 * beta * (nq + k)            # inner product per coefficient
+              + 2 * k * nq                   # P -> Q conversion per coefficient
+              + 2 * nq + 2 * k) * n          # scaling by P^-1, ... per coefficient (combine, INTT n^-1)
+    modmul += (2 * k + 2 * nq) * (n // 2) * logn   # the INTT of the P limbs and the NTT of the Q limbs
+    peak_valu = 256 * 64 * 2.4e9 / 10
+    return {"rotations_per_s": rate, "level": level, "bytes_per_rotation": nbytes,
+            "hbm_GBps": rate * nbytes / 1e9, "hbm_peak_GBps": 8000.0, "hbm_frac": rate * nbytes / 8e12,
+            "modmul_per_rotation": modmul, "valu_Tmodmul_s": rate * modmul / 1e12,
+            "valu_peak_Tmodmul_s": peak_valu / 1e12, "valu_frac": rate * modmul / peak_valu}
 
 
 def main():
@@ -169,22 +250,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-rotations", type=int, default=12)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--reps", type=int, default=20, help="repetitions of every sub-measurement (median)")
+    ap.add_argument("--cpu-rotations", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain-reps", type=int, default=2)
-    ap.add_argument("--mode", type=int, default=2, choices=(0, 1, 2, 3),
-                    help="plan mode of the timed step: 0 batched, 1 plain, 2 lazy ModDown, "
-                         "3 baby-step/giant-step with double hoisting")
+    ap.add_argument("--skip", default="", help="comma list of extra sections to skip: "
+                    "layers,other,rot,gelu,block,linear,imagenet,uneven,serving")
+    ap.add_argument("--mode", type=int, default=0, choices=(0, 1, 2, 3, 4),
+                    help="plan mode of the timed step: 0 batched (complete key-switched rotations), 1 plain, "
+                         "2 lazy ModDown, 3 baby-step/giant-step with double hoisting, 4 key-stationary")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
-    ap.add_argument("--profile-run", choices=("gelu", "block"),
-                    help="for kernel traces: five degree-59 GELU evaluations on one level-20 ciphertext, or five "
-                         "runs of the 16x32x32 block, then exit")
+    ap.add_argument("--profile-run", choices=("gelu", "block", "imagenet", "rotations"),
+                    help="for kernel traces: five degree-59 GELU evaluations, five runs of the 16x32x32 block, "
+                         "the 112x112x64 stage in mode 4, or 5 x 32 hoisted rotations at level 20, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         eprint("bench.py measures one GPU: the whole path runs on a single MI355X "
                "(sharding across GPUs is described, not implemented); use --gpus 1")
         sys.exit(2)
+    skip = set(x for x in args.skip.split(",") if x)
 
     import torch
     from paper_2306_09189_amd import hecnn
@@ -196,19 +280,20 @@ def main():
     x = rng.uniform(-1, 1, (32, 32, 32))
     w1 = rng.normal(0, 0.05, (32, 32, 3, 3))
     w2 = rng.normal(0, 0.05, (64, 32, 3, 3))
-    if args.profile_run:
-        from numpy.polynomial import chebyshev as Cheb
+    from numpy.polynomial import chebyshev as Cheb
 
-        def gelu_f(v):
-            return 0.5 * v * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (v + 0.044715 * v ** 3)))
-        coef = Cheb.chebinterpolate(lambda y: gelu_f(15.0 * y), 59)
+    def gelu(v):
+        return 0.5 * v * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (v + 0.044715 * v ** 3)))
+    bound = 15.0
+    coef = Cheb.chebinterpolate(lambda y: gelu(bound * y), 59)
+    if args.profile_run:
         ctx.keygen(2002)
         if args.profile_run == "gelu":
             ct = ctx.encrypt(ctx.encode(rng.uniform(-1, 1, ctx.N), LEVEL, 2.0 ** LOG_SCALE), 6)
             for _ in range(5):
                 r = ctx.cheb_eval(ct, coef, -1.0, 1.0)
                 del r
-        else:
+        elif args.profile_run == "block":
             xb = rng.uniform(-1, 1, (16, 32, 32))
             wb1, wb2 = rng.normal(0, 1 / 12.0, (16, 16, 3, 3)), rng.normal(0, 1 / 12.0, (16, 16, 3, 3))
             bn = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
@@ -218,7 +303,31 @@ def main():
             for _ in range(5):
                 ob = blk.run(imb)
                 del ob
+        elif args.profile_run == "imagenet":
+            xi = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
+            wi = rng.normal(0, 0.05, (64, 64, 3, 3))
+            imi = ctx.image_encrypt(xi, LEVEL, 9)
+            pi = ctx.conv2d_plan(imi, wi, basis=27)
+            pi.set_mode(4)
+            ctx.gen_rotation_keys(pi.steps())
+            yi = pi.run(imi)
+            ctx.gen_rotation_keys(ctx.avgpool_steps(yi))
+            for _ in range(3):
+                yi = pi.run(imi)
+                zi = ctx.avgpool(yi, 4)
+                del zi
+        else:
+            ctx.gen_rotation_keys(list(range(1, 33)))
+            ct = ctx.encrypt(ctx.encode(rng.uniform(-1, 1, ctx.N), LEVEL, 2.0 ** LOG_SCALE), 5)
+            for _ in range(5):
+                rs = ctx.rotate_hoisted(ct, list(range(1, 33)))
+                del rs
         ctx.sync()
+        # a plain device copy of exactly 256 MiB last: it calibrates the byte counters of a --pmc pass
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
         eprint("profile run done")
         return
     if args.pmc_run:
@@ -255,7 +364,7 @@ def main():
     eprint("setup %.2f s, rotation keys %.1f GiB" % (setup_s, ctx.key_bytes() / 2 ** 30))
     del o1
 
-    from oracle import he_layers as hl  # FP64 reference for the accuracy check only
+    from oracle import he_layers as hl  # FP64 references for the accuracy checks only
     ref = hl.ref_conv2d(hl.ref_conv2d(x, w1, 1, 1), w2, 1, 2)
 
     def step(check=False):
@@ -267,184 +376,48 @@ def main():
             return float(np.abs(y - ref).max())
         return None
 
-    p1.set_mode(args.mode)
-    p2.set_mode(args.mode)
-    for _ in range(args.warmup):
-        step()
-    err = step(check=True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # the dominant kernel is timed launch by launch with HIP events on the
-    # library's stream during the timed steps
-    dom = DOMINANT[args.mode]
-    ctx.prof_start(dom)
-    first_launch = ctx.prof_launches(dom)
-    ks0 = ctx.keyswitch_count()
-    t = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t
-    launches, units, kms = ctx.prof_stop()
-    ms_step = wall * 1e3 / args.steps
-    # key-switch inner products actually computed in the timed steps (636 per
-    # step in modes 0-2; fewer in mode 3, which trades rotations for giant steps)
-    ks_step = (ctx.keyswitch_count() - ks0) / args.steps
-    value = ks_step * args.steps / wall
-    roofline = dominant_roofline(dom, launches, units, kms)
-    if roofline:
-        # dispatch range of the timed region in a kernel trace of this same command
-        roofline["trace_dispatch_range"] = [first_launch, first_launch + launches]
-
-    # conv-layer latency (conv 3x3 32->32) in each plan mode: batched (hoisted
-    # ModUp, 16 rotations per key-switch launch), plain (one launch chain per
-    # rotation) and lazy ModDown (key switch fused with the weight products)
-    def conv_ms(mode, reps):
+    def run_steps(mode, nsteps, profile_kernel=None):
         p1.set_mode(mode)
-        im = ctx.image_encrypt(x, LEVEL, 3002)
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            s = time.perf_counter()
-            o = p1.run(im)
-            ctx.sync()
-            ts.append((time.perf_counter() - s) * 1e3)
-            del o
-        p1.set_mode(args.mode)
-        return float(np.median(ts))
+        p2.set_mode(mode)
+        for _ in range(args.warmup):
+            step()
+        err = step(check=True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if profile_kernel:
+            ctx.prof_start(profile_kernel)
+            first = ctx.prof_launches(profile_kernel)
+        ks0 = ctx.keyswitch_count()
+        t = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(nsteps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        prof = None
+        if profile_kernel:
+            launches, units, kms = ctx.prof_stop()
+            prof = dominant_roofline(profile_kernel, launches, units, kms)
+            if prof:
+                prof["trace_dispatch_range"] = [first, first + launches]
+        return {"wall": wall, "ms_per_step": wall * 1e3 / nsteps, "gpu_event_ms_per_step":
+                ev0.elapsed_time(ev1) / nsteps, "keyswitches_per_step": (ctx.keyswitch_count() - ks0) / nsteps,
+                "max_abs_err_vs_fp64": err, "roofline": prof}
 
-    conv_b = conv_ms(0, 5)
-    conv_p = conv_ms(1, max(1, args.plain_reps))
-    conv_l = conv_ms(2, 5)
-    conv_g = conv_ms(3, 5)
-
-    # the whole step in the other fast mode (lazy ModDown <-> baby-step/giant-step)
-    other = 3 if args.mode != 3 else 2
-    p1.set_mode(other)
-    p2.set_mode(other)
-    step()
-    err_other = step(check=True)
-    torch.cuda.synchronize()
-    k0 = ctx.keyswitch_count()
-    s = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_other = (time.perf_counter() - s) * 1e3 / args.steps
-    ks_other = (ctx.keyswitch_count() - k0) / args.steps
-    p1.set_mode(args.mode)
-    p2.set_mode(args.mode)
-
-    # isolated rotations at level 20
-    ctx.gen_rotation_keys(list(range(1, 33)))
-    ct = ctx.encrypt(ctx.encode(rng.uniform(-1, 1, ctx.N), LEVEL, 2.0 ** LOG_SCALE), 5)
-    ctx.sync()
-    s = time.perf_counter()
-    for _ in range(3):
-        rs = ctx.rotate_hoisted(ct, list(range(1, 33)))
-        del rs
-    ctx.sync()
-    rot_hoisted = 96 / (time.perf_counter() - s)
-    s = time.perf_counter()
-    for i in range(32):
-        r = ctx.rotate(ct, 1 + i)
-        del r
-    ctx.sync()
-    rot_single = 32 / (time.perf_counter() - s)
-
-    # GELU as the degree-59 Chebyshev interpolant over [-15, 15] (its map onto
-    # [-1, 1] folded into the input) on one ciphertext at level 20, and the
-    # conv -> bias -> GELU -> conv -> pool block on a 16x32x32 CIFAR stage
-    from numpy.polynomial import chebyshev as Cheb
-
-    def gelu(v):
-        return 0.5 * v * (1.0 + np.tanh(np.sqrt(2.0 / np.pi) * (v + 0.044715 * v ** 3)))
-    bound = 15.0
-    coef = Cheb.chebinterpolate(lambda y: gelu(bound * y), 59)
-    zg = rng.uniform(-1, 1, ctx.N)
-    ctg = ctx.encrypt(ctx.encode(zg, LEVEL, 2.0 ** LOG_SCALE), 6)
-    ts = []
-    for _ in range(5):
-        ctx.sync()
-        s = time.perf_counter()
-        g = ctx.cheb_eval(ctg, coef, -1.0, 1.0)
-        ctx.sync()
-        ts.append((time.perf_counter() - s) * 1e3)
-    gelu_ms = float(np.median(ts))
-    gelu_err = float(np.abs(ctx.decrypt(g) - gelu(bound * zg)).max())
-    gelu_levels = LEVEL - g.level
-    del g, ctg
-    xb = rng.uniform(-1, 1, (16, 32, 32))
-    wb1, wb2 = rng.normal(0, 1 / 12.0, (16, 16, 3, 3)), rng.normal(0, 1 / 12.0, (16, 16, 3, 3))
-    bn1 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
-    bn2 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
-    imb = ctx.image_encrypt(xb, LEVEL, 7)
-    bmode = args.mode if args.mode >= 2 else 2
-    blk = ctx.block(imb, wb1, bn1, wb2, bn2, bound, coef, mode=bmode)
-    ctx.gen_rotation_keys(blk.steps())
-    ts = []
-    for _ in range(4):
-        ctx.sync()
-        k0 = ctx.keyswitch_count()
-        s = time.perf_counter()
-        ob = blk.run(imb)
-        ctx.sync()
-        ts.append((time.perf_counter() - s) * 1e3)
-        ks_block = ctx.keyswitch_count() - k0
-    block_ms = float(np.median(ts[1:]))
-    block_err = float(np.abs(ob.decrypt() - hl.ref_basic_block(xb, wb1, bn1, wb2, bn2, bound, coef)).max())
-    del ob, blk, imb
-    # the classifier head of a CIFAR ResNet: global average pooling of a
-    # 64x8x8 stage folded into a 64 -> 10 linear layer (rotate-and-add)
-    xl = rng.uniform(-1, 1, (64, 8, 8))
-    wl = rng.normal(0, 0.1, (10, 64))
-    iml = ctx.image_encrypt(xl, LEVEL, 8)
-    ctx.gen_rotation_keys(ctx.linear_steps(iml))
-    ts = []
-    for _ in range(4):
-        ctx.sync()
-        s = time.perf_counter()
-        ol = ctx.linear(iml, wl, True)
-        ctx.sync()
-        ts.append((time.perf_counter() - s) * 1e3)
-    linear_ms = float(np.median(ts[1:]))
-    linear_err = float(np.abs(ctx.decrypt(ol)[:10] - hl.ref_linear(xl, wl, True)).max())
-    del ol, iml
-    # a 112x112x64 stage of an ImageNet ResNet (32 shards of two padded
-    # 128x128 channels): conv 3x3 64->64 with basis-mask weight plaintexts
-    # (masks at 2^27), then 2x2 pooling with lazy ModDown; second calls timed
-    xi = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
-    wi = rng.normal(0, 0.05, (64, 64, 3, 3))
-    imi = ctx.image_encrypt(xi, LEVEL, 9)
-    pi = ctx.conv2d_plan(imi, wi, basis=27)
-    ctx.gen_rotation_keys(pi.steps())
-    ctx.gen_rotation_keys(ctx.avgpool_steps(imi))
-    inet = {}
-    for name, fn in (("conv", lambda: pi.run(imi)), ("pool", lambda: ctx.avgpool(yi, 2))):
-        r = fn()
-        ctx.sync()
-        del r
-        s = time.perf_counter()
-        r = fn()
-        ctx.sync()
-        inet[name] = (time.perf_counter() - s) * 1e3
-        if name == "conv":
-            yi = r
-        else:
-            zi = r
-    inet_err = float(np.abs(zi.decrypt() - hl.ref_avgpool2x2(hl.ref_conv2d(xi, wi, 1))).max())
-    del pi, yi, zi, imi
-
+    # ---- the timed step (the headline): complete key-switched rotations ----
+    main_run = run_steps(args.mode, args.steps, DOMINANT[args.mode])
+    ks_step = main_run["keyswitches_per_step"]
+    value = ks_step * args.steps / main_run["wall"]
     out = {
         "metric": "key-switched rotations/sec + HE conv-layer ms at 2N=2^16; batched vs plain",
         "value": value,
-        "unit": "key-switched rotations/s",
+        "unit": ("key-switched rotations/s (complete: automorphism, key switch, ModDown each)"
+                 if args.mode in (0, 1, 4) else "key-switch inner products/s (ModDown once per output sum)"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -454,34 +427,266 @@ def main():
                                "(2 shards -> downsample -> 1 ct), encrypt+decrypt included",
                    "ring_dim": 1 << LOGN, "level": LEVEL, "dnum": DNUM, "special_primes": K,
                    "rotations_per_step": rotations_per_step(), "keyswitches_per_step": ks_step},
-        "conv_layer_ms_batched": conv_b,
-        "conv_layer_ms_plain": conv_p,
-        "conv_layer_ms_lazy_moddown": conv_l,
-        "conv_layer_ms_bsgs": conv_g,
-        "plan_mode": {0: "batched", 1: "plain", 2: "lazy_moddown", 3: "bsgs_double_hoisting"}[args.mode],
-        "other_mode": {"plan_mode": {2: "lazy_moddown", 3: "bsgs_double_hoisting"}[other], "ms_per_step": ms_other,
-                       "keyswitches_per_step": ks_other, "max_abs_err_vs_fp64": err_other},
-        "rot_per_s_hoisted_level20": rot_hoisted,
-        "rot_per_s_single_level20": rot_single,
-        "gelu_deg59_ms_per_ct_level20": gelu_ms,
-        "gelu_levels": gelu_levels,
-        "gelu_max_abs_err_vs_gelu": gelu_err,
-        "block_16x32x32_ms": block_ms,
-        "block_plan_mode": bmode,
-        "block_keyswitches": ks_block,
-        "block_max_abs_err_vs_fp64": block_err,
-        "pool_linear_64x8x8_to_10_ms": linear_ms,
-        "pool_linear_max_abs_err_vs_fp64": linear_err,
-        "imagenet_112x112x64_conv_ms_basis_mask": inet["conv"],
-        "imagenet_112x112x64_pool_ms_lazy": inet["pool"],
-        "imagenet_112x112x64_max_abs_err_vs_fp64": inet_err,
-        "max_abs_err_vs_fp64": err,
-        "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
-        "roofline": roofline,
+        "plan_mode": MODE_NAMES[args.mode],
+        "max_abs_err_vs_fp64": main_run["max_abs_err_vs_fp64"],
+        "gpu_event_ms_per_step": main_run["gpu_event_ms_per_step"],
+        "roofline": main_run["roofline"],
+        "launch_params": hecnn.tune_describe(),
     }
+    eprint("step mode %d: %.2f ms, %.0f rotations/s" % (args.mode, main_run["ms_per_step"], value))
+
+    # ---- the same step in the other modes ----
+    if "other" not in skip:
+        others = {}
+        for mode in (2, 3, 4, 0):
+            if mode == args.mode:
+                continue
+            r = run_steps(mode, args.steps, DOMINANT[mode] if mode == 2 else None)
+            others[MODE_NAMES[mode]] = {"ms_per_step": r["ms_per_step"],
+                                        "keyswitches_per_step": r["keyswitches_per_step"],
+                                        "keyswitches_per_s": r["keyswitches_per_step"] * 1e3 / r["ms_per_step"],
+                                        "max_abs_err_vs_fp64": r["max_abs_err_vs_fp64"]}
+            if r["roofline"]:
+                others[MODE_NAMES[mode]]["roofline"] = r["roofline"]
+        out["other_modes"] = others
+        p1.set_mode(args.mode)
+        p2.set_mode(args.mode)
+
+    # ---- conv-layer ms (conv 3x3 32->32) in every plan mode ----
+    if "layers" not in skip:
+        im = ctx.image_encrypt(x, LEVEL, 3002)
+        layer = {}
+        for mode in (1, 0, 4, 2, 3):
+            p1.set_mode(mode)
+            layer[MODE_NAMES[mode]] = timed(ctx, lambda: p1.run(im), args.reps)
+        p1.set_mode(args.mode)
+        out["conv_layer_ms"] = layer
+        out["conv_layer_ms_plain"] = layer["plain"]
+        out["conv_layer_ms_batched"] = layer["batched"]
+        del im
+
+    # ---- isolated complete rotations at level 20: hoisted sets and single ----
+    if "rot" not in skip:
+        ctx.gen_rotation_keys(list(range(1, 33)))
+        ct = ctx.encrypt(ctx.encode(rng.uniform(-1, 1, ctx.N), LEVEL, 2.0 ** LOG_SCALE), 5)
+        hms = timed(ctx, lambda: ctx.rotate_hoisted(ct, list(range(1, 33))), args.reps)
+        sms = timed(ctx, lambda: ctx.rotate(ct, 7), args.reps)
+        out["rotation_roofline_hoisted_level20"] = rotation_roofline(32e3 / hms, LEVEL)
+        out["rot_per_s_hoisted_level20"] = 32e3 / hms
+        out["rot_per_s_single_level20"] = 1e3 / sms
+        del ct
+
+    # ---- GELU, the basic block and the pool-linear head ----
+    if "gelu" not in skip:
+        zg = rng.uniform(-1, 1, ctx.N)
+        ctg = ctx.encrypt(ctx.encode(zg, LEVEL, 2.0 ** LOG_SCALE), 6)
+        out["gelu_deg59_ms_per_ct_level20"] = timed(ctx, lambda: ctx.cheb_eval(ctg, coef, -1.0, 1.0), args.reps)
+        g = ctx.cheb_eval(ctg, coef, -1.0, 1.0)
+        out["gelu_levels"] = LEVEL - g.level
+        out["gelu_max_abs_err_vs_gelu"] = float(np.abs(ctx.decrypt(g) - gelu(bound * zg)).max())
+        del g, ctg
+    if "block" not in skip:
+        xb = rng.uniform(-1, 1, (16, 32, 32))
+        wb1, wb2 = rng.normal(0, 1 / 12.0, (16, 16, 3, 3)), rng.normal(0, 1 / 12.0, (16, 16, 3, 3))
+        bn1 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
+        bn2 = (rng.uniform(0.5, 1.5, 16), rng.normal(0, 0.5, 16))
+        imb = ctx.image_encrypt(xb, LEVEL, 7)
+        blk = ctx.block(imb, wb1, bn1, wb2, bn2, bound, coef, mode=2)
+        ctx.gen_rotation_keys(blk.steps())
+        out["block_16x32x32_ms"] = timed(ctx, lambda: blk.run(imb), args.reps)
+        ob = blk.run(imb)
+        out["block_max_abs_err_vs_fp64"] = float(np.abs(ob.decrypt() - hl.ref_basic_block(
+            xb, wb1, bn1, wb2, bn2, bound, coef)).max())
+        del ob, blk, imb
+    if "linear" not in skip:
+        xl = rng.uniform(-1, 1, (64, 8, 8))
+        wl = rng.normal(0, 0.1, (10, 64))
+        iml = ctx.image_encrypt(xl, LEVEL, 8)
+        ctx.gen_rotation_keys(ctx.linear_steps(iml))
+        out["pool_linear_64x8x8_to_10_ms"] = timed(ctx, lambda: ctx.linear(iml, wl, True), args.reps)
+        ol = ctx.linear(iml, wl, True)
+        out["pool_linear_max_abs_err_vs_fp64"] = float(np.abs(ctx.decrypt(ol)[:10] - hl.ref_linear(xl, wl, True)).max())
+        del ol, iml
+
+    # ---- the 112x112x64 ImageNet stage (32 shards): plain vs batched vs key-stationary ----
+    if "imagenet" not in skip:
+        out["imagenet_112x112x64"] = imagenet_stage(ctx, hecnn, hl, rng, max(5, args.reps // 2))
+
+    # ---- the uneven batch: 13 instances, 48 ciphertexts at levels 2..24, eager vs one captured graph ----
+    if "uneven" not in skip:
+        out["uneven_batch_48ct"] = uneven_batch(ctx, hl, args.reps)
+
+    # ---- serving: Poisson arrivals of the two request shapes ----
+    if "serving" not in skip:
+        out["serving"] = serving(ctx, hecnn, hl)
+
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_rotations, args.cpu_seconds, args.mode)
+        out["cpu_baseline"] = cpu_baseline_runs(args.cpu_rotations, args.cpu_seconds, args.mode)
     print(json.dumps(out), flush=True)
+
+
+MODE_NAMES = {0: "batched", 1: "plain", 2: "lazy_moddown", 3: "bsgs_double_hoisting", 4: "key_stationary"}
+
+
+def imagenet_stage(ctx, hecnn, hl, rng, reps):
+    """conv 3x3 64->64 (basis-mask weight plaintexts, masks at 2^27) + 2x2
+    average pooling of a 64x112x112 activation in 32 shards of two padded
+    128x128 channels, level 20, in each evaluation form; the key-stationary
+    form's launch parameters chosen by the autotuner first."""
+    xi = np.clip(rng.normal(0, 1, (64, 112, 112)), -4, 4)
+    wi = rng.normal(0, 0.05, (64, 64, 3, 3))
+    imi = ctx.image_encrypt(xi, LEVEL, 9)
+    pi = ctx.conv2d_plan(imi, wi, basis=27)
+    ctx.gen_rotation_keys(pi.steps())
+    y0 = pi.run(imi)
+    ctx.gen_rotation_keys(ctx.avgpool_steps(y0))
+    del y0
+    fp = hl.ref_avgpool2x2(hl.ref_conv2d(xi, wi, 1))
+    pi.set_mode(4)
+    t = time.perf_counter()
+    report = ctx.autotune_conv(pi, imi, reps=2)
+    tune_s = time.perf_counter() - t
+    res = {"shards": 32, "level": LEVEL, "autotune": {"report": report, "seconds": tune_s,
+                                                      "chosen": hecnn.tune_describe()}}
+    forms = (("plain", 1, 0), ("batched", 0, 0), ("key_stationary", 4, 4), ("lazy_moddown", 2, 2))
+    for name, cmode, pmode in forms:
+        pi.set_mode(cmode)
+        n = max(3, reps // 4) if name == "plain" else reps
+        conv_ms = timed(ctx, lambda: pi.run(imi), n)
+        yi = pi.run(imi)
+        pool_ms = timed(ctx, lambda: ctx.avgpool(yi, pmode), n)
+        zi = ctx.avgpool(yi, pmode)
+        err = float(np.abs(zi.decrypt() - fp).max())
+        res[name] = {"conv_ms": conv_ms, "pool_ms": pool_ms, "total_ms": conv_ms + pool_ms, "reps": n,
+                     "max_abs_err_vs_fp64": err}
+        del yi, zi
+        eprint("imagenet %s: conv %.1f ms pool %.1f ms err %.2g" % (name, conv_ms, pool_ms, err))
+    del pi, imi
+    return res
+
+
+def uneven_batch(ctx, hl, reps):
+    """One 64x112x112 instance (32 shards, basis-mask, key-stationary), four
+    16x56x56 (2 shards) and eight 32x32x32 (1 shard; lazy ModDown), 48
+    ciphertexts, each at its own level drawn uniformly from 2..24, each
+    through a 3x3 convolution and rescale: eager launches vs replays of one
+    captured HIP graph (the first launch records it)."""
+    rng = np.random.default_rng(4004)
+    shapes = [(64, 112, 112)] + [(16, 56, 56)] * 4 + [(32, 32, 32)] * 8
+    levels = rng.integers(2, 25, size=len(shapes))
+    batch = ctx.batch()
+    inst = []
+    for i, (shape, level) in enumerate(zip(shapes, levels)):
+        C = shape[0]
+        xx = np.clip(rng.normal(0, 1, shape), -4, 4) if C == 64 else rng.uniform(-1, 1, shape)
+        ww = rng.normal(0, 0.05, (C, C, 3, 3))
+        im = ctx.image_encrypt(xx, int(level), 6000 + i)
+        if C == 64:
+            pl = ctx.conv2d_plan(im, ww, basis=27)
+            pl.set_mode(4)
+        else:
+            pl = ctx.conv2d_plan(im, ww)
+            pl.set_mode(2)
+        ctx.gen_rotation_keys(pl.steps())
+        batch.add(pl, im)
+        inst.append((xx, ww))
+    eager_ms = timed(ctx, lambda: batch.launch(graph=False), reps)
+    t = time.perf_counter()
+    batch.launch(graph=True)
+    ctx.sync()
+    capture_ms = (time.perf_counter() - t) * 1e3
+    graph_ms = timed(ctx, lambda: batch.launch(graph=True), reps)
+    err = 0.0
+    for i, (xx, ww) in enumerate(inst):
+        err = max(err, float(np.abs(batch.output(i).decrypt() - hl.ref_conv2d(xx, ww, 1)).max()))
+    eprint("uneven batch: eager %.1f ms graph %.1f ms (capture %.0f ms) err %.2g" % (eager_ms, graph_ms,
+                                                                                   capture_ms, err))
+    return {"instances": len(shapes), "ciphertexts": 48, "levels": [int(v) for v in levels],
+            "eager_ms": eager_ms, "graph_ms": graph_ms, "first_graph_launch_ms": capture_ms,
+            "max_abs_err_vs_fp64": err, "reps": reps}
+
+
+def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
+    """Encrypted-inference requests under Poisson arrivals: 70 % a 3x32x32
+    image (channels padded to 4, duplicated) through conv 3x3 3->32 and 2x2
+    average pooling, 30 % a 3x224x224 image (each channel in two shards)
+    through the stem conv 3x3 stride 2, 3->64; level 20, keys and plans
+    resident.  Saturation throughput from a burst, then arrivals at 0.5x and
+    0.8x of it; p50 / p99 latency (submit -> result on the device) and
+    requests/s."""
+    rng = np.random.default_rng(5005)
+    wa = rng.normal(0, 0.05, (32, 3, 3, 3))
+    wb = rng.normal(0, 0.05, (64, 3, 3, 3))
+    like_a = ctx.image_encrypt(rng.uniform(-1, 1, (3, 32, 32)), LEVEL, 7001)
+    like_b = ctx.image_encrypt(rng.uniform(-1, 1, (3, 224, 224)), LEVEL, 7002)
+    pa = ctx.conv2d_plan(like_a, wa)
+    pa.set_mode(4)
+    ctx.gen_rotation_keys(pa.steps())
+    ctx.gen_rotation_keys(ctx.avgpool_steps(pa.run(like_a)))
+    pb = ctx.conv2d_plan(like_b, wb, stride=2, q_only=True)
+    pb.set_mode(4)
+    ctx.gen_rotation_keys(pb.steps())
+    ctx.sync()
+    srv = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
+    res = {"lanes": lanes, "max_batch": max_batch, "mix": "70% 3x32x32 conv 3->32 + pool, 30% 3x224x224 stem "
+           "conv s2 3->64", "level": LEVEL}
+    try:
+        ma = srv.add_model(pa, like_a, pool_mode=4)
+        mb = srv.add_model(pb, like_b)
+        res["footprint_bytes"] = {"block": srv.footprint(ma), "stem": srv.footprint(mb)}
+        reqs = []
+        for i in range(n_requests):
+            m = ma if rng.uniform() < 0.7 else mb
+            shape = (3, 32, 32) if m == ma else (3, 224, 224)
+            xx = rng.uniform(-1, 1, shape)
+            reqs.append((m, xx, ctx.image_encrypt(xx, LEVEL, 8000 + i)))
+        ctx.sync()
+        # saturation: everything at once
+        t = time.perf_counter()
+        ids = [srv.submit(m, im) for (m, xx, im) in reqs]
+        for rid in ids:
+            o, _ = srv.poll(rid)
+            o.free()
+        sat = len(reqs) / (time.perf_counter() - t)
+        res["saturation_req_per_s"] = sat
+        for load in (0.5, 0.8):
+            srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
+            try:
+                srv_l.add_model(pa, like_a, pool_mode=4)
+                srv_l.add_model(pb, like_b)
+                lam = load * sat
+                gaps = rng.exponential(1.0 / lam, size=len(reqs))
+                t = time.perf_counter()
+                due = t
+                ids = []
+                for (m, xx, im), gap in zip(reqs, gaps):
+                    due += gap
+                    d = due - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    ids.append(srv_l.submit(m, im))
+                errs, checked = [], {ma: 0, mb: 0}
+                for (m, xx, im), rid in zip(reqs, ids):
+                    o, ms = srv_l.poll(rid)
+                    if checked[m] < 2:  # accuracy of the first two results of each kind
+                        checked[m] += 1
+                        w = wa if m == ma else wb
+                        ref = (hl.ref_avgpool2x2(hl.ref_conv2d(xx, w, 1)) if m == ma else hl.ref_conv2d(xx, w, 1, 2))
+                        errs.append(float(np.abs(o.decrypt() - ref).max()))
+                    o.free()
+                st = srv_l.stats()
+                res["load_%.1f" % load] = {"arrival_req_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                           "mean_ms": st["mean_ms"], "req_per_s": st["req_per_s"],
+                                           "batches": st["batches"], "max_concurrent": st["max_concurrent"],
+                                           "peak_admitted_bytes": st["peak_mem"],
+                                           "max_abs_err_vs_fp64": max(errs) if errs else None}
+                eprint("serving load %.1f: p50 %.0f ms p99 %.0f ms %.2f req/s" % (load, st["p50_ms"], st["p99_ms"],
+                                                                                st["req_per_s"]))
+            finally:
+                srv_l.stop()
+    finally:
+        srv.stop()
+    return res
 
 
 if __name__ == "__main__":

@@ -251,9 +251,15 @@ hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec
  * rotations of each input (lazy ModDown per (giant, output) sum), and each
  * output sums its giant rotations of those sums with one more lazy ModDown --
  * babies + giants x outputs key switches instead of one per amount.  Its
- * plaintexts are encoded on the first switch to mode 3.  Modes 2 and 3 also
- * take the stride-2 downsampling lazily (he_avgpool_ex mode 2).  Returns
- * HEC_EINVAL for any other mode. */
+ * plaintexts are encoded on the first switch to mode 3.  4 = key-stationary
+ * batched: the ciphertexts of modes 0/1, with the rotations of all input
+ * shards taken together amount by amount (Section 4.1, "With Image Shards":
+ * every output shard sums over all input shards, which all rotate by the same
+ * amounts), so each rotation key is read once per group of up to 64 shards
+ * instead of once per shard, and the ModDowns of a batch of amounts x shards
+ * share their launches.  Modes 2 and 3 also take the stride-2 downsampling
+ * lazily (he_avgpool_ex mode 2), mode 4 key-stationary (he_avgpool_ex mode
+ * 4).  Returns HEC_EINVAL for any other mode. */
 hec_status he_conv2d_plan_set_mode(hec_conv_plan *plan, int mode);
 /* Rotation steps a plan (or an avgpool of `like`) needs keys for. */
 hec_status he_conv2d_plan_steps(const hec_conv_plan *plan, int32_t *steps, size_t cap, size_t *count);
@@ -273,8 +279,12 @@ hec_status he_avgpool(hec_ctx *ctx, const hec_image *in, uint32_t window, hec_im
  * bound); 3 = as 2, except that masked sums of at least 32 rotations are
  * evaluated by baby and giant steps (amount = (i mod G) + (i - i mod G) in
  * units of the stage's shift, G = ceil(sqrt(count)); masks rotated back by the
- * giant step), also beyond the paper.  Other modes: HEC_EINVAL.  Plans in
- * modes 2 and 3 use the same mode for their stride-2 downsampling. */
+ * giant step), also beyond the paper; 4 = the ciphertexts of mode 0, with
+ * the rotations of every stage (2x2 window sums, horizontal and vertical
+ * reductions) taken for all image shards together amount by amount, each key
+ * read once per stage for up to 64 shards (channel shards and the fused
+ * one-level reduction take mode 0).  Other modes: HEC_EINVAL.  Plans in modes
+ * 2, 3 and 4 use the same mode for their stride-2 downsampling. */
 hec_status he_avgpool_ex(hec_ctx *ctx, const hec_image *in, uint32_t window, int mode, hec_image **out);
 
 /* Linear layer (Section 4.3, "Linear"): W is [O][C*H*W] over the input in
@@ -332,6 +342,109 @@ hec_status he_block_create(hec_ctx *ctx, const hec_image *like, const double *w1
 hec_status he_block_steps(const hec_block *block, int32_t *steps, size_t cap, size_t *count);
 hec_status he_block_run(hec_ctx *ctx, const hec_block *block, const hec_image *in, hec_image **out);
 void he_block_free(hec_block *block);
+
+/* ---- batches: many layer evaluations as one launch -------------------------
+ * A batch lists (convolution plan, input image) items -- e.g. the images of
+ * several requests, each at its own level and limb count, each through its 3x3
+ * convolution and rescale (Section 4.1; the plan's mode applies).  Items keep
+ * pointers to their plan and input, which must outlive the batch.
+ * hec_batch_launch(HEC_BATCH_EAGER) runs the items one after another on the
+ * context stream.  HEC_BATCH_GRAPH: the first launch runs the items once
+ * eagerly on memory the batch keeps (so that the recording allocates
+ * nothing), records them on a capture stream into one HIP graph and launches
+ * it; later launches replay the graph on the context stream, re-reading the
+ * inputs' current contents and rewriting the same outputs.  Ciphertexts are
+ * the same bit for bit in both modes.  Items cannot be added after the
+ * capture (HEC_EBUSY). */
+typedef struct hec_batch hec_batch;
+#define HEC_BATCH_EAGER 0
+#define HEC_BATCH_GRAPH 1
+hec_status hec_batch_begin(hec_ctx *ctx, hec_batch **out);
+hec_status hec_batch_add(hec_batch *batch, const hec_conv_plan *plan, const hec_image *in, uint32_t *index);
+hec_status hec_batch_launch(hec_batch *batch, int mode);
+/* Borrowed output of item i from the last launch (eager outputs until the next
+ * eager launch, graph outputs until hec_batch_free); NULL before a launch. */
+const hec_image *hec_batch_output(const hec_batch *batch, uint32_t i);
+uint32_t hec_batch_size(const hec_batch *batch);
+/* Waits for the context stream, then frees the batch, its graph and memory. */
+void hec_batch_free(hec_batch *batch);
+
+/* ---- tuning: launch parameters and their autotuner -------------------------
+ * Process-wide parameters that decide how work is cut into launches, never
+ * its residues (every value gives the same ciphertexts bit for bit):
+ *   ntt16_radix  16 | 2        2^16 transforms as two radix-16 register passes,
+ *                              or as radix-2 stages over LDS tiles
+ *   ntt_tile     2048 | 4096 | 8192   words per LDS tile of the radix-2 form
+ *   ntt_group    0 | 64 | 256 | 1024  at most this many limbs per transform
+ *                              launch (0: every limb of a batch in one launch)
+ *   ks_rot_batch 4 | 8 | 16    rotations per key-switch launch of a hoisted set
+ *   ks_amounts   1 | 2 | 4 | 8 | 16   rotation amounts per key-stationary
+ *                              launch (plan and pooling mode 4)
+ * hec_tune_set rejects names and values outside these lists (HEC_EINVAL).
+ * hec_tune_save / hec_tune_load persist them as "name value" lines. */
+hec_status hec_tune_set(const char *name, int64_t value);
+hec_status hec_tune_get(const char *name, int64_t *value);
+/* "name=value ..." of every parameter (NUL-terminated; HEC_EINVAL if cap is too small). */
+hec_status hec_tune_describe(char *buf, size_t cap);
+hec_status hec_tune_save(const char *path);
+hec_status hec_tune_load(const char *path);
+/* Autotuner: times he_conv2d_plan_run(plan, in) (median of reps runs after an
+ * untimed one) under every candidate of each parameter in turn, starting from
+ * the current values; a candidate is kept only if the plan's output equals the
+ * output under the starting values bit for bit and it is more than 2 % faster.
+ * Leaves the chosen values set; report (nullable) receives the chosen values
+ * and every timing.  Synchronizes. */
+hec_status hec_autotune_conv(hec_ctx *ctx, const hec_conv_plan *plan, const hec_image *in, uint32_t reps,
+                             char *report, size_t cap);
+
+/* ---- serving: a request loop for encrypted inference ----------------------
+ * Background, "Threat Model": the client encrypts its image and decrypts the
+ * result, the server evaluates with the weights in the clear.  A server keeps
+ * the context's evaluation and rotation keys and its models' plans resident
+ * in HBM (generate every key the models need before hec_server_start) and
+ * evaluates requests on `lanes` worker threads, each with its own HIP stream
+ * and memory pool over the shared tables and keys, so that requests on
+ * different lanes overlap on the device.  Admission is by device memory: a
+ * model's footprint is the peak memory of one evaluation (measured by
+ * hec_server_add_model, which also warms every lane); requests leave the queue
+ * in arrival order while the footprints of the requests being evaluated stay
+ * within mem_budget bytes; a request whose footprint alone exceeds the budget
+ * is rejected (its poll returns HEC_ENOMEM).  Continuous batching: a lane
+ * that frees up takes the oldest waiting request with the later waiting
+ * requests of the same model (at most max_batch, as memory allows) and
+ * evaluates them as one batch (plan mode 4: the rotations of all their shards
+ * share each key read).  A request's ciphertexts do not depend on what it was
+ * batched or overlapped with. */
+typedef struct hec_server hec_server;
+typedef struct {
+    uint32_t lanes;       /* worker threads / HIP streams, 1..16 */
+    uint32_t max_batch;   /* requests of one model evaluated together, >= 1 */
+    size_t mem_budget;    /* device bytes for requests being evaluated */
+} hec_server_params;
+typedef struct {
+    uint64_t completed, rejected, batches, batched_requests, max_concurrent;
+    size_t peak_mem;                              /* largest sum of admitted footprints */
+    double p50_ms, p99_ms, mean_ms, req_per_s;    /* latency submit -> done; completed per second */
+} hec_server_stats_t;
+hec_status hec_server_start(hec_ctx *ctx, const hec_server_params *params, hec_server **out);
+/* A model: the convolution plan, then 2x2 average pooling in he_avgpool_ex
+ * mode pool_mode (-1: none).  `like` is an input of the plan's layout and
+ * level (evaluated once per lane).  Before the first submit (HEC_EBUSY after). */
+hec_status hec_server_add_model(hec_server *server, const hec_conv_plan *plan, int pool_mode, const hec_image *like,
+                                uint32_t *model);
+size_t hec_server_model_footprint(const hec_server *server, uint32_t model);
+/* Queue the evaluation of `in` (borrowed until its poll reports it done). */
+hec_status hec_server_submit(hec_server *server, uint32_t model, const hec_image *in, uint64_t *request);
+/* HEC_OK: done, *out receives the result (owned by the caller; free it with
+ * hec_image_free before hec_server_stop, whose lanes own its memory) and
+ * *latency_ms the time from submit to completion; HEC_EBUSY: not done yet
+ * (wait = 0); any other status: the request failed (rejected: HEC_ENOMEM).
+ * A request is reported once. */
+hec_status hec_server_poll(hec_server *server, uint64_t request, int wait, hec_image **out, double *latency_ms);
+hec_status hec_server_stats(hec_server *server, hec_server_stats_t *stats);
+/* Evaluates what is queued, joins the workers and frees the server (and any
+ * result not yet polled). */
+hec_status hec_server_stop(hec_server *server);
 
 void hec_ct_free(hec_ct *ct);
 void hec_pt_free(hec_pt *pt);

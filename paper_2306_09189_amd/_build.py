@@ -24,6 +24,9 @@ SOURCES = [
     ("hec_layers.cpp", "cxx"),
     ("hec_poly.cpp", "cxx"),
     ("hec_block.cpp", "cxx"),
+    ("hec_batch.cpp", "cxx"),
+    ("hec_server.cpp", "cxx"),
+    ("hec_tune.cpp", "cxx"),
     ("hec_host.cpp", "cxx"),
 ]
 

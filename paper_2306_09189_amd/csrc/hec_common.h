@@ -60,6 +60,17 @@ struct KsBatch {
     u32 g[HEC_KS_BATCH];
 };
 
+// Key-stationary key switch: rotation t of a launch (key[t], g[t]) applied to
+// every input u < S with bit u of mask[t] set (inputs' hoisted digits at
+// D + u * dstride), e_{t,u} at out[t] + u * estride ([2][nqp][n]).
+struct KsMulti {
+    const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
+    u64 *out[HEC_KS_BATCH];
+    u64 mask[HEC_KS_BATCH];
+    u32 g[HEC_KS_BATCH];
+};
+#define HEC_MULTI_MAX_INPUTS 64
+
 // Key switching fused with plaintext products, accumulated before ModDown.
 // Term t is a rotation by g[t] of ciphertext ct[t] (key[t] == null when
 // g[t] == 1; D[t] its ModUp, unused then) whose result is multiplied by
@@ -111,6 +122,17 @@ struct CombineBatch {
     u32 g[HEC_KS_BATCH];
 };
 
+// Launch parameters the autotuner (hec_tune.cpp) chooses among; every choice
+// gives the same residues.  Process-wide; read when work is enqueued.
+struct TuneParams {
+    int ntt16_radix = 16;  // 2^16 transforms: 16 = two radix-16 register passes, 2 = radix-2 LDS tiles
+    int ntt_tile = 4096;   // words per LDS tile of the radix-2 transforms (2048, 4096, 8192)
+    int ntt_group = 0;     // at most this many limbs per transform launch (0: all in one)
+    int ks_rot_batch = 16; // rotations per key-switch launch of a hoisted set (1..HEC_KS_BATCH)
+    int ks_amounts = 4;    // amounts per key-stationary launch over many inputs (1..HEC_KS_BATCH)
+};
+TuneParams &hec_tune_params();
+
 // ---- launchers (hec_kernels.hip) -----------------------------------------
 // NTT / INTT of `nlimbs` limbs of `npolys` polynomials: limb l of poly p sits
 // at base + p*poly_stride + l*n and uses prime pmap[l] (device array).
@@ -137,13 +159,18 @@ void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u
 
 // Base conversion of npolys polynomials in groups of `group` that share a source: polynomial z uses
 // descriptor d_desc[(z % group) * desc_stride], reads src + (z / group)*src_poly_stride and writes
-// dst + z*dst_poly_stride; nout_max bounds the descriptors' nout.  copy_in also copies the input limbs
-// to the same positions of the destination.
+// dst + z*dst_poly_stride; nout_max bounds the descriptors' nout and nin_max their nin.  copy_in also
+// copies the input limbs to the same positions of the destination.
 void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int group, int nout_max, const u64 *src,
-               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st);
+               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st,
+               int nin_max);
 
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st);
+// the same products as hec_ks_inner for nrot <= HEC_KS_BATCH rotations x S <= HEC_MULTI_MAX_INPUTS inputs,
+// each key read once for all inputs; false (nothing launched) for sizes out of range
+bool hec_ks_inner_multi(const DevTables &T, const KsMulti &kb, int nrot, const u64 *D, size_t dstride, int S,
+                        size_t estride, int beta, int nqp, const u32 *pmap, int NLK, hipStream_t st);
 
 // E_v (+)= sum_t pt[t][v] * KS_t, KS_t = (sum_j sigma_g(D_j) key_j + P sigma_g(c0), sum_j sigma_g(D_j) key'_j)
 // or P * (c0, c1) for g == 1, over the terms' own ciphertexts and ModUps (b.ct, b.D);
@@ -186,6 +213,13 @@ bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64
                       int npolys, const u32 *pmap, int nlimbs, hipStream_t st);
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
                          hipStream_t st);
+// ModDown tail of nrot <= HEC_KS_BATCH entries fused into the forward NTT of
+// their P -> Q conversions y ([2 nrot][nq][n], coefficient form; overwritten
+// by the column pass): out_r = (e_r - NTT(y_r)) P^-1 + sigma_g(c0_r) (+ add),
+// the residues of hec_ntt_fwd + hec_moddown_combine; 2N = 2^16 only (false,
+// nothing launched, otherwise)
+bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, const CombineBatch &cb,
+                         const LevelC *lc, const u32 *pmap, hipStream_t st);
 void hec_rescale_spread(const DevTables &T, const u64 *last_coef, u64 *tmp, size_t last_stride, size_t tmp_stride,
                         int npolys, u32 level, hipStream_t st);
 void hec_rescale_finish(const DevTables &T, u64 *out, const u64 *c, const u64 *tmp, size_t so, size_t sc,

@@ -31,6 +31,7 @@ extern "C" const char *hec_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 void *DevPool::get(size_t bytes)
 {
+    std::lock_guard<std::mutex> lk(mu_);
     if (!bytes) bytes = 8;
     auto it = free_.find(bytes);
     void *p = nullptr;
@@ -48,19 +49,23 @@ void *DevPool::get(size_t bytes)
     }
     live_[p] = bytes;
     bytes_live += bytes;
+    peak_live = std::max(peak_live, bytes_live);
     return p;
 }
-void DevPool::put(void *p)
+bool DevPool::put(void *p)
 {
+    std::lock_guard<std::mutex> lk(mu_);
     auto it = live_.find(p);
-    if (it == live_.end()) return;
+    if (it == live_.end()) return false;
     free_.emplace(it->second, p);
     bytes_live -= it->second;
     bytes_cached += it->second;
     live_.erase(it);
+    return true;
 }
 void DevPool::release_all()
 {
+    std::lock_guard<std::mutex> lk(mu_);
     for (auto &kv : free_) hipFree(kv.second);
     for (auto &kv : live_) hipFree(kv.first);
     free_.clear();
@@ -360,6 +365,54 @@ extern "C" void hec_ctx_destroy(hec_ctx *c)
     delete c;
 }
 
+// A serving lane: everything read-only of `parent` shared (tables, keys), its
+// own stream, memory pool, encoder status word and caches, so that one worker
+// thread per lane evaluates concurrently with the others.
+hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out)
+{
+    *out = nullptr;
+    HEC_TRY_HIP(hipSetDevice(parent->dev));
+    std::unique_ptr<hec_ctx> c(new hec_ctx());
+    c->prm = parent->prm;
+    c->dev = parent->dev;
+    c->logn = parent->logn; c->n = parent->n; c->N = parent->N; c->L = parent->L; c->k = parent->k;
+    c->dnum = parent->dnum; c->alpha = parent->alpha; c->NLK = parent->NLK;
+    c->mod = parent->mod;
+    c->T = parent->T;
+    c->d_pc = parent->d_pc;
+    c->d_tw = parent->d_tw; c->d_twsh = parent->d_twsh; c->d_itw = parent->d_itw; c->d_itwsh = parent->d_itwsh;
+    c->d_maps = parent->d_maps;
+    c->qp_off = parent->qp_off;
+    c->d_modup = parent->d_modup; c->d_moddown = parent->d_moddown; c->d_lvl = parent->d_lvl;
+    c->d_pmodq = parent->d_pmodq; c->d_pmodq_m = parent->d_pmodq_m; c->d_gauss = parent->d_gauss;
+    c->d_crt_m = parent->d_crt_m; c->d_crt_inv = parent->d_crt_inv; c->d_crt_invsh = parent->d_crt_invsh;
+    c->h_modup = parent->h_modup; c->h_moddown = parent->h_moddown;
+    c->d_enc_tw = parent->d_enc_tw; c->d_enc_root = parent->d_enc_root;
+    c->have_keys = parent->have_keys; c->key_seed = parent->key_seed;
+    c->d_sN = parent->d_sN; c->d_sM = parent->d_sM; c->d_pk = parent->d_pk;
+    c->rotkeys = parent->rotkeys;
+    c->rlk = parent->rlk;
+    c->lane = true;
+    HEC_TRY_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+    c->d_flag = (int *)c->pool.get(256);
+    if (!c->d_flag) {
+        hipStreamDestroy(c->st);
+        HEC_FAIL(HEC_ENOMEM, "lane status word");
+    }
+    *out = c.release();
+    return HEC_OK;
+}
+
+void ctx_lane_destroy(hec_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->dev);
+    hipStreamSynchronize(c->st);
+    hipStreamDestroy(c->st);
+    c->pool.release_all();
+    delete c;
+}
+
 extern "C" hec_status hec_ctx_sync(hec_ctx *c)
 {
     if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
@@ -410,11 +463,11 @@ hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale)
     ct->d = d;
     return ct;
 }
-hec_ct *ct_clone(const hec_ct *a)
+hec_ct *ct_clone(hec_ctx *c, const hec_ct *a)
 {
-    hec_ct *r = ct_new(a->ctx, a->level, a->scale);
+    hec_ct *r = ct_new(c, a->level, a->scale);
     if (!r) return nullptr;
-    hipMemcpyAsync(r->d, a->d, (size_t)2 * (a->level + 1) * a->ctx->n * 8, hipMemcpyDeviceToDevice, a->ctx->st);
+    hipMemcpyAsync(r->d, a->d, (size_t)2 * (a->level + 1) * c->n * 8, hipMemcpyDeviceToDevice, c->st);
     return r;
 }
 void ct_free(hec_ct *p)
@@ -449,6 +502,7 @@ extern "C" hec_status ckks_ct_info(const hec_ct *ct, uint32_t *level, double *sc
 static hec_status gen_swk(hec_ctx *c, uint32_t g, const u64 *tgt = nullptr, u64 **out = nullptr)
 {
     if (!tgt && c->rotkeys.count(g)) return HEC_OK;
+    PoolScope ps(c, &c->pool);  // keys live as long as the context
     const size_t n = c->n, NLK = c->NLK;
     u64 *key = c->alloc((size_t)c->dnum * 2 * NLK * n);
     u64 *e = c->alloc(NLK * n);
@@ -478,6 +532,7 @@ hec_status relin_key(hec_ctx *c, const u64 **key)
 {
     if (!c->have_keys) HEC_FAIL(HEC_ENOKEY, "no keys");
     if (!c->rlk) {
+        PoolScope ps(c, &c->pool);
         const size_t n = c->n, NLK = c->NLK;
         u64 *s2 = c->alloc(NLK * n);
         if (!s2) HEC_FAIL(HEC_ENOMEM, "key allocation");
@@ -862,10 +917,13 @@ hec_status ct_modup_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, u64
                 hipMemcpyAsync(cc + i * nq * n, cts[i]->d + nq * n, nq * n * 8, hipMemcpyDeviceToDevice, c->st));
         hec_ntt_inv(c->T, cc, nq * n, (int)cnt, c->idmap(), nq, c->st);
     }
-    uint32_t nout_max = 0;
-    for (uint32_t j = 0; j < beta; j++) nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
+    uint32_t nout_max = 0, nin_max = 0;
+    for (uint32_t j = 0; j < beta; j++) {
+        nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
+        nin_max = std::max(nin_max, c->h_modup[(size_t)lvl * c->dnum + j].nin);
+    }
     hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)beta, (int)nout_max, cc, D, nq * n,
-              (size_t)nqp * n, (int)(cnt * beta), 1, c->st);
+              (size_t)nqp * n, (int)(cnt * beta), 1, c->st, (int)nin_max);
     hec_ntt_fwd(c->T, D, (size_t)nqp * n, (int)(cnt * beta), c->qpmap(lvl), (int)nqp, c->st);
     c->release(cc);
     *Dall = D;
@@ -878,6 +936,7 @@ const u64 *ones_qp(hec_ctx *c, uint32_t lvl)
 {
     auto it = c->ones_qp.find(lvl);
     if (it != c->ones_qp.end()) return it->second;
+    PoolScope ps(c, &c->pool);  // cached for the context's lifetime
     const size_t n = c->n, nqp = lvl + 1 + c->k;
     std::vector<u64> h(nqp * n);
     for (size_t l = 0; l < nqp; l++) {
@@ -910,8 +969,9 @@ hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vecto
     if (!y) HEC_FAIL(HEC_ENOMEM, "ModDown buffer");
     hec_ntt_inv(c->T, Eall + (size_t)nq * n, (size_t)nqp * n, (int)(2 * cnt), c->qpmap(lvl) + nq, k, c->st);
     hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, Eall, y, (size_t)nqp * n, (size_t)nq * n, (int)(2 * cnt), 0,
-              c->st);
-    hec_ntt_fwd(c->T, y, (size_t)nq * n, (int)(2 * cnt), c->qpmap(lvl), nq, c->st);
+              c->st, (int)c->k);
+    const bool fused = c->logn == 16;  // the combine as the epilogue of the forward NTT's row pass
+    if (!fused) hec_ntt_fwd(c->T, y, (size_t)nq * n, (int)(2 * cnt), c->qpmap(lvl), nq, c->st);
     for (size_t b0 = 0; b0 < cnt; b0 += HEC_KS_BATCH) {
         const size_t nb = std::min((size_t)HEC_KS_BATCH, cnt - b0);
         CombineBatch cb{};
@@ -925,7 +985,9 @@ hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vecto
                 cb.add[r][1] = (*adds)[b0 + r][1];
             }
         }
-        hec_moddown_combine(c->T, cb, (int)nb, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        if (!fused || !hec_ntt_fwd_moddown(c->T, y + b0 * 2 * (size_t)nq * n, (int)nb, (int)nq, (int)nqp, cb,
+                                           c->d_lvl + lvl, c->qpmap(lvl), c->st))
+            hec_moddown_combine(c->T, cb, (int)nb, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
     }
     c->release(y);
     HEC_TRY_HIP(hipGetLastError());
@@ -949,7 +1011,7 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     }
     for (size_t i = 0; i < cnt; i++)
         if (c->galois(steps[i]) == 1) {
-            outs[i] = ct_clone(ct);
+            outs[i] = ct_clone(c, ct);
             if (!outs[i]) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
         }
     if (todo.empty()) return HEC_OK;
@@ -957,8 +1019,9 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     HEC_CHECK(ct_modup(c, ct, &D));
     const u64 *c0 = ct->d;
     // key switch in batches
-    for (size_t b0 = 0; b0 < todo.size(); b0 += HEC_KS_BATCH) {
-        const int R = (int)std::min((size_t)HEC_KS_BATCH, todo.size() - b0);
+    const size_t kbn = (size_t)std::max(1, std::min((int)HEC_KS_BATCH, hec_tune_params().ks_rot_batch));
+    for (size_t b0 = 0; b0 < todo.size(); b0 += kbn) {
+        const int R = (int)std::min(kbn, todo.size() - b0);
         u64 *e = c->alloc((size_t)R * 2 * nqp * n);
         u64 *y = c->alloc((size_t)R * 2 * nq * n);
         if (!e || !y) HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
@@ -980,11 +1043,15 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
         }
         hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
         c->ks_count += (uint64_t)R;
-        // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine
+        // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine (the
+        // combine fused into the NTT's last pass where the ring allows)
         hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
-        hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
-        hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
-        hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st, (int)c->k);
+        for (int r = 0; r < R; r++) cb.c0[r] = c0;
+        if (!hec_ntt_fwd_moddown(c->T, y, R, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), c->st)) {
+            hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
+            hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        }
         c->release(e);
         c->release(y);
     }
@@ -1013,7 +1080,7 @@ hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, in
     const uint32_t g = c->galois(step);
     if (g == 1) {
         for (size_t i = 0; i < cts.size(); i++)
-            if (!(outs[i] = ct_clone(cts[i]))) {
+            if (!(outs[i] = ct_clone(c, cts[i]))) {
                 free_all_cts(outs);
                 HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
             }
@@ -1051,9 +1118,11 @@ hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, in
             hec_ks_inner(c->T, kb, R, nullptr, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
             c->ks_count += (uint64_t)R;
             hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
-            hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st);
-            hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
-            hec_moddown_combine(c->T, cb, R, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+            hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st, (int)c->k);
+            if (!hec_ntt_fwd_moddown(c->T, y, R, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), c->st)) {
+                hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
+                hec_moddown_combine(c->T, cb, R, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+            }
         }
         c->release(e);
         c->release(y);
@@ -1061,6 +1130,109 @@ hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, in
     c->release(Dall);
     if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("batched rotation launch");
     if (s != HEC_OK) free_all_cts(outs);
+    return s;
+}
+
+// Key-stationary hoisted rotations of several ciphertexts at one level: every
+// input takes one ModUp (all in one set of launches), then the nonzero amounts
+// go through the key switch in batches of `batch` (<= HEC_KS_BATCH), each key
+// read once for all inputs of its batch (k_ks_inner_multi), and the ModDowns of
+// a batch's rotations share one set of NTT and base-conversion launches.
+// want[a] has bit u set when input u needs amount a.  sink(a0, na, rots) gets
+// the rotations of amounts a0 .. a0+na-1 as rots[(a - a0) * S + u] (null
+// where not wanted), valid until it returns; they equal ct_rotate_hoisted's bit
+// for bit (same ModUp, the same inner products and reductions, same ModDown).
+hec_status ct_rotate_multi(hec_ctx *c, const std::vector<const hec_ct *> &ins, const std::vector<int32_t> &amounts,
+                           const std::vector<uint64_t> &want, size_t batch, const RotSink &sink)
+{
+    const size_t S = ins.size();
+    if (!S || amounts.empty()) return HEC_OK;
+    if (S > HEC_MULTI_MAX_INPUTS) HEC_FAIL(HEC_EINVAL, "more than %d inputs in a key-stationary batch",
+                                           HEC_MULTI_MAX_INPUTS);
+    if (want.size() != amounts.size()) HEC_FAIL(HEC_EINVAL, "one input mask per amount");
+    batch = std::max<size_t>(1, std::min<size_t>(batch, HEC_KS_BATCH));
+    const size_t n = c->n;
+    const uint32_t lvl = ins[0]->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    for (int32_t a : amounts) {
+        const uint32_t g = c->galois(a);
+        if (g == 1) HEC_FAIL(HEC_EINVAL, "zero rotation in a key-stationary batch");
+        if (!c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", a);
+    }
+    u64 *Dall = nullptr;
+    HEC_CHECK(ct_modup_many(c, ins, &Dall));
+    const size_t dstride = (size_t)beta * nqp * n, estride = 2ull * nqp * n, ystride = 2ull * nq * n;
+    hec_status s = HEC_OK;
+    for (size_t a0 = 0; a0 < amounts.size() && s == HEC_OK; a0 += batch) {
+        const size_t na = std::min(batch, amounts.size() - a0), R = na * S;
+        u64 *e = c->alloc(R * estride), *y = c->alloc(R * ystride), *ro = c->alloc(R * ystride);
+        if (!e || !y || !ro) {
+            c->release(e);
+            c->release(y);
+            c->release(ro);
+            s = HEC_ENOMEM;
+            hec_set_error("key-stationary rotation buffers");
+            break;
+        }
+        KsMulti kb{};
+        for (size_t t = 0; t < na; t++) {
+            const uint32_t g = c->galois(amounts[a0 + t]);
+            kb.key[t] = c->rotkeys[g];
+            kb.out[t] = e + t * S * estride;
+            kb.mask[t] = want[a0 + t];
+            kb.g[t] = g;
+            c->ks_count += (uint64_t)__builtin_popcountll(want[a0 + t]);
+        }
+        if (!hec_ks_inner_multi(c->T, kb, (int)na, Dall, dstride, (int)S, estride, (int)beta, (int)nqp,
+                                c->qpmap(lvl), (int)c->NLK, c->st)) {
+            s = HEC_EINVAL;
+            hec_set_error("key-stationary key switch launch");
+        }
+        // ModDown of every slot of the batch (slots not wanted carry unused
+        // values); the combine as the epilogue of the forward NTT where the
+        // ring allows, in groups of HEC_KS_BATCH consecutive slots
+        const bool fused = c->logn == 16;
+        if (s == HEC_OK) {
+            hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, (int)(2 * R), c->qpmap(lvl) + nq, k, c->st);
+            hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, (int)(2 * R), 0,
+                      c->st, (int)c->k);
+            if (!fused) hec_ntt_fwd(c->T, y, (size_t)nq * n, (int)(2 * R), c->qpmap(lvl), nq, c->st);
+        }
+        std::vector<hec_ct> cts(R);
+        std::vector<hec_ct *> rots(R, nullptr);
+        for (size_t r0 = 0; r0 < R && s == HEC_OK; r0 += HEC_KS_BATCH) {
+            const size_t nr = std::min((size_t)HEC_KS_BATCH, R - r0);
+            CombineBatch cb{};
+            int nb = 0;
+            for (size_t r = r0; r < r0 + nr; r++) {
+                const size_t t = r / S, u = r % S;
+                const int slot = fused ? (int)(r - r0) : nb;
+                if (!((want[a0 + t] >> u) & 1)) continue;
+                cts[r].ctx = c;
+                cts[r].level = lvl;
+                cts[r].scale = ins[u]->scale;
+                cts[r].d = ro + r * ystride;
+                rots[r] = &cts[r];
+                cb.out[slot] = cts[r].d;
+                cb.e[slot] = e + r * estride;
+                cb.y[slot] = y + r * ystride;
+                cb.c0[slot] = ins[u]->d;
+                cb.g[slot] = kb.g[t];
+                nb++;
+            }
+            if (fused)
+                hec_ntt_fwd_moddown(c->T, y + r0 * ystride, (int)nr, (int)nq, (int)nqp, cb, c->d_lvl + lvl,
+                                    c->qpmap(lvl), c->st);
+            else if (nb)
+                hec_moddown_combine(c->T, cb, nb, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        }
+        if (s == HEC_OK && hipGetLastError() != hipSuccess) s = HEC_EDEVICE, hec_set_error("key-stationary launch");
+        if (s == HEC_OK) s = sink(a0, na, rots);
+        c->release(e);
+        c->release(y);
+        c->release(ro);
+    }
+    c->release(Dall);
     return s;
 }
 
@@ -1180,7 +1352,7 @@ extern "C" hec_status ckks_add(hec_ctx *c, const hec_ct *a, const hec_ct *b, hec
     if (a->level != b->level) HEC_FAIL(HEC_ELEVEL, "level mismatch");
     if (a->scale != b->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch");
     HEC_TRY_HIP(hipSetDevice(c->dev));
-    hec_ct *o = ct_clone(a);
+    hec_ct *o = ct_clone(c, a);
     if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
     hec_status s = ct_add_inplace(c, o, b);
     if (s != HEC_OK) { ct_free(o); return s; }
@@ -1428,7 +1600,7 @@ hec_status ct_add_pt(hec_ctx *c, const hec_ct *a, const hec_pt *pt, hec_ct **out
     if (a->scale != pt->scale) HEC_FAIL(HEC_ESCALE, "scale mismatch in plaintext addition");
     const size_t nq = a->level + 1;
     u64 *t = c->alloc(nq * c->n);
-    hec_ct *o = ct_clone(a);
+    hec_ct *o = ct_clone(c, a);
     if (!t || !o) {
         c->release(t);
         ct_free(o);

@@ -1,6 +1,7 @@
 // hec_internal.h -- host-side structures of the library (not part of the ABI).
 #pragma once
 #include <array>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -41,13 +42,20 @@ void hec_set_error(const char *fmt, ...);
 // to later work on the same stream.  When the device is out of memory the
 // cached blocks go back to it (after its queued work is done) and the
 // allocation is tried once more.
+// Thread-safe: a server's workers and its clients (freeing results) share pools.
 struct DevPool {
     std::unordered_multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> live_;
-    size_t bytes_live = 0, bytes_cached = 0;
+    size_t bytes_live = 0, bytes_cached = 0, peak_live = 0;
+    std::mutex mu_;
     void *get(size_t bytes);
-    void put(void *p);
+    bool put(void *p);  // false: not a block of this pool
     void release_all();
+    size_t live()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return bytes_live;
+    }
 };
 
 struct Layout {
@@ -98,14 +106,30 @@ struct hec_ctx {
     std::map<std::string, hec_pt *> mask_cache;
     std::map<uint32_t, u64 *> ones_qp;     // level -> the constant 1 over Q_l and P, Montgomery form
     uint64_t ks_count = 0;                 // key-switch inner products computed (one per rotation by g != 1)
+    bool lane = false;                     // a serving lane: tables and keys belong to its parent
     std::mutex mu;
 
     const u32 *idmap() const { return d_maps; }
     const u32 *qpmap(uint32_t level) const { return d_maps + qp_off[level]; }
     size_t limb() const { return (size_t)n; }
     uint32_t galois(int64_t step) const;
-    u64 *alloc(size_t words) { return (u64 *)pool.get(words * 8); }
-    void release(void *p) { if (p) pool.put(p); }
+    // where evaluation temporaries and results come from: the context's pool,
+    // or the memory a captured graph keeps (hec_batch) while it records
+    DevPool *active = &pool;
+    u64 *alloc(size_t words) { return (u64 *)active->get(words * 8); }
+    void release(void *p)
+    {
+        if (p && !active->put(p) && active != &pool) pool.put(p);
+    }
+};
+
+// Routes the context's allocations to `p` for the scope (caches that outlive
+// any batch are filled from the context's own pool).
+struct PoolScope {
+    hec_ctx *c;
+    DevPool *prev;
+    PoolScope(hec_ctx *c_, DevPool *p) : c(c_), prev(c_->active) { c->active = p; }
+    ~PoolScope() { c->active = prev; }
 };
 
 struct hec_ct {
@@ -132,12 +156,19 @@ struct hec_image {
 
 // ---- internal API (hec_ctx.hip) -------------------------------------------
 hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale);
-hec_ct *ct_clone(const hec_ct *a);
+// a copy made on (allocated from and ordered on) context c
+hec_ct *ct_clone(hec_ctx *c, const hec_ct *a);
 hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
 hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
 // every ciphertext (all at one level) rotated by `step`: one batched ModUp, key
 // switch and ModDown; the same ciphertexts as one rotation at a time
 hec_status ct_rotate_many(hec_ctx *c, const std::vector<const hec_ct *> &cts, int32_t step, std::vector<hec_ct *> &outs);
+// key-stationary hoisted rotations of several ciphertexts at one level (ct_rotate_multi in hec_ctx.hip):
+// want[a] bit u = input u needs amounts[a] (nonzero); the sink receives each batch of amounts' rotations,
+// rots[(a - a0) * S + u] (null where not wanted), borrowed until it returns
+typedef std::function<hec_status(size_t a0, size_t na, const std::vector<hec_ct *> &rots)> RotSink;
+hec_status ct_rotate_multi(hec_ctx *c, const std::vector<const hec_ct *> &ins, const std::vector<int32_t> &amounts,
+                           const std::vector<uint64_t> &want, size_t batch, const RotSink &sink);
 // npolys polynomials [npolys][l+1][n] at level l divided by q_l (*d replaced by [npolys][l][n])
 hec_status rescale_polys(hec_ctx *c, u64 **d, uint32_t l, int npolys);
 // the per-limb residues of the integer r (and Shoup companions) for limbs 0..nlimbs-1
@@ -183,6 +214,10 @@ bool have_rotkey(hec_ctx *c, int32_t step);
 // ct + pt (pt at the ciphertext's level and scale, without special-prime limbs)
 hec_status ct_add_pt(hec_ctx *c, const hec_ct *a, const hec_pt *pt, hec_ct **out);
 
+// serving lanes (hec_ctx.hip): contexts that share a parent's tables and keys
+hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out);
+void ctx_lane_destroy(hec_ctx *lane);
+
 // ---- polynomial evaluation (hec_poly.cpp) ----------------------------------
 // level and scale of the Chebyshev evaluation of a (level, scale) input, from a
 // run over levels and scales only (also checks the constants and the level budget)
@@ -203,6 +238,12 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t level, const
                             uint32_t basis = 0);
 // output layout of a plan (before the downsampling of a strided one)
 const Layout &conv_plan_out(const hec_conv_plan *p);
+// several images of a plan's layout and level, and the 2x2 pooling of several images of one layout,
+// in one evaluation (key-stationary over all their shards in mode 4; image by image otherwise)
+hec_status conv_plan_run_multi(hec_ctx *c, const hec_conv_plan *p, const std::vector<const hec_image *> &ins,
+                               std::vector<hec_image *> &outs);
+hec_status avgpool_multi(hec_ctx *c, const std::vector<const hec_image *> &ins, int mode,
+                         std::vector<hec_image *> &outs);
 // in + the per-channel bias (new handles in out)
 hec_status image_add_bias(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, const double *bias,
                           std::vector<hec_ct *> &out);

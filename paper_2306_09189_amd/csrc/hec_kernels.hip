@@ -9,8 +9,11 @@
 //     once (base conversion, key-switch inner product).
 // Everything runs on the VALU: this is exact modular arithmetic, not a float
 // contraction, so the matrix cores are not used.
+#include <atomic>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,8 +33,17 @@ struct Prof {
     uint64_t launches = 0, units = 0;
 };
 Prof g_prof;
-// launches of every named kernel since the library was loaded
-std::map<std::string, uint64_t> g_count;
+// launches of every named kernel since the library was loaded (counters are
+// never freed, so a launch site keeps a pointer to its own)
+std::mutex g_count_mu;
+std::map<std::string, std::unique_ptr<std::atomic<uint64_t>>> g_count;
+std::atomic<uint64_t> *prof_counter(const char *name)
+{
+    std::lock_guard<std::mutex> lk(g_count_mu);
+    auto &p = g_count[name];
+    if (!p) p.reset(new std::atomic<uint64_t>(0));
+    return p.get();
+}
 hipEvent_t prof_event()
 {
     hipEvent_t e;
@@ -73,14 +85,16 @@ int hec_prof_collect(uint64_t *launches, uint64_t *units, double *ms)
 }
 uint64_t hec_prof_count(const char *name)
 {
+    std::lock_guard<std::mutex> lk(g_count_mu);
     auto it = g_count.find(name);
-    return it == g_count.end() ? 0 : it->second;
+    return it == g_count.end() ? 0 : it->second->load();
 }
 // A timed launch passes its events to the dispatch itself (hipExtLaunchKernelGGL),
 // so the two timestamps bracket the kernel's execution and nothing else.
 #define KLAUNCH(kname, nunits, kernel, grid, block, lds, st, ...)                                                  \
     do {                                                                                                           \
-        g_count[kname]++;                                                                                          \
+        static std::atomic<uint64_t> *cnt_ = prof_counter(kname);                                                  \
+        cnt_->fetch_add(1, std::memory_order_relaxed);                                                             \
         if (g_prof.on && !strcmp(g_prof.name, kname)) {                                                            \
             hipEvent_t e0_ = prof_event(), e1_ = prof_event();                                                     \
             hipExtLaunchKernelGGL(kernel, grid, block, lds, st, e0_, e1_, 0, __VA_ARGS__);                        \
@@ -385,21 +399,12 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_s
     for (int i = 0; i < 16; i++) a[(size_t)(16 * hb + i) * 256 + col] = x[i];
 }
 
-// forward row pass: stages 8..15 inside 16 rows of 256 words; fully reduced
-// output (RS: written as (c - output) q_l^-1 to the rescaled polynomial)
-template <bool RS>
-__global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
-                                                        RescaleFuse f, DevTables T)
+// forward row pass: stages 8..15 inside 16 rows of 256 words; the fully
+// reduced output of each row is left in its LDS row lr (padded) for the
+// epilogue of the caller
+DEV void ntt16_fwd_rows_body(const u64 *a, u64 *lr, u32 grow, u32 row, u32 l, const u64 *w, const u64 *ws, u64 q)
 {
-    __shared__ u64 lds[16 * 272];
-    const Ntt16Item it = ntt16_item(npolys);
-    const u32 pi = pmap[it.limb];
-    const u64 q = T.pc[pi].q, q2 = 2 * q;
-    const u32 r0 = it.tile * 16;
-    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
-    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
-    const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
-    const u32 grow = r0 + row;
+    const u64 q2 = 2 * q;
     u64 x[16];
 #pragma unroll
     for (int h = 0; h < 16; h++) x[h] = a[row * 256 + l + 16 * h];
@@ -413,7 +418,6 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
                 ct_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
             }
     }
-    u64 *lr = lds + row * 272;
 #pragma unroll
     for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = x[h];
     __syncthreads();
@@ -433,6 +437,24 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
 #pragma unroll
     for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = reduce4(x[i], q);
     __syncthreads();
+}
+
+// forward row pass; fully reduced output (RS: written as (c - output) q_l^-1
+// to the rescaled polynomial)
+template <bool RS>
+__global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+                                                        RescaleFuse f, DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const u64 q = T.pc[pi].q;
+    const u32 r0 = it.tile * 16;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
+    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
+    const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
+    u64 *lr = lds + row * 272;
+    ntt16_fwd_rows_body(a, lr, r0 + row, row, l, w, ws, q);
     if (RS) {
         const size_t off = ((size_t)it.limb << 16) + (size_t)r0 * 256 + row * 256;
         const u64 *cp = f.c + it.poly * f.cs + off;
@@ -444,6 +466,42 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
     } else {
 #pragma unroll
         for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = lr[N16_PAD(l + 16 * h)];
+    }
+}
+
+// forward row pass of the P -> Q conversion y of a batch of ModDowns (poly z
+// = entry z / 2, polynomial z % 2) with the ModDown tail as its epilogue:
+// out = (e - NTT(y)) P^-1 (+ sigma_g(c0) on polynomial 0, + add), so NTT(y) is
+// never written back and read again.  Same residues as the row pass followed
+// by k_moddown_combine.
+__global__ void __launch_bounds__(256) k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 nqp, const u32 *pmap, u32 npolys,
+                                                           CombineBatch cb, const LevelC *lc, DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const u64 q = T.pc[pi].q;
+    const u32 r0 = it.tile * 16;
+    const size_t ps = (size_t)nq << 16;
+    u64 *a = y + it.poly * ps + ((size_t)it.limb << 16) + (size_t)r0 * 256;
+    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
+    const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
+    u64 *lr = lds + row * 272;
+    ntt16_fwd_rows_body(a, lr, r0 + row, row, l, w, ws, q);
+    const u32 r = it.poly >> 1, p = it.poly & 1, i = it.limb;
+    if (!cb.out[r]) return;  // a slot of the batch nobody asked for
+    const u64 pinv = lc->pinv[i], pinv_sh = lc->pinv_sh[i];
+    const u64 *e = cb.e[r] + ((size_t)p * nqp + i) * 65536;
+    u64 *out = cb.out[r] + ((size_t)p * nq + i) * 65536;
+    const u64 *c0 = (p == 0 && cb.c0[r]) ? cb.c0[r] + (size_t)i * 65536 : nullptr;
+    const u64 *ad = cb.add[r][p] ? cb.add[r][p] + (size_t)i * 65536 : nullptr;
+#pragma unroll
+    for (int h = 0; h < 16; h++) {
+        const u32 k = (r0 + row) * 256 + l + 16 * h;
+        u64 v = shoup_mul(sub_mod(e[k], lr[N16_PAD(l + 16 * h)], q), pinv, pinv_sh, q);
+        if (c0) v = add_mod(v, c0[auto_src(k, cb.g[r], 16)], q);
+        if (ad) v = add_mod(v, ad[k], q);
+        out[k] = v;
     }
 }
 
@@ -545,11 +603,42 @@ __global__ void __launch_bounds__(256) k_ntt16_inv_cols(u64 *base, size_t poly_s
     for (int h = 0; h < 16; h++) a[(size_t)(l + 16 * h) * 256 + col] = shoup_mul(x[h], pc.ninv, pc.ninv_sh, q);
 }
 
+TuneParams &hec_tune_params()
+{
+    static TuneParams p;
+    return p;
+}
+static void ntt_launch_one(const DevTables &T, bool inv, u64 *base, size_t poly_stride, int npolys, const u32 *pmap,
+                           int nlimbs, hipStream_t st);
+
 static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stride, int npolys, const u32 *pmap,
                        int nlimbs, hipStream_t st)
 {
     if (nlimbs <= 0 || npolys <= 0) return;
-    if (T.logn == 16) {
+    const TuneParams &tp = hec_tune_params();
+    // limb grouping: several launches of at most ntt_group limbs each
+    if (tp.ntt_group > 0 && (int64_t)nlimbs * npolys > tp.ntt_group) {
+        if (nlimbs > tp.ntt_group) {
+            for (int p = 0; p < npolys; p++)
+                for (int l0 = 0; l0 < nlimbs; l0 += tp.ntt_group)
+                    ntt_launch_one(T, inv, base + (size_t)p * poly_stride + (size_t)l0 * T.n, poly_stride, 1,
+                                   pmap + l0, std::min(tp.ntt_group, nlimbs - l0), st);
+        } else {
+            const int per = tp.ntt_group / nlimbs;
+            for (int p0 = 0; p0 < npolys; p0 += per)
+                ntt_launch_one(T, inv, base + (size_t)p0 * poly_stride, poly_stride, std::min(per, npolys - p0), pmap,
+                               nlimbs, st);
+        }
+        return;
+    }
+    ntt_launch_one(T, inv, base, poly_stride, npolys, pmap, nlimbs, st);
+}
+
+static void ntt_launch_one(const DevTables &T, bool inv, u64 *base, size_t poly_stride, int npolys, const u32 *pmap,
+                           int nlimbs, hipStream_t st)
+{
+    const TuneParams &tp = hec_tune_params();
+    if (T.logn == 16 && tp.ntt16_radix == 16) {
         const uint64_t limbs = (uint64_t)nlimbs * npolys;
         dim3 g((u32)(16 * limbs));
         const u32 np = (u32)npolys;
@@ -569,8 +658,10 @@ static void ntt_launch(const DevTables &T, bool inv, u64 *base, size_t poly_stri
     ntt_split(T.logn, logn1, logn2);
     u32 n1 = 1u << logn1, n2 = 1u << logn2;
     u32 C = n2 < 16 ? n2 : 16;
-    u32 R = NTT_TILE / n2;
+    const u32 tile = (tp.ntt_tile == 2048 || tp.ntt_tile == 8192) ? (u32)tp.ntt_tile : NTT_TILE;
+    u32 R = tile / n2;
     if (R > n1) R = n1;
+    if (R < 1) R = 1;
     dim3 gc(n2 / C, nlimbs, npolys), gr(n1 / R, nlimbs, npolys);
     size_t lc = (size_t)n1 * C * 8, lr = (size_t)R * n2 * 8;
     if (!inv) {
@@ -596,6 +687,19 @@ bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64
     KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<true>, g, dim3(256), 0, st, dst, dst_stride, pmap, np, src,
             src_stride, T);
     KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, dst, dst_stride, pmap, np, T);
+    return true;
+}
+bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, const CombineBatch &cb,
+                         const LevelC *lc, const u32 *pmap, hipStream_t st)
+{
+    if (T.logn != 16 || nrot < 1 || nrot > HEC_KS_BATCH || nq < 1) return false;
+    const u32 np = 2u * (u32)nrot;
+    const uint64_t limbs = (uint64_t)nq * np;
+    dim3 g((u32)(16 * limbs));
+    KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, y, (size_t)nq << 16, pmap, np,
+            RescaleFuse{}, T);
+    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np, cb,
+            lc, T);
     return true;
 }
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
@@ -809,61 +913,104 @@ void hec_sample_small(const DevTables &T, int64_t *out, u64 seed, u32 purpose, u
 // ---------------------------------------------------------------------------
 // fast base conversion (coefficient form)
 // ---------------------------------------------------------------------------
-#define BC_THREADS 256
-#define BC_OUT 8  // outputs per workgroup (a grid row of workgroups per group of outputs)
-// Workgroup (x, y, z): 256 coefficients, outputs y*BC_OUT .. y*BC_OUT+7 of
+// Workgroup (x, y, z): 256 coefficients; outputs y*per .. y*per+per-1 of
 // descriptor dd[(z % group) * dstride], source src + (z / group)*sps,
 // destination dst + z*dps (groups of `group` polynomials share a source, e.g.
-// the digits of one ModUp).
-// With copy_in, the row y = ngroups copies the input limbs to the same
-// positions of the destination (a ModUp digit then holds all its limbs).
-// The inputs a_i stay in registers (loop bounds fixed at compile time); the
-// descriptor fields are uniform over the workgroup.
+// the digits of one ModUp).  Each lane computes its coefficient's a_i once and
+// then every output of its group from them, so the inputs are read and scaled
+// once per coefficient, not once per group of eight outputs; the descriptor's
+// matrix and the output primes' constants are staged in LDS (every lane reads
+// the same word: a broadcast).  NIN (the number of inputs) is a compile-time
+// constant so that the a_i stay in registers.  With copy_in the lanes of the
+// first output group also copy the inputs to the same positions of the
+// destination (a ModUp digit then holds all its limbs).
+#define BC_THREADS 256
+template <int NIN>
 __global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 dstride, u32 group, const u64 *src,
-                                                      u64 *dst, size_t sps, size_t dps, u32 ngroups, u32 copy_in,
+                                                      u64 *dst, size_t sps, size_t dps, u32 per, u32 copy_in,
                                                       DevTables T)
 {
+    __shared__ u64 hat[HEC_MAX_BCONV_IN * HEC_MAX_LIMBS];
+    __shared__ u64 oq[HEC_MAX_LIMBS], oqi[HEC_MAX_LIMBS];
+    __shared__ u32 opos[HEC_MAX_LIMBS];
     const BconvDesc *d = dd + (blockIdx.z % group) * dstride;
+    const u32 nout = d->nout, nin = d->nin;
+    const u32 j0 = blockIdx.y * per;
+    const u32 j1 = j0 + per < nout ? j0 + per : nout;
+    for (u32 e = threadIdx.x; e < nin * nout; e += BC_THREADS) hat[e] = d->hat_m[e];
+    for (u32 j = threadIdx.x; j < nout; j += BC_THREADS) {
+        const PrimeC pc = T.pc[d->out_prime[j]];
+        oq[j] = pc.q;
+        oqi[j] = pc.qinv_neg;
+        opos[j] = d->out_pos[j];
+    }
+    __syncthreads();
     const size_t n = T.n;
     const u32 t = blockIdx.x * BC_THREADS + threadIdx.x;
-    if (t >= n) return;
-    const u32 nin = d->nin, nout = d->nout;
+    if (t >= n || j0 >= nout) return;
     const u64 *s = src + (blockIdx.z / group) * sps;
     u64 *o = dst + blockIdx.z * dps;
-    if (blockIdx.y == ngroups) {
-        if (copy_in)
-            for (u32 i = 0; i < nin; i++) o[(size_t)d->in_pos[i] * n + t] = s[(size_t)d->in_pos[i] * n + t];
-        return;
-    }
-    const u32 j0 = blockIdx.y * BC_OUT;
-    if (j0 >= nout) return;
-    const u32 j1 = j0 + BC_OUT < nout ? j0 + BC_OUT : nout;
-    u64 a[HEC_MAX_BCONV_IN];
+    u64 a[NIN];
 #pragma unroll
-    for (u32 i = 0; i < HEC_MAX_BCONV_IN; i++) {
+    for (int i = 0; i < NIN; i++) {
         a[i] = 0;
-        if (i < nin) {
+        if ((u32)i < nin) {
+            const u64 x = s[(size_t)d->in_pos[i] * n + t];
+            if (copy_in && blockIdx.y == 0) o[(size_t)d->in_pos[i] * n + t] = x;
             const u64 q = T.pc[d->in_prime[i]].q;
-            a[i] = shoup_mul(s[(size_t)d->in_pos[i] * n + t], d->inv_hat[i], d->inv_hat_sh[i], q);
+            a[i] = shoup_mul(x, d->inv_hat[i], d->inv_hat_sh[i], q);
         }
     }
     for (u32 j = j0; j < j1; j++) {
         acc128 acc = {0, 0};
 #pragma unroll
-        for (u32 i = 0; i < HEC_MAX_BCONV_IN; i++)
-            if (i < nin) mac(acc, a[i], d->hat_m[i * nout + j]);
-        const PrimeC pc = T.pc[d->out_prime[j]];
-        o[(size_t)d->out_pos[j] * n + t] = redc(acc.hi, acc.lo, pc.q, pc.qinv_neg);
+        for (int i = 0; i < NIN; i++)
+            if ((u32)i < nin) mac(acc, a[i], hat[i * nout + j]);
+        o[(size_t)opos[j] * n + t] = redc(acc.hi, acc.lo, oq[j], oqi[j]);
     }
 }
-void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int group, int nout_max, const u64 *src,
-               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st)
+template <int NIN>
+static void bconv_launch(dim3 g, uint64_t units, hipStream_t st, const BconvDesc *d_desc, u32 dstride, u32 group,
+                         const u64 *src, u64 *dst, size_t sps, size_t dps, u32 per, u32 copy_in, const DevTables &T)
 {
-    if (npolys <= 0 || group <= 0) return;
-    const u32 ngroups = ((u32)nout_max + BC_OUT - 1) / BC_OUT;
-    dim3 g((T.n + BC_THREADS - 1) / BC_THREADS, ngroups + (copy_in ? 1 : 0), npolys);
-    KLAUNCH("k_bconv", (uint64_t)npolys, k_bconv, g, dim3(BC_THREADS), 0, st, d_desc, (u32)desc_stride, (u32)group,
-            src, dst, src_poly_stride, dst_poly_stride, ngroups, (u32)(copy_in ? 1 : 0), T);
+    KLAUNCH("k_bconv", units, k_bconv<NIN>, g, dim3(BC_THREADS), 0, st, d_desc, dstride, group, src, dst, sps, dps,
+            per, copy_in, T);
+}
+// nin_max: the largest input count among the launch's descriptors (the digits
+// of a ModUp have alpha inputs but a partial last one)
+void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int group, int nout_max, const u64 *src,
+               u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st,
+               int nin_max)
+{
+    const int nin = nin_max;
+    if (npolys <= 0 || group <= 0 || nin < 1 || nin > HEC_MAX_BCONV_IN) return;
+    // all outputs of a coefficient in one lane when the launch has workgroups
+    // enough to fill the chip; else groups of 8 outputs (more, smaller lanes)
+    const u32 chunks = (T.n + BC_THREADS - 1) / BC_THREADS;
+    const u32 per = (uint64_t)chunks * npolys >= 2048 ? (u32)nout_max : 8u;
+    const u32 ngroups = ((u32)nout_max + per - 1) / per;
+    dim3 g(chunks, ngroups, npolys);
+#define BCV_ARGS g, (uint64_t)npolys, st, d_desc, (u32)desc_stride, (u32)group, src, dst, src_poly_stride, \
+                 dst_poly_stride, per, (u32)(copy_in ? 1 : 0), T
+    switch (nin) {
+    case 1: bconv_launch<1>(BCV_ARGS); break;
+    case 2: bconv_launch<2>(BCV_ARGS); break;
+    case 3: bconv_launch<3>(BCV_ARGS); break;
+    case 4: bconv_launch<4>(BCV_ARGS); break;
+    case 5: bconv_launch<5>(BCV_ARGS); break;
+    case 6: bconv_launch<6>(BCV_ARGS); break;
+    case 7: bconv_launch<7>(BCV_ARGS); break;
+    case 8: bconv_launch<8>(BCV_ARGS); break;
+    case 9: bconv_launch<9>(BCV_ARGS); break;
+    case 10: bconv_launch<10>(BCV_ARGS); break;
+    case 11: bconv_launch<11>(BCV_ARGS); break;
+    case 12: bconv_launch<12>(BCV_ARGS); break;
+    case 13: bconv_launch<13>(BCV_ARGS); break;
+    case 14: bconv_launch<14>(BCV_ARGS); break;
+    case 15: bconv_launch<15>(BCV_ARGS); break;
+    default: bconv_launch<16>(BCV_ARGS);
+    }
+#undef BCV_ARGS
 }
 
 // ---------------------------------------------------------------------------
@@ -906,6 +1053,90 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
     dim3 g(nchunks * (u32)nqp * (u32)nrot);
     KLAUNCH("k_ks_inner", (uint64_t)nrot * nqp, k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp,
             pmap, (u32)NLK, (u32)nrot, nchunks, T);
+}
+
+// Key-stationary form of the same products for several inputs that share the
+// rotations of a launch (the image shards of a layer): each thread loads its
+// coefficient of the term's key limbs once into registers and loops over the
+// inputs, so a key is read from HBM once per launch instead of once per input.
+// Same accumulation as k_ks_inner (digits in order, one reduction), so the
+// same residues.  Flat XCD-aware grid over (limb, rotation, chunk).
+template <int BETA>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_inner_multi(KsMulti kb, const u64 *D, size_t dstride, u32 S,
+                                                               size_t estride, u32 beta_rt, u32 nqp, const u32 *pmap,
+                                                               u32 NLK, u32 nrot, u32 nchunks, DevTables T)
+{
+    const u32 w = blockIdx.x, total = gridDim.x;
+    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 chunk = i % nchunks, rest = i / nchunks;
+    const u32 r = rest % nrot, o = rest / nrot;
+    const u32 k = chunk * EW_THREADS + threadIdx.x;
+    if (k >= T.n) return;
+    const u32 beta = BETA ? BETA : beta_rt;
+    const u32 pi = pmap[o];
+    const PrimeC pc = T.pc[pi];
+    const u32 src = auto_src(k, kb.g[r], T.logn);
+    const size_t n = T.n;
+    const u64 *key = kb.key[r];
+    const u64 m = kb.mask[r];
+    u64 *out = kb.out[r];
+    u64 kb0[BETA ? BETA : 1], kb1[BETA ? BETA : 1];
+    if (BETA) {
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+            kb0[j] = key[(((size_t)j * 2 + 0) * NLK + pi) * n + k];
+            kb1[j] = key[(((size_t)j * 2 + 1) * NLK + pi) * n + k];
+        }
+    }
+    for (u32 u = 0; u < S; u++) {
+        if (!((m >> u) & 1)) continue;
+        const u64 *Du = D + (size_t)u * dstride;
+        acc128 a0 = {0, 0}, a1 = {0, 0};
+        if (BETA) {
+#pragma unroll
+            for (int j = 0; j < BETA; j++) {
+                const u64 d = Du[((size_t)j * nqp + o) * n + src];
+                mac(a0, d, kb0[j]);
+                mac(a1, d, kb1[j]);
+            }
+        } else {
+            for (u32 j = 0; j < beta; j++) {
+                const u64 d = Du[((size_t)j * nqp + o) * n + src];
+                mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
+                mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+            }
+        }
+        u64 *e = out + (size_t)u * estride;
+        e[(size_t)o * n + k] = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
+        e[((size_t)nqp + o) * n + k] = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+    }
+}
+template <int BETA>
+static void ks_inner_multi_launch(dim3 g, uint64_t units, hipStream_t st, const KsMulti &kb, const u64 *D,
+                                  size_t dstride, u32 S, size_t estride, u32 beta, u32 nqp, const u32 *pmap, u32 NLK,
+                                  u32 nrot, u32 nchunks, const DevTables &T)
+{
+    KLAUNCH("k_ks_inner_multi", units, k_ks_inner_multi<BETA>, g, dim3(EW_THREADS), 0, st, kb, D, dstride, S, estride,
+            beta, nqp, pmap, NLK, nrot, nchunks, T);
+}
+bool hec_ks_inner_multi(const DevTables &T, const KsMulti &kb, int nrot, const u64 *D, size_t dstride, int S,
+                        size_t estride, int beta, int nqp, const u32 *pmap, int NLK, hipStream_t st)
+{
+    if (nrot < 1 || nrot > HEC_KS_BATCH || S < 1 || S > HEC_MULTI_MAX_INPUTS || beta < 1) return false;
+    const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
+    dim3 g(nchunks * (u32)nqp * (u32)nrot);
+    // units: key limbs read once, digits once per input, outputs written
+    const uint64_t units = (uint64_t)nrot * 2 * beta * nqp + (uint64_t)S * beta * nqp + (uint64_t)nrot * S * 2 * nqp;
+#define KSM_ARGS g, units, st, kb, D, dstride, (u32)S, estride, (u32)beta, (u32)nqp, pmap, (u32)NLK, (u32)nrot, nchunks, T
+    switch (beta) {
+    case 1: ks_inner_multi_launch<1>(KSM_ARGS); break;
+    case 2: ks_inner_multi_launch<2>(KSM_ARGS); break;
+    case 3: ks_inner_multi_launch<3>(KSM_ARGS); break;
+    case 4: ks_inner_multi_launch<4>(KSM_ARGS); break;
+    default: ks_inner_multi_launch<0>(KSM_ARGS);
+    }
+#undef KSM_ARGS
+    return true;
 }
 
 // Key switching fused with the plaintext products of a convolution, summed

@@ -497,6 +497,7 @@ static hec_status get_masks(hec_ctx *c, const Layout &L, char kind, const std::v
     }
     for (auto &v : vecs) zp.push_back(v.data());
     std::vector<hec_pt *> pts;
+    PoolScope ps(c, &c->pool);  // cached for the context's lifetime
     HEC_CHECK(pt_encode_many(c, zp, L.N, level, scale, pts, true));
     for (size_t a = 0; a < miss.size(); a++) {
         c->mask_cache[keys[miss[a]]] = pts[a];
@@ -958,10 +959,10 @@ static hec_status downsample(hec_ctx *c, const std::vector<hec_ct *> &in, const 
         if (!select) {
             std::vector<hec_ct *> r;
             HEC_CHECK(rotate_list(c, ct, {1, (int32_t)mp, (int32_t)mp + 1}, r));
-            D = ct_clone(ct);
+            D = ct_clone(c, ct);
             for (auto *x : r) HEC_CHECK(sum_into(c, D, x));
         } else {
-            D = ct_clone(ct);
+            D = ct_clone(c, ct);
         }
         std::vector<int32_t> hs;
         for (uint32_t i = 0; i < Wo; i++) hs.push_back((int32_t)i);
@@ -991,7 +992,7 @@ static hec_status duplicate(hec_ctx *c, hec_ct *ct, Layout &L, uint32_t d, hec_c
     for (uint32_t m = 1; m < d; m++) sh.push_back(-(int32_t)(m * step) * Bn);
     std::vector<hec_ct *> r;
     HEC_CHECK(rotate_list(c, ct, sh, r));
-    hec_ct *acc = ct_clone(ct);
+    hec_ct *acc = ct_clone(c, ct);
     for (auto *x : r) HEC_CHECK(sum_into(c, acc, x));
     std::vector<int32_t> lam = L.maps[0];
     for (uint32_t b = 0; b < L.nb() / 4; b++)
@@ -1048,7 +1049,7 @@ static hec_status downsample_channel(hec_ctx *c, const std::vector<hec_ct *> &in
             out.push_back(a);
             continue;
         }
-        hec_ct *D = ct_clone(ct);
+        hec_ct *D = ct_clone(c, ct);
         if (!select) {
             std::vector<hec_ct *> r;
             HEC_CHECK(rotate_list(c, ct, {1, (int32_t)mp, (int32_t)mp + 1}, r));
@@ -1078,7 +1079,7 @@ static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Lay
     std::vector<std::vector<std::pair<int32_t, int32_t>>> groups;
     for (size_t s0 = 0; s0 < t; s0 += 4) {
         const size_t g = std::min((size_t)4, t - s0);
-        hec_ct *acc = ct_clone(ds[s0]);
+        hec_ct *acc = ct_clone(c, ds[s0]);
         for (size_t e = 1; e < g; e++) {
             hec_ct *r = nullptr;
             HEC_CHECK(ckks_rotate(c, ds[s0 + e], -(int32_t)(e * q4), &r));
@@ -1110,28 +1111,169 @@ static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Lay
     return HEC_OK;
 }
 
-static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                       int mode, std::vector<hec_ct *> &out, Layout &ol)
+static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots, const std::vector<RotTerm> &its,
+                                size_t i0, std::vector<hec_ct *> &acc, std::vector<char> &first, const BasisArg *bt);
+
+// out[u] = sum_t masks[t] * rot(ins[u], steps[t]) for every input u at once:
+// the nonzero rotations of all inputs amount by amount (ct_rotate_multi), the
+// products and sums as plaintext-product batches (mac_rotations).  The same
+// rotations and the same exact sums as one masked sum per input (mode 0).
+static hec_status masked_sums_multi(hec_ctx *c, const std::vector<const hec_ct *> &ins,
+                                    const std::vector<int32_t> &steps, const std::vector<hec_pt *> &masks,
+                                    std::vector<hec_ct *> &out)
 {
-    std::vector<hec_ct *> ds;
-    if (L.channel) {
-        HEC_CHECK(downsample_channel(c, in, L, select, mode, ds));
-        const uint32_t H2 = select ? (L.H + 1) / 2 : L.H / 2, W2 = select ? (L.W + 1) / 2 : L.W / 2;
-        hec_status s = merge_channel(c, ds, L, H2, W2, out, ol);
-        free_all(ds);
+    const size_t S = ins.size();
+    out.assign(S, nullptr);
+    for (size_t u = 0; u < S; u++)
+        if (!(out[u] = ct_new(c, ins[u]->level, 1.0))) {
+            free_all(out);
+            HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+        }
+    std::vector<char> first(S, 1);
+    std::vector<hec_ct *> zr;
+    std::vector<RotTerm> zi;
+    std::vector<int32_t> amounts;
+    std::vector<size_t> tidx;
+    for (size_t t = 0; t < steps.size(); t++) {
+        if (c->galois(steps[t]) != 1) {
+            amounts.push_back(steps[t]);
+            tidx.push_back(t);
+            continue;
+        }
+        for (size_t u = 0; u < S; u++) {
+            zr.push_back(const_cast<hec_ct *>(ins[u]));
+            RotTerm rt;
+            rt.amount = steps[t];
+            rt.pts.push_back({(uint32_t)u, masks[t]});
+            zi.push_back(std::move(rt));
+        }
+    }
+    hec_status s = zr.empty() ? HEC_OK : mac_rotations(c, zr, zi, 0, out, first, nullptr);
+    for (size_t u0 = 0; u0 < S && s == HEC_OK && !amounts.empty(); u0 += HEC_MULTI_MAX_INPUTS) {
+        const size_t G = std::min((size_t)HEC_MULTI_MAX_INPUTS, S - u0);
+        std::vector<const hec_ct *> grp(ins.begin() + u0, ins.begin() + u0 + G);
+        const uint64_t all = G == 64 ? ~0ull : ((1ull << G) - 1);
+        std::vector<uint64_t> want(amounts.size(), all);
+        auto sink = [&](size_t a0, size_t na, const std::vector<hec_ct *> &rots) -> hec_status {
+            std::vector<hec_ct *> rs;
+            std::vector<RotTerm> its;
+            for (size_t u = 0; u < G; u++)
+                for (size_t t = 0; t < na; t++) {
+                    rs.push_back(rots[t * G + u]);
+                    RotTerm rt;
+                    rt.amount = amounts[a0 + t];
+                    rt.pts.push_back({(uint32_t)(u0 + u), masks[tidx[a0 + t]]});
+                    its.push_back(std::move(rt));
+                }
+            return mac_rotations(c, rs, its, 0, out, first, nullptr);
+        };
+        s = ct_rotate_multi(c, grp, amounts, want, (size_t)hec_tune_params().ks_amounts, sink);
+    }
+    for (size_t u = 0; u < S && s == HEC_OK; u++)
+        if (first[u]) s = HEC_ELAYOUT, hec_set_error("masked sum without a term");
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
+// Pooling mode 4 on image shards with two levels or more (Section 4.2): the
+// 2x2 window sums, the horizontal and the vertical masked reductions of all
+// shards together, stage by stage, each rotation key read once per stage for
+// all shards; the same ciphertexts as mode 0.  Other layouts: false in *done.
+static hec_status downsample_multi(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                                   std::vector<hec_ct *> &out, Layout &nl, bool *done)
+{
+    *done = false;
+    if (L.channel || in.empty()) return HEC_OK;
+    const uint32_t lvl = in[0]->level;
+    for (auto *ct : in)
+        if (ct->level != lvl) return HEC_OK;
+    if (lvl < 2) return HEC_OK;  // the fused one-level reduction stays per shard
+    const uint32_t mp = L.mp;
+    uint32_t Ho, Wo;
+    double val;
+    if (select) {
+        Ho = (L.H + 1) / 2; Wo = (L.W + 1) / 2; val = 1.0;
+    } else {
+        if (L.H % 2 || L.W % 2) HEC_FAIL(HEC_ELAYOUT, "average pooling needs even H and W");
+        Ho = L.H / 2; Wo = L.W / 2; val = 0.25;
+    }
+    const size_t S = in.size();
+    std::vector<hec_ct *> D(S, nullptr);
+    for (size_t u = 0; u < S; u++)
+        if (!(D[u] = ct_clone(c, in[u]))) { free_all(D); HEC_FAIL(HEC_ENOMEM, "ciphertext allocation"); }
+    std::vector<const hec_ct *> ins(in.begin(), in.end());
+    hec_status s = HEC_OK;
+    if (!select) {
+        // D = M + M<<1 + M<<mp + M<<(mp+1)
+        const std::vector<int32_t> win = {1, (int32_t)mp, (int32_t)mp + 1};
+        for (size_t u0 = 0; u0 < S && s == HEC_OK; u0 += HEC_MULTI_MAX_INPUTS) {
+            const size_t G = std::min((size_t)HEC_MULTI_MAX_INPUTS, S - u0);
+            std::vector<const hec_ct *> grp(ins.begin() + u0, ins.begin() + u0 + G);
+            std::vector<uint64_t> want(win.size(), G == 64 ? ~0ull : ((1ull << G) - 1));
+            s = ct_rotate_multi(c, grp, win, want, (size_t)hec_tune_params().ks_amounts,
+                                [&](size_t, size_t na, const std::vector<hec_ct *> &rots) -> hec_status {
+                                    for (size_t t = 0; t < na; t++)
+                                        for (size_t u = 0; u < G; u++)
+                                            HEC_CHECK(ct_add_inplace(c, D[u0 + u], rots[t * G + u]));
+                                    return HEC_OK;
+                                });
+        }
+    }
+    std::vector<int32_t> hs, vs;
+    std::vector<std::pair<uint32_t, uint32_t>> ij, jj;
+    for (uint32_t i = 0; i < Wo; i++) {
+        hs.push_back((int32_t)i);
+        ij.push_back({i, 0});
+    }
+    for (uint32_t j = 0; j < Ho; j++) {
+        vs.push_back((int32_t)(3 * j * mp / 2));
+        jj.push_back({0, j});
+    }
+    std::vector<hec_pt *> mh, mv;
+    std::vector<hec_ct *> M1, M2;
+    if (s == HEC_OK) s = get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], mh);
+    if (s == HEC_OK) s = masked_sums_multi(c, std::vector<const hec_ct *>(D.begin(), D.end()), hs, mh, M1);
+    free_all(D);
+    for (size_t u = 0; u < M1.size() && s == HEC_OK; u++) s = ct_rescale(c, M1[u]);
+    const uint32_t l1 = lvl - 1;
+    if (s == HEC_OK) s = get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], mv);
+    if (s == HEC_OK) s = masked_sums_multi(c, std::vector<const hec_ct *>(M1.begin(), M1.end()), vs, mv, M2);
+    free_all(M1);
+    for (size_t u = 0; u < M2.size() && s == HEC_OK; u++) s = ct_rescale(c, M2[u]);
+    if (s != HEC_OK) {
+        free_all(M2);
         return s;
     }
-    Layout nl;
-    HEC_CHECK(downsample(c, in, L, select, mode, ds, nl));
+    out = M2;
+    nl = Layout();
+    nl.N = L.N; nl.C = L.C; nl.H = Ho; nl.W = Wo; nl.mp = mp / 2;
+    for (auto &m : L.maps) {
+        std::vector<int32_t> nm(4 * L.nb(), -1);
+        for (uint32_t b = 0; b < L.nb(); b++) nm[4 * b] = m[b];
+        nl.maps.push_back(nm);
+    }
+    *done = true;
+    return HEC_OK;
+}
+
+static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                                       int mode, std::vector<hec_ct *> &out, Layout &ol);
+
+// Consolidation of downsampled image shards (layout nl) into groups of four
+// and duplication when one or two were downsampled (Section 4.2); ds consumed.
+static hec_status merge_downsampled(hec_ctx *c, std::vector<hec_ct *> &ds, const Layout &nl,
+                                    std::vector<hec_ct *> &out, Layout &ol)
+{
     const size_t t = ds.size();
     out.clear();
     if (t == 1) {
         hec_ct *o = nullptr;
-        hec_status s = duplicate(c, ds[0], nl, 4, &o);
+        Layout dl = nl;
+        hec_status s = duplicate(c, ds[0], dl, 4, &o);
         free_all(ds);
         HEC_CHECK(s);
         out.push_back(o);
-        ol = nl;
+        ol = dl;
         return HEC_OK;
     }
     const int32_t Bn = (int32_t)nl.B();
@@ -1139,7 +1281,7 @@ static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &
     cl.maps.clear();
     for (size_t s0 = 0; s0 < t; s0 += 4) {
         const size_t g = std::min((size_t)4, t - s0);  // short last group when t % 4 != 0
-        hec_ct *acc = ct_clone(ds[s0]);
+        hec_ct *acc = ct_clone(c, ds[s0]);
         for (size_t e = 1; e < g; e++) {
             hec_ct *r = nullptr;
             HEC_CHECK(ckks_rotate(c, ds[s0 + e], -(int32_t)e * Bn, &r));
@@ -1160,6 +1302,75 @@ static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &
     }
     ol = cl;
     return HEC_OK;
+}
+
+// Downsampling (and consolidation) of several images of one layout: in mode
+// 4 the stages of image-sharded layouts run over the shards of all images
+// together (one key read per stage for all of them), then every image is
+// consolidated on its own; otherwise image by image.  Same ciphertexts as one
+// downsample_and_merge per image.
+static hec_status downsample_and_merge_multi(hec_ctx *c, const std::vector<std::vector<hec_ct *>> &ins,
+                                             const Layout &L, bool select, int mode,
+                                             std::vector<std::vector<hec_ct *>> &outs, Layout &ol)
+{
+    outs.assign(ins.size(), {});
+    if (L.channel || mode != 4 || ins.size() == 1) {
+        for (size_t r = 0; r < ins.size(); r++) {
+            hec_status s = downsample_and_merge(c, ins[r], L, select, mode, outs[r], ol);
+            if (s != HEC_OK) {
+                for (auto &v : outs) free_all(v);
+                return s;
+            }
+        }
+        return HEC_OK;
+    }
+    const size_t t = ins[0].size();
+    std::vector<hec_ct *> all;
+    Layout Lk = L;
+    Lk.maps.clear();
+    for (auto &v : ins) {
+        if (v.size() != t) HEC_FAIL(HEC_ELAYOUT, "images of one batch differ in shard count");
+        all.insert(all.end(), v.begin(), v.end());
+        Lk.maps.insert(Lk.maps.end(), L.maps.begin(), L.maps.end());
+    }
+    std::vector<hec_ct *> ds;
+    Layout nlk;
+    bool done = false;
+    HEC_CHECK(downsample_multi(c, all, Lk, select, ds, nlk, &done));
+    if (!done) {
+        for (size_t r = 0; r < ins.size(); r++) HEC_CHECK(downsample_and_merge(c, ins[r], L, select, 0, outs[r], ol));
+        return HEC_OK;
+    }
+    Layout nl = nlk;
+    nl.maps.assign(nlk.maps.begin(), nlk.maps.begin() + t);
+    hec_status s = HEC_OK;
+    for (size_t r = 0; r < ins.size(); r++) {
+        std::vector<hec_ct *> mine(ds.begin() + r * t, ds.begin() + (r + 1) * t);
+        for (size_t i = 0; i < t; i++) ds[r * t + i] = nullptr;
+        if (s == HEC_OK) s = merge_downsampled(c, mine, nl, outs[r], ol);
+        else free_all(mine);
+    }
+    if (s != HEC_OK)
+        for (auto &v : outs) free_all(v);
+    return s;
+}
+
+static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
+                                       int mode, std::vector<hec_ct *> &out, Layout &ol)
+{
+    std::vector<hec_ct *> ds;
+    if (L.channel) {
+        HEC_CHECK(downsample_channel(c, in, L, select, mode == 4 ? 0 : mode, ds));
+        const uint32_t H2 = select ? (L.H + 1) / 2 : L.H / 2, W2 = select ? (L.W + 1) / 2 : L.W / 2;
+        hec_status s = merge_channel(c, ds, L, H2, W2, out, ol);
+        free_all(ds);
+        return s;
+    }
+    Layout nl;
+    bool done = false;
+    if (mode == 4) HEC_CHECK(downsample_multi(c, in, L, select, ds, nl, &done));
+    if (!done) HEC_CHECK(downsample(c, in, L, select, mode == 4 ? 0 : mode, ds, nl));
+    return merge_downsampled(c, ds, nl, out, ol);
 }
 
 // rotation steps of a pooling step (for key generation)
@@ -1478,7 +1689,7 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
 
 extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
-    if (!p || mode < 0 || mode > 3) HEC_FAIL(HEC_EINVAL, "bad mode");
+    if (!p || mode < 0 || mode > 4) HEC_FAIL(HEC_EINVAL, "bad mode");
     if (p->q_only && mode >= 2) HEC_FAIL(HEC_EINVAL, "plan without special-prime limbs runs in modes 0 and 1 only");
     if (p->basis && mode == 3) HEC_FAIL(HEC_EINVAL, "basis-mask plan runs in modes 0, 1 and 2");
     if (mode == 3) {
@@ -1557,6 +1768,66 @@ static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots,
     return HEC_OK;
 }
 
+// Plan mode 4: the products of mode 0 with the rotations of all input shards
+// taken together amount by amount (ct_rotate_multi: each rotation key read
+// once for the shards of a group of up to 64 instead of once per shard), the
+// zero rotations straight from the inputs.  Every rotation and every sum is
+// the one mode 0 computes, so the ciphertexts are mode 0's bit for bit.
+static hec_status conv_key_stationary(hec_ctx *c, const std::vector<const hec_ct *> &ins,
+                                      const std::vector<std::vector<hec_conv_plan::Item>> &items,
+                                      std::vector<hec_ct *> &acc, std::vector<char> &first, const BasisArg *bt)
+{
+    typedef hec_conv_plan::Item Item;
+    std::vector<hec_ct *> zr;
+    std::vector<Item> zi;
+    for (size_t u = 0; u < ins.size(); u++)
+        for (const Item &it : items[u])
+            if (c->galois(it.amount) == 1) {
+                zr.push_back(const_cast<hec_ct *>(ins[u]));
+                zi.push_back(it);
+            }
+    if (!zr.empty()) HEC_CHECK(mac_rotations(c, zr, zi, 0, acc, first, bt));
+    for (size_t u0 = 0; u0 < ins.size(); u0 += HEC_MULTI_MAX_INPUTS) {
+        const size_t S = std::min((size_t)HEC_MULTI_MAX_INPUTS, ins.size() - u0);
+        std::vector<const hec_ct *> grp(ins.begin() + u0, ins.begin() + u0 + S);
+        // amounts in first-use order; per (amount, shard) the items that rotate by it
+        std::vector<int32_t> amounts;
+        std::vector<uint64_t> want;
+        std::map<int32_t, size_t> idx;
+        std::vector<std::vector<std::vector<const Item *>>> by;  // [amount][shard]
+        for (size_t u = 0; u < S; u++)
+            for (const Item &it : items[u0 + u]) {
+                if (c->galois(it.amount) == 1) continue;
+                auto f = idx.find(it.amount);
+                size_t a;
+                if (f == idx.end()) {
+                    a = amounts.size();
+                    idx[it.amount] = a;
+                    amounts.push_back(it.amount);
+                    want.push_back(0);
+                    by.emplace_back(S);
+                } else {
+                    a = f->second;
+                }
+                want[a] |= 1ull << u;
+                by[a][u].push_back(&it);
+            }
+        auto sink = [&](size_t a0, size_t na, const std::vector<hec_ct *> &rots) -> hec_status {
+            std::vector<hec_ct *> rs;
+            std::vector<Item> its;
+            for (size_t t = 0; t < na; t++)
+                for (size_t u = 0; u < S; u++)
+                    for (const Item *it : by[a0 + t][u]) {
+                        rs.push_back(rots[t * S + u]);
+                        its.push_back(*it);
+                    }
+            return rs.empty() ? HEC_OK : mac_rotations(c, rs, its, 0, acc, first, bt);
+        };
+        HEC_CHECK(ct_rotate_multi(c, grp, amounts, want, (size_t)hec_tune_params().ks_amounts, sink));
+    }
+    return HEC_OK;
+}
+
 #define ROT_CHUNK 32
 extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, const hec_image *in, hec_image **out)
 {
@@ -1595,6 +1866,8 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         free_all(acc);
         s = bsgs_eval(c, ins, p->bsgs, p->gv, nout, acc);
         std::fill(first.begin(), first.end(), 0);
+    } else if (p->mode == 4) {
+        s = conv_key_stationary(c, ins, p->items, acc, first, btp);
     }
     for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode < 2; u++) {
         const auto &its = p->items[u];
@@ -1623,11 +1896,123 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         im->lay = p->out;
         im->shards = acc;
     } else {
-        s = downsample_and_merge(c, acc, p->out, true, p->mode >= 2 ? p->mode : 0, im->shards, im->lay);
+        s = downsample_and_merge(c, acc, p->out, true, p->mode == 1 ? 0 : p->mode, im->shards, im->lay);
         free_all(acc);
         if (s != HEC_OK) { hec_image_free(im); return s; }
     }
     *out = im;
+    return HEC_OK;
+}
+
+// Several images of a plan's layout and level in one evaluation (a server's
+// batch of requests): in mode 4 the rotations of all shards of all images go
+// through the key switch together amount by amount (each key read once per
+// group of up to 64 shards of the whole batch) and the stride-2 downsampling
+// stages likewise; other modes run image by image.  Same ciphertexts as one
+// he_conv2d_plan_run per image.
+hec_status conv_plan_run_multi(hec_ctx *c, const hec_conv_plan *p, const std::vector<const hec_image *> &ins,
+                               std::vector<hec_image *> &outs)
+{
+    outs.assign(ins.size(), nullptr);
+    auto fail = [&](hec_status s) {
+        for (auto *&im : outs) {
+            hec_image_free(im);
+            im = nullptr;
+        }
+        return s;
+    };
+    if (p->mode != 4 || ins.size() == 1) {
+        for (size_t r = 0; r < ins.size(); r++) {
+            hec_status s = he_conv2d_plan_run(c, p, ins[r], &outs[r]);
+            if (s != HEC_OK) return fail(s);
+        }
+        return HEC_OK;
+    }
+    for (auto *im : ins) {
+        if (!same_layout(p->in, im->lay)) HEC_FAIL(HEC_ELAYOUT, "image layout differs from the plan's");
+        for (auto *sh : im->shards)
+            if (sh->level != p->level) HEC_FAIL(HEC_ELEVEL, "image level differs from the plan's");
+    }
+    for (int32_t st : p->steps)
+        if (!have_rotkey(c, st)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", st);
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    const size_t nout = p->out.shards(), K = ins.size();
+    std::vector<const hec_ct *> all;
+    std::vector<std::vector<hec_conv_plan::Item>> items;
+    for (size_t r = 0; r < K; r++)
+        for (size_t u = 0; u < ins[r]->shards.size(); u++) {
+            all.push_back(ins[r]->shards[u]);
+            items.push_back(p->items[u]);
+            for (auto &it : items.back())
+                for (auto &pp : it.pts) pp.first += (uint32_t)(r * nout);
+        }
+    std::vector<hec_ct *> acc(K * nout, nullptr);
+    std::vector<char> first(K * nout, 1);
+    for (auto *&a : acc)
+        if (!(a = ct_new(c, p->level, 1.0))) { free_all(acc); HEC_FAIL(HEC_ENOMEM, "accumulator allocation"); }
+    BasisArg bt{};
+    if (p->basis) {
+        bt.E = p->E;
+        bt.nb = p->nbasis;
+        bt.nqp = p->level + 1 + c->k;
+    }
+    hec_status s = conv_key_stationary(c, all, items, acc, first, p->basis ? &bt : nullptr);
+    for (size_t v = 0; v < acc.size() && s == HEC_OK; v++) {
+        if (first[v]) s = HEC_ELAYOUT, hec_set_error("output shard %zu received no product", v % nout);
+        else s = ct_rescale(c, acc[v]);
+    }
+    if (s != HEC_OK) { free_all(acc); return s; }
+    std::vector<std::vector<hec_ct *>> per(K);
+    for (size_t r = 0; r < K; r++) per[r].assign(acc.begin() + r * nout, acc.begin() + (r + 1) * nout);
+    if (p->stride == 1) {
+        for (size_t r = 0; r < K; r++) {
+            outs[r] = new hec_image();
+            outs[r]->ctx = c;
+            outs[r]->lay = p->out;
+            outs[r]->shards = per[r];
+        }
+        return HEC_OK;
+    }
+    std::vector<std::vector<hec_ct *>> ds;
+    Layout ol;
+    s = downsample_and_merge_multi(c, per, p->out, true, 4, ds, ol);
+    free_all(acc);
+    if (s != HEC_OK) return s;
+    for (size_t r = 0; r < K; r++) {
+        outs[r] = new hec_image();
+        outs[r]->ctx = c;
+        outs[r]->lay = ol;
+        outs[r]->shards = ds[r];
+    }
+    return HEC_OK;
+}
+
+// 2x2 average pooling of several images of one layout (he_avgpool_ex per
+// image; mode 4 takes the stages of all images' shards together)
+hec_status avgpool_multi(hec_ctx *c, const std::vector<const hec_image *> &ins, int mode,
+                         std::vector<hec_image *> &outs)
+{
+    outs.assign(ins.size(), nullptr);
+    if (ins.empty()) return HEC_OK;
+    const Layout &L = ins[0]->lay;
+    std::set<int32_t> steps;
+    for (auto *im : ins) {
+        if (!same_layout(L, im->lay)) HEC_FAIL(HEC_ELAYOUT, "images of one pooling batch differ in layout");
+        if (im->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
+    }
+    pool_steps(L, false, ins[0]->shards[0]->level, steps);
+    for (int32_t st : steps)
+        if (!have_rotkey(c, st)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", st);
+    std::vector<std::vector<hec_ct *>> in(ins.size()), ds;
+    for (size_t r = 0; r < ins.size(); r++) in[r] = ins[r]->shards;
+    Layout ol;
+    HEC_CHECK(downsample_and_merge_multi(c, in, L, false, mode, ds, ol));
+    for (size_t r = 0; r < ins.size(); r++) {
+        outs[r] = new hec_image();
+        outs[r]->ctx = c;
+        outs[r]->lay = ol;
+        outs[r]->shards = ds[r];
+    }
     return HEC_OK;
 }
 
@@ -1664,8 +2049,9 @@ extern "C" hec_status he_avgpool_ex(hec_ctx *c, const hec_image *in, uint32_t wi
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!c || !in) HEC_FAIL(HEC_EINVAL, "NULL argument");
-    if (mode != 0 && mode != 2 && mode != 3)
-        HEC_FAIL(HEC_EINVAL, "pooling mode must be 0 (per rotation), 2 (lazy ModDown) or 3 (baby-step/giant-step)");
+    if (mode != 0 && mode != 2 && mode != 3 && mode != 4)
+        HEC_FAIL(HEC_EINVAL, "pooling mode must be 0 (per rotation), 2 (lazy ModDown), 3 (baby-step/giant-step) "
+                             "or 4 (key-stationary over the shards)");
     if (window != 2) HEC_FAIL(HEC_EINVAL, "only 2x2 pooling is supported");
     if (in->shards.empty()) HEC_FAIL(HEC_ELAYOUT, "empty image");
     HEC_TRY_HIP(hipSetDevice(c->dev));

@@ -26,6 +26,10 @@ EXPORTS = [
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
     "he_conv2d_plan_create_ex", "hec_gauss_table",
+    "hec_batch_begin", "hec_batch_add", "hec_batch_launch", "hec_batch_output", "hec_batch_size", "hec_batch_free",
+    "hec_server_start", "hec_server_add_model", "hec_server_model_footprint", "hec_server_submit", "hec_server_poll",
+    "hec_server_stats", "hec_server_stop",
+    "hec_tune_set", "hec_tune_get", "hec_tune_describe", "hec_tune_save", "hec_tune_load", "hec_autotune_conv",
 ]
 
 
@@ -33,6 +37,17 @@ class HecError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))
         self.status = status
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("mem_budget", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("batched_requests", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint64),
+                ("peak_mem", ctypes.c_size_t), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("req_per_s", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -125,6 +140,25 @@ def lib():
             "hec_prof_launches": (u64, [ctypes.c_char_p]),
             "he_image_channel_shard": (c, [vp, u32, i32p, i32p]),
             "hec_gauss_table": (c, [dbl, u64p, sz]),
+            "hec_batch_begin": (c, [vp, P(vp)]),
+            "hec_batch_add": (c, [vp, vp, vp, u32p]),
+            "hec_batch_launch": (c, [vp, c]),
+            "hec_batch_output": (vp, [vp, u32]),
+            "hec_batch_size": (u32, [vp]),
+            "hec_batch_free": (None, [vp]),
+            "hec_server_start": (c, [vp, P(ServerParams), P(vp)]),
+            "hec_server_add_model": (c, [vp, vp, c, vp, u32p]),
+            "hec_server_model_footprint": (sz, [vp, u32]),
+            "hec_server_submit": (c, [vp, u32, vp, P(ctypes.c_uint64)]),
+            "hec_server_poll": (c, [vp, ctypes.c_uint64, c, P(vp), dblp]),
+            "hec_server_stats": (c, [vp, P(ServerStats)]),
+            "hec_server_stop": (c, [vp]),
+            "hec_tune_set": (c, [ctypes.c_char_p, ctypes.c_int64]),
+            "hec_tune_get": (c, [ctypes.c_char_p, i64p]),
+            "hec_tune_describe": (c, [ctypes.c_char_p, sz]),
+            "hec_tune_save": (c, [ctypes.c_char_p]),
+            "hec_tune_load": (c, [ctypes.c_char_p]),
+            "hec_autotune_conv": (c, [vp, vp, vp, u32, ctypes.c_char_p, sz]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -139,6 +173,30 @@ def gauss_table(sigma):
     T = np.zeros(19, dtype=np.uint64)
     check(lib().hec_gauss_table(float(sigma), _p(T, u64p), len(T)))
     return T
+
+
+def tune_set(name, value):
+    check(lib().hec_tune_set(name.encode(), int(value)))
+
+
+def tune_get(name):
+    v = ctypes.c_int64()
+    check(lib().hec_tune_get(name.encode(), ctypes.byref(v)))
+    return v.value
+
+
+def tune_describe():
+    buf = ctypes.create_string_buffer(512)
+    check(lib().hec_tune_describe(buf, len(buf)))
+    return buf.value.decode()
+
+
+def tune_save(path):
+    check(lib().hec_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    check(lib().hec_tune_load(os.fsencode(path)))
 
 
 def check(status):
@@ -306,6 +364,97 @@ class ConvPlan(_Handle):
         out = vp()
         check(lib().he_conv2d_plan_run(self.ctx.h, self.h, img.h, ctypes.byref(out)))
         return Image(self.ctx, out.value)
+
+
+HEC_BATCH_EAGER, HEC_BATCH_GRAPH = 0, 1
+
+
+class Batch(_Handle):
+    """(plan, image) items run as one launch: eagerly, or recorded once into a
+    HIP graph and replayed (graph=True).  Keeps its items' plans and images."""
+    _free_fn = "hec_batch_free"
+
+    def __init__(self, ctx, handle):
+        super().__init__(ctx, handle)
+        self._keep = []
+
+    def add(self, plan, img):
+        i = ctypes.c_uint32()
+        check(lib().hec_batch_add(self.h, plan.h, img.h, ctypes.byref(i)))
+        self._keep.append((plan, img))
+        return i.value
+
+    def launch(self, graph=False):
+        check(lib().hec_batch_launch(self.h, HEC_BATCH_GRAPH if graph else HEC_BATCH_EAGER))
+
+    def __len__(self):
+        return lib().hec_batch_size(self.h)
+
+    def output(self, i):
+        """Borrowed output image of item i from the last launch (valid while the batch lives
+        and, for eager launches, until the next eager launch)."""
+        h = lib().hec_batch_output(self.h, int(i))
+        if not h:
+            raise IndexError(i)
+        img = Image(self.ctx, h, owned=False)
+        img._batch = self
+        return img
+
+
+class Server:
+    """Request loop over a context (lanes, memory admission, continuous
+    batching); see hec_server_* in include/hecnn.h.  Keeps submitted images
+    alive until their results are polled; results it hands out are freed by
+    stop() (they live in the server's memory)."""
+
+    def __init__(self, ctx, lanes=2, max_batch=4, mem_budget=32 << 30):
+        self.ctx = ctx
+        prm = ServerParams(int(lanes), int(max_batch), int(mem_budget))
+        h = vp()
+        check(lib().hec_server_start(ctx.h, ctypes.byref(prm), ctypes.byref(h)))
+        self.h = h.value
+        self._keep, self._inputs, self._results = [], {}, []
+
+    def add_model(self, plan, like, pool_mode=-1):
+        m = ctypes.c_uint32()
+        check(lib().hec_server_add_model(self.h, plan.h, int(pool_mode), like.h, ctypes.byref(m)))
+        self._keep.append((plan, like))
+        return m.value
+
+    def footprint(self, model):
+        return lib().hec_server_model_footprint(self.h, int(model))
+
+    def submit(self, model, img):
+        rid = ctypes.c_uint64()
+        check(lib().hec_server_submit(self.h, int(model), img.h, ctypes.byref(rid)))
+        self._inputs[rid.value] = img
+        return rid.value
+
+    def poll(self, rid, wait=True):
+        """-> (Image, latency_ms) when done, None when not (wait=False); raises HecError if it failed."""
+        out, lat = vp(), ctypes.c_double()
+        st = lib().hec_server_poll(self.h, int(rid), int(bool(wait)), ctypes.byref(out), ctypes.byref(lat))
+        if st == HEC_EBUSY and not wait:
+            return None
+        self._inputs.pop(rid, None)
+        check(st)
+        img = Image(self.ctx, out.value)
+        self._results.append(img)
+        return img, lat.value
+
+    def stats(self):
+        st = ServerStats()
+        check(lib().hec_server_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def stop(self):
+        if self.h:
+            for img in self._results:
+                img.free()
+            self._results = []
+            h, self.h = self.h, None
+            check(lib().hec_server_stop(h))
+            self._inputs.clear()
 
 
 class Context:
@@ -569,6 +718,17 @@ class Context:
         out = np.zeros(n.value, dtype=np.int32)
         check(lib().he_linear_steps(self.h, img.h, _p(out, i32p), len(out), ctypes.byref(n)))
         return [int(x) for x in out]
+
+    def autotune_conv(self, plan, img, reps=3):
+        """Pick the launch parameters for plan.run(img) (bit-identical output); returns the report."""
+        buf = ctypes.create_string_buffer(4096)
+        check(lib().hec_autotune_conv(self.h, plan.h, img.h, int(reps), buf, len(buf)))
+        return buf.value.decode()
+
+    def batch(self):
+        out = vp()
+        check(lib().hec_batch_begin(self.h, ctypes.byref(out)))
+        return Batch(self, out.value)
 
     def sync(self):
         check(lib().hec_ctx_sync(self.h))

@@ -38,8 +38,9 @@ def check_ct_decrypt_vs_oracle(ctx, ct, o, oct_):
 def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1, basis=None, tol=1e-5):
     """Encrypt x on both sides, apply ops ('conv', w, stride) / ('pool',),
     compare every shard bit for bit after every op; return final decryption.
-    mode 2 runs the convolutions with lazy ModDown on both sides; basis = s
-    builds their weight plaintexts in basis-mask form on both sides."""
+    mode 2 runs the convolutions with lazy ModDown on both sides, mode 3 by
+    baby and giant steps; modes 1 and 4 compute mode 0's ciphertexts; basis =
+    s builds their weight plaintexts in basis-mask form on both sides."""
     C, H, W = x.shape
     img = ctx.image_encrypt(x, level, seed)
     lay = hl.natural_layout(prm.N, C, H, W)
@@ -60,7 +61,7 @@ def run_pipeline(ctx, prm, o, x, ops, level, seed, mode=0, pad=1, basis=None, to
             ref = hl.ref_conv2d(ref, w, pad, stride)
         else:
             ctx.gen_rotation_keys(ctx.avgpool_steps(img))
-            img = ctx.avgpool(img, mode=mode if mode >= 2 else 0)
+            img = ctx.avgpool(img, mode=0 if mode == 1 else mode)
             cts, lay = hl.avgpool2x2(be, cts, lay, lazy=(mode == 2), bsgs=(mode == 3))
             ref = hl.ref_avgpool2x2(ref)
         Cn, Hn, Wn, mp, t = img.info()

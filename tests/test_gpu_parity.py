@@ -166,6 +166,38 @@ def test_layers_bit_exact(small, shape, ops):
 
 @pytest.mark.parametrize("shape,ops", [
     ((4, 8, 8), [("conv", (4, 3), 1)]),                             # one shard, duplicated copies
+    ((16, 16, 16), [("conv", (8, 3), 1)]),                          # 8 input shards -> 4 outputs
+    ((4, 16, 16), [("conv", (16, 3), 1)]),                          # 2 shards -> 8 outputs
+    ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv, 4 shards -> 1
+    ((2, 32, 32), [("conv", (3, 3), 1)]),                           # channel shards
+    ((8, 16, 16), [("pool",), ("conv", (8, 3), 1)]),                # 4 shards pooled (permuted blocks), then conv
+    ((4, 16, 16), [("conv", (4, 3), 1), ("pool",)]),                # 2 shards pooled -> consolidate + dup x2
+    ((16, 16, 16), [("conv", (8, 3), 1), ("pool",)]),               # 8 shards -> 4 -> 1
+    ((1, 64, 64), [("pool",), ("conv", (2, 3), 1)]),                # channel shards: pooled per shard
+    ((4, 8, 8), [("pool",), ("pool",)]),                            # the second pool fused (one level)
+])
+def test_layers_key_stationary_bit_exact(small, shape, ops):
+    """Plan and pooling mode 4 (rotations of all input shards amount by
+    amount, each key read once for all shards) give the ciphertexts of mode
+    0: compared with the oracle's per-rotation form bit for bit."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(sum(shape) + 400)
+    x = rng.uniform(-1, 1, shape)
+    cin = shape[0]
+    real_ops = []
+    for op in ops:
+        if op[0] == "conv":
+            co, k = op[1]
+            real_ops.append(("conv", rng.normal(0, 0.1, (co, cin, k, k)), op[2]))
+            cin = co
+        else:
+            real_ops.append(op)
+    log("key-stationary layers", shape, [op[0] for op in ops])
+    run_pipeline(ctx, prm, o, x, real_ops, 6, seed=53, mode=4)
+
+
+@pytest.mark.parametrize("shape,ops", [
+    ((4, 8, 8), [("conv", (4, 3), 1)]),                             # one shard, duplicated copies
     ((4, 16, 16), [("conv", (16, 3), 1), ("pool",)]),               # 2 shards -> 8 outputs (two groups of 4)
     ((16, 16, 16), [("conv", (8, 3), 1)]),                          # 8 input shards -> 4 outputs
     ((4, 16, 16), [("conv", (8, 3), 2)]),                           # strided conv
@@ -247,10 +279,11 @@ def test_plan_mode_rejected(small):
     ctx, prm, o = small
     img = ctx.image_encrypt(np.zeros((1, 8, 8)), 3, 1)
     plan = ctx.conv2d_plan(img, np.ones((1, 1, 3, 3)))
-    with pytest.raises(hecnn.HecError) as e:
-        plan.set_mode(4)
-    assert e.value.status == hecnn.HEC_EINVAL
-    for bad in (1, 4):
+    for bad in (5, -1):
+        with pytest.raises(hecnn.HecError) as e:
+            plan.set_mode(bad)
+        assert e.value.status == hecnn.HEC_EINVAL
+    for bad in (1, 5):
         with pytest.raises(hecnn.HecError) as e:
             ctx.avgpool(img, mode=bad)
         assert e.value.status == hecnn.HEC_EINVAL
