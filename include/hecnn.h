@@ -131,6 +131,21 @@ hec_status ckks_rotate(hec_ctx *ctx, const hec_ct *ct, int32_t step, hec_ct **ou
 /* n rotations of one ciphertext sharing a single ModUp (the "rotations
  * computed once and cached" of Section 4.1).  outs[0..n) receive new handles. */
 hec_status ckks_rotate_hoisted(hec_ctx *ctx, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * rotation of ckks_rotate written into the caller's ciphertext `out` (created
+ * beforehand at the input's level, e.g. by ckks_ct_import; not the input
+ * itself), bit-identical to ckks_rotate.  Allocates, frees and synchronizes
+ * nothing: its temporaries (c1 in coefficient form, the ModUp digits, the
+ * key-switch product and the ModDown conversion: n * (3 (level+1) +
+ * (beta + 2) (level+1+k)) words, beta = ceil((level+1)/alpha)) live in one
+ * static device array of 128 MiB per GPU, held until the process ends (at
+ * 2N = 2^16 with 8 special primes and 3 digits: 104 MiB at level 20, 120 MiB
+ * at level 24); a rotation that needs more fails with HEC_EINVAL.  All calls on one GPU share that array: calls that overlap
+ * on one GPU (several streams or contexts of the device, several threads)
+ * race and must be ordered by the caller.  Errors: HEC_ELEVEL (out at another
+ * level), HEC_ENOKEY, HEC_EINVAL; out keeps its contents on error. */
+hec_status ckks_rotate_noalloc(hec_ctx *ctx, const hec_ct *in, int32_t step, hec_ct *out);
 /* Divide by the last prime and drop it (level - 1, scale / q_level). */
 hec_status ckks_rescale(hec_ctx *ctx, hec_ct *inout);
 /* ct * pt (levels must match; scales multiply). */

@@ -52,6 +52,9 @@ struct DevTables {
     const u64 *itw, *itw_sh;  // psi^-brv(k), [prime][n]
 };
 
+// scratch array of the allocation-free rotation, per device
+#define HEC_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
 #define HEC_KS_BATCH 16
 struct KsBatch {
     const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form

@@ -73,6 +73,31 @@ void DevPool::release_all()
     bytes_live = bytes_cached = 0;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free rotation (ckks_rotate_noalloc)
+// ---------------------------------------------------------------------------
+// One array per device: every GPU that loads the library holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: its device address is resolved once per device (with that device
+// current) when a context is created there and kept in g_scratch_ptr.
+#define HEC_MAX_DEVICES 64
+static __device__ __align__(256) u64 scratch[HEC_NOALLOC_SCRATCH_BYTES / 8];
+static u64 *g_scratch_ptr[HEC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static hec_status scratch_init(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= HEC_MAX_DEVICES) HEC_FAIL(HEC_EDEVICE, "device %d beyond %d", dev, HEC_MAX_DEVICES);
+    if (g_scratch_ptr[dev]) return HEC_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        HEC_FAIL(HEC_EDEVICE, "scratch of the allocation-free rotation: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (u64 *)ptr;
+    return HEC_OK;
+}
+
 uint32_t hec_ctx::galois(int64_t step) const
 {
     int64_t r = step % (int64_t)N;
@@ -320,6 +345,7 @@ extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_
     HEC_TRY_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) HEC_FAIL(HEC_EDEVICE, "no HIP device %d", device);
     HEC_TRY_HIP(hipSetDevice(device));
+    HEC_CHECK(scratch_init(device));
 
     std::unique_ptr<hec_ctx> c(new hec_ctx());
     c->prm = *p;
@@ -1255,6 +1281,72 @@ extern "C" hec_status ckks_rotate(hec_ctx *c, const hec_ct *ct, int32_t step, he
     if (!out) HEC_FAIL(HEC_EINVAL, "out is NULL");
     *out = nullptr;
     return ckks_rotate_hoisted(c, ct, &step, 1, out);
+}
+
+// The rotation of ckks_rotate with every temporary in the device's scratch
+// array: c1 to coefficients, ModUp of its digits, key-switch inner product,
+// ModDown and the sigma_g(c0) term, the same launches (hence the same bits)
+// as ckks_rotate; nothing allocated, freed or synchronized.
+extern "C" hec_status ckks_rotate_noalloc(hec_ctx *c, const hec_ct *in, int32_t step, hec_ct *out)
+{
+    if (!c || !in || !out) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (in->ctx != c || out->ctx != c) HEC_FAIL(HEC_EINVAL, "ciphertext of another context");
+    if (out == in || out->d == in->d) HEC_FAIL(HEC_EINVAL, "out must not be the input");
+    if (out->level != in->level) HEC_FAIL(HEC_ELEVEL, "out is at level %u, the input at %u", out->level, in->level);
+    const size_t n = c->n;
+    const uint32_t lvl = in->level, nq = lvl + 1, k = c->k, nqp = nq + k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    const uint32_t g = c->galois(step);
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    if (g == 1) {
+        HEC_TRY_HIP(hipMemcpyAsync(out->d, in->d, 2 * (size_t)nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+        out->scale = in->scale;
+        return HEC_OK;
+    }
+    auto key = c->rotkeys.find(g);
+    if (key == c->rotkeys.end()) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", step);
+    // c1 in coefficient form, the ModUp digits, the key-switch product and the
+    // P -> Q conversion, one after the other in the scratch array
+    const size_t words = n * ((size_t)nq + (size_t)beta * nqp + 2ull * nqp + 2ull * nq);
+    if (words * 8 > HEC_NOALLOC_SCRATCH_BYTES)
+        HEC_FAIL(HEC_EINVAL, "rotation at level %u needs %zu MiB of scratch, the limit is %llu MiB", lvl,
+                 (words * 8) >> 20, (unsigned long long)(HEC_NOALLOC_SCRATCH_BYTES >> 20));
+    u64 *const sp = g_scratch_ptr[c->dev];
+    if (!sp) HEC_FAIL(HEC_EDEVICE, "scratch not resolved on device %d", c->dev);
+    u64 *cc = sp, *D = cc + (size_t)nq * n, *e = D + (size_t)beta * nqp * n, *y = e + 2ull * nqp * n;
+    if (!hec_ntt_inv_from(c->T, cc, nq * n, in->d + (size_t)nq * n, 0, 1, c->idmap(), (int)nq, c->st)) {
+        HEC_TRY_HIP(hipMemcpyAsync(cc, in->d + (size_t)nq * n, (size_t)nq * n * 8, hipMemcpyDeviceToDevice, c->st));
+        hec_ntt_inv(c->T, cc, nq * n, 1, c->idmap(), nq, c->st);
+    }
+    uint32_t nout_max = 0, nin_max = 0;
+    for (uint32_t j = 0; j < beta; j++) {
+        nout_max = std::max(nout_max, c->h_modup[(size_t)lvl * c->dnum + j].nout);
+        nin_max = std::max(nin_max, c->h_modup[(size_t)lvl * c->dnum + j].nin);
+    }
+    hec_bconv(c->T, c->d_modup + (size_t)lvl * c->dnum, 1, (int)beta, (int)nout_max, cc, D, nq * n, (size_t)nqp * n,
+              (int)beta, 1, c->st, (int)nin_max);
+    hec_ntt_fwd(c->T, D, (size_t)nqp * n, (int)beta, c->qpmap(lvl), (int)nqp, c->st);
+    KsBatch kb{};
+    kb.key[0] = key->second;
+    kb.out[0] = e;
+    kb.g[0] = g;
+    hec_ks_inner(c->T, kb, 1, D, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
+    c->ks_count += 1;
+    hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2, c->qpmap(lvl) + nq, k, c->st);
+    hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2, 0, c->st, (int)c->k);
+    CombineBatch cb{};
+    cb.out[0] = out->d;
+    cb.e[0] = e;
+    cb.y[0] = y;
+    cb.c0[0] = in->d;
+    cb.g[0] = g;
+    if (!hec_ntt_fwd_moddown(c->T, y, 1, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), c->st)) {
+        hec_ntt_fwd(c->T, y, (size_t)nq * n, 2, c->qpmap(lvl), nq, c->st);
+        hec_moddown_combine(c->T, cb, 1, in->d, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+    }
+    HEC_TRY_HIP(hipGetLastError());
+    out->scale = in->scale;
+    return HEC_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,7 @@ EXPORTS = [
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
-    "he_conv2d_plan_create_ex", "hec_gauss_table",
+    "he_conv2d_plan_create_ex", "hec_gauss_table", "ckks_rotate_noalloc",
     "hec_batch_begin", "hec_batch_add", "hec_batch_launch", "hec_batch_output", "hec_batch_size", "hec_batch_free",
     "hec_server_start", "hec_server_add_model", "hec_server_model_footprint", "hec_server_submit", "hec_server_poll",
     "hec_server_stats", "hec_server_stop",
@@ -92,6 +92,7 @@ def lib():
             "ckks_decrypt": (c, [vp, vp, dblp, sz]),
             "ckks_rotate": (c, [vp, vp, ctypes.c_int32, P(vp)]),
             "ckks_rotate_hoisted": (c, [vp, vp, i32p, sz, P(vp)]),
+            "ckks_rotate_noalloc": (c, [vp, vp, ctypes.c_int32, vp]),
             "ckks_rescale": (c, [vp, vp]),
             "ckks_mul_pt": (c, [vp, vp, vp, P(vp)]),
             "ckks_add": (c, [vp, vp, vp, P(vp)]),
@@ -560,6 +561,12 @@ class Context:
         out = vp()
         check(lib().ckks_rotate(self.h, ct.h, int(step), ctypes.byref(out)))
         return Ciphertext(self, out.value)
+
+    def rotate_noalloc(self, ct, step, out):
+        """ct rotated by step into the existing ciphertext out (same level):
+        the allocation-free entry point; returns out."""
+        check(lib().ckks_rotate_noalloc(self.h, ct.h, int(step), out.h))
+        return out
 
     def rotate_hoisted(self, ct, steps):
         st = _arr(steps, np.int32)
