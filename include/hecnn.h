@@ -389,6 +389,9 @@ void hec_batch_free(hec_batch *batch);
  * its residues (every value gives the same ciphertexts bit for bit):
  *   ntt16_radix  16 | 2        2^16 transforms as two radix-16 register passes,
  *                              or as radix-2 stages over LDS tiles
+ *   ntt_fp64     1 | 0         in the radix-16 form, the limbs of primes below
+ *                              2^50 with exact double butterflies (every value
+ *                              an integer below 2^52), or 64-bit integers
  *   ntt_tile     2048 | 4096 | 8192   words per LDS tile of the radix-2 form
  *   ntt_group    0 | 64 | 256 | 1024  at most this many limbs per transform
  *                              launch (0: every limb of a batch in one launch)

@@ -16,6 +16,9 @@ struct PrimeC {
     u64 r2;        // 2^128 mod q (into Montgomery form)
     u64 ninv;      // n^-1 mod q
     u64 ninv_sh;   // Shoup companion of ninv
+    double qd, ninv_q;  // q and n^-1 / q as doubles (primes below 2^50: the exact double butterflies)
+    u32 fp;             // q < 2^50: the 2^16 transforms may run in doubles
+    u32 pad_;
 };
 
 // Fast base conversion from `nin` limbs to `nout` limbs (ModUp of one digit,
@@ -50,6 +53,8 @@ struct DevTables {
     const PrimeC *pc;
     const u64 *tw, *tw_sh;    // psi^brv(k), [prime][n]
     const u64 *itw, *itw_sh;  // psi^-brv(k), [prime][n]
+    const double2 *twf, *itwf;  // (w, w / q) as doubles for the primes below 2^50, [prime][n]
+    u32 fp_on;                  // the 2^16 transforms of those primes in doubles (a launch parameter)
 };
 
 // scratch array of the allocation-free rotation, per device
@@ -133,6 +138,7 @@ struct TuneParams {
     int ntt_group = 0;     // at most this many limbs per transform launch (0: all in one)
     int ks_rot_batch = 16; // rotations per key-switch launch of a hoisted set (1..HEC_KS_BATCH)
     int ks_amounts = 4;    // amounts per key-stationary launch over many inputs (1..HEC_KS_BATCH)
+    int ntt_fp64 = 1;      // 2^16 transforms of primes below 2^50 with exact double butterflies (0: integers)
 };
 TuneParams &hec_tune_params();
 
@@ -182,6 +188,17 @@ bool hec_ks_inner_multi(const DevTables &T, const KsMulti &kb, int nrot, const u
 // ba (nullable): the plaintexts in basis-mask form.
 bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, int beta, int nq, int nqp,
                 const u32 *pmap, const u64 *pm, int NLK, int first, hipStream_t st, const BasisArg *ba = nullptr);
+
+// The same products for S inputs at once (input u: D[t] + u ds, ct[t] + u cs, output E[0] + u es), each
+// input with one output and the terms' keys and plaintexts (pt[t][0]) shared: the workgroups of the S
+// inputs of one (limb, chunk) are neighbours, so a key or plaintext limb is read from HBM once for all of
+// them.  Same residues as one hec_ks_mac per input.
+struct ShardArg {
+    u32 S;
+    size_t ds, cs, es;
+};
+bool hec_ks_mac_shards(const DevTables &T, const KsMacBatch &b, int nterms, int beta, int nq, int nqp,
+                       const u32 *pmap, const u64 *pm, int NLK, int first, const ShardArg &sh, hipStream_t st);
 
 // the products of b (nterms <= HEC_MAC_TERMS, nout <= HEC_MAC_OUTS) summed in 128 bits and reduced once
 // (the same residues as multiply-accumulating them one at a time); bit v of `first`: output v written

@@ -40,11 +40,13 @@ void *DevPool::get(size_t bytes)
         free_.erase(it);
         bytes_cached -= bytes;
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
-        // give the cached blocks back (once the queued work that may still use them is done) and retry once
+        // give the cached blocks back (once the queued work that may still use them is done) and retry once,
+        // those of the pool this one spills into as well
         (void)hipDeviceSynchronize();
         for (auto &kv : free_) hipFree(kv.second);
         free_.clear();
         bytes_cached = 0;
+        if (spill && spill != this) spill->trim();
         if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
     }
     live_[p] = bytes;
@@ -62,6 +64,15 @@ bool DevPool::put(void *p)
     bytes_cached += it->second;
     live_.erase(it);
     return true;
+}
+void DevPool::trim()
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : free_) hipFree(kv.second);
+    free_.clear();
+    bytes_cached = 0;
 }
 void DevPool::release_all()
 {
@@ -129,6 +140,7 @@ static hec_status build_tables(hec_ctx *c)
     // primes
     std::vector<PrimeC> pc(NLK);
     std::vector<u64> tw((size_t)NLK * n), twsh((size_t)NLK * n), itw((size_t)NLK * n), itwsh((size_t)NLK * n);
+    std::vector<double2> twf((size_t)NLK * n), itwf((size_t)NLK * n);
     for (uint32_t i = 0; i < NLK; i++) {
         u64 q = c->mod[i];
         // -q^-1 mod 2^64 by Newton iteration
@@ -140,6 +152,9 @@ static hec_status build_tables(hec_ctx *c)
         pc[i].r2 = mulmod(r1, r1, q);
         pc[i].ninv = invmod(n % q, q);
         pc[i].ninv_sh = shoup_of(pc[i].ninv, q);
+        pc[i].fp = q < (1ull << 50) ? 1u : 0u;
+        pc[i].qd = (double)q;
+        pc[i].ninv_q = (double)pc[i].ninv / (double)q;
         u64 psi = find_root_2n(q, n), ipsi = invmod(psi, q);
         std::vector<u64> pw(n), ipw(n);
         pw[0] = ipw[0] = 1;
@@ -153,6 +168,9 @@ static hec_status build_tables(hec_ctx *c)
             twsh[(size_t)i * n + t] = shoup_of(w, q);
             itw[(size_t)i * n + t] = iw;
             itwsh[(size_t)i * n + t] = shoup_of(iw, q);
+            // w and w / q (each rounded to nearest) for the double butterflies
+            twf[(size_t)i * n + t] = make_double2((double)w, (double)w / (double)q);
+            itwf[(size_t)i * n + t] = make_double2((double)iw, (double)iw / (double)q);
         }
     }
     c->d_pc = (PrimeC *)c->pool.get(sizeof(PrimeC) * NLK);
@@ -160,7 +178,12 @@ static hec_status build_tables(hec_ctx *c)
     c->d_twsh = c->alloc((size_t)NLK * n);
     c->d_itw = c->alloc((size_t)NLK * n);
     c->d_itwsh = c->alloc((size_t)NLK * n);
-    if (!c->d_pc || !c->d_tw || !c->d_twsh || !c->d_itw || !c->d_itwsh) HEC_FAIL(HEC_ENOMEM, "table allocation");
+    c->d_twf = (double2 *)c->alloc((size_t)NLK * n * 2);
+    c->d_itwf = (double2 *)c->alloc((size_t)NLK * n * 2);
+    if (!c->d_pc || !c->d_tw || !c->d_twsh || !c->d_itw || !c->d_itwsh || !c->d_twf || !c->d_itwf)
+        HEC_FAIL(HEC_ENOMEM, "table allocation");
+    HEC_CHECK(upload(c->d_twf, twf.data(), twf.size() * sizeof(double2), c->st));
+    HEC_CHECK(upload(c->d_itwf, itwf.data(), itwf.size() * sizeof(double2), c->st));
     HEC_CHECK(upload(c->d_pc, pc.data(), sizeof(PrimeC) * NLK, c->st));
     HEC_CHECK(upload(c->d_tw, tw.data(), tw.size() * 8, c->st));
     HEC_CHECK(upload(c->d_twsh, twsh.data(), twsh.size() * 8, c->st));
@@ -322,6 +345,9 @@ static hec_status build_tables(hec_ctx *c)
     c->T.tw_sh = c->d_twsh;
     c->T.itw = c->d_itw;
     c->T.itw_sh = c->d_itwsh;
+    c->T.twf = c->d_twf;
+    c->T.itwf = c->d_itwf;
+    c->T.fp_on = 1;
     HEC_TRY_HIP(hipStreamSynchronize(c->st));
     return HEC_OK;
 }
@@ -407,6 +433,7 @@ hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out)
     c->T = parent->T;
     c->d_pc = parent->d_pc;
     c->d_tw = parent->d_tw; c->d_twsh = parent->d_twsh; c->d_itw = parent->d_itw; c->d_itwsh = parent->d_itwsh;
+    c->d_twf = parent->d_twf; c->d_itwf = parent->d_itwf;
     c->d_maps = parent->d_maps;
     c->qp_off = parent->qp_off;
     c->d_modup = parent->d_modup; c->d_moddown = parent->d_moddown; c->d_lvl = parent->d_lvl;
@@ -419,6 +446,7 @@ hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out)
     c->rotkeys = parent->rotkeys;
     c->rlk = parent->rlk;
     c->lane = true;
+    c->pool.spill = &parent->pool;
     HEC_TRY_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
     c->d_flag = (int *)c->pool.get(256);
     if (!c->d_flag) {

@@ -48,8 +48,12 @@ struct DevPool {
     std::unordered_map<void *, size_t> live_;
     size_t bytes_live = 0, bytes_cached = 0, peak_live = 0;
     std::mutex mu_;
+    // another pool whose cached blocks go back to the device too when this
+    // one runs out (a batch's or a serving lane's pool spills into its context's)
+    DevPool *spill = nullptr;
     void *get(size_t bytes);
     bool put(void *p);  // false: not a block of this pool
+    void trim();        // cached blocks back to the device (after the device's queued work)
     void release_all();
     size_t live()
     {
@@ -83,6 +87,7 @@ struct hec_ctx {
     // device tables
     PrimeC *d_pc = nullptr;
     u64 *d_tw = nullptr, *d_twsh = nullptr, *d_itw = nullptr, *d_itwsh = nullptr;
+    double2 *d_twf = nullptr, *d_itwf = nullptr;
     u32 *d_maps = nullptr;           // identity map (NLK) followed by QP maps of every level
     std::vector<size_t> qp_off;      // offset of level l's QP map in d_maps
     BconvDesc *d_modup = nullptr;    // [level][digit]

@@ -314,6 +314,98 @@ DEV u64 reduce4(u64 x, u64 q)
     return x >= q ? x - q : x;
 }
 
+// The arithmetic of the 2^16 transforms, in one of two exact forms:
+//  * ArInt: 64-bit integers (any prime below 2^61), Shoup products by the
+//    twiddles, values kept lazily in [0, 4q);
+//  * ArFp: IEEE doubles, for primes below 2^50.  Every value is an integer
+//    below 4q < 2^52, so it and every sum below are exact doubles.  The
+//    product y w (y < 4q, w < q) is split exactly into ph + pl (ph = fl(y w),
+//    pl = fma(y, w, -ph)); the quotient estimate k = floor(fl(y fl(w / q)))
+//    differs from y w / q by less than 1 (both roundings below 2^-53
+//    relative, y w / q < 2^52), so r = fma(-k, q, ph) + pl = y w - k q is an
+//    exact integer in (-q, 2q) (|ph - k q| < 2q + 2^49 < 2^52 makes the fma
+//    exact) and one conditional add puts it in [0, 2q).  That is the same
+//    lazy range as the integer Shoup product, about half the instructions on
+//    the VALU (the double multiply-add issues at the integer rate).
+// Both keep the same ranges, so the canonical outputs -- and every bit that
+// leaves a transform -- are the same.  Between the two passes the working
+// values are stored in their own form (doubles as their bits).
+struct ArInt {
+    typedef u64 V;
+    u64 q, q2;
+    const u64 *w, *ws;
+    DEV V in(u64 r) const { return r; }
+    DEV V mid_in(u64 b) const { return b; }
+    DEV u64 mid_out(V x) const { return x; }
+    DEV void ct(V &x, V &y, u32 idx) const { ct_bfly(x, y, w[idx], ws[idx], q2, q); }
+    DEV void gs(V &x, V &y, u32 idx) const { gs_bfly(x, y, w[idx], ws[idx], q2, q); }
+    DEV u64 full(V x) const { return reduce4(x, q); }  // [0, 4q) -> [0, q)
+};
+struct ArFp {
+    typedef double V;
+    double q, q2;
+    const double2 *t;  // (w, fl(w / q))
+    DEV V in(u64 r) const { return (double)r; }
+    DEV V mid_in(u64 b) const { return __longlong_as_double((long long)b); }
+    DEV u64 mid_out(V x) const { return (u64)__double_as_longlong(x); }
+    DEV V mulmod(V y, double w, double wq) const
+    {
+        const double ph = y * w;
+        const double pl = fma(y, w, -ph);
+        const double k = floor(y * wq);
+        const double r = fma(-k, q, ph) + pl;
+        return r < 0.0 ? r + q : r;  // [0, 2q)
+    }
+    DEV void ct(V &x, V &y, u32 idx) const
+    {
+        const double2 tw = t[idx];
+        const V u = x >= q2 ? x - q2 : x;
+        const V v = mulmod(y, tw.x, tw.y);
+        x = u + v;
+        y = u - v + q2;
+    }
+    DEV void gs(V &x, V &y, u32 idx) const
+    {
+        const double2 tw = t[idx];
+        const V u = x, v = y;
+        const V s = u + v;
+        x = s >= q2 ? s - q2 : s;
+        y = mulmod(u - v + q2, tw.x, tw.y);
+    }
+    DEV u64 full(V x) const
+    {
+        x = x >= q2 ? x - q2 : x;
+        x = x >= q ? x - q : x;
+        return (u64)x;
+    }
+};
+DEV ArInt ar_int(const PrimeC &pc, const u64 *w, const u64 *ws, u32 pi)
+{
+    ArInt a;
+    a.q = pc.q;
+    a.q2 = 2 * pc.q;
+    a.w = w + ((size_t)pi << 16);
+    a.ws = ws + ((size_t)pi << 16);
+    return a;
+}
+DEV ArFp ar_fp(const PrimeC &pc, const double2 *t, u32 pi)
+{
+    ArFp a;
+    a.q = pc.qd;
+    a.q2 = 2.0 * pc.qd;
+    a.t = t + ((size_t)pi << 16);
+    return a;
+}
+DEV bool use_fp(const DevTables &T, const PrimeC &pc) { return T.fp_on && pc.fp && T.twf; }
+// the tables as a launch of the 2^16 transforms sees them: the double
+// butterflies on or off as the launch parameter says
+static DevTables tuned(const DevTables &T)
+{
+    DevTables t = T;
+    t.fp_on = hec_tune_params().ntt_fp64 ? 1u : 0u;
+    return t;
+}
+
 #define N16_PAD(c) ((c) + ((c) >> 4))  // padded LDS index inside a 256-point row (17 words per 16)
 DEV u64 mod64(u64 x, const PrimeC &pc);
 
@@ -337,8 +429,39 @@ DEV Ntt16Item ntt16_item(u32 npolys)
     return it;
 }
 
-// forward column pass: stages 0..7 over the 256 rows of 16 columns (RS: the
-// input is the centered dropped limb of a rescale, reduced mod this limb's prime)
+// forward column pass: stages 0..7 over the 256 rows of 16 columns (x holds
+// the 16 points l + 16 h of column col, in the working form of Ar)
+template <class Ar>
+DEV void ntt16_fwd_cols_body(const Ar &ar, typename Ar::V *x, u64 *a, u64 *lds, u32 col, u32 l)
+{
+    typedef typename Ar::V V;
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int half = 8 >> s;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) ar.ct(x[h], x[h + half], (1u << s) + (h >> (4 - s)));
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) lds[(l + 16 * h) * 16 + col] = ar.mid_out(x[h]);
+    __syncthreads();
+    const u32 hb = l;  // round B: rows 16*hb + i
+    V y[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) y[i] = ar.mid_in(lds[(16 * hb + i) * 16 + col]);
+#pragma unroll
+    for (int s = 4; s < 8; s++) {
+        const int half = 128 >> s;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) ar.ct(y[i], y[i + half], (1u << s) + ((16 * hb + i) >> (8 - s)));
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) a[(size_t)(16 * hb + i) * 256 + col] = ar.mid_out(y[i]);
+}
+
+// (RS: the input is the centered dropped limb of a rescale, reduced mod this
+// limb's prime)
 template <bool RS>
 __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         RescaleFuse f, DevTables T)
@@ -346,97 +469,78 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_s
     __shared__ u64 lds[256 * 16];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
-    const u64 q = T.pc[pi].q, q2 = 2 * q;
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q;
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
-    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
     const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
-    u64 x[16];
+    u64 r[16];
     if (RS) {
-        const PrimeC pc = T.pc[pi];
         const u64 ql = T.pc[f.level].q;
         const u64 *src = f.last + it.poly * f.ls + it.tile * 16;
 #pragma unroll
         for (int h = 0; h < 16; h++) {
             const u64 v = src[(size_t)(l + 16 * h) * 256 + col];
             if (v <= (ql - 1) / 2) {
-                x[h] = mod64(v, pc);
+                r[h] = mod64(v, pc);
             } else {
                 const u64 m = mod64(ql - v, pc);
-                x[h] = m ? q - m : 0;
+                r[h] = m ? q - m : 0;
             }
         }
     } else {
 #pragma unroll
-        for (int h = 0; h < 16; h++) x[h] = a[(size_t)(l + 16 * h) * 256 + col];
+        for (int h = 0; h < 16; h++) r[h] = a[(size_t)(l + 16 * h) * 256 + col];
     }
+    if (use_fp(T, pc)) {
+        const ArFp ar = ar_fp(pc, T.twf, pi);
+        double x[16];
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
-        const int half = 8 >> s;
-#pragma unroll
-        for (int h = 0; h < 16; h++)
-            if (!(h & half)) {
-                const u32 idx = (1u << s) + (h >> (4 - s));
-                ct_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
-            }
+        for (int h = 0; h < 16; h++) x[h] = ar.in(r[h]);
+        ntt16_fwd_cols_body(ar, x, a, lds, col, l);
+    } else {
+        ntt16_fwd_cols_body(ar_int(pc, T.tw, T.tw_sh, pi), r, a, lds, col, l);
     }
-#pragma unroll
-    for (int h = 0; h < 16; h++) lds[(l + 16 * h) * 16 + col] = x[h];
-    __syncthreads();
-    const u32 hb = l;  // round B: rows 16*hb + i
-#pragma unroll
-    for (int i = 0; i < 16; i++) x[i] = lds[(16 * hb + i) * 16 + col];
-#pragma unroll
-    for (int s = 4; s < 8; s++) {
-        const int half = 128 >> s;
-#pragma unroll
-        for (int i = 0; i < 16; i++)
-            if (!(i & half)) {
-                const u32 idx = (1u << s) + ((16 * hb + i) >> (8 - s));
-                ct_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
-            }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) a[(size_t)(16 * hb + i) * 256 + col] = x[i];
 }
 
 // forward row pass: stages 8..15 inside 16 rows of 256 words; the fully
 // reduced output of each row is left in its LDS row lr (padded) for the
 // epilogue of the caller
-DEV void ntt16_fwd_rows_body(const u64 *a, u64 *lr, u32 grow, u32 row, u32 l, const u64 *w, const u64 *ws, u64 q)
+template <class Ar>
+DEV void ntt16_fwd_rows_core(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 row, u32 l)
 {
-    const u64 q2 = 2 * q;
-    u64 x[16];
+    typedef typename Ar::V V;
+    V x[16];
 #pragma unroll
-    for (int h = 0; h < 16; h++) x[h] = a[row * 256 + l + 16 * h];
+    for (int h = 0; h < 16; h++) x[h] = ar.mid_in(a[row * 256 + l + 16 * h]);
 #pragma unroll
     for (int s2 = 0; s2 < 4; s2++) {
         const int half = 8 >> s2;
 #pragma unroll
         for (int h = 0; h < 16; h++)
-            if (!(h & half)) {
-                const u32 idx = (256u << s2) + (grow << s2) + (h >> (4 - s2));
-                ct_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
-            }
+            if (!(h & half)) ar.ct(x[h], x[h + half], (256u << s2) + (grow << s2) + (h >> (4 - s2)));
     }
 #pragma unroll
-    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = x[h];
+    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = ar.mid_out(x[h]);
     __syncthreads();
     const u32 hb = l;
 #pragma unroll
-    for (int i = 0; i < 16; i++) x[i] = lr[N16_PAD(16 * hb + i)];
+    for (int i = 0; i < 16; i++) x[i] = ar.mid_in(lr[N16_PAD(16 * hb + i)]);
 #pragma unroll
     for (int s2 = 4; s2 < 8; s2++) {
         const int half = 128 >> s2;
 #pragma unroll
         for (int i = 0; i < 16; i++)
-            if (!(i & half)) {
-                const u32 idx = (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2));
-                ct_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
-            }
+            if (!(i & half)) ar.ct(x[i], x[i + half], (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2)));
     }
 #pragma unroll
-    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = reduce4(x[i], q);
+    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = ar.full(x[i]);
     __syncthreads();
+}
+DEV void ntt16_fwd_rows_body(const DevTables &T, const PrimeC &pc, u32 pi, const u64 *a, u64 *lr, u32 grow, u32 row,
+                             u32 l)
+{
+    if (use_fp(T, pc)) ntt16_fwd_rows_core(ar_fp(pc, T.twf, pi), a, lr, grow, row, l);
+    else ntt16_fwd_rows_core(ar_int(pc, T.tw, T.tw_sh, pi), a, lr, grow, row, l);
 }
 
 // forward row pass; fully reduced output (RS: written as (c - output) q_l^-1
@@ -448,13 +552,13 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
     __shared__ u64 lds[16 * 272];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
-    const u64 q = T.pc[pi].q;
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q;
     const u32 r0 = it.tile * 16;
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
-    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
     const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
     u64 *lr = lds + row * 272;
-    ntt16_fwd_rows_body(a, lr, r0 + row, row, l, w, ws, q);
+    ntt16_fwd_rows_body(T, pc, pi, a, lr, r0 + row, row, l);
     if (RS) {
         const size_t off = ((size_t)it.limb << 16) + (size_t)r0 * 256 + row * 256;
         const u64 *cp = f.c + it.poly * f.cs + off;
@@ -480,14 +584,14 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 n
     __shared__ u64 lds[16 * 272];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
-    const u64 q = T.pc[pi].q;
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q;
     const u32 r0 = it.tile * 16;
     const size_t ps = (size_t)nq << 16;
     u64 *a = y + it.poly * ps + ((size_t)it.limb << 16) + (size_t)r0 * 256;
-    const u64 *w = T.tw + ((size_t)pi << 16), *ws = T.tw_sh + ((size_t)pi << 16);
     const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
     u64 *lr = lds + row * 272;
-    ntt16_fwd_rows_body(a, lr, r0 + row, row, l, w, ws, q);
+    ntt16_fwd_rows_body(T, pc, pi, a, lr, r0 + row, row, l);
     const u32 r = it.poly >> 1, p = it.poly & 1, i = it.limb;
     if (!cb.out[r]) return;  // a slot of the batch nobody asked for
     const u64 pinv = lc->pinv[i], pinv_sh = lc->pinv_sh[i];
@@ -507,6 +611,39 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 n
 
 // inverse row pass: stages 15..8 (Gentleman-Sande) inside 16 rows (OOP: the
 // input read from src with its own poly stride, the output written to base)
+template <class Ar>
+DEV void ntt16_inv_rows_core(const Ar &ar, const u64 *in, u64 *a, u64 *lr, u32 grow, u32 row, u32 l)
+{
+    typedef typename Ar::V V;
+    V x[16];
+#pragma unroll
+    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = in[row * 256 + l + 16 * h];
+    __syncthreads();
+    const u32 hb = l;
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = ar.in(lr[N16_PAD(16 * hb + i)]);
+#pragma unroll
+    for (int s2 = 7; s2 >= 4; s2--) {
+        const int half = 128 >> s2;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) ar.gs(x[i], x[i + half], (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2)));
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = ar.mid_out(x[i]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = ar.mid_in(lr[N16_PAD(l + 16 * h)]);
+#pragma unroll
+    for (int s2 = 3; s2 >= 0; s2--) {
+        const int half = 8 >> s2;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) ar.gs(x[h], x[h + half], (256u << s2) + (grow << s2) + (h >> (4 - s2)));
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = ar.mid_out(x[h]);
+}
 template <bool OOP>
 __global__ void __launch_bounds__(256) k_ntt16_inv_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         const u64 *src, size_t src_stride, DevTables T)
@@ -514,51 +651,56 @@ __global__ void __launch_bounds__(256) k_ntt16_inv_rows(u64 *base, size_t poly_s
     __shared__ u64 lds[16 * 272];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
-    const u64 q = T.pc[pi].q, q2 = 2 * q;
+    const PrimeC pc = T.pc[pi];
     const u32 r0 = it.tile * 16;
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
-    const u64 *w = T.itw + ((size_t)pi << 16), *ws = T.itw_sh + ((size_t)pi << 16);
     const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
-    const u32 grow = r0 + row;
     u64 *lr = lds + row * 272;
-    u64 x[16];
     const u64 *in = OOP ? src + it.poly * src_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256 : a;
-#pragma unroll
-    for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = in[row * 256 + l + 16 * h];
-    __syncthreads();
-    const u32 hb = l;
-#pragma unroll
-    for (int i = 0; i < 16; i++) x[i] = lr[N16_PAD(16 * hb + i)];
-#pragma unroll
-    for (int s2 = 7; s2 >= 4; s2--) {
-        const int half = 128 >> s2;
-#pragma unroll
-        for (int i = 0; i < 16; i++)
-            if (!(i & half)) {
-                const u32 idx = (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2));
-                gs_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
-            }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = x[i];
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 16; h++) x[h] = lr[N16_PAD(l + 16 * h)];
-#pragma unroll
-    for (int s2 = 3; s2 >= 0; s2--) {
-        const int half = 8 >> s2;
-#pragma unroll
-        for (int h = 0; h < 16; h++)
-            if (!(h & half)) {
-                const u32 idx = (256u << s2) + (grow << s2) + (h >> (4 - s2));
-                gs_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
-            }
-    }
-#pragma unroll
-    for (int h = 0; h < 16; h++) a[row * 256 + l + 16 * h] = x[h];
+    if (use_fp(T, pc)) ntt16_inv_rows_core(ar_fp(pc, T.itwf, pi), in, a, lr, r0 + row, row, l);
+    else ntt16_inv_rows_core(ar_int(pc, T.itw, T.itw_sh, pi), in, a, lr, r0 + row, row, l);
 }
 
 // inverse column pass: stages 7..0, then the factor n^-1; fully reduced output
+template <class Ar>
+DEV void ntt16_inv_cols_core(const Ar &ar, u64 *a, u64 *lds, u32 col, u32 l, const PrimeC &pc);
+DEV u64 ninv_full(const ArInt &ar, u64 x, const PrimeC &pc) { return shoup_mul(x, pc.ninv, pc.ninv_sh, pc.q); }
+DEV u64 ninv_full(const ArFp &ar, double x, const PrimeC &pc)
+{
+    double r = ar.mulmod(x, (double)pc.ninv, pc.ninv_q);  // [0, 2q)
+    r = r >= ar.q ? r - ar.q : r;
+    return (u64)r;
+}
+template <class Ar>
+DEV void ntt16_inv_cols_core(const Ar &ar, u64 *a, u64 *lds, u32 col, u32 l, const PrimeC &pc)
+{
+    typedef typename Ar::V V;
+    const u32 hb = l;
+    V x[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = ar.mid_in(a[(size_t)(16 * hb + i) * 256 + col]);
+#pragma unroll
+    for (int s = 7; s >= 4; s--) {
+        const int half = 128 >> s;
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+            if (!(i & half)) ar.gs(x[i], x[i + half], (1u << s) + ((16 * hb + i) >> (8 - s)));
+    }
+#pragma unroll
+    for (int i = 0; i < 16; i++) lds[(16 * hb + i) * 16 + col] = ar.mid_out(x[i]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 16; h++) x[h] = ar.mid_in(lds[(l + 16 * h) * 16 + col]);
+#pragma unroll
+    for (int s = 3; s >= 0; s--) {
+        const int half = 8 >> s;
+#pragma unroll
+        for (int h = 0; h < 16; h++)
+            if (!(h & half)) ar.gs(x[h], x[h + half], (1u << s) + (h >> (4 - s)));
+    }
+#pragma unroll
+    for (int h = 0; h < 16; h++) a[(size_t)(l + 16 * h) * 256 + col] = ninv_full(ar, x[h], pc);
+}
 __global__ void __launch_bounds__(256) k_ntt16_inv_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         DevTables T)
 {
@@ -566,41 +708,10 @@ __global__ void __launch_bounds__(256) k_ntt16_inv_cols(u64 *base, size_t poly_s
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
-    const u64 q = pc.q, q2 = 2 * q;
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
-    const u64 *w = T.itw + ((size_t)pi << 16), *ws = T.itw_sh + ((size_t)pi << 16);
     const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
-    const u32 hb = l;
-    u64 x[16];
-#pragma unroll
-    for (int i = 0; i < 16; i++) x[i] = a[(size_t)(16 * hb + i) * 256 + col];
-#pragma unroll
-    for (int s = 7; s >= 4; s--) {
-        const int half = 128 >> s;
-#pragma unroll
-        for (int i = 0; i < 16; i++)
-            if (!(i & half)) {
-                const u32 idx = (1u << s) + ((16 * hb + i) >> (8 - s));
-                gs_bfly(x[i], x[i + half], w[idx], ws[idx], q2, q);
-            }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) lds[(16 * hb + i) * 16 + col] = x[i];
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 16; h++) x[h] = lds[(l + 16 * h) * 16 + col];
-#pragma unroll
-    for (int s = 3; s >= 0; s--) {
-        const int half = 8 >> s;
-#pragma unroll
-        for (int h = 0; h < 16; h++)
-            if (!(h & half)) {
-                const u32 idx = (1u << s) + (h >> (4 - s));
-                gs_bfly(x[h], x[h + half], w[idx], ws[idx], q2, q);
-            }
-    }
-#pragma unroll
-    for (int h = 0; h < 16; h++) a[(size_t)(l + 16 * h) * 256 + col] = shoup_mul(x[h], pc.ninv, pc.ninv_sh, q);
+    if (use_fp(T, pc)) ntt16_inv_cols_core(ar_fp(pc, T.itwf, pi), a, lds, col, l, pc);
+    else ntt16_inv_cols_core(ar_int(pc, T.itw, T.itw_sh, pi), a, lds, col, l, pc);
 }
 
 TuneParams &hec_tune_params()
@@ -644,13 +755,13 @@ static void ntt_launch_one(const DevTables &T, bool inv, u64 *base, size_t poly_
         const u32 np = (u32)npolys;
         if (!inv) {
             KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
-                    np, RescaleFuse{}, T);
+                    np, RescaleFuse{}, tuned(T));
             KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
-                    np, RescaleFuse{}, T);
+                    np, RescaleFuse{}, tuned(T));
         } else {
             KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
-                    np, nullptr, (size_t)0, T);
-            KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, T);
+                    np, nullptr, (size_t)0, tuned(T));
+            KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, base, poly_stride, pmap, np, tuned(T));
         }
         return;
     }
@@ -685,8 +796,8 @@ bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64
     dim3 g((u32)(16 * limbs));
     const u32 np = (u32)npolys;
     KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<true>, g, dim3(256), 0, st, dst, dst_stride, pmap, np, src,
-            src_stride, T);
-    KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, dst, dst_stride, pmap, np, T);
+            src_stride, tuned(T));
+    KLAUNCH("k_ntt16_inv_cols", limbs, k_ntt16_inv_cols, g, dim3(256), 0, st, dst, dst_stride, pmap, np, tuned(T));
     return true;
 }
 bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, const CombineBatch &cb,
@@ -697,9 +808,9 @@ bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, 
     const uint64_t limbs = (uint64_t)nq * np;
     dim3 g((u32)(16 * limbs));
     KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, y, (size_t)nq << 16, pmap, np,
-            RescaleFuse{}, T);
+            RescaleFuse{}, tuned(T));
     KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np, cb,
-            lc, T);
+            lc, tuned(T));
     return true;
 }
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
@@ -711,8 +822,8 @@ bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pm
     dim3 g((u32)(16 * limbs));
     const size_t ps = (size_t)l << 16;
     const u32 np = (u32)npolys;
-    KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, T);
-    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, T);
+    KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, tuned(T));
+    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, tuned(T));
     return true;
 }
 void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
@@ -1165,12 +1276,15 @@ DEV void st2(u64 *p, u64x2 v) { *(u64x2 *)p = v; }
 template <int BETA, int NOUT>
 __global__ void __launch_bounds__(EW_THREADS) __attribute__((amdgpu_waves_per_eu(NOUT == 1 ? 5 : 4)))
 k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK,
-         u32 first, u32 nchunks, u32 ngroups, DevTables T)
+         u32 first, u32 nchunks, u32 ngroups, ShardArg sh, DevTables T)
 {
     const u32 w = blockIdx.x, total = gridDim.x;
-    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
-    // output groups of the same (limb, chunk) are neighbours: they run together
-    // on one XCD and share the key and digit reads through its L2
+    const u32 i0 = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    // the inputs of a multi-input launch (same terms, keys and plaintexts) are
+    // the fastest index, then the output groups: the workgroups of one (limb,
+    // chunk) are neighbours, run together on one XCD and share the key,
+    // plaintext and digit reads through its L2
+    const u32 u = i0 % sh.S, i = i0 / sh.S;
     const u32 grp = i % ngroups, rest = i / ngroups;
     const u32 chunk = rest % nchunks, o = rest / nchunks;
     const u32 vb = grp * NOUT;
@@ -1190,7 +1304,7 @@ k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq, u32 nqp, const u
     // rotations by zero: P * (c0, c1)
     if (isq)
         for (u32 t = 0; t < nz; t++) {
-            const u64 *ct = b.ct[t];
+            const u64 *ct = b.ct[t] + u * sh.cs;
             const u64x2 c0 = ld2(ct + (size_t)o * n + k), c1 = ld2(ct + ((size_t)nq + o) * n + k);
             const u64 e00 = mont_mul(c0.x, pmo, pc.q, pc.qinv_neg), e01 = mont_mul(c0.y, pmo, pc.q, pc.qinv_neg);
             const u64 e10 = mont_mul(c1.x, pmo, pc.q, pc.qinv_neg), e11 = mont_mul(c1.y, pmo, pc.q, pc.qinv_neg);
@@ -1209,7 +1323,7 @@ k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq, u32 nqp, const u
         const u32 src = auto_src(k, b.g[t], T.logn);
         const u32 sb = src & ~1u;
         const bool sw = src & 1u;
-        const u64 *key = b.key[t], *D = b.D[t], *ct = b.ct[t];
+        const u64 *key = b.key[t], *D = b.D[t] + u * sh.ds, *ct = b.ct[t] + u * sh.cs;
         // issue the loads of the input and plaintext limbs together with the key
         // loads below (addresses always valid; unused values are ignored)
         const u64x2 c = ld2(ct + (size_t)(isq ? o : 0) * n + sb);
@@ -1250,6 +1364,7 @@ k_ks_mac(KsMacBatch b, u32 nz, u32 nterms, u32 beta_rt, u32 nq, u32 nqp, const u
     for (int v = 0; v < NOUT; v++) {
         u64 *E = b.E[vb + v];
         if (!E) continue;
+        E += u * sh.es;
 #pragma unroll
         for (int p = 0; p < 2; p++) {
             u64 *dst = E + ((size_t)p * nqp + o) * n + k;
@@ -1493,17 +1608,17 @@ static void ks_mac_w_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacB
 template <int BETA, int NOUT>
 static void ks_mac_launch(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
                           u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
-                          u32 ngroups, const DevTables &T)
+                          u32 ngroups, const ShardArg &sh, const DevTables &T)
 {
     KLAUNCH("k_ks_mac", units, (k_ks_mac<BETA, NOUT>), g, dim3(EW_THREADS), 0, st, b, nz, nterms, beta, nq, nqp,
-            pmap, pm, NLK, first, nchunks, ngroups, T);
+            pmap, pm, NLK, first, nchunks, ngroups, sh, T);
 }
 template <int NOUT>
 static void ks_mac_beta(dim3 g, uint64_t units, hipStream_t st, const KsMacBatch &b, u32 nz, u32 nterms, u32 beta,
                         u32 nq, u32 nqp, const u32 *pmap, const u64 *pm, u32 NLK, u32 first, u32 nchunks,
-                        u32 ngroups, const DevTables &T)
+                        u32 ngroups, const DevTables &T, const ShardArg &sh = ShardArg{1, 0, 0, 0})
 {
-#define KSM_ARGS g, units, st, b, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T
+#define KSM_ARGS g, units, st, b, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, sh, T
     switch (beta) {
     case 1: ks_mac_launch<1, NOUT>(KSM_ARGS); break;
     case 2: ks_mac_launch<2, NOUT>(KSM_ARGS); break;
@@ -1580,6 +1695,31 @@ bool hec_ks_mac(const DevTables &T, const KsMacBatch &b, int nterms, int nout, i
         ks_mac_beta<1>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
     else
         ks_mac_beta<2>(g, units, st, bb, nz, nterms, beta, nq, nqp, pmap, pm, NLK, first, nchunks, ngroups, T);
+    return true;
+}
+
+bool hec_ks_mac_shards(const DevTables &T, const KsMacBatch &b, int nterms, int beta, int nq, int nqp,
+                       const u32 *pmap, const u64 *pm, int NLK, int first, const ShardArg &sh, hipStream_t st)
+{
+    if (nterms < 0 || nterms > HEC_KS_BATCH || sh.S < 1 || !b.E[0]) return false;
+    u32 nz = 0;
+    while ((int)nz < nterms && b.g[nz] == 1) nz++;
+    for (int t = 0; t < nterms; t++) {
+        if (!b.ct[t] || !b.pt[t][0]) return false;
+        if (t >= (int)nz && (b.g[t] == 1 || !b.key[t] || !b.D[t])) return false;  // zero rotations come first
+    }
+    // units: every key and plaintext limb once, the inputs' digits and ciphertexts once, the accumulators
+    uint64_t units = (uint64_t)sh.S * ((uint64_t)beta * nqp + 2ull * nq) + (((first & 1) ? 2ull : 4ull) * nqp) * sh.S;
+    for (int t = 0; t < nterms; t++) units += (t >= (int)nz ? 2ull * beta * nqp : 0) + (t >= (int)nz ? nqp : nq);
+    KsMacBatch bb = b;
+    for (int v = 1; v < HEC_MAC_OUT; v++) {
+        bb.E[v] = nullptr;
+        for (int t = 0; t < HEC_KS_BATCH; t++) bb.pt[t][v] = nullptr;
+    }
+    const u32 nchunks = (T.n / 2 + EW_THREADS - 1) / EW_THREADS;
+    dim3 g(nchunks * (u32)nqp * sh.S);
+    ks_mac_beta<1>(g, units, st, bb, nz, (u32)nterms, (u32)beta, (u32)nq, (u32)nqp, pmap, pm, (u32)NLK, (u32)first,
+                   nchunks, 1, T, sh);
     return true;
 }
 

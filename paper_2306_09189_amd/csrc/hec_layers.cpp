@@ -1175,12 +1175,96 @@ static hec_status masked_sums_multi(hec_ctx *c, const std::vector<const hec_ct *
     return s;
 }
 
+// The lazy form (reading of mode 2) of the same masked sums for every input
+// at once: out[u] = ModDown(sum_t masks[t] * KS_t(ins[u])) with the key-switch
+// products taken over Q_l and P and one ModDown per input (P * mask * c0 for
+// rotations by zero).  The inputs are gathered into one buffer so that one
+// fused key-switch launch per batch of 16 amounts covers all of them with each
+// key and mask limb read once (hec_ks_mac_shards); the same sums, so the same
+// ciphertexts as one lazy masked sum per input.
+static hec_status masked_sums_lazy_multi(hec_ctx *c, const std::vector<const hec_ct *> &ins,
+                                         const std::vector<int32_t> &steps, const std::vector<hec_pt *> &masks,
+                                         std::vector<hec_ct *> &out)
+{
+    out.clear();
+    const size_t n = c->n, S0 = ins.size();
+    const uint32_t lvl = ins[0]->level, nq = lvl + 1, nqp = nq + c->k;
+    const uint32_t beta = (nq + c->alpha - 1) / c->alpha;
+    std::vector<size_t> order;  // rotations by zero first (the kernel takes them as a leading run)
+    for (size_t t = 0; t < steps.size(); t++)
+        if (c->galois(steps[t]) == 1) order.push_back(t);
+    for (size_t t = 0; t < steps.size(); t++) {
+        const uint32_t g = c->galois(steps[t]);
+        if (g == 1) continue;
+        if (!c->rotkeys.count(g)) HEC_FAIL(HEC_ENOKEY, "no rotation key for step %d", steps[t]);
+        order.push_back(t);
+    }
+    for (auto *m : masks)
+        if (!m->has_p || m->level != lvl) HEC_FAIL(HEC_EINVAL, "masks of a lazy sum need the special-prime limbs");
+    const size_t G = 32;  // inputs per launch group
+    hec_status s = HEC_OK;
+    for (size_t u0 = 0; u0 < S0 && s == HEC_OK; u0 += G) {
+        const size_t S = std::min(G, S0 - u0);
+        const size_t cs = 2ull * nq * n, ds = (size_t)beta * nqp * n, es = 2ull * nqp * n;
+        u64 *buf = c->alloc(S * cs), *E = c->alloc(S * es);
+        if (!buf || !E) {
+            c->release(buf);
+            c->release(E);
+            s = HEC_ENOMEM;
+            hec_set_error("lazy masked sum buffers");
+            break;
+        }
+        std::vector<hec_ct> views(S);
+        std::vector<const hec_ct *> vp(S);
+        for (size_t u = 0; u < S && s == HEC_OK; u++) {
+            if (ins[u0 + u]->level != lvl) s = HEC_ELEVEL, hec_set_error("lazy sum over inputs at different levels");
+            else if (hipMemcpyAsync(buf + u * cs, ins[u0 + u]->d, cs * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+                s = HEC_EDEVICE, hec_set_error("input gather");
+            views[u] = *ins[u0 + u];
+            views[u].d = buf + u * cs;
+            vp[u] = &views[u];
+        }
+        u64 *Dall = nullptr;
+        if (s == HEC_OK) s = ct_modup_many(c, vp, &Dall);
+        for (size_t b0 = 0; b0 < order.size() && s == HEC_OK; b0 += HEC_KS_BATCH) {
+            const size_t nt = std::min((size_t)HEC_KS_BATCH, order.size() - b0);
+            KsMacBatch b{};
+            b.E[0] = E;
+            for (size_t t = 0; t < nt; t++) {
+                const size_t ti = order[b0 + t];
+                const uint32_t g = c->galois(steps[ti]);
+                b.g[t] = g;
+                b.key[t] = g == 1 ? nullptr : c->rotkeys[g];
+                b.D[t] = Dall;
+                b.ct[t] = buf;
+                b.pt[t][0] = masks[ti]->d;
+                if (g != 1) c->ks_count += S;
+            }
+            if (!hec_ks_mac_shards(c->T, b, (int)nt, (int)beta, (int)nq, (int)nqp, c->qpmap(lvl), c->d_pmodq_m,
+                                   (int)c->NLK, b0 == 0 ? 1 : 0, ShardArg{(u32)S, ds, cs, es}, c->st))
+                s = HEC_EINVAL, hec_set_error("invalid multi-input key-switch batch");
+        }
+        std::vector<hec_ct *> o(S, nullptr);
+        for (size_t u = 0; u < S && s == HEC_OK; u++)
+            if (!(o[u] = ct_new(c, lvl, ins[u0 + u]->scale * masks[order[0]]->scale)))
+                s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+        if (s == HEC_OK) s = ct_moddown_many(c, lvl, E, o);
+        c->release(Dall);
+        c->release(buf);
+        c->release(E);
+        if (s == HEC_OK) out.insert(out.end(), o.begin(), o.end());
+        else free_all(o);
+    }
+    if (s != HEC_OK) free_all(out);
+    return s;
+}
+
 // Pooling mode 4 on image shards with two levels or more (Section 4.2): the
 // 2x2 window sums, the horizontal and the vertical masked reductions of all
 // shards together, stage by stage, each rotation key read once per stage for
 // all shards; the same ciphertexts as mode 0.  Other layouts: false in *done.
 static hec_status downsample_multi(hec_ctx *c, const std::vector<hec_ct *> &in, const Layout &L, bool select,
-                                   std::vector<hec_ct *> &out, Layout &nl, bool *done)
+                                   std::vector<hec_ct *> &out, Layout &nl, bool *done, bool lazy = false)
 {
     *done = false;
     if (L.channel || in.empty()) return HEC_OK;
@@ -1232,12 +1316,18 @@ static hec_status downsample_multi(hec_ctx *c, const std::vector<hec_ct *> &in, 
     std::vector<hec_pt *> mh, mv;
     std::vector<hec_ct *> M1, M2;
     if (s == HEC_OK) s = get_masks(c, L, 'h', ij, Wo, val, lvl, (double)c->mod[lvl], mh);
-    if (s == HEC_OK) s = masked_sums_multi(c, std::vector<const hec_ct *>(D.begin(), D.end()), hs, mh, M1);
+    if (s == HEC_OK) {
+        const std::vector<const hec_ct *> Dc(D.begin(), D.end());
+        s = lazy ? masked_sums_lazy_multi(c, Dc, hs, mh, M1) : masked_sums_multi(c, Dc, hs, mh, M1);
+    }
     free_all(D);
     for (size_t u = 0; u < M1.size() && s == HEC_OK; u++) s = ct_rescale(c, M1[u]);
     const uint32_t l1 = lvl - 1;
     if (s == HEC_OK) s = get_masks(c, L, 'v', jj, Wo, 1.0, l1, (double)c->mod[l1], mv);
-    if (s == HEC_OK) s = masked_sums_multi(c, std::vector<const hec_ct *>(M1.begin(), M1.end()), vs, mv, M2);
+    if (s == HEC_OK) {
+        const std::vector<const hec_ct *> Mc(M1.begin(), M1.end());
+        s = lazy ? masked_sums_lazy_multi(c, Mc, vs, mv, M2) : masked_sums_multi(c, Mc, vs, mv, M2);
+    }
     free_all(M1);
     for (size_t u = 0; u < M2.size() && s == HEC_OK; u++) s = ct_rescale(c, M2[u]);
     if (s != HEC_OK) {
@@ -1314,7 +1404,7 @@ static hec_status downsample_and_merge_multi(hec_ctx *c, const std::vector<std::
                                              std::vector<std::vector<hec_ct *>> &outs, Layout &ol)
 {
     outs.assign(ins.size(), {});
-    if (L.channel || mode != 4 || ins.size() == 1) {
+    if (L.channel || (mode != 4 && mode != 2) || ins.size() == 1) {
         for (size_t r = 0; r < ins.size(); r++) {
             hec_status s = downsample_and_merge(c, ins[r], L, select, mode, outs[r], ol);
             if (s != HEC_OK) {
@@ -1336,9 +1426,9 @@ static hec_status downsample_and_merge_multi(hec_ctx *c, const std::vector<std::
     std::vector<hec_ct *> ds;
     Layout nlk;
     bool done = false;
-    HEC_CHECK(downsample_multi(c, all, Lk, select, ds, nlk, &done));
+    HEC_CHECK(downsample_multi(c, all, Lk, select, ds, nlk, &done, mode == 2));
     if (!done) {
-        for (size_t r = 0; r < ins.size(); r++) HEC_CHECK(downsample_and_merge(c, ins[r], L, select, 0, outs[r], ol));
+        for (size_t r = 0; r < ins.size(); r++) HEC_CHECK(downsample_and_merge(c, ins[r], L, select, mode, outs[r], ol));
         return HEC_OK;
     }
     Layout nl = nlk;
@@ -1368,7 +1458,9 @@ static hec_status downsample_and_merge(hec_ctx *c, const std::vector<hec_ct *> &
     }
     Layout nl;
     bool done = false;
-    if (mode == 4) HEC_CHECK(downsample_multi(c, in, L, select, ds, nl, &done));
+    // modes 4 and 2: the stages of all image shards together (mode 2 for more than one shard)
+    if (mode == 4 || (mode == 2 && in.size() > 1))
+        HEC_CHECK(downsample_multi(c, in, L, select, ds, nl, &done, mode == 2));
     if (!done) HEC_CHECK(downsample(c, in, L, select, mode == 4 ? 0 : mode, ds, nl));
     return merge_downsampled(c, ds, nl, out, ol);
 }
