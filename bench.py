@@ -205,6 +205,16 @@ def cpu_baseline_runs(n_rot, seconds, mode):
             "host_nproc": nproc, "host_cpu_model": model}
 
 
+def guarded(fn):
+    """A secondary measurement: its failure is reported in its own field
+    (with the error) instead of ending the run before the line is printed."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 -- any failure of the section is recorded, not raised
+        eprint("section failed: %r" % (e,))
+        return {"error": repr(e)}
+
+
 def timed(ctx, fn, reps, warm=1):
     """Median wall ms of fn() over reps calls (after warm untimed ones), the
     device drained before and after each."""
@@ -510,15 +520,15 @@ def main():
 
     # ---- the 112x112x64 ImageNet stage (32 shards): plain vs batched vs key-stationary ----
     if "imagenet" not in skip:
-        out["imagenet_112x112x64"] = imagenet_stage(ctx, hecnn, hl, rng, max(5, args.reps // 2))
+        out["imagenet_112x112x64"] = guarded(lambda: imagenet_stage(ctx, hecnn, hl, rng, max(5, args.reps // 2)))
 
     # ---- the uneven batch: 13 instances, 48 ciphertexts at levels 2..24, eager vs one captured graph ----
     if "uneven" not in skip:
-        out["uneven_batch_48ct"] = uneven_batch(ctx, hl, args.reps)
+        out["uneven_batch_48ct"] = guarded(lambda: uneven_batch(ctx, hl, args.reps))
 
     # ---- serving: Poisson arrivals of the two request shapes ----
     if "serving" not in skip:
-        out["serving"] = serving(ctx, hecnn, hl)
+        out["serving"] = guarded(lambda: serving(ctx, hecnn, hl))
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_runs(args.cpu_rotations, args.cpu_seconds, args.mode)
@@ -649,43 +659,43 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
             o.free()
         sat = len(reqs) / (time.perf_counter() - t)
         res["saturation_req_per_s"] = sat
-        for load in (0.5, 0.8):
-            srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
-            try:
-                srv_l.add_model(pa, like_a, pool_mode=4)
-                srv_l.add_model(pb, like_b)
-                lam = load * sat
-                gaps = rng.exponential(1.0 / lam, size=len(reqs))
-                t = time.perf_counter()
-                due = t
-                ids = []
-                for (m, xx, im), gap in zip(reqs, gaps):
-                    due += gap
-                    d = due - time.perf_counter()
-                    if d > 0:
-                        time.sleep(d)
-                    ids.append(srv_l.submit(m, im))
-                errs, checked = [], {ma: 0, mb: 0}
-                for (m, xx, im), rid in zip(reqs, ids):
-                    o, ms = srv_l.poll(rid)
-                    if checked[m] < 2:  # accuracy of the first two results of each kind
-                        checked[m] += 1
-                        w = wa if m == ma else wb
-                        ref = (hl.ref_avgpool2x2(hl.ref_conv2d(xx, w, 1)) if m == ma else hl.ref_conv2d(xx, w, 1, 2))
-                        errs.append(float(np.abs(o.decrypt() - ref).max()))
-                    o.free()
-                st = srv_l.stats()
-                res["load_%.1f" % load] = {"arrival_req_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                                           "mean_ms": st["mean_ms"], "req_per_s": st["req_per_s"],
-                                           "batches": st["batches"], "max_concurrent": st["max_concurrent"],
-                                           "peak_admitted_bytes": st["peak_mem"],
-                                           "max_abs_err_vs_fp64": max(errs) if errs else None}
-                eprint("serving load %.1f: p50 %.0f ms p99 %.0f ms %.2f req/s" % (load, st["p50_ms"], st["p99_ms"],
-                                                                                st["req_per_s"]))
-            finally:
-                srv_l.stop()
     finally:
-        srv.stop()
+        srv.stop()  # its lanes' memory back before the servers of the timed loads start
+    for load in (0.5, 0.8):
+        srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
+        try:
+            srv_l.add_model(pa, like_a, pool_mode=4)
+            srv_l.add_model(pb, like_b)
+            lam = load * sat
+            gaps = rng.exponential(1.0 / lam, size=len(reqs))
+            t = time.perf_counter()
+            due = t
+            ids = []
+            for (m, xx, im), gap in zip(reqs, gaps):
+                due += gap
+                d = due - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                ids.append(srv_l.submit(m, im))
+            errs, checked = [], {ma: 0, mb: 0}
+            for (m, xx, im), rid in zip(reqs, ids):
+                o, ms = srv_l.poll(rid)
+                if checked[m] < 2:  # accuracy of the first two results of each kind
+                    checked[m] += 1
+                    w = wa if m == ma else wb
+                    ref = (hl.ref_avgpool2x2(hl.ref_conv2d(xx, w, 1)) if m == ma else hl.ref_conv2d(xx, w, 1, 2))
+                    errs.append(float(np.abs(o.decrypt() - ref).max()))
+                o.free()
+            st = srv_l.stats()
+            res["load_%.1f" % load] = {"arrival_req_per_s": lam, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                       "mean_ms": st["mean_ms"], "req_per_s": st["req_per_s"],
+                                       "batches": st["batches"], "max_concurrent": st["max_concurrent"],
+                                       "peak_admitted_bytes": st["peak_mem"],
+                                       "max_abs_err_vs_fp64": max(errs) if errs else None}
+            eprint("serving load %.1f: p50 %.0f ms p99 %.0f ms %.2f req/s" % (load, st["p50_ms"], st["p99_ms"],
+                                                                            st["req_per_s"]))
+        finally:
+            srv_l.stop()
     return res
 
 

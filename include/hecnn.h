@@ -228,8 +228,8 @@ hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const doub
                                  uint32_t kw, uint32_t stride, uint32_t pad, hec_conv_plan **out);
 /* With flags = HEC_PLAN_Q_ONLY the weight plaintexts are kept over Q_l only
  * (21 instead of 29 limbs at level 20 with 8 special primes): such a plan
- * runs in modes 0 and 1 only (he_conv2d_plan_set_mode returns HEC_EINVAL for
- * 2 and 3).  For layers whose plaintexts would not fit in HBM otherwise, e.g.
+ * runs in modes 0, 1 and 4, whose products follow complete rotations
+ * (he_conv2d_plan_set_mode returns HEC_EINVAL for 2 and 3).  For layers whose plaintexts would not fit in HBM otherwise, e.g.
  * the 112x112x64 layer's 18432 plaintexts (267 GiB over Q and P, 193 GiB
  * over Q).  Unknown flag bits: HEC_EINVAL. */
 #define HEC_PLAN_Q_ONLY 1u
@@ -245,7 +245,7 @@ hec_status he_conv2d_plan_create(hec_ctx *ctx, const hec_image *like, const doub
  * rounding of w^_b (2^(s-1) / q_l absolute per weight) and of E_b (relative
  * 2^-s).  Needs an image-sharded input with at most 2 blocks per shard
  * (HEC_ELAYOUT otherwise), |w^_b| < 2^31 and primes of at least 37 bits
- * (HEC_EINVAL otherwise); runs in modes 0, 1 and 2 (he_conv2d_plan_set_mode
+ * (HEC_EINVAL otherwise); runs in modes 0, 1, 2 and 4 (he_conv2d_plan_set_mode
  * returns HEC_EINVAL for 3); excludes HEC_PLAN_Q_ONLY (HEC_EINVAL). */
 #define HEC_PLAN_BASIS 2u
 #define HEC_PLAN_BASIS_SCALE(s) ((uint32_t)(s) << 8)

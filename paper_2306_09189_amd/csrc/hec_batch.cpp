@@ -63,7 +63,7 @@ extern "C" hec_status hec_batch_begin(hec_ctx *c, hec_batch **out)
     if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
     hec_batch *b = new hec_batch();
     b->ctx = c;
-    b->gmem.spill = &c->pool;
+    b->gmem.trimmable = false;
     *out = b;
     return HEC_OK;
 }

@@ -29,26 +29,71 @@ extern "C" const char *hec_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // pool
 // ---------------------------------------------------------------------------
+namespace {
+// every pool of the process, so that a failed allocation can release the
+// cached blocks of all pools of its device (never destroyed: pools may
+// outlive the library's static objects at exit)
+struct PoolRegistry {
+    std::mutex mu;
+    std::set<DevPool *> pools;
+};
+PoolRegistry &registry()
+{
+    static PoolRegistry *r = new PoolRegistry();
+    return *r;
+}
+void trim_device_pools(int dev)
+{
+    PoolRegistry &r = registry();
+    std::lock_guard<std::mutex> lk(r.mu);
+    (void)hipDeviceSynchronize();
+    for (DevPool *p : r.pools)
+        if (p->trimmable && p->dev.load() == dev) p->release_cached();
+}
+}  // namespace
+
+DevPool::DevPool()
+{
+    PoolRegistry &r = registry();
+    std::lock_guard<std::mutex> lk(r.mu);
+    r.pools.insert(this);
+}
+DevPool::~DevPool()
+{
+    PoolRegistry &r = registry();
+    std::lock_guard<std::mutex> lk(r.mu);
+    r.pools.erase(this);
+}
 void *DevPool::get(size_t bytes)
 {
-    std::lock_guard<std::mutex> lk(mu_);
     if (!bytes) bytes = 8;
-    auto it = free_.find(bytes);
     void *p = nullptr;
-    if (it != free_.end()) {
-        p = it->second;
-        free_.erase(it);
-        bytes_cached -= bytes;
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
-        // give the cached blocks back (once the queued work that may still use them is done) and retry once,
-        // those of the pool this one spills into as well
-        (void)hipDeviceSynchronize();
-        for (auto &kv : free_) hipFree(kv.second);
-        free_.clear();
-        bytes_cached = 0;
-        if (spill && spill != this) spill->trim();
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = free_.find(bytes);
+        if (it != free_.end()) {
+            p = it->second;
+            free_.erase(it);
+            bytes_cached -= bytes;
+            live_[p] = bytes;
+            bytes_live += bytes;
+            peak_live = std::max(peak_live, bytes_live);
+            return p;
+        }
     }
+    int d = 0;
+    (void)hipGetDevice(&d);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        // the failed call's error is cleared so that a later check of the launch status does not report it
+        (void)hipGetLastError();
+        trim_device_pools(d);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    if (dev.load() < 0) dev.store(d);
     live_[p] = bytes;
     bytes_live += bytes;
     peak_live = std::max(peak_live, bytes_live);
@@ -65,14 +110,21 @@ bool DevPool::put(void *p)
     live_.erase(it);
     return true;
 }
-void DevPool::trim()
+void DevPool::release_cached()
 {
     std::lock_guard<std::mutex> lk(mu_);
-    if (free_.empty()) return;
-    (void)hipDeviceSynchronize();
     for (auto &kv : free_) hipFree(kv.second);
     free_.clear();
     bytes_cached = 0;
+}
+void DevPool::trim()
+{
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (free_.empty()) return;
+    }
+    (void)hipDeviceSynchronize();
+    release_cached();
 }
 void DevPool::release_all()
 {
@@ -446,7 +498,6 @@ hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out)
     c->rotkeys = parent->rotkeys;
     c->rlk = parent->rlk;
     c->lane = true;
-    c->pool.spill = &parent->pool;
     HEC_TRY_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
     c->d_flag = (int *)c->pool.get(256);
     if (!c->d_flag) {

@@ -1,6 +1,7 @@
 // hec_internal.h -- host-side structures of the library (not part of the ABI).
 #pragma once
 #include <array>
+#include <atomic>
 #include <functional>
 #include <map>
 #include <memory>
@@ -48,12 +49,20 @@ struct DevPool {
     std::unordered_map<void *, size_t> live_;
     size_t bytes_live = 0, bytes_cached = 0, peak_live = 0;
     std::mutex mu_;
-    // another pool whose cached blocks go back to the device too when this
-    // one runs out (a batch's or a serving lane's pool spills into its context's)
-    DevPool *spill = nullptr;
+    // When an allocation fails, every trimmable pool of the device gives its
+    // cached blocks back (after the device's queued work) and the allocation
+    // is tried once more.  A batch's pool is not trimmable: its cached blocks
+    // are the temporaries of a captured graph that its replays still use.
+    bool trimmable = true;
+    std::atomic<int> dev{-1};  // device of the blocks (set at the first allocation)
+    DevPool();
+    ~DevPool();
+    DevPool(const DevPool &) = delete;
+    DevPool &operator=(const DevPool &) = delete;
     void *get(size_t bytes);
     bool put(void *p);  // false: not a block of this pool
     void trim();        // cached blocks back to the device (after the device's queued work)
+    void release_cached();  // the same without waiting (the caller has synchronized)
     void release_all();
     size_t live()
     {

@@ -1782,7 +1782,8 @@ hec_status conv_plan_create(hec_ctx *c, const Layout &lay, uint32_t lvl, const d
 extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
 {
     if (!p || mode < 0 || mode > 4) HEC_FAIL(HEC_EINVAL, "bad mode");
-    if (p->q_only && mode >= 2) HEC_FAIL(HEC_EINVAL, "plan without special-prime limbs runs in modes 0 and 1 only");
+    if (p->q_only && (mode == 2 || mode == 3))
+        HEC_FAIL(HEC_EINVAL, "plan without special-prime limbs runs in modes 0, 1 and 4 only");
     if (p->basis && mode == 3) HEC_FAIL(HEC_EINVAL, "basis-mask plan runs in modes 0, 1 and 2");
     if (mode == 3) {
         HEC_TRY_HIP(hipSetDevice(p->ctx->dev));

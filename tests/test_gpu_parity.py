@@ -431,7 +431,8 @@ def test_basis_plan_errors(small):
 
 def test_q_only_plan(small):
     """A plan whose weight plaintexts are kept over Q only gives the same
-    ciphertexts as a full plan in modes 0 and 1 and refuses modes 2 and 3."""
+    ciphertexts as a full plan in modes 0, 1 and 4 (the products follow
+    complete rotations) and refuses modes 2 and 3 (products over Q*P)."""
     from paper_2306_09189_amd import hecnn
     ctx, prm, o = small
     rng = np.random.default_rng(77)
@@ -443,7 +444,7 @@ def test_q_only_plan(small):
     ctx.gen_rotation_keys(full.steps())
     assert qo.steps() == full.steps()
     a = full.run(img)
-    for mode in (0, 1):
+    for mode in (0, 1, 4):
         qo.set_mode(mode)
         b = qo.run(img)
         for u in range(a.info()[-1]):
