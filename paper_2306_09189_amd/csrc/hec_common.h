@@ -17,6 +17,7 @@ struct PrimeC {
     u64 ninv;      // n^-1 mod q
     u64 ninv_sh;   // Shoup companion of ninv
     double qd, ninv_q;  // q and n^-1 / q as doubles (primes below 2^50: the exact double butterflies)
+    double qinv_d;      // 1 / q rounded to the nearest double
     u32 fp;             // q < 2^50: the 2^16 transforms may run in doubles
     u32 pad_;
 };
@@ -54,6 +55,10 @@ struct DevTables {
     const u64 *tw, *tw_sh;    // psi^brv(k), [prime][n]
     const u64 *itw, *itw_sh;  // psi^-brv(k), [prime][n]
     const double2 *twf, *itwf;  // (w, w / q) as doubles for the primes below 2^50, [prime][n]
+    // forward row-pass twists of the 2^16 transforms (n = 2^16 only, else null), [prime][row][col]
+    // of the 256 x 256 view: psi^(col (1 + 2 brv8(row))), with Shoup companions, and as doubles
+    const u64 *z, *z_sh;
+    const double *zf;
     u32 fp_on;                  // the 2^16 transforms of those primes in doubles (a launch parameter)
 };
 

@@ -207,6 +207,7 @@ static hec_status build_tables(hec_ctx *c)
         pc[i].fp = q < (1ull << 50) ? 1u : 0u;
         pc[i].qd = (double)q;
         pc[i].ninv_q = (double)pc[i].ninv / (double)q;
+        pc[i].qinv_d = 1.0 / (double)q;
         u64 psi = find_root_2n(q, n), ipsi = invmod(psi, q);
         std::vector<u64> pw(n), ipw(n);
         pw[0] = ipw[0] = 1;
@@ -241,6 +242,45 @@ static hec_status build_tables(hec_ctx *c)
     HEC_CHECK(upload(c->d_twsh, twsh.data(), twsh.size() * 8, c->st));
     HEC_CHECK(upload(c->d_itw, itw.data(), itw.size() * 8, c->st));
     HEC_CHECK(upload(c->d_itwsh, itwsh.data(), itwsh.size() * 8, c->st));
+    if (c->logn == 16) {
+        // Forward row-pass twists of the 2^16 transforms.  In the 256 x 256
+        // view the twiddle of row-pass stage 8 + s, row r, butterfly group
+        // t < 2^s is psi^brv16(2^(8+s) + r 2^s + t) = R_r^(2^(7-s)) psi^brv16(t)
+        // with R_r = psi^(1 + 2 brv8(r)) (the three parts occupy disjoint
+        // bits).  The factor R_r^(2^(7-s)) is met by the input at column c
+        // exactly when bit 7-s of c is set, so over the whole pass it multiplies
+        // that input by R_r^c: the pass is the element-wise product by R_r^c
+        // followed by butterflies with the 128 row-independent twiddles
+        // psi^brv16(t).  Same residues, one twist per element in place of the
+        // row's own 255 twiddles.
+        std::vector<u64> z((size_t)NLK * n), zsh((size_t)NLK * n);
+        std::vector<double> zf((size_t)NLK * n);
+        for (uint32_t i = 0; i < NLK; i++) {
+            const u64 q = c->mod[i];
+            const u64 psi = find_root_2n(q, n);
+            std::vector<u64> pw(n);
+            pw[0] = 1;
+            for (uint32_t t = 1; t < n; t++) pw[t] = mulmod(pw[t - 1], psi, q);
+            for (uint32_t r = 0; r < 256; r++)
+                for (uint32_t col = 0; col < 256; col++) {
+                    const uint64_t e = ((uint64_t)col * (1 + 2 * brv(r, 8))) % (2ull * n);  // psi^n = -1
+                    const u64 w = e < n ? pw[e] : q - pw[e - n];
+                    const size_t at = (size_t)i * n + r * 256 + col;
+                    z[at] = w;
+                    zsh[at] = shoup_of(w, q);
+                    zf[at] = (double)w;
+                }
+        }
+        c->d_z = c->alloc((size_t)NLK * n);
+        c->d_zsh = c->alloc((size_t)NLK * n);
+        c->d_zf = (double *)c->alloc((size_t)NLK * n);
+        if (!c->d_z || !c->d_zsh || !c->d_zf) HEC_FAIL(HEC_ENOMEM, "table allocation");
+        HEC_CHECK(upload(c->d_z, z.data(), z.size() * 8, c->st));
+        HEC_CHECK(upload(c->d_zsh, zsh.data(), zsh.size() * 8, c->st));
+        HEC_CHECK(upload(c->d_zf, zf.data(), zf.size() * 8, c->st));
+        // the host vectors go out of scope below: the copies must have finished
+        HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    }
 
     // limb -> prime maps: identity, then QP_l = q_0..q_l, p_0..p_{k-1} per level
     std::vector<u32> maps;
@@ -399,6 +439,9 @@ static hec_status build_tables(hec_ctx *c)
     c->T.itw_sh = c->d_itwsh;
     c->T.twf = c->d_twf;
     c->T.itwf = c->d_itwf;
+    c->T.z = c->d_z;
+    c->T.z_sh = c->d_zsh;
+    c->T.zf = c->d_zf;
     c->T.fp_on = 1;
     HEC_TRY_HIP(hipStreamSynchronize(c->st));
     return HEC_OK;
@@ -486,6 +529,7 @@ hec_status ctx_lane_create(hec_ctx *parent, hec_ctx **out)
     c->d_pc = parent->d_pc;
     c->d_tw = parent->d_tw; c->d_twsh = parent->d_twsh; c->d_itw = parent->d_itw; c->d_itwsh = parent->d_itwsh;
     c->d_twf = parent->d_twf; c->d_itwf = parent->d_itwf;
+    c->d_z = parent->d_z; c->d_zsh = parent->d_zsh; c->d_zf = parent->d_zf;
     c->d_maps = parent->d_maps;
     c->qp_off = parent->qp_off;
     c->d_modup = parent->d_modup; c->d_moddown = parent->d_moddown; c->d_lvl = parent->d_lvl;

@@ -97,6 +97,8 @@ struct hec_ctx {
     PrimeC *d_pc = nullptr;
     u64 *d_tw = nullptr, *d_twsh = nullptr, *d_itw = nullptr, *d_itwsh = nullptr;
     double2 *d_twf = nullptr, *d_itwf = nullptr;
+    u64 *d_z = nullptr, *d_zsh = nullptr;  // forward row-pass twists (n = 2^16)
+    double *d_zf = nullptr;
     u32 *d_maps = nullptr;           // identity map (NLK) followed by QP maps of every level
     std::vector<size_t> qp_off;      // offset of level l's QP map in d_maps
     BconvDesc *d_modup = nullptr;    // [level][digit]

@@ -156,6 +156,37 @@ DEV void mac(acc128 &acc, u64 a, u64 b)
     acc.lo += lo;
     acc.hi += hi + (acc.lo < lo ? 1 : 0);
 }
+// Sums of up to 16 products a_i b_i with a_i, b_i < 2^60 (every prime here
+// has at most 60 bits), exact, without a carry per product: each factor is
+// split into 30-bit halves and the four partial products (each below 2^60) go
+// to four 64-bit accumulators, which 16 of them cannot overflow.  One
+// 32 x 32 -> 64 multiply-add per partial product; the 128-bit total is
+// assembled once.  Same integer as the acc128 sum, so the same reduction.
+struct acc30 {
+    u64 s00, s01, s10, s11;
+};
+#define M30 0x3fffffffu
+DEV u64 split30(u64 x) { return (u64)((u32)x & M30) | ((x >> 30) << 32); }  // (low 30 bits, high bits) as (lo, hi) words
+DEV void mac30(acc30 &s, u64 a, u64 b)  // a, b as split30 gives them
+{
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+    s.s00 += (u64)a0 * b0;
+    s.s01 += (u64)a0 * b1;
+    s.s10 += (u64)a1 * b0;
+    s.s11 += (u64)a1 * b1;
+}
+// hi:lo = s00 + (s01 + s10) 2^30 + s11 2^60
+DEV void acc30_total(const acc30 &s, u64 &lo, u64 &hi)
+{
+    const u64 m = s.s01 + s.s10;
+    const u64 mc = m < s.s01 ? 1 : 0;  // the carry of m, weight 2^94
+    const u64 t = m << 30;
+    lo = s.s00 + t;
+    hi = (m >> 34) + (mc << 30) + (lo < t ? 1 : 0);
+    const u64 t2 = s.s11 << 60;
+    lo += t2;
+    hi += (s.s11 >> 4) + (lo < t2 ? 1 : 0);
+}
 DEV u32 brev_bits(u32 x, u32 bits) { return __brev(x) >> (32 - bits); }
 // Evaluation-form index of sigma_g: slot k holds a(psi^(2 brv(k) + 1));
 // sigma_g(a) at that root is a(psi^((2 brv(k)+1) g)).
@@ -333,18 +364,22 @@ DEV u64 reduce4(u64 x, u64 q)
 struct ArInt {
     typedef u64 V;
     u64 q, q2;
-    const u64 *w, *ws;
+    const u64 *w, *ws;  // twiddles psi^(+-brv(k)) (for the row pass: the first 128, staged in LDS)
+    const u64 *z, *zs;  // row-pass twists
     DEV V in(u64 r) const { return r; }
     DEV V mid_in(u64 b) const { return b; }
     DEV u64 mid_out(V x) const { return x; }
     DEV void ct(V &x, V &y, u32 idx) const { ct_bfly(x, y, w[idx], ws[idx], q2, q); }
     DEV void gs(V &x, V &y, u32 idx) const { gs_bfly(x, y, w[idx], ws[idx], q2, q); }
+    DEV V twist(V x, u32 k) const { return shoup_lazy(x, z[k], zs[k], q); }  // [0, 2q)
     DEV u64 full(V x) const { return reduce4(x, q); }  // [0, 4q) -> [0, q)
 };
 struct ArFp {
     typedef double V;
     double q, q2;
-    const double2 *t;  // (w, fl(w / q))
+    const double2 *t;  // (w, fl(w / q)) (for the forward row pass: the first 128, staged in LDS)
+    const double *tz;  // forward row-pass twists (words; their quotients by q rebuilt below)
+    double qi;         // fl(1 / q)
     DEV V in(u64 r) const { return (double)r; }
     DEV V mid_in(u64 b) const { return __longlong_as_double((long long)b); }
     DEV u64 mid_out(V x) const { return (u64)__double_as_longlong(x); }
@@ -372,6 +407,18 @@ struct ArFp {
         x = s >= q2 ? s - q2 : s;
         y = mulmod(u - v + q2, tw.x, tw.y);
     }
+    // x z_k, [0, 2q).  The quotient z / q is rebuilt from fl(1 / q) by one
+    // residual step, e = z - fl(z / q)' q exactly (fma) and the quotient
+    // corrected by e / q: within half an ulp plus 2^-104 relative of z / q,
+    // inside what mulmod needs (its estimate of y z / q stays within 1 of the
+    // truth for y < 4q < 2^52).
+    DEV V twist(V x, u32 k) const
+    {
+        const double w = tz[k];
+        const double w0 = w * qi;
+        const double wq = fma(fma(-w0, q, w), qi, w0);
+        return mulmod(x, w, wq);
+    }
     DEV u64 full(V x) const
     {
         x = x >= q2 ? x - q2 : x;
@@ -386,6 +433,7 @@ DEV ArInt ar_int(const PrimeC &pc, const u64 *w, const u64 *ws, u32 pi)
     a.q2 = 2 * pc.q;
     a.w = w + ((size_t)pi << 16);
     a.ws = ws + ((size_t)pi << 16);
+    a.z = a.zs = nullptr;  // no twist outside the forward row pass
     return a;
 }
 DEV ArFp ar_fp(const PrimeC &pc, const double2 *t, u32 pi)
@@ -394,9 +442,73 @@ DEV ArFp ar_fp(const PrimeC &pc, const double2 *t, u32 pi)
     a.q = pc.qd;
     a.q2 = 2.0 * pc.qd;
     a.t = t + ((size_t)pi << 16);
+    a.tz = nullptr;  // no twist outside the forward row pass
+    a.qi = pc.qinv_d;
+    return a;
+}
+// the forward row pass's arithmetic: the twiddles psi^brv(t), t < 128, from
+// their LDS copy bt (stage_row_twiddles), the twists of prime pi from HBM
+DEV ArInt ar_int_rows(const PrimeC &pc, const u64 *bt, const u64 *z, const u64 *zs, u32 pi)
+{
+    ArInt a;
+    a.q = pc.q;
+    a.q2 = 2 * pc.q;
+    a.w = bt;
+    a.ws = bt + 128;
+    a.z = z + ((size_t)pi << 16);
+    a.zs = zs + ((size_t)pi << 16);
+    return a;
+}
+DEV ArFp ar_fp_rows(const PrimeC &pc, const double2 *bt, const double *zf, u32 pi)
+{
+    ArFp a;
+    a.q = pc.qd;
+    a.q2 = 2.0 * pc.qd;
+    a.t = bt;
+    a.tz = zf + ((size_t)pi << 16);
+    a.qi = pc.qinv_d;
     return a;
 }
 DEV bool use_fp(const DevTables &T, const PrimeC &pc) { return T.fp_on && pc.fp && T.twf; }
+// the first CNT (<= 256) twiddles of prime pi in LDS (as (w, w / q) doubles,
+// or as CNT words followed by their Shoup companions), all lanes then
+// synchronized: the 128 of a forward row pass, the 256 of a column pass
+template <int CNT>
+DEV void stage_twiddles(bool fp, const u64 *w, const u64 *ws, const double2 *wf, u32 pi, double2 *bt)
+{
+    const u32 t = threadIdx.x;
+    if (t < CNT) {
+        const size_t at = ((size_t)pi << 16) + t;
+        if (fp) {
+            bt[t] = wf[at];
+        } else {
+            ((u64 *)bt)[t] = w[at];
+            ((u64 *)bt)[CNT + t] = ws[at];
+        }
+    }
+    __syncthreads();
+}
+// the column passes' arithmetic with the twiddles of their LDS copy
+DEV ArInt ar_int_lds(const PrimeC &pc, const u64 *bt, u32 cnt)
+{
+    ArInt a;
+    a.q = pc.q;
+    a.q2 = 2 * pc.q;
+    a.w = bt;
+    a.ws = bt + cnt;
+    a.z = a.zs = nullptr;
+    return a;
+}
+DEV ArFp ar_fp_lds(const PrimeC &pc, const double2 *bt)
+{
+    ArFp a;
+    a.q = pc.qd;
+    a.q2 = 2.0 * pc.qd;
+    a.t = bt;
+    a.tz = nullptr;
+    a.qi = pc.qinv_d;
+    return a;
+}
 // the tables as a launch of the 2^16 transforms sees them: the double
 // butterflies on or off as the launch parameter says
 static DevTables tuned(const DevTables &T)
@@ -463,16 +575,20 @@ DEV void ntt16_fwd_cols_body(const Ar &ar, typename Ar::V *x, u64 *a, u64 *lds, 
 // (RS: the input is the centered dropped limb of a rescale, reduced mod this
 // limb's prime)
 template <bool RS>
-__global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[256 * 16];
+    __shared__ double2 bt[256];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
     const u64 q = pc.q;
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
     const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const bool fp = use_fp(T, pc);
+    stage_twiddles<256>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
     u64 r[16];
     if (RS) {
         const u64 ql = T.pc[f.level].q;
@@ -491,14 +607,14 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_cols(u64 *base, size_t poly_s
 #pragma unroll
         for (int h = 0; h < 16; h++) r[h] = a[(size_t)(l + 16 * h) * 256 + col];
     }
-    if (use_fp(T, pc)) {
-        const ArFp ar = ar_fp(pc, T.twf, pi);
+    if (fp) {
+        const ArFp ar = ar_fp_lds(pc, bt);
         double x[16];
 #pragma unroll
         for (int h = 0; h < 16; h++) x[h] = ar.in(r[h]);
         ntt16_fwd_cols_body(ar, x, a, lds, col, l);
     } else {
-        ntt16_fwd_cols_body(ar_int(pc, T.tw, T.tw_sh, pi), r, a, lds, col, l);
+        ntt16_fwd_cols_body(ar_int_lds(pc, (const u64 *)bt, 256), r, a, lds, col, l);
     }
 }
 
@@ -510,14 +626,16 @@ DEV void ntt16_fwd_rows_core(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 
 {
     typedef typename Ar::V V;
     V x[16];
+    // the row's twist R^c first (column c = l + 16 h); then the butterflies of
+    // group t of every stage take the row-independent twiddle psi^brv16(t)
 #pragma unroll
-    for (int h = 0; h < 16; h++) x[h] = ar.mid_in(a[row * 256 + l + 16 * h]);
+    for (int h = 0; h < 16; h++) x[h] = ar.twist(ar.mid_in(a[row * 256 + l + 16 * h]), grow * 256 + l + 16 * h);
 #pragma unroll
     for (int s2 = 0; s2 < 4; s2++) {
         const int half = 8 >> s2;
 #pragma unroll
         for (int h = 0; h < 16; h++)
-            if (!(h & half)) ar.ct(x[h], x[h + half], (256u << s2) + (grow << s2) + (h >> (4 - s2)));
+            if (!(h & half)) ar.ct(x[h], x[h + half], h >> (4 - s2));
     }
 #pragma unroll
     for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = ar.mid_out(x[h]);
@@ -530,26 +648,31 @@ DEV void ntt16_fwd_rows_core(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 
         const int half = 128 >> s2;
 #pragma unroll
         for (int i = 0; i < 16; i++)
-            if (!(i & half)) ar.ct(x[i], x[i + half], (256u << s2) + (grow << s2) + ((16 * hb + i) >> (8 - s2)));
+            if (!(i & half)) ar.ct(x[i], x[i + half], (16 * hb + i) >> (8 - s2));
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = ar.full(x[i]);
     __syncthreads();
 }
-DEV void ntt16_fwd_rows_body(const DevTables &T, const PrimeC &pc, u32 pi, const u64 *a, u64 *lr, u32 grow, u32 row,
-                             u32 l)
+// bt: 128 double2 of LDS for the staged twiddles
+DEV void ntt16_fwd_rows_body(const DevTables &T, const PrimeC &pc, u32 pi, const u64 *a, u64 *lr, double2 *bt,
+                             u32 grow, u32 row, u32 l)
 {
-    if (use_fp(T, pc)) ntt16_fwd_rows_core(ar_fp(pc, T.twf, pi), a, lr, grow, row, l);
-    else ntt16_fwd_rows_core(ar_int(pc, T.tw, T.tw_sh, pi), a, lr, grow, row, l);
+    const bool fp = use_fp(T, pc);
+    stage_twiddles<128>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
+    if (fp) ntt16_fwd_rows_core(ar_fp_rows(pc, bt, T.zf, pi), a, lr, grow, row, l);
+    else ntt16_fwd_rows_core(ar_int_rows(pc, (const u64 *)bt, T.z, T.z_sh, pi), a, lr, grow, row, l);
 }
 
 // forward row pass; fully reduced output (RS: written as (c - output) q_l^-1
 // to the rescaled polynomial)
 template <bool RS>
-__global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
+    __shared__ double2 bt[128];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
@@ -558,7 +681,7 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)r0 * 256;
     const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
     u64 *lr = lds + row * 272;
-    ntt16_fwd_rows_body(T, pc, pi, a, lr, r0 + row, row, l);
+    ntt16_fwd_rows_body(T, pc, pi, a, lr, bt, r0 + row, row, l);
     if (RS) {
         const size_t off = ((size_t)it.limb << 16) + (size_t)r0 * 256 + row * 256;
         const u64 *cp = f.c + it.poly * f.cs + off;
@@ -578,10 +701,12 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows(u64 *base, size_t poly_s
 // out = (e - NTT(y)) P^-1 (+ sigma_g(c0) on polynomial 0, + add), so NTT(y) is
 // never written back and read again.  Same residues as the row pass followed
 // by k_moddown_combine.
-__global__ void __launch_bounds__(256) k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 nqp, const u32 *pmap, u32 npolys,
-                                                           CombineBatch cb, const LevelC *lc, DevTables T)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 nqp, const u32 *pmap, u32 npolys, CombineBatch cb, const LevelC *lc,
+                    DevTables T)
 {
     __shared__ u64 lds[16 * 272];
+    __shared__ double2 bt[128];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
@@ -591,7 +716,7 @@ __global__ void __launch_bounds__(256) k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 n
     u64 *a = y + it.poly * ps + ((size_t)it.limb << 16) + (size_t)r0 * 256;
     const u32 row = threadIdx.x >> 4, l = threadIdx.x & 15;
     u64 *lr = lds + row * 272;
-    ntt16_fwd_rows_body(T, pc, pi, a, lr, r0 + row, row, l);
+    ntt16_fwd_rows_body(T, pc, pi, a, lr, bt, r0 + row, row, l);
     const u32 r = it.poly >> 1, p = it.poly & 1, i = it.limb;
     if (!cb.out[r]) return;  // a slot of the batch nobody asked for
     const u64 pinv = lc->pinv[i], pinv_sh = lc->pinv_sh[i];
@@ -1048,7 +1173,7 @@ __global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 d
     const u32 nout = d->nout, nin = d->nin;
     const u32 j0 = blockIdx.y * per;
     const u32 j1 = j0 + per < nout ? j0 + per : nout;
-    for (u32 e = threadIdx.x; e < nin * nout; e += BC_THREADS) hat[e] = d->hat_m[e];
+    for (u32 e = threadIdx.x; e < NIN * nout; e += BC_THREADS) hat[e] = e < nin * nout ? split30(d->hat_m[e]) : 0;
     for (u32 j = threadIdx.x; j < nout; j += BC_THREADS) {
         const PrimeC pc = T.pc[d->out_prime[j]];
         oq[j] = pc.q;
@@ -1061,6 +1186,8 @@ __global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 d
     if (t >= n || j0 >= nout) return;
     const u64 *s = src + (blockIdx.z / group) * sps;
     u64 *o = dst + blockIdx.z * dps;
+    // a_i in split form; rows past nin (a partial digit) are zero on both
+    // sides, so their products vanish without a branch
     u64 a[NIN];
 #pragma unroll
     for (int i = 0; i < NIN; i++) {
@@ -1069,15 +1196,16 @@ __global__ void __launch_bounds__(BC_THREADS) k_bconv(const BconvDesc *dd, u32 d
             const u64 x = s[(size_t)d->in_pos[i] * n + t];
             if (copy_in && blockIdx.y == 0) o[(size_t)d->in_pos[i] * n + t] = x;
             const u64 q = T.pc[d->in_prime[i]].q;
-            a[i] = shoup_mul(x, d->inv_hat[i], d->inv_hat_sh[i], q);
+            a[i] = split30(shoup_mul(x, d->inv_hat[i], d->inv_hat_sh[i], q));
         }
     }
     for (u32 j = j0; j < j1; j++) {
-        acc128 acc = {0, 0};
+        acc30 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < NIN; i++)
-            if ((u32)i < nin) mac(acc, a[i], hat[i * nout + j]);
-        o[(size_t)opos[j] * n + t] = redc(acc.hi, acc.lo, oq[j], oqi[j]);
+        for (int i = 0; i < NIN; i++) mac30(acc, a[i], hat[i * nout + j]);
+        u64 lo, hi;
+        acc30_total(acc, lo, hi);
+        o[(size_t)opos[j] * n + t] = redc(hi, lo, oq[j], oqi[j]);
     }
 }
 template <int NIN>
@@ -1147,11 +1275,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *
     const size_t n = T.n;
     const u64 *key = kb.key[r];
     const u64 *Dr = kb.D[r] ? kb.D[r] : D;
+    // the key is streamed once (non-temporal, so that it does not evict from
+    // L2 the hoisted digits that every rotation of the launch reads again)
     acc128 a0 = {0, 0}, a1 = {0, 0};
     for (u32 j = 0; j < beta; j++) {
         u64 d = Dr[((size_t)j * nqp + o) * n + src];
-        mac(a0, d, key[(((size_t)j * 2 + 0) * NLK + pi) * n + k]);
-        mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
+        mac(a0, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k));
+        mac(a1, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k));
     }
     u64 *out = kb.out[r];
     out[(size_t)o * n + k] = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
@@ -1195,8 +1325,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner_multi(KsMulti kb, const
     if (BETA) {
 #pragma unroll
         for (int j = 0; j < BETA; j++) {
-            kb0[j] = key[(((size_t)j * 2 + 0) * NLK + pi) * n + k];
-            kb1[j] = key[(((size_t)j * 2 + 1) * NLK + pi) * n + k];
+            kb0[j] = __builtin_nontemporal_load(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k);
+            kb1[j] = __builtin_nontemporal_load(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k);
         }
     }
     for (u32 u = 0; u < S; u++) {
