@@ -37,20 +37,22 @@ def eprint(*a):
 #    is one limb (2^16 words = 512 KiB) moved to or from HBM, counting every key,
 #    plaintext and accumulator limb once and the hoisted digits and the input
 #    ciphertext once per launch.  Bound: HBM, 8 TB/s.
-#  * batched / plain (modes 0, 1): the row pass of the 2^16 forward NTT.  One
-#    unit = one limb, 8 butterfly stages x 2^15 butterflies (one modular
-#    multiplication each), 2 x 512 KiB moved.  Bound: the VALU.  256 CUs x 64
-#    lanes x 2.4 GHz = 39.3 T lane-instructions/s (the fp64 FMA rate, 78.6
-#    TFLOP/s / 2; 64-bit integer multiply-add issues at the same rate on gfx950);
-#    a 64-bit Shoup modular multiplication needs 10 integer multiply
-#    instructions -> 3.93 T modmul/s.
+#  * batched / plain / key-stationary (modes 0, 1, 4): the row pass of the 2^16
+#    forward NTT (k_ntt16_fwd_rows; mostly its ModDown form, whose epilogue
+#    finishes the rotation).  Unit: one limb moved -- per transformed limb the
+#    limb read and, in the ModDown form, the key-switch product read, sigma_g(c0)
+#    read (first polynomial) and the rotated limb written; the twiddle and twist
+#    tables are constants and not counted.  At 2^18 butterflies of ~17 VALU
+#    instructions per 1-2 MiB moved it issues 2.4-4.3 instructions per byte,
+#    below the chip's ridge of 39.3 T lane-instructions/s / 8 TB/s = 4.9: its
+#    roof is HBM, 8 TB/s.
 LIMB_BYTES = 8 << LOGN
 KERNELS = {
     "k_ks_mac": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                  "bytes_per_unit": LIMB_BYTES,
                  "traffic_file": os.path.join(ROOT, "profiles", "ks_mac_2e16_traffic.txt")},
-    "k_ntt16_fwd_rows": {"bound": "alu", "unit": "Tmodmul/s", "peak": 256 * 64 * 2.4e9 / 10 / 1e12,
-                         "per_unit": 8 * (1 << 15) / 1e12, "bytes_per_unit": 2 * LIMB_BYTES,
+    "k_ntt16_fwd_rows": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
+                         "bytes_per_unit": LIMB_BYTES,
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
 }
 DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac", 4: "k_ntt16_fwd_rows"}

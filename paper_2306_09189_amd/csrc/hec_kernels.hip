@@ -166,7 +166,8 @@ struct acc30 {
     u64 s00, s01, s10, s11;
 };
 #define M30 0x3fffffffu
-DEV u64 split30(u64 x) { return (u64)((u32)x & M30) | ((x >> 30) << 32); }  // (low 30 bits, high bits) as (lo, hi) words
+// x < 2^60 as the words (low 30 bits, high 30 bits)
+DEV u64 split30(u64 x) { return (u64)((u32)x & M30) | ((x >> 30) << 32); }
 DEV void mac30(acc30 &s, u64 a, u64 b)  // a, b as split30 gives them
 {
     const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
@@ -881,8 +882,9 @@ static void ntt_launch_one(const DevTables &T, bool inv, u64 *base, size_t poly_
         if (!inv) {
             KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
                     np, RescaleFuse{}, tuned(T));
-            KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
-                    np, RescaleFuse{}, tuned(T));
+            // units of the row pass: 2^16-word limbs read or written (here one of each per limb)
+            KLAUNCH("k_ntt16_fwd_rows", 2 * limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride,
+                    pmap, np, RescaleFuse{}, tuned(T));
         } else {
             KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
                     np, nullptr, (size_t)0, tuned(T));
@@ -934,7 +936,13 @@ bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, 
     dim3 g((u32)(16 * limbs));
     KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, y, (size_t)nq << 16, pmap, np,
             RescaleFuse{}, tuned(T));
-    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np, cb,
+    // limbs moved: y read; for every entry asked for, e read and the output written, sigma_g(c0)
+    // read on polynomial 0 and the added polynomials read
+    uint64_t units = 0;
+    for (int r = 0; r < nrot; r++)
+        for (int p = 0; p < 2; p++)
+            units += (uint64_t)nq * (cb.out[r] ? 3 + (p == 0 && cb.c0[r] ? 1 : 0) + (cb.add[r][p] ? 1 : 0) : 1);
+    KLAUNCH("k_ntt16_fwd_rows", units, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np, cb,
             lc, tuned(T));
     return true;
 }
@@ -948,7 +956,9 @@ bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pm
     const size_t ps = (size_t)l << 16;
     const u32 np = (u32)npolys;
     KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, tuned(T));
-    KLAUNCH("k_ntt16_fwd_rows", limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, tuned(T));
+    // limbs moved: the transformed limb and c read, the rescaled limb written
+    KLAUNCH("k_ntt16_fwd_rows", 3 * limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f,
+            tuned(T));
     return true;
 }
 void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,
@@ -1857,41 +1867,71 @@ bool hec_ks_mac_shards(const DevTables &T, const KsMacBatch &b, int nterms, int 
 // products of all terms for up to HEC_MAC_OUTS outputs accumulated in 128 bits
 // (< HEC_MAC_TERMS q^2 < q 2^64) and reduced once, so every rotated input is
 // read once per group of outputs.
+// NOUT: outputs the accumulators are sized for (>= nout).  Up to four
+// outputs the products are summed by 30-bit halves (acc30: four
+// multiply-adds and no carry per product); eight keep the 128-bit form, whose
+// accumulators take half the registers.  Same integer sums, same residues.
+template <int NOUT>
 __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms, u32 nout, u32 nq, u32 first,
                                                           DevTables T)
 {
+    constexpr bool SPLIT = NOUT <= 4;
     const u32 o = blockIdx.y;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (k >= T.n) return;
     const PrimeC pc = T.pc[o];
     const size_t n = T.n, off = (size_t)o * n + k;
-    acc128 acc[HEC_MAC_OUTS][2];
+    acc30 s[SPLIT ? NOUT : 1][2];
+    acc128 acc[SPLIT ? 1 : NOUT][2];
 #pragma unroll
-    for (int v = 0; v < HEC_MAC_OUTS; v++) acc[v][0] = acc[v][1] = acc128{0, 0};
+    for (int v = 0; v < (SPLIT ? NOUT : 1); v++) s[v][0] = s[v][1] = acc30{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < (SPLIT ? 1 : NOUT); v++) acc[v][0] = acc[v][1] = acc128{0, 0};
     for (u32 t = 0; t < nterms; t++) {
         const u64 *ct = b.ct[t];
         const u64 c0 = ct[off], c1 = ct[(size_t)nq * n + off];
+        const u64 c0s = split30(c0), c1s = split30(c1);
 #pragma unroll
-        for (int v = 0; v < HEC_MAC_OUTS; v++) {
+        for (int v = 0; v < NOUT; v++) {
             const u64 *pt = b.pt[t][v];
             if (!pt) continue;
             const u64 m = pt[off];
-            mac(acc[v][0], c0, m);
-            mac(acc[v][1], c1, m);
+            if (SPLIT) {
+                const u64 ms = split30(m);
+                mac30(s[SPLIT ? v : 0][0], c0s, ms);
+                mac30(s[SPLIT ? v : 0][1], c1s, ms);
+            } else {
+                mac(acc[SPLIT ? 0 : v][0], c0, m);
+                mac(acc[SPLIT ? 0 : v][1], c1, m);
+            }
         }
     }
 #pragma unroll
-    for (int v = 0; v < HEC_MAC_OUTS; v++) {
+    for (int v = 0; v < NOUT; v++) {
         u64 *out = b.out[v];
         if ((u32)v >= nout || !out) continue;
 #pragma unroll
         for (int p = 0; p < 2; p++) {
             u64 *dst = out + (size_t)p * nq * n + off;
-            u64 r = redc(acc[v][p].hi, acc[v][p].lo, pc.q, pc.qinv_neg);
+            u64 lo, hi;
+            if (SPLIT) {
+                acc30_total(s[SPLIT ? v : 0][p], lo, hi);
+            } else {
+                lo = acc[SPLIT ? 0 : v][p].lo;
+                hi = acc[SPLIT ? 0 : v][p].hi;
+            }
+            u64 r = redc(hi, lo, pc.q, pc.qinv_neg);
             if (!((first >> v) & 1)) r = add_mod(r, *dst, pc.q);
             *dst = r;
         }
     }
+}
+template <int NOUT>
+static void mac_terms_launch(dim3 g, hipStream_t st, const MacBatch &b, int nterms, int nout, int nq, int first,
+                             const DevTables &T)
+{
+    KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms<NOUT>, g, dim3(EW_THREADS), 0, st, b, (u32)nterms,
+            (u32)nout, (u32)nq, (u32)first, T);
 }
 // the same with basis-mask plaintexts: pt[t][v] points at the nb signed weights of (term t, output v)
 __global__ void __launch_bounds__(EW_THREADS) k_mac_terms_basis(MacBatch b, BasisArg ba, u32 nterms, u32 nout, u32 nq,
@@ -1937,9 +1977,14 @@ bool hec_mac_terms(const DevTables &T, const MacBatch &b, int nterms, int nout, 
     if (ba)
         KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms_basis, g, dim3(EW_THREADS), 0, st, b, *ba,
                 (u32)nterms, (u32)nout, (u32)nq, (u32)first, T);
+    else if (nout == 1)
+        mac_terms_launch<1>(g, st, b, nterms, nout, nq, first, T);
+    else if (nout == 2)
+        mac_terms_launch<2>(g, st, b, nterms, nout, nq, first, T);
+    else if (nout <= 4)
+        mac_terms_launch<4>(g, st, b, nterms, nout, nq, first, T);
     else
-        KLAUNCH("k_mac_terms", (uint64_t)nq * nterms, k_mac_terms, g, dim3(EW_THREADS), 0, st, b, (u32)nterms,
-                (u32)nout, (u32)nq, (u32)first, T);
+        mac_terms_launch<HEC_MAC_OUTS>(g, st, b, nterms, nout, nq, first, T);
     return true;
 }
 
