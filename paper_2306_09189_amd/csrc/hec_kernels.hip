@@ -1311,14 +1311,19 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 // coefficient of the term's key limbs once into registers and loops over the
 // inputs, so a key is read from HBM once per launch instead of once per input.
 // Same accumulation as k_ks_inner (digits in order, one reduction), so the
-// same residues.  Flat XCD-aware grid over (limb, rotation, chunk).
+// same residues.  Flat grid over (limb, rotation, chunk) in plain order:
+// workgroups are dealt to the 8 XCDs round-robin, so all of them work on the
+// same limb at a time and the digits of that limb for every input (beta limbs
+// per input, 48 MiB for 32 inputs -- beyond one XCD's L2) are read from HBM
+// once and by the other rotations of the launch from the shared last-level
+// cache.  (k_ks_inner, whose limb's digits fit one L2, walks one contiguous
+// run of items per XCD instead.)
 template <int BETA>
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner_multi(KsMulti kb, const u64 *D, size_t dstride, u32 S,
                                                                size_t estride, u32 beta_rt, u32 nqp, const u32 *pmap,
                                                                u32 NLK, u32 nrot, u32 nchunks, DevTables T)
 {
-    const u32 w = blockIdx.x, total = gridDim.x;
-    const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
+    const u32 i = blockIdx.x;
     const u32 chunk = i % nchunks, rest = i / nchunks;
     const u32 r = rest % nrot, o = rest / nrot;
     const u32 k = chunk * EW_THREADS + threadIdx.x;
@@ -1357,9 +1362,11 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner_multi(KsMulti kb, const
                 mac(a1, d, key[(((size_t)j * 2 + 1) * NLK + pi) * n + k]);
             }
         }
+        // written past the caches: 2 limbs per input and rotation, read back
+        // only by the ModDowns after the launch
         u64 *e = out + (size_t)u * estride;
-        e[(size_t)o * n + k] = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
-        e[((size_t)nqp + o) * n + k] = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+        __builtin_nontemporal_store(redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), e + (size_t)o * n + k);
+        __builtin_nontemporal_store(redc(a1.hi, a1.lo, pc.q, pc.qinv_neg), e + ((size_t)nqp + o) * n + k);
     }
 }
 template <int BETA>
