@@ -271,6 +271,8 @@ def main():
     ap.add_argument("--mode", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="plan mode of the timed step: 0 batched (complete key-switched rotations), 1 plain, "
                          "2 lazy ModDown, 3 baby-step/giant-step with double hoisting, 4 key-stationary")
+    ap.add_argument("--tune", default="", help="launch parameters to set first, e.g. ntt_row_vals=16,ks_amounts=8 "
+                    "(every value gives the same ciphertexts)")
     ap.add_argument("--pmc-run", action="store_true", help="short workload for rocprofv3 --pmc passes")
     ap.add_argument("--profile-run", choices=("gelu", "block", "imagenet", "rotations"),
                     help="for kernel traces: five degree-59 GELU evaluations, five runs of the 16x32x32 block, "
@@ -285,6 +287,9 @@ def main():
     import torch
     from paper_2306_09189_amd import hecnn
 
+    for kv in (x for x in args.tune.split(",") if x):
+        name, val = kv.split("=")
+        hecnn.tune_set(name.strip(), int(val))
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     ctx = hecnn.Context(LOGN, L, Q0, QB, K, PB, DNUM, LOG_SCALE, device=0, stream=stream.cuda_stream)

@@ -392,6 +392,9 @@ void hec_batch_free(hec_batch *batch);
  *   ntt_fp64     1 | 0         in the radix-16 form, the limbs of primes below
  *                              2^50 with exact double butterflies (every value
  *                              an integer below 2^52), or 64-bit integers
+ *   ntt_row_vals 16 | 8        values per lane of the radix-16 form's forward
+ *                              row pass (16: 256 lanes per 16-row tile, radix
+ *                              16-16 rounds; 8: 512 lanes, radix 8-8-4)
  *   ntt_tile     2048 | 4096 | 8192   words per LDS tile of the radix-2 form
  *   ntt_group    0 | 64 | 256 | 1024  at most this many limbs per transform
  *                              launch (0: every limb of a batch in one launch)

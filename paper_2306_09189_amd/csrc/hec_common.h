@@ -144,6 +144,7 @@ struct TuneParams {
     int ks_rot_batch = 16; // rotations per key-switch launch of a hoisted set (1..HEC_KS_BATCH)
     int ks_amounts = 4;    // amounts per key-stationary launch over many inputs (1..HEC_KS_BATCH)
     int ntt_fp64 = 1;      // 2^16 transforms of primes below 2^50 with exact double butterflies (0: integers)
+    int ntt_row_vals = 16; // values per lane of the 2^16 forward row pass (16: 256 lanes per tile, 8: 512)
 };
 TuneParams &hec_tune_params();
 

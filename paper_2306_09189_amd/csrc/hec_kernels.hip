@@ -697,6 +697,126 @@ k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
     }
 }
 
+// Forward row pass with 8 values per lane: 512 lanes per 16-row tile, 32 per
+// row, radix-8, radix-8 and radix-4 rounds with two LDS exchanges.  Half the
+// registers of the 16-value form, so up to twice the waves per SIMD to cover
+// the memory latency.  Same butterflies (the twist, then twiddle psi^brv16(t)
+// for group t = c >> (8 - s) of stage 8 + s), same residues.  Leaves the fully
+// reduced values of columns 4 (l + 32 g) + i (g < 2, i < 4) in y[4 g + i].
+template <class Ar>
+DEV void ntt16_fwd_rows_core8(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 l, u64 *y)
+{
+    typedef typename Ar::V V;
+    V x[8];
+#pragma unroll
+    for (int h = 0; h < 8; h++) x[h] = ar.twist(ar.mid_in(a[l + 32 * h]), grow * 256 + l + 32 * h);
+#pragma unroll
+    for (int s2 = 0; s2 < 3; s2++) {  // columns l + 32 h
+        const int half = 4 >> s2;
+#pragma unroll
+        for (int h = 0; h < 8; h++)
+            if (!(h & half)) ar.ct(x[h], x[h + half], h >> (3 - s2));
+    }
+#pragma unroll
+    for (int h = 0; h < 8; h++) lr[N16_PAD(l + 32 * h)] = ar.mid_out(x[h]);
+    __syncthreads();
+    const u32 cb = 32 * (l >> 2) + (l & 3);  // columns cb + 4 j: each read by this lane alone,
+#pragma unroll                              // so it may overwrite them without a barrier
+    for (int j = 0; j < 8; j++) x[j] = ar.mid_in(lr[N16_PAD(cb + 4 * j)]);
+#pragma unroll
+    for (int s2 = 3; s2 < 6; s2++) {
+        const int half = 4 >> (s2 - 3);
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (!(j & half)) ar.ct(x[j], x[j + half], (cb + 4 * j) >> (8 - s2));
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) lr[N16_PAD(cb + 4 * j)] = ar.mid_out(x[j]);
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < 2; g++) {  // columns 4 m + i, m = l + 32 g
+        const u32 m = l + 32 * g;
+#pragma unroll
+        for (int i = 0; i < 4; i++) x[4 * g + i] = ar.mid_in(lr[N16_PAD(4 * m + i)]);
+        ar.ct(x[4 * g], x[4 * g + 2], m);
+        ar.ct(x[4 * g + 1], x[4 * g + 3], m);
+        ar.ct(x[4 * g], x[4 * g + 1], 2 * m);
+        ar.ct(x[4 * g + 2], x[4 * g + 3], 2 * m + 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++) y[k] = ar.full(x[k]);
+}
+DEV void ntt16_fwd_rows_body8(const DevTables &T, const PrimeC &pc, u32 pi, const u64 *a, u64 *lr, double2 *bt,
+                              u32 grow, u32 l, u64 *y)
+{
+    const bool fp = use_fp(T, pc);
+    stage_twiddles<128>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
+    if (fp) ntt16_fwd_rows_core8(ar_fp_rows(pc, bt, T.zf, pi), a, lr, grow, l, y);
+    else ntt16_fwd_rows_core8(ar_int_rows(pc, (const u64 *)bt, T.z, T.z_sh, pi), a, lr, grow, l, y);
+}
+// column of value k of a lane in the 8-value row pass
+#define R8_COL(l, k) (4 * ((l) + 32 * ((k) >> 2)) + ((k) & 3))
+
+template <bool RS>
+__global__ void __launch_bounds__(512) k_ntt16_fwd_rows8(u64 *base, size_t poly_stride, const u32 *pmap,
+                                                         u32 npolys, RescaleFuse f, DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    __shared__ double2 bt[128];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q;
+    const u32 r0 = it.tile * 16;
+    const u32 row = threadIdx.x >> 5, l = threadIdx.x & 31;
+    u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + (size_t)(r0 + row) * 256;
+    u64 y[8];
+    ntt16_fwd_rows_body8(T, pc, pi, a, lds + row * 272, bt, r0 + row, l, y);
+    if (RS) {
+        const size_t off = ((size_t)it.limb << 16) + (size_t)(r0 + row) * 256;
+        const u64 *cp = f.c + it.poly * f.cs + off;
+        u64 *op = f.out + it.poly * f.os + off;
+        const u64 qi = f.lc->qlinv[it.limb], qis = f.lc->qlinv_sh[it.limb];
+#pragma unroll
+        for (int k = 0; k < 8; k++) op[R8_COL(l, k)] = shoup_mul(sub_mod(cp[R8_COL(l, k)], y[k], q), qi, qis, q);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k++) a[R8_COL(l, k)] = y[k];
+    }
+}
+__global__ void __launch_bounds__(512) k_ntt16_fwd_rows8_md(u64 *yb, u32 nq, u32 nqp, const u32 *pmap, u32 npolys,
+                                                            CombineBatch cb, const LevelC *lc, DevTables T)
+{
+    __shared__ u64 lds[16 * 272];
+    __shared__ double2 bt[128];
+    const Ntt16Item it = ntt16_item(npolys);
+    const u32 pi = pmap[it.limb];
+    const PrimeC pc = T.pc[pi];
+    const u64 q = pc.q;
+    const u32 r0 = it.tile * 16;
+    const u32 row = threadIdx.x >> 5, l = threadIdx.x & 31;
+    const size_t ps = (size_t)nq << 16;
+    const u64 *a = yb + it.poly * ps + ((size_t)it.limb << 16) + (size_t)(r0 + row) * 256;
+    u64 y[8];
+    ntt16_fwd_rows_body8(T, pc, pi, a, lds + row * 272, bt, r0 + row, l, y);
+    const u32 r = it.poly >> 1, p = it.poly & 1, i = it.limb;
+    if (!cb.out[r]) return;  // a slot of the batch nobody asked for
+    const u64 pinv = lc->pinv[i], pinv_sh = lc->pinv_sh[i];
+    const size_t ro = (size_t)(r0 + row) * 256;
+    const u64 *e = cb.e[r] + ((size_t)p * nqp + i) * 65536 + ro;
+    u64 *out = cb.out[r] + ((size_t)p * nq + i) * 65536 + ro;
+    const u64 *c0 = (p == 0 && cb.c0[r]) ? cb.c0[r] + (size_t)i * 65536 : nullptr;
+    const u64 *ad = cb.add[r][p] ? cb.add[r][p] + (size_t)i * 65536 + ro : nullptr;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const u32 c = R8_COL(l, k);
+        u64 v = shoup_mul(sub_mod(e[c], y[k], q), pinv, pinv_sh, q);
+        if (c0) v = add_mod(v, c0[auto_src((u32)ro + c, cb.g[r], 16)], q);
+        if (ad) v = add_mod(v, ad[c], q);
+        out[c] = v;
+    }
+}
+
 // forward row pass of the P -> Q conversion y of a batch of ModDowns (poly z
 // = entry z / 2, polynomial z % 2) with the ModDown tail as its epilogue:
 // out = (e - NTT(y)) P^-1 (+ sigma_g(c0) on polynomial 0, + add), so NTT(y) is
@@ -883,8 +1003,12 @@ static void ntt_launch_one(const DevTables &T, bool inv, u64 *base, size_t poly_
             KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
                     np, RescaleFuse{}, tuned(T));
             // units of the row pass: 2^16-word limbs read or written (here one of each per limb)
-            KLAUNCH("k_ntt16_fwd_rows", 2 * limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base, poly_stride,
-                    pmap, np, RescaleFuse{}, tuned(T));
+            if (tp.ntt_row_vals == 8)
+                KLAUNCH("k_ntt16_fwd_rows", 2 * limbs, k_ntt16_fwd_rows8<false>, g, dim3(512), 0, st, base,
+                        poly_stride, pmap, np, RescaleFuse{}, tuned(T));
+            else
+                KLAUNCH("k_ntt16_fwd_rows", 2 * limbs, k_ntt16_fwd_rows<false>, g, dim3(256), 0, st, base,
+                        poly_stride, pmap, np, RescaleFuse{}, tuned(T));
         } else {
             KLAUNCH("k_ntt16_inv_rows", limbs, k_ntt16_inv_rows<false>, g, dim3(256), 0, st, base, poly_stride, pmap,
                     np, nullptr, (size_t)0, tuned(T));
@@ -942,8 +1066,12 @@ bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, 
     for (int r = 0; r < nrot; r++)
         for (int p = 0; p < 2; p++)
             units += (uint64_t)nq * (cb.out[r] ? 3 + (p == 0 && cb.c0[r] ? 1 : 0) + (cb.add[r][p] ? 1 : 0) : 1);
-    KLAUNCH("k_ntt16_fwd_rows", units, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np, cb,
-            lc, tuned(T));
+    if (hec_tune_params().ntt_row_vals == 8)
+        KLAUNCH("k_ntt16_fwd_rows", units, k_ntt16_fwd_rows8_md, g, dim3(512), 0, st, y, (u32)nq, (u32)nqp, pmap, np,
+                cb, lc, tuned(T));
+    else
+        KLAUNCH("k_ntt16_fwd_rows", units, k_ntt16_fwd_rows_md, g, dim3(256), 0, st, y, (u32)nq, (u32)nqp, pmap, np,
+                cb, lc, tuned(T));
     return true;
 }
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
@@ -957,8 +1085,12 @@ bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pm
     const u32 np = (u32)npolys;
     KLAUNCH("k_ntt16_fwd_cols", limbs, k_ntt16_fwd_cols<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f, tuned(T));
     // limbs moved: the transformed limb and c read, the rescaled limb written
-    KLAUNCH("k_ntt16_fwd_rows", 3 * limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f,
-            tuned(T));
+    if (hec_tune_params().ntt_row_vals == 8)
+        KLAUNCH("k_ntt16_fwd_rows", 3 * limbs, k_ntt16_fwd_rows8<true>, g, dim3(512), 0, st, tmp, ps, pmap, np, f,
+                tuned(T));
+    else
+        KLAUNCH("k_ntt16_fwd_rows", 3 * limbs, k_ntt16_fwd_rows<true>, g, dim3(256), 0, st, tmp, ps, pmap, np, f,
+                tuned(T));
     return true;
 }
 void hec_ntt_fwd(const DevTables &T, u64 *base, size_t poly_stride, int npolys, const u32 *pmap, int nlimbs,

@@ -27,6 +27,7 @@ const std::vector<Tunable> &tunables()
     static const std::vector<Tunable> t = {
         {"ntt16_radix", &TuneParams::ntt16_radix, {16, 2}},
         {"ntt_fp64", &TuneParams::ntt_fp64, {1, 0}},
+        {"ntt_row_vals", &TuneParams::ntt_row_vals, {16, 8}},
         {"ntt_tile", &TuneParams::ntt_tile, {2048, 4096, 8192}},
         {"ntt_group", &TuneParams::ntt_group, {0, 64, 256, 1024}},
         {"ks_rot_batch", &TuneParams::ks_rot_batch, {4, 8, 16}},
