@@ -1425,9 +1425,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *
         mac(a0, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k));
         mac(a1, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k));
     }
+    // written past the caches too (read back by the ModDowns after the launch)
     u64 *out = kb.out[r];
-    out[(size_t)o * n + k] = redc(a0.hi, a0.lo, pc.q, pc.qinv_neg);
-    out[((size_t)nqp + o) * n + k] = redc(a1.hi, a1.lo, pc.q, pc.qinv_neg);
+    __builtin_nontemporal_store(redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), out + (size_t)o * n + k);
+    __builtin_nontemporal_store(redc(a1.hi, a1.lo, pc.q, pc.qinv_neg), out + ((size_t)nqp + o) * n + k);
 }
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
                   int NLK, hipStream_t st)
