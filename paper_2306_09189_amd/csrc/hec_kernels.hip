@@ -447,6 +447,11 @@ DEV ArFp ar_fp(const PrimeC &pc, const double2 *t, u32 pi)
     a.qi = pc.qinv_d;
     return a;
 }
+// LDS position of twiddle t in a row pass's table: one pad entry after every
+// 8, so that the lanes of a row, which read entries 2^(s-4) apart in the
+// second round of stage 8 + s, fall in different banks
+#define RPAD(t) ((t) + ((t) >> 3))
+#define RTAB 144  // entries of the padded table of 128
 // the forward row pass's arithmetic: the twiddles psi^brv(t), t < 128, from
 // their LDS copy bt (stage_row_twiddles), the twists of prime pi from HBM
 DEV ArInt ar_int_rows(const PrimeC &pc, const u64 *bt, const u64 *z, const u64 *zs, u32 pi)
@@ -455,7 +460,7 @@ DEV ArInt ar_int_rows(const PrimeC &pc, const u64 *bt, const u64 *z, const u64 *
     a.q = pc.q;
     a.q2 = 2 * pc.q;
     a.w = bt;
-    a.ws = bt + 128;
+    a.ws = bt + RTAB;
     a.z = z + ((size_t)pi << 16);
     a.zs = zs + ((size_t)pi << 16);
     return a;
@@ -472,19 +477,21 @@ DEV ArFp ar_fp_rows(const PrimeC &pc, const double2 *bt, const double *zf, u32 p
 }
 DEV bool use_fp(const DevTables &T, const PrimeC &pc) { return T.fp_on && pc.fp && T.twf; }
 // the first CNT (<= 256) twiddles of prime pi in LDS (as (w, w / q) doubles,
-// or as CNT words followed by their Shoup companions), all lanes then
-// synchronized: the 128 of a forward row pass, the 256 of a column pass
-template <int CNT>
+// or as words followed by their Shoup companions), all lanes then
+// synchronized: the 128 of a forward row pass (PAD: at RPAD(t), companions
+// from RTAB on), the 256 of a column pass (in order, companions from CNT on)
+template <int CNT, bool PAD>
 DEV void stage_twiddles(bool fp, const u64 *w, const u64 *ws, const double2 *wf, u32 pi, double2 *bt)
 {
     const u32 t = threadIdx.x;
     if (t < CNT) {
         const size_t at = ((size_t)pi << 16) + t;
+        const u32 pos = PAD ? RPAD(t) : t;
         if (fp) {
-            bt[t] = wf[at];
+            bt[pos] = wf[at];
         } else {
-            ((u64 *)bt)[t] = w[at];
-            ((u64 *)bt)[CNT + t] = ws[at];
+            ((u64 *)bt)[pos] = w[at];
+            ((u64 *)bt)[(PAD ? RTAB : CNT) + pos] = ws[at];
         }
     }
     __syncthreads();
@@ -589,7 +596,7 @@ k_ntt16_fwd_cols(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
     u64 *a = base + it.poly * poly_stride + ((size_t)it.limb << 16) + it.tile * 16;
     const u32 col = threadIdx.x & 15, l = threadIdx.x >> 4;
     const bool fp = use_fp(T, pc);
-    stage_twiddles<256>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
+    stage_twiddles<256, false>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
     u64 r[16];
     if (RS) {
         const u64 ql = T.pc[f.level].q;
@@ -636,7 +643,7 @@ DEV void ntt16_fwd_rows_core(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 
         const int half = 8 >> s2;
 #pragma unroll
         for (int h = 0; h < 16; h++)
-            if (!(h & half)) ar.ct(x[h], x[h + half], h >> (4 - s2));
+            if (!(h & half)) ar.ct(x[h], x[h + half], RPAD(h >> (4 - s2)));
     }
 #pragma unroll
     for (int h = 0; h < 16; h++) lr[N16_PAD(l + 16 * h)] = ar.mid_out(x[h]);
@@ -649,7 +656,7 @@ DEV void ntt16_fwd_rows_core(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32 
         const int half = 128 >> s2;
 #pragma unroll
         for (int i = 0; i < 16; i++)
-            if (!(i & half)) ar.ct(x[i], x[i + half], (16 * hb + i) >> (8 - s2));
+            if (!(i & half)) ar.ct(x[i], x[i + half], RPAD((16 * hb + i) >> (8 - s2)));
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) lr[N16_PAD(16 * hb + i)] = ar.full(x[i]);
@@ -660,7 +667,7 @@ DEV void ntt16_fwd_rows_body(const DevTables &T, const PrimeC &pc, u32 pi, const
                              u32 grow, u32 row, u32 l)
 {
     const bool fp = use_fp(T, pc);
-    stage_twiddles<128>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
+    stage_twiddles<128, true>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
     if (fp) ntt16_fwd_rows_core(ar_fp_rows(pc, bt, T.zf, pi), a, lr, grow, row, l);
     else ntt16_fwd_rows_core(ar_int_rows(pc, (const u64 *)bt, T.z, T.z_sh, pi), a, lr, grow, row, l);
 }
@@ -673,7 +680,7 @@ k_ntt16_fwd_rows(u64 *base, size_t poly_stride, const u32 *pmap, u32 npolys,
                                                         RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
-    __shared__ double2 bt[128];
+    __shared__ double2 bt[RTAB];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
@@ -715,7 +722,7 @@ DEV void ntt16_fwd_rows_core8(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32
         const int half = 4 >> s2;
 #pragma unroll
         for (int h = 0; h < 8; h++)
-            if (!(h & half)) ar.ct(x[h], x[h + half], h >> (3 - s2));
+            if (!(h & half)) ar.ct(x[h], x[h + half], RPAD(h >> (3 - s2)));
     }
 #pragma unroll
     for (int h = 0; h < 8; h++) lr[N16_PAD(l + 32 * h)] = ar.mid_out(x[h]);
@@ -728,7 +735,7 @@ DEV void ntt16_fwd_rows_core8(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32
         const int half = 4 >> (s2 - 3);
 #pragma unroll
         for (int j = 0; j < 8; j++)
-            if (!(j & half)) ar.ct(x[j], x[j + half], (cb + 4 * j) >> (8 - s2));
+            if (!(j & half)) ar.ct(x[j], x[j + half], RPAD((cb + 4 * j) >> (8 - s2)));
     }
 #pragma unroll
     for (int j = 0; j < 8; j++) lr[N16_PAD(cb + 4 * j)] = ar.mid_out(x[j]);
@@ -738,10 +745,10 @@ DEV void ntt16_fwd_rows_core8(const Ar &ar, const u64 *a, u64 *lr, u32 grow, u32
         const u32 m = l + 32 * g;
 #pragma unroll
         for (int i = 0; i < 4; i++) x[4 * g + i] = ar.mid_in(lr[N16_PAD(4 * m + i)]);
-        ar.ct(x[4 * g], x[4 * g + 2], m);
-        ar.ct(x[4 * g + 1], x[4 * g + 3], m);
-        ar.ct(x[4 * g], x[4 * g + 1], 2 * m);
-        ar.ct(x[4 * g + 2], x[4 * g + 3], 2 * m + 1);
+        ar.ct(x[4 * g], x[4 * g + 2], RPAD(m));
+        ar.ct(x[4 * g + 1], x[4 * g + 3], RPAD(m));
+        ar.ct(x[4 * g], x[4 * g + 1], RPAD(2 * m));
+        ar.ct(x[4 * g + 2], x[4 * g + 3], RPAD(2 * m + 1));
     }
 #pragma unroll
     for (int k = 0; k < 8; k++) y[k] = ar.full(x[k]);
@@ -750,7 +757,7 @@ DEV void ntt16_fwd_rows_body8(const DevTables &T, const PrimeC &pc, u32 pi, cons
                               u32 grow, u32 l, u64 *y)
 {
     const bool fp = use_fp(T, pc);
-    stage_twiddles<128>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
+    stage_twiddles<128, true>(fp, T.tw, T.tw_sh, T.twf, pi, bt);
     if (fp) ntt16_fwd_rows_core8(ar_fp_rows(pc, bt, T.zf, pi), a, lr, grow, l, y);
     else ntt16_fwd_rows_core8(ar_int_rows(pc, (const u64 *)bt, T.z, T.z_sh, pi), a, lr, grow, l, y);
 }
@@ -762,7 +769,7 @@ __global__ void __launch_bounds__(512) k_ntt16_fwd_rows8(u64 *base, size_t poly_
                                                          u32 npolys, RescaleFuse f, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
-    __shared__ double2 bt[128];
+    __shared__ double2 bt[RTAB];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
@@ -788,7 +795,7 @@ __global__ void __launch_bounds__(512) k_ntt16_fwd_rows8_md(u64 *yb, u32 nq, u32
                                                             CombineBatch cb, const LevelC *lc, DevTables T)
 {
     __shared__ u64 lds[16 * 272];
-    __shared__ double2 bt[128];
+    __shared__ double2 bt[RTAB];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
@@ -827,7 +834,7 @@ k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 nqp, const u32 *pmap, u32 npolys, Combin
                     DevTables T)
 {
     __shared__ u64 lds[16 * 272];
-    __shared__ double2 bt[128];
+    __shared__ double2 bt[RTAB];
     const Ntt16Item it = ntt16_item(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
