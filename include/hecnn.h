@@ -399,6 +399,9 @@ void hec_batch_free(hec_batch *batch);
  *   ntt_group    0 | 64 | 256 | 1024  at most this many limbs per transform
  *                              launch (0: every limb of a batch in one launch)
  *   ks_rot_batch 4 | 8 | 16    rotations per key-switch launch of a hoisted set
+ *   ks_overlap   0 | 1         a hoisted set's batches all on the context
+ *                              stream, or alternating between it and a second
+ *                              stream (forked and joined inside the call)
  *   ks_amounts   1 | 2 | 4 | 8 | 16   rotation amounts per key-stationary
  *                              launch (plan and pooling mode 4)
  * hec_tune_set rejects names and values outside these lists (HEC_EINVAL).

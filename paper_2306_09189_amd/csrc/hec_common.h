@@ -145,6 +145,7 @@ struct TuneParams {
     int ks_amounts = 4;    // amounts per key-stationary launch over many inputs (1..HEC_KS_BATCH)
     int ntt_fp64 = 1;      // 2^16 transforms of primes below 2^50 with exact double butterflies (0: integers)
     int ntt_row_vals = 16; // values per lane of the 2^16 forward row pass (16: 256 lanes per tile, 8: 512)
+    int ks_overlap = 0;    // hoisted rotation batches alternate between two streams (0: all on one)
 };
 TuneParams &hec_tune_params();
 

@@ -503,11 +503,43 @@ extern "C" hec_status hec_ctx_create(const hec_params *p, int device, void *hip_
     return HEC_OK;
 }
 
+static void side_release(hec_ctx *c)
+{
+    if (c->side) {
+        hipStreamSynchronize(c->side);
+        hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
+    c->side = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
+}
+// the side stream and its events, created at first use
+static hec_status side_stream(hec_ctx *c)
+{
+    if (c->side) return HEC_OK;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (s) hipStreamDestroy(s);
+        if (a) hipEventDestroy(a);
+        HEC_FAIL(HEC_EDEVICE, "side stream: %s", hipGetErrorString(e));
+    }
+    c->side = s;
+    c->ev_fork = a;
+    c->ev_join = b;
+    return HEC_OK;
+}
+
 extern "C" void hec_ctx_destroy(hec_ctx *c)
 {
     if (!c) return;
     hipSetDevice(c->dev);
     hipStreamSynchronize(c->st);
+    side_release(c);
     c->pool.release_all();
     delete c;
 }
@@ -557,6 +589,7 @@ void ctx_lane_destroy(hec_ctx *c)
     if (!c) return;
     hipSetDevice(c->dev);
     hipStreamSynchronize(c->st);
+    side_release(c);
     hipStreamDestroy(c->st);
     c->pool.release_all();
     delete c;
@@ -1167,20 +1200,50 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     u64 *D = nullptr;
     HEC_CHECK(ct_modup(c, ct, &D));
     const u64 *c0 = ct->d;
-    // key switch in batches
+    // key switch in batches; with more than one batch and ks_overlap, odd
+    // batches run on the side stream (forked after the ModUp, joined at the
+    // end), each stream with its own buffers, so that one batch's key switch
+    // overlaps the other's ModDown; the residues do not depend on it
     const size_t kbn = (size_t)std::max(1, std::min((int)HEC_KS_BATCH, hec_tune_params().ks_rot_batch));
-    for (size_t b0 = 0; b0 < todo.size(); b0 += kbn) {
+    const size_t nb = (todo.size() + kbn - 1) / kbn;
+    const bool two = nb > 1 && hec_tune_params().ks_overlap;
+    if (two) {
+        hec_status f = side_stream(c);
+        if (f == HEC_OK) {
+            hipError_t e = hipEventRecord(c->ev_fork, c->st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+            if (e != hipSuccess) f = HEC_EDEVICE, hec_set_error("stream fork: %s", hipGetErrorString(e));
+        }
+        if (f != HEC_OK) {
+            c->release(D);
+            for (size_t i = 0; i < cnt; i++) {
+                ct_free(outs[i]);
+                outs[i] = nullptr;
+            }
+            return f;
+        }
+    }
+    const size_t emax = std::min(kbn, todo.size()) * 2 * nqp * n, ymax = std::min(kbn, todo.size()) * 2 * nq * n;
+    u64 *E[2] = {c->alloc(emax), two ? c->alloc(emax) : nullptr};
+    u64 *Y[2] = {c->alloc(ymax), two ? c->alloc(ymax) : nullptr};
+    hec_status s = (!E[0] || !Y[0] || (two && (!E[1] || !Y[1]))) ? HEC_ENOMEM : HEC_OK;
+    if (s != HEC_OK) hec_set_error("key-switch buffers");
+    for (size_t b0 = 0, bi = 0; b0 < todo.size() && s == HEC_OK; b0 += kbn, bi++) {
         const int R = (int)std::min(kbn, todo.size() - b0);
-        u64 *e = c->alloc((size_t)R * 2 * nqp * n);
-        u64 *y = c->alloc((size_t)R * 2 * nq * n);
-        if (!e || !y) HEC_FAIL(HEC_ENOMEM, "key-switch buffers");
+        const int side = two ? (int)(bi & 1) : 0;
+        hipStream_t st = side ? c->side : c->st;
+        u64 *e = E[side], *y = Y[side];
         KsBatch kb{};
         CombineBatch cb{};
-        for (int r = 0; r < R; r++) {
+        for (int r = 0; r < R && s == HEC_OK; r++) {
             size_t i = todo[b0 + r];
             uint32_t g = c->galois(steps[i]);
             hec_ct *o = ct_new(c, lvl, ct->scale);
-            if (!o) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
+            if (!o) {
+                s = HEC_ENOMEM;
+                hec_set_error("ciphertext allocation");
+                break;
+            }
             outs[i] = o;
             kb.key[r] = c->rotkeys[g];
             kb.out[r] = e + (size_t)r * 2 * nqp * n;
@@ -1190,19 +1253,40 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             cb.y[r] = y + (size_t)r * 2 * nq * n;
             cb.g[r] = g;
         }
-        hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, c->st);
+        if (s != HEC_OK) break;
+        hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, st);
         c->ks_count += (uint64_t)R;
         // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine (the
         // combine fused into the NTT's last pass where the ring allows)
-        hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, c->st);
-        hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, c->st, (int)c->k);
+        hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, st);
+        hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, st, (int)c->k);
         for (int r = 0; r < R; r++) cb.c0[r] = c0;
-        if (!hec_ntt_fwd_moddown(c->T, y, R, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), c->st)) {
-            hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, c->st);
-            hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), c->st);
+        if (!hec_ntt_fwd_moddown(c->T, y, R, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), st)) {
+            hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, st);
+            hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), st);
         }
-        c->release(e);
-        c->release(y);
+    }
+    if (two) {
+        // join: the main stream waits for the side stream's batches before
+        // anything after this call (and before the buffers are reused)
+        hipError_t e1 = hipEventRecord(c->ev_join, c->side);
+        hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(c->st, c->ev_join, 0) : e1;
+        if (e2 != hipSuccess && s == HEC_OK) {
+            s = HEC_EDEVICE;
+            hec_set_error("stream join: %s", hipGetErrorString(e2));
+        }
+    }
+    for (int i = 0; i < 2; i++) {
+        c->release(E[i]);
+        c->release(Y[i]);
+    }
+    if (s != HEC_OK) {
+        c->release(D);
+        for (size_t i = 0; i < cnt; i++) {
+            ct_free(outs[i]);
+            outs[i] = nullptr;
+        }
+        return s;
     }
     c->release(D);
     HEC_TRY_HIP(hipGetLastError());

@@ -89,6 +89,12 @@ struct hec_ctx {
     hec_params prm{};
     int dev = 0;
     hipStream_t st = nullptr;
+    // second stream (default priority) on which every other batch of a hoisted
+    // rotation set runs, so that one batch's key switch (HBM-bound) overlaps
+    // the previous batch's ModDown (transforms); forked from and joined back
+    // into st by the two events; created at first use
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t logn = 0, n = 0, N = 0, L = 0, k = 0, dnum = 0, alpha = 0, NLK = 0;
     std::vector<uint64_t> mod;
     DevPool pool;
