@@ -628,9 +628,10 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
     image (channels padded to 4, duplicated) through conv 3x3 3->32 and 2x2
     average pooling, 30 % a 3x224x224 image (each channel in two shards)
     through the stem conv 3x3 stride 2, 3->64; level 20, keys and plans
-    resident.  Saturation throughput from a burst, then arrivals at 0.5x and
-    0.8x of it; p50 / p99 latency (submit -> result on the device) and
-    requests/s."""
+    resident; the convolutions key-stationary (mode 4), the pooling and the
+    stem's downsampling with lazy ModDown (mode 2).  Saturation throughput
+    from a burst, then arrivals at 0.5x and 0.8x of it; p50 / p99 latency
+    (submit -> result on the device) and requests/s."""
     rng = np.random.default_rng(5005)
     wa = rng.normal(0, 0.05, (32, 3, 3, 3))
     wb = rng.normal(0, 0.05, (64, 3, 3, 3))
@@ -642,13 +643,15 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
     ctx.gen_rotation_keys(ctx.avgpool_steps(pa.run(like_a)))
     pb = ctx.conv2d_plan(like_b, wb, stride=2, q_only=True)
     pb.set_mode(4)
+    pb.set_downsample_mode(2)
     ctx.gen_rotation_keys(pb.steps())
     ctx.sync()
     srv = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
     res = {"lanes": lanes, "max_batch": max_batch, "mix": "70% 3x32x32 conv 3->32 + pool, 30% 3x224x224 stem "
-           "conv s2 3->64", "level": LEVEL}
+           "conv s2 3->64", "forms": "convolutions key-stationary (mode 4), pooling and the stem's downsampling "
+           "lazy (mode 2)", "level": LEVEL}
     try:
-        ma = srv.add_model(pa, like_a, pool_mode=4)
+        ma = srv.add_model(pa, like_a, pool_mode=2)
         mb = srv.add_model(pb, like_b)
         res["footprint_bytes"] = {"block": srv.footprint(ma), "stem": srv.footprint(mb)}
         reqs = []
@@ -671,7 +674,7 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
     for load in (0.5, 0.8):
         srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
         try:
-            srv_l.add_model(pa, like_a, pool_mode=4)
+            srv_l.add_model(pa, like_a, pool_mode=2)
             srv_l.add_model(pb, like_b)
             lam = load * sat
             gaps = rng.exponential(1.0 / lam, size=len(reqs))

@@ -276,6 +276,15 @@ hec_status he_conv2d_plan_run(hec_ctx *ctx, const hec_conv_plan *plan, const hec
  * lazily (he_avgpool_ex mode 2), mode 4 key-stationary (he_avgpool_ex mode
  * 4).  Returns HEC_EINVAL for any other mode. */
 hec_status he_conv2d_plan_set_mode(hec_conv_plan *plan, int mode);
+/* Form of a stride-2 plan's downsampling step (Section 4.1, strided
+ * convolution: the stride-1 convolution followed by the downsampling of the
+ * pooling) independently of how the convolution itself runs: -1 = the plan
+ * mode's own form (the default), or one of he_avgpool_ex's modes 0
+ * (complete rotations), 2 (lazy ModDown) and 4 (key-stationary).  A server's
+ * stem layer, for example, convolves key-stationary over Q-only plaintexts
+ * and downsamples lazily.  HEC_EINVAL for other values or for a stride-1
+ * plan. */
+hec_status he_conv2d_plan_set_downsample_mode(hec_conv_plan *plan, int mode);
 /* Rotation steps a plan (or an avgpool of `like`) needs keys for. */
 hec_status he_conv2d_plan_steps(const hec_conv_plan *plan, int32_t *steps, size_t cap, size_t *count);
 hec_status he_avgpool_steps(hec_ctx *ctx, const hec_image *like, int32_t *steps, size_t cap, size_t *count);

@@ -1501,6 +1501,7 @@ struct hec_conv_plan {
     Layout in, out;  // out = unstrided output layout
     uint32_t level = 0, stride = 1;
     int mode = 0;
+    int ds_mode = -1;  // form of the stride-2 downsampling (-1: the plan mode's own)
     bool q_only = false;  // weight plaintexts over Q only: modes 0 and 1
     // basis-mask form (basis = s > 0): the plaintexts of items are borrowed
     // handles on weight rows of Wt (the nb integers round(w_b q_l / 2^s), as
@@ -1793,6 +1794,16 @@ extern "C" hec_status he_conv2d_plan_set_mode(hec_conv_plan *p, int mode)
     return HEC_OK;
 }
 
+extern "C" hec_status he_conv2d_plan_set_downsample_mode(hec_conv_plan *p, int mode)
+{
+    if (!p) HEC_FAIL(HEC_EINVAL, "plan is NULL");
+    if (p->stride != 2) HEC_FAIL(HEC_EINVAL, "a stride-1 plan has no downsampling step");
+    if (mode != -1 && mode != 0 && mode != 2 && mode != 4)
+        HEC_FAIL(HEC_EINVAL, "downsampling mode must be -1, 0, 2 or 4");
+    p->ds_mode = mode;
+    return HEC_OK;
+}
+
 extern "C" hec_status he_conv2d_plan_steps(const hec_conv_plan *p, int32_t *steps, size_t cap, size_t *count)
 {
     if (!p) HEC_FAIL(HEC_EINVAL, "plan is NULL");
@@ -1989,7 +2000,8 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
         im->lay = p->out;
         im->shards = acc;
     } else {
-        s = downsample_and_merge(c, acc, p->out, true, p->mode == 1 ? 0 : p->mode, im->shards, im->lay);
+        const int dm = p->ds_mode >= 0 ? p->ds_mode : (p->mode == 1 ? 0 : p->mode);
+        s = downsample_and_merge(c, acc, p->out, true, dm, im->shards, im->lay);
         free_all(acc);
         if (s != HEC_OK) { hec_image_free(im); return s; }
     }
@@ -2068,7 +2080,7 @@ hec_status conv_plan_run_multi(hec_ctx *c, const hec_conv_plan *p, const std::ve
     }
     std::vector<std::vector<hec_ct *>> ds;
     Layout ol;
-    s = downsample_and_merge_multi(c, per, p->out, true, 4, ds, ol);
+    s = downsample_and_merge_multi(c, per, p->out, true, p->ds_mode >= 0 ? p->ds_mode : 4, ds, ol);
     free_all(acc);
     if (s != HEC_OK) return s;
     for (size_t r = 0; r < K; r++) {

@@ -21,6 +21,7 @@ EXPORTS = [
     "ckks_ct_import", "ckks_pt_export", "ckks_pt_import", "ckks_encode_coeffs", "he_image_encrypt",
     "he_image_decrypt", "he_image_info", "he_image_block_map", "he_image_shard", "he_conv2d_sharded",
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
+    "he_conv2d_plan_set_downsample_mode",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
     "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
@@ -125,6 +126,7 @@ def lib():
             "he_conv2d_plan_run": (c, [vp, vp, vp, P(vp)]),
             "he_conv2d_plan_create_ex": (c, [vp, vp, dblp, u32, u32, u32, u32, u32, u32, P(vp)]),
             "he_conv2d_plan_set_mode": (c, [vp, c]),
+            "he_conv2d_plan_set_downsample_mode": (c, [vp, c]),
             "he_conv2d_plan_steps": (c, [vp, i32p, sz, szp]),
             "he_avgpool_steps": (c, [vp, vp, i32p, sz, szp]),
             "he_linear_steps": (c, [vp, vp, i32p, sz, szp]),
@@ -360,6 +362,10 @@ class ConvPlan(_Handle):
 
     def set_mode(self, mode):
         check(lib().he_conv2d_plan_set_mode(self.h, int(mode)))
+
+    def set_downsample_mode(self, mode):
+        """Form of a stride-2 plan's downsampling: -1 (the plan mode's own), 0, 2 or 4."""
+        check(lib().he_conv2d_plan_set_downsample_mode(self.h, int(mode)))
 
     def run(self, img):
         out = vp()

@@ -452,3 +452,44 @@ def test_q_only_plan(small):
     for mode in (2, 3):
         with pytest.raises(hecnn.HecError):
             qo.set_mode(mode)
+
+
+@pytest.mark.parametrize("shape,co,mode,dsm", [
+    ((4, 16, 16), 8, 4, 2),    # image shards: key-stationary conv, lazy downsampling
+    ((4, 16, 16), 8, 0, 2),    # batched conv, lazy downsampling
+    ((4, 16, 16), 8, 2, 0),    # lazy conv, downsampling by complete rotations
+    ((3, 28, 28), 4, 4, 2),    # channel shards (a stem): key-stationary conv, lazy downsampling
+    ((8, 16, 16), 8, 0, 4),    # batched conv, key-stationary downsampling
+])
+def test_strided_downsample_mode_bit_exact(small, shape, co, mode, dsm):
+    """A stride-2 plan whose downsampling step takes its own form: the oracle's
+    stride-1 convolution in the plan's form followed by its downsampling in
+    the chosen form (Section 4.1: strided convolution = convolution, then the
+    pooling's downsampling), every shard bit for bit."""
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = small
+    rng = np.random.default_rng(400 + 10 * mode + dsm + shape[0])
+    x = rng.uniform(-1, 1, shape)
+    w = rng.normal(0, 0.1, (co, shape[0], 3, 3))
+    level, seed = 6, 4100 + mode
+    img = ctx.image_encrypt(x, level, seed)
+    plan = ctx.conv2d_plan(img, w, stride=2)
+    plan.set_mode(mode)
+    plan.set_downsample_mode(dsm)
+    ctx.gen_rotation_keys(plan.steps())
+    out = plan.run(img)
+    lay = hl.natural_layout(prm.N, *shape)
+    be = hl.CkksBackend(o)
+    cts = [o.encrypt(o.encode(v, level, 2.0 ** 40), seed=seed, index=u) for u, v in enumerate(hl.pack(x, lay))]
+    oc, ol = hl.conv2d(be, cts, lay, w, pad=1, stride=1, lazy=(mode == 2))
+    dc, dl = hl.downsample_and_merge(be, oc, ol, select=True, lazy=(dsm == 2))
+    assert out.info()[4] == len(dc)
+    for u in range(len(dc)):
+        assert out.shard_info(u) == (dc[u].level, dc[u].scale)
+        assert (out.shard_export(u) == dc[u].data).all(), u
+    assert np.abs(out.decrypt() - hl.ref_conv2d(x, w, 1, 2)).max() < 1e-5
+    check_decrypt_vs_oracle(out, o, dc)
+    with pytest.raises(hecnn.HecError):
+        plan.set_downsample_mode(3)
+    with pytest.raises(hecnn.HecError):
+        ctx.conv2d_plan(img, w).set_downsample_mode(2)   # stride 1: no downsampling

@@ -38,16 +38,20 @@ def setup():
     return ctx, models, rng
 
 
-def reference(ctx, plan, img):
-    return ctx.avgpool(plan.run(img), mode=4)
+def reference(ctx, plan, img, pool_mode):
+    return ctx.avgpool(plan.run(img), mode=pool_mode)
 
 
-def test_server_alone_vs_mix(setup):
+@pytest.mark.parametrize("pool_mode", [4, 2])
+def test_server_alone_vs_mix(setup, pool_mode):
+    """pool_mode 4: key-stationary pooling; 2: lazy ModDown pooling, which a
+    batch takes over the shards of all its images in one fused launch per
+    group of terms -- the same bits as each image pooled alone."""
     from paper_2306_09189_amd import hecnn
     ctx, models, rng = setup
     srv = hecnn.Server(ctx, lanes=2, max_batch=4, mem_budget=8 << 30)
     try:
-        mids = [srv.add_model(plan, like, pool_mode=4) for (_, _, plan, like) in models]
+        mids = [srv.add_model(plan, like, pool_mode=pool_mode) for (_, _, plan, like) in models]
         assert all(srv.footprint(m) > 0 for m in mids)
         # a pool of request images of both models
         reqs = []
@@ -56,7 +60,7 @@ def test_server_alone_vs_mix(setup):
             shape, w, plan, like = models[m]
             x = rng.uniform(-1, 1, shape)
             reqs.append((m, x, ctx.image_encrypt(x, 6, 100 + i)))
-        refs = [exports(reference(ctx, models[m][2], img)) for (m, x, img) in reqs]
+        refs = [exports(reference(ctx, models[m][2], img, pool_mode)) for (m, x, img) in reqs]
         # alone: one request at a time on an idle server
         for j in (0, 7):
             m, x, img = reqs[j]
