@@ -1206,7 +1206,11 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     // overlaps the other's ModDown; the residues do not depend on it
     const size_t kbn = (size_t)std::max(1, std::min((int)HEC_KS_BATCH, hec_tune_params().ks_rot_batch));
     const size_t nb = (todo.size() + kbn - 1) / kbn;
-    const bool two = nb > 1 && hec_tune_params().ks_overlap;
+    // (not while the stream is being captured into a graph: a recording
+    // stays on the one stream it captures)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (nb > 1 && hec_tune_params().ks_overlap) (void)hipStreamIsCapturing(c->st, &cap);
+    const bool two = nb > 1 && hec_tune_params().ks_overlap && cap == hipStreamCaptureStatusNone;
     if (two) {
         hec_status f = side_stream(c);
         if (f == HEC_OK) {

@@ -94,3 +94,35 @@ def test_batch_replay_reads_current_inputs(ring):
     assert np.abs(r2 - hl.ref_conv2d(x2, w, 1)).max() < 1e-5
     b1.launch(graph=True)
     assert np.abs(b1.output(0).decrypt() - r1).max() == 0
+
+
+def test_batch_graph_with_two_streams(ring):
+    """With hoisted rotation batches on two streams (ks_overlap=1) the eager
+    launch forks and joins a second stream; the recorded graph keeps to the
+    one stream it captures.  Both give the same bits, also on replays."""
+    from paper_2306_09189_amd import hecnn
+    ctx, prm, o = ring
+    saved = hecnn.tune_get("ks_overlap")
+    hecnn.tune_set("ks_overlap", 1)
+    try:
+        rng = np.random.default_rng(19)
+        x = rng.uniform(-1, 1, (4, 16, 16))
+        w = rng.normal(0, 0.1, (4, 4, 3, 3))
+        img = ctx.image_encrypt(x, 8, 700)
+        plan = ctx.conv2d_plan(img, w)
+        plan.set_mode(0)      # 35 hoisted rotations: more than one batch of 16
+        ctx.gen_rotation_keys(plan.steps())
+        b = ctx.batch()
+        b.add(plan, img)
+        b.launch(graph=False)
+        eager = exports(b.output(0))
+        hecnn.tune_set("ks_overlap", 0)
+        single = exports(plan.run(img))
+        hecnn.tune_set("ks_overlap", 1)
+        assert all((a == s).all() for a, s in zip(eager, single))
+        for rep in range(3):
+            b.launch(graph=True)
+            assert all((a == e).all() for a, e in zip(exports(b.output(0)), eager)), rep
+            _ = plan.run(img)   # eager two-stream work between replays
+    finally:
+        hecnn.tune_set("ks_overlap", saved)
