@@ -530,10 +530,12 @@ def main():
         out["imagenet_112x112x64"] = guarded(lambda: imagenet_stage(ctx, hecnn, hl, rng, max(5, args.reps // 2)))
 
     # ---- the uneven batch: 13 instances, 48 ciphertexts at levels 2..24, eager vs one captured graph ----
+    ctx.release_cached()  # the cached blocks of the sections before go back to the device
     if "uneven" not in skip:
         out["uneven_batch_48ct"] = guarded(lambda: uneven_batch(ctx, hl, args.reps))
 
     # ---- serving: Poisson arrivals of the two request shapes ----
+    ctx.release_cached()
     if "serving" not in skip:
         out["serving"] = guarded(lambda: serving(ctx, hecnn, hl))
 
@@ -646,7 +648,7 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
     pb.set_downsample_mode(2)
     ctx.gen_rotation_keys(pb.steps())
     ctx.sync()
-    srv = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
+    srv = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=64 << 30)
     res = {"lanes": lanes, "max_batch": max_batch, "mix": "70% 3x32x32 conv 3->32 + pool, 30% 3x224x224 stem "
            "conv s2 3->64", "forms": "convolutions key-stationary (mode 4), pooling and the stem's downsampling "
            "lazy (mode 2)", "level": LEVEL}
@@ -672,7 +674,7 @@ def serving(ctx, hecnn, hl, n_requests=24, lanes=2, max_batch=4):
     finally:
         srv.stop()  # its lanes' memory back before the servers of the timed loads start
     for load in (0.5, 0.8):
-        srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=96 << 30)
+        srv_l = hecnn.Server(ctx, lanes=lanes, max_batch=max_batch, mem_budget=64 << 30)
         try:
             srv_l.add_model(pa, like_a, pool_mode=2)
             srv_l.add_model(pb, like_b)

@@ -485,6 +485,12 @@ void hec_image_free(hec_image *img);
 
 /* Wait for all enqueued work of the context. */
 hec_status hec_ctx_sync(hec_ctx *ctx);
+/* Give the device memory the library keeps cached for reuse (its pools' free
+ * blocks, on every context and serving lane of the device; not the memory of
+ * live objects, keys, plans or captured batches) back to the device, after
+ * the device's queued work.  Allocation does this by itself when HBM runs
+ * short; the pools always leave 1 GiB of the device free for the runtime. */
+hec_status hec_ctx_release_cached(hec_ctx *ctx);
 
 /* ---- diagnostics ---------------------------------------------------------- */
 

@@ -42,6 +42,7 @@ PoolRegistry &registry()
     static PoolRegistry *r = new PoolRegistry();
     return *r;
 }
+}  // namespace
 void trim_device_pools(int dev)
 {
     PoolRegistry &r = registry();
@@ -50,7 +51,6 @@ void trim_device_pools(int dev)
     for (DevPool *p : r.pools)
         if (p->trimmable && p->dev.load() == dev) p->release_cached();
 }
-}  // namespace
 
 DevPool::DevPool()
 {
@@ -83,11 +83,26 @@ void *DevPool::get(size_t bytes)
     }
     int d = 0;
     (void)hipGetDevice(&d);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    // The pools leave HBM_RESERVE of the device free for the runtime itself
+    // (queues, and the scratch memory it allocates per queue at the first
+    // launch of a kernel that needs it): when a block would cut into it, the
+    // cached blocks of every pool of the device go back first, and if the
+    // block still does not fit the allocation fails here with a null result
+    // rather than leaving the runtime short later.
+    auto fits = [&]() {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return true;  // no figure: leave it to hipMalloc
+        }
+        return fr >= bytes + HBM_RESERVE;
+    };
+    bool ok = fits() && hipMalloc(&p, bytes) == hipSuccess;
+    if (!ok) {
         // the failed call's error is cleared so that a later check of the launch status does not report it
         (void)hipGetLastError();
         trim_device_pools(d);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (!fits() || hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
@@ -599,6 +614,15 @@ extern "C" hec_status hec_ctx_sync(hec_ctx *c)
 {
     if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
     HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    return HEC_OK;
+}
+
+extern "C" hec_status hec_ctx_release_cached(hec_ctx *c)
+{
+    if (!c) HEC_FAIL(HEC_EINVAL, "ctx is NULL");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    trim_device_pools(c->dev);
+    HEC_TRY_HIP(hipGetLastError());
     return HEC_OK;
 }
 

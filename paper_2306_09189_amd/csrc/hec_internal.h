@@ -44,6 +44,11 @@ void hec_set_error(const char *fmt, ...);
 // cached blocks go back to it (after its queued work is done) and the
 // allocation is tried once more.
 // Thread-safe: a server's workers and its clients (freeing results) share pools.
+// device memory the pools leave free for the runtime (queues, per-queue scratch)
+#define HBM_RESERVE (1ull << 30)
+// every trimmable pool of device dev gives its cached blocks back (after the
+// device's queued work)
+void trim_device_pools(int dev);
 struct DevPool {
     std::unordered_multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> live_;

@@ -23,7 +23,7 @@ EXPORTS = [
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
     "he_conv2d_plan_set_downsample_mode",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
-    "hec_ctx_sync", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
+    "hec_ctx_sync", "hec_ctx_release_cached", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
     "he_conv2d_plan_create_ex", "hec_gauss_table", "ckks_rotate_noalloc",
@@ -138,6 +138,7 @@ def lib():
             "hec_pt_free": (None, [vp]),
             "hec_image_free": (None, [vp]),
             "hec_ctx_sync": (c, [vp]),
+            "hec_ctx_release_cached": (c, [vp]),
             "hec_prof_start": (c, [vp, ctypes.c_char_p]),
             "hec_prof_stop": (c, [vp, u64p, u64p, dblp]),
             "hec_prof_launches": (u64, [ctypes.c_char_p]),
@@ -745,6 +746,10 @@ class Context:
 
     def sync(self):
         check(lib().hec_ctx_sync(self.h))
+
+    def release_cached(self):
+        """Device memory cached by the library's pools back to the device."""
+        check(lib().hec_ctx_release_cached(self.h))
 
     def prof_start(self, kernel):
         check(lib().hec_prof_start(self.h, kernel.encode()))

@@ -493,3 +493,21 @@ def test_strided_downsample_mode_bit_exact(small, shape, co, mode, dsm):
         plan.set_downsample_mode(3)
     with pytest.raises(hecnn.HecError):
         ctx.conv2d_plan(img, w).set_downsample_mode(2)   # stride 1: no downsampling
+
+
+def test_release_cached_keeps_results(small):
+    """Giving the pools' cached blocks back to the device (hec_ctx_release_cached)
+    changes nothing that is computed afterwards."""
+    ctx, prm, o = small
+    rng = np.random.default_rng(808)
+    x = rng.uniform(-1, 1, (4, 16, 16))
+    w = rng.normal(0, 0.1, (4, 4, 3, 3))
+    img = ctx.image_encrypt(x, 5, 808)
+    plan = ctx.conv2d_plan(img, w)
+    ctx.gen_rotation_keys(plan.steps())
+    a = plan.run(img)
+    first = [a.shard_export(u) for u in range(a.info()[4])]
+    del a
+    ctx.release_cached()
+    b = plan.run(img)
+    assert all((b.shard_export(u) == f).all() for u, f in enumerate(first))
