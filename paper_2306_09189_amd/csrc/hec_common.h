@@ -70,6 +70,10 @@ struct KsBatch {
     const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
     u64 *out[HEC_KS_BATCH];        // [2][nqp][n]
     const u64 *D[HEC_KS_BATCH];    // this entry's own hoisted digits (null: the launch's shared D)
+    // c0 of the rotated ciphertext ([nq][n], NTT form): P * sigma_g(c0) is
+    // added to the Q limbs of polynomial 0, so that the ModDown that follows
+    // yields ModDown(e) + sigma_g(c0) exactly (null: nothing added)
+    const u64 *c0[HEC_KS_BATCH];
     u32 g[HEC_KS_BATCH];
 };
 
@@ -181,8 +185,9 @@ void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int
                u64 *dst, size_t src_poly_stride, size_t dst_poly_stride, int npolys, int copy_in, hipStream_t st,
                int nin_max);
 
+// pm, nq: [P * 2^64]_{q_i} of the Q limbs i < nq, for the entries with c0 set
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
-                  int NLK, hipStream_t st);
+                  int NLK, hipStream_t st, const u64 *pm = nullptr, int nq = 0);
 // the same products as hec_ks_inner for nrot <= HEC_KS_BATCH rotations x S <= HEC_MULTI_MAX_INPUTS inputs,
 // each key read once for all inputs; false (nothing launched) for sizes out of range
 bool hec_ks_inner_multi(const DevTables &T, const KsMulti &kb, int nrot, const u64 *D, size_t dstride, int S,

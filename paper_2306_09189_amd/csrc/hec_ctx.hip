@@ -1276,22 +1276,23 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             kb.key[r] = c->rotkeys[g];
             kb.out[r] = e + (size_t)r * 2 * nqp * n;
             kb.g[r] = g;
+            kb.c0[r] = c0;  // P * sigma_g(c0) folded into the key-switch product
             cb.out[r] = o->d;
             cb.e[r] = kb.out[r];
             cb.y[r] = y + (size_t)r * 2 * nq * n;
             cb.g[r] = g;
         }
         if (s != HEC_OK) break;
-        hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, st);
+        hec_ks_inner(c->T, kb, R, D, beta, nqp, c->qpmap(lvl), c->NLK, st, c->d_pmodq_m, (int)nq);
         c->ks_count += (uint64_t)R;
         // ModDown: INTT of the P limbs, P -> Q_l conversion, NTT, combine (the
         // combine fused into the NTT's last pass where the ring allows)
         hec_ntt_inv(c->T, e + (size_t)nq * n, (size_t)nqp * n, 2 * R, c->qpmap(lvl) + nq, k, st);
         hec_bconv(c->T, c->d_moddown + lvl, 0, 1, nq, e, y, (size_t)nqp * n, (size_t)nq * n, 2 * R, 0, st, (int)c->k);
-        for (int r = 0; r < R; r++) cb.c0[r] = c0;
+        // (cb.c0 stays null: sigma_g(c0) is already in e)
         if (!hec_ntt_fwd_moddown(c->T, y, R, (int)nq, (int)nqp, cb, c->d_lvl + lvl, c->qpmap(lvl), st)) {
             hec_ntt_fwd(c->T, y, (size_t)nq * n, 2 * R, c->qpmap(lvl), nq, st);
-            hec_moddown_combine(c->T, cb, R, c0, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), st);
+            hec_moddown_combine(c->T, cb, R, nullptr, nq, nqp, c->d_lvl + lvl, c->qpmap(lvl), st);
         }
     }
     if (two) {

@@ -1410,7 +1410,7 @@ void hec_bconv(const DevTables &T, const BconvDesc *d_desc, int desc_stride, int
 // XCD and reused from its L2 by every rotation of the batch.
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *D, u32 beta, u32 nqp,
                                                          const u32 *pmap, u32 NLK, u32 nrot, u32 nchunks,
-                                                         DevTables T)
+                                                         const u64 *pm, u32 nq, DevTables T)
 {
     const u32 w = blockIdx.x, total = gridDim.x;
     const u32 i = (total & 7) ? w : (w & 7) * (total >> 3) + (w >> 3);
@@ -1432,18 +1432,21 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(KsBatch kb, const u64 *
         mac(a0, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 0) * NLK + pi) * n + k));
         mac(a1, d, __builtin_nontemporal_load(key + (((size_t)j * 2 + 1) * NLK + pi) * n + k));
     }
+    // P * sigma_g(c0) on a Q limb of polynomial 0 (beta + 1 products below
+    // q * 2^64): the ModDown's epilogue then reads no c0
+    if (kb.c0[r] && o < nq) mac(a0, kb.c0[r][(size_t)o * n + src], pm[o]);
     // written past the caches too (read back by the ModDowns after the launch)
     u64 *out = kb.out[r];
     __builtin_nontemporal_store(redc(a0.hi, a0.lo, pc.q, pc.qinv_neg), out + (size_t)o * n + k);
     __builtin_nontemporal_store(redc(a1.hi, a1.lo, pc.q, pc.qinv_neg), out + ((size_t)nqp + o) * n + k);
 }
 void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D, int beta, int nqp, const u32 *pmap,
-                  int NLK, hipStream_t st)
+                  int NLK, hipStream_t st, const u64 *pm, int nq)
 {
     const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
     dim3 g(nchunks * (u32)nqp * (u32)nrot);
     KLAUNCH("k_ks_inner", (uint64_t)nrot * nqp, k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp,
-            pmap, (u32)NLK, (u32)nrot, nchunks, T);
+            pmap, (u32)NLK, (u32)nrot, nchunks, pm, (u32)(pm ? nq : 0), T);
 }
 
 // Key-stationary form of the same products for several inputs that share the
