@@ -37,15 +37,18 @@ def eprint(*a):
 #    is one limb (2^16 words = 512 KiB) moved to or from HBM, counting every key,
 #    plaintext and accumulator limb once and the hoisted digits and the input
 #    ciphertext once per launch.  Bound: HBM, 8 TB/s.
-#  * batched / plain / key-stationary (modes 0, 1, 4): the row pass of the 2^16
-#    forward NTT (k_ntt16_fwd_rows; mostly its ModDown form, whose epilogue
-#    finishes the rotation).  Unit: one limb moved -- per transformed limb the
-#    limb read and, in the ModDown form, the key-switch product read, sigma_g(c0)
-#    read (first polynomial) and the rotated limb written; the twiddle and twist
-#    tables are constants and not counted.  At 2^18 butterflies of ~17 VALU
-#    instructions per 1-2 MiB moved it issues 2.4-4.3 instructions per byte,
-#    below the chip's ridge of 39.3 T lane-instructions/s / 8 TB/s = 4.9: its
-#    roof is HBM, 8 TB/s.
+#  * batched (mode 0): the key-switch inner product of the hoisted rotation
+#    sets, k_ks_inner.  Unit: one limb moved -- per rotation its 2 beta key
+#    limbs read and its 2 products written per limb, the shared hoisted digits
+#    and the folded c0 read once per launch.  Bound: HBM, 8 TB/s.
+#  * plain / key-stationary (modes 1, 4): the row pass of the 2^16 forward NTT
+#    (k_ntt16_fwd_rows; its ModDown form finishes each rotation).  Unit: one
+#    limb moved -- per transformed limb the limb read and, in the ModDown form,
+#    the key-switch product (and where not folded into it sigma_g(c0)) read and
+#    the rotated limb written; the twiddle and twist tables are constants and
+#    not counted.  At 2^18 butterflies of ~17 VALU instructions per 1-2 MiB
+#    moved it issues 2.4-4.3 instructions per byte, below the chip's ridge of
+#    39.3 T lane-instructions/s / 8 TB/s = 4.9: its roof is HBM, 8 TB/s.
 LIMB_BYTES = 8 << LOGN
 KERNELS = {
     "k_ks_mac": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
@@ -54,8 +57,11 @@ KERNELS = {
     "k_ntt16_fwd_rows": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                          "bytes_per_unit": LIMB_BYTES,
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
+    "k_ks_inner": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
+                   "bytes_per_unit": LIMB_BYTES,
+                   "traffic_file": os.path.join(ROOT, "profiles", "ks_inner_2e16_traffic.txt")},
 }
-DOMINANT = {0: "k_ntt16_fwd_rows", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac", 4: "k_ntt16_fwd_rows"}
+DOMINANT = {0: "k_ks_inner", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac", 4: "k_ntt16_fwd_rows"}
 
 
 def read_traffic(path):
@@ -76,6 +82,8 @@ def read_traffic(path):
 SOURCE_REGIONS = {
     "k_ks_mac": ("typedef u64 u64x2 __attribute__((ext_vector_type(2)));", "__global__ void k_moddown_combine("),
     "k_ntt16_fwd_rows": ("// NTT: merged Cooley-Tukey forward transform", "void hec_ntt_fwd("),
+    "k_ks_inner": ("// key-switch inner product with the automorphism folded into the read:",
+                   "// Key-stationary form of the same products"),
 }
 
 

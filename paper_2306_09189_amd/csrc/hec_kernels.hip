@@ -1445,8 +1445,18 @@ void hec_ks_inner(const DevTables &T, const KsBatch &kb, int nrot, const u64 *D,
 {
     const u32 nchunks = (T.n + EW_THREADS - 1) / EW_THREADS;
     dim3 g(nchunks * (u32)nqp * (u32)nrot);
-    KLAUNCH("k_ks_inner", (uint64_t)nrot * nqp, k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp,
-            pmap, (u32)NLK, (u32)nrot, nchunks, pm, (u32)(pm ? nq : 0), T);
+    // units: limbs moved -- per rotation its 2 beta key limbs read and 2
+    // products written per limb; the shared digits (beta limbs per limb, or
+    // each entry's own) and the folded c0 limbs read once
+    uint64_t units = 0, own = 0, fold = 0;
+    for (int r = 0; r < nrot; r++) {
+        own += kb.D[r] ? 1 : 0;
+        fold += (pm && kb.c0[r]) ? 1 : 0;
+    }
+    units = (uint64_t)nrot * nqp * (2 * beta + 2) + (uint64_t)(D ? 1 + own : own) * beta * nqp +
+            (fold ? (uint64_t)nq : 0);
+    KLAUNCH("k_ks_inner", units, k_ks_inner, g, dim3(EW_THREADS), 0, st, kb, D, (u32)beta, (u32)nqp, pmap, (u32)NLK,
+            (u32)nrot, nchunks, pm, (u32)(pm ? nq : 0), T);
 }
 
 // Key-stationary form of the same products for several inputs that share the
