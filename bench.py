@@ -59,7 +59,10 @@ KERNELS = {
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
     "k_ks_inner": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                    "bytes_per_unit": LIMB_BYTES,
-                   "traffic_file": os.path.join(ROOT, "profiles", "ks_inner_2e16_traffic.txt")},
+                   "traffic_file": os.path.join(ROOT, "profiles", "ks_inner_2e16_traffic.txt"),
+                   # its access mix per (rotation, limb): 2 beta = 6 key streams read, 2 product
+                   # streams written, one 64-bit word of each per lane
+                   "probe_mix": (6, 2)},
 }
 DOMINANT = {0: "k_ks_inner", 1: "k_ntt16_fwd_rows", 2: "k_ks_mac", 3: "k_ks_mac", 4: "k_ntt16_fwd_rows"}
 
@@ -113,6 +116,25 @@ def dominant_roofline(kernel, launches, units, kms):
             "unit": spec["unit"], "frac": achieved / spec["peak"], "traffic": traffic,
             "avg_launch_us": avg_s * 1e6, "launches": launches, "avg_units_per_launch": avg_units,
             "algorithmic_bytes_per_launch": avg_units * spec["bytes_per_unit"]}
+
+
+def access_mix_probe(ctx, roof):
+    """The dominant kernel's access mix without its arithmetic: a kernel that
+    reads and writes the same number of 64-bit streams, one word of each per
+    lane, over the bytes of the kernel's average launch.  Its bandwidth is what
+    this access shape can draw from HBM; `kernel_frac_of_probe` = the kernel's
+    achieved bandwidth / the probe's."""
+    if not roof or "probe_mix" not in KERNELS[roof["kernel"]]:
+        return None
+    nr, nw = KERNELS[roof["kernel"]]["probe_mix"]
+    words = max(1, round(roof["algorithmic_bytes_per_launch"] / 8 / (nr + nw) / (1 << LOGN))) << LOGN
+    us = guarded(lambda: ctx.probe_stream(nr, nw, words, 20))
+    if not isinstance(us, float):
+        return None
+    gbps = (nr + nw) * words * 8 / (us * 1e-6) / 1e9
+    return {"streams_read": nr, "streams_written": nw, "bytes_per_launch": (nr + nw) * words * 8,
+            "avg_launch_us": us, "achieved": gbps, "unit": "GB/s", "frac_of_peak": gbps / roof["peak"],
+            "kernel_frac_of_probe": roof["achieved"] / gbps}
 
 
 def rotations_per_step():
@@ -459,6 +481,9 @@ def main():
         "launch_params": hecnn.tune_describe(),
     }
     eprint("step mode %d: %.2f ms, %.0f rotations/s" % (args.mode, main_run["ms_per_step"], value))
+    probe = access_mix_probe(ctx, main_run["roofline"])
+    if probe:
+        out["roofline"]["access_mix_probe"] = probe
 
     # ---- the same step in the other modes ----
     if "other" not in skip:

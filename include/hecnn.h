@@ -495,15 +495,29 @@ hec_status hec_ctx_release_cached(hec_ctx *ctx);
 /* ---- diagnostics ---------------------------------------------------------- */
 
 /* Time every launch of the named kernel with HIP events on the context stream
- * until hec_prof_stop (one kernel at a time per process).  Names:
- * k_ntt16_fwd_cols, k_ntt16_fwd_rows, k_ntt16_inv_rows, k_ntt16_inv_cols
- * (units: 2^16-word limbs), k_ks_inner (units: rotation x limb),
- * k_moddown_combine (units: rotation x output limb), k_bconv (units:
- * polynomials), k_ew (units: limbs).  Both calls synchronize the stream. */
+ * until hec_prof_stop (one kernel at a time per process).  Names and units:
+ * k_ntt16_fwd_cols, k_ntt16_inv_rows, k_ntt16_inv_cols (limbs transformed);
+ * k_ntt16_fwd_rows (limbs moved to or from HBM: 2 per transformed limb, 3 in
+ * the rescale form; in the ModDown form the product limb read, the rotated
+ * limb written and what is added read); k_ks_inner, k_ks_inner_multi,
+ * k_ks_mac (limbs moved: keys, plaintexts and outputs of every rotation,
+ * shared digits and inputs once per launch); k_moddown_combine (rotation x
+ * output limb); k_mac_terms (limb x term); k_bconv (polynomials); k_ew
+ * (limbs).  Both calls synchronize the stream. */
 hec_status hec_prof_start(hec_ctx *ctx, const char *kernel);
 hec_status hec_prof_stop(hec_ctx *ctx, uint64_t *launches, uint64_t *units, double *total_ms);
 /* Launches of the named kernel since the library was loaded (all contexts). */
 uint64_t hec_prof_launches(const char *kernel);
+/* Bandwidth probe: times a kernel that reads `nread` (1..8) and writes
+ * `nwrite` (1..4) streams of `words` (256..2^32) 64-bit words, one word of
+ * each stream per lane, non-temporal -- the access mix of a streaming kernel
+ * without its arithmetic -- over `reps` (1..10000) launches after one
+ * warm-up, on the context stream; *us_per_launch = the average duration in
+ * microseconds (HIP events).  Allocates and frees its own (nread + nwrite) *
+ * words * 8 bytes of device memory (HEC_ENOMEM if they do not fit);
+ * synchronizes the stream; not for use under graph capture.  HEC_EINVAL for
+ * counts out of range. */
+hec_status hec_probe_stream(hec_ctx *ctx, int nread, int nwrite, uint64_t words, int reps, double *us_per_launch);
 /* The thresholds of the discrete Gaussian sampler (Background, "Homomorphic
  * encryption": the error polynomials of keys and encryptions; sigma as in
  * hec_params): T[i] = floor(2^63 * sum_{|x| <= i} w(x) / sum_{|x| <= 19} w(x)),

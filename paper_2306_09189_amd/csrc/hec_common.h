@@ -322,6 +322,10 @@ void hec_decode(const double *m, double scale, const u32 *root, const double4 *t
                 u32 nz, u32 logn, hipStream_t st);
 
 // launch timing of one kernel by name (NULL stops); collect syncs the events
+#define HEC_PROBE_MAX_READ 8
+#define HEC_PROBE_MAX_WRITE 4
+// nr (1..8) streams of `words` u64 at in read, nw (1..4) at out written
+void hec_probe_stream(const u64 *in, u64 *out, size_t words, int nr, int nw, hipStream_t st);
 void hec_prof_select(const char *name);
 int hec_prof_collect(uint64_t *launches, uint64_t *units, double *ms);
 uint64_t hec_prof_count(const char *name);

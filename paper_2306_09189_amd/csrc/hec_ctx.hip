@@ -1702,6 +1702,50 @@ extern "C" hec_status hec_prof_start(hec_ctx *c, const char *kernel)
 
 extern "C" uint64_t hec_prof_launches(const char *kernel) { return kernel ? hec_prof_count(kernel) : 0; }
 
+extern "C" hec_status hec_probe_stream(hec_ctx *c, int nread, int nwrite, uint64_t words, int reps,
+                                       double *us_per_launch)
+{
+    if (!c || !us_per_launch) HEC_FAIL(HEC_EINVAL, "NULL argument");
+    if (nread < 1 || nread > HEC_PROBE_MAX_READ || nwrite < 1 || nwrite > HEC_PROBE_MAX_WRITE)
+        HEC_FAIL(HEC_EINVAL, "streams: 1..%d read, 1..%d written", HEC_PROBE_MAX_READ, HEC_PROBE_MAX_WRITE);
+    if (words < 256 || words > (1ull << 32) || reps < 1 || reps > 10000) HEC_FAIL(HEC_EINVAL, "words or reps out of range");
+    HEC_TRY_HIP(hipSetDevice(c->dev));
+    HEC_TRY_HIP(hipStreamSynchronize(c->st));
+    u64 *in = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hec_status st = HEC_OK;
+    float ms = 0;
+    if (hipMalloc(&in, (size_t)nread * words * 8) != hipSuccess || hipMalloc(&out, (size_t)nwrite * words * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        hec_set_error("probe buffers (%llu bytes)", (unsigned long long)((nread + nwrite) * words * 8));
+        st = HEC_ENOMEM;
+        goto done;
+    }
+    if (hipMemsetAsync(in, 1, (size_t)nread * words * 8, c->st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        hec_set_error("probe set-up failed");
+        st = HEC_EDEVICE;
+        goto done;
+    }
+    hec_probe_stream(in, out, words, nread, nwrite, c->st);  // warm-up
+    (void)hipEventRecord(e0, c->st);
+    for (int i = 0; i < reps; i++) hec_probe_stream(in, out, words, nread, nwrite, c->st);
+    (void)hipEventRecord(e1, c->st);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+        hipGetLastError() != hipSuccess) {
+        hec_set_error("probe launch failed");
+        st = HEC_EDEVICE;
+        goto done;
+    }
+    *us_per_launch = ms * 1e3 / reps;
+done:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    return st;
+}
+
 extern "C" hec_status hec_prof_stop(hec_ctx *c, uint64_t *launches, uint64_t *units, double *total_ms)
 {
     if (!c || !launches || !units || !total_ms) HEC_FAIL(HEC_EINVAL, "NULL argument");

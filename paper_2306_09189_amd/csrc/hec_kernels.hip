@@ -2418,3 +2418,27 @@ void hec_tensor(const DevTables &T, u64 *t, const u64 *a, const u64 *b, int nq, 
     dim3 g((T.n + EW_THREADS - 1) / EW_THREADS, nq, cnt);
     KLAUNCH("k_tensor", (uint64_t)nq * cnt, k_tensor, g, dim3(EW_THREADS), 0, st, t, a, b, (size_t)nq * T.n, T);
 }
+
+// Bandwidth probe: `nr` streams of `words` u64 read and `nw` written, one word
+// of each per lane, non-temporal, plain grid order -- the access mix of a
+// streaming kernel without its arithmetic (every output word depends on every
+// word read, so no load is dropped).
+__global__ void __launch_bounds__(EW_THREADS) k_probe_stream(const u64 *in, u64 *out, size_t words, u32 nr, u32 nw)
+{
+    const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= words) return;
+    u64 v[HEC_PROBE_MAX_READ];
+#pragma unroll
+    for (u32 r = 0; r < HEC_PROBE_MAX_READ; r++)
+        if (r < nr) v[r] = __builtin_nontemporal_load(in + (size_t)r * words + k);
+    u64 x = 0;
+#pragma unroll
+    for (u32 r = 0; r < HEC_PROBE_MAX_READ; r++)
+        if (r < nr) x += v[r];
+    for (u32 w = 0; w < nw; w++) __builtin_nontemporal_store(x + w, out + (size_t)w * words + k);
+}
+void hec_probe_stream(const u64 *in, u64 *out, size_t words, int nr, int nw, hipStream_t st)
+{
+    dim3 g((u32)((words + EW_THREADS - 1) / EW_THREADS));
+    hipLaunchKernelGGL(k_probe_stream, g, dim3(EW_THREADS), 0, st, in, out, words, (u32)nr, (u32)nw);
+}

@@ -23,7 +23,7 @@ EXPORTS = [
     "he_conv2d_plan_create", "he_conv2d_plan_run", "he_conv2d_plan_set_mode", "he_conv2d_plan_steps",
     "he_conv2d_plan_set_downsample_mode",
     "he_avgpool_steps", "he_conv2d_plan_free", "he_avgpool", "he_avgpool_ex", "he_linear", "he_linear_steps", "hec_ct_free", "hec_pt_free", "hec_image_free",
-    "hec_ctx_sync", "hec_ctx_release_cached", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "he_image_channel_shard",
+    "hec_ctx_sync", "hec_ctx_release_cached", "hec_prof_start", "hec_prof_stop", "hec_prof_launches", "hec_probe_stream", "he_image_channel_shard",
     "ckks_sub", "ckks_mul", "ckks_mul_const", "ckks_add_const", "ckks_drop", "he_cheb_eval", "he_image_cheb_eval",
     "ckks_add_pt", "he_image_add_bias", "he_block_create", "he_block_steps", "he_block_run", "he_block_free",
     "he_conv2d_plan_create_ex", "hec_gauss_table", "ckks_rotate_noalloc",
@@ -142,6 +142,7 @@ def lib():
             "hec_prof_start": (c, [vp, ctypes.c_char_p]),
             "hec_prof_stop": (c, [vp, u64p, u64p, dblp]),
             "hec_prof_launches": (u64, [ctypes.c_char_p]),
+            "hec_probe_stream": (c, [vp, ctypes.c_int, ctypes.c_int, u64, ctypes.c_int, dblp]),
             "he_image_channel_shard": (c, [vp, u32, i32p, i32p]),
             "hec_gauss_table": (c, [dbl, u64p, sz]),
             "hec_batch_begin": (c, [vp, P(vp)]),
@@ -759,6 +760,13 @@ class Context:
         a, b, t = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
         check(lib().hec_prof_stop(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
         return a.value, b.value, t.value
+
+    def probe_stream(self, nread, nwrite, words, reps=20):
+        """Average microseconds per launch of a kernel that reads `nread` and
+        writes `nwrite` streams of `words` 64-bit words (no arithmetic)."""
+        t = ctypes.c_double()
+        check(lib().hec_probe_stream(self.h, nread, nwrite, words, reps, ctypes.byref(t)))
+        return t.value
 
     @staticmethod
     def prof_launches(kernel):
