@@ -560,7 +560,7 @@ def main():
 
     # ---- the 112x112x64 ImageNet stage (32 shards): plain vs batched vs key-stationary ----
     if "imagenet" not in skip:
-        out["imagenet_112x112x64"] = guarded(lambda: imagenet_stage(ctx, hecnn, hl, rng, max(5, args.reps // 2)))
+        out["imagenet_112x112x64"] = guarded(lambda: imagenet_stage(ctx, hecnn, hl, rng, args.reps))
 
     # ---- the uneven batch: 13 instances, 48 ciphertexts at levels 2..24, eager vs one captured graph ----
     ctx.release_cached()  # the cached blocks of the sections before go back to the device
@@ -603,7 +603,7 @@ def imagenet_stage(ctx, hecnn, hl, rng, reps):
     forms = (("plain", 1, 0), ("batched", 0, 0), ("key_stationary", 4, 4), ("lazy_moddown", 2, 2))
     for name, cmode, pmode in forms:
         pi.set_mode(cmode)
-        n = max(3, reps // 4) if name == "plain" else reps
+        n = reps
         conv_ms = timed(ctx, lambda: pi.run(imi), n)
         yi = pi.run(imi)
         pool_ms = timed(ctx, lambda: ctx.avgpool(yi, pmode), n)
