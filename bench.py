@@ -53,13 +53,15 @@ LIMB_BYTES = 8 << LOGN
 KERNELS = {
     "k_ks_mac": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                  "bytes_per_unit": LIMB_BYTES,
-                 "traffic_file": os.path.join(ROOT, "profiles", "ks_mac_2e16_traffic.txt")},
+                 "traffic_file": os.path.join(ROOT, "profiles", "ks_mac_2e16_traffic.txt"),
+                 "valu_file": os.path.join(ROOT, "profiles", "ks_mac_2e16_valu.txt")},
     "k_ntt16_fwd_rows": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                          "bytes_per_unit": LIMB_BYTES,
                          "traffic_file": os.path.join(ROOT, "profiles", "ntt16_fwd_rows_2e16_traffic.txt")},
     "k_ks_inner": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0, "per_unit": LIMB_BYTES / 1e9,
                    "bytes_per_unit": LIMB_BYTES,
                    "traffic_file": os.path.join(ROOT, "profiles", "ks_inner_2e16_traffic.txt"),
+                   "valu_file": os.path.join(ROOT, "profiles", "ks_inner_2e16_valu.txt"),
                    # its access mix per (rotation, limb): 2 beta = 6 key streams read, 2 product
                    # streams written, one 64-bit word of each per lane
                    "probe_mix": (6, 2)},
@@ -112,10 +114,19 @@ def dominant_roofline(kernel, launches, units, kms):
     rec = read_traffic(spec["traffic_file"])
     if rec and rec.get("source_sha") == kernel_source_sha(kernel):
         traffic = (float(rec["fetch_bytes_per_unit"]) + float(rec["write_bytes_per_unit"])) * avg_units
-    return {"bound": spec["bound"], "kernel": kernel, "achieved": achieved, "peak": spec["peak"],
-            "unit": spec["unit"], "frac": achieved / spec["peak"], "traffic": traffic,
-            "avg_launch_us": avg_s * 1e6, "launches": launches, "avg_units_per_launch": avg_units,
-            "algorithmic_bytes_per_launch": avg_units * spec["bytes_per_unit"]}
+    out = {"bound": spec["bound"], "kernel": kernel, "achieved": achieved, "peak": spec["peak"],
+           "unit": spec["unit"], "frac": achieved / spec["peak"], "traffic": traffic,
+           "avg_launch_us": avg_s * 1e6, "launches": launches, "avg_units_per_launch": avg_units,
+           "algorithmic_bytes_per_launch": avg_units * spec["bytes_per_unit"]}
+    # VALU issue fraction: the PMC pass's quad-cycles per unit (while the
+    # kernel's source is the one measured) x the units of the timed launches /
+    # the issue slots of their duration (1024 SIMDs, 2.4 GHz, a wave64
+    # instruction per SIMD every 4 cycles)
+    rec = read_traffic(spec["valu_file"]) if "valu_file" in spec else None
+    if rec and rec.get("source_sha") == kernel_source_sha(kernel):
+        qc = float(rec["valu_quad_cycles_per_unit"]) * avg_units
+        out["valu"] = {"quad_cycles_per_launch": qc, "issue_frac": qc / (1024 * avg_s * 2.4e9 / 4)}
+    return out
 
 
 def access_mix_probe(ctx, roof):
