@@ -407,7 +407,7 @@ void hec_batch_free(hec_batch *batch);
  *   ntt_tile     2048 | 4096 | 8192   words per LDS tile of the radix-2 form
  *   ntt_group    0 | 64 | 256 | 1024  at most this many limbs per transform
  *                              launch (0: every limb of a batch in one launch)
- *   ks_rot_batch 4 | 8 | 16    rotations per key-switch launch of a hoisted set
+ *   ks_rot_batch 4 | 8 | 16 | 32   rotations per key-switch launch of a hoisted set
  *   ks_overlap   0 | 1         a hoisted set's batches all on the context
  *                              stream, or alternating between it and a second
  *                              stream (forked and joined inside the call)

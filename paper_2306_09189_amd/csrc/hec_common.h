@@ -65,16 +65,21 @@ struct DevTables {
 // scratch array of the allocation-free rotation, per device
 #define HEC_NOALLOC_SCRATCH_BYTES (128ull << 20)
 
+// HEC_KS_BATCH: terms per launch of the kernels that sum key-switch or
+// plaintext products (their carry-free 30-bit sums hold at most 16);
+// HEC_ROT_BATCH: rotations per key-switch launch of a hoisted set and per
+// batch of ModDowns (no sums across entries, so larger launches)
 #define HEC_KS_BATCH 16
+#define HEC_ROT_BATCH 32
 struct KsBatch {
-    const u64 *key[HEC_KS_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
-    u64 *out[HEC_KS_BATCH];        // [2][nqp][n]
-    const u64 *D[HEC_KS_BATCH];    // this entry's own hoisted digits (null: the launch's shared D)
+    const u64 *key[HEC_ROT_BATCH];  // [dnum][2][L+1+k][n], Montgomery form
+    u64 *out[HEC_ROT_BATCH];        // [2][nqp][n]
+    const u64 *D[HEC_ROT_BATCH];    // this entry's own hoisted digits (null: the launch's shared D)
     // c0 of the rotated ciphertext ([nq][n], NTT form): P * sigma_g(c0) is
     // added to the Q limbs of polynomial 0, so that the ModDown that follows
     // yields ModDown(e) + sigma_g(c0) exactly (null: nothing added)
-    const u64 *c0[HEC_KS_BATCH];
-    u32 g[HEC_KS_BATCH];
+    const u64 *c0[HEC_ROT_BATCH];
+    u32 g[HEC_ROT_BATCH];
 };
 
 // Key-stationary key switch: rotation t of a launch (key[t], g[t]) applied to
@@ -131,12 +136,12 @@ struct MacBatch {
 };
 
 struct CombineBatch {
-    u64 *out[HEC_KS_BATCH];        // [2][nq][n]
-    const u64 *e[HEC_KS_BATCH];    // [2][nqp][n], Q limbs in NTT form
-    const u64 *y[HEC_KS_BATCH];    // [2][nq][n], NTT form
-    const u64 *c0[HEC_KS_BATCH];   // this entry's own c0 (null: the launch's shared c0)
-    const u64 *add[HEC_KS_BATCH][2];  // [nq][n] added to poly 0 / 1 of the entry as is (null: nothing)
-    u32 g[HEC_KS_BATCH];
+    u64 *out[HEC_ROT_BATCH];        // [2][nq][n]
+    const u64 *e[HEC_ROT_BATCH];    // [2][nqp][n], Q limbs in NTT form
+    const u64 *y[HEC_ROT_BATCH];    // [2][nq][n], NTT form
+    const u64 *c0[HEC_ROT_BATCH];   // this entry's own c0 (null: the launch's shared c0)
+    const u64 *add[HEC_ROT_BATCH][2];  // [nq][n] added to poly 0 / 1 of the entry as is (null: nothing)
+    u32 g[HEC_ROT_BATCH];
 };
 
 // Launch parameters the autotuner (hec_tune.cpp) chooses among; every choice
@@ -145,7 +150,7 @@ struct TuneParams {
     int ntt16_radix = 16;  // 2^16 transforms: 16 = two radix-16 register passes, 2 = radix-2 LDS tiles
     int ntt_tile = 4096;   // words per LDS tile of the radix-2 transforms (2048, 4096, 8192)
     int ntt_group = 0;     // at most this many limbs per transform launch (0: all in one)
-    int ks_rot_batch = 16; // rotations per key-switch launch of a hoisted set (1..HEC_KS_BATCH)
+    int ks_rot_batch = 32; // rotations per key-switch launch of a hoisted set (1..HEC_ROT_BATCH)
     int ks_amounts = 4;    // amounts per key-stationary launch over many inputs (1..HEC_KS_BATCH)
     int ntt_fp64 = 1;      // 2^16 transforms of primes below 2^50 with exact double butterflies (0: integers)
     int ntt_row_vals = 16; // values per lane of the 2^16 forward row pass (16: 256 lanes per tile, 8: 512)
@@ -245,7 +250,7 @@ bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64
                       int npolys, const u32 *pmap, int nlimbs, hipStream_t st);
 bool hec_ntt_fwd_rescale(const DevTables &T, u64 *tmp, int npolys, const u32 *pmap, const RescaleFuse &f,
                          hipStream_t st);
-// ModDown tail of nrot <= HEC_KS_BATCH entries fused into the forward NTT of
+// ModDown tail of nrot <= HEC_ROT_BATCH entries fused into the forward NTT of
 // their P -> Q conversions y ([2 nrot][nq][n], coefficient form; overwritten
 // by the column pass): out_r = (e_r - NTT(y_r)) P^-1 + sigma_g(c0_r) (+ add),
 // the residues of hec_ntt_fwd + hec_moddown_combine; 2N = 2^16 only (false,

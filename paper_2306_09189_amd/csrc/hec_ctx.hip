@@ -1228,7 +1228,7 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
     // batches run on the side stream (forked after the ModUp, joined at the
     // end), each stream with its own buffers, so that one batch's key switch
     // overlaps the other's ModDown; the residues do not depend on it
-    const size_t kbn = (size_t)std::max(1, std::min((int)HEC_KS_BATCH, hec_tune_params().ks_rot_batch));
+    const size_t kbn = (size_t)std::max(1, std::min((int)HEC_ROT_BATCH, hec_tune_params().ks_rot_batch));
     const size_t nb = (todo.size() + kbn - 1) / kbn;
     // (not while the stream is being captured into a graph: a recording
     // stays on the one stream it captures)

@@ -1061,7 +1061,7 @@ bool hec_ntt_inv_from(const DevTables &T, u64 *dst, size_t dst_stride, const u64
 bool hec_ntt_fwd_moddown(const DevTables &T, u64 *y, int nrot, int nq, int nqp, const CombineBatch &cb,
                          const LevelC *lc, const u32 *pmap, hipStream_t st)
 {
-    if (T.logn != 16 || nrot < 1 || nrot > HEC_KS_BATCH || nq < 1) return false;
+    if (T.logn != 16 || nrot < 1 || nrot > HEC_ROT_BATCH || nq < 1) return false;
     const u32 np = 2u * (u32)nrot;
     const uint64_t limbs = (uint64_t)nq * np;
     dim3 g((u32)(16 * limbs));

@@ -30,7 +30,7 @@ const std::vector<Tunable> &tunables()
         {"ntt_row_vals", &TuneParams::ntt_row_vals, {16, 8}},
         {"ntt_tile", &TuneParams::ntt_tile, {2048, 4096, 8192}},
         {"ntt_group", &TuneParams::ntt_group, {0, 64, 256, 1024}},
-        {"ks_rot_batch", &TuneParams::ks_rot_batch, {4, 8, 16}},
+        {"ks_rot_batch", &TuneParams::ks_rot_batch, {4, 8, 16, 32}},
         {"ks_overlap", &TuneParams::ks_overlap, {0, 1}},
         {"ks_amounts", &TuneParams::ks_amounts, {1, 2, 4, 8, 16}},
     };

@@ -110,7 +110,7 @@ def test_batch_graph_with_two_streams(ring):
         w = rng.normal(0, 0.1, (4, 4, 3, 3))
         img = ctx.image_encrypt(x, 8, 700)
         plan = ctx.conv2d_plan(img, w)
-        plan.set_mode(0)      # 35 hoisted rotations: more than one batch of 16
+        plan.set_mode(0)      # 35 hoisted rotations: more than one batch (32 by default)
         ctx.gen_rotation_keys(plan.steps())
         b = ctx.batch()
         b.add(plan, img)

@@ -11,7 +11,7 @@ from checks import log
 pytestmark = pytest.mark.gpu
 
 NAMES = {"ntt16_radix": [16, 2], "ntt_fp64": [1, 0], "ntt_row_vals": [16, 8], "ntt_tile": [2048, 4096, 8192], "ntt_group": [0, 64, 256, 1024],
-         "ks_rot_batch": [4, 8, 16], "ks_overlap": [0, 1], "ks_amounts": [1, 2, 4, 8, 16]}
+         "ks_rot_batch": [4, 8, 16, 32], "ks_overlap": [0, 1], "ks_amounts": [1, 2, 4, 8, 16]}
 
 
 @pytest.fixture

@@ -7,7 +7,7 @@ import pytest
 from paper_2306_09189_amd import hecnn
 
 NAMES = {"ntt16_radix": [16, 2], "ntt_fp64": [1, 0], "ntt_row_vals": [16, 8], "ntt_tile": [2048, 4096, 8192], "ntt_group": [0, 64, 256, 1024],
-         "ks_rot_batch": [4, 8, 16], "ks_overlap": [0, 1], "ks_amounts": [1, 2, 4, 8, 16]}
+         "ks_rot_batch": [4, 8, 16, 32], "ks_overlap": [0, 1], "ks_amounts": [1, 2, 4, 8, 16]}
 
 pytestmark = pytest.mark.skipif(not os.path.exists(hecnn.LIB_PATH), reason="library not built")
 
@@ -23,7 +23,7 @@ def restore():
 def test_defaults_and_candidates(restore):
     assert {k: hecnn.tune_get(k) for k in NAMES} == {"ntt16_radix": 16, "ntt_fp64": 1, "ntt_row_vals": 16,
                                                        "ntt_tile": 4096, "ntt_group": 0,
-                                                       "ks_rot_batch": 16, "ks_overlap": 0, "ks_amounts": 4}
+                                                       "ks_rot_batch": 32, "ks_overlap": 0, "ks_amounts": 4}
     for k, vals in NAMES.items():
         for v in vals:
             hecnn.tune_set(k, v)
