@@ -1202,7 +1202,8 @@ hec_status ct_moddown_many(hec_ctx *c, uint32_t lvl, u64 *Eall, const std::vecto
 
 hec_status ct_moddown(hec_ctx *c, uint32_t lvl, u64 *E, hec_ct *out) { return ct_moddown_many(c, lvl, E, {out}); }
 
-hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt, hec_ct **outs)
+hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t cnt, hec_ct **outs,
+                             const u64 *Dg)
 {
     const size_t n = c->n;
     const uint32_t lvl = ct->level, nq = lvl + 1, k = c->k, nqp = nq + k;
@@ -1221,8 +1222,10 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             if (!outs[i]) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
         }
     if (todo.empty()) return HEC_OK;
-    u64 *D = nullptr;
-    HEC_CHECK(ct_modup(c, ct, &D));
+    // the digits: the caller's, or this call's own ModUp (released at the end)
+    u64 *Down = nullptr;
+    if (!Dg) HEC_CHECK(ct_modup(c, ct, &Down));
+    const u64 *D = Dg ? Dg : Down;
     const u64 *c0 = ct->d;
     // key switch in batches; with more than one batch and ks_overlap, odd
     // batches run on the side stream (forked after the ModUp, joined at the
@@ -1243,7 +1246,7 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
             if (e != hipSuccess) f = HEC_EDEVICE, hec_set_error("stream fork: %s", hipGetErrorString(e));
         }
         if (f != HEC_OK) {
-            c->release(D);
+            c->release(Down);
             for (size_t i = 0; i < cnt; i++) {
                 ct_free(outs[i]);
                 outs[i] = nullptr;
@@ -1310,14 +1313,14 @@ hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps,
         c->release(Y[i]);
     }
     if (s != HEC_OK) {
-        c->release(D);
+        c->release(Down);
         for (size_t i = 0; i < cnt; i++) {
             ct_free(outs[i]);
             outs[i] = nullptr;
         }
         return s;
     }
-    c->release(D);
+    c->release(Down);
     HEC_TRY_HIP(hipGetLastError());
     return HEC_OK;
 }

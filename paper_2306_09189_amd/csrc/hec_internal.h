@@ -185,7 +185,10 @@ struct hec_image {
 hec_ct *ct_new(hec_ctx *c, uint32_t level, double scale);
 // a copy made on (allocated from and ordered on) context c
 hec_ct *ct_clone(hec_ctx *c, const hec_ct *a);
-hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs);
+// hoisted rotations of ct; D: ct's ModUp digits if the caller has them (from
+// ct_modup of the same ciphertext, kept by the caller), else null: computed here
+hec_status ct_rotate_hoisted(hec_ctx *c, const hec_ct *ct, const int32_t *steps, size_t n, hec_ct **outs,
+                             const u64 *D = nullptr);
 hec_status ct_rescale(hec_ctx *c, hec_ct *ct);
 // every ciphertext (all at one level) rotated by `step`: one batched ModUp, key
 // switch and ModDown; the same ciphertexts as one rotation at a time

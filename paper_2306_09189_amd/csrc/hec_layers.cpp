@@ -1975,19 +1975,27 @@ extern "C" hec_status he_conv2d_plan_run(hec_ctx *c, const hec_conv_plan *p, con
     }
     for (size_t u = 0; u < p->items.size() && s == HEC_OK && p->mode < 2; u++) {
         const auto &its = p->items[u];
+        // mode 0: one ModUp of the shard for all its chunks of rotations
+        u64 *Du = nullptr;
+        if (p->mode == 0) {
+            bool any = false;
+            for (const auto &it : its) any = any || c->galois(it.amount) != 1;
+            if (any) s = ct_modup(c, in->shards[u], &Du);
+        }
         for (size_t i0 = 0; i0 < its.size() && s == HEC_OK; i0 += ROT_CHUNK) {
             size_t cnt = std::min((size_t)ROT_CHUNK, its.size() - i0);
             std::vector<int32_t> st(cnt);
             for (size_t t = 0; t < cnt; t++) st[t] = its[i0 + t].amount;
             std::vector<hec_ct *> rots(cnt, nullptr);
             if (p->mode == 0) {
-                s = ckks_rotate_hoisted(c, in->shards[u], st.data(), cnt, rots.data());
+                s = ct_rotate_hoisted(c, in->shards[u], st.data(), cnt, rots.data(), Du);
             } else {
                 for (size_t t = 0; t < cnt && s == HEC_OK; t++) s = ckks_rotate(c, in->shards[u], st[t], &rots[t]);
             }
             if (s == HEC_OK) s = mac_rotations(c, rots, its, i0, acc, first, btp);
             free_all(rots);
         }
+        c->release(Du);
     }
     for (size_t v = 0; v < nout && s == HEC_OK; v++) {
         if (first[v]) s = HEC_ELAYOUT, hec_set_error("output shard %zu received no product", v);
