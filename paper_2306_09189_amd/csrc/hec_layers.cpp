@@ -531,19 +531,8 @@ static hec_status rotate_list(hec_ctx *c, const hec_ct *ct, const std::vector<in
     return ckks_rotate_hoisted(c, ct, steps.data(), steps.size(), out.data());
 }
 
-// masked sum: acc = sum_t rots[t] * pts[t]
-static hec_status masked_sum(hec_ctx *c, const std::vector<hec_ct *> &rots, const std::vector<hec_pt *> &pts,
-                             hec_ct **out)
-{
-    hec_ct *acc = ct_new(c, rots[0]->level, 1.0);
-    if (!acc) HEC_FAIL(HEC_ENOMEM, "ciphertext allocation");
-    for (size_t t = 0; t < rots.size(); t++) {
-        hec_status s = ct_mac_pt(c, acc, rots[t], pts[t], t == 0);
-        if (s != HEC_OK) { ct_free(acc); return s; }
-    }
-    *out = acc;
-    return HEC_OK;
-}
+static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots, const std::vector<RotTerm> &its,
+                                size_t i0, std::vector<hec_ct *> &acc, std::vector<char> &first, const BasisArg *bt);
 
 // Lazy ModDown: the key-switch products of every rotation are multiplied by
 // their plaintexts and summed over Q_l and P; each output then takes one
@@ -687,14 +676,23 @@ static hec_status rot_masked_sums(hec_ctx *c, const hec_ct *ct, const std::vecto
         }
         return lazy_rotate_mac(c, {ct}, terms, masks.size(), out);
     }
+    if (steps.empty()) HEC_FAIL(HEC_ELAYOUT, "masked sum without a term");
     std::vector<hec_ct *> rots;
     HEC_CHECK(rotate_list(c, ct, steps, rots));
+    // every output's products and sums as plaintext-product batches (exact
+    // sums, one reduction per output: the residues of one MAC at a time)
+    const size_t no = masks.size();
     hec_status s = HEC_OK;
-    for (size_t o = 0; o < masks.size() && s == HEC_OK; o++) {
-        hec_ct *acc = nullptr;
-        s = masked_sum(c, rots, masks[o], &acc);
-        if (s == HEC_OK) out.push_back(acc);
+    out.assign(no, nullptr);
+    for (size_t o = 0; o < no && s == HEC_OK; o++)
+        if (!(out[o] = ct_new(c, rots[0]->level, 1.0))) s = HEC_ENOMEM, hec_set_error("ciphertext allocation");
+    std::vector<RotTerm> its(rots.size());
+    for (size_t t = 0; t < rots.size(); t++) {
+        its[t].amount = steps[t];
+        for (size_t o = 0; o < no; o++) its[t].pts.push_back({(uint32_t)o, masks[o][t]});
     }
+    std::vector<char> first(no, 1);
+    if (s == HEC_OK) s = mac_rotations(c, rots, its, 0, out, first, nullptr);
     free_all(rots);
     if (s != HEC_OK) free_all(out);
     return s;
@@ -1110,9 +1108,6 @@ static hec_status merge_channel(hec_ctx *c, std::vector<hec_ct *> &ds, const Lay
     }
     return HEC_OK;
 }
-
-static hec_status mac_rotations(hec_ctx *c, const std::vector<hec_ct *> &rots, const std::vector<RotTerm> &its,
-                                size_t i0, std::vector<hec_ct *> &acc, std::vector<char> &first, const BasisArg *bt);
 
 // out[u] = sum_t masks[t] * rot(ins[u], steps[t]) for every input u at once:
 // the nonzero rotations of all inputs amount by amount (ct_rotate_multi), the
