@@ -85,7 +85,8 @@ def read_traffic(path):
 # the kernel itself with its launcher (a change elsewhere in the file leaves a
 # recorded PMC measurement valid)
 SOURCE_REGIONS = {
-    "k_ks_mac": ("typedef u64 u64x2 __attribute__((ext_vector_type(2)));", "__global__ void k_moddown_combine("),
+    "k_ks_mac": ("typedef u64 u64x2 __attribute__((ext_vector_type(2)));",
+                 "// Sums of plaintext products over Q: each lane one coefficient of one limb, the"),
     "k_ntt16_fwd_rows": ("// NTT: merged Cooley-Tukey forward transform", "void hec_ntt_fwd("),
     "k_ks_inner": ("// key-switch inner product with the automorphism folded into the read:",
                    "// Key-stationary form of the same products"),

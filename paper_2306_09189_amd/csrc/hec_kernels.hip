@@ -537,6 +537,18 @@ DEV u64 mod64(u64 x, const PrimeC &pc);
 struct Ntt16Item {
     u32 tile, poly, limb;
 };
+// the same items in plain grid order (workgroups dealt to the XCDs round
+// robin, so the chip works through the limbs in order)
+DEV Ntt16Item ntt16_item_plain(u32 npolys)
+{
+    const u32 i = blockIdx.x;
+    Ntt16Item it;
+    it.tile = i & 15;
+    const u32 rest = i >> 4;
+    it.poly = rest % npolys;
+    it.limb = rest / npolys;
+    return it;
+}
 DEV Ntt16Item ntt16_item(u32 npolys)
 {
     const u32 w = blockIdx.x, total = gridDim.x;  // total = 16 * nlimbs * npolys, a multiple of 8
@@ -835,7 +847,10 @@ k_ntt16_fwd_rows_md(u64 *y, u32 nq, u32 nqp, const u32 *pmap, u32 npolys, Combin
 {
     __shared__ u64 lds[16 * 272];
     __shared__ double2 bt[RTAB];
-    const Ntt16Item it = ntt16_item(npolys);
+    // plain order: the rotated ciphertexts are written limb by limb across the
+    // chip, so the weight products that follow (which walk the limbs from the
+    // top) find the last-written limbs still in the last-level cache
+    const Ntt16Item it = ntt16_item_plain(npolys);
     const u32 pi = pmap[it.limb];
     const PrimeC pc = T.pc[pi];
     const u64 q = pc.q;
@@ -2036,7 +2051,9 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_terms(MacBatch b, u32 nterms
                                                           DevTables T)
 {
     constexpr bool SPLIT = NOUT <= 4;
-    const u32 o = blockIdx.y;
+    // limbs from the top: the ModDown row pass writes them in order, so the
+    // last written are read first, from the last-level cache
+    const u32 o = gridDim.y - 1 - blockIdx.y;
     const size_t k = (size_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (k >= T.n) return;
     const PrimeC pc = T.pc[o];
