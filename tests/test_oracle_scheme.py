@@ -76,6 +76,31 @@ def test_moddown_bigint(small):
         assert cand, c
 
 
+def test_moddown_absorbs_multiples_of_P(med):
+    """ModDown(e + P a) = ModDown(e) + a exactly, for any e over Q_l and P and
+    any a over Q_l (P a is zero on the special primes, so the conversion of
+    the P part is unchanged, and the division by P returns a): the identity
+    that lets a hoisted rotation add P * sigma_g(c0) to its key-switch product
+    instead of adding sigma_g(c0) after the ModDown."""
+    p, o = med
+    rng = np.random.default_rng(11)
+    for level in (0, 2, 5):
+        mods = p.q[: level + 1] + p.p
+        e = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in mods])
+        a = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in p.q[: level + 1]])
+        P = 1
+        for t in p.p:
+            P *= t
+        ePa = e.copy()
+        for i, q in enumerate(p.q[: level + 1]):
+            ePa[i] = np.array([(int(x) + int(y) * (P % q)) % q for x, y in zip(e[i], a[i])], dtype=np.uint64)
+        lhs = o.moddown(level, ePa)
+        base = o.moddown(level, e)
+        rhs = np.stack([np.array([(int(x) + int(y)) % q for x, y in zip(base[i], a[i])], dtype=np.uint64)
+                        for i, q in enumerate(p.q[: level + 1])])
+        assert (lhs == rhs).all(), level
+
+
 def test_rescale_bigint(small):
     p, o = small
     rng = np.random.default_rng(2)
